@@ -1,0 +1,242 @@
+"""FP64 CPU oracle for the spectral Gaussian-random-field path.
+
+TEST INFRASTRUCTURE ONLY: the test suite, the smoke check and the CPU-baseline
+leg of the benchmark may import this package; the product library never does.
+It shares no code with the HIP path.
+
+The arithmetic lives in ``grf_oracle.c`` (plain C, double precision, OpenMP
+over output points).  This module compiles it with gcc (``build()``), loads it
+with ctypes and wraps each entry point for numpy arrays.  Every function states
+the passage of Icardi et al. (2022) that it follows:
+
+- ``sample_modes``: wavevectors from the normalised spectral densities of App. A
+  (eqs. gauSpe, expSpe, matSpe) and uniform phases for the random-phase form of
+  Sec. 4.1 eq. DiscreteFT;
+- ``field_points`` / ``field_grid`` / ``field_cells``: the discrete spectral sum of
+  Sec. 4.1 eq. DiscreteFT in its random-phase reading,
+  ``Y(x) = sqrt(2 sigma^2/N) sum_j cos(k_j.x + phi_j)`` with ``k = z/ell`` per axis;
+- ``field_grid_separable``: the same sum through the product of per-axis complex
+  exponentials (algebraic identity behind the matrix-core form);
+- ``lognormal`` / ``facies``: the scaling and truncation steps of Sec. 4.1 and the
+  single-truncation rule of Sec. 3.1;
+- ``grad_points``: exact derivatives of a loss through ``Y`` (chain rule).
+
+Parity pins for this module are the ``-m "not gpu"`` tests in
+``tests/test_oracle_pins.py``; none of them re-types the formulas above.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from pathlib import Path
+
+import numpy as np
+
+_HERE = Path(__file__).resolve().parent
+_SRC = _HERE / "grf_oracle.c"
+_LIB = _HERE / "libgrf_oracle.so"
+
+GAUSSIAN, EXPONENTIAL, MATERN = 0, 1, 2
+
+_lib = None
+
+
+def build(force: bool = True) -> Path:
+    """Compile the oracle with gcc (-O2, no fast-math, OpenMP)."""
+    if force or not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+        tmp = _LIB.with_suffix(".so.tmp%d" % os.getpid())
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-Wall", "-Wextra",
+               "-o", str(tmp), str(_SRC), "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not _LIB.exists() or _LIB.stat().st_mtime < _SRC.stat().st_mtime:
+            build(force=True)
+        lib = ctypes.CDLL(str(_LIB))
+        d = ctypes.POINTER(ctypes.c_double)
+        i64 = ctypes.c_int64
+        lib.orc_philox4x32_10.argtypes = [ctypes.POINTER(ctypes.c_uint32)] * 3
+        lib.orc_words.argtypes = [ctypes.c_uint64, i64, ctypes.c_uint32, ctypes.POINTER(ctypes.c_uint64)]
+        lib.orc_sample_modes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, i64, ctypes.c_uint64, d, d]
+        lib.orc_sample_modes.restype = ctypes.c_int
+        lib.orc_field_points.argtypes = [ctypes.c_int, i64, d, d, ctypes.c_double, d, i64, d, d]
+        lib.orc_field_cells.argtypes = [ctypes.c_int, i64, d, d, ctypes.c_double, d,
+                                        ctypes.POINTER(i64), d, d, i64, ctypes.POINTER(i64), d]
+        lib.orc_field_grid.argtypes = [ctypes.c_int, i64, d, d, ctypes.c_double, d,
+                                       ctypes.POINTER(i64), d, d, d]
+        lib.orc_field_grid_separable.argtypes = lib.orc_field_grid.argtypes
+        lib.orc_lognormal.argtypes = [i64, d, ctypes.c_double, d]
+        lib.orc_facies.argtypes = [i64, d, ctypes.c_int, d, ctypes.POINTER(ctypes.c_uint8)]
+        lib.orc_grad_points.argtypes = [ctypes.c_int, i64, d, d, ctypes.c_double, d, i64, d, d,
+                                        d, d, d, d]
+        _lib = lib
+    return _lib
+
+
+def _dp(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def _f64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def philox4x32_10(ctr, key):
+    """One Philox4x32-10 block (Salmon et al., SC'11) -> 4 uint32."""
+    lib = _load()
+    c = (ctypes.c_uint32 * 4)(*[int(v) & 0xFFFFFFFF for v in ctr])
+    k = (ctypes.c_uint32 * 2)(*[int(v) & 0xFFFFFFFF for v in key])
+    o = (ctypes.c_uint32 * 4)()
+    lib.orc_philox4x32_10(c, k, o)
+    return [int(v) for v in o]
+
+
+def words(seed: int, j: int, slot: int):
+    """The two 64-bit words of draw slot ``slot`` of mode ``j``."""
+    lib = _load()
+    w = (ctypes.c_uint64 * 2)()
+    lib.orc_words(ctypes.c_uint64(seed), j, slot, w)
+    return int(w[0]), int(w[1])
+
+
+def sample_modes(dim: int, cov: int, n: int, seed: int, nu: float = 0.5):
+    """Mode table (z[dim][n], phi[n]) for covariance ``cov`` (App. A densities)."""
+    lib = _load()
+    z = np.empty((dim, n), dtype=np.float64)
+    phi = np.empty(n, dtype=np.float64)
+    rc = lib.orc_sample_modes(dim, cov, float(nu), n, ctypes.c_uint64(seed), _dp(z), _dp(phi))
+    if rc != 0:
+        raise ValueError("orc_sample_modes: bad arguments")
+    return z, phi
+
+
+def _ell(ell, dim):
+    e = np.ones(3, dtype=np.float64)
+    e[:dim] = np.asarray(ell, dtype=np.float64).reshape(-1)[:dim]
+    return e
+
+
+def field_points(z, phi, sigma, ell, x):
+    """Y at points x[P][dim] (Sec. 4.1 eq. DiscreteFT, random-phase reading)."""
+    lib = _load()
+    z = _f64(z)
+    phi = _f64(phi)
+    dim, n = z.shape
+    x = _f64(x).reshape(-1, dim)
+    y = np.empty(x.shape[0], dtype=np.float64)
+    lib.orc_field_points(dim, n, _dp(z), _dp(phi), float(sigma), _dp(_ell(ell, dim)), x.shape[0],
+                         _dp(x), _dp(y))
+    return y
+
+
+def _grid_args(shape, origin, h, dim):
+    gn = (ctypes.c_int64 * 3)(*([int(v) for v in shape] + [1] * (3 - len(shape))))
+    o = np.zeros(3)
+    o[:dim] = np.asarray(origin, dtype=np.float64)[:dim]
+    hh = np.ones(3)
+    hh[:dim] = np.asarray(h, dtype=np.float64)[:dim]
+    return gn, o, hh
+
+
+def field_grid(z, phi, sigma, ell, shape, origin=None, h=None):
+    """Y on a structured grid, shape (nx, ny[, nz]); returned flat with x fastest."""
+    lib = _load()
+    z = _f64(z)
+    phi = _f64(phi)
+    dim, n = z.shape
+    origin = np.zeros(dim) if origin is None else origin
+    h = np.ones(dim) if h is None else h
+    gn, o, hh = _grid_args(shape, origin, h, dim)
+    C = int(np.prod(shape[:dim]))
+    y = np.empty(C, dtype=np.float64)
+    lib.orc_field_grid(dim, n, _dp(z), _dp(phi), float(sigma), _dp(_ell(ell, dim)), gn, _dp(o),
+                       _dp(hh), _dp(y))
+    return y
+
+
+def field_grid_separable(z, phi, sigma, ell, shape, origin=None, h=None):
+    """Same field through prod_a exp(i k_a x_a) (validation of the identity)."""
+    lib = _load()
+    z = _f64(z)
+    phi = _f64(phi)
+    dim, n = z.shape
+    origin = np.zeros(dim) if origin is None else origin
+    h = np.ones(dim) if h is None else h
+    gn, o, hh = _grid_args(shape, origin, h, dim)
+    C = int(np.prod(shape[:dim]))
+    y = np.empty(C, dtype=np.float64)
+    lib.orc_field_grid_separable(dim, n, _dp(z), _dp(phi), float(sigma), _dp(_ell(ell, dim)), gn,
+                                 _dp(o), _dp(hh), _dp(y))
+    return y
+
+
+def field_cells(z, phi, sigma, ell, shape, cells, origin=None, h=None):
+    """Y at selected grid cells (linear indices, x fastest)."""
+    lib = _load()
+    z = _f64(z)
+    phi = _f64(phi)
+    dim, n = z.shape
+    origin = np.zeros(dim) if origin is None else origin
+    h = np.ones(dim) if h is None else h
+    gn, o, hh = _grid_args(shape, origin, h, dim)
+    cells = np.ascontiguousarray(cells, dtype=np.int64)
+    y = np.empty(cells.size, dtype=np.float64)
+    lib.orc_field_cells(dim, n, _dp(z), _dp(phi), float(sigma), _dp(_ell(ell, dim)), gn, _dp(o),
+                        _dp(hh), cells.size, cells.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)),
+                        _dp(y))
+    return y
+
+
+def lognormal(y, mu):
+    """K = exp(mu + Y)."""
+    lib = _load()
+    y = _f64(y)
+    k = np.empty_like(y)
+    lib.orc_lognormal(y.size, _dp(y), float(mu), _dp(k))
+    return k
+
+
+def facies(y, thresholds):
+    """Number of thresholds strictly below Y (uint8); one threshold gives [Y > t]."""
+    lib = _load()
+    y = _f64(y)
+    thr = _f64(np.atleast_1d(thresholds))
+    out = np.empty(y.size, dtype=np.uint8)
+    lib.orc_facies(y.size, _dp(y), thr.size, _dp(thr), out.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8)))
+    return out
+
+
+def grad_points(z, phi, sigma, ell, x, g):
+    """Exact gradients of L through Y at points x, given g = dL/dY.
+
+    Returns dict with dphi[n], dk[dim][n], dsigma, dell[dim].
+    """
+    lib = _load()
+    z = _f64(z)
+    phi = _f64(phi)
+    dim, n = z.shape
+    x = _f64(x).reshape(-1, dim)
+    g = _f64(g)
+    dphi = np.empty(n)
+    dk = np.empty((dim, n))
+    dsig = np.empty(1)
+    dell = np.empty(3)
+    lib.orc_grad_points(dim, n, _dp(z), _dp(phi), float(sigma), _dp(_ell(ell, dim)), x.shape[0],
+                        _dp(x), _dp(g), _dp(dphi), _dp(dk), _dp(dsig), _dp(dell))
+    return {"dphi": dphi, "dk": dk, "dsigma": float(dsig[0]), "dell": dell[:dim].copy()}
+
+
+def grid_centres(shape, origin=None, h=None):
+    """Cell-centre coordinates [C][dim] of a grid, x index fastest."""
+    dim = len(shape)
+    origin = np.zeros(dim) if origin is None else np.asarray(origin, dtype=np.float64)
+    h = np.ones(dim) if h is None else np.asarray(h, dtype=np.float64)
+    axes = [origin[a] + (np.arange(shape[a]) + 0.5) * h[a] for a in range(dim)]
+    mesh = np.meshgrid(*axes, indexing="ij")
+    return np.stack([m.reshape(-1, order="F") for m in mesh], axis=1)
