@@ -1,0 +1,243 @@
+/*
+ * grf.h -- C ABI of the MI355X (gfx950) spectral Gaussian-random-field library.
+ *
+ * The library evaluates the random-phase form of the discrete spectral sum of
+ * Icardi et al. (2022), Sec. 4.1 eq. DiscreteFT,
+ *
+ *     Y(x) = sqrt(2 sigma^2 / N) * sum_{j<N} cos(k_j . x + phi_j),   k_{j,a} = z_{j,a} / ell_a,
+ *
+ * at structured-grid cell centres or at arbitrary points, with wavevectors z_j drawn
+ * from the normalised spectral density of the covariance (App. A) and anisotropic
+ * correlation lengths by per-axis rescaling of frequency space (Sec. 4.1), followed
+ * by the log-normal scaling K = exp(mu + Y) or the truncation rule of Sec. 3.1.
+ *
+ * Conventions shared by every entry point:
+ *  - Every function returns an int status: GRF_OK (0) or a negative GRF_E* code.
+ *    No function throws, aborts or exits.  On failure grf_last_error() returns a
+ *    message for the calling thread.
+ *  - Argument validation happens on the host before anything is enqueued: an
+ *    invalid call enqueues no work and leaves outputs untouched.
+ *  - "device" pointers are HIP device memory of the current device; "host"
+ *    pointers are ordinary process memory.  All buffers are owned by the caller.
+ *    The library allocates device memory only inside a grf_plan (batched path).
+ *  - `stream` is a hipStream_t passed as void* (NULL = the default stream).  Device
+ *    work is enqueued asynchronously on it; the library never synchronises the
+ *    device except inside grf_plan_create/destroy and the autotuner.
+ *  - Grid cells are ordered with the x index fastest: c = i + nx (j + ny k).
+ *    Cell centres are origin_a + (i_a + 1/2) h_a.
+ *  - Mode tables are axis-major: z[a * n + j] for axis a < dim, mode j < n.
+ *  - Calls on different streams, or from different threads, are independent.
+ */
+#ifndef GRF_H
+#define GRF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define GRF_VERSION 10000 /* 1.0.0 */
+
+/* status codes */
+#define GRF_OK 0
+#define GRF_EINVAL (-1)       /* bad spec, shape, method or null required pointer */
+#define GRF_ENOMEM (-2)       /* workspace too small, or plan allocation failed */
+#define GRF_EDEVICE (-3)      /* HIP runtime error (message carries hipGetErrorString) */
+#define GRF_EUNSUPPORTED (-4) /* valid but unsupported combination (e.g. separable on points) */
+
+/* covariance families (App. A) */
+#define GRF_COV_GAUSSIAN 0    /* C(r) = sigma^2 exp(-|r/ell|^2), eq. gauSpe */
+#define GRF_COV_EXPONENTIAL 1 /* C(r) = sigma^2 exp(-|r/ell|),   eq. expSpe */
+#define GRF_COV_MATERN 2      /* eq. matSpe with 2*nu a positive integer <= 64 */
+
+/* evaluation methods */
+#define GRF_AUTO (-1)       /* separable FP16 on grids with >= 2^16 cells, else DIRECT_F32 */
+#define GRF_DIRECT_F32 0    /* one cos per mode and cell, FP64 per-axis phase reduction */
+#define GRF_DIRECT_F64 1    /* FP64 throughout (small problems, reference-grade) */
+#define GRF_SEP_BF16 2      /* matrix-core contraction, bf16 tables, one pass */
+#define GRF_SEP_F16 3       /* matrix-core contraction, fp16 tables, one pass */
+#define GRF_SEP_BF16_X3 4   /* bf16 hi+lo split tables, three passes */
+#define GRF_SEP_F16_X3 5    /* fp16 hi+lo split tables, three passes */
+
+#define GRF_MAX_THRESHOLDS 15
+
+/* Generator options (App. B dictionary: correlation, Kmean, Ksigma, Lcorr, nu, nfreq,
+ * disableY/disableZ as dim). */
+typedef struct grf_spec {
+    int32_t dim;            /* 2 or 3 */
+    int32_t cov;            /* GRF_COV_* */
+    double sigma2;          /* variance of Y (of ln K), > 0 */
+    double mu;              /* mean of ln K (used by the caller's epilogue) */
+    double ell[3];          /* correlation lengths per axis, > 0 (ell[2] ignored for dim 2) */
+    int64_t n_modes;        /* N >= 1 */
+    uint64_t seed;          /* Philox4x32-10 key */
+    int32_t len_convention; /* 0: ell as above; 1: Gaussian ell given as the paper's lambda,
+                               converted by ell = 2 lambda / sqrt(pi) (eq. gauSpe) */
+    double nu;              /* Matern smoothness; 2*nu must be an integer in [1, 64] */
+} grf_spec;
+
+/* A mode table in device memory plus the scalars that enter the field. */
+typedef struct grf_modes {
+    int32_t dim;        /* 2 or 3 */
+    int32_t pad_;
+    int64_t n;          /* number of modes N >= 1 */
+    const double* z;    /* device, [dim][n]: standardised wavevectors, k = z / ell */
+    const double* phi;  /* device, [n]: phases in radians */
+    double sigma;       /* standard deviation, amplitude = sigma * sqrt(2 / N) */
+    double ell[3];      /* correlation lengths (> 0) */
+} grf_modes;
+
+/* Structured grid: centres origin + (i + 1/2) h, x index fastest; n[2] = 1 for dim 2. */
+typedef struct grf_grid {
+    int64_t n[3];
+    double origin[3];
+    double h[3];
+} grf_grid;
+
+/* Epilogue applied to Y before the store (Sec. 4.1 scaling, Sec. 3.1 truncation rule). */
+typedef struct grf_epi {
+    float mu;                                /* K = exp(mu + Y) (written when k != NULL) */
+    int32_t n_thresholds;                    /* facies index = #{i : t_i < Y} (when ind != NULL);  */
+    float thresholds[GRF_MAX_THRESHOLDS];    /* one threshold t gives I = [Y > t] (strict) */
+} grf_epi;
+
+/* Library version (GRF_VERSION of the build). */
+int grf_version(void);
+
+/* Message for the last failed call on this thread ("" if none).  Never NULL. */
+const char* grf_last_error(void);
+
+/*
+ * make_modes -- draw a mode table on the host (App. A spectral densities; phases for
+ * Sec. 4.1 eq. DiscreteFT in its random-phase reading).
+ *   spec    host; validated (dim, cov, n_modes >= 1, nu for Matern).
+ *   z_out   host, [dim][n_modes] doubles, written.
+ *   phi_out host, [n_modes] doubles in [0, 2 pi), written.
+ * Philox4x32-10 keyed by spec->seed, counter (j lo, j hi, slot, 0); Box-Muller normals.
+ * Gaussian z = sqrt(2) g; exponential z = g / |h0|; Matern z = g sqrt(2nu / chi2_{2nu}).
+ * Deterministic in (dim, cov, nu, n_modes, seed); a prefix of a longer table equals the
+ * shorter table.  Does not touch the GPU.
+ */
+int make_modes(const grf_spec* spec, double* z_out, double* phi_out);
+
+/* Device workspace (bytes) that eval_field_grid needs for this problem and method. */
+int eval_field_grid_ws_size(const grf_modes* modes, const grf_grid* grid, int method, size_t* bytes);
+
+/*
+ * eval_field_grid -- Y, K and/or facies index at every cell centre of a structured grid.
+ *   modes, grid, epi  host structs (modes->z / phi point to device memory).
+ *   method            GRF_DIRECT_F32 | GRF_DIRECT_F64 | GRF_SEP_* | GRF_AUTO.
+ *   y, k              device float[C] or NULL; ind device uint8[C] or NULL (C = cells).
+ *                     At least one output must be non-NULL.  epi may be NULL when
+ *                     k and ind are NULL.
+ *   ws, ws_bytes      device workspace of at least eval_field_grid_ws_size bytes
+ *                     (GRF_ENOMEM otherwise); contents on entry are ignored.
+ * Separable methods require dim 3 grids with nx, ny >= 1 (any size; ragged tiles
+ * are masked) or dim 2 grids.  Phases are range-reduced per axis in FP64.
+ */
+int eval_field_grid(const grf_modes* modes, const grf_grid* grid, int method, const grf_epi* epi,
+                    float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes, void* stream);
+
+/* FP64 outputs of the plain method (Sec. 4.1 eq. DiscreteFT), DIRECT_F64 only:
+ * y64 / k64 device double[C] or NULL (at least one non-NULL); mu is used for k64. */
+int eval_field_grid_f64(const grf_modes* modes, const grf_grid* grid, double mu, double* y64,
+                        double* k64, void* ws, size_t ws_bytes, void* stream);
+
+/* Device workspace (bytes) that eval_field_points needs. */
+int eval_field_points_ws_size(const grf_modes* modes, int64_t n_points, int method, size_t* bytes);
+
+/*
+ * eval_field_points -- the field at P arbitrary points (unstructured cell centres,
+ * Sec. 4.1: the direct sum applies to any mesh).
+ *   xyz      device double[P][dim] (row-major).
+ *   method   GRF_DIRECT_F32 (phase a.x + psi reduced in FP64 per mode and point, cos
+ *            and sum in FP32) or GRF_DIRECT_F64; separable methods -> GRF_EUNSUPPORTED.
+ *   y, k, ind, epi, ws: as eval_field_grid.  P = 0 is a no-op.
+ */
+int eval_field_points(const grf_modes* modes, const double* xyz, int64_t n_points, int method,
+                      const grf_epi* epi, float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes,
+                      void* stream);
+
+/*
+ * epilogue_apply -- stand-alone epilogue over an existing field (memory-bound form):
+ * k[c] = exp(epi->mu + y[c]) if k != NULL; ind[c] = #{i : t_i < y[c]} if ind != NULL.
+ * y, k: device float[n]; ind: device uint8[n].  n = 0 is a no-op.
+ */
+int epilogue_apply(const float* y, int64_t n, const grf_epi* epi, float* k, uint8_t* ind,
+                   void* stream);
+
+/*
+ * Gradients of a scalar loss L through Y at P points, given g = dL/dY (field_backward).
+ * With theta_jp = k_j . x_p + phi_j and A = sigma sqrt(2/N) (chain rule through
+ * Sec. 4.1 eq. DiscreteFT, k = z / ell):
+ *   grad_phi[j]      = -A sum_p g_p sin theta_jp
+ *   grad_k[a*n + j]  = -A sum_p g_p x_{p,a} sin theta_jp
+ *   grad_sigma[0]    = sum_p g_p Y_p / sigma        (Y recomputed unless y_saved given)
+ *   grad_ell[a]      = -(1/ell_a) sum_j k_{j,a} grad_k[a*n + j]
+ *   xyz     device double[P][dim];  grad_y device float[P];  y_saved device float[P] or NULL.
+ *   outputs device float arrays (any may be NULL); overwritten, not accumulated.
+ *   ws      device workspace of field_backward_ws_size bytes.
+ * Sines are recomputed (no stored cosines); sums over points are reduced in a fixed
+ * order (deterministic).  P = 0 writes zeros.
+ */
+int field_backward_ws_size(const grf_modes* modes, int64_t n_points, size_t* bytes);
+int field_backward(const grf_modes* modes, const double* xyz, int64_t n_points, const float* grad_y,
+                   const float* y_saved, float* grad_phi, float* grad_k, float* grad_sigma,
+                   float* grad_ell, void* ws, size_t ws_bytes, void* stream);
+
+/* The same gradients for a dense dL/dY over every cell of a structured grid.
+ * grad_y device float[C] (x fastest). */
+int field_backward_grid_ws_size(const grf_modes* modes, const grf_grid* grid, size_t* bytes);
+int field_backward_grid(const grf_modes* modes, const grf_grid* grid, const float* grad_y,
+                        const float* y_saved, float* grad_phi, float* grad_k, float* grad_sigma,
+                        float* grad_ell, void* ws, size_t ws_bytes, void* stream);
+
+/*
+ * Batched ensembles of independent realisations on grids of uneven size, evaluated
+ * in one persistent launch (plus the per-axis table build) captured in a hipGraph.
+ */
+typedef struct grf_batch_item {
+    grf_modes modes; /* per-instance mode table (device) and scalars */
+    grf_grid grid;   /* dim 2 or 3 grid */
+    float* y;        /* device float[cells of this grid] */
+} grf_batch_item;
+
+typedef struct grf_plan grf_plan;
+
+/* Plan flags */
+#define GRF_PLAN_GRAPH 1    /* capture the launch sequence in a hipGraph and replay it */
+#define GRF_PLAN_AUTOTUNE 2 /* time candidate tile shapes on first use (cached per size class) */
+
+/*
+ * grf_plan_create -- a plan owns device memory for the batch's tables and descriptors,
+ * the autotuned tile choices and the captured graph, keyed by the batch signature.
+ *   method  GRF_DIRECT_F32 or a GRF_SEP_* method (GRF_AUTO -> GRF_SEP_F16).
+ *   flags   GRF_PLAN_* bits.
+ *   tune_cache_path  host string or NULL: a text file where tuned tile choices are read
+ *                    from and appended to.
+ */
+int grf_plan_create(grf_plan** plan, int method, int flags, const char* tune_cache_path);
+int grf_plan_destroy(grf_plan* plan);
+
+/*
+ * eval_field_batch -- evaluate n items.  items is a host array; each item's outputs
+ * receive exactly what eval_field_grid(method) would write for y.  The first call with a
+ * new batch signature (sizes, pointers, method) builds descriptors, tunes if asked and
+ * captures the graph; later calls with the same signature replay it.  Calls on one plan
+ * must not overlap (they share the plan's device memory).
+ */
+int eval_field_batch(grf_plan* plan, const grf_batch_item* items, int32_t n, void* stream);
+
+/* Statistics of the last eval_field_batch call on this plan (for benchmarks):
+ * tile_m/tile_n chosen for the separable path (0 for direct), replayed = 1 if the graph
+ * was replayed, work_items = tiles in the persistent queue. */
+int grf_plan_info(const grf_plan* plan, int32_t* tile_m, int32_t* tile_n, int32_t* replayed,
+                  int64_t* work_items);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GRF_H */

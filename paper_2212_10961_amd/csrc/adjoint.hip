@@ -1,0 +1,228 @@
+// Adjoint of the spectral sum (field_backward).
+//
+// With theta_jp = k_j . x_p + phi_j and A = sigma sqrt(2/N) (Sec. 4.1 eq. DiscreteFT,
+// k = z / ell), the gradients of L given g_p = dL/dY_p are
+//   dL/dphi_j = -A S_j,  dL/dk_{a,j} = -A U_{a,j},  S_j = sum_p g_p sin theta_jp,
+//   U_{a,j} = sum_p g_p x_{p,a} sin theta_jp,
+//   dL/dsigma = sum_p g_p Y_p / sigma = (A / sigma) sum_j C_j,  C_j = sum_p g_p cos theta_jp,
+//   dL/dell_a = sum_j dL/dk_{a,j} (-z_{a,j} / ell_a^2).
+//
+// Layout: one lane per mode, points streamed uniformly through the block (their
+// coordinates and g come in through scalar loads).  The phase is formed and reduced
+// in FP64 per mode and point; sines (and cosines when Y is not saved) are recomputed,
+// never stored.  Per-chunk partial sums go to the workspace and are reduced in a
+// fixed order, so results are bitwise reproducible.
+#include <hip/hip_runtime.h>
+
+#include "grf_internal.h"
+
+namespace grf {
+
+namespace {
+
+struct Geo {
+    int64_t nx, ny;
+    double ox, oy, oz, hx, hy, hz;
+};
+
+template <int DIM, bool GRID, bool WANT_C>
+__global__ __launch_bounds__(256) void k_bwd(const double4* __restrict__ prm, int64_t ldp,
+                                            const double* __restrict__ xyz, int64_t P, int64_t chunk, Geo geo,
+                                            const float* __restrict__ gy, float* __restrict__ partial)
+{
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t ch = blockIdx.y;
+    const int64_t p0 = ch * chunk;
+    const int64_t p1 = min(P, p0 + chunk);
+    const double4 m = prm[min(j, ldp - 1)];
+    float s = 0.f, ux = 0.f, uy = 0.f, uz = 0.f, cc = 0.f;
+    for (int64_t p = p0; p < p1; ++p) {
+        double x, y, z = 0.0;
+        if (GRID) {
+            const int64_t i = p % geo.nx, q = p / geo.nx;
+            x = geo.ox + (static_cast<double>(i) + 0.5) * geo.hx;
+            y = geo.oy + (static_cast<double>(q % geo.ny) + 0.5) * geo.hy;
+            if (DIM == 3) z = geo.oz + (static_cast<double>(q / geo.ny) + 0.5) * geo.hz;
+        } else {
+            x = xyz[p * DIM];
+            y = xyz[p * DIM + 1];
+            if (DIM == 3) z = xyz[p * DIM + 2];
+        }
+        const float g = gy[p];
+        double ph = DIM == 3 ? fma(m.z, z, m.w) : m.w;
+        ph = fma(m.y, y, ph);
+        ph = fma(m.x, x, ph);
+        ph -= floor(ph);
+        const float f = static_cast<float>(ph);
+        const float sn = __builtin_amdgcn_sinf(f);
+        s = fmaf(g, sn, s);
+        ux = fmaf(g * static_cast<float>(x), sn, ux);
+        uy = fmaf(g * static_cast<float>(y), sn, uy);
+        if (DIM == 3) uz = fmaf(g * static_cast<float>(z), sn, uz);
+        if (WANT_C) cc = fmaf(g, __builtin_amdgcn_cosf(f), cc);
+    }
+    if (j < ldp) {
+        float* out = partial + ch * 5 * ldp;
+        out[j] = s;
+        out[ldp + j] = ux;
+        out[2 * ldp + j] = uy;
+        out[3 * ldp + j] = uz;
+        out[4 * ldp + j] = cc;
+    }
+}
+
+__device__ inline float block_sum(float v, float* sh)
+{
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    const int w = threadIdx.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) sh[w] = v;
+    __syncthreads();
+    float r = 0.f;
+    for (int i = 0; i < static_cast<int>(blockDim.x >> 6); ++i) r += sh[i];
+    return r;
+}
+
+// Per-mode reduction over chunks (fixed order) and per-block partials of the scalar sums.
+__global__ __launch_bounds__(256) void k_bwd_reduce(const float* __restrict__ partial, int64_t nch, int64_t n,
+                                                   int64_t ldp, int dim, float amp, const double* __restrict__ z,
+                                                   double ell0, double ell1, double ell2, float* __restrict__ gphi,
+                                                   float* __restrict__ gk, float* __restrict__ scal)
+{
+    __shared__ float sh[4];
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    float tl[3] = {0.f, 0.f, 0.f}, tc = 0.f;
+    if (j < n) {
+        float S = 0.f, U[3] = {0.f, 0.f, 0.f}, C = 0.f;
+        for (int64_t c = 0; c < nch; ++c) {
+            const float* pc = partial + c * 5 * ldp;
+            S += pc[j];
+            U[0] += pc[ldp + j];
+            U[1] += pc[2 * ldp + j];
+            U[2] += pc[3 * ldp + j];
+            C += pc[4 * ldp + j];
+        }
+        if (gphi) gphi[j] = -amp * S;
+        const double ell[3] = {ell0, ell1, ell2};
+        for (int a = 0; a < dim; ++a) {
+            const float gka = -amp * U[a];
+            if (gk) gk[a * n + j] = gka;
+            tl[a] = static_cast<float>(static_cast<double>(gka) * (-z[a * n + j] / (ell[a] * ell[a])));
+        }
+        tc = C;
+    }
+    const float r0 = block_sum(tl[0], sh);
+    const float r1 = block_sum(tl[1], sh);
+    const float r2 = block_sum(tl[2], sh);
+    const float r3 = block_sum(tc, sh);
+    if (threadIdx.x == 0) {
+        scal[blockIdx.x * 4 + 0] = r0;
+        scal[blockIdx.x * 4 + 1] = r1;
+        scal[blockIdx.x * 4 + 2] = r2;
+        scal[blockIdx.x * 4 + 3] = r3;
+    }
+}
+
+// sum_p g_p y_p over chunks of the points (when Y was saved by the forward pass).
+__global__ __launch_bounds__(256) void k_dot_partial(const float* __restrict__ a, const float* __restrict__ b,
+                                                    int64_t P, float* __restrict__ out)
+{
+    __shared__ float sh[4];
+    float v = 0.f;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; p < P; p += stride) v += a[p] * b[p];
+    const float r = block_sum(v, sh);
+    if (threadIdx.x == 0) out[blockIdx.x] = r;
+}
+
+__global__ __launch_bounds__(256) void k_bwd_final(const float* __restrict__ scal, int nblk, int dim,
+                                                  const float* __restrict__ dotp, int ndot, float amp, float sigma,
+                                                  float* __restrict__ gsigma, float* __restrict__ gell)
+{
+    if (threadIdx.x != 0) return;
+    float acc[4] = {0.f, 0.f, 0.f, 0.f};
+    for (int b = 0; b < nblk; ++b)
+        for (int q = 0; q < 4; ++q) acc[q] += scal[b * 4 + q];
+    if (gell)
+        for (int a = 0; a < dim; ++a) gell[a] = acc[a];
+    if (gsigma) {
+        if (dotp) {
+            float d = 0.f;
+            for (int b = 0; b < ndot; ++b) d += dotp[b];
+            gsigma[0] = d / sigma;
+        } else {
+            gsigma[0] = amp / sigma * acc[3];
+        }
+    }
+}
+
+template <int DIM, bool GRID>
+void launch_bwd_main(const BwdArgs& a, int64_t chunk, const Geo& geo, bool want_c, hipStream_t s)
+{
+    const dim3 grid(static_cast<unsigned>((a.ldp + 255) / 256), static_cast<unsigned>(a.nchunks));
+    const double4* prm = reinterpret_cast<const double4*>(a.params);
+    if (want_c)
+        hipLaunchKernelGGL((k_bwd<DIM, GRID, true>), grid, dim3(256), 0, s, prm, a.ldp, a.xyz, a.P, chunk, geo, a.gy,
+                           a.partial);
+    else
+        hipLaunchKernelGGL((k_bwd<DIM, GRID, false>), grid, dim3(256), 0, s, prm, a.ldp, a.xyz, a.P, chunk, geo, a.gy,
+                           a.partial);
+}
+
+}  // namespace
+
+int64_t bwd_chunks(int64_t P)
+{
+    int64_t c = (P + 127) / 128;
+    if (c < 1) c = 1;
+    if (c > 256) c = 256;
+    return c;
+}
+
+hipError_t launch_backward(const BwdArgs& a, hipStream_t s)
+{
+    const int64_t chunk = a.P > 0 ? (a.P + a.nchunks - 1) / a.nchunks : 0;
+    Geo geo{};
+    const bool grid = a.xyz == nullptr;
+    if (grid) {
+        geo.nx = a.gn[0];
+        geo.ny = a.gn[1];
+        geo.ox = a.go[0];
+        geo.oy = a.go[1];
+        geo.oz = a.dim == 3 ? a.go[2] : 0.0;
+        geo.hx = a.gh[0];
+        geo.hy = a.gh[1];
+        geo.hz = a.dim == 3 ? a.gh[2] : 0.0;
+    }
+    const bool want_c = a.gsigma != nullptr && a.ysaved == nullptr;
+    if (a.dim == 3) {
+        if (grid) launch_bwd_main<3, true>(a, chunk, geo, want_c, s);
+        else launch_bwd_main<3, false>(a, chunk, geo, want_c, s);
+    } else {
+        if (grid) launch_bwd_main<2, true>(a, chunk, geo, want_c, s);
+        else launch_bwd_main<2, false>(a, chunk, geo, want_c, s);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+
+    const int nblk = static_cast<int>((a.n + 255) / 256);
+    hipLaunchKernelGGL(k_bwd_reduce, dim3(nblk), dim3(256), 0, s, a.partial, a.nchunks, a.n, a.ldp, a.dim, a.amp, a.z,
+                       a.ell[0], a.ell[1], a.dim == 3 ? a.ell[2] : 1.0, a.gphi, a.gk, a.scal_partial);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    const float* dotp = nullptr;
+    int ndot = 0;
+    if (a.gsigma && a.ysaved && a.P > 0) {
+        ndot = 1024;
+        float* dp = a.scal_partial + 4 * nblk;
+        hipLaunchKernelGGL(k_dot_partial, dim3(ndot), dim3(256), 0, s, a.gy, a.ysaved, a.P, dp);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+        dotp = dp;
+    }
+    hipLaunchKernelGGL(k_bwd_final, dim3(1), dim3(64), 0, s, a.scal_partial, nblk, a.dim, dotp, ndot, a.amp, a.sigma,
+                       a.gsigma, a.gell);
+    return hipGetLastError();
+}
+
+}  // namespace grf

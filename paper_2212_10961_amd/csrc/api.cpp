@@ -1,0 +1,415 @@
+// C-ABI entry points: validation, workspace layout and dispatch to the kernels.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "grf_internal.h"
+
+namespace grf {
+
+static thread_local char g_err[512] = "";
+
+int fail(int code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int fail_hip(hipError_t e, const char* what)
+{
+    return fail(GRF_EDEVICE, "HIP error in %s: %s", what, hipGetErrorString(e));
+}
+
+Epi make_epi(const grf_epi* e)
+{
+    Epi r{};
+    if (e) {
+        r.mu = e->mu;
+        r.nthr = e->n_thresholds;
+        for (int i = 0; i < GRF_MAX_THRESHOLDS; ++i) r.thr[i] = i < e->n_thresholds ? e->thresholds[i] : 0.f;
+    }
+    return r;
+}
+
+static int check_modes(const grf_modes* m, const char* fn)
+{
+    if (!m) return fail(GRF_EINVAL, "%s: modes is NULL", fn);
+    if (m->dim != 2 && m->dim != 3) return fail(GRF_EINVAL, "%s: dim must be 2 or 3 (got %d)", fn, m->dim);
+    if (m->n < 1) return fail(GRF_EINVAL, "%s: number of modes must be >= 1", fn);
+    if (m->n > (int64_t(1) << 31)) return fail(GRF_EINVAL, "%s: too many modes", fn);
+    if (!m->z || !m->phi) return fail(GRF_EINVAL, "%s: modes z/phi pointer is NULL", fn);
+    if (!(m->sigma >= 0.0) || !std::isfinite(m->sigma)) return fail(GRF_EINVAL, "%s: sigma must be finite and >= 0", fn);
+    for (int a = 0; a < m->dim; ++a)
+        if (!(m->ell[a] > 0.0) || !std::isfinite(m->ell[a]))
+            return fail(GRF_EINVAL, "%s: ell[%d] must be finite and > 0", fn, a);
+    return GRF_OK;
+}
+
+static int check_grid(const grf_grid* g, int dim, const char* fn)
+{
+    if (!g) return fail(GRF_EINVAL, "%s: grid is NULL", fn);
+    for (int a = 0; a < 3; ++a) {
+        if (g->n[a] < 1) return fail(GRF_EINVAL, "%s: grid n[%d] must be >= 1", fn, a);
+        if (a < dim && (!std::isfinite(g->h[a]) || !std::isfinite(g->origin[a])))
+            return fail(GRF_EINVAL, "%s: grid origin/h must be finite", fn);
+    }
+    if (dim == 2 && g->n[2] != 1) return fail(GRF_EINVAL, "%s: dim 2 grid needs n[2] == 1", fn);
+    if (g->n[0] > (1 << 24) || g->n[1] > (1 << 24) || g->n[2] > (1 << 24))
+        return fail(GRF_EINVAL, "%s: grid side too large", fn);
+    const int64_t cells = g->n[0] * g->n[1] * g->n[2];
+    if (cells > (int64_t(1) << 40)) return fail(GRF_EINVAL, "%s: grid too large", fn);
+    return GRF_OK;
+}
+
+static int check_epi(const grf_epi* e, const float* k, const uint8_t* ind, const char* fn)
+{
+    if ((k || ind) && !e) return fail(GRF_EINVAL, "%s: epi is NULL but k or ind requested", fn);
+    if (e && (e->n_thresholds < 0 || e->n_thresholds > GRF_MAX_THRESHOLDS))
+        return fail(GRF_EINVAL, "%s: n_thresholds must be in [0, %d]", fn, GRF_MAX_THRESHOLDS);
+    if (ind && e && e->n_thresholds < 1) return fail(GRF_EINVAL, "%s: ind requested with no thresholds", fn);
+    if (e)
+        for (int i = 1; i < e->n_thresholds; ++i)
+            if (!(e->thresholds[i] >= e->thresholds[i - 1]))
+                return fail(GRF_EINVAL, "%s: thresholds must be ascending", fn);
+    return GRF_OK;
+}
+
+static bool is_sep(int m) { return m >= GRF_SEP_BF16 && m <= GRF_SEP_F16_X3; }
+static bool is_hilo(int m) { return m == GRF_SEP_BF16_X3 || m == GRF_SEP_F16_X3; }
+static bool is_bf16(int m) { return m == GRF_SEP_BF16 || m == GRF_SEP_BF16_X3; }
+
+static int resolve_grid_method(int method, const grf_grid* g)
+{
+    if (method == GRF_AUTO) {
+        const int64_t cells = g->n[0] * g->n[1] * g->n[2];
+        return cells >= (int64_t(1) << 16) ? GRF_SEP_F16 : GRF_DIRECT_F32;
+    }
+    return method;
+}
+
+// Workspace layout of eval_field_grid for a resolved method.  With `base` == nullptr
+// it only measures.
+struct GridWs {
+    void* t[3] = {nullptr, nullptr, nullptr};
+    void* tlo[3] = {nullptr, nullptr, nullptr};
+    size_t bytes = 0;
+};
+
+static GridWs grid_ws(const grf_modes* m, const grf_grid* g, int method, void* base)
+{
+    GridWs w;
+    Carve c(base);
+    const int64_t ldp = padded_modes(m->n);
+    const int dim = m->dim;
+    if (method == GRF_DIRECT_F32) {
+        for (int a = 0; a < 3; ++a) w.t[a] = c.take<float>(size_t(g->n[a]) * ldp);
+    } else if (method == GRF_DIRECT_F64) {
+        for (int a = 0; a < 3; ++a) w.t[a] = c.take<double>(size_t(g->n[a]) * ldp);
+    } else if (is_sep(method)) {
+        const bool hilo = is_hilo(method);
+        if (dim == 2) {
+            w.t[0] = c.take<uint32_t>(size_t(g->n[0]) * ldp);
+            if (hilo) w.tlo[0] = c.take<uint32_t>(size_t(g->n[0]) * ldp);
+        } else {
+            w.t[0] = c.take<float2>(size_t(g->n[0]) * ldp);
+            w.t[2] = c.take<float2>(size_t(g->n[2]) * ldp);
+        }
+        w.t[1] = c.take<uint32_t>(size_t(g->n[1]) * ldp);
+        if (hilo) w.tlo[1] = c.take<uint32_t>(size_t(g->n[1]) * ldp);
+    }
+    w.bytes = c.used;
+    return w;
+}
+
+static hipError_t build_tables(const grf_modes* m, const grf_grid* g, int method, const GridWs& w,
+                               hipStream_t s)
+{
+    const int64_t ldp = padded_modes(m->n);
+    for (int a = 0; a < 3; ++a) {
+        AxisTableArgs t{};
+        t.z = m->z;
+        t.phi = m->phi;
+        t.n = m->n;
+        t.ldp = ldp;
+        t.axis = a;
+        t.ell = a < m->dim ? m->ell[a] : 1.0;
+        t.origin = g->origin[a];
+        t.h = g->h[a];
+        t.count = g->n[a];
+        t.with_psi = (a == 1);
+        t.conj = false;
+        t.out = w.t[a];
+        t.out_lo = w.tlo[a];
+        if (a >= m->dim) t.z = nullptr;  // axis absent: zero phase
+        if (method == GRF_DIRECT_F32) {
+            t.format = TF_REV_F32;
+        } else if (method == GRF_DIRECT_F64) {
+            t.format = TF_REV_F64;
+        } else {
+            const bool hilo = is_hilo(method), bf = is_bf16(method);
+            if (a == 1 || (a == 0 && m->dim == 2)) {
+                t.format = bf ? (hilo ? TF_BF16_HILO : TF_BF16) : (hilo ? TF_F16_HILO : TF_F16);
+                t.conj = (a == 0);
+            } else if (a == 0 || (a == 2 && m->dim == 3)) {
+                t.format = TF_CPLX_F32;
+            } else {
+                continue;  // dim 2: no z table for the separable form
+            }
+        }
+        hipError_t e = launch_axis_table(t, s);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+}  // namespace grf
+
+using namespace grf;
+
+extern "C" {
+
+int grf_version(void) { return GRF_VERSION; }
+
+const char* grf_last_error(void) { return g_err; }
+
+int eval_field_grid_ws_size(const grf_modes* modes, const grf_grid* grid, int method, size_t* bytes)
+{
+    int rc;
+    if ((rc = check_modes(modes, "eval_field_grid_ws_size"))) return rc;
+    if ((rc = check_grid(grid, modes->dim, "eval_field_grid_ws_size"))) return rc;
+    if (!bytes) return fail(GRF_EINVAL, "eval_field_grid_ws_size: bytes is NULL");
+    method = resolve_grid_method(method, grid);
+    if (method < GRF_DIRECT_F32 || method > GRF_SEP_F16_X3)
+        return fail(GRF_EINVAL, "eval_field_grid_ws_size: unknown method %d", method);
+    *bytes = grid_ws(modes, grid, method, nullptr).bytes;
+    return GRF_OK;
+}
+
+int eval_field_grid(const grf_modes* modes, const grf_grid* grid, int method, const grf_epi* epi,
+                    float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes, void* stream)
+{
+    const char* fn = "eval_field_grid";
+    int rc;
+    if ((rc = check_modes(modes, fn))) return rc;
+    if ((rc = check_grid(grid, modes->dim, fn))) return rc;
+    if (!y && !k && !ind) return fail(GRF_EINVAL, "%s: no output requested", fn);
+    if ((rc = check_epi(epi, k, ind, fn))) return rc;
+    method = resolve_grid_method(method, grid);
+    if (method < GRF_DIRECT_F32 || method > GRF_SEP_F16_X3) return fail(GRF_EINVAL, "%s: unknown method %d", fn, method);
+    const GridWs need = grid_ws(modes, grid, method, nullptr);
+    if (ws_bytes < need.bytes || (!ws && need.bytes))
+        return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need.bytes, ws_bytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const GridWs w = grid_ws(modes, grid, method, ws);
+    const Epi e = make_epi(epi);
+    const float amp = static_cast<float>(modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n)));
+    const int64_t ldp = padded_modes(modes->n);
+
+    GRF_HIP(build_tables(modes, grid, method, w, s));
+    if (method == GRF_DIRECT_F32) {
+        GRF_HIP(launch_direct_grid_f32(static_cast<const float*>(w.t[0]), static_cast<const float*>(w.t[1]),
+                                       static_cast<const float*>(w.t[2]), modes->n, ldp, grid->n, amp, e,
+                                       y, k, ind, s));
+    } else if (method == GRF_DIRECT_F64) {
+        const double amp64 = modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n));
+        GRF_HIP(launch_direct_grid_f64(static_cast<const double*>(w.t[0]), static_cast<const double*>(w.t[1]),
+                                       static_cast<const double*>(w.t[2]), modes->n, ldp, grid->n, amp64, e,
+                                       0.0, y, k, ind, nullptr, nullptr, s));
+    } else {
+        SepArgs a{};
+        a.method = method;
+        a.n = modes->n;
+        a.ldp = ldp;
+        a.nx = grid->n[0];
+        a.ny = grid->n[1];
+        a.nz = grid->n[2];
+        a.px = w.t[0];
+        a.px_lo = w.tlo[0];
+        a.qy = w.t[1];
+        a.qy_lo = w.tlo[1];
+        a.ez = modes->dim == 3 ? static_cast<const float2*>(w.t[2]) : nullptr;
+        a.amp = amp;
+        a.epi = e;
+        a.y = y;
+        a.k = k;
+        a.ind = ind;
+        a.tile = 0;
+        GRF_HIP(launch_sep(a, s));
+    }
+    return GRF_OK;
+}
+
+int eval_field_grid_f64(const grf_modes* modes, const grf_grid* grid, double mu, double* y64, double* k64,
+                        void* ws, size_t ws_bytes, void* stream)
+{
+    const char* fn = "eval_field_grid_f64";
+    int rc;
+    if ((rc = check_modes(modes, fn))) return rc;
+    if ((rc = check_grid(grid, modes->dim, fn))) return rc;
+    if (!y64 && !k64) return fail(GRF_EINVAL, "%s: no output requested", fn);
+    if (!std::isfinite(mu)) return fail(GRF_EINVAL, "%s: mu must be finite", fn);
+    const GridWs need = grid_ws(modes, grid, GRF_DIRECT_F64, nullptr);
+    if (ws_bytes < need.bytes || !ws)
+        return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need.bytes, ws_bytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const GridWs w = grid_ws(modes, grid, GRF_DIRECT_F64, ws);
+    GRF_HIP(build_tables(modes, grid, GRF_DIRECT_F64, w, s));
+    const double amp64 = modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n));
+    GRF_HIP(launch_direct_grid_f64(static_cast<const double*>(w.t[0]), static_cast<const double*>(w.t[1]),
+                                   static_cast<const double*>(w.t[2]), modes->n, padded_modes(modes->n),
+                                   grid->n, amp64, Epi{}, mu, nullptr, nullptr, nullptr, y64, k64, s));
+    return GRF_OK;
+}
+
+int eval_field_points_ws_size(const grf_modes* modes, int64_t n_points, int method, size_t* bytes)
+{
+    int rc;
+    if ((rc = check_modes(modes, "eval_field_points_ws_size"))) return rc;
+    if (!bytes) return fail(GRF_EINVAL, "eval_field_points_ws_size: bytes is NULL");
+    if (n_points < 0) return fail(GRF_EINVAL, "eval_field_points_ws_size: n_points < 0");
+    if (method == GRF_AUTO) method = GRF_DIRECT_F32;
+    if (is_sep(method)) return fail(GRF_EUNSUPPORTED, "eval_field_points_ws_size: separable methods need a grid");
+    if (method != GRF_DIRECT_F32 && method != GRF_DIRECT_F64)
+        return fail(GRF_EINVAL, "eval_field_points_ws_size: unknown method %d", method);
+    *bytes = align256(sizeof(double) * 4 * size_t(padded_modes(modes->n)));
+    return GRF_OK;
+}
+
+int eval_field_points(const grf_modes* modes, const double* xyz, int64_t n_points, int method,
+                      const grf_epi* epi, float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes,
+                      void* stream)
+{
+    const char* fn = "eval_field_points";
+    int rc;
+    if ((rc = check_modes(modes, fn))) return rc;
+    if (n_points < 0) return fail(GRF_EINVAL, "%s: n_points < 0", fn);
+    if (n_points > (int64_t(1) << 40)) return fail(GRF_EINVAL, "%s: too many points", fn);
+    if (method == GRF_AUTO) method = GRF_DIRECT_F32;
+    if (is_sep(method)) return fail(GRF_EUNSUPPORTED, "%s: separable methods need a structured grid", fn);
+    if (method != GRF_DIRECT_F32 && method != GRF_DIRECT_F64) return fail(GRF_EINVAL, "%s: unknown method %d", fn, method);
+    if ((rc = check_epi(epi, k, ind, fn))) return rc;
+    if (n_points == 0) return GRF_OK;
+    if (!y && !k && !ind) return fail(GRF_EINVAL, "%s: no output requested", fn);
+    if (!xyz) return fail(GRF_EINVAL, "%s: xyz is NULL", fn);
+    const size_t need = align256(sizeof(double) * 4 * size_t(padded_modes(modes->n)));
+    if (!ws || ws_bytes < need) return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    double* params = static_cast<double*>(ws);
+    const int64_t ldp = padded_modes(modes->n);
+    GRF_HIP(launch_mode_params(modes->z, modes->phi, modes->dim, modes->n, ldp, modes->ell, params, s));
+    const float amp = static_cast<float>(modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n)));
+    GRF_HIP(launch_direct_points(params, modes->n, modes->dim, xyz, n_points, method == GRF_DIRECT_F64, amp,
+                                 make_epi(epi), y, k, ind, s));
+    return GRF_OK;
+}
+
+int epilogue_apply(const float* y, int64_t n, const grf_epi* epi, float* k, uint8_t* ind, void* stream)
+{
+    const char* fn = "epilogue_apply";
+    if (n < 0) return fail(GRF_EINVAL, "%s: n < 0", fn);
+    if (!epi) return fail(GRF_EINVAL, "%s: epi is NULL", fn);
+    int rc;
+    if ((rc = check_epi(epi, k, ind, fn))) return rc;
+    if (n == 0) return GRF_OK;
+    if (!k && !ind) return fail(GRF_EINVAL, "%s: no output requested", fn);
+    if (!y) return fail(GRF_EINVAL, "%s: y is NULL", fn);
+    GRF_HIP(launch_epilogue(y, n, make_epi(epi), k, ind, static_cast<hipStream_t>(stream)));
+    return GRF_OK;
+}
+
+int field_backward_ws_size(const grf_modes* modes, int64_t n_points, size_t* bytes)
+{
+    int rc;
+    if ((rc = check_modes(modes, "field_backward_ws_size"))) return rc;
+    if (!bytes) return fail(GRF_EINVAL, "field_backward_ws_size: bytes is NULL");
+    if (n_points < 0) return fail(GRF_EINVAL, "field_backward_ws_size: n_points < 0");
+    const int64_t ldp = padded_modes(modes->n);
+    const int64_t nch = bwd_chunks(n_points);
+    *bytes = align256(sizeof(double) * 4 * ldp) + align256(sizeof(float) * 5 * ldp * nch) +
+             align256(sizeof(float) * bwd_scal_floats(modes->n));
+    return GRF_OK;
+}
+
+static int backward_common(const char* fn, const grf_modes* modes, const double* xyz, const grf_grid* grid,
+                           int64_t P, const float* grad_y, const float* y_saved, float* grad_phi,
+                           float* grad_k, float* grad_sigma, float* grad_ell, void* ws, size_t ws_bytes,
+                           void* stream)
+{
+    size_t need = 0;
+    int rc = field_backward_ws_size(modes, P, &need);
+    if (rc) return rc;
+    if (!grad_phi && !grad_k && !grad_sigma && !grad_ell) return fail(GRF_EINVAL, "%s: no output requested", fn);
+    if (P > 0 && !grad_y) return fail(GRF_EINVAL, "%s: grad_y is NULL", fn);
+    if (P > 0 && !xyz && !grid) return fail(GRF_EINVAL, "%s: xyz is NULL", fn);
+    if (!ws || ws_bytes < need) return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t ldp = padded_modes(modes->n);
+    Carve c(ws);
+    double* params = c.take<double>(4 * ldp);
+    float* partial = c.take<float>(5 * ldp * bwd_chunks(P));
+    float* scal = c.take<float>(bwd_scal_floats(modes->n));
+    GRF_HIP(launch_mode_params(modes->z, modes->phi, modes->dim, modes->n, ldp, modes->ell, params, s));
+    BwdArgs a{};
+    a.params = params;
+    a.n = modes->n;
+    a.ldp = ldp;
+    a.dim = modes->dim;
+    a.xyz = xyz;
+    a.gn = grid ? grid->n : nullptr;
+    a.go = grid ? grid->origin : nullptr;
+    a.gh = grid ? grid->h : nullptr;
+    a.P = P;
+    a.gy = grad_y;
+    a.ysaved = y_saved;
+    a.amp = static_cast<float>(modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n)));
+    a.sigma = static_cast<float>(modes->sigma);
+    a.ell = modes->ell;
+    a.z = modes->z;
+    a.gphi = grad_phi;
+    a.gk = grad_k;
+    a.gsigma = grad_sigma;
+    a.gell = grad_ell;
+    a.partial = partial;
+    a.scal_partial = scal;
+    a.nchunks = bwd_chunks(P);
+    GRF_HIP(launch_backward(a, s));
+    return GRF_OK;
+}
+
+int field_backward(const grf_modes* modes, const double* xyz, int64_t n_points, const float* grad_y,
+                   const float* y_saved, float* grad_phi, float* grad_k, float* grad_sigma, float* grad_ell,
+                   void* ws, size_t ws_bytes, void* stream)
+{
+    int rc = check_modes(modes, "field_backward");
+    if (rc) return rc;
+    if (n_points < 0) return fail(GRF_EINVAL, "field_backward: n_points < 0");
+    if (modes->sigma <= 0.0 && grad_sigma) return fail(GRF_EINVAL, "field_backward: sigma must be > 0 for grad_sigma");
+    return backward_common("field_backward", modes, xyz, nullptr, n_points, grad_y, y_saved, grad_phi, grad_k,
+                           grad_sigma, grad_ell, ws, ws_bytes, stream);
+}
+
+int field_backward_grid_ws_size(const grf_modes* modes, const grf_grid* grid, size_t* bytes)
+{
+    int rc;
+    if ((rc = check_modes(modes, "field_backward_grid_ws_size"))) return rc;
+    if ((rc = check_grid(grid, modes->dim, "field_backward_grid_ws_size"))) return rc;
+    return field_backward_ws_size(modes, grid->n[0] * grid->n[1] * grid->n[2], bytes);
+}
+
+int field_backward_grid(const grf_modes* modes, const grf_grid* grid, const float* grad_y, const float* y_saved,
+                        float* grad_phi, float* grad_k, float* grad_sigma, float* grad_ell, void* ws,
+                        size_t ws_bytes, void* stream)
+{
+    int rc = check_modes(modes, "field_backward_grid");
+    if (rc) return rc;
+    if ((rc = check_grid(grid, modes->dim, "field_backward_grid"))) return rc;
+    if (modes->sigma <= 0.0 && grad_sigma) return fail(GRF_EINVAL, "field_backward_grid: sigma must be > 0 for grad_sigma");
+    return backward_common("field_backward_grid", modes, nullptr, grid, grid->n[0] * grid->n[1] * grid->n[2],
+                           grad_y, y_saved, grad_phi, grad_k, grad_sigma, grad_ell, ws, ws_bytes, stream);
+}
+
+}  // extern "C"

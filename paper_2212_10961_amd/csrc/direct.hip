@@ -1,0 +1,317 @@
+// Direct spectral sums (Sec. 4.1 eq. DiscreteFT, random-phase reading):
+//   Y_c = A sum_j cos(2 pi r_jc),   r_jc = frac-reduced phase in revolutions,
+// one hardware cosine per mode and cell, plus the fused epilogue
+// (K = exp(mu + Y), facies index = #{thresholds below Y}; Secs. 4.1 and 3.1).
+//
+// v_cos_f32 takes its argument in revolutions and reduces it exactly, so the
+// per-axis FP64-reduced fractions are summed in FP32 (values in [0, 3)) and fed
+// to it without a further reduction.
+#include <hip/hip_runtime.h>
+
+#include "grf_internal.h"
+
+namespace grf {
+
+namespace {
+
+__device__ __forceinline__ float cos_rev(float r) { return __builtin_amdgcn_cosf(r); }
+
+__device__ __forceinline__ void store_out(int64_t c, float yv, const Epi& e, float* __restrict__ y,
+                                          float* __restrict__ k, uint8_t* __restrict__ ind)
+{
+    if (y) y[c] = yv;
+    if (k) k[c] = expf(e.mu + yv);
+    if (ind) {
+        int f = 0;
+        for (int i = 0; i < e.nthr; ++i) f += (yv > e.thr[i]) ? 1 : 0;
+        ind[c] = static_cast<uint8_t>(f);
+    }
+}
+
+// ---------------------------------------------------------------------------- grid, FP32
+// Block tile: 64 x-cells by 64 (y,z) pairs; 256 threads; each lane owns 4 x 4 cells
+// (x = x0 + lx + 16 rx, q = q0 + 16 w + ly + 4 rq).  Mode chunks of 64 are staged in
+// LDS: sx[x][j] = Tx, sq[q][j] = Ty + Tz (psi folded in Ty).  Rows are padded to 68
+// floats so the 16 distinct x rows of a wave's 128-bit reads hit distinct banks.
+constexpr int kDgB = 64;
+constexpr int kDgJ = 64;
+constexpr int kDgRow = (kDgJ + 4) / 4;  // float4 per padded row
+
+__global__ __launch_bounds__(256, 2) void k_direct_grid(const float* __restrict__ tx, const float* __restrict__ ty,
+                                                       const float* __restrict__ tz, int n, int64_t ldp, int nx,
+                                                       int ny, int64_t nq, int nxt, float amp, Epi epi,
+                                                       float* __restrict__ y, float* __restrict__ k,
+                                                       uint8_t* __restrict__ ind)
+{
+    __shared__ float4 sx[kDgB * kDgRow];
+    __shared__ float4 sq[kDgB * kDgRow];
+    const int t = threadIdx.x;
+    const int w = t >> 6, l = t & 63;
+    const int lx = l & 15, lq = w * 16 + (l >> 4);
+    const int64_t bid = blockIdx.x;
+    const int x0 = static_cast<int>(bid % nxt) * kDgB;
+    const int64_t q0 = (bid / nxt) * kDgB;
+
+    float acc[4][4];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
+
+    for (int j0 = 0; j0 < n; j0 += kDgJ) {
+#pragma unroll
+        for (int it = 0; it < 4; ++it) {
+            const int e = it * 256 + t;
+            const int row = e >> 4, c4 = e & 15;
+            const int xg = min(x0 + row, nx - 1);
+            sx[row * kDgRow + c4] = *reinterpret_cast<const float4*>(tx + static_cast<int64_t>(xg) * ldp + j0 + 4 * c4);
+            const int64_t q = min(q0 + row, nq - 1);
+            const int64_t yy = q % ny, zz = q / ny;
+            const float4 a = *reinterpret_cast<const float4*>(ty + yy * ldp + j0 + 4 * c4);
+            const float4 b = *reinterpret_cast<const float4*>(tz + zz * ldp + j0 + 4 * c4);
+            sq[row * kDgRow + c4] = make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+        }
+        __syncthreads();
+        const int jn = min(kDgJ, n - j0);
+        const int j4 = jn >> 2;
+        for (int m = 0; m < j4; ++m) {
+            float4 vx[4], vq[4];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) vx[r] = sx[(lx + 16 * r) * kDgRow + m];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) vq[r] = sq[(lq + 4 * r) * kDgRow + m];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b) {
+                    acc[a][b] += cos_rev(vx[a].x + vq[b].x);
+                    acc[a][b] += cos_rev(vx[a].y + vq[b].y);
+                    acc[a][b] += cos_rev(vx[a].z + vq[b].z);
+                    acc[a][b] += cos_rev(vx[a].w + vq[b].w);
+                }
+        }
+        const float* sxf = reinterpret_cast<const float*>(sx);
+        const float* sqf = reinterpret_cast<const float*>(sq);
+        for (int m = j4 * 4; m < jn; ++m) {
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < 4; ++b)
+                    acc[a][b] += cos_rev(sxf[(lx + 16 * a) * kDgRow * 4 + m] + sqf[(lq + 4 * b) * kDgRow * 4 + m]);
+        }
+        __syncthreads();
+    }
+
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int x = x0 + lx + 16 * a;
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+            const int64_t q = q0 + lq + 4 * b;
+            if (x < nx && q < nq) store_out(q * nx + x, amp * acc[a][b], epi, y, k, ind);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------- grid, FP64
+// One thread per cell, FP64 per-axis fractions summed and reduced in FP64, cos by
+// the device library's cospi.  For small problems and as a reference-grade path.
+__global__ __launch_bounds__(256) void k_direct_grid_f64(const double* __restrict__ tx, const double* __restrict__ ty,
+                                                        const double* __restrict__ tz, int n, int64_t ldp, int nx,
+                                                        int ny, int64_t C, double amp, Epi epi, double mu64,
+                                                        float* __restrict__ y, float* __restrict__ k,
+                                                        uint8_t* __restrict__ ind, double* __restrict__ y64,
+                                                        double* __restrict__ k64)
+{
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    const int64_t i = c % nx, q = c / nx;
+    const int64_t jy = q % ny, kz = q / ny;
+    const double* rx = tx + i * ldp;
+    const double* ry = ty + jy * ldp;
+    const double* rz = tz + kz * ldp;
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) {
+        double f = rx[j] + ry[j] + rz[j];
+        f -= floor(f);
+        s += cospi(2.0 * f);
+    }
+    const double yv = amp * s;
+    if (y64) y64[c] = yv;
+    if (k64) k64[c] = exp(mu64 + yv);
+    if (y || k || ind) store_out(c, static_cast<float>(yv), epi, y, k, ind);
+}
+
+// ---------------------------------------------------------------------------- points
+// Each lane owns R points; every mode's (a_x, a_y, a_z, psi) in revolutions is
+// uniform across the block (scalar loads).  The phase a.x + psi is formed and
+// reduced in FP64 per mode and point, then the cosine and the sum run in FP32.
+template <int DIM, int R>
+__global__ __launch_bounds__(256) void k_direct_points(const double4* __restrict__ prm, int n,
+                                                      const double* __restrict__ xyz, int64_t P, float amp,
+                                                      Epi epi, float* __restrict__ y, float* __restrict__ k,
+                                                      uint8_t* __restrict__ ind)
+{
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * (256 * R) + threadIdx.x;
+    double px[R], py[R], pz[R];
+    float acc[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t p = min(base + 256 * r, P - 1);
+        px[r] = xyz[p * DIM];
+        py[r] = xyz[p * DIM + 1];
+        pz[r] = DIM == 3 ? xyz[p * DIM + 2] : 0.0;
+        acc[r] = 0.f;
+    }
+    for (int j = 0; j < n; ++j) {
+        const double4 m = prm[j];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            double ph = DIM == 3 ? fma(m.z, pz[r], m.w) : m.w;
+            ph = fma(m.y, py[r], ph);
+            ph = fma(m.x, px[r], ph);
+            ph -= floor(ph);
+            acc[r] += cos_rev(static_cast<float>(ph));
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int64_t p = base + 256 * r;
+        if (p < P) store_out(p, amp * acc[r], epi, y, k, ind);
+    }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_direct_points_f64(const double4* __restrict__ prm, int n,
+                                                          const double* __restrict__ xyz, int64_t P, double amp,
+                                                          Epi epi, float* __restrict__ y, float* __restrict__ k,
+                                                          uint8_t* __restrict__ ind)
+{
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    const double px = xyz[p * DIM], py = xyz[p * DIM + 1], pz = DIM == 3 ? xyz[p * DIM + 2] : 0.0;
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) {
+        const double4 m = prm[j];
+        double ph = fma(m.x, px, fma(m.y, py, fma(m.z, pz, m.w)));
+        ph -= floor(ph);
+        s += cospi(2.0 * ph);
+    }
+    store_out(p, static_cast<float>(amp * s), epi, y, k, ind);
+}
+
+// ---------------------------------------------------------------------------- epilogue
+// Stand-alone epilogue: 4 cells per thread, 16-byte loads and stores.
+__global__ __launch_bounds__(256) void k_epilogue(const float* __restrict__ y, int64_t n, Epi epi,
+                                                 float* __restrict__ k, uint8_t* __restrict__ ind)
+{
+    const int64_t n4 = n >> 2;
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; i < n4; i += stride) {
+        const float4 v = reinterpret_cast<const float4*>(y)[i];
+        if (k)
+            reinterpret_cast<float4*>(k)[i] =
+                make_float4(expf(epi.mu + v.x), expf(epi.mu + v.y), expf(epi.mu + v.z), expf(epi.mu + v.w));
+        if (ind) {
+            int f0 = 0, f1 = 0, f2 = 0, f3 = 0;
+            for (int t = 0; t < epi.nthr; ++t) {
+                const float th = epi.thr[t];
+                f0 += v.x > th;
+                f1 += v.y > th;
+                f2 += v.z > th;
+                f3 += v.w > th;
+            }
+            reinterpret_cast<uint32_t*>(ind)[i] = static_cast<uint32_t>(f0) | (static_cast<uint32_t>(f1) << 8) |
+                                                  (static_cast<uint32_t>(f2) << 16) | (static_cast<uint32_t>(f3) << 24);
+        }
+    }
+    // ragged tail (n not a multiple of 4)
+    if (blockIdx.x == 0 && threadIdx.x < (n & 3)) {
+        const int64_t c = n4 * 4 + threadIdx.x;
+        store_out(c, y[c], epi, nullptr, k, ind);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_epilogue_scalar(const float* __restrict__ y, int64_t n, Epi epi,
+                                                        float* __restrict__ k, uint8_t* __restrict__ ind)
+{
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; c < n; c += stride)
+        store_out(c, y[c], epi, nullptr, k, ind);
+}
+
+}  // namespace
+
+hipError_t launch_direct_grid_f32(const float* tx, const float* ty, const float* tz, int64_t n, int64_t ldp,
+                                  const int64_t* gn, float amp, const Epi& epi, float* y, float* k, uint8_t* ind,
+                                  hipStream_t s)
+{
+    const int nx = static_cast<int>(gn[0]), ny = static_cast<int>(gn[1]);
+    const int64_t nq = gn[1] * gn[2];
+    const int nxt = (nx + kDgB - 1) / kDgB;
+    const int64_t blocks = static_cast<int64_t>(nxt) * ((nq + kDgB - 1) / kDgB);
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_direct_grid, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, tx, ty, tz,
+                       static_cast<int>(n), ldp, nx, ny, nq, nxt, amp, epi, y, k, ind);
+    return hipGetLastError();
+}
+
+hipError_t launch_direct_grid_f64(const double* tx, const double* ty, const double* tz, int64_t n, int64_t ldp,
+                                  const int64_t* gn, double amp, const Epi& epi, double mu64, float* y, float* k,
+                                  uint8_t* ind, double* y64, double* k64, hipStream_t s)
+{
+    const int64_t C = gn[0] * gn[1] * gn[2];
+    const int64_t blocks = (C + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_direct_grid_f64, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, tx, ty, tz,
+                       static_cast<int>(n), ldp, static_cast<int>(gn[0]), static_cast<int>(gn[1]), C, amp, epi, mu64,
+                       y, k, ind, y64, k64);
+    return hipGetLastError();
+}
+
+hipError_t launch_direct_points(const double* params, int64_t n, int dim, const double* xyz, int64_t P, bool fp64,
+                                float amp, const Epi& epi, float* y, float* k, uint8_t* ind, hipStream_t s)
+{
+    const double4* prm = reinterpret_cast<const double4*>(params);
+    if (fp64) {
+        const int64_t blocks = (P + 255) / 256;
+        if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+        if (dim == 3)
+            hipLaunchKernelGGL(k_direct_points_f64<3>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, prm,
+                               static_cast<int>(n), xyz, P, static_cast<double>(amp), epi, y, k, ind);
+        else
+            hipLaunchKernelGGL(k_direct_points_f64<2>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, prm,
+                               static_cast<int>(n), xyz, P, static_cast<double>(amp), epi, y, k, ind);
+        return hipGetLastError();
+    }
+    constexpr int R = 4;
+    const int64_t blocks = (P + 256 * R - 1) / (256 * R);
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (dim == 3)
+        hipLaunchKernelGGL((k_direct_points<3, R>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, prm,
+                           static_cast<int>(n), xyz, P, amp, epi, y, k, ind);
+    else
+        hipLaunchKernelGGL((k_direct_points<2, R>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, prm,
+                           static_cast<int>(n), xyz, P, amp, epi, y, k, ind);
+    return hipGetLastError();
+}
+
+hipError_t launch_epilogue(const float* y, int64_t n, const Epi& epi, float* k, uint8_t* ind, hipStream_t s)
+{
+    const bool aligned = (reinterpret_cast<uintptr_t>(y) % 16 == 0) && (reinterpret_cast<uintptr_t>(k) % 16 == 0) &&
+                         (reinterpret_cast<uintptr_t>(ind) % 4 == 0);
+    if (!aligned) {
+        int64_t blocks = (n + 255) / 256;
+        if (blocks > 256 * 64) blocks = 256 * 64;
+        hipLaunchKernelGGL(k_epilogue_scalar, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, y, n, epi, k, ind);
+        return hipGetLastError();
+    }
+    const int64_t n4 = n >> 2;
+    int64_t blocks = (n4 + 255) / 256;
+    if (blocks < 1) blocks = 1;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    hipLaunchKernelGGL(k_epilogue, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, y, n, epi, k, ind);
+    return hipGetLastError();
+}
+
+}  // namespace grf

@@ -1,0 +1,124 @@
+// make_modes: host-side spectral sampler for the mode table.
+//
+// Wavevectors follow the normalised spectral densities of App. A (eqs. gauSpe,
+// expSpe, matSpe) with per-axis rescaling k = z / ell (Sec. 4.1); phases are
+// uniform on [0, 2 pi) for the random-phase form of Sec. 4.1 eq. DiscreteFT.
+//
+// Random numbers come from Philox4x32-10 (Salmon et al., SC'11): key = seed,
+// counter = (mode lo, mode hi, slot, 0); every block yields two 64-bit words
+// (out1:out0, out3:out2).  Slot 0 -> phase, slots 1-2 -> the d spatial normals,
+// slots 3.. -> radial mixing normals.  Uniform on (0,1): ((w >> 11) + 1/2) 2^-53;
+// normals by Box-Muller (pairs: r cos, r sin).
+#include <cmath>
+#include <cstdint>
+
+#include "grf_internal.h"
+
+namespace {
+
+struct Philox {
+    uint32_t key0, key1;
+
+    static inline void round(uint32_t& x0, uint32_t& x1, uint32_t& x2, uint32_t& x3, uint32_t k0,
+                             uint32_t k1)
+    {
+        const uint64_t m0 = 0xD2511F53ull * x0;
+        const uint64_t m1 = 0xCD9E8D57ull * x2;
+        const uint32_t y0 = static_cast<uint32_t>(m1 >> 32) ^ x1 ^ k0;
+        const uint32_t y2 = static_cast<uint32_t>(m0 >> 32) ^ x3 ^ k1;
+        x1 = static_cast<uint32_t>(m1);
+        x3 = static_cast<uint32_t>(m0);
+        x0 = y0;
+        x2 = y2;
+    }
+
+    // Two 64-bit words for counter (lo, hi, slot, 0).
+    void block(uint64_t ctr, uint32_t slot, uint64_t& w0, uint64_t& w1) const
+    {
+        uint32_t x0 = static_cast<uint32_t>(ctr), x1 = static_cast<uint32_t>(ctr >> 32);
+        uint32_t x2 = slot, x3 = 0;
+        uint32_t k0 = key0, k1 = key1;
+        round(x0, x1, x2, x3, k0, k1);
+        for (int r = 1; r < 10; ++r) {
+            k0 += 0x9E3779B9u;
+            k1 += 0xBB67AE85u;
+            round(x0, x1, x2, x3, k0, k1);
+        }
+        w0 = (static_cast<uint64_t>(x1) << 32) | x0;
+        w1 = (static_cast<uint64_t>(x3) << 32) | x2;
+    }
+};
+
+inline double to_unit(uint64_t w) { return (static_cast<double>(w >> 11) + 0.5) * 0x1.0p-53; }
+
+constexpr double kTwoPi = 6.283185307179586476925286766559;
+
+inline void box_muller(const Philox& g, uint64_t j, uint32_t slot, double out[2])
+{
+    uint64_t w0, w1;
+    g.block(j, slot, w0, w1);
+    const double rad = std::sqrt(-2.0 * std::log(to_unit(w0)));
+    const double ang = kTwoPi * to_unit(w1);
+    out[0] = rad * std::cos(ang);
+    out[1] = rad * std::sin(ang);
+}
+
+}  // namespace
+
+extern "C" int make_modes(const grf_spec* spec, double* z_out, double* phi_out)
+{
+    using grf::fail;
+    if (!spec) return fail(GRF_EINVAL, "make_modes: spec is NULL");
+    if (spec->dim != 2 && spec->dim != 3) return fail(GRF_EINVAL, "make_modes: dim must be 2 or 3 (got %d)", spec->dim);
+    if (spec->n_modes < 1) return fail(GRF_EINVAL, "make_modes: n_modes must be >= 1");
+    if (!z_out || !phi_out) return fail(GRF_EINVAL, "make_modes: output pointer is NULL");
+    int dof = 0;
+    switch (spec->cov) {
+    case GRF_COV_GAUSSIAN:
+    case GRF_COV_EXPONENTIAL:
+        break;
+    case GRF_COV_MATERN: {
+        const double m = 2.0 * spec->nu;
+        dof = static_cast<int>(std::lround(m));
+        if (!(m > 0.0) || std::fabs(m - dof) > 1e-12 || dof < 1 || dof > 64)
+            return fail(GRF_EINVAL, "make_modes: Matern needs 2*nu an integer in [1, 64] (nu = %g)", spec->nu);
+        break;
+    }
+    default:
+        return fail(GRF_EINVAL, "make_modes: unknown covariance %d", spec->cov);
+    }
+
+    const Philox gen{static_cast<uint32_t>(spec->seed), static_cast<uint32_t>(spec->seed >> 32)};
+    const int64_t n = spec->n_modes;
+    const int dim = spec->dim;
+    for (int64_t j = 0; j < n; ++j) {
+        const uint64_t jj = static_cast<uint64_t>(j);
+        uint64_t w0, w1;
+        gen.block(jj, 0u, w0, w1);
+        phi_out[j] = kTwoPi * to_unit(w0);
+
+        double g[4];
+        box_muller(gen, jj, 1u, g);
+        box_muller(gen, jj, 2u, g + 2);
+
+        double radial;
+        if (spec->cov == GRF_COV_GAUSSIAN) {
+            radial = std::sqrt(2.0);  // k ~ N(0, 2/ell^2): correlation exp(-r^2/ell^2)
+        } else if (spec->cov == GRF_COV_EXPONENTIAL) {
+            double h[2];
+            box_muller(gen, jj, 3u, h);
+            radial = 1.0 / std::fabs(h[0]);  // multivariate Cauchy
+        } else {
+            double chi2 = 0.0;
+            for (int i = 0; i < dof; i += 2) {
+                double h[2];
+                box_muller(gen, jj, 3u + static_cast<uint32_t>(i / 2), h);
+                chi2 += h[0] * h[0];
+                if (i + 1 < dof) chi2 += h[1] * h[1];
+            }
+            radial = std::sqrt(static_cast<double>(dof) / chi2);  // multivariate t, 2 nu dof
+        }
+        for (int a = 0; a < dim; ++a) z_out[static_cast<int64_t>(a) * n + j] = g[a] * radial;
+    }
+    return GRF_OK;
+}

@@ -1,0 +1,328 @@
+"""Python binding of the spectral Gaussian-random-field library.
+
+Thin marshalling over the C ABI (include/grf.h): torch supplies device memory
+and the current HIP stream, every arithmetic step runs in the library's HIP
+kernels.  Field definition (Icardi et al. 2022, Sec. 4.1 eq. DiscreteFT,
+random-phase reading):
+
+    Y(x) = sigma sqrt(2/N) sum_j cos(k_j . x + phi_j),   k_{j,a} = z_{j,a} / ell_a,
+
+with z drawn from the App. A spectral densities, followed by K = exp(mu + Y)
+or the truncation rule of Sec. 3.1.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _lib as L
+from ._lib import GrfError, check
+
+__all__ = [
+    "Modes", "make_modes", "modes_from_tables", "field_grid", "field_grid_f64", "field_points",
+    "epilogue", "field_backward", "field_backward_grid", "GRFPoints", "Plan", "method_id",
+    "GAUSSIAN", "EXPONENTIAL", "MATERN", "GrfError", "version", "paper_lambda_to_ell",
+]
+
+GAUSSIAN, EXPONENTIAL, MATERN = L.GRF_COV_GAUSSIAN, L.GRF_COV_EXPONENTIAL, L.GRF_COV_MATERN
+
+
+def version() -> int:
+    return L.load().grf_version()
+
+
+def method_id(method) -> int:
+    if isinstance(method, str):
+        return L.METHODS[method]
+    return int(method)
+
+
+def paper_lambda_to_ell(lam: float) -> float:
+    """Gaussian covariance written with the integral scale lambda of App. A eq. gauSpe,
+    exp(-(pi/4)(r/lambda)^2), equals exp(-r^2/ell^2) for ell = 2 lambda / sqrt(pi)."""
+    return 2.0 * lam / math.sqrt(math.pi)
+
+
+@dataclass
+class Modes:
+    """A device-resident mode table plus the scalars of the field."""
+    z: torch.Tensor      # float64 [dim][n] on the GPU
+    phi: torch.Tensor    # float64 [n] on the GPU
+    sigma: float
+    ell: Sequence[float]
+
+    @property
+    def dim(self) -> int:
+        return int(self.z.shape[0])
+
+    @property
+    def n(self) -> int:
+        return int(self.z.shape[1])
+
+    def c(self) -> L.GrfModes:
+        m = L.GrfModes()
+        m.dim = self.dim
+        m.n = self.n
+        m.z = self.z.data_ptr()
+        m.phi = self.phi.data_ptr()
+        m.sigma = float(self.sigma)
+        e = list(self.ell) + [1.0] * (3 - len(self.ell))
+        m.ell = (ctypes.c_double * 3)(*[float(v) for v in e[:3]])
+        return m
+
+
+def make_modes(dim: int, cov: int, n_modes: int, seed: int, nu: float = 0.5):
+    """Host mode table (z[dim][n], phi[n]) as numpy float64 (library sampler)."""
+    spec = L.GrfSpec()
+    spec.dim, spec.cov, spec.n_modes, spec.seed, spec.nu = dim, cov, n_modes, seed, float(nu)
+    spec.sigma2 = 1.0
+    spec.ell = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    z = np.empty((dim, n_modes), dtype=np.float64)
+    phi = np.empty(n_modes, dtype=np.float64)
+    check(L.load().make_modes(ctypes.byref(spec), z.ctypes.data, phi.ctypes.data))
+    return z, phi
+
+
+def modes_from_tables(z, phi, sigma: float, ell, device="cuda") -> Modes:
+    zt = torch.as_tensor(np.ascontiguousarray(z), dtype=torch.float64).to(device).contiguous()
+    pt = torch.as_tensor(np.ascontiguousarray(phi), dtype=torch.float64).to(device).contiguous()
+    return Modes(zt, pt, float(sigma), [float(v) for v in ell])
+
+
+def _grid(shape, origin=None, h=None) -> L.GrfGrid:
+    g = L.GrfGrid()
+    n = list(shape) + [1] * (3 - len(shape))
+    o = list(origin) if origin is not None else [0.0] * len(shape)
+    hh = list(h) if h is not None else [1.0] * len(shape)
+    o += [0.0] * (3 - len(o))
+    hh += [1.0] * (3 - len(hh))
+    g.n = (ctypes.c_int64 * 3)(*[int(v) for v in n])
+    g.origin = (ctypes.c_double * 3)(*[float(v) for v in o])
+    g.h = (ctypes.c_double * 3)(*[float(v) for v in hh])
+    return g
+
+
+def _epi(mu=None, thresholds=None) -> L.GrfEpi:
+    e = L.GrfEpi()
+    e.mu = float(mu) if mu is not None else 0.0
+    thr = [] if thresholds is None else [float(t) for t in np.atleast_1d(thresholds)]
+    e.n_thresholds = len(thr)
+    e.thresholds = (ctypes.c_float * L.GRF_MAX_THRESHOLDS)(*(thr + [0.0] * (L.GRF_MAX_THRESHOLDS - len(thr))))
+    return e
+
+
+def _stream(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _workspace(nbytes: int, device) -> torch.Tensor:
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def field_grid(modes: Modes, shape, origin=None, h=None, method="direct_f32", mu=None, thresholds=None,
+               want_y=True, want_k=False, want_ind=False, out=None, workspace=None, stream=None):
+    """Y, K = exp(mu + Y) and/or the facies index on a structured grid (x fastest).
+
+    Returns a dict of flat device tensors.  ``out`` may hold preallocated 'y'/'k'/'ind'.
+    """
+    lib = L.load()
+    dev = modes.z.device
+    m, g = modes.c(), _grid(shape, origin, h)
+    meth = method_id(method)
+    cells = int(np.prod(list(shape)))
+    need = ctypes.c_size_t()
+    check(lib.eval_field_grid_ws_size(ctypes.byref(m), ctypes.byref(g), meth, ctypes.byref(need)))
+    ws = workspace if workspace is not None and workspace.numel() >= need.value else _workspace(need.value, dev)
+    out = dict(out or {})
+    if want_y and "y" not in out:
+        out["y"] = torch.empty(cells, dtype=torch.float32, device=dev)
+    if want_k and "k" not in out:
+        out["k"] = torch.empty(cells, dtype=torch.float32, device=dev)
+    if want_ind and "ind" not in out:
+        out["ind"] = torch.empty(cells, dtype=torch.uint8, device=dev)
+    e = _epi(mu, thresholds)
+    check(lib.eval_field_grid(ctypes.byref(m), ctypes.byref(g), meth, ctypes.byref(e), _ptr(out.get("y")),
+                              _ptr(out.get("k")), _ptr(out.get("ind")), ctypes.c_void_p(ws.data_ptr()),
+                              ws.numel(), _stream(stream)))
+    return out
+
+
+def grid_workspace_bytes(modes: Modes, shape, method) -> int:
+    need = ctypes.c_size_t()
+    check(L.load().eval_field_grid_ws_size(ctypes.byref(modes.c()), ctypes.byref(_grid(shape)),
+                                           method_id(method), ctypes.byref(need)))
+    return need.value
+
+
+def field_grid_f64(modes: Modes, shape, origin=None, h=None, mu=0.0, want_k=True, stream=None):
+    """FP64 Y and K of the plain method on a structured grid."""
+    lib = L.load()
+    dev = modes.z.device
+    m, g = modes.c(), _grid(shape, origin, h)
+    cells = int(np.prod(list(shape)))
+    need = ctypes.c_size_t()
+    check(lib.eval_field_grid_ws_size(ctypes.byref(m), ctypes.byref(g), L.GRF_DIRECT_F64, ctypes.byref(need)))
+    ws = _workspace(need.value, dev)
+    y = torch.empty(cells, dtype=torch.float64, device=dev)
+    k = torch.empty(cells, dtype=torch.float64, device=dev) if want_k else None
+    check(lib.eval_field_grid_f64(ctypes.byref(m), ctypes.byref(g), float(mu), _ptr(y), _ptr(k),
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+    return {"y": y, "k": k}
+
+
+def field_points(modes: Modes, xyz: torch.Tensor, method="direct_f32", mu=None, thresholds=None, want_y=True,
+                 want_k=False, want_ind=False, out=None, workspace=None, stream=None):
+    """The field at points xyz (device float64 [P][dim])."""
+    lib = L.load()
+    dev = modes.z.device
+    if xyz.dtype != torch.float64 or not xyz.is_contiguous() or xyz.dim() != 2 or xyz.shape[1] != modes.dim:
+        raise ValueError("xyz must be a contiguous float64 [P][dim] device tensor")
+    P = int(xyz.shape[0])
+    m = modes.c()
+    meth = method_id(method)
+    need = ctypes.c_size_t()
+    check(lib.eval_field_points_ws_size(ctypes.byref(m), P, meth, ctypes.byref(need)))
+    ws = workspace if workspace is not None and workspace.numel() >= need.value else _workspace(need.value, dev)
+    out = dict(out or {})
+    if want_y and "y" not in out:
+        out["y"] = torch.empty(P, dtype=torch.float32, device=dev)
+    if want_k and "k" not in out:
+        out["k"] = torch.empty(P, dtype=torch.float32, device=dev)
+    if want_ind and "ind" not in out:
+        out["ind"] = torch.empty(P, dtype=torch.uint8, device=dev)
+    e = _epi(mu, thresholds)
+    check(lib.eval_field_points(ctypes.byref(m), ctypes.c_void_p(xyz.data_ptr()), P, meth, ctypes.byref(e),
+                                _ptr(out.get("y")), _ptr(out.get("k")), _ptr(out.get("ind")),
+                                ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+    return out
+
+
+def epilogue(y: torch.Tensor, mu=None, thresholds=None, want_k=True, want_ind=False, out=None, stream=None):
+    """Stand-alone epilogue over an existing FP32 field."""
+    lib = L.load()
+    out = dict(out or {})
+    n = y.numel()
+    if want_k and "k" not in out:
+        out["k"] = torch.empty(n, dtype=torch.float32, device=y.device)
+    if want_ind and "ind" not in out:
+        out["ind"] = torch.empty(n, dtype=torch.uint8, device=y.device)
+    e = _epi(mu, thresholds)
+    check(lib.epilogue_apply(_ptr(y), n, ctypes.byref(e), _ptr(out.get("k")), _ptr(out.get("ind")),
+                             _stream(stream)))
+    return out
+
+
+def _bwd_outputs(modes: Modes, dev):
+    return {"dphi": torch.empty(modes.n, dtype=torch.float32, device=dev),
+            "dk": torch.empty(modes.dim, modes.n, dtype=torch.float32, device=dev),
+            "dsigma": torch.empty(1, dtype=torch.float32, device=dev),
+            "dell": torch.empty(modes.dim, dtype=torch.float32, device=dev)}
+
+
+def field_backward(modes: Modes, xyz: torch.Tensor, grad_y: torch.Tensor, y_saved=None, stream=None):
+    """Gradients of L through Y at points, given grad_y = dL/dY (float32 [P])."""
+    lib = L.load()
+    dev = modes.z.device
+    P = int(xyz.shape[0])
+    m = modes.c()
+    need = ctypes.c_size_t()
+    check(lib.field_backward_ws_size(ctypes.byref(m), P, ctypes.byref(need)))
+    ws = _workspace(need.value, dev)
+    o = _bwd_outputs(modes, dev)
+    check(lib.field_backward(ctypes.byref(m), _ptr(xyz), P, _ptr(grad_y), _ptr(y_saved), _ptr(o["dphi"]),
+                             _ptr(o["dk"]), _ptr(o["dsigma"]), _ptr(o["dell"]), ctypes.c_void_p(ws.data_ptr()),
+                             ws.numel(), _stream(stream)))
+    return o
+
+
+def field_backward_grid(modes: Modes, shape, grad_y: torch.Tensor, origin=None, h=None, y_saved=None,
+                        stream=None):
+    """Gradients for a dense dL/dY over every cell of a structured grid."""
+    lib = L.load()
+    dev = modes.z.device
+    m, g = modes.c(), _grid(shape, origin, h)
+    need = ctypes.c_size_t()
+    check(lib.field_backward_grid_ws_size(ctypes.byref(m), ctypes.byref(g), ctypes.byref(need)))
+    ws = _workspace(need.value, dev)
+    o = _bwd_outputs(modes, dev)
+    check(lib.field_backward_grid(ctypes.byref(m), ctypes.byref(g), _ptr(grad_y), _ptr(y_saved), _ptr(o["dphi"]),
+                                  _ptr(o["dk"]), _ptr(o["dsigma"]), _ptr(o["dell"]),
+                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+    return o
+
+
+class GRFPoints(torch.autograd.Function):
+    """Y at fixed points as a differentiable function of (phi, z, sigma, ell).
+
+    forward(phi [n] f64, z [dim][n] f64, sigma (0-d f64), ell [dim] f64, xyz [P][dim] f64) -> Y [P] f32.
+    backward runs the library's adjoint kernel (field_backward); the gradient w.r.t. z
+    follows from k = z / ell: dL/dz_{a,j} = dL/dk_{a,j} / ell_a.
+    """
+
+    @staticmethod
+    def forward(ctx, phi, z, sigma, ell, xyz):
+        modes = Modes(z.detach().contiguous(), phi.detach().contiguous(), float(sigma),
+                      [float(v) for v in ell.detach().cpu()])
+        y = field_points(modes, xyz, method="direct_f32")["y"]
+        ctx.save_for_backward(phi, z, sigma, ell, xyz, y)
+        return y
+
+    @staticmethod
+    def backward(ctx, gy):
+        phi, z, sigma, ell, xyz, y = ctx.saved_tensors
+        modes = Modes(z.detach().contiguous(), phi.detach().contiguous(), float(sigma),
+                      [float(v) for v in ell.detach().cpu()])
+        g = field_backward(modes, xyz, gy.detach().to(torch.float32).contiguous(), y_saved=y)
+        ellv = ell.detach().to(torch.float64).reshape(-1, 1)
+        dz = g["dk"].to(torch.float64) / ellv
+        return (g["dphi"].to(phi.dtype), dz.to(z.dtype), g["dsigma"].reshape(()).to(sigma.dtype),
+                g["dell"].to(ell.dtype), None)
+
+
+class Plan:
+    """Batched ensembles on uneven grids (persistent launch + hipGraph + autotuner)."""
+
+    def __init__(self, method="sep_f16", graph=True, autotune=True, tune_cache: Optional[str] = None):
+        lib = L.load()
+        h = ctypes.c_void_p()
+        flags = (L.GRF_PLAN_GRAPH if graph else 0) | (L.GRF_PLAN_AUTOTUNE if autotune else 0)
+        check(lib.grf_plan_create(ctypes.byref(h), method_id(method), flags,
+                                  tune_cache.encode() if tune_cache else None))
+        self._h = h
+
+    def run(self, items, stream=None):
+        """items: list of (Modes, shape, y tensor) — y flat float32 device tensors."""
+        arr = (L.GrfBatchItem * len(items))()
+        for i, (m, shape, y) in enumerate(items):
+            arr[i].modes = m.c()
+            arr[i].grid = _grid(shape)
+            arr[i].y = y.data_ptr()
+        check(L.load().eval_field_batch(self._h, arr, len(items), _stream(stream)))
+
+    def info(self):
+        tm, tn, rep = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        wi = ctypes.c_int64()
+        check(L.load().grf_plan_info(self._h, ctypes.byref(tm), ctypes.byref(tn), ctypes.byref(rep),
+                                     ctypes.byref(wi)))
+        return {"tile_m": tm.value, "tile_n": tn.value, "replayed": rep.value, "work_items": wi.value}
+
+    def close(self):
+        if self._h:
+            L.load().grf_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

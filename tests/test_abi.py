@@ -1,0 +1,203 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports every
+symbol include/grf.h declares, validates arguments before touching the device,
+and its host sampler matches the oracle's bit for bit."""
+import ctypes
+import re
+from pathlib import Path
+
+import numpy as np
+import pytest
+
+from paper_2212_10961_amd import _lib as L
+from paper_2212_10961_amd import workloads as wl
+
+HEADER = Path(__file__).resolve().parents[1] / "include" / "grf.h"
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not L.LIB_PATH.exists():
+        import __graft_entry__
+        __graft_entry__.build()
+    return L.load()
+
+
+def _declared():
+    text = HEADER.read_text()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\**\s*([A-Za-z_][A-Za-z0-9_]*)\s*\(", text, re.M)
+    return sorted(set(n for n in names if n not in ("if", "while")))
+
+
+def test_exports_every_declared_symbol(lib):
+    declared = _declared()
+    assert set(declared) == set(L.EXPORTS), declared
+    for name in declared:
+        assert hasattr(lib, name), name
+
+
+def test_version_and_error_string(lib):
+    assert lib.grf_version() == 10000
+    assert isinstance(lib.grf_last_error(), bytes)
+
+
+def _spec(**kw):
+    s = L.GrfSpec()
+    s.dim, s.cov, s.n_modes, s.seed, s.sigma2 = 3, 0, 16, 1, 1.0
+    s.ell = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    s.nu = 0.5
+    for k, v in kw.items():
+        setattr(s, k, v)
+    return s
+
+
+@pytest.mark.parametrize("bad", [dict(dim=1), dict(dim=4), dict(n_modes=0), dict(cov=7), dict(cov=2, nu=0.3)])
+def test_make_modes_rejects(lib, bad):
+    s = _spec(**bad)
+    z = np.empty(64 * 3)
+    p = np.empty(64)
+    assert lib.make_modes(ctypes.byref(s), z.ctypes.data, p.ctypes.data) == L.GRF_EINVAL
+    assert len(lib.grf_last_error()) > 0
+    s = _spec()
+    assert lib.make_modes(ctypes.byref(s), None, p.ctypes.data) == L.GRF_EINVAL
+    assert lib.make_modes(None, z.ctypes.data, p.ctypes.data) == L.GRF_EINVAL
+
+
+@pytest.mark.parametrize("dim,cov,nu", [(2, 0, 0.5), (3, 0, 0.5), (2, 1, 0.5), (3, 1, 0.5), (3, 2, 1.0),
+                                        (2, 2, 1.5), (3, 2, 0.5)])
+def test_make_modes_matches_oracle_sampler(lib, orc, dim, cov, nu):
+    from paper_2212_10961_amd import grf
+    for seed in (0, 2, 0xFFFFFFFFFFFFFFFF, 123456789012345):
+        z, p = grf.make_modes(dim, cov, 333, seed, nu=nu)
+        zo, po = orc.sample_modes(dim, cov, 333, seed, nu=nu)
+        # phases come straight from the raw Philox words: identical bits
+        np.testing.assert_array_equal(p, po)
+        # wavevectors pass through libm (log, cos, sin, sqrt) built by two compilers:
+        # equal to a few ulp, and bit-equal for the vast majority of modes
+        np.testing.assert_allclose(z, zo, rtol=2e-15, atol=0)
+        assert np.count_nonzero(z != zo) <= z.size // 50
+
+
+def test_workload_seeds_match(lib, orc):
+    from paper_2212_10961_amd import grf
+    for name in ("grid2d_64_gauss", "grid3d_256_exp", "points_2m_gauss", "adjoint_grid3d_128"):
+        c = wl.WORKLOADS[name]
+        z, p = grf.make_modes(c["dim"], c["cov"], c["n_modes"], c["seed"])
+        zo, po = orc.sample_modes(c["dim"], c["cov"], c["n_modes"], c["seed"])
+        np.testing.assert_allclose(z, zo, rtol=2e-15, atol=0)
+        np.testing.assert_array_equal(p, po)
+
+
+def _modes(dim=3, n=16, z=1, phi=1, sigma=1.0, ell=(1.0, 1.0, 1.0)):
+    m = L.GrfModes()
+    m.dim, m.n, m.z, m.phi, m.sigma = dim, n, z, phi, sigma
+    m.ell = (ctypes.c_double * 3)(*ell)
+    return m
+
+
+def _grid(n=(8, 8, 8)):
+    g = L.GrfGrid()
+    g.n = (ctypes.c_int64 * 3)(*n)
+    g.origin = (ctypes.c_double * 3)(0, 0, 0)
+    g.h = (ctypes.c_double * 3)(1, 1, 1)
+    return g
+
+
+@pytest.mark.parametrize("mk,gk,meth,code", [
+    (dict(dim=1), {}, 0, L.GRF_EINVAL),
+    (dict(n=0), {}, 0, L.GRF_EINVAL),
+    (dict(z=None), {}, 0, L.GRF_EINVAL),
+    (dict(ell=(1.0, 0.0, 1.0)), {}, 0, L.GRF_EINVAL),
+    (dict(ell=(1.0, -2.0, 1.0)), {}, 0, L.GRF_EINVAL),
+    (dict(sigma=float("nan")), {}, 0, L.GRF_EINVAL),
+    ({}, dict(n=(0, 4, 4)), 0, L.GRF_EINVAL),
+    (dict(dim=2), dict(n=(4, 4, 2)), 0, L.GRF_EINVAL),
+    ({}, {}, 9, L.GRF_EINVAL),
+])
+def test_grid_validation_before_launch(lib, mk, gk, meth, code):
+    m, g = _modes(**mk), _grid(**gk)
+    bytes_ = ctypes.c_size_t()
+    assert lib.eval_field_grid_ws_size(ctypes.byref(m), ctypes.byref(g), meth, ctypes.byref(bytes_)) == code
+    # non-null fake device pointers: validation must reject before any launch
+    assert lib.eval_field_grid(ctypes.byref(m), ctypes.byref(g), meth, None, ctypes.c_void_p(16), None, None,
+                               ctypes.c_void_p(16), 1 << 30, None) == code
+
+
+def test_grid_output_and_workspace_checks(lib):
+    m, g = _modes(), _grid()
+    need = ctypes.c_size_t()
+    assert lib.eval_field_grid_ws_size(ctypes.byref(m), ctypes.byref(g), 0, ctypes.byref(need)) == 0
+    assert need.value > 0
+    # no output at all
+    assert lib.eval_field_grid(ctypes.byref(m), ctypes.byref(g), 0, None, None, None, None,
+                               ctypes.c_void_p(16), need.value, None) == L.GRF_EINVAL
+    # k requested without epilogue
+    assert lib.eval_field_grid(ctypes.byref(m), ctypes.byref(g), 0, None, None, ctypes.c_void_p(16), None,
+                               ctypes.c_void_p(16), need.value, None) == L.GRF_EINVAL
+    # workspace too small
+    assert lib.eval_field_grid(ctypes.byref(m), ctypes.byref(g), 0, None, ctypes.c_void_p(16), None, None,
+                               ctypes.c_void_p(16), need.value - 1, None) == L.GRF_ENOMEM
+    # indicator without thresholds / unsorted thresholds
+    e = L.GrfEpi()
+    e.n_thresholds = 0
+    assert lib.eval_field_grid(ctypes.byref(m), ctypes.byref(g), 0, ctypes.byref(e), None, None,
+                               ctypes.c_void_p(16), ctypes.c_void_p(16), need.value, None) == L.GRF_EINVAL
+    e.n_thresholds = 2
+    e.thresholds[0], e.thresholds[1] = 1.0, 0.5
+    assert lib.eval_field_grid(ctypes.byref(m), ctypes.byref(g), 0, ctypes.byref(e), None, None,
+                               ctypes.c_void_p(16), ctypes.c_void_p(16), need.value, None) == L.GRF_EINVAL
+    e.n_thresholds = 16
+    assert lib.eval_field_grid(ctypes.byref(m), ctypes.byref(g), 0, ctypes.byref(e), None, None,
+                               ctypes.c_void_p(16), ctypes.c_void_p(16), need.value, None) == L.GRF_EINVAL
+
+
+def test_workspace_sizes_scale(lib):
+    m = _modes(n=4096)
+    need = {}
+    for meth in range(6):
+        b = ctypes.c_size_t()
+        assert lib.eval_field_grid_ws_size(ctypes.byref(m), ctypes.byref(_grid((256, 256, 256))), meth,
+                                           ctypes.byref(b)) == 0
+        need[meth] = b.value
+    assert need[1] == 2 * need[0]                 # FP64 vs FP32 revolution tables
+    assert need[4] > need[2] and need[5] > need[3]  # hi+lo tables
+    # AUTO on a large grid resolves to the separable fp16 form
+    b = ctypes.c_size_t()
+    assert lib.eval_field_grid_ws_size(ctypes.byref(m), ctypes.byref(_grid((256, 256, 256))), -1,
+                                       ctypes.byref(b)) == 0
+    assert b.value == need[3]
+
+
+def test_points_validation(lib):
+    m = _modes()
+    b = ctypes.c_size_t()
+    assert lib.eval_field_points_ws_size(ctypes.byref(m), 10, L.GRF_SEP_F16, ctypes.byref(b)) == L.GRF_EUNSUPPORTED
+    assert lib.eval_field_points_ws_size(ctypes.byref(m), -1, 0, ctypes.byref(b)) == L.GRF_EINVAL
+    assert lib.eval_field_points_ws_size(ctypes.byref(m), 10, 0, ctypes.byref(b)) == 0
+    # P = 0 is a no-op even with null pointers
+    assert lib.eval_field_points(ctypes.byref(m), None, 0, 0, None, ctypes.c_void_p(16), None, None, None, 0,
+                                 None) == 0
+    assert lib.eval_field_points(ctypes.byref(m), None, 5, 0, None, ctypes.c_void_p(16), None, None,
+                                 ctypes.c_void_p(16), b.value, None) == L.GRF_EINVAL
+    assert lib.eval_field_points(ctypes.byref(m), ctypes.c_void_p(16), 5, 0, None, ctypes.c_void_p(16), None,
+                                 None, ctypes.c_void_p(16), b.value - 1, None) == L.GRF_ENOMEM
+
+
+def test_epilogue_and_backward_validation(lib):
+    e = L.GrfEpi()
+    e.mu = 0.0
+    e.n_thresholds = 1
+    assert lib.epilogue_apply(None, 0, ctypes.byref(e), ctypes.c_void_p(16), None, None) == 0
+    assert lib.epilogue_apply(None, 4, ctypes.byref(e), ctypes.c_void_p(16), None, None) == L.GRF_EINVAL
+    assert lib.epilogue_apply(ctypes.c_void_p(16), 4, None, ctypes.c_void_p(16), None, None) == L.GRF_EINVAL
+    assert lib.epilogue_apply(ctypes.c_void_p(16), -1, ctypes.byref(e), ctypes.c_void_p(16), None, None) == L.GRF_EINVAL
+    m = _modes()
+    b = ctypes.c_size_t()
+    assert lib.field_backward_ws_size(ctypes.byref(m), 1000, ctypes.byref(b)) == 0
+    assert lib.field_backward(ctypes.byref(m), ctypes.c_void_p(16), 1000, ctypes.c_void_p(16), None, None, None,
+                              None, None, ctypes.c_void_p(16), b.value, None) == L.GRF_EINVAL  # no outputs
+    assert lib.field_backward(ctypes.byref(m), ctypes.c_void_p(16), 1000, None, None, ctypes.c_void_p(16), None,
+                              None, None, ctypes.c_void_p(16), b.value, None) == L.GRF_EINVAL  # no grad_y
+    assert lib.field_backward(ctypes.byref(m), ctypes.c_void_p(16), 1000, ctypes.c_void_p(16), None,
+                              ctypes.c_void_p(16), None, None, None, ctypes.c_void_p(16), b.value - 1,
+                              None) == L.GRF_ENOMEM

@@ -1,0 +1,223 @@
+"""GPU parity: the HIP path through the C ABI against the FP64 oracle, element by element.
+
+Each side draws its own mode table from the same seed (library sampler vs oracle
+sampler); all other inputs come from paper_2212_10961_amd.workloads.  Tolerances are
+stated in tests/gpu_common.py.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import TOL, assert_field, assert_indicator, errors, modes_pair, to_np
+from paper_2212_10961_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+METHODS = ["direct_f32", "direct_f64", "sep_f16", "sep_bf16", "sep_f16_x3", "sep_bf16_x3"]
+
+
+@pytest.fixture(scope="module")
+def grf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2212_10961_amd.grf as g
+    return g
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+# ------------------------------------------------------------------ plain FP64 workload (64x64)
+
+def test_grid2d_64_gauss_plain(orc, grf):
+    c = wl.WORKLOADS["grid2d_64_gauss"]
+    sigma = math.sqrt(c["sigma2"])
+    _say("case grid2d_64_gauss direct_f64/direct_f32")
+    (zo, po), m = modes_pair(orc, grf, c["dim"], c["cov"], c["n_modes"], c["seed"], sigma, c["ell"])
+    ref = orc.field_grid(zo, po, sigma, c["ell"], c["shape"])
+    kref = orc.lognormal(ref, c["mu"])
+    o64 = grf.field_grid_f64(m, c["shape"], mu=c["mu"])
+    y64, k64 = to_np(o64["y"]), to_np(o64["k"])
+    assert np.max(np.abs(y64 - ref)) <= 1e-11 * sigma
+    assert np.max(np.abs(k64 - kref) / kref) <= 1e-11
+    for meth in ("direct_f64", "direct_f32", "sep_f16_x3"):
+        o = grf.field_grid(m, c["shape"], method=meth, mu=c["mu"], want_k=True)
+        y, k = to_np(o["y"]), to_np(o["k"])
+        if meth == "direct_f64":
+            assert np.max(np.abs(y - ref)) <= 1e-6 * sigma  # FP32 store of an FP64 sum
+        else:
+            assert_field(y, ref, sigma, meth, "grid2d_64")
+        assert np.max(np.abs(k - kref) / kref) <= 3 * TOL["sep_f16_x3"]["band"] * sigma + 1e-6
+
+
+# ------------------------------------------------------------------ ragged multi-tile grids
+
+@pytest.mark.parametrize("meth", METHODS)
+def test_grid3d_ragged_all_methods(orc, grf, meth):
+    shape, o, h, ell = (70, 45, 9), (0.5, -3.0, 2.0), (1.0, 1.5, 0.75), (6.0, 5.0, 2.0)
+    sigma = 1.7
+    _say(f"case grid3d_ragged {shape} N=100 exp {meth}")
+    (zo, po), m = modes_pair(orc, grf, 3, wl.EXPONENTIAL, 100, 77, sigma, ell)
+    ref = orc.field_grid(zo, po, sigma, ell, shape, origin=o, h=h)
+    out = grf.field_grid(m, shape, origin=o, h=h, method=meth, mu=0.25, thresholds=[-0.5, 0.3, 1.0],
+                         want_k=True, want_ind=True)
+    y = to_np(out["y"])
+    assert_field(y, ref, sigma, meth, "grid3d_ragged")
+    kref = orc.lognormal(ref, 0.25)
+    band = TOL[meth]["band"] * sigma
+    assert np.max(np.abs(to_np(out["k"]) - kref) / kref) <= 1.01 * band + 1e-6
+    assert_indicator(to_np(out["ind"]), ref, [-0.5, 0.3, 1.0], sigma, meth)
+
+
+@pytest.mark.parametrize("meth", ["direct_f32", "sep_f16", "sep_f16_x3", "sep_bf16_x3"])
+def test_grid2d_ragged(orc, grf, meth):
+    shape, ell, sigma = (150, 97), (9.0, 4.0), 1.0
+    _say(f"case grid2d_ragged {shape} N=65 gauss {meth}")
+    (zo, po), m = modes_pair(orc, grf, 2, wl.GAUSSIAN, 65, 78, sigma, ell)
+    ref = orc.field_grid(zo, po, sigma, ell, shape, origin=(3.0, -7.0), h=(0.5, 2.0))
+    y = to_np(grf.field_grid(m, shape, origin=(3.0, -7.0), h=(0.5, 2.0), method=meth)["y"])
+    assert_field(y, ref, sigma, meth, "grid2d_ragged")
+
+
+@pytest.mark.parametrize("shape", [(1, 1, 1), (1, 7, 3), (33, 1, 1), (64, 64, 1), (300, 2, 2)])
+@pytest.mark.parametrize("meth", ["direct_f32", "sep_f16_x3"])
+def test_grid_degenerate_shapes(orc, grf, shape, meth):
+    _say(f"case degenerate {shape} {meth}")
+    (zo, po), m = modes_pair(orc, grf, 3, wl.GAUSSIAN, 7, 79, 1.0, (2.0, 3.0, 1.0))
+    ref = orc.field_grid(zo, po, 1.0, (2.0, 3.0, 1.0), shape)
+    y = to_np(grf.field_grid(m, shape, method=meth)["y"])
+    assert_field(y, ref, 1.0, meth, f"degenerate{shape}")
+
+
+@pytest.mark.parametrize("meth", ["direct_f32", "direct_f64", "sep_f16_x3"])
+def test_single_mode_closed_form_gpu(grf, meth):
+    # N=1, k=(2 pi/8, 0, 0), phi=0: Y_i = sqrt(2) cos(pi (2i+1)/8)
+    _say(f"case single_mode {meth}")
+    z = np.array([[2 * math.pi / 8], [0.0], [0.0]])
+    m = grf.modes_from_tables(z, np.zeros(1), 1.0, (1.0, 1.0, 1.0))
+    y = to_np(grf.field_grid(m, (16, 3, 2), method=meth)["y"]).reshape(2, 3, 16)
+    c1, c3 = math.sqrt(2 + math.sqrt(2)) / 2, math.sqrt(2 - math.sqrt(2)) / 2
+    pat = np.sqrt(2.0) * np.array([c1, c3, -c3, -c1, -c1, -c3, c3, c1] * 2)
+    tol = {"direct_f32": 1e-6, "direct_f64": 1e-7, "sep_f16_x3": 2e-6}[meth]
+    np.testing.assert_allclose(y, np.broadcast_to(pat, y.shape), atol=tol, rtol=0)
+
+
+# ------------------------------------------------------------------ full-size workloads, sampled
+
+@pytest.mark.parametrize("meth", ["direct_f32", "sep_f16", "sep_bf16", "sep_f16_x3", "sep_bf16_x3"])
+def test_grid3d_256_exp_sampled(orc, grf, meth):
+    c = wl.WORKLOADS["grid3d_256_exp"]
+    sigma = math.sqrt(c["sigma2"])
+    _say(f"case grid3d_256_exp full size {meth}")
+    (zo, po), m = modes_pair(orc, grf, 3, c["cov"], c["n_modes"], c["seed"], sigma, c["ell"])
+    out = grf.field_grid(m, c["shape"], method=meth, mu=c["mu"], want_k=True)
+    C = int(np.prod(c["shape"]))
+    cells = wl.sample_cells(C, 1500, 902)
+    ref = orc.field_cells(zo, po, sigma, c["ell"], c["shape"], cells)
+    y = to_np(out["y"])[cells]
+    assert_field(y, ref, sigma, meth, "grid3d_256 sampled")
+    k = to_np(out["k"])[cells]
+    kref = orc.lognormal(ref, c["mu"])
+    assert np.max(np.abs(k - kref) / kref) <= 1.01 * TOL[meth]["band"] * sigma + 1e-6
+
+
+def test_points_small_and_indicator(orc, grf):
+    c = wl.WORKLOADS["points_2m_gauss"]
+    sigma = math.sqrt(c["sigma2"])
+    x = wl.points_uniform(3001, c["box"], 903)
+    xt = torch.from_numpy(x).cuda()
+    _say("case points 3001 N=777")
+    (zo, po), m = modes_pair(orc, grf, 3, c["cov"], 777, 904, sigma, c["ell"])
+    ref = orc.field_points(zo, po, sigma, c["ell"], x)
+    for meth in ("direct_f32", "direct_f64"):
+        out = grf.field_points(m, xt, method=meth, mu=0.1, thresholds=[c["threshold"]], want_k=True, want_ind=True)
+        y = to_np(out["y"])
+        if meth == "direct_f64":
+            assert np.max(np.abs(y - ref)) <= 1e-6 * sigma
+        else:
+            assert_field(y, ref, sigma, meth, "points3001")
+            assert_indicator(to_np(out["ind"]), ref, [c["threshold"]], sigma, meth)
+        kref = orc.lognormal(ref, 0.1)
+        assert np.max(np.abs(to_np(out["k"]) - kref) / kref) <= 2e-4
+
+
+def test_points_2d_exponential_large_phases(orc, grf):
+    # heavy-tailed wavevectors and far-from-origin points: the FP64 phase reduction matters
+    x = wl.points_uniform(2000, (5000.0, 3000.0), 905) + np.array([1e5, -2e5])
+    _say("case points2d exp offset N=300")
+    (zo, po), m = modes_pair(orc, grf, 2, wl.EXPONENTIAL, 300, 906, 1.0, (3.0, 1.0))
+    ref = orc.field_points(zo, po, 1.0, (3.0, 1.0), x)
+    y = to_np(grf.field_points(m, torch.from_numpy(x).cuda())["y"])
+    assert_field(y, ref, 1.0, "direct_f32", "points2d_offset")
+
+
+def test_points_edge_counts(orc, grf):
+    (zo, po), m = modes_pair(orc, grf, 3, wl.GAUSSIAN, 64, 907, 1.0, (1.0, 2.0, 3.0))
+    _say("case points P=0,1,1025")
+    out = grf.field_points(m, torch.zeros(0, 3, dtype=torch.float64, device="cuda"))
+    assert out["y"].numel() == 0
+    for P in (1, 1025):
+        x = wl.points_uniform(P, (10.0, 10.0, 10.0), 908 + P)
+        ref = orc.field_points(zo, po, 1.0, (1.0, 2.0, 3.0), x)
+        y = to_np(grf.field_points(m, torch.from_numpy(x).cuda())["y"])
+        assert_field(y, ref, 1.0, "direct_f32", f"P={P}")
+
+
+def test_points_2m_gauss_sampled(orc, grf):
+    c = wl.WORKLOADS["points_2m_gauss"]
+    sigma = math.sqrt(c["sigma2"])
+    x = wl.points_uniform(c["n_points"], c["box"], c["point_seed"])
+    _say("case points_2m_gauss full size")
+    (zo, po), m = modes_pair(orc, grf, 3, c["cov"], c["n_modes"], c["seed"], sigma, c["ell"])
+    out = grf.field_points(m, torch.from_numpy(x).cuda(), thresholds=[c["threshold"]], want_ind=True)
+    idx = wl.sample_cells(c["n_points"], 1500, 910)
+    ref = orc.field_points(zo, po, sigma, c["ell"], x[idx])
+    assert_field(to_np(out["y"])[idx], ref, sigma, "direct_f32", "points_2m sampled")
+    ind = to_np(out["ind"])
+    assert_indicator(ind[idx], ref, [c["threshold"]], sigma, "direct_f32")
+    frac = ind.mean()
+    print(f"  indicator proportion {frac:.4f} (Gaussian law 0.36184)")
+    assert abs(frac - 0.36184) < 0.03
+
+
+def test_resolution_independence_gpu(orc, grf):
+    """Sec. 4.1: the same modes give the same field at any resolution or on any mesh."""
+    (zo, po), m = modes_pair(orc, grf, 3, wl.EXPONENTIAL, 256, 911, 1.0, (8.0, 8.0, 2.0))
+    _say("case resolution independence")
+    coarse = to_np(grf.field_grid(m, (20, 12, 6), h=(3.0, 3.0, 3.0))["y"]).reshape(6, 12, 20)
+    fine = to_np(grf.field_grid(m, (60, 36, 18), h=(1.0, 1.0, 1.0))["y"]).reshape(18, 36, 60)
+    # coincident centres; both carry the DIRECT_F32 error
+    assert np.max(np.abs(fine[1::3, 1::3, 1::3] - coarse)) <= 2 * TOL["direct_f32"]["band"]
+    pts = orc.grid_centres((20, 12, 6), h=(3.0, 3.0, 3.0))
+    yp = to_np(grf.field_points(m, torch.from_numpy(pts).cuda())["y"]).reshape(6, 12, 20)
+    assert np.max(np.abs(yp - coarse)) <= 2 * TOL["direct_f32"]["band"]
+
+
+# ------------------------------------------------------------------ stand-alone epilogue
+
+@pytest.mark.parametrize("n", [0, 1, 7, 4096, 1_000_003])
+def test_epilogue_standalone(orc, grf, n):
+    _say(f"case epilogue n={n}")
+    y = (wl.rng(912, n).standard_normal(n) * 1.5).astype(np.float32)
+    yt = torch.from_numpy(y).cuda()
+    out = grf.epilogue(yt, mu=-0.3, thresholds=[-1.0, 0.0, 0.5], want_k=True, want_ind=True)
+    k, ind = to_np(out["k"]), to_np(out["ind"])
+    y64 = y.astype(np.float64)
+    if n:
+        kref = orc.lognormal(y64, -0.3)
+        assert np.max(np.abs(k - kref) / kref) <= 4e-7
+        np.testing.assert_array_equal(ind, orc.facies(y64, [-1.0, 0.0, 0.5]))
+
+
+# ------------------------------------------------------------------ determinism
+
+def test_bitwise_reproducible(orc, grf):
+    (zo, po), m = modes_pair(orc, grf, 3, wl.EXPONENTIAL, 1000, 913, 1.0, (4.0, 4.0, 1.0))
+    _say("case determinism")
+    for meth in ("direct_f32", "sep_f16", "sep_f16_x3"):
+        a = to_np(grf.field_grid(m, (96, 80, 7), method=meth)["y"])
+        b = to_np(grf.field_grid(m, (96, 80, 7), method=meth)["y"])
+        np.testing.assert_array_equal(a, b)
