@@ -236,6 +236,19 @@ int eval_field_batch(grf_plan* plan, const grf_batch_item* items, int32_t n, voi
 int grf_plan_info(const grf_plan* plan, int32_t* tile_m, int32_t* tile_n, int32_t* replayed,
                   int64_t* work_items);
 
+/*
+ * Kernel timer (instrumentation for benchmarks).  While enabled, every call records a
+ * pair of HIP events on its stream around its main kernel: the sum kernel of
+ * eval_field_grid / eval_field_points, the epilogue kernel of epilogue_apply, the main
+ * adjoint kernel of field_backward(_grid) and the persistent kernel of eval_field_batch.
+ *   grf_kernel_timer_enable(1) clears the record and starts recording; (0) stops.
+ *   grf_kernel_timer_read waits for the recorded events and returns the summed kernel
+ *   time (ms) and the number of timed launches.  Events are created on first use and
+ *   reused; recording is process-wide and guarded by a mutex.
+ */
+int grf_kernel_timer_enable(int enable);
+int grf_kernel_timer_read(double* total_ms, int64_t* launches);
+
 #ifdef __cplusplus
 }
 #endif

@@ -79,6 +79,13 @@ def _load():
     return _lib
 
 
+def threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    lib = _load()
+    lib.orc_threads.restype = ctypes.c_int
+    return int(lib.orc_threads())
+
+
 def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 

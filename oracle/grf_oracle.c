@@ -44,6 +44,20 @@
 
 #define ORC_PI 3.14159265358979323846
 
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Threads the OpenMP loops below will use (1 without OpenMP). */
+int orc_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
 /* ------------------------------------------------------------------ RNG */
 
 static uint32_t orc_mulhi32(uint32_t a, uint32_t b, uint32_t* lo)

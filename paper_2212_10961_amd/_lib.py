@@ -29,6 +29,7 @@ EXPORTS = [
     "eval_field_grid_f64", "eval_field_points_ws_size", "eval_field_points", "epilogue_apply",
     "field_backward_ws_size", "field_backward", "field_backward_grid_ws_size", "field_backward_grid",
     "grf_plan_create", "grf_plan_destroy", "eval_field_batch", "grf_plan_info",
+    "grf_kernel_timer_enable", "grf_kernel_timer_read",
 ]
 
 
@@ -97,6 +98,8 @@ def load():
         "grf_plan_destroy": ([vp], ctypes.c_int),
         "eval_field_batch": ([vp, P(GrfBatchItem), i32, vp], ctypes.c_int),
         "grf_plan_info": ([vp, P(i32), P(i32), P(i32), P(i64)], ctypes.c_int),
+        "grf_kernel_timer_enable": ([ctypes.c_int], ctypes.c_int),
+        "grf_kernel_timer_read": ([P(ctypes.c_double), P(i64)], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)

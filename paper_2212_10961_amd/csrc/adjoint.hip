@@ -195,6 +195,7 @@ hipError_t launch_backward(const BwdArgs& a, hipStream_t s)
         geo.hz = a.dim == 3 ? a.gh[2] : 0.0;
     }
     const bool want_c = a.gsigma != nullptr && a.ysaved == nullptr;
+    timer_mark(s, true);
     if (a.dim == 3) {
         if (grid) launch_bwd_main<3, true>(a, chunk, geo, want_c, s);
         else launch_bwd_main<3, false>(a, chunk, geo, want_c, s);
@@ -202,6 +203,7 @@ hipError_t launch_backward(const BwdArgs& a, hipStream_t s)
         if (grid) launch_bwd_main<2, true>(a, chunk, geo, want_c, s);
         else launch_bwd_main<2, false>(a, chunk, geo, want_c, s);
     }
+    timer_mark(s, false);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
 

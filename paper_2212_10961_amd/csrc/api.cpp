@@ -3,6 +3,8 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
+#include <vector>
 
 #include "grf_internal.h"
 
@@ -17,6 +19,35 @@ int fail(int code, const char* fmt, ...)
     std::vsnprintf(g_err, sizeof(g_err), fmt, ap);
     va_end(ap);
     return code;
+}
+
+namespace {
+struct KernelTimer {
+    std::mutex mu;
+    bool on = false;
+    std::vector<hipEvent_t> ev;  // start/stop pairs
+    size_t used = 0;             // events recorded since enable
+};
+KernelTimer& ktimer()
+{
+    static KernelTimer t;
+    return t;
+}
+}  // namespace
+
+void timer_mark(hipStream_t s, bool begin)
+{
+    KernelTimer& t = ktimer();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (!t.on) return;
+    if (begin && (t.used & 1)) return;   // unmatched begin: ignore
+    if (!begin && !(t.used & 1)) return; // stop without start
+    if (t.used == t.ev.size()) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return;
+        t.ev.push_back(e);
+    }
+    if (hipEventRecord(t.ev[t.used], s) == hipSuccess) ++t.used;
 }
 
 int fail_hip(hipError_t e, const char* what)
@@ -35,7 +66,7 @@ Epi make_epi(const grf_epi* e)
     return r;
 }
 
-static int check_modes(const grf_modes* m, const char* fn)
+int check_modes(const grf_modes* m, const char* fn)
 {
     if (!m) return fail(GRF_EINVAL, "%s: modes is NULL", fn);
     if (m->dim != 2 && m->dim != 3) return fail(GRF_EINVAL, "%s: dim must be 2 or 3 (got %d)", fn, m->dim);
@@ -49,7 +80,7 @@ static int check_modes(const grf_modes* m, const char* fn)
     return GRF_OK;
 }
 
-static int check_grid(const grf_grid* g, int dim, const char* fn)
+int check_grid(const grf_grid* g, int dim, const char* fn)
 {
     if (!g) return fail(GRF_EINVAL, "%s: grid is NULL", fn);
     for (int a = 0; a < 3; ++a) {
@@ -78,9 +109,6 @@ static int check_epi(const grf_epi* e, const float* k, const uint8_t* ind, const
     return GRF_OK;
 }
 
-static bool is_sep(int m) { return m >= GRF_SEP_BF16 && m <= GRF_SEP_F16_X3; }
-static bool is_hilo(int m) { return m == GRF_SEP_BF16_X3 || m == GRF_SEP_F16_X3; }
-static bool is_bf16(int m) { return m == GRF_SEP_BF16 || m == GRF_SEP_BF16_X3; }
 
 static int resolve_grid_method(int method, const grf_grid* g)
 {
@@ -91,15 +119,7 @@ static int resolve_grid_method(int method, const grf_grid* g)
     return method;
 }
 
-// Workspace layout of eval_field_grid for a resolved method.  With `base` == nullptr
-// it only measures.
-struct GridWs {
-    void* t[3] = {nullptr, nullptr, nullptr};
-    void* tlo[3] = {nullptr, nullptr, nullptr};
-    size_t bytes = 0;
-};
-
-static GridWs grid_ws(const grf_modes* m, const grf_grid* g, int method, void* base)
+GridWs grid_ws(const grf_modes* m, const grf_grid* g, int method, void* base)
 {
     GridWs w;
     Carve c(base);
@@ -115,7 +135,9 @@ static GridWs grid_ws(const grf_modes* m, const grf_grid* g, int method, void* b
             w.t[0] = c.take<uint32_t>(size_t(g->n[0]) * ldp);
             if (hilo) w.tlo[0] = c.take<uint32_t>(size_t(g->n[0]) * ldp);
         } else {
-            w.t[0] = c.take<float2>(size_t(g->n[0]) * ldp);
+            // Ex feeds the on-the-fly product Ex * Ez[z]: half pairs for one pass, float2 for hi+lo
+            if (hilo) w.t[0] = c.take<float2>(size_t(g->n[0]) * ldp);
+            else w.t[0] = c.take<uint32_t>(size_t(g->n[0]) * ldp);
             w.t[2] = c.take<float2>(size_t(g->n[2]) * ldp);
         }
         w.t[1] = c.take<uint32_t>(size_t(g->n[1]) * ldp);
@@ -125,10 +147,10 @@ static GridWs grid_ws(const grf_modes* m, const grf_grid* g, int method, void* b
     return w;
 }
 
-static hipError_t build_tables(const grf_modes* m, const grf_grid* g, int method, const GridWs& w,
-                               hipStream_t s)
+int grid_table_descs(const grf_modes* m, const grf_grid* g, int method, const GridWs& w, AxisTableArgs* out)
 {
     const int64_t ldp = padded_modes(m->n);
+    int nd = 0;
     for (int a = 0; a < 3; ++a) {
         AxisTableArgs t{};
         t.z = m->z;
@@ -154,13 +176,27 @@ static hipError_t build_tables(const grf_modes* m, const grf_grid* g, int method
             if (a == 1 || (a == 0 && m->dim == 2)) {
                 t.format = bf ? (hilo ? TF_BF16_HILO : TF_BF16) : (hilo ? TF_F16_HILO : TF_F16);
                 t.conj = (a == 0);
-            } else if (a == 0 || (a == 2 && m->dim == 3)) {
+            } else if (a == 0) {  // 3-D x axis: (Re, -Im) Ex for the product with Ez
+                t.format = hilo ? TF_CPLX_F32 : (bf ? TF_BF16 : TF_F16);
+                t.conj = true;
+            } else if (a == 2 && m->dim == 3) {
                 t.format = TF_CPLX_F32;
             } else {
                 continue;  // dim 2: no z table for the separable form
             }
         }
-        hipError_t e = launch_axis_table(t, s);
+        out[nd++] = t;
+    }
+    return nd;
+}
+
+static hipError_t build_tables(const grf_modes* m, const grf_grid* g, int method, const GridWs& w,
+                               hipStream_t s)
+{
+    AxisTableArgs d[3];
+    const int nd = grid_table_descs(m, g, method, w, d);
+    for (int i = 0; i < nd; ++i) {
+        hipError_t e = launch_axis_table(d[i], s);
         if (e != hipSuccess) return e;
     }
     return hipSuccess;
@@ -173,6 +209,33 @@ using namespace grf;
 extern "C" {
 
 int grf_version(void) { return GRF_VERSION; }
+
+int grf_kernel_timer_enable(int enable)
+{
+    KernelTimer& t = ktimer();
+    std::lock_guard<std::mutex> lk(t.mu);
+    t.on = enable != 0;
+    if (t.on) t.used = 0;
+    return GRF_OK;
+}
+
+int grf_kernel_timer_read(double* total_ms, int64_t* launches)
+{
+    if (!total_ms || !launches) return fail(GRF_EINVAL, "grf_kernel_timer_read: NULL output");
+    KernelTimer& t = ktimer();
+    std::lock_guard<std::mutex> lk(t.mu);
+    double sum = 0.0;
+    const size_t pairs = t.used / 2;
+    for (size_t i = 0; i < pairs; ++i) {
+        GRF_HIP(hipEventSynchronize(t.ev[2 * i + 1]));
+        float ms = 0.f;
+        GRF_HIP(hipEventElapsedTime(&ms, t.ev[2 * i], t.ev[2 * i + 1]));
+        sum += ms;
+    }
+    *total_ms = sum;
+    *launches = static_cast<int64_t>(pairs);
+    return GRF_OK;
+}
 
 const char* grf_last_error(void) { return g_err; }
 
@@ -210,6 +273,7 @@ int eval_field_grid(const grf_modes* modes, const grf_grid* grid, int method, co
     const int64_t ldp = padded_modes(modes->n);
 
     GRF_HIP(build_tables(modes, grid, method, w, s));
+    TimedScope timed(s);
     if (method == GRF_DIRECT_F32) {
         GRF_HIP(launch_direct_grid_f32(static_cast<const float*>(w.t[0]), static_cast<const float*>(w.t[1]),
                                        static_cast<const float*>(w.t[2]), modes->n, ldp, grid->n, amp, e,
@@ -237,7 +301,7 @@ int eval_field_grid(const grf_modes* modes, const grf_grid* grid, int method, co
         a.y = y;
         a.k = k;
         a.ind = ind;
-        a.tile = 0;
+        a.tile = -1;  // size-based default
         GRF_HIP(launch_sep(a, s));
     }
     return GRF_OK;
@@ -302,6 +366,7 @@ int eval_field_points(const grf_modes* modes, const double* xyz, int64_t n_point
     const int64_t ldp = padded_modes(modes->n);
     GRF_HIP(launch_mode_params(modes->z, modes->phi, modes->dim, modes->n, ldp, modes->ell, params, s));
     const float amp = static_cast<float>(modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n)));
+    TimedScope timed(s);
     GRF_HIP(launch_direct_points(params, modes->n, modes->dim, xyz, n_points, method == GRF_DIRECT_F64, amp,
                                  make_epi(epi), y, k, ind, s));
     return GRF_OK;
@@ -317,6 +382,7 @@ int epilogue_apply(const float* y, int64_t n, const grf_epi* epi, float* k, uint
     if (n == 0) return GRF_OK;
     if (!k && !ind) return fail(GRF_EINVAL, "%s: no output requested", fn);
     if (!y) return fail(GRF_EINVAL, "%s: y is NULL", fn);
+    TimedScope timed(static_cast<hipStream_t>(stream));
     GRF_HIP(launch_epilogue(y, n, make_epi(epi), k, ind, static_cast<hipStream_t>(stream)));
     return GRF_OK;
 }

@@ -36,21 +36,18 @@ __device__ __forceinline__ void store_out(int64_t c, float yv, const Epi& e, flo
 constexpr int kDgB = 64;
 constexpr int kDgJ = 64;
 constexpr int kDgRow = (kDgJ + 4) / 4;  // float4 per padded row
+static_assert(kDgB == kDirectTile, "tile side shared with the batch planner");
 
-__global__ __launch_bounds__(256, 2) void k_direct_grid(const float* __restrict__ tx, const float* __restrict__ ty,
-                                                       const float* __restrict__ tz, int n, int64_t ldp, int nx,
-                                                       int ny, int64_t nq, int nxt, float amp, Epi epi,
-                                                       float* __restrict__ y, float* __restrict__ k,
-                                                       uint8_t* __restrict__ ind)
+// One 64 x 64 (x, (y,z)) tile; `sx`, `sq` are LDS arrays of kDgB * kDgRow float4.  Whole block.
+__device__ __forceinline__ void direct_tile(const float* __restrict__ tx, const float* __restrict__ ty,
+                                            const float* __restrict__ tz, int n, int64_t ldp, int nx, int ny,
+                                            int64_t nq, int x0, int64_t q0, float amp, const Epi& epi,
+                                            float* __restrict__ y, float* __restrict__ k, uint8_t* __restrict__ ind,
+                                            float4* sx, float4* sq)
 {
-    __shared__ float4 sx[kDgB * kDgRow];
-    __shared__ float4 sq[kDgB * kDgRow];
     const int t = threadIdx.x;
     const int w = t >> 6, l = t & 63;
     const int lx = l & 15, lq = w * 16 + (l >> 4);
-    const int64_t bid = blockIdx.x;
-    const int x0 = static_cast<int>(bid % nxt) * kDgB;
-    const int64_t q0 = (bid / nxt) * kDgB;
 
     float acc[4][4];
 #pragma unroll
@@ -110,6 +107,47 @@ __global__ __launch_bounds__(256, 2) void k_direct_grid(const float* __restrict_
             const int64_t q = q0 + lq + 4 * b;
             if (x < nx && q < nq) store_out(q * nx + x, amp * acc[a][b], epi, y, k, ind);
         }
+    }
+}
+
+__global__ __launch_bounds__(256, 2) void k_direct_grid(const float* __restrict__ tx, const float* __restrict__ ty,
+                                                       const float* __restrict__ tz, int n, int64_t ldp, int nx,
+                                                       int ny, int64_t nq, int nxt, float amp, Epi epi,
+                                                       float* __restrict__ y, float* __restrict__ k,
+                                                       uint8_t* __restrict__ ind)
+{
+    __shared__ float4 sx[kDgB * kDgRow];
+    __shared__ float4 sq[kDgB * kDgRow];
+    const int64_t bid = blockIdx.x;
+    direct_tile(tx, ty, tz, n, ldp, nx, ny, nq, static_cast<int>(bid % nxt) * kDgB, (bid / nxt) * kDgB, amp, epi, y,
+                k, ind, sx, sq);
+}
+
+// Persistent batched form: blocks pull (instance, tile) work items from one atomic counter
+// until the queue is drained.
+__global__ __launch_bounds__(256, 2) void k_direct_batch(const DirectBatchItem* __restrict__ items, int n_inst,
+                                                        int64_t total, unsigned long long* counter)
+{
+    __shared__ float4 sx[kDgB * kDgRow];
+    __shared__ float4 sq[kDgB * kDgRow];
+    __shared__ unsigned long long s_item;
+    const Epi none{};
+    for (;;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1ull);
+        __syncthreads();
+        const int64_t it = static_cast<int64_t>(s_item);
+        __syncthreads();
+        if (it >= total) break;
+        int lo = 0, hi = n_inst - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].item0 <= it) lo = mid;
+            else hi = mid - 1;
+        }
+        const DirectBatchItem& b = items[lo];
+        const int64_t local = it - b.item0;
+        direct_tile(b.tx, b.ty, b.tz, b.n, b.ldp, b.nx, b.ny, b.nq, static_cast<int>(local % b.nxt) * kDgB,
+                    (local / b.nxt) * kDgB, b.amp, none, b.y, nullptr, nullptr, sx, sq);
     }
 }
 
@@ -294,6 +332,20 @@ hipError_t launch_direct_points(const double* params, int64_t n, int dim, const 
         hipLaunchKernelGGL((k_direct_points<2, R>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, prm,
                            static_cast<int>(n), xyz, P, amp, epi, y, k, ind);
     return hipGetLastError();
+}
+
+hipError_t launch_direct_batch(const DirectBatchItem* items, int n_inst, int64_t total, unsigned long long* counter,
+                               int grid, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_direct_batch, dim3(grid), dim3(256), 0, s, items, n_inst, total, counter);
+    return hipGetLastError();
+}
+
+int direct_batch_blocks_per_cu()
+{
+    int nb = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_direct_batch, 256, 0) != hipSuccess) return 1;
+    return nb > 0 ? nb : 1;
 }
 
 hipError_t launch_epilogue(const float* y, int64_t n, const Epi& epi, float* k, uint8_t* ind, hipStream_t s)

@@ -22,6 +22,22 @@ int fail_hip(hipError_t e, const char* what);
         if (e_ != hipSuccess) return ::grf::fail_hip(e_, #call); \
     } while (0)
 
+// ---------------------------------------------------------------- validation (host)
+int check_modes(const grf_modes* m, const char* fn);
+int check_grid(const grf_grid* g, int dim, const char* fn);
+inline bool is_sep(int m) { return m >= GRF_SEP_BF16 && m <= GRF_SEP_F16_X3; }
+inline bool is_hilo(int m) { return m == GRF_SEP_BF16_X3 || m == GRF_SEP_F16_X3; }
+inline bool is_bf16(int m) { return m == GRF_SEP_BF16 || m == GRF_SEP_BF16_X3; }
+
+// ---------------------------------------------------------------- kernel timer
+// Records an event pair around the main kernel of a call while the timer is enabled.
+void timer_mark(hipStream_t s, bool begin);
+struct TimedScope {
+    hipStream_t s;
+    explicit TimedScope(hipStream_t st) : s(st) { timer_mark(s, true); }
+    ~TimedScope() { timer_mark(s, false); }
+};
+
 // ---------------------------------------------------------------- epilogue
 struct Epi {
     float mu;
@@ -86,6 +102,16 @@ struct AxisTableArgs {
 };
 hipError_t launch_axis_table(const AxisTableArgs& a, hipStream_t s);
 
+// Table layout of eval_field_grid for a resolved method (base == nullptr: measure only),
+// and the descriptors of the tables it builds (returns how many, <= 3).
+struct GridWs {
+    void* t[3] = {nullptr, nullptr, nullptr};
+    void* tlo[3] = {nullptr, nullptr, nullptr};
+    size_t bytes = 0;
+};
+GridWs grid_ws(const grf_modes* m, const grf_grid* g, int method, void* base);
+int grid_table_descs(const grf_modes* m, const grf_grid* g, int method, const GridWs& w, AxisTableArgs* out);
+
 // Per-mode parameters in revolutions: (a_x, a_y, a_z, psi) as double4, [ldp] rows,
 // padded modes get a = 0, psi = 0.
 hipError_t launch_mode_params(const double* z, const double* phi, int dim, int64_t n, int64_t ldp,
@@ -112,7 +138,8 @@ struct SepArgs {
     int method;            // GRF_SEP_*
     int64_t n, ldp;        // modes, padded row length
     int64_t nx, ny, nz;
-    const void* px;        // 2-D: half/bf16 pair table [nx][ldp] (conj); 3-D: float2 [nx][ldp]
+    const void* px;        // x side, (Re, -Im) pairs [nx][ldp]: half/bf16 pairs, except
+                           // 3-D hi+lo where it is float2 (the product with Ez is formed on chip)
     const void* px_lo;     // 2-D X3: lo table
     const void* qy;        // half/bf16 pair table [ny][ldp]
     const void* qy_lo;     // X3: lo table
@@ -122,11 +149,48 @@ struct SepArgs {
     float* y;
     float* k;
     uint8_t* ind;
-    int tile;              // 0 = default; else tile selector (see sep.hip)
+    int tile;              // < 0: size-based default; else tile selector (see sep.hip)
 };
 hipError_t launch_sep(const SepArgs& a, hipStream_t s);
 int sep_tile_count();                // number of tile selectors
 void sep_tile_shape(int tile, int* bm, int* bn);
+int sep_default_tile(int64_t nx, int64_t ny, int64_t nz);
+
+// ---------------------------------------------------------------- batched (persistent) launches
+// One descriptor per instance; work items [item0, item0 + tiles_x * tiles_y * nz) belong to it.
+struct SepBatchItem {
+    SepArgs a;
+    int64_t item0;
+    int32_t tiles_x, tiles_y;
+    int32_t variant;  // 0: 128x128 tiles, 1: 64x64 tiles
+    int32_t pad_;
+};
+hipError_t launch_sep_batch(int method, bool d3, const SepBatchItem* items, int n_inst, int64_t total,
+                            unsigned long long* counter, int grid, hipStream_t s);
+int sep_batch_blocks_per_cu(int method, bool d3);
+
+struct DirectBatchItem {
+    const float* tx;
+    const float* ty;
+    const float* tz;
+    float* y;
+    int64_t ldp;
+    int64_t nq;       // ny * nz
+    int64_t item0;
+    int32_t n, nx, ny, nxt;  // nxt: 64-cell tiles along x
+    float amp;
+    int32_t pad_;
+};
+hipError_t launch_direct_batch(const DirectBatchItem* items, int n_inst, int64_t total,
+                               unsigned long long* counter, int grid, hipStream_t s);
+int direct_batch_blocks_per_cu();
+constexpr int kDirectTile = 64;  // cells per tile side of the direct grid kernel
+
+// Batched per-axis tables: one launch over the concatenation of many AxisTableArgs.
+// prefix[i] = first element index of descriptor i (count * ldp elements each).
+hipError_t launch_axis_tables_batched(const AxisTableArgs* descs, const int64_t* prefix, int ndesc,
+                                      int64_t total, hipStream_t s);
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, hipStream_t s);
 
 // ---------------------------------------------------------------- adjoint
 struct BwdArgs {

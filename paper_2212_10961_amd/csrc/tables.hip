@@ -34,11 +34,9 @@ __device__ inline uint32_t pack_bf162(float re, float im)
 __device__ inline float half_to_float(uint16_t b) { return static_cast<float>(__builtin_bit_cast(_Float16, b)); }
 __device__ inline float bf16_to_float(uint16_t b) { return static_cast<float>(__builtin_bit_cast(__bf16, b)); }
 
-__global__ __launch_bounds__(256) void k_axis_table(AxisTableArgs a)
+// Entry e (= i * ldp + j) of one per-axis table.
+__device__ __forceinline__ void axis_table_entry(const AxisTableArgs& a, int64_t e)
 {
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    const int64_t total = a.count * a.ldp;
-    if (e >= total) return;
     const int64_t i = e / a.ldp;
     const int64_t j = e - i * a.ldp;
 
@@ -87,6 +85,35 @@ __global__ __launch_bounds__(256) void k_axis_table(AxisTableArgs a)
     }
 }
 
+__global__ __launch_bounds__(256) void k_axis_table(AxisTableArgs a)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= a.count * a.ldp) return;
+    axis_table_entry(a, e);
+}
+
+// Many tables in one launch: element e belongs to descriptor d with prefix[d] <= e < prefix[d+1].
+__global__ __launch_bounds__(256) void k_axis_tables_batched(const AxisTableArgs* __restrict__ descs,
+                                                             const int64_t* __restrict__ prefix, int ndesc,
+                                                             int64_t total)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= total) return;
+    int lo = 0, hi = ndesc - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (prefix[mid] <= e) lo = mid;
+        else hi = mid - 1;
+    }
+    const AxisTableArgs a = descs[lo];
+    axis_table_entry(a, e - prefix[lo]);
+}
+
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
 __global__ __launch_bounds__(256) void k_mode_params(const double* z, const double* phi, int dim, int64_t n,
                                                      int64_t ldp, double ex, double ey, double ez,
                                                      double4* out)
@@ -111,6 +138,23 @@ hipError_t launch_axis_table(const AxisTableArgs& a, hipStream_t s)
     if (total <= 0) return hipSuccess;
     const int64_t blocks = (total + 255) / 256;
     hipLaunchKernelGGL(k_axis_table, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_axis_tables_batched(const AxisTableArgs* descs, const int64_t* prefix, int ndesc, int64_t total,
+                                      hipStream_t s)
+{
+    if (total <= 0) return hipSuccess;
+    const int64_t blocks = (total + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_axis_tables_batched, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, descs, prefix,
+                       ndesc, total);
+    return hipGetLastError();
+}
+
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, p, v);
     return hipGetLastError();
 }
 

@@ -36,6 +36,23 @@ def version() -> int:
     return L.load().grf_version()
 
 
+class KernelTimer:
+    """Sums the device time of each call's main kernel (HIP events on its stream)."""
+
+    def __enter__(self):
+        check(L.load().grf_kernel_timer_enable(1))
+        return self
+
+    def __exit__(self, *exc):
+        check(L.load().grf_kernel_timer_enable(0))
+        return False
+
+    def read(self):
+        ms, n = ctypes.c_double(), ctypes.c_int64()
+        check(L.load().grf_kernel_timer_read(ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value, n.value
+
+
 def method_id(method) -> int:
     if isinstance(method, str):
         return L.METHODS[method]

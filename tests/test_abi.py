@@ -183,6 +183,46 @@ def test_points_validation(lib):
                                  None, ctypes.c_void_p(16), b.value - 1, None) == L.GRF_ENOMEM
 
 
+def test_plan_validation(lib):
+    h = ctypes.c_void_p()
+    assert lib.grf_plan_create(ctypes.byref(h), L.GRF_DIRECT_F64, 0, None) == L.GRF_EINVAL
+    assert lib.grf_plan_create(ctypes.byref(h), L.GRF_SEP_F16, 64, None) == L.GRF_EINVAL
+    assert lib.grf_plan_create(None, L.GRF_SEP_F16, 0, None) == L.GRF_EINVAL
+    assert lib.grf_plan_create(ctypes.byref(h), L.GRF_SEP_F16, L.GRF_PLAN_GRAPH | L.GRF_PLAN_AUTOTUNE, None) == 0
+    assert h.value
+    assert lib.eval_field_batch(h, None, 0, None) == 0          # empty batch: no-op
+    assert lib.eval_field_batch(h, None, 2, None) == L.GRF_EINVAL
+    assert lib.eval_field_batch(None, None, 1, None) == L.GRF_EINVAL
+    items = (L.GrfBatchItem * 2)()
+    items[0].modes = _modes(dim=2)
+    items[0].grid = _grid((8, 8, 1))
+    items[0].y = 16
+    items[1].modes = _modes(dim=3)     # mixed 2-D / 3-D in a separable batch
+    items[1].grid = _grid((8, 8, 8))
+    items[1].y = 16
+    assert lib.eval_field_batch(h, items, 2, None) == L.GRF_EUNSUPPORTED
+    items[1].modes = _modes(dim=2, ell=(1.0, 0.0, 1.0))
+    items[1].grid = _grid((8, 8, 1))
+    assert lib.eval_field_batch(h, items, 2, None) == L.GRF_EINVAL
+    items[1].modes = _modes(dim=2)
+    items[1].y = 0
+    assert lib.eval_field_batch(h, items, 2, None) == L.GRF_EINVAL
+    tm, tn, rep, wi = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    assert lib.grf_plan_info(h, ctypes.byref(tm), ctypes.byref(tn), ctypes.byref(rep), ctypes.byref(wi)) == 0
+    assert wi.value == 0 and rep.value == 0
+    assert lib.grf_plan_destroy(h) == 0
+    assert lib.grf_plan_destroy(None) == 0
+
+
+def test_kernel_timer_host_side(lib):
+    assert lib.grf_kernel_timer_enable(1) == 0
+    ms, n = ctypes.c_double(), ctypes.c_int64()
+    assert lib.grf_kernel_timer_read(ctypes.byref(ms), ctypes.byref(n)) == 0
+    assert n.value == 0 and ms.value == 0.0
+    assert lib.grf_kernel_timer_enable(0) == 0
+    assert lib.grf_kernel_timer_read(None, ctypes.byref(n)) == L.GRF_EINVAL
+
+
 def test_epilogue_and_backward_validation(lib):
     e = L.GrfEpi()
     e.mu = 0.0

@@ -1,0 +1,152 @@
+"""Batched ensembles (persistent launch + hipGraph + autotuner) against solo evaluations and
+the FP64 oracle.  Inputs follow the uneven-ensemble recipe of workloads.batch_instances."""
+import math
+import os
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import TOL, assert_field, modes_pair, to_np
+from paper_2212_10961_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def grf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2212_10961_amd.grf as g
+    return g
+
+
+def _instances(orc, grf, count, side_hi, n_modes, seed, dim=2):
+    inst = wl.batch_instances(count, seed=seed, side_lo=20, side_hi=side_hi, n_modes=n_modes)
+    out = []
+    for p in inst:
+        shape = p["shape"] if dim == 2 else (p["shape"][0], p["shape"][1], 3)
+        ell = p["ell"] if dim == 2 else (p["ell"][0], p["ell"][1], 2.0)
+        (zo, po), m = modes_pair(orc, grf, dim, p["cov"], n_modes, p["seed"], math.sqrt(p["sigma2"]), ell)
+        out.append(dict(shape=shape, ell=ell, sigma=math.sqrt(p["sigma2"]), zo=zo, po=po, m=m,
+                        y=torch.empty(int(np.prod(shape)), device="cuda")))
+    return out
+
+
+@pytest.mark.parametrize("meth", ["direct_f32", "sep_f16", "sep_f16_x3", "sep_bf16_x3"])
+def test_batch_matches_solo_and_oracle(orc, grf, meth):
+    print(f"case batch small {meth}", flush=True)
+    inst = _instances(orc, grf, 24, 300, 192, 31)
+    plan = grf.Plan(meth, graph=True, autotune=False)
+    plan.run([(d["m"], d["shape"], d["y"]) for d in inst])
+    info = plan.info()
+    assert info["replayed"] == 0 and info["work_items"] > 0
+    for i, d in enumerate(inst):
+        y = to_np(d["y"])
+        solo = to_np(grf.field_grid(d["m"], d["shape"], method=meth)["y"])
+        if meth == "direct_f32":
+            np.testing.assert_array_equal(y, solo)  # same tile kernel, same tables
+        else:
+            rel = np.sqrt(np.mean((y - solo) ** 2) / np.mean(solo ** 2))
+            assert rel <= 2 * TOL[meth]["rel"], (i, rel)
+        if i % 6 == 0:
+            cells = wl.sample_cells(y.size, 200, 500 + i)
+            ref = orc.field_cells(d["zo"], d["po"], d["sigma"], d["ell"], d["shape"], cells)
+            assert_field(y[cells], ref, d["sigma"], meth, f"batch[{i}] {d['shape']}")
+    plan.close()
+
+
+def test_batch_graph_replay_and_updates(orc, grf):
+    """Replays of the captured graph, with eager work between them, equal eager evaluations;
+    new mode values at the same addresses are picked up by the replay (tables rebuilt in-graph)."""
+    print("case batch graph replay", flush=True)
+    inst = _instances(orc, grf, 10, 260, 128, 32)
+    items = [(d["m"], d["shape"], d["y"]) for d in inst]
+    plan = grf.Plan("sep_f16", graph=True, autotune=False)
+    plan.run(items)
+    first = [to_np(d["y"]).copy() for d in inst]
+    for rep in range(4):
+        scratch = torch.randn(1 << 20, device="cuda")  # eager work between replays
+        _ = (scratch * 2.0).sum().item()
+        for d in inst:
+            d["y"].fill_(float("nan"))
+        plan.run(items)
+        assert plan.info()["replayed"] == 1
+        for d, f in zip(inst, first):
+            np.testing.assert_array_equal(to_np(d["y"]), f)
+    # change the phases in place: the replay must use the new values
+    for d in inst:
+        d["m"].phi.add_(0.37)
+    plan.run(items)
+    assert plan.info()["replayed"] == 1
+    for d in inst[:4]:
+        solo = to_np(grf.field_grid(d["m"], d["shape"], method="sep_f16")["y"])
+        y = to_np(d["y"])
+        assert np.sqrt(np.mean((y - solo) ** 2) / np.mean(solo ** 2)) <= 2 * TOL["sep_f16"]["rel"]
+    # a different output pointer is a new signature: rebuilt, not replayed
+    items[0] = (inst[0]["m"], inst[0]["shape"], torch.empty_like(inst[0]["y"]))
+    plan.run(items)
+    assert plan.info()["replayed"] == 0
+    plan.close()
+
+
+def test_batch_direct_3d_and_no_graph(orc, grf):
+    print("case batch direct 3d", flush=True)
+    inst = _instances(orc, grf, 6, 150, 100, 33, dim=3)
+    plan = grf.Plan("direct_f32", graph=False, autotune=False)
+    plan.run([(d["m"], d["shape"], d["y"]) for d in inst])
+    for d in inst:
+        np.testing.assert_array_equal(to_np(d["y"]), to_np(grf.field_grid(d["m"], d["shape"])["y"]))
+    plan.close()
+
+
+def test_batch_sep_3d(orc, grf):
+    print("case batch sep 3d", flush=True)
+    inst = _instances(orc, grf, 6, 150, 100, 34, dim=3)
+    plan = grf.Plan("sep_f16_x3", graph=True, autotune=True)
+    plan.run([(d["m"], d["shape"], d["y"]) for d in inst])
+    for d in inst:
+        ref = orc.field_grid(d["zo"], d["po"], d["sigma"], d["ell"], d["shape"])
+        assert_field(to_np(d["y"]), ref, d["sigma"], "sep_f16_x3", f"batch3d {d['shape']}")
+    plan.close()
+
+
+def test_autotune_cache(orc, grf, tmp_path):
+    print("case autotune cache", flush=True)
+    cache = tmp_path / "tune.txt"
+    inst = _instances(orc, grf, 12, 600, 256, 35)
+    items = [(d["m"], d["shape"], d["y"]) for d in inst]
+    plan = grf.Plan("sep_f16", graph=True, autotune=True, tune_cache=str(cache))
+    plan.run(items)
+    plan.close()
+    lines = [l for l in cache.read_text().splitlines() if l.strip()]
+    assert lines and all(l.startswith("sep ") and l.split()[-1] in ("0", "1") for l in lines)
+    ys = [to_np(d["y"]).copy() for d in inst]
+    plan2 = grf.Plan("sep_f16", graph=True, autotune=True, tune_cache=str(cache))
+    plan2.run(items)  # classes come from the cache: nothing new is appended
+    plan2.close()
+    assert cache.read_text().splitlines() == lines
+    for d, y in zip(inst, ys):
+        np.testing.assert_array_equal(to_np(d["y"]), y)
+
+
+def test_batch512_full_sampled(orc, grf):
+    """The 512-instance uneven ensemble, sides 64..1024, N=2048, one persistent launch."""
+    print("case batch512 full", flush=True)
+    inst = wl.batch_instances()
+    items, keep = [], []
+    for i, p in enumerate(inst):
+        z, phi = grf.make_modes(2, p["cov"], p["n_modes"], p["seed"])
+        m = grf.modes_from_tables(z, phi, math.sqrt(p["sigma2"]), p["ell"])
+        y = torch.empty(p["shape"][0] * p["shape"][1], device="cuda")
+        items.append((m, p["shape"], y))
+        if i % 64 == 0:
+            keep.append((i, p, y))
+    plan = grf.Plan("sep_f16", graph=True, autotune=True)
+    plan.run(items)
+    for i, p, y in keep:
+        zo, po = orc.sample_modes(2, p["cov"], p["n_modes"], p["seed"])
+        cells = wl.sample_cells(p["shape"][0] * p["shape"][1], 300, 600 + i)
+        ref = orc.field_cells(zo, po, math.sqrt(p["sigma2"]), p["ell"], p["shape"], cells)
+        assert_field(to_np(y)[cells], ref, math.sqrt(p["sigma2"]), "sep_f16", f"batch512[{i}] {p['shape']}")
+    plan.close()
