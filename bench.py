@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline (oracle) leg")
     ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
     ap.add_argument("--only", default=None, help="time a single grid method (profiling runs)")
+    ap.add_argument("--extras", default="points,epilogue,adjoint,batch",
+                    help="comma-separated extra workloads to time (points, epilogue, adjoint, batch)")
+    ap.add_argument("--extras-only", action="store_true", help="skip the headline workload (profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run one plain 1 GiB device copy (for scaling PMC byte counters)")
     args = ap.parse_args()
@@ -96,6 +99,10 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": a.numel() * 4, "copy_bytes_written": b.numel() * 4}))
+        return
+
+    if args.extras_only:
+        print(json.dumps({"extras": extras(args, grf, wl, torch, np, dev)}))
         return
 
     cfg = wl.WORKLOADS["grid3d_256_exp"]
@@ -231,6 +238,23 @@ def _timed(torch, grf, fn, steps, warm):
 
 
 def extras(args, grf, wl, torch, np, dev):
+    sel = set(s.strip() for s in args.extras.split(",") if s.strip())
+    out = {}
+    if "points" in sel:
+        out.update(points_extra(grf, wl, torch, np, dev))
+    if "epilogue" in sel:
+        out.update(epilogue_extra(grf, wl, torch, np, dev))
+    if "adjoint" in sel:
+        out.update(adjoint_extra(grf, wl, torch, np, dev))
+    if "batch" in sel:
+        try:
+            out["batch512_2d"] = batch_extra(grf, wl, torch, np, dev)
+        except grf.GrfError as e:
+            out["batch512_2d"] = {"error": str(e)}
+    return out
+
+
+def points_extra(grf, wl, torch, np, dev):
     out = {}
     # unstructured points, FP64 phase reduction per mode and point, indicator epilogue
     c = wl.WORKLOADS["points_2m_gauss"]
@@ -247,7 +271,11 @@ def extras(args, grf, wl, torch, np, dev):
                               "roofline": {"bound": "alu", "achieved": work / (kms * 1e-3), "peak": COS_PEAK,
                                            "unit": "mode·point/s", "frac": work / (kms * 1e-3) / COS_PEAK},
                               "indicator_fraction": float(o["ind"].float().mean().item())}
+    return out
 
+
+def epilogue_extra(grf, wl, torch, np, dev):
+    out = {}
     # stand-alone epilogue over the 256^3 field: read Y, write K and the indicator
     n = 256 ** 3
     y = torch.randn(n, device=dev)
@@ -259,7 +287,11 @@ def extras(args, grf, wl, torch, np, dev):
                                                              "peak": HBM_PEAK / 1e9, "unit": "GB/s",
                                                              "frac": nbytes / (kms * 1e-3) / HBM_PEAK,
                                                              "algorithmic": "4 B read + 4 B + 1 B written per cell"}}
+    return out
 
+
+def adjoint_extra(grf, wl, torch, np, dev):
+    out = {}
     # adjoint workload: forward + backward at 10,000 observation cells, and the dense variant
     c = wl.WORKLOADS["adjoint_grid3d_128"]
     log("[bench] extras: adjoint_grid3d_128")
@@ -284,12 +316,6 @@ def extras(args, grf, wl, torch, np, dev):
                   "bwd_over_fwd_direct": db_ms / df_ms,
                   "bwd_roofline": {"bound": "alu", "achieved": Cg * c["n_modes"] / (db_k * 1e-3), "peak": COS_PEAK,
                                    "unit": "mode·cell/s", "frac": Cg * c["n_modes"] / (db_k * 1e-3) / COS_PEAK}}}
-
-    # batched ensemble
-    try:
-        out["batch512_2d"] = batch_extra(grf, wl, torch, np, dev)
-    except grf.GrfError as e:
-        out["batch512_2d"] = {"error": str(e)}
     return out
 
 

@@ -156,6 +156,76 @@ __global__ __launch_bounds__(256) void k_bwd_final(const float* __restrict__ sca
     }
 }
 
+// Dense adjoint on a structured grid from the per-axis revolution tables (FP64-reduced,
+// psi folded into the y table): theta_jc / 2 pi = Tx[i][j] + Ty[y][j] + Tz[z][j].
+// One lane per mode; the block walks a chunk of 16 x 16 (x, (y,z)) cell tiles.  Each lane
+// keeps its mode's 16 + 16 table entries of the tile in registers, and the per-cell
+// weights (g, g x, g y, g z) are shared through LDS (broadcast reads).  Cells outside the
+// grid get g = 0.
+constexpr int kBT = 16;
+
+template <bool WANT_C>
+__global__ __launch_bounds__(256) void k_bwd_grid_tab(const float* __restrict__ tx, const float* __restrict__ ty,
+                                                     const float* __restrict__ tz, int64_t ldp, Geo geo, int64_t nq,
+                                                     int nxt, int64_t ntiles, int64_t tiles_per_chunk,
+                                                     const float* __restrict__ gy, float* __restrict__ partial)
+{
+    __shared__ float4 sw[kBT * kBT];
+    const int t = threadIdx.x;
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + t;
+    const int64_t jc = min(j, ldp - 1);
+    const int64_t ch = blockIdx.y;
+    const int64_t t0 = ch * tiles_per_chunk, t1 = min(ntiles, t0 + tiles_per_chunk);
+    float s = 0.f, ux = 0.f, uy = 0.f, uz = 0.f, cc = 0.f;
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t x0 = (tile % nxt) * kBT;
+        const int64_t q0 = (tile / nxt) * kBT;
+        float vx[kBT], vq[kBT];
+#pragma unroll
+        for (int r = 0; r < kBT; ++r) {
+            vx[r] = tx[min(x0 + r, geo.nx - 1) * ldp + jc];
+            const int64_t q = min(q0 + r, nq - 1);
+            vq[r] = ty[(q % geo.ny) * ldp + jc] + tz[(q / geo.ny) * ldp + jc];
+        }
+        __syncthreads();  // previous tile's weights are no longer read
+        {
+            const int64_t xi = x0 + (t % kBT), q = q0 + (t / kBT);
+            float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (xi < geo.nx && q < nq) {
+                const float g = gy[q * geo.nx + xi];
+                const float x = static_cast<float>(geo.ox + (static_cast<double>(xi) + 0.5) * geo.hx);
+                const float y = static_cast<float>(geo.oy + (static_cast<double>(q % geo.ny) + 0.5) * geo.hy);
+                const float z = static_cast<float>(geo.oz + (static_cast<double>(q / geo.ny) + 0.5) * geo.hz);
+                w = make_float4(g, g * x, g * y, g * z);
+            }
+            sw[t] = w;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int b = 0; b < kBT; ++b) {
+#pragma unroll
+            for (int a = 0; a < kBT; ++a) {
+                const float4 w = sw[b * kBT + a];
+                const float p = vx[a] + vq[b];
+                const float sn = __builtin_amdgcn_sinf(p);
+                s = fmaf(w.x, sn, s);
+                ux = fmaf(w.y, sn, ux);
+                uy = fmaf(w.z, sn, uy);
+                uz = fmaf(w.w, sn, uz);
+                if (WANT_C) cc = fmaf(w.x, __builtin_amdgcn_cosf(p), cc);
+            }
+        }
+    }
+    if (j < ldp) {
+        float* out = partial + ch * 5 * ldp;
+        out[j] = s;
+        out[ldp + j] = ux;
+        out[2 * ldp + j] = uy;
+        out[3 * ldp + j] = uz;
+        out[4 * ldp + j] = cc;
+    }
+}
+
 template <int DIM, bool GRID>
 void launch_bwd_main(const BwdArgs& a, int64_t chunk, const Geo& geo, bool want_c, hipStream_t s)
 {
@@ -196,7 +266,19 @@ hipError_t launch_backward(const BwdArgs& a, hipStream_t s)
     }
     const bool want_c = a.gsigma != nullptr && a.ysaved == nullptr;
     timer_mark(s, true);
-    if (a.dim == 3) {
+    if (grid && a.tx) {
+        const int64_t nq = a.gn[1] * a.gn[2];
+        const int nxt = static_cast<int>((a.gn[0] + kBT - 1) / kBT);
+        const int64_t ntiles = static_cast<int64_t>(nxt) * ((nq + kBT - 1) / kBT);
+        const int64_t per = (ntiles + a.nchunks - 1) / a.nchunks;
+        const dim3 g(static_cast<unsigned>((a.ldp + 255) / 256), static_cast<unsigned>(a.nchunks));
+        if (want_c)
+            hipLaunchKernelGGL(k_bwd_grid_tab<true>, g, dim3(256), 0, s, a.tx, a.ty, a.tz, a.ldp, geo, nq, nxt, ntiles,
+                               per, a.gy, a.partial);
+        else
+            hipLaunchKernelGGL(k_bwd_grid_tab<false>, g, dim3(256), 0, s, a.tx, a.ty, a.tz, a.ldp, geo, nq, nxt,
+                               ntiles, per, a.gy, a.partial);
+    } else if (a.dim == 3) {
         if (grid) launch_bwd_main<3, true>(a, chunk, geo, want_c, s);
         else launch_bwd_main<3, false>(a, chunk, geo, want_c, s);
     } else {

@@ -110,6 +110,16 @@ static int check_epi(const grf_epi* e, const float* k, const uint8_t* ind, const
 }
 
 
+// Workspace of eval_field_points: per-mode parameters, plus the per-slice partial sums when
+// the FP32 path splits the modes across blocks (few points).
+static size_t points_ws_bytes(int64_t n, int64_t P, int method)
+{
+    size_t b = align256(sizeof(double) * 4 * size_t(padded_modes(n)));
+    const int slices = method == GRF_DIRECT_F32 ? points_mode_slices(P, n) : 1;
+    if (slices > 1) b += align256(sizeof(float) * size_t(slices) * size_t(P));
+    return b;
+}
+
 static int resolve_grid_method(int method, const grf_grid* g)
 {
     if (method == GRF_AUTO) {
@@ -173,6 +183,9 @@ int grid_table_descs(const grf_modes* m, const grf_grid* g, int method, const Gr
             t.format = TF_REV_F64;
         } else {
             const bool hilo = is_hilo(method), bf = is_bf16(method);
+            // single-pass operands are rounded to fp16/bf16 (2^-11 or 2^-8): the hardware
+            // sin/cos of the FP64-reduced fraction (|err| ~1e-7) is far below that
+            t.fast_trig = !hilo;
             if (a == 1 || (a == 0 && m->dim == 2)) {
                 t.format = bf ? (hilo ? TF_BF16_HILO : TF_BF16) : (hilo ? TF_F16_HILO : TF_F16);
                 t.conj = (a == 0);
@@ -339,7 +352,7 @@ int eval_field_points_ws_size(const grf_modes* modes, int64_t n_points, int meth
     if (is_sep(method)) return fail(GRF_EUNSUPPORTED, "eval_field_points_ws_size: separable methods need a grid");
     if (method != GRF_DIRECT_F32 && method != GRF_DIRECT_F64)
         return fail(GRF_EINVAL, "eval_field_points_ws_size: unknown method %d", method);
-    *bytes = align256(sizeof(double) * 4 * size_t(padded_modes(modes->n)));
+    *bytes = points_ws_bytes(modes->n, n_points, method);
     return GRF_OK;
 }
 
@@ -359,16 +372,19 @@ int eval_field_points(const grf_modes* modes, const double* xyz, int64_t n_point
     if (n_points == 0) return GRF_OK;
     if (!y && !k && !ind) return fail(GRF_EINVAL, "%s: no output requested", fn);
     if (!xyz) return fail(GRF_EINVAL, "%s: xyz is NULL", fn);
-    const size_t need = align256(sizeof(double) * 4 * size_t(padded_modes(modes->n)));
+    const size_t need = points_ws_bytes(modes->n, n_points, method);
     if (!ws || ws_bytes < need) return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    double* params = static_cast<double*>(ws);
     const int64_t ldp = padded_modes(modes->n);
+    Carve c(ws);
+    double* params = c.take<double>(4 * ldp);
+    float* partial = method == GRF_DIRECT_F32 ? c.take<float>(size_t(points_mode_slices(n_points, modes->n)) * n_points)
+                                              : nullptr;
     GRF_HIP(launch_mode_params(modes->z, modes->phi, modes->dim, modes->n, ldp, modes->ell, params, s));
     const float amp = static_cast<float>(modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n)));
     TimedScope timed(s);
     GRF_HIP(launch_direct_points(params, modes->n, modes->dim, xyz, n_points, method == GRF_DIRECT_F64, amp,
-                                 make_epi(epi), y, k, ind, s));
+                                 make_epi(epi), y, k, ind, partial, s));
     return GRF_OK;
 }
 
@@ -406,7 +422,7 @@ static int backward_common(const char* fn, const grf_modes* modes, const double*
                            void* stream)
 {
     size_t need = 0;
-    int rc = field_backward_ws_size(modes, P, &need);
+    int rc = grid ? field_backward_grid_ws_size(modes, grid, &need) : field_backward_ws_size(modes, P, &need);
     if (rc) return rc;
     if (!grad_phi && !grad_k && !grad_sigma && !grad_ell) return fail(GRF_EINVAL, "%s: no output requested", fn);
     if (P > 0 && !grad_y) return fail(GRF_EINVAL, "%s: grad_y is NULL", fn);
@@ -419,7 +435,15 @@ static int backward_common(const char* fn, const grf_modes* modes, const double*
     float* partial = c.take<float>(5 * ldp * bwd_chunks(P));
     float* scal = c.take<float>(bwd_scal_floats(modes->n));
     GRF_HIP(launch_mode_params(modes->z, modes->phi, modes->dim, modes->n, ldp, modes->ell, params, s));
+    GridWs tabs;
+    if (grid) {  // per-axis FP32 revolution tables of the direct method
+        tabs = grid_ws(modes, grid, GRF_DIRECT_F32, c.base + c.used);
+        GRF_HIP(build_tables(modes, grid, GRF_DIRECT_F32, tabs, s));
+    }
     BwdArgs a{};
+    a.tx = static_cast<const float*>(tabs.t[0]);
+    a.ty = static_cast<const float*>(tabs.t[1]);
+    a.tz = static_cast<const float*>(tabs.t[2]);
     a.params = params;
     a.n = modes->n;
     a.ldp = ldp;
@@ -463,7 +487,9 @@ int field_backward_grid_ws_size(const grf_modes* modes, const grf_grid* grid, si
     int rc;
     if ((rc = check_modes(modes, "field_backward_grid_ws_size"))) return rc;
     if ((rc = check_grid(grid, modes->dim, "field_backward_grid_ws_size"))) return rc;
-    return field_backward_ws_size(modes, grid->n[0] * grid->n[1] * grid->n[2], bytes);
+    if ((rc = field_backward_ws_size(modes, grid->n[0] * grid->n[1] * grid->n[2], bytes))) return rc;
+    *bytes += grid_ws(modes, grid, GRF_DIRECT_F32, nullptr).bytes;  // revolution tables
+    return GRF_OK;
 }
 
 int field_backward_grid(const grf_modes* modes, const grf_grid* grid, const float* grad_y, const float* y_saved,

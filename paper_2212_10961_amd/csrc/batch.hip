@@ -36,7 +36,7 @@ struct grf_plan {
     int n_inst = 0;
     int n_desc = 0;
     int64_t total_items = 0;
-    int64_t table_elems = 0;
+    int64_t table_blocks = 0;
     int grid = 0;
     int32_t tile_m = 0, tile_n = 0;
     int32_t replayed = 0;
@@ -159,7 +159,7 @@ hipError_t enqueue(grf_plan* p, hipStream_t s, const void* items, int n_items_de
 {
     hipError_t e = launch_fill_u64(p->d_counter, 0ull, s);
     if (e != hipSuccess) return e;
-    e = launch_axis_tables_batched(p->d_tdesc, p->d_tprefix, p->n_desc, p->table_elems, s);
+    e = launch_axis_tables_batched(p->d_tdesc, p->d_tprefix, p->n_desc, p->table_blocks, s);
     if (e != hipSuccess) return e;
     if (is_sep(p->method))
         return launch_sep_batch(p->method, p->d3, static_cast<const SepBatchItem*>(items), n_items_desc, total,
@@ -209,12 +209,12 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
         const int nd = grid_table_descs(&items[i].modes, &items[i].grid, p->method, ws[i], d);
         for (int k = 0; k < nd; ++k) {
             td.push_back(d[k]);
-            tpre.push_back(elems);
-            elems += d[k].count * d[k].ldp;
+            tpre.push_back(elems);  // in 256-element blocks
+            elems += (d[k].count * d[k].ldp + 255) / 256;
         }
     }
     p->n_desc = static_cast<int>(td.size());
-    p->table_elems = elems;
+    p->table_blocks = elems;
     GRF_HIP(ensure(p->d_tdesc, p->cap_tdesc, td.size() * sizeof(AxisTableArgs) + tpre.size() * sizeof(int64_t) + 256));
     p->d_tprefix = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(p->d_tdesc) +
                                               align256(td.size() * sizeof(AxisTableArgs)));
@@ -302,7 +302,7 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
                 if (!p->tuned.count(keys[i]) && std::find(pending.begin(), pending.end(), keys[i]) == pending.end())
                     pending.push_back(keys[i]);
         if (!pending.empty()) {
-            GRF_HIP(launch_axis_tables_batched(p->d_tdesc, p->d_tprefix, p->n_desc, p->table_elems, p->cap));
+            GRF_HIP(launch_axis_tables_batched(p->d_tdesc, p->d_tprefix, p->n_desc, p->table_blocks, p->cap));
             hipEvent_t e0, e1;
             GRF_HIP(hipEventCreate(&e0));
             GRF_HIP(hipEventCreate(&e1));

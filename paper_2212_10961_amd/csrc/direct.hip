@@ -181,16 +181,33 @@ __global__ __launch_bounds__(256) void k_direct_grid_f64(const double* __restric
 }
 
 // ---------------------------------------------------------------------------- points
+__global__ __launch_bounds__(256) void k_points_reduce(const float* __restrict__ partial, int slices, int64_t P,
+                                                      float amp, Epi epi, float* __restrict__ y,
+                                                      float* __restrict__ k, uint8_t* __restrict__ ind)
+{
+    const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (p >= P) return;
+    float s = 0.f;
+    for (int q = 0; q < slices; ++q) s += partial[static_cast<int64_t>(q) * P + p];
+    store_out(p, amp * s, epi, y, k, ind);
+}
+
 // Each lane owns R points; every mode's (a_x, a_y, a_z, psi) in revolutions is
 // uniform across the block (scalar loads).  The phase a.x + psi is formed and
 // reduced in FP64 per mode and point, then the cosine and the sum run in FP32.
+// With few points the modes are split over blockIdx.y slices of `mslice` modes each:
+// every slice writes its raw partial sums to partial[slice][P] and k_points_reduce adds
+// them in slice order and applies the epilogue.
 template <int DIM, int R>
 __global__ __launch_bounds__(256) void k_direct_points(const double4* __restrict__ prm, int n,
                                                       const double* __restrict__ xyz, int64_t P, float amp,
                                                       Epi epi, float* __restrict__ y, float* __restrict__ k,
-                                                      uint8_t* __restrict__ ind)
+                                                      uint8_t* __restrict__ ind, int mslice,
+                                                      float* __restrict__ partial)
 {
     const int64_t base = static_cast<int64_t>(blockIdx.x) * (256 * R) + threadIdx.x;
+    const int j0 = static_cast<int>(blockIdx.y) * mslice;
+    const int j1 = min(n, j0 + mslice);
     double px[R], py[R], pz[R];
     float acc[R];
 #pragma unroll
@@ -201,7 +218,7 @@ __global__ __launch_bounds__(256) void k_direct_points(const double4* __restrict
         pz[r] = DIM == 3 ? xyz[p * DIM + 2] : 0.0;
         acc[r] = 0.f;
     }
-    for (int j = 0; j < n; ++j) {
+    for (int j = j0; j < j1; ++j) {
         const double4 m = prm[j];
 #pragma unroll
         for (int r = 0; r < R; ++r) {
@@ -215,7 +232,9 @@ __global__ __launch_bounds__(256) void k_direct_points(const double4* __restrict
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t p = base + 256 * r;
-        if (p < P) store_out(p, amp * acc[r], epi, y, k, ind);
+        if (p >= P) continue;
+        if (partial) partial[static_cast<int64_t>(blockIdx.y) * P + p] = acc[r];
+        else store_out(p, amp * acc[r], epi, y, k, ind);
     }
 }
 
@@ -308,7 +327,8 @@ hipError_t launch_direct_grid_f64(const double* tx, const double* ty, const doub
 }
 
 hipError_t launch_direct_points(const double* params, int64_t n, int dim, const double* xyz, int64_t P, bool fp64,
-                                float amp, const Epi& epi, float* y, float* k, uint8_t* ind, hipStream_t s)
+                                float amp, const Epi& epi, float* y, float* k, uint8_t* ind, float* partial,
+                                hipStream_t s)
 {
     const double4* prm = reinterpret_cast<const double4*>(params);
     if (fp64) {
@@ -322,16 +342,35 @@ hipError_t launch_direct_points(const double* params, int64_t n, int dim, const 
                                static_cast<int>(n), xyz, P, static_cast<double>(amp), epi, y, k, ind);
         return hipGetLastError();
     }
-    constexpr int R = 4;
+    constexpr int R = kPointsPerLane;
     const int64_t blocks = (P + 256 * R - 1) / (256 * R);
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    const int slices = points_mode_slices(P, n);
+    const int mslice = static_cast<int>((n + slices - 1) / slices);
+    float* part = slices > 1 ? partial : nullptr;
+    const dim3 g(static_cast<unsigned>(blocks), static_cast<unsigned>(slices));
     if (dim == 3)
-        hipLaunchKernelGGL((k_direct_points<3, R>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, prm,
-                           static_cast<int>(n), xyz, P, amp, epi, y, k, ind);
+        hipLaunchKernelGGL((k_direct_points<3, R>), g, dim3(256), 0, s, prm, static_cast<int>(n), xyz, P, amp, epi, y,
+                           k, ind, mslice, part);
     else
-        hipLaunchKernelGGL((k_direct_points<2, R>), dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, prm,
-                           static_cast<int>(n), xyz, P, amp, epi, y, k, ind);
+        hipLaunchKernelGGL((k_direct_points<2, R>), g, dim3(256), 0, s, prm, static_cast<int>(n), xyz, P, amp, epi, y,
+                           k, ind, mslice, part);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || slices == 1) return e;
+    hipLaunchKernelGGL(k_points_reduce, dim3(static_cast<unsigned>((P + 255) / 256)), dim3(256), 0, s, partial, slices,
+                       P, amp, epi, y, k, ind);
     return hipGetLastError();
+}
+
+int points_mode_slices(int64_t P, int64_t n)
+{
+    // Enough blocks to fill 256 CUs several times over; each slice keeps >= 64 modes.
+    if (P <= 0 || n <= 0) return 1;
+    const int64_t pblocks = (P + 256 * kPointsPerLane - 1) / (256 * kPointsPerLane);
+    int64_t s = (2048 + pblocks - 1) / pblocks;
+    s = std::min<int64_t>(s, std::max<int64_t>(n / 64, 1));
+    s = std::min<int64_t>(s, 64);
+    return static_cast<int>(std::max<int64_t>(s, 1));
 }
 
 hipError_t launch_direct_batch(const DirectBatchItem* items, int n_inst, int64_t total, unsigned long long* counter,

@@ -96,6 +96,8 @@ struct AxisTableArgs {
     int64_t count;  // number of grid points along the axis
     bool with_psi;
     bool conj;      // store (re, -im) for half formats
+    bool fast_trig; // cos/sin of the FP64-reduced fraction by the hardware units (FP32);
+                    // for tables rounded to one fp16/bf16 (or FP32) pass, else FP64 sincospi
     int format;
     void* out;      // primary table
     void* out_lo;   // lo table for *_HILO formats
@@ -125,9 +127,13 @@ hipError_t launch_direct_grid_f64(const double* tx, const double* ty, const doub
                                   int64_t ldp, const int64_t* gn, double amp, const Epi& epi,
                                   double mu64, float* y, float* k, uint8_t* ind, double* y64,
                                   double* k64, hipStream_t s);
+// `partial` (workspace, points_mode_slices(P, n) * P floats when that is > 1) receives the
+// per-slice sums when the modes are split across blocks.
 hipError_t launch_direct_points(const double* params, int64_t n, int dim, const double* xyz,
                                 int64_t P, bool fp64, float amp, const Epi& epi, float* y, float* k,
-                                uint8_t* ind, hipStream_t s);
+                                uint8_t* ind, float* partial, hipStream_t s);
+constexpr int kPointsPerLane = 4;
+int points_mode_slices(int64_t P, int64_t n);
 hipError_t launch_epilogue(const float* y, int64_t n, const Epi& epi, float* k, uint8_t* ind,
                            hipStream_t s);
 
@@ -154,7 +160,7 @@ struct SepArgs {
 hipError_t launch_sep(const SepArgs& a, hipStream_t s);
 int sep_tile_count();                // number of tile selectors
 void sep_tile_shape(int tile, int* bm, int* bn);
-int sep_default_tile(int64_t nx, int64_t ny, int64_t nz);
+int sep_default_tile(int method, int64_t nx, int64_t ny, int64_t nz);
 
 // ---------------------------------------------------------------- batched (persistent) launches
 // One descriptor per instance; work items [item0, item0 + tiles_x * tiles_y * nz) belong to it.
@@ -186,10 +192,10 @@ hipError_t launch_direct_batch(const DirectBatchItem* items, int n_inst, int64_t
 int direct_batch_blocks_per_cu();
 constexpr int kDirectTile = 64;  // cells per tile side of the direct grid kernel
 
-// Batched per-axis tables: one launch over the concatenation of many AxisTableArgs.
-// prefix[i] = first element index of descriptor i (count * ldp elements each).
-hipError_t launch_axis_tables_batched(const AxisTableArgs* descs, const int64_t* prefix, int ndesc,
-                                      int64_t total, hipStream_t s);
+// Batched per-axis tables: one launch over many AxisTableArgs (device array).  Descriptor i
+// owns 256-element blocks [bprefix[i], bprefix[i+1]) (ceil(count * ldp / 256) of them).
+hipError_t launch_axis_tables_batched(const AxisTableArgs* descs, const int64_t* bprefix, int ndesc,
+                                      int64_t total_blocks, hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, hipStream_t s);
 
 // ---------------------------------------------------------------- adjoint
@@ -211,6 +217,9 @@ struct BwdArgs {
     float* gk;
     float* gsigma;
     float* gell;
+    const float* tx;       // grid path: FP32 revolution tables (psi in ty), or nullptr
+    const float* ty;
+    const float* tz;
     float* partial;        // workspace [nchunks][5][ldp]
     float* scal_partial;   // workspace [nblocks]
     int64_t nchunks;

@@ -386,12 +386,13 @@ void sep_tile_shape(int tile, int* bm, int* bn)
     *bn = kTiles[tile].bn;
 }
 
-int sep_default_tile(int64_t nx, int64_t ny, int64_t nz)
+int sep_default_tile(int method, int64_t nx, int64_t ny, int64_t nz)
 {
-    // Large slices: 256x256 (operand reuse); small or thin grids: smaller tiles keep the
+    // Large slices: 256x256 (operand reuse), or 128x256 for the hi+lo forms whose doubled
+    // LDS stages do not fit twice at 256x256; small or thin grids: smaller tiles keep the
     // device busy and waste less on ragged edges.
     const int64_t t256 = ((nx + 255) / 256) * ((ny + 255) / 256) * nz;
-    if (nx >= 192 && ny >= 192 && t256 >= 128) return 0;
+    if (nx >= 192 && ny >= 192 && t256 >= 128) return (method == GRF_SEP_F16_X3 || method == GRF_SEP_BF16_X3) ? 3 : 0;
     const int64_t t128 = ((nx + 127) / 128) * ((ny + 127) / 128) * nz;
     if (nx >= 96 && ny >= 96 && t128 >= 64) return 1;
     return 2;
@@ -429,7 +430,7 @@ int sep_batch_blocks_per_cu(int method, bool d3)
 
 hipError_t launch_sep(const SepArgs& a, hipStream_t s)
 {
-    int tile = a.tile < 0 ? sep_default_tile(a.nx, a.ny, a.nz) : a.tile;
+    int tile = a.tile < 0 ? sep_default_tile(a.method, a.nx, a.ny, a.nz) : a.tile;
     if (tile >= sep_tile_count()) return hipErrorInvalidValue;
     switch (a.method) {
     case GRF_SEP_BF16: return launch_d<true, false>(a, tile, s);

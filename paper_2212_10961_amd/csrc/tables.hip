@@ -59,7 +59,13 @@ __device__ __forceinline__ void axis_table_entry(const AxisTableArgs& a, int64_t
         break;
     default: {
         double sn, cs;
-        sincospi(2.0 * f, &sn, &cs);
+        if (a.fast_trig) {
+            const float fr = static_cast<float>(f);  // revolutions in [0, 1)
+            cs = static_cast<double>(__builtin_amdgcn_cosf(fr));
+            sn = static_cast<double>(__builtin_amdgcn_sinf(fr));
+        } else {
+            sincospi(2.0 * f, &sn, &cs);
+        }
         if (zero) { sn = 0.0; cs = 0.0; }
         if (a.conj) sn = -sn;
         if (a.format == TF_CPLX_F32) {
@@ -92,21 +98,23 @@ __global__ __launch_bounds__(256) void k_axis_table(AxisTableArgs a)
     axis_table_entry(a, e);
 }
 
-// Many tables in one launch: element e belongs to descriptor d with prefix[d] <= e < prefix[d+1].
+// Many tables in one launch.  Blocks are assigned to descriptors: descriptor d owns blocks
+// [bprefix[d], bprefix[d+1]) and its element e is handled by block bprefix[d] + e / 256.
+// The descriptor lookup depends only on the block index, so it runs once per block on the
+// scalar unit.
 __global__ __launch_bounds__(256) void k_axis_tables_batched(const AxisTableArgs* __restrict__ descs,
-                                                             const int64_t* __restrict__ prefix, int ndesc,
-                                                             int64_t total)
+                                                             const int64_t* __restrict__ bprefix, int ndesc)
 {
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= total) return;
+    const int64_t b = blockIdx.x;
     int lo = 0, hi = ndesc - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
-        if (prefix[mid] <= e) lo = mid;
+        if (bprefix[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
-    const AxisTableArgs a = descs[lo];
-    axis_table_entry(a, e - prefix[lo]);
+    const AxisTableArgs& a = descs[lo];
+    const int64_t e = (b - bprefix[lo]) * 256 + threadIdx.x;
+    if (e < a.count * a.ldp) axis_table_entry(a, e);
 }
 
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v)
@@ -141,14 +149,13 @@ hipError_t launch_axis_table(const AxisTableArgs& a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_axis_tables_batched(const AxisTableArgs* descs, const int64_t* prefix, int ndesc, int64_t total,
-                                      hipStream_t s)
+hipError_t launch_axis_tables_batched(const AxisTableArgs* descs, const int64_t* bprefix, int ndesc,
+                                      int64_t total_blocks, hipStream_t s)
 {
-    if (total <= 0) return hipSuccess;
-    const int64_t blocks = (total + 255) / 256;
-    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_axis_tables_batched, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, descs, prefix,
-                       ndesc, total);
+    if (total_blocks <= 0 || ndesc <= 0) return hipSuccess;
+    if (total_blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_axis_tables_batched, dim3(static_cast<unsigned>(total_blocks)), dim3(256), 0, s, descs,
+                       bprefix, ndesc);
     return hipGetLastError();
 }
 

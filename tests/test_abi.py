@@ -174,6 +174,11 @@ def test_points_validation(lib):
     assert lib.eval_field_points_ws_size(ctypes.byref(m), 10, L.GRF_SEP_F16, ctypes.byref(b)) == L.GRF_EUNSUPPORTED
     assert lib.eval_field_points_ws_size(ctypes.byref(m), -1, 0, ctypes.byref(b)) == L.GRF_EINVAL
     assert lib.eval_field_points_ws_size(ctypes.byref(m), 10, 0, ctypes.byref(b)) == 0
+    small = b.value
+    for P in (0, 1, 10_000, 3_000_000):  # P = 0 must not divide by zero on the host
+        assert lib.eval_field_points_ws_size(ctypes.byref(_modes(n=4096)), P, 0, ctypes.byref(b)) == 0
+    assert b.value >= small
+    assert lib.eval_field_points_ws_size(ctypes.byref(m), 5, 0, ctypes.byref(b)) == 0
     # P = 0 is a no-op even with null pointers
     assert lib.eval_field_points(ctypes.byref(m), None, 0, 0, None, ctypes.c_void_p(16), None, None, None, 0,
                                  None) == 0
