@@ -169,6 +169,7 @@ int grid_table_descs(const grf_modes* m, const grf_grid* g, int method, const Gr
         t.ldp = ldp;
         t.axis = a;
         t.ell = a < m->dim ? m->ell[a] : 1.0;
+        t.freq_scale = 1.0 / (6.283185307179586476925286766559 * t.ell);
         t.origin = g->origin[a];
         t.h = g->h[a];
         t.count = g->n[a];
@@ -189,11 +190,14 @@ int grid_table_descs(const grf_modes* m, const grf_grid* g, int method, const Gr
             if (a == 1 || (a == 0 && m->dim == 2)) {
                 t.format = bf ? (hilo ? TF_BF16_HILO : TF_BF16) : (hilo ? TF_F16_HILO : TF_F16);
                 t.conj = (a == 0);
+                t.blocked = true;
             } else if (a == 0) {  // 3-D x axis: (Re, -Im) Ex for the product with Ez
                 t.format = hilo ? TF_CPLX_F32 : (bf ? TF_BF16 : TF_F16);
                 t.conj = true;
+                t.blocked = true;
             } else if (a == 2 && m->dim == 3) {
-                t.format = TF_CPLX_F32;
+                // the one-pass fp16 form multiplies in packed fp16; the others in FP32
+                t.format = (!hilo && !bf) ? TF_F16 : TF_CPLX_F32;
             } else {
                 continue;  // dim 2: no z table for the separable form
             }

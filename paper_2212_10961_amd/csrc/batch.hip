@@ -209,8 +209,8 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
         const int nd = grid_table_descs(&items[i].modes, &items[i].grid, p->method, ws[i], d);
         for (int k = 0; k < nd; ++k) {
             td.push_back(d[k]);
-            tpre.push_back(elems);  // in 256-element blocks
-            elems += (d[k].count * d[k].ldp + 255) / 256;
+            tpre.push_back(elems);  // in 256-thread blocks
+            elems += axis_table_blocks(d[k]);
         }
     }
     p->n_desc = static_cast<int>(td.size());
@@ -307,9 +307,20 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
             GRF_HIP(hipEventCreate(&e0));
             GRF_HIP(hipEventCreate(&e1));
             for (const std::string& key : pending) {
+                // Up to 16 instances of the class, repeated until even the larger tile gives
+                // every resident block several work items: the comparison is then one of
+                // throughput on a full device, as in the real batch.
+                std::vector<SepBatchItem> cls;
+                for (int32_t i = 0; i < n && cls.size() < 16; ++i)
+                    if (keys[i] == key) cls.push_back(si[i]);
                 std::vector<SepBatchItem> sub;
-                for (int32_t i = 0; i < n && sub.size() < 16; ++i)
-                    if (keys[i] == key) sub.push_back(si[i]);
+                int64_t big_tiles = 0;
+                while (big_tiles < 4 * int64_t(p->grid) && sub.size() < 8192) {
+                    for (const SepBatchItem& b : cls) {
+                        sub.push_back(b);
+                        big_tiles += ((b.a.nx + 127) / 128) * ((b.a.ny + 127) / 128) * b.a.nz;
+                    }
+                }
                 float best = 1e30f;
                 int bestv = 0;
                 for (int v = 0; v < 2; ++v) {

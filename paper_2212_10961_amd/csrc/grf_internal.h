@@ -91,6 +91,7 @@ struct AxisTableArgs {
     int64_t ldp;
     int axis;
     double ell;
+    double freq_scale;  // 1 / (2 pi ell): revolutions per unit length per unit of z
     double origin;
     double h;
     int64_t count;  // number of grid points along the axis
@@ -98,11 +99,14 @@ struct AxisTableArgs {
     bool conj;      // store (re, -im) for half formats
     bool fast_trig; // cos/sin of the FP64-reduced fraction by the hardware units (FP32);
                     // for tables rounded to one fp16/bf16 (or FP32) pass, else FP64 sincospi
+    bool blocked;   // stage-major layout [ldp / 32][count][32] (the separable operands: one
+                    // 32-mode stage of every row is contiguous), else row-major [count][ldp]
     int format;
     void* out;      // primary table
     void* out_lo;   // lo table for *_HILO formats
 };
 hipError_t launch_axis_table(const AxisTableArgs& a, hipStream_t s);
+int64_t axis_table_blocks(const AxisTableArgs& a);  // 256-thread blocks one table needs
 
 // Table layout of eval_field_grid for a resolved method (base == nullptr: measure only),
 // and the descriptors of the tables it builds (returns how many, <= 3).

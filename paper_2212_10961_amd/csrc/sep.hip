@@ -27,6 +27,7 @@ namespace {
 typedef _Float16 half8 __attribute__((ext_vector_type(8)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 
 constexpr int kJC = 32;         // modes per LDS stage (64 reals of K)
 constexpr int kRowW = kJC + 4;  // padded LDS row, in 32-bit words
@@ -101,42 +102,51 @@ __device__ __forceinline__ void sep_tile(const SepArgs& a, int64_t tx, int64_t t
     const uint32_t* qy_lo = static_cast<const uint32_t*>(a.qy_lo);
 
     // global row offsets of this thread's chunks
+    // Operand tables are stage-major, [ldp / 32][rows][32]: stage j0 of row r starts at
+    // j0 * rows + r * 32, so a stage of consecutive rows is one contiguous run.
+    constexpr bool PK = D3 && !X3 && !BF;  // one-pass fp16 3-D: Ez in half pairs, packed fp16 product
     int64_t offa[CA], offb[CB];
 #pragma unroll
-    for (int i = 0; i < CA; ++i) offa[i] = min(y0 + ((t + NT * i) >> 3), a.ny - 1) * ldp + 4 * c4;
+    for (int i = 0; i < CA; ++i) offa[i] = min(y0 + ((t + NT * i) >> 3), a.ny - 1) * kJC + 4 * c4;
 #pragma unroll
-    for (int i = 0; i < CB; ++i) offb[i] = min(x0 + ((t + NT * i) >> 3), a.nx - 1) * ldp + 4 * c4;
+    for (int i = 0; i < CB; ++i) offb[i] = min(x0 + ((t + NT * i) >> 3), a.nx - 1) * kJC + 4 * c4;
 
     // Raw global data of one stage held by this thread: CA chunks (4 modes each) of A, CB of B;
     // 3-D: B chunks are Ex (pairs when !X3, float2 when X3) plus this thread's Ez chunk.
     uint4 ra[CA], ral[X3 ? CA : 1], rb[D3 && X3 ? 2 * CB : CB], rbl[!D3 && X3 ? CB : 1];
     float4 rez0 = make_float4(0.f, 0.f, 0.f, 0.f), rez1 = rez0;
+    uint4 rezh = make_uint4(0u, 0u, 0u, 0u);
 
     auto load = [&](int64_t j0) {
+        const int64_t sa = j0 * a.ny, sb = j0 * a.nx;
 #pragma unroll
         for (int i = 0; i < CA; ++i) {
-            ra[i] = *reinterpret_cast<const uint4*>(qy + offa[i] + j0);
-            if constexpr (X3) ral[i] = *reinterpret_cast<const uint4*>(qy_lo + offa[i] + j0);
+            ra[i] = *reinterpret_cast<const uint4*>(qy + sa + offa[i]);
+            if constexpr (X3) ral[i] = *reinterpret_cast<const uint4*>(qy_lo + sa + offa[i]);
         }
         if constexpr (D3) {
-            const float4* ez = reinterpret_cast<const float4*>(a.ez + z0 * ldp + j0 + 4 * c4);
-            rez0 = ez[0];
-            rez1 = ez[1];
+            if constexpr (PK) {
+                rezh = *reinterpret_cast<const uint4*>(reinterpret_cast<const uint32_t*>(a.ez) + z0 * ldp + j0 + 4 * c4);
+            } else {
+                const float4* ez = reinterpret_cast<const float4*>(a.ez + z0 * ldp + j0 + 4 * c4);
+                rez0 = ez[0];
+                rez1 = ez[1];
+            }
 #pragma unroll
             for (int i = 0; i < CB; ++i) {
                 if constexpr (X3) {
-                    const uint4* ex = reinterpret_cast<const uint4*>(static_cast<const float2*>(a.px) + offb[i] + j0);
+                    const uint4* ex = reinterpret_cast<const uint4*>(static_cast<const float2*>(a.px) + sb + offb[i]);
                     rb[2 * i] = ex[0];
                     rb[2 * i + 1] = ex[1];
                 } else {
-                    rb[i] = *reinterpret_cast<const uint4*>(static_cast<const uint32_t*>(a.px) + offb[i] + j0);
+                    rb[i] = *reinterpret_cast<const uint4*>(static_cast<const uint32_t*>(a.px) + sb + offb[i]);
                 }
             }
         } else {
 #pragma unroll
             for (int i = 0; i < CB; ++i) {
-                rb[i] = *reinterpret_cast<const uint4*>(static_cast<const uint32_t*>(a.px) + offb[i] + j0);
-                if constexpr (X3) rbl[i] = *reinterpret_cast<const uint4*>(static_cast<const uint32_t*>(a.px_lo) + offb[i] + j0);
+                rb[i] = *reinterpret_cast<const uint4*>(static_cast<const uint32_t*>(a.px) + sb + offb[i]);
+                if constexpr (X3) rbl[i] = *reinterpret_cast<const uint4*>(static_cast<const uint32_t*>(a.px_lo) + sb + offb[i]);
             }
         }
     };
@@ -149,10 +159,31 @@ __device__ __forceinline__ void sep_tile(const SepArgs& a, int64_t tx, int64_t t
             *reinterpret_cast<uint4*>(sA + row * kRowW + 4 * c4) = ra[i];
             if constexpr (X3) *reinterpret_cast<uint4*>(sA + (BM + row) * kRowW + 4 * c4) = ral[i];
         }
+        // packed fp16 factors of this thread's Ez chunk: P' = er (zr, -zi) + ei (zi, zr)
+        h2 z1[4], z2[4];
+        if constexpr (PK) {
+            const uint32_t zw[4] = {rezh.x, rezh.y, rezh.z, rezh.w};
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const h2 z = __builtin_bit_cast(h2, zw[m]);
+                z1[m] = h2{z.x, static_cast<_Float16>(-z.y)};
+                z2[m] = h2{z.y, z.x};
+            }
+        }
 #pragma unroll
         for (int i = 0; i < CB; ++i) {
             const int row = (t + NT * i) >> 3;
-            if constexpr (D3) {
+            if constexpr (PK) {
+                const uint32_t w[4] = {rb[i].x, rb[i].y, rb[i].z, rb[i].w};
+                uint32_t h[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const h2 e = __builtin_bit_cast(h2, w[m]);  // (Re Ex, -Im Ex)
+                    const h2 p = h2{e.x, e.x} * z1[m] + h2{e.y, e.y} * z2[m];
+                    h[m] = __builtin_bit_cast(uint32_t, p);
+                }
+                *reinterpret_cast<uint4*>(sB + row * kRowW + 4 * c4) = make_uint4(h[0], h[1], h[2], h[3]);
+            } else if constexpr (D3) {
                 // P = Ex * Ez, stored as (Re P, -Im P); Ex arrives as (Re, -Im)
                 float er[4], ei[4];
                 if constexpr (X3) {

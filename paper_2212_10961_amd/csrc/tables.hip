@@ -35,17 +35,17 @@ __device__ inline float half_to_float(uint16_t b) { return static_cast<float>(__
 __device__ inline float bf16_to_float(uint16_t b) { return static_cast<float>(__builtin_bit_cast(__bf16, b)); }
 
 // Entry e (= i * ldp + j) of one per-axis table.
-__device__ __forceinline__ void axis_table_entry(const AxisTableArgs& a, int64_t e)
+__device__ __forceinline__ void axis_table_entry(const AxisTableArgs& a, int64_t i, int64_t j)
 {
-    const int64_t i = e / a.ldp;
-    const int64_t j = e - i * a.ldp;
+    // row-major [count][ldp], or stage-major [ldp / 32][count][32]
+    const int64_t e = a.blocked ? ((j >> 5) * a.count + i) * 32 + (j & 31) : i * a.ldp + j;
 
     double f = 0.0;
     bool zero = j >= a.n;
     if (!zero) {
         const double x = a.origin + (static_cast<double>(i) + 0.5) * a.h;
         double t = 0.0;
-        if (a.z) t = (a.z[static_cast<int64_t>(a.axis) * a.n + j] * kInvTwoPi / a.ell) * x;
+        if (a.z) t = (a.z[static_cast<int64_t>(a.axis) * a.n + j] * a.freq_scale) * x;
         if (a.with_psi) t += a.phi[j] * kInvTwoPi;
         f = t - floor(t);  // exact in FP64
     }
@@ -91,16 +91,20 @@ __device__ __forceinline__ void axis_table_entry(const AxisTableArgs& a, int64_t
     }
 }
 
-__global__ __launch_bounds__(256) void k_axis_table(AxisTableArgs a)
+// Block b of a table covers row b / jblocks, modes 256 (b % jblocks) + threadIdx.x, with
+// jblocks = ceil(ldp / 256): the row/mode split is a per-block (scalar) division.
+__device__ __forceinline__ void axis_table_block(const AxisTableArgs& a, int64_t b)
 {
-    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
-    if (e >= a.count * a.ldp) return;
-    axis_table_entry(a, e);
+    const int64_t jblocks = (a.ldp + 255) / 256;
+    const int64_t i = b / jblocks;
+    const int64_t j = (b - i * jblocks) * 256 + threadIdx.x;
+    if (j < a.ldp) axis_table_entry(a, i, j);
 }
 
-// Many tables in one launch.  Blocks are assigned to descriptors: descriptor d owns blocks
-// [bprefix[d], bprefix[d+1]) and its element e is handled by block bprefix[d] + e / 256.
-// The descriptor lookup depends only on the block index, so it runs once per block on the
+__global__ __launch_bounds__(256) void k_axis_table(AxisTableArgs a) { axis_table_block(a, blockIdx.x); }
+
+// Many tables in one launch: descriptor d owns blocks [bprefix[d], bprefix[d+1]).  The
+// descriptor lookup depends only on the block index, so it runs once per block on the
 // scalar unit.
 __global__ __launch_bounds__(256) void k_axis_tables_batched(const AxisTableArgs* __restrict__ descs,
                                                              const int64_t* __restrict__ bprefix, int ndesc)
@@ -112,9 +116,7 @@ __global__ __launch_bounds__(256) void k_axis_tables_batched(const AxisTableArgs
         if (bprefix[mid] <= b) lo = mid;
         else hi = mid - 1;
     }
-    const AxisTableArgs& a = descs[lo];
-    const int64_t e = (b - bprefix[lo]) * 256 + threadIdx.x;
-    if (e < a.count * a.ldp) axis_table_entry(a, e);
+    axis_table_block(descs[lo], b - bprefix[lo]);
 }
 
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v)
@@ -140,11 +142,13 @@ __global__ __launch_bounds__(256) void k_mode_params(const double* z, const doub
 
 }  // namespace
 
+int64_t axis_table_blocks(const AxisTableArgs& a) { return a.count * ((a.ldp + 255) / 256); }
+
 hipError_t launch_axis_table(const AxisTableArgs& a, hipStream_t s)
 {
-    const int64_t total = a.count * a.ldp;
-    if (total <= 0) return hipSuccess;
-    const int64_t blocks = (total + 255) / 256;
+    const int64_t blocks = axis_table_blocks(a);
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_axis_table, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, a);
     return hipGetLastError();
 }
