@@ -157,7 +157,7 @@ def main():
         oracle.field_cells(z, phi, sigma, cfg["ell"], shape, probe)
         dt = time.perf_counter() - t0
         rate = probe.size * N / max(dt, 1e-9)
-        m_cells = int(min(max(10.0 * rate / N, 1024), 400_000))
+        m_cells = int(min(max(12.0 * rate / N, 1024), 4_000_000))  # ~12 s of oracle work
         cells = wl.sample_cells(C, m_cells, 4243)
         log(f"[bench] cpu_baseline: oracle on {cells.size} sampled cells x {N} modes, {threads} threads")
         t0 = time.perf_counter()
@@ -178,7 +178,10 @@ def main():
             log(f"[bench] {m}: rel_rms {rel:.2e}")
 
     # ------------------------------------------------------------ headline: best variant at rel-RMS <= 1e-3
-    ok = [m for m in methods if m.startswith("sep") and (m not in errs or errs[m]["rel_rms"] <= 1e-3)]
+    # Without a measured error, only forms whose error bound is below the bar qualify
+    # (the one-pass bf16 form has rel-RMS ~2e-3 and never does).
+    ok = [m for m in methods if m.startswith("sep") and
+          (errs[m]["rel_rms"] <= 1e-3 if m in errs else m != "sep_bf16")]
     head = min(ok, key=lambda m: results[m]["ms_per_step"]) if ok else methods[0]
     r = results[head]
     passes = 3 if head.endswith("x3") else 1

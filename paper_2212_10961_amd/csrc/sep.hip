@@ -105,11 +105,20 @@ __device__ __forceinline__ void sep_tile(const SepArgs& a, int64_t tx, int64_t t
     // Operand tables are stage-major, [ldp / 32][rows][32]: stage j0 of row r starts at
     // j0 * rows + r * 32, so a stage of consecutive rows is one contiguous run.
     constexpr bool PK = D3 && !X3 && !BF;  // one-pass fp16 3-D: Ez in half pairs, packed fp16 product
+    // Many tiles read the same operand rows at the same time (every z-slice shares Q and Ex).
+    // Each tile visits its rows in a rotated order so that concurrent requests from different
+    // CUs land on different cache lines (and L2 channels) instead of queueing on one.
+    const int rot = static_cast<int>((z0 * 37 + tx * 11 + ty * 5) & 31) * 8;  // rows, multiple of 8
+    int rowa[CA], rowb[CB];
+#pragma unroll
+    for (int i = 0; i < CA; ++i) rowa[i] = (((t + NT * i) >> 3) + rot) % BM;
+#pragma unroll
+    for (int i = 0; i < CB; ++i) rowb[i] = (((t + NT * i) >> 3) + rot) % BN;
     int64_t offa[CA], offb[CB];
 #pragma unroll
-    for (int i = 0; i < CA; ++i) offa[i] = min(y0 + ((t + NT * i) >> 3), a.ny - 1) * kJC + 4 * c4;
+    for (int i = 0; i < CA; ++i) offa[i] = min(y0 + rowa[i], a.ny - 1) * kJC + 4 * c4;
 #pragma unroll
-    for (int i = 0; i < CB; ++i) offb[i] = min(x0 + ((t + NT * i) >> 3), a.nx - 1) * kJC + 4 * c4;
+    for (int i = 0; i < CB; ++i) offb[i] = min(x0 + rowb[i], a.nx - 1) * kJC + 4 * c4;
 
     // Raw global data of one stage held by this thread: CA chunks (4 modes each) of A, CB of B;
     // 3-D: B chunks are Ex (pairs when !X3, float2 when X3) plus this thread's Ez chunk.
@@ -155,7 +164,7 @@ __device__ __forceinline__ void sep_tile(const SepArgs& a, int64_t tx, int64_t t
         uint32_t* sB = sA + NB * BM * kRowW;
 #pragma unroll
         for (int i = 0; i < CA; ++i) {
-            const int row = (t + NT * i) >> 3;
+            const int row = rowa[i];
             *reinterpret_cast<uint4*>(sA + row * kRowW + 4 * c4) = ra[i];
             if constexpr (X3) *reinterpret_cast<uint4*>(sA + (BM + row) * kRowW + 4 * c4) = ral[i];
         }
@@ -172,7 +181,7 @@ __device__ __forceinline__ void sep_tile(const SepArgs& a, int64_t tx, int64_t t
         }
 #pragma unroll
         for (int i = 0; i < CB; ++i) {
-            const int row = (t + NT * i) >> 3;
+            const int row = rowb[i];
             if constexpr (PK) {
                 const uint32_t w[4] = {rb[i].x, rb[i].y, rb[i].z, rb[i].w};
                 uint32_t h[4];
