@@ -140,6 +140,23 @@ int eval_field_grid_ws_size(const grf_modes* modes, const grf_grid* grid, int me
 int eval_field_grid(const grf_modes* modes, const grf_grid* grid, int method, const grf_epi* epi,
                     float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * eval_field_grid_tile -- eval_field_grid with an explicit tile shape for the separable
+ * methods (tuning and tests).  tile = -1 is the size-based default (what eval_field_grid
+ * uses); 0 .. grf_sep_tile_count()-1 selects a shape.  Any selector gives the same field up
+ * to the rounding of the fp16/bf16 operands' FP32 accumulation order.  A selector >= 0 with
+ * a direct method, or one out of range, is GRF_EINVAL.  Other arguments as eval_field_grid.
+ */
+int eval_field_grid_tile(const grf_modes* modes, const grf_grid* grid, int method, int tile, const grf_epi* epi,
+                         float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes, void* stream);
+
+/* Number of separable tile selectors. */
+int grf_sep_tile_count(void);
+
+/* Block shape of a separable tile selector for a method (GRF_SEP_*) and dim (2 or 3):
+ * rows (y cells) x cols (x cells) per block, and the z-slices one block covers. */
+int grf_sep_tile_shape(int tile, int method, int dim, int32_t* rows, int32_t* cols, int32_t* slices);
+
 /* FP64 outputs of the plain method (Sec. 4.1 eq. DiscreteFT), DIRECT_F64 only:
  * y64 / k64 device double[C] or NULL (at least one non-NULL); mu is used for k64. */
 int eval_field_grid_f64(const grf_modes* modes, const grf_grid* grid, double mu, double* y64,

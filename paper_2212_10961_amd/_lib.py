@@ -26,6 +26,7 @@ METHODS = {
 # Every symbol include/grf.h declares.
 EXPORTS = [
     "grf_version", "grf_last_error", "make_modes", "eval_field_grid_ws_size", "eval_field_grid",
+    "eval_field_grid_tile", "grf_sep_tile_count", "grf_sep_tile_shape",
     "eval_field_grid_f64", "eval_field_points_ws_size", "eval_field_points", "epilogue_apply",
     "field_backward_ws_size", "field_backward", "field_backward_grid_ws_size", "field_backward_grid",
     "grf_plan_create", "grf_plan_destroy", "eval_field_batch", "grf_plan_info",
@@ -85,6 +86,10 @@ def load():
         "eval_field_grid_ws_size": ([P(GrfModes), P(GrfGrid), ctypes.c_int, P(sz)], ctypes.c_int),
         "eval_field_grid": ([P(GrfModes), P(GrfGrid), ctypes.c_int, P(GrfEpi), vp, vp, vp, vp, sz, vp],
                             ctypes.c_int),
+        "eval_field_grid_tile": ([P(GrfModes), P(GrfGrid), ctypes.c_int, ctypes.c_int, P(GrfEpi), vp, vp, vp,
+                                  vp, sz, vp], ctypes.c_int),
+        "grf_sep_tile_count": ([], ctypes.c_int),
+        "grf_sep_tile_shape": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, P(i32), P(i32), P(i32)], ctypes.c_int),
         "eval_field_grid_f64": ([P(GrfModes), P(GrfGrid), ctypes.c_double, vp, vp, vp, sz, vp], ctypes.c_int),
         "eval_field_points_ws_size": ([P(GrfModes), i64, ctypes.c_int, P(sz)], ctypes.c_int),
         "eval_field_points": ([P(GrfModes), vp, i64, ctypes.c_int, P(GrfEpi), vp, vp, vp, vp, sz, vp],

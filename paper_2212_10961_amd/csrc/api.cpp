@@ -212,11 +212,7 @@ static hipError_t build_tables(const grf_modes* m, const grf_grid* g, int method
 {
     AxisTableArgs d[3];
     const int nd = grid_table_descs(m, g, method, w, d);
-    for (int i = 0; i < nd; ++i) {
-        hipError_t e = launch_axis_table(d[i], s);
-        if (e != hipSuccess) return e;
-    }
-    return hipSuccess;
+    return launch_axis_tables(d, nd, s);
 }
 
 }  // namespace grf
@@ -269,10 +265,13 @@ int eval_field_grid_ws_size(const grf_modes* modes, const grf_grid* grid, int me
     return GRF_OK;
 }
 
-int eval_field_grid(const grf_modes* modes, const grf_grid* grid, int method, const grf_epi* epi,
-                    float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes, void* stream)
+}  // extern "C"
+
+namespace grf {
+
+static int grid_eval(const char* fn, const grf_modes* modes, const grf_grid* grid, int method, int tile,
+                     const grf_epi* epi, float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes, void* stream)
 {
-    const char* fn = "eval_field_grid";
     int rc;
     if ((rc = check_modes(modes, fn))) return rc;
     if ((rc = check_grid(grid, modes->dim, fn))) return rc;
@@ -280,6 +279,9 @@ int eval_field_grid(const grf_modes* modes, const grf_grid* grid, int method, co
     if ((rc = check_epi(epi, k, ind, fn))) return rc;
     method = resolve_grid_method(method, grid);
     if (method < GRF_DIRECT_F32 || method > GRF_SEP_F16_X3) return fail(GRF_EINVAL, "%s: unknown method %d", fn, method);
+    if (tile < -1 || tile >= sep_tile_count())
+        return fail(GRF_EINVAL, "%s: tile selector %d outside [-1, %d)", fn, tile, sep_tile_count());
+    if (tile >= 0 && !is_sep(method)) return fail(GRF_EINVAL, "%s: tile selectors apply to separable methods", fn);
     const GridWs need = grid_ws(modes, grid, method, nullptr);
     if (ws_bytes < need.bytes || (!ws && need.bytes))
         return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need.bytes, ws_bytes);
@@ -318,9 +320,42 @@ int eval_field_grid(const grf_modes* modes, const grf_grid* grid, int method, co
         a.y = y;
         a.k = k;
         a.ind = ind;
-        a.tile = -1;  // size-based default
+        a.tile = tile;  // -1: size-based default
         GRF_HIP(launch_sep(a, s));
     }
+    return GRF_OK;
+}
+
+}  // namespace grf
+
+extern "C" {
+
+int eval_field_grid(const grf_modes* modes, const grf_grid* grid, int method, const grf_epi* epi,
+                    float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes, void* stream)
+{
+    return grid_eval("eval_field_grid", modes, grid, method, -1, epi, y, k, ind, ws, ws_bytes, stream);
+}
+
+int eval_field_grid_tile(const grf_modes* modes, const grf_grid* grid, int method, int tile, const grf_epi* epi,
+                         float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes, void* stream)
+{
+    return grid_eval("eval_field_grid_tile", modes, grid, method, tile, epi, y, k, ind, ws, ws_bytes, stream);
+}
+
+int grf_sep_tile_count(void) { return sep_tile_count(); }
+
+int grf_sep_tile_shape(int tile, int method, int dim, int32_t* rows, int32_t* cols, int32_t* slices)
+{
+    const char* fn = "grf_sep_tile_shape";
+    if (tile < 0 || tile >= sep_tile_count()) return fail(GRF_EINVAL, "%s: tile %d outside [0, %d)", fn, tile, sep_tile_count());
+    if (!is_sep(method)) return fail(GRF_EINVAL, "%s: method %d is not separable", fn, method);
+    if (dim != 2 && dim != 3) return fail(GRF_EINVAL, "%s: dim must be 2 or 3", fn);
+    if (!rows || !cols || !slices) return fail(GRF_EINVAL, "%s: NULL output", fn);
+    int bm = 0, bn = 0;
+    sep_tile_shape(tile, &bm, &bn);
+    *rows = bm;
+    *cols = bn;
+    *slices = sep_tile_slices(tile, method, dim == 3);
     return GRF_OK;
 }
 

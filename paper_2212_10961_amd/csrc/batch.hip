@@ -46,7 +46,7 @@ struct grf_plan {
     void* d_items = nullptr;
     size_t cap_items = 0;
     AxisTableArgs* d_tdesc = nullptr;
-    int64_t* d_tprefix = nullptr;
+    uint64_t* d_tblk = nullptr;  // per work block: (descriptor << 40) | local block
     size_t cap_tdesc = 0;
     unsigned long long* d_counter = nullptr;
 
@@ -159,7 +159,7 @@ hipError_t enqueue(grf_plan* p, hipStream_t s, const void* items, int n_items_de
 {
     hipError_t e = launch_fill_u64(p->d_counter, 0ull, s);
     if (e != hipSuccess) return e;
-    e = launch_axis_tables_batched(p->d_tdesc, p->d_tprefix, p->n_desc, p->table_blocks, s);
+    e = launch_axis_tables_batched(p->d_tdesc, p->d_tblk, p->table_blocks, s);
     if (e != hipSuccess) return e;
     if (is_sep(p->method))
         return launch_sep_batch(p->method, p->d3, static_cast<const SepBatchItem*>(items), n_items_desc, total,
@@ -201,25 +201,36 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
     }
     GRF_HIP(ensure(p->d_tables, p->cap_tables, tbytes));
     std::vector<AxisTableArgs> td;
-    std::vector<int64_t> tpre;
-    int64_t elems = 0;
+    std::vector<uint64_t> blk;
+    {
+        int64_t total = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            AxisTableArgs d[3];
+            const int nd = grid_table_descs(&items[i].modes, &items[i].grid, p->method, ws[i], d);
+            for (int k = 0; k < nd; ++k) total += axis_table_blocks(d[k]);
+        }
+        if (total > 0x7fffffff) return fail(GRF_EINVAL, "%s: batch tables too large for one launch", fn);
+        blk.reserve(static_cast<size_t>(total));
+    }
     for (int32_t i = 0; i < n; ++i) {
         ws[i] = grid_ws(&items[i].modes, &items[i].grid, p->method, static_cast<char*>(p->d_tables) + toff[i]);
         AxisTableArgs d[3];
         const int nd = grid_table_descs(&items[i].modes, &items[i].grid, p->method, ws[i], d);
         for (int k = 0; k < nd; ++k) {
+            const uint64_t di = td.size();
             td.push_back(d[k]);
-            tpre.push_back(elems);  // in 256-thread blocks
-            elems += axis_table_blocks(d[k]);
+            const int64_t nb = axis_table_blocks(d[k]);
+            for (int64_t w = 0; w < nb; ++w) blk.push_back((di << 40) | static_cast<uint64_t>(w));
         }
     }
+    if (td.size() >= (size_t(1) << 23)) return fail(GRF_EINVAL, "%s: too many tables in one batch", fn);
     p->n_desc = static_cast<int>(td.size());
-    p->table_blocks = elems;
-    GRF_HIP(ensure(p->d_tdesc, p->cap_tdesc, td.size() * sizeof(AxisTableArgs) + tpre.size() * sizeof(int64_t) + 256));
-    p->d_tprefix = reinterpret_cast<int64_t*>(reinterpret_cast<char*>(p->d_tdesc) +
-                                              align256(td.size() * sizeof(AxisTableArgs)));
+    p->table_blocks = static_cast<int64_t>(blk.size());
+    GRF_HIP(ensure(p->d_tdesc, p->cap_tdesc, align256(td.size() * sizeof(AxisTableArgs)) + blk.size() * sizeof(uint64_t)));
+    p->d_tblk = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(p->d_tdesc) +
+                                            align256(td.size() * sizeof(AxisTableArgs)));
     GRF_HIP(hipMemcpy(p->d_tdesc, td.data(), td.size() * sizeof(AxisTableArgs), hipMemcpyHostToDevice));
-    GRF_HIP(hipMemcpy(p->d_tprefix, tpre.data(), tpre.size() * sizeof(int64_t), hipMemcpyHostToDevice));
+    GRF_HIP(hipMemcpy(p->d_tblk, blk.data(), blk.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
     if (!p->d_counter) {
         void* q = nullptr;
         GRF_HIP(hipMalloc(&q, 256));
@@ -302,7 +313,7 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
                 if (!p->tuned.count(keys[i]) && std::find(pending.begin(), pending.end(), keys[i]) == pending.end())
                     pending.push_back(keys[i]);
         if (!pending.empty()) {
-            GRF_HIP(launch_axis_tables_batched(p->d_tdesc, p->d_tprefix, p->n_desc, p->table_blocks, p->cap));
+            GRF_HIP(launch_axis_tables_batched(p->d_tdesc, p->d_tblk, p->table_blocks, p->cap));
             hipEvent_t e0, e1;
             GRF_HIP(hipEventCreate(&e0));
             GRF_HIP(hipEventCreate(&e1));
@@ -395,7 +406,6 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
         GRF_HIP(hipGraphInstantiate(&p->exec, p->graph, nullptr, nullptr, 0));
     }
     p->built = true;
-    (void)fn;
     return GRF_OK;
 }
 

@@ -106,7 +106,8 @@ struct AxisTableArgs {
     void* out_lo;   // lo table for *_HILO formats
 };
 hipError_t launch_axis_table(const AxisTableArgs& a, hipStream_t s);
-int64_t axis_table_blocks(const AxisTableArgs& a);  // 256-thread blocks one table needs
+hipError_t launch_axis_tables(const AxisTableArgs* d, int nd, hipStream_t s);  // nd <= 3, one launch
+int64_t axis_table_blocks(const AxisTableArgs& a);  // 256-thread work blocks one table needs
 
 // Table layout of eval_field_grid for a resolved method (base == nullptr: measure only),
 // and the descriptors of the tables it builds (returns how many, <= 3).
@@ -164,6 +165,7 @@ struct SepArgs {
 hipError_t launch_sep(const SepArgs& a, hipStream_t s);
 int sep_tile_count();                // number of tile selectors
 void sep_tile_shape(int tile, int* bm, int* bn);
+int sep_tile_slices(int tile, int method, bool d3);  // z-slices per block
 int sep_default_tile(int method, int64_t nx, int64_t ny, int64_t nz);
 
 // ---------------------------------------------------------------- batched (persistent) launches
@@ -196,10 +198,11 @@ hipError_t launch_direct_batch(const DirectBatchItem* items, int n_inst, int64_t
 int direct_batch_blocks_per_cu();
 constexpr int kDirectTile = 64;  // cells per tile side of the direct grid kernel
 
-// Batched per-axis tables: one launch over many AxisTableArgs (device array).  Descriptor i
-// owns 256-element blocks [bprefix[i], bprefix[i+1]) (ceil(count * ldp / 256) of them).
-hipError_t launch_axis_tables_batched(const AxisTableArgs* descs, const int64_t* bprefix, int ndesc,
-                                      int64_t total_blocks, hipStream_t s);
+// Batched per-axis tables: one launch over many AxisTableArgs (device array).  blk[b]
+// (device, total_blocks entries) = (descriptor << 40) | work block within that table, for
+// work blocks 0 .. axis_table_blocks(descriptor) - 1 of every descriptor.
+hipError_t launch_axis_tables_batched(const AxisTableArgs* descs, const uint64_t* blk, int64_t total_blocks,
+                                      hipStream_t s);
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, hipStream_t s);
 
 // ---------------------------------------------------------------- adjoint

@@ -13,9 +13,9 @@
 // were reduced in FP64 before rounding.  Output rows are y, columns x, so each wave's
 // stores are 128-byte runs along x.
 //
-// Pipeline: global loads for stage s+1 are issued into registers before the MFMAs of
-// stage s; the 3-D operand P_z = Ex * Ez[z] is formed from those registers while they
-// are written to the other LDS buffer (double-buffered when both copies fit in LDS).
+// Pipeline: the operands of stage s+1 (32 modes) are loaded while the MFMAs consume stage s
+// from the other LDS buffer.  Most forms load straight into LDS; the 3-D forms that need
+// FP32 products (bf16, hi+lo) stage through registers and form P_z = Ex * Ez[z] there.
 #include <hip/hip_runtime.h>
 
 #include "grf_internal.h"
@@ -78,11 +78,13 @@ struct SepShape {
     static constexpr int LDS_WORDS = NBUF * STAGE_W;
 };
 
-// One output tile (rows y0.., cols x0.., slice z0) of the separable contraction.
+// One output tile (rows y0.., cols x0.., slice z0) of the separable contraction, with the
+// operand stages staged through registers (used where the B operand needs FP32 arithmetic:
+// the 3-D bf16 and hi+lo forms).
 // WM x WN waves; each wave owns TM x TN MFMA tiles of 32x32 (rows y, cols x).
 // `smem` must hold SepShape<...>::LDS_WORDS words.  Called by whole blocks.
 template <int WM, int WN, int TM, int TN, bool BF, bool X3, bool D3>
-__device__ __forceinline__ void sep_tile(const SepArgs& a, int64_t tx, int64_t ty, int64_t z0, uint4* smem)
+__device__ __forceinline__ void sep_tile_reg(const SepArgs& a, int64_t tx, int64_t ty, int64_t z0, uint4* smem)
 {
     using S = SepShape<WM, WN, TM, TN, X3>;
     constexpr int NT = S::NT, BM = S::BM, BN = S::BN, NB = S::NB, STAGE_W = S::STAGE_W, NBUF = S::NBUF;
@@ -310,13 +312,369 @@ __device__ __forceinline__ void sep_tile(const SepArgs& a, int64_t tx, int64_t t
         }
 }
 
-template <int WM, int WN, int TM, int TN, bool BF, bool X3, bool D3>
+// ---- direct-to-LDS staging -------------------------------------------------------------
+//
+// Operand stages go from global memory straight into LDS (global_load_lds_dwordx4: the 64
+// lanes of one instruction fill one contiguous 1 KiB run, lane l at byte 16 l), so no
+// registers, LDS stores or waits sit between a prefetch and the MFMAs.  LDS rows are
+// unpadded (one stage of one table row = 32 words = 8 chunks of 16 bytes); chunk c of row r
+// lives at chunk c ^ swz(r) of that row, which puts the 16 lanes of a fragment read (16
+// consecutive rows, one logical chunk) on distinct banks.  The two stage buffers are
+// separate LDS objects so that waits for the buffer in flight do not land on reads of the
+// other one.  In 3-D the one-pass fp16 operand P_z = Ex * Ez[z] is formed on the B
+// fragments in registers (packed fp16), and a block may cover ZS consecutive z-slices that
+// share every A and Ex fragment it reads.
+typedef __attribute__((address_space(3))) void lds_void;
+typedef const __attribute__((address_space(1))) void gbl_void;
+
+__device__ __forceinline__ int swz(int r) { return (r ^ (r >> 3)) & 7; }
+
+__device__ __forceinline__ void load_to_lds(const uint32_t* g, char* s)
+{
+    __builtin_amdgcn_global_load_lds((gbl_void*)g, (lds_void*)s, 16, 0, 0);
+}
+
+__device__ __forceinline__ void wait_loads() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// LDS stage: A rows (hi, lo), B rows (hi, lo), then EZR rows of Ez (one per z-slice, 3-D).
+template <int WM, int WN, int TM, int TN, bool X3, int EZR>
+struct DlShape {
+    static constexpr int NW = WM * WN;
+    static constexpr int BM = WM * TM * 32, BN = WN * TN * 32;
+    static constexpr int NB = X3 ? 2 : 1;
+    static constexpr int ROW_B = kJC * 4;  // bytes of one stage of one table row
+    static constexpr int EZ_OFF = NB * (BM + BN) * ROW_B;
+    static constexpr int STAGE_B = EZ_OFF + EZR * ROW_B;
+    static constexpr bool FITS = 2 * STAGE_B <= 160 * 1024 && (BM / 8) % NW == 0 && (BN / 8) % NW == 0;
+};
+
+// Forms that stage directly into LDS: every table reaches the MFMAs unchanged, except the
+// one-pass fp16 3-D product, which is formed in packed fp16 on the fragments.
+template <int WM, int WN, int TM, int TN, int ZS, bool BF, bool X3, bool D3>
+constexpr bool use_dl()
+{
+    return DlShape<WM, WN, TM, TN, X3, D3 ? ZS : 0>::FITS && !(D3 && (X3 || BF));
+}
+
+// One output tile (rows y0.., cols x0.., slices zb*ZS .. zb*ZS+ZS-1) with direct-to-LDS
+// staging.  `lds0` and `lds1` each hold DlShape<..., D3 ? ZS : 0>::STAGE_B bytes.  Called by
+// whole blocks.
+template <int WM, int WN, int TM, int TN, int ZS, bool BF, bool X3, bool D3>
+__device__ __forceinline__ void sep_tile_dl(const SepArgs& a, int64_t tx, int64_t ty, int64_t zb, uint4* lds0,
+                                            uint4* lds1)
+{
+    using S = DlShape<WM, WN, TM, TN, X3, D3 ? ZS : 0>;
+    constexpr int BM = S::BM, BN = S::BN, NB = S::NB, ROW_B = S::ROW_B, NW = S::NW, EZ_OFF = S::EZ_OFF;
+    constexpr int KA = BM / 8 / NW, KB = BN / 8 / NW;  // 1 KiB load instructions per wave and stage
+    static_assert(!D3 || (!X3 && !BF), "3-D direct staging is the one-pass fp16 form");
+    static_assert(D3 || ZS == 1, "2-D tiles cover one slice");
+
+    const int l = threadIdx.x & 63, h = l >> 5;
+    const int wave = __builtin_amdgcn_readfirstlane(static_cast<int>(threadIdx.x >> 6));
+    const int wm = wave / WN, wn = wave % WN;
+    const int64_t x0 = tx * BN, y0 = ty * BM, z0 = zb * ZS;
+    const int64_t ldp = a.ldp;
+
+    const uint32_t* qy = static_cast<const uint32_t*>(a.qy);
+    const uint32_t* qy_lo = static_cast<const uint32_t*>(a.qy_lo);
+    const uint32_t* px = static_cast<const uint32_t*>(a.px);
+    const uint32_t* px_lo = static_cast<const uint32_t*>(a.px_lo);
+
+    // Load assignment: instruction k of this wave fills LDS rows 8 rb .. 8 rb + 7 of its
+    // operand.  Tiles start at rotated row blocks so that concurrent requests of different
+    // CUs (every z-slice reads the same Q and Ex rows) spread over cache lines and channels.
+    const int rot = static_cast<int>((zb * 37 + tx * 11 + ty * 5) & 31);
+    int32_t offa[KA], offb[KB];
+    int lda[KA], ldb[KB];
+#pragma unroll
+    for (int k = 0; k < KA; ++k) {
+        const int rb = (wave * KA + k + rot) & (BM / 8 - 1);
+        const int row = rb * 8 + (l >> 3);
+        offa[k] = static_cast<int32_t>(min(y0 + row, a.ny - 1) * kJC + 4 * ((l & 7) ^ swz(row)));
+        lda[k] = rb * 8 * ROW_B;
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const int rb = (wave * KB + k + rot) & (BN / 8 - 1);
+        const int row = rb * 8 + (l >> 3);
+        offb[k] = static_cast<int32_t>(min(x0 + row, a.nx - 1) * kJC + 4 * ((l & 7) ^ swz(row)));
+        ldb[k] = rb * 8 * ROW_B;
+    }
+
+    // 3-D: lanes 0 .. 8 ZS - 1 of wave 0 also stage the Ez words (half pairs) of the z-slices
+    const uint32_t* ezl =
+        D3 ? reinterpret_cast<const uint32_t*>(a.ez) + min(z0 + (l >> 3), a.nz - 1) * ldp + 4 * (l & 7) : nullptr;
+
+    auto issue = [&](int64_t j0, char* buf) {
+        if constexpr (D3) {
+            if (wave == 0 && l < 8 * ZS) load_to_lds(ezl + j0, buf + EZ_OFF);
+        }
+        const uint32_t* sa = qy + j0 * a.ny;
+#pragma unroll
+        for (int k = 0; k < KA; ++k) load_to_lds(sa + offa[k], buf + lda[k]);
+        if constexpr (X3) {
+            const uint32_t* sl = qy_lo + j0 * a.ny;
+#pragma unroll
+            for (int k = 0; k < KA; ++k) load_to_lds(sl + offa[k], buf + BM * ROW_B + lda[k]);
+        }
+        const uint32_t* sb = px + j0 * a.nx;
+#pragma unroll
+        for (int k = 0; k < KB; ++k) load_to_lds(sb + offb[k], buf + NB * BM * ROW_B + ldb[k]);
+        if constexpr (X3) {
+            const uint32_t* sl = px_lo + j0 * a.nx;
+#pragma unroll
+            for (int k = 0; k < KB; ++k) load_to_lds(sl + offb[k], buf + (NB * BM + BN) * ROW_B + ldb[k]);
+        }
+    };
+
+    // fragment rows of this lane: byte offset of the row and the chunk swizzle (with h folded in)
+    int fra[TM], ga[TM], frb[TN], gb[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int row = (wm * TM + i) * 32 + (l & 31);
+        fra[i] = row * ROW_B;
+        ga[i] = swz(row) ^ h;
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+        const int col = (wn * TN + j) * 32 + (l & 31);
+        frb[j] = col * ROW_B;
+        gb[j] = swz(col) ^ h;
+    }
+
+    f32x16 acc[ZS][TM][TN];
+#pragma unroll
+    for (int zs = 0; zs < ZS; ++zs)
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j)
+#pragma unroll
+                for (int e = 0; e < 16; ++e) acc[zs][i][j][e] = 0.f;
+
+    // Fragments of one k-step (8 modes): A rows (hi, lo), B columns (hi, lo), Ez words.
+    struct Frag {
+        uint4 a[TM], al[X3 ? TM : 1], b[TN], bl[X3 ? TN : 1], ez[D3 ? ZS : 1];
+    };
+    auto read = [&](const char* buf, int ks, Frag& f) {
+        const char* sA = buf;
+        const char* sB = buf + NB * BM * ROW_B;
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int o = fra[i] + (((2 * ks) ^ ga[i]) << 4);
+            f.a[i] = *reinterpret_cast<const uint4*>(sA + o);
+            if constexpr (X3) f.al[i] = *reinterpret_cast<const uint4*>(sA + BM * ROW_B + o);
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int o = frb[j] + (((2 * ks) ^ gb[j]) << 4);
+            f.b[j] = *reinterpret_cast<const uint4*>(sB + o);
+            if constexpr (X3) f.bl[j] = *reinterpret_cast<const uint4*>(sB + BN * ROW_B + o);
+        }
+        if constexpr (D3) {
+            // this lane's Ez words are modes 8 ks + 4 h .. + 3 (a broadcast read)
+#pragma unroll
+            for (int zs = 0; zs < ZS; ++zs)
+                f.ez[zs] = *reinterpret_cast<const uint4*>(buf + EZ_OFF + zs * ROW_B + ((2 * ks + h) << 4));
+        }
+    };
+    auto mac = [&](const Frag& f) {
+        if constexpr (D3) {
+#pragma unroll
+            for (int zs = 0; zs < ZS; ++zs) {
+                // P' = (Re P, -Im P) = e.x (zr, -zi) + e.y (zi, zr), with e = (Re Ex, -Im Ex)
+                const uint32_t zw[4] = {f.ez[zs].x, f.ez[zs].y, f.ez[zs].z, f.ez[zs].w};
+                h2 z1[4], z2[4];
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const h2 z = __builtin_bit_cast(h2, zw[m]);
+                    z1[m] = h2{z.x, static_cast<_Float16>(-z.y)};
+                    z2[m] = h2{z.y, z.x};
+                }
+                uint4 fp[TN];
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    const uint32_t w[4] = {f.b[j].x, f.b[j].y, f.b[j].z, f.b[j].w};
+                    uint32_t p[4];
+#pragma unroll
+                    for (int m = 0; m < 4; ++m) {
+                        const h2 e = __builtin_bit_cast(h2, w[m]);
+                        p[m] = __builtin_bit_cast(uint32_t, h2{e.x, e.x} * z1[m] + h2{e.y, e.y} * z2[m]);
+                    }
+                    fp[j] = make_uint4(p[0], p[1], p[2], p[3]);
+                }
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j) acc[zs][i][j] = mfma<false>(f.a[i], fp[j], acc[zs][i][j]);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) {
+                    acc[0][i][j] = mfma<BF>(f.a[i], f.b[j], acc[0][i][j]);
+                    if constexpr (X3) {
+                        acc[0][i][j] = mfma<BF>(f.a[i], f.bl[j], acc[0][i][j]);
+                        acc[0][i][j] = mfma<BF>(f.al[i], f.b[j], acc[0][i][j]);
+                    }
+                }
+        }
+    };
+    // With one wave per SIMD (four-wave blocks, two z-slices) the MFMA pipe has no other wave
+    // to cover the read -> product -> MFMA chain, so each k-step is split into two fenced
+    // scheduling regions: the LDS reads of the next k-step ride along the MFMAs of slice 0,
+    // and the Ez products of the next k-step along the MFMAs of slice 1.
+    constexpr bool PIPE = D3 && NW == 4 && ZS == 2 && TM * TN == 8;
+    auto prod = [&](const Frag& f, int zs, uint4(&fp)[TN]) {
+        // P' = (Re P, -Im P) = e.x (zr, -zi) + e.y (zi, zr), with e = (Re Ex, -Im Ex)
+        const uint32_t zw[4] = {f.ez[zs].x, f.ez[zs].y, f.ez[zs].z, f.ez[zs].w};
+        h2 z1[4], z2[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const h2 z = __builtin_bit_cast(h2, zw[m]);
+            z1[m] = h2{z.x, static_cast<_Float16>(-z.y)};
+            z2[m] = h2{z.y, z.x};
+        }
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const uint32_t w[4] = {f.b[j].x, f.b[j].y, f.b[j].z, f.b[j].w};
+            uint32_t p[4];
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const h2 e = __builtin_bit_cast(h2, w[m]);
+                p[m] = __builtin_bit_cast(uint32_t, h2{e.x, e.x} * z1[m] + h2{e.y, e.y} * z2[m]);
+            }
+            fp[j] = make_uint4(p[0], p[1], p[2], p[3]);
+        }
+    };
+    auto compute_pipe = [&](const char* buf) {
+        if constexpr (PIPE) {
+        Frag f[2];
+        uint4 fp[2][2][TN];
+        read(buf, 0, f[0]);
+        prod(f[0], 0, fp[0][0]);
+        prod(f[0], 1, fp[0][1]);
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int ks = 0; ks < kJC / 8; ++ks) {
+            const int c = ks & 1, n = c ^ 1;
+            if (ks + 1 < kJC / 8) read(buf, ks + 1, f[n]);
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[0][i][j] = mfma<false>(f[c].a[i], fp[c][0][j], acc[0][i][j]);
+            if (ks + 1 < kJC / 8) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);  // DS read
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+            if (ks + 1 < kJC / 8) {
+                prod(f[n], 0, fp[n][0]);
+                prod(f[n], 1, fp[n][1]);
+            }
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[1][i][j] = mfma<false>(f[c].a[i], fp[c][1][j], acc[1][i][j]);
+            if (ks + 1 < kJC / 8) {
+#pragma unroll
+                for (int r = 0; r < 8; ++r) {
+                    __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);  // MFMA
+                    __builtin_amdgcn_sched_group_barrier(0x002, 5, 0);  // VALU
+                }
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+        }
+    };
+    auto compute = [&](const char* buf) {
+        if constexpr (PIPE) {
+            compute_pipe(buf);
+        } else {
+#pragma unroll
+            for (int ks = 0; ks < kJC / 8; ++ks) {
+                Frag f;
+                read(buf, ks, f);
+                mac(f);
+            }
+        }
+    };
+
+    // Two stages per iteration (ldp is a multiple of 64, so the stage count is even): the
+    // loads of the next stage are in flight while the current buffer feeds the MFMAs.
+    char* b0 = reinterpret_cast<char*>(lds0);
+    char* b1 = reinterpret_cast<char*>(lds1);
+    const int64_t nstage = ldp / kJC;
+    issue(0, b0);
+    for (int64_t s = 0; s < nstage; s += 2) {
+        wait_loads();
+        __syncthreads();  // stage s is in b0 for every wave; every wave is done with b1
+        issue((s + 1) * kJC, b1);
+        __builtin_amdgcn_sched_barrier(0);  // keep the prefetch ahead of the MFMAs it overlaps
+        compute(b0);
+        wait_loads();
+        __syncthreads();  // stage s + 1 is in b1; every wave is done with b0
+        if (s + 2 < nstage) issue((s + 2) * kJC, b0);
+        __builtin_amdgcn_sched_barrier(0);
+        compute(b1);
+    }
+
+    // ---- epilogue: D[row][col], lane holds rows 8(e/4) + 4(l/32) + e%4, col l%32
+#pragma unroll
+    for (int zs = 0; zs < ZS; ++zs) {
+        if (z0 + zs >= a.nz) break;
+        const int64_t plane = (z0 + zs) * a.ny * a.nx;
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int j = 0; j < TN; ++j) {
+                const int64_t x = x0 + (wn * TN + j) * 32 + (l & 31);
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int64_t y = y0 + (wm * TM + i) * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                    if (x < a.nx && y < a.ny) {
+                        const int64_t c = plane + y * a.nx + x;
+                        const float yv = a.amp * acc[zs][i][j][e];
+                        if (a.y) a.y[c] = yv;
+                        if (a.k) a.k[c] = expf(a.epi.mu + yv);
+                        if (a.ind) {
+                            int f = 0;
+                            for (int q = 0; q < a.epi.nthr; ++q) f += (yv > a.epi.thr[q]) ? 1 : 0;
+                            a.ind[c] = static_cast<uint8_t>(f);
+                        }
+                    }
+                }
+            }
+    }
+}
+
+// Tile body for one block: direct-to-LDS staging where the form allows it, else registers.
+// ZS applies to the direct 3-D form only; the other forms cover one slice per block.
+template <int WM, int WN, int TM, int TN, int ZS, bool BF, bool X3, bool D3>
+constexpr int slices_per_block()
+{
+    return (use_dl<WM, WN, TM, TN, ZS, BF, X3, D3>() && D3) ? ZS : 1;
+}
+
+template <int WM, int WN, int TM, int TN, int ZS, bool BF, bool X3, bool D3>
 __global__ __launch_bounds__(WM* WN * 64) void k_sep(SepArgs a, int tiles_x, int tiles_y)
 {
-    __shared__ uint4 smem[SepShape<WM, WN, TM, TN, X3>::LDS_WORDS / 4];
     const int64_t bid = blockIdx.x;
     const int64_t rest = bid / tiles_x;
-    sep_tile<WM, WN, TM, TN, BF, X3, D3>(a, bid % tiles_x, rest % tiles_y, rest / tiles_y, smem);
+    if constexpr (use_dl<WM, WN, TM, TN, ZS, BF, X3, D3>()) {
+        constexpr int Q = DlShape<WM, WN, TM, TN, X3, D3 ? ZS : 0>::STAGE_B / 16;
+        __shared__ uint4 lds0[Q];
+        __shared__ uint4 lds1[Q];
+        sep_tile_dl<WM, WN, TM, TN, slices_per_block<WM, WN, TM, TN, ZS, BF, X3, D3>(), BF, X3, D3>(
+            a, bid % tiles_x, rest % tiles_y, rest / tiles_y, lds0, lds1);
+    } else {
+        __shared__ uint4 smem[SepShape<WM, WN, TM, TN, X3>::LDS_WORDS / 4];
+        sep_tile_reg<WM, WN, TM, TN, BF, X3, D3>(a, bid % tiles_x, rest % tiles_y, rest / tiles_y, smem);
+    }
 }
 
 // Persistent batched form: blocks pull (instance, tile, slice) work items from one atomic
@@ -332,9 +690,14 @@ template <bool BF, bool X3, bool D3>
 __global__ __launch_bounds__(256) void k_sep_batch(const SepBatchItem* __restrict__ items, int n_inst, int64_t total,
                                                    unsigned long long* counter)
 {
+    constexpr bool DL = use_dl<2, 2, 2, 2, 1, BF, X3, D3>();
+    static_assert(DL == use_dl<2, 2, 1, 1, 1, BF, X3, D3>(), "both batch tiles stage the same way");
+    constexpr int QD = DlShape<2, 2, 2, 2, X3, D3 ? 1 : 0>::STAGE_B / 16;
     constexpr int W0 = X3 ? BigT3::LDS_WORDS : BigT::LDS_WORDS;
     constexpr int W1 = X3 ? SmallT3::LDS_WORDS : SmallT::LDS_WORDS;
-    __shared__ uint4 smem[(W0 > W1 ? W0 : W1) / 4];
+    constexpr int Q0 = DL ? QD : (W0 > W1 ? W0 : W1) / 4;
+    __shared__ uint4 lds0[Q0];
+    __shared__ uint4 lds1[DL ? QD : 1];
     __shared__ unsigned long long s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1ull);
@@ -351,10 +714,19 @@ __global__ __launch_bounds__(256) void k_sep_batch(const SepBatchItem* __restric
         const SepBatchItem& b = items[lo];
         const int64_t local = it - b.item0;
         const int64_t rest = local / b.tiles_x;
-        if (b.variant == 0)
-            sep_tile<2, 2, 2, 2, BF, X3, D3>(b.a, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, smem);
-        else
-            sep_tile<2, 2, 1, 1, BF, X3, D3>(b.a, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, smem);
+        if constexpr (DL) {
+            if (b.variant == 0)
+                sep_tile_dl<2, 2, 2, 2, 1, BF, X3, D3>(b.a, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0,
+                                                       lds1);
+            else
+                sep_tile_dl<2, 2, 1, 1, 1, BF, X3, D3>(b.a, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0,
+                                                       lds1);
+        } else {
+            if (b.variant == 0)
+                sep_tile_reg<2, 2, 2, 2, BF, X3, D3>(b.a, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0);
+            else
+                sep_tile_reg<2, 2, 1, 1, BF, X3, D3>(b.a, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0);
+        }
     }
 }
 
@@ -377,37 +749,57 @@ int batch_occupancy_t()
 struct TileCfg {
     int bm, bn;
 };
-// tile selectors: 0 = 256x256 (8 waves), 1 = 128x128 (4 waves), 2 = 64x64 (4 waves), 3 = 128x256 (8 waves),
-// 4 = 256x256 (4 waves of 128x128)
-constexpr TileCfg kTiles[] = {{256, 256}, {128, 128}, {64, 64}, {128, 256}, {256, 256}};
+// tile selectors (rows y x cols x per block): 0 = 256x256 (8 waves), 1 = 128x128 (4 waves),
+// 2 = 64x64 (4 waves), 3 = 128x256 (8 waves); covering two z-slices per block in the one-pass
+// fp16 3-D form (one slice in the other forms): 4 = 128x256 (8 waves), 5 = 128x128 (4 waves),
+// 6 = 128x256 (8 waves of 128x32), 7 = 256x128 (8 waves of 128x32), 8 = 256x128 (4 waves of
+// 128x64); 9 = 256x256 (4 waves of 128x128, one slice).  sep_tile_slices gives the slices.
+constexpr TileCfg kTiles[] = {{256, 256}, {128, 128}, {64, 64},  {128, 256}, {128, 256},
+                              {128, 128}, {128, 256}, {256, 128}, {256, 128}, {256, 256}};
+
+template <int WM, int WN, int TM, int TN, int ZS, bool BF, bool X3, bool D3>
+hipError_t launch_k(const SepArgs& a, hipStream_t s)
+{
+    constexpr int BM = WM * TM * 32, BN = WN * TN * 32;
+    constexpr int zs = slices_per_block<WM, WN, TM, TN, ZS, BF, X3, D3>();
+    const int tiles_x = static_cast<int>((a.nx + BN - 1) / BN);
+    const int tiles_y = static_cast<int>((a.ny + BM - 1) / BM);
+    const int64_t blocks = static_cast<int64_t>(tiles_x) * tiles_y * ((a.nz + zs - 1) / zs);
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_sep<WM, WN, TM, TN, ZS, BF, X3, D3>), dim3(static_cast<unsigned>(blocks)), dim3(WM * WN * 64),
+                       0, s, a, tiles_x, tiles_y);
+    return hipGetLastError();
+}
 
 template <bool BF, bool X3, bool D3>
 hipError_t launch_t(const SepArgs& a, int tile, hipStream_t s)
 {
-    const int bm = kTiles[tile].bm, bn = kTiles[tile].bn;
-    const int tiles_x = static_cast<int>((a.nx + bn - 1) / bn);
-    const int tiles_y = static_cast<int>((a.ny + bm - 1) / bm);
-    const int64_t blocks = static_cast<int64_t>(tiles_x) * tiles_y * a.nz;
-    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    const dim3 g(static_cast<unsigned>(blocks));
     switch (tile) {
-    case 0:
-        hipLaunchKernelGGL((k_sep<2, 4, 4, 2, BF, X3, D3>), g, dim3(512), 0, s, a, tiles_x, tiles_y);
-        break;
-    case 1:
-        hipLaunchKernelGGL((k_sep<2, 2, 2, 2, BF, X3, D3>), g, dim3(256), 0, s, a, tiles_x, tiles_y);
-        break;
-    case 2:
-        hipLaunchKernelGGL((k_sep<2, 2, 1, 1, BF, X3, D3>), g, dim3(256), 0, s, a, tiles_x, tiles_y);
-        break;
-    case 3:
-        hipLaunchKernelGGL((k_sep<2, 4, 2, 2, BF, X3, D3>), g, dim3(512), 0, s, a, tiles_x, tiles_y);
-        break;
-    default:
-        hipLaunchKernelGGL((k_sep<2, 2, 4, 4, BF, X3, D3>), g, dim3(256), 0, s, a, tiles_x, tiles_y);
-        break;
+    case 0: return launch_k<2, 4, 4, 2, 1, BF, X3, D3>(a, s);
+    case 1: return launch_k<2, 2, 2, 2, 1, BF, X3, D3>(a, s);
+    case 2: return launch_k<2, 2, 1, 1, 1, BF, X3, D3>(a, s);
+    case 3: return launch_k<2, 4, 2, 2, 1, BF, X3, D3>(a, s);
+    case 4: return D3 ? launch_k<2, 4, 2, 2, 2, BF, X3, D3>(a, s) : launch_k<2, 4, 2, 2, 1, BF, X3, D3>(a, s);
+    case 5: return D3 ? launch_k<2, 2, 2, 2, 2, BF, X3, D3>(a, s) : launch_k<2, 2, 2, 2, 1, BF, X3, D3>(a, s);
+    case 6: return launch_k<1, 8, 4, 1, 2, BF, X3, D3>(a, s);
+    case 7: return launch_k<2, 4, 4, 1, 2, BF, X3, D3>(a, s);
+    case 8: return launch_k<2, 2, 4, 2, 2, BF, X3, D3>(a, s);
+    default: return launch_k<2, 2, 4, 4, 1, BF, X3, D3>(a, s);
     }
-    return hipGetLastError();
+}
+
+// z-slices one block of tile selector `tile` covers (mirrors launch_t).
+template <bool BF, bool X3, bool D3>
+int slices_t(int tile)
+{
+    switch (tile) {
+    case 4: return D3 ? slices_per_block<2, 4, 2, 2, 2, BF, X3, D3>() : 1;
+    case 5: return D3 ? slices_per_block<2, 2, 2, 2, 2, BF, X3, D3>() : 1;
+    case 6: return slices_per_block<1, 8, 4, 1, 2, BF, X3, D3>();
+    case 7: return slices_per_block<2, 4, 4, 1, 2, BF, X3, D3>();
+    case 8: return slices_per_block<2, 2, 4, 2, 2, BF, X3, D3>();
+    default: return 1;
+    }
 }
 
 template <bool BF, bool X3>
@@ -426,13 +818,28 @@ void sep_tile_shape(int tile, int* bm, int* bn)
     *bn = kTiles[tile].bn;
 }
 
+int sep_tile_slices(int tile, int method, bool d3)
+{
+    switch (method) {
+    case GRF_SEP_BF16: return d3 ? slices_t<true, false, true>(tile) : slices_t<true, false, false>(tile);
+    case GRF_SEP_F16: return d3 ? slices_t<false, false, true>(tile) : slices_t<false, false, false>(tile);
+    case GRF_SEP_BF16_X3: return d3 ? slices_t<true, true, true>(tile) : slices_t<true, true, false>(tile);
+    default: return d3 ? slices_t<false, true, true>(tile) : slices_t<false, true, false>(tile);
+    }
+}
+
 int sep_default_tile(int method, int64_t nx, int64_t ny, int64_t nz)
 {
     // Large slices: 256x256 (operand reuse), or 128x256 for the hi+lo forms whose doubled
     // LDS stages do not fit twice at 256x256; small or thin grids: smaller tiles keep the
     // device busy and waste less on ragged edges.
     const int64_t t256 = ((nx + 255) / 256) * ((ny + 255) / 256) * nz;
-    if (nx >= 192 && ny >= 192 && t256 >= 128) return (method == GRF_SEP_F16_X3 || method == GRF_SEP_BF16_X3) ? 3 : 0;
+    if (nx >= 192 && ny >= 192 && t256 >= 128) {
+        if (method == GRF_SEP_F16_X3 || method == GRF_SEP_BF16_X3) return 3;
+        // one-pass fp16 over several slices: 256x128 blocks covering two z-slices
+        if (method == GRF_SEP_F16 && nz >= 2) return 7;
+        return 0;
+    }
     const int64_t t128 = ((nx + 127) / 128) * ((ny + 127) / 128) * nz;
     if (nx >= 96 && ny >= 96 && t128 >= 64) return 1;
     return 2;
@@ -472,6 +879,7 @@ hipError_t launch_sep(const SepArgs& a, hipStream_t s)
 {
     int tile = a.tile < 0 ? sep_default_tile(a.method, a.nx, a.ny, a.nz) : a.tile;
     if (tile >= sep_tile_count()) return hipErrorInvalidValue;
+    if (a.ldp <= 0 || a.ldp % (2 * kJC) != 0) return hipErrorInvalidValue;  // whole pairs of stages
     switch (a.method) {
     case GRF_SEP_BF16: return launch_d<true, false>(a, tile, s);
     case GRF_SEP_F16: return launch_d<false, false>(a, tile, s);

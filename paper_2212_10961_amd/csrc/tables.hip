@@ -34,89 +34,127 @@ __device__ inline uint32_t pack_bf162(float re, float im)
 __device__ inline float half_to_float(uint16_t b) { return static_cast<float>(__builtin_bit_cast(_Float16, b)); }
 __device__ inline float bf16_to_float(uint16_t b) { return static_cast<float>(__builtin_bit_cast(__bf16, b)); }
 
-// Entry e (= i * ldp + j) of one per-axis table.
-__device__ __forceinline__ void axis_table_entry(const AxisTableArgs& a, int64_t i, int64_t j)
-{
-    // row-major [count][ldp], or stage-major [ldp / 32][count][32]
-    const int64_t e = a.blocked ? ((j >> 5) * a.count + i) * 32 + (j & 31) : i * a.ldp + j;
+// Rows of one table that a work block covers; a work block is (row group, 256-mode chunk),
+// one mode per thread, so the per-mode factors are loaded and scaled once per row group.
+constexpr int kTabRows = 16;
 
-    double f = 0.0;
-    bool zero = j >= a.n;
-    if (!zero) {
+// Rows i0 .. i1-1 of the table for this thread's mode j: f = frac(a_j x_i (+ psi_j)) formed
+// and reduced in FP64, then stored in format FMT.  `a` is a register copy of the descriptor,
+// so no field is re-read from memory between the stores.
+template <int FMT, bool FAST, bool BLOCKED>
+__device__ __forceinline__ void axis_table_rows(const AxisTableArgs a, int64_t i0, int64_t i1, int64_t j, double az,
+                                                double ps, bool zero)
+{
+    const double sgn = a.conj ? -1.0 : 1.0;
+    for (int64_t i = i0; i < i1; ++i) {
+        // row-major [count][ldp], or stage-major [ldp / 32][count][32]
+        const int64_t e = BLOCKED ? ((j >> 5) * a.count + i) * 32 + (j & 31) : i * a.ldp + j;
         const double x = a.origin + (static_cast<double>(i) + 0.5) * a.h;
-        double t = 0.0;
-        if (a.z) t = (a.z[static_cast<int64_t>(a.axis) * a.n + j] * a.freq_scale) * x;
-        if (a.with_psi) t += a.phi[j] * kInvTwoPi;
-        f = t - floor(t);  // exact in FP64
-    }
+        const double t = az * x + ps;  // ps = 0 (exact) for tables without the phase
+        const double f = zero ? 0.0 : t - floor(t);  // exact in FP64
 
-    switch (a.format) {
-    case TF_REV_F32:
-        static_cast<float*>(a.out)[e] = static_cast<float>(f);
-        break;
-    case TF_REV_F64:
-        static_cast<double*>(a.out)[e] = f;
-        break;
-    default: {
-        double sn, cs;
-        if (a.fast_trig) {
-            const float fr = static_cast<float>(f);  // revolutions in [0, 1)
-            cs = static_cast<double>(__builtin_amdgcn_cosf(fr));
-            sn = static_cast<double>(__builtin_amdgcn_sinf(fr));
+        if constexpr (FMT == TF_REV_F32) {
+            static_cast<float*>(a.out)[e] = static_cast<float>(f);
+        } else if constexpr (FMT == TF_REV_F64) {
+            static_cast<double*>(a.out)[e] = f;
+        } else if constexpr (FAST && (FMT == TF_CPLX_F32 || FMT == TF_F16 || FMT == TF_BF16)) {
+            // one rounding to the table format: the hardware cos/sin of the FP64-reduced
+            // fraction in revolutions (|err| ~1e-7) is far below it
+            const float fr = static_cast<float>(f);
+            const float cs = zero ? 0.f : __builtin_amdgcn_cosf(fr);
+            const float sn = zero ? 0.f : __builtin_amdgcn_sinf(fr) * static_cast<float>(sgn);
+            if constexpr (FMT == TF_CPLX_F32) static_cast<float2*>(a.out)[e] = make_float2(cs, sn);
+            else if constexpr (FMT == TF_F16) static_cast<uint32_t*>(a.out)[e] = pack_half2(cs, sn);
+            else static_cast<uint32_t*>(a.out)[e] = pack_bf162(cs, sn);
         } else {
+            double sn, cs;
             sincospi(2.0 * f, &sn, &cs);
-        }
-        if (zero) { sn = 0.0; cs = 0.0; }
-        if (a.conj) sn = -sn;
-        if (a.format == TF_CPLX_F32) {
-            static_cast<float2*>(a.out)[e] = make_float2(static_cast<float>(cs), static_cast<float>(sn));
-        } else if (a.format == TF_F16 || a.format == TF_F16_HILO) {
-            const uint32_t hi = pack_half2(static_cast<float>(cs), static_cast<float>(sn));
-            static_cast<uint32_t*>(a.out)[e] = hi;
-            if (a.format == TF_F16_HILO) {
-                const double rl = cs - static_cast<double>(half_to_float(static_cast<uint16_t>(hi & 0xffff)));
-                const double il = sn - static_cast<double>(half_to_float(static_cast<uint16_t>(hi >> 16)));
-                static_cast<uint32_t*>(a.out_lo)[e] = pack_half2(static_cast<float>(rl), static_cast<float>(il));
+            if (zero) { sn = 0.0; cs = 0.0; }
+            sn *= sgn;
+            if constexpr (FMT == TF_CPLX_F32) {
+                static_cast<float2*>(a.out)[e] = make_float2(static_cast<float>(cs), static_cast<float>(sn));
+            } else if constexpr (FMT == TF_F16 || FMT == TF_F16_HILO) {
+                const uint32_t hi = pack_half2(static_cast<float>(cs), static_cast<float>(sn));
+                static_cast<uint32_t*>(a.out)[e] = hi;
+                if constexpr (FMT == TF_F16_HILO) {
+                    const double rl = cs - static_cast<double>(half_to_float(static_cast<uint16_t>(hi & 0xffff)));
+                    const double il = sn - static_cast<double>(half_to_float(static_cast<uint16_t>(hi >> 16)));
+                    static_cast<uint32_t*>(a.out_lo)[e] = pack_half2(static_cast<float>(rl), static_cast<float>(il));
+                }
+            } else {
+                const uint32_t hi = pack_bf162(static_cast<float>(cs), static_cast<float>(sn));
+                static_cast<uint32_t*>(a.out)[e] = hi;
+                if constexpr (FMT == TF_BF16_HILO) {
+                    const double rl = cs - static_cast<double>(bf16_to_float(static_cast<uint16_t>(hi & 0xffff)));
+                    const double il = sn - static_cast<double>(bf16_to_float(static_cast<uint16_t>(hi >> 16)));
+                    static_cast<uint32_t*>(a.out_lo)[e] = pack_bf162(static_cast<float>(rl), static_cast<float>(il));
+                }
             }
-        } else {
-            const uint32_t hi = pack_bf162(static_cast<float>(cs), static_cast<float>(sn));
-            static_cast<uint32_t*>(a.out)[e] = hi;
-            if (a.format == TF_BF16_HILO) {
-                const double rl = cs - static_cast<double>(bf16_to_float(static_cast<uint16_t>(hi & 0xffff)));
-                const double il = sn - static_cast<double>(bf16_to_float(static_cast<uint16_t>(hi >> 16)));
-                static_cast<uint32_t*>(a.out_lo)[e] = pack_bf162(static_cast<float>(rl), static_cast<float>(il));
-            }
         }
-    }
     }
 }
 
-// Block b of a table covers row b / jblocks, modes 256 (b % jblocks) + threadIdx.x, with
-// jblocks = ceil(ldp / 256): the row/mode split is a per-block (scalar) division.
-__device__ __forceinline__ void axis_table_block(const AxisTableArgs& a, int64_t b)
+template <int FMT>
+__device__ __forceinline__ void axis_table_rows_t(const AxisTableArgs& a, int64_t i0, int64_t i1, int64_t j,
+                                                  double az, double ps, bool zero)
 {
-    const int64_t jblocks = (a.ldp + 255) / 256;
-    const int64_t i = b / jblocks;
-    const int64_t j = (b - i * jblocks) * 256 + threadIdx.x;
-    if (j < a.ldp) axis_table_entry(a, i, j);
+    if (a.blocked) {
+        if (a.fast_trig) axis_table_rows<FMT, true, true>(a, i0, i1, j, az, ps, zero);
+        else axis_table_rows<FMT, false, true>(a, i0, i1, j, az, ps, zero);
+    } else {
+        if (a.fast_trig) axis_table_rows<FMT, true, false>(a, i0, i1, j, az, ps, zero);
+        else axis_table_rows<FMT, false, false>(a, i0, i1, j, az, ps, zero);
+    }
 }
 
-__global__ __launch_bounds__(256) void k_axis_table(AxisTableArgs a) { axis_table_block(a, blockIdx.x); }
+// Work block w of one table: rows kTabRows (w / jchunks) .., modes 256 (w % jchunks) + tid.
+__device__ __forceinline__ void axis_table_block(const AxisTableArgs a, int64_t w)
+{
+    const int64_t jchunks = (a.ldp + 255) / 256;
+    const int64_t rg = w / jchunks;
+    const int64_t j = (w - rg * jchunks) * 256 + threadIdx.x;
+    if (j >= a.ldp) return;
+    const bool zero = j >= a.n;
+    double az = 0.0, ps = 0.0;
+    if (!zero) {
+        if (a.z) az = a.z[static_cast<int64_t>(a.axis) * a.n + j] * a.freq_scale;
+        if (a.with_psi) ps = a.phi[j] * kInvTwoPi;
+    }
+    const int64_t i0 = rg * kTabRows;
+    const int64_t i1 = min(i0 + kTabRows, a.count);
+    switch (a.format) {
+    case TF_REV_F32: axis_table_rows<TF_REV_F32, true, false>(a, i0, i1, j, az, ps, zero); break;
+    case TF_REV_F64: axis_table_rows<TF_REV_F64, true, false>(a, i0, i1, j, az, ps, zero); break;
+    case TF_CPLX_F32: axis_table_rows_t<TF_CPLX_F32>(a, i0, i1, j, az, ps, zero); break;
+    case TF_F16: axis_table_rows_t<TF_F16>(a, i0, i1, j, az, ps, zero); break;
+    case TF_F16_HILO: axis_table_rows_t<TF_F16_HILO>(a, i0, i1, j, az, ps, zero); break;
+    case TF_BF16: axis_table_rows_t<TF_BF16>(a, i0, i1, j, az, ps, zero); break;
+    default: axis_table_rows_t<TF_BF16_HILO>(a, i0, i1, j, az, ps, zero); break;
+    }
+}
 
-// Many tables in one launch: descriptor d owns blocks [bprefix[d], bprefix[d+1]).  The
-// descriptor lookup depends only on the block index, so it runs once per block on the
-// scalar unit.
-__global__ __launch_bounds__(256) void k_axis_tables_batched(const AxisTableArgs* __restrict__ descs,
-                                                             const int64_t* __restrict__ bprefix, int ndesc)
+// Up to three tables (one grid's axes) in one launch; table t owns work blocks
+// [start[t], start[t + 1]).
+struct TableSet {
+    AxisTableArgs d[3];
+    int64_t start[4];
+};
+
+__global__ __launch_bounds__(256) void k_axis_tables3(TableSet ts)
 {
     const int64_t b = blockIdx.x;
-    int lo = 0, hi = ndesc - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (bprefix[mid] <= b) lo = mid;
-        else hi = mid - 1;
-    }
-    axis_table_block(descs[lo], b - bprefix[lo]);
+    if (b >= ts.start[2]) axis_table_block(ts.d[2], b - ts.start[2]);
+    else if (b >= ts.start[1]) axis_table_block(ts.d[1], b - ts.start[1]);
+    else axis_table_block(ts.d[0], b);
+}
+
+// Many tables in one launch: entry b of `blk` packs (descriptor << 40) | local work block,
+// one load per block instead of a search over the descriptor prefix.
+__global__ __launch_bounds__(256) void k_axis_tables_batched(const AxisTableArgs* __restrict__ descs,
+                                                             const uint64_t* __restrict__ blk)
+{
+    const uint64_t w = blk[blockIdx.x];
+    axis_table_block(descs[w >> 40], static_cast<int64_t>(w & ((uint64_t(1) << 40) - 1)));
 }
 
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v)
@@ -142,24 +180,35 @@ __global__ __launch_bounds__(256) void k_mode_params(const double* z, const doub
 
 }  // namespace
 
-int64_t axis_table_blocks(const AxisTableArgs& a) { return a.count * ((a.ldp + 255) / 256); }
+int64_t axis_table_blocks(const AxisTableArgs& a) { return ((a.count + kTabRows - 1) / kTabRows) * ((a.ldp + 255) / 256); }
 
-hipError_t launch_axis_table(const AxisTableArgs& a, hipStream_t s)
+hipError_t launch_axis_tables(const AxisTableArgs* d, int nd, hipStream_t s)
 {
-    const int64_t blocks = axis_table_blocks(a);
-    if (blocks <= 0) return hipSuccess;
-    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_axis_table, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, a);
+    if (nd < 0 || nd > 3) return hipErrorInvalidValue;
+    TableSet ts{};
+    int64_t b = 0;
+    for (int t = 0; t < 3; ++t) {
+        ts.start[t] = b;
+        if (t < nd) {
+            ts.d[t] = d[t];
+            b += axis_table_blocks(d[t]);
+        }
+    }
+    ts.start[3] = b;
+    if (b <= 0) return hipSuccess;
+    if (b > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_axis_tables3, dim3(static_cast<unsigned>(b)), dim3(256), 0, s, ts);
     return hipGetLastError();
 }
 
-hipError_t launch_axis_tables_batched(const AxisTableArgs* descs, const int64_t* bprefix, int ndesc,
-                                      int64_t total_blocks, hipStream_t s)
+hipError_t launch_axis_table(const AxisTableArgs& a, hipStream_t s) { return launch_axis_tables(&a, 1, s); }
+
+hipError_t launch_axis_tables_batched(const AxisTableArgs* descs, const uint64_t* blk, int64_t total_blocks,
+                                      hipStream_t s)
 {
-    if (total_blocks <= 0 || ndesc <= 0) return hipSuccess;
+    if (total_blocks <= 0) return hipSuccess;
     if (total_blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_axis_tables_batched, dim3(static_cast<unsigned>(total_blocks)), dim3(256), 0, s, descs,
-                       bprefix, ndesc);
+    hipLaunchKernelGGL(k_axis_tables_batched, dim3(static_cast<unsigned>(total_blocks)), dim3(256), 0, s, descs, blk);
     return hipGetLastError();
 }
 

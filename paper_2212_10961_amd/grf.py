@@ -25,7 +25,7 @@ from ._lib import GrfError, check
 
 __all__ = [
     "Modes", "make_modes", "modes_from_tables", "field_grid", "field_grid_f64", "field_points",
-    "epilogue", "field_backward", "field_backward_grid", "GRFPoints", "Plan", "method_id",
+    "epilogue", "field_backward", "field_backward_grid", "GRFPoints", "Plan", "method_id", "sep_tiles",
     "GAUSSIAN", "EXPONENTIAL", "MATERN", "GrfError", "version", "paper_lambda_to_ell",
 ]
 
@@ -147,10 +147,11 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
 
 
 def field_grid(modes: Modes, shape, origin=None, h=None, method="direct_f32", mu=None, thresholds=None,
-               want_y=True, want_k=False, want_ind=False, out=None, workspace=None, stream=None):
+               want_y=True, want_k=False, want_ind=False, out=None, workspace=None, stream=None, tile=None):
     """Y, K = exp(mu + Y) and/or the facies index on a structured grid (x fastest).
 
     Returns a dict of flat device tensors.  ``out`` may hold preallocated 'y'/'k'/'ind'.
+    ``tile`` selects a separable tile shape (None: the size-based default).
     """
     lib = L.load()
     dev = modes.z.device
@@ -168,9 +169,24 @@ def field_grid(modes: Modes, shape, origin=None, h=None, method="direct_f32", mu
     if want_ind and "ind" not in out:
         out["ind"] = torch.empty(cells, dtype=torch.uint8, device=dev)
     e = _epi(mu, thresholds)
-    check(lib.eval_field_grid(ctypes.byref(m), ctypes.byref(g), meth, ctypes.byref(e), _ptr(out.get("y")),
-                              _ptr(out.get("k")), _ptr(out.get("ind")), ctypes.c_void_p(ws.data_ptr()),
-                              ws.numel(), _stream(stream)))
+    ptrs = (_ptr(out.get("y")), _ptr(out.get("k")), _ptr(out.get("ind")), ctypes.c_void_p(ws.data_ptr()),
+            ws.numel(), _stream(stream))
+    if tile is None:
+        check(lib.eval_field_grid(ctypes.byref(m), ctypes.byref(g), meth, ctypes.byref(e), *ptrs))
+    else:
+        check(lib.eval_field_grid_tile(ctypes.byref(m), ctypes.byref(g), meth, int(tile), ctypes.byref(e), *ptrs))
+    return out
+
+
+def sep_tiles(method, dim):
+    """[(rows, cols, slices)] of every separable tile selector for a method and dim."""
+    lib = L.load()
+    out = []
+    for t in range(lib.grf_sep_tile_count()):
+        r, c, z = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        check(lib.grf_sep_tile_shape(t, method_id(method), int(dim), ctypes.byref(r), ctypes.byref(c),
+                                     ctypes.byref(z)))
+        out.append((r.value, c.value, z.value))
     return out
 
 

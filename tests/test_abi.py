@@ -151,6 +151,34 @@ def test_grid_output_and_workspace_checks(lib):
                                ctypes.c_void_p(16), ctypes.c_void_p(16), need.value, None) == L.GRF_EINVAL
 
 
+def test_tile_selector_validation(lib):
+    m, g = _modes(), _grid()
+    need = ctypes.c_size_t()
+    assert lib.eval_field_grid_ws_size(ctypes.byref(m), ctypes.byref(g), L.GRF_SEP_F16_X3, ctypes.byref(need)) == 0
+    nt = lib.grf_sep_tile_count()
+    assert nt >= 1
+    args = (None, ctypes.c_void_p(16), None, None, ctypes.c_void_p(16), need.value, None)
+    for bad_tile in (-2, nt, nt + 5):
+        assert lib.eval_field_grid_tile(ctypes.byref(m), ctypes.byref(g), L.GRF_SEP_F16_X3, bad_tile,
+                                        *args) == L.GRF_EINVAL
+    # tile selectors are for the separable methods only
+    assert lib.eval_field_grid_tile(ctypes.byref(m), ctypes.byref(g), L.GRF_DIRECT_F32, 0, *args) == L.GRF_EINVAL
+    r, c, z = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    refs = (ctypes.byref(r), ctypes.byref(c), ctypes.byref(z))
+    assert lib.grf_sep_tile_shape(nt, L.GRF_SEP_F16, 3, *refs) == L.GRF_EINVAL
+    assert lib.grf_sep_tile_shape(0, L.GRF_DIRECT_F32, 3, *refs) == L.GRF_EINVAL
+    assert lib.grf_sep_tile_shape(0, L.GRF_SEP_F16, 4, *refs) == L.GRF_EINVAL
+    assert lib.grf_sep_tile_shape(0, L.GRF_SEP_F16, 3, None, None, None) == L.GRF_EINVAL
+    for meth in (L.GRF_SEP_BF16, L.GRF_SEP_F16, L.GRF_SEP_BF16_X3, L.GRF_SEP_F16_X3):
+        for dim in (2, 3):
+            for t in range(nt):
+                assert lib.grf_sep_tile_shape(t, meth, dim, *refs) == 0
+                assert r.value in (64, 128, 256) and c.value in (64, 128, 256)
+                assert z.value in (1, 2)
+                if dim == 2:
+                    assert z.value == 1
+
+
 def test_workspace_sizes_scale(lib):
     m = _modes(n=4096)
     need = {}

@@ -82,6 +82,25 @@ def test_grid2d_ragged(orc, grf, meth):
     assert_field(y, ref, sigma, meth, "grid2d_ragged")
 
 
+@pytest.mark.parametrize("meth", ["sep_f16", "sep_bf16", "sep_f16_x3", "sep_bf16_x3"])
+def test_every_sep_tile(orc, grf, meth):
+    # Every tile selector on grids spanning several blocks of the largest tiles with ragged
+    # edges in x and y and an odd slice count (tiles covering two z-slices mask the last).
+    cases = [((300, 270, 5), (7.0, 5.0, 2.0), 3), ((530, 290), (11.0, 6.0), 2)]
+    for shape, ell, dim in cases:
+        (zo, po), m = modes_pair(orc, grf, dim, wl.EXPONENTIAL, 150, 81 + dim, 1.3, ell)
+        origin, h = (1.5, -2.0, 0.5)[:dim], (0.75, 1.25, 2.0)[:dim]
+        ref = orc.field_grid(zo, po, 1.3, ell, shape, origin=origin, h=h)
+        for t, (rows, cols, zs) in enumerate(grf.sep_tiles(meth, dim)):
+            _say(f"case every_sep_tile {shape} {meth} tile {t} ({rows}x{cols}x{zs})")
+            out = grf.field_grid(m, shape, origin=origin, h=h, method=meth, mu=0.1, thresholds=[0.2],
+                                 want_k=True, want_ind=True, tile=t)
+            assert_field(to_np(out["y"]), ref, 1.3, meth, f"tile{t}")
+            kref = orc.lognormal(ref, 0.1)
+            assert np.max(np.abs(to_np(out["k"]) - kref) / kref) <= 1.01 * TOL[meth]["band"] * 1.3 + 1e-6
+            assert_indicator(to_np(out["ind"]), ref, [0.2], 1.3, meth)
+
+
 @pytest.mark.parametrize("shape", [(1, 1, 1), (1, 7, 3), (33, 1, 1), (64, 64, 1), (300, 2, 2)])
 @pytest.mark.parametrize("meth", ["direct_f32", "sep_f16_x3"])
 def test_grid_degenerate_shapes(orc, grf, shape, meth):
