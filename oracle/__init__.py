@@ -19,7 +19,12 @@ the passage of Icardi et al. (2022) that it follows:
   exponentials (algebraic identity behind the matrix-core form);
 - ``lognormal`` / ``facies``: the scaling and truncation steps of Sec. 4.1 and the
   single-truncation rule of Sec. 3.1;
-- ``grad_points``: exact derivatives of a loss through ``Y`` (chain rule).
+- ``grad_points``: exact derivatives of a loss through ``Y`` (chain rule);
+- ``pluri`` / ``pluri_proportions``: the bitruncated (pluri-Gaussian) truncation rule of
+  Sec. 3.1 and its facies proportions for independent fields (the product formula there);
+- ``field_points_mat`` / ``grad_points_rot``: general anisotropy (rotations) of frequency
+  space, named as the extension of the per-axis rescaling in Sec. 4.1;
+- ``snap_periodic``: the "periodic" option of App. B as wavevectors on the box's lattice.
 
 Parity pins for this module are the ``-m "not gpu"`` tests in
 ``tests/test_oracle_pins.py``; none of them re-types the formulas above.
@@ -75,6 +80,14 @@ def _load():
         lib.orc_facies.argtypes = [i64, d, ctypes.c_int, d, ctypes.POINTER(ctypes.c_uint8)]
         lib.orc_grad_points.argtypes = [ctypes.c_int, i64, d, d, ctypes.c_double, d, i64, d, d,
                                         d, d, d, d]
+        u8 = ctypes.POINTER(ctypes.c_uint8)
+        lib.orc_pluri.argtypes = [i64, d, d, ctypes.c_int, d, ctypes.c_int, d, u8, d, u8, d]
+        lib.orc_pluri_proportions.argtypes = [ctypes.c_int, d, ctypes.c_double, ctypes.c_int, d,
+                                              ctypes.c_double, u8, ctypes.c_int, d]
+        lib.orc_field_points_mat.argtypes = [ctypes.c_int, i64, d, d, ctypes.c_double, d, i64, d, d]
+        lib.orc_snap_periodic.argtypes = [ctypes.c_int, i64, d, d, d, d, d]
+        lib.orc_grad_points_rot.argtypes = [ctypes.c_int, i64, d, d, ctypes.c_double, d, d, i64, d, d,
+                                            d, d, d, d]
         _lib = lib
     return _lib
 
@@ -236,6 +249,110 @@ def grad_points(z, phi, sigma, ell, x, g):
     dell = np.empty(3)
     lib.orc_grad_points(dim, n, _dp(z), _dp(phi), float(sigma), _dp(_ell(ell, dim)), x.shape[0],
                         _dp(x), _dp(g), _dp(dphi), _dp(dk), _dp(dsig), _dp(dell))
+    return {"dphi": dphi, "dk": dk, "dsigma": float(dsig[0]), "dell": dell[:dim].copy()}
+
+
+def _u8p(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint8))
+
+
+def _rule(rule, nt, ns):
+    r = np.ascontiguousarray(rule, dtype=np.uint8).reshape(-1)
+    if r.size != (nt + 1) * (ns + 1):
+        raise ValueError("rule must have (len(t) + 1) * (len(s) + 1) entries")
+    return r
+
+
+def pluri(y1, y2, t, s, rule, values=None):
+    """Bitruncated (pluri-Gaussian) rule of Sec. 3.1: facies rule[i * (len(s)+1) + j] with
+    i = #{t < Y1}, j = #{s < Y2}; returns (facies uint8, values[facies] or None)."""
+    lib = _load()
+    y1 = _f64(y1)
+    y2 = _f64(y2)
+    t = _f64(np.atleast_1d(t)) if len(np.atleast_1d(t)) else np.zeros(0)
+    s = _f64(np.atleast_1d(s)) if len(np.atleast_1d(s)) else np.zeros(0)
+    r = _rule(rule, t.size, s.size)
+    out = np.empty(y1.size, dtype=np.uint8)
+    if values is not None:
+        vals = _f64(values)
+        val = np.empty(y1.size)
+        lib.orc_pluri(y1.size, _dp(y1), _dp(y2), t.size, _dp(t), s.size, _dp(s), _u8p(r), _dp(vals), _u8p(out),
+                      _dp(val))
+        return out, val
+    lib.orc_pluri(y1.size, _dp(y1), _dp(y2), t.size, _dp(t), s.size, _dp(s), _u8p(r), None, _u8p(out), None)
+    return out, None
+
+
+def pluri_proportions(t, v1, s, v2, rule, nfac):
+    """Facies proportions of the bitruncated rule for independent N(0, v1), N(0, v2) fields
+    (product formula of Sec. 3.1)."""
+    lib = _load()
+    t = _f64(np.atleast_1d(t)) if len(np.atleast_1d(t)) else np.zeros(0)
+    s = _f64(np.atleast_1d(s)) if len(np.atleast_1d(s)) else np.zeros(0)
+    r = _rule(rule, t.size, s.size)
+    p = np.empty(nfac)
+    lib.orc_pluri_proportions(t.size, _dp(t), float(v1), s.size, _dp(s), float(v2), _u8p(r), nfac, _dp(p))
+    return p
+
+
+def rotation_matrix(dim, angles):
+    """Orthonormal R: a rotation by angles[0] about z (2-D: the plane rotation); in 3-D then
+    by angles[1] about y and angles[2] about x (R = Rx Ry Rz)."""
+    a = list(angles) + [0.0] * 3
+    c0, s0 = np.cos(a[0]), np.sin(a[0])
+    rz = np.array([[c0, -s0, 0.0], [s0, c0, 0.0], [0.0, 0.0, 1.0]])
+    if dim == 2:
+        return rz[:2, :2].copy()
+    c1, s1 = np.cos(a[1]), np.sin(a[1])
+    c2, s2 = np.cos(a[2]), np.sin(a[2])
+    ry = np.array([[c1, 0.0, s1], [0.0, 1.0, 0.0], [-s1, 0.0, c1]])
+    rx = np.array([[1.0, 0.0, 0.0], [0.0, c2, -s2], [0.0, s2, c2]])
+    return rx @ ry @ rz
+
+
+def field_points_mat(z, phi, sigma, M, x):
+    """Y at points with wavevectors k_j = M z_j (general anisotropy, Sec. 4.1)."""
+    lib = _load()
+    z = _f64(z)
+    phi = _f64(phi)
+    dim, n = z.shape
+    M = _f64(M).reshape(dim, dim)
+    x = _f64(x).reshape(-1, dim)
+    y = np.empty(x.shape[0])
+    lib.orc_field_points_mat(dim, n, _dp(z), _dp(phi), float(sigma), _dp(M), x.shape[0], _dp(x), _dp(y))
+    return y
+
+
+def snap_periodic(z, ell, period, rot=None):
+    """Standardised table whose wavevectors R diag(1/ell) z lie on the lattice 2 pi m / L
+    along every axis with L > 0 (App. B "periodic")."""
+    lib = _load()
+    z = _f64(z)
+    dim, n = z.shape
+    e = _ell(ell, dim)
+    per = np.zeros(3)
+    per[:dim] = np.asarray(period, dtype=np.float64)[:dim]
+    out = np.empty_like(z)
+    r = None if rot is None else _f64(rot).reshape(dim, dim)
+    lib.orc_snap_periodic(dim, n, _dp(z), _dp(e), None if r is None else _dp(r), _dp(per), _dp(out))
+    return out
+
+
+def grad_points_rot(z, phi, sigma, ell, rot, x, g):
+    """Exact gradients through the rotated field k = R diag(1/ell) z (dell with R fixed)."""
+    lib = _load()
+    z = _f64(z)
+    phi = _f64(phi)
+    dim, n = z.shape
+    r = _f64(rot).reshape(dim, dim)
+    x = _f64(x).reshape(-1, dim)
+    g = _f64(g)
+    dphi = np.empty(n)
+    dk = np.empty((dim, n))
+    dsig = np.empty(1)
+    dell = np.empty(3)
+    lib.orc_grad_points_rot(dim, n, _dp(z), _dp(phi), float(sigma), _dp(_ell(ell, dim)), _dp(r), x.shape[0],
+                            _dp(x), _dp(g), _dp(dphi), _dp(dk), _dp(dsig), _dp(dell))
     return {"dphi": dphi, "dk": dk, "dsigma": float(dsig[0]), "dell": dell[:dim].copy()}
 
 

@@ -324,3 +324,164 @@ void orc_grad_points(int dim, int64_t n, const double* z, const double* phi, dou
         dell[a] = acc;
     }
 }
+
+/* ------------------------------------------------------------------ pluri-Gaussian (bitruncated) */
+
+/*
+ * Bitruncated rule (Sec. 3.1, truncation-rule figure): two independent fields Y1, Y2
+ * are thresholded separately; cell c lies in bin (i, j) with i = #{a : t_a < Y1_c} and
+ * j = #{b : s_b < Y2_c} (strict inequalities, so Y == t falls in the lower bin), and the
+ * rule maps the (nt + 1) x (ns + 1) bins to facies: facies_c = rule[i * (ns + 1) + j].
+ * With ns = 0 this is the single truncation of orc_facies composed with rule[i].
+ * When values != NULL, val_c = values[facies_c] (the "values" option of App. B).
+ */
+void orc_pluri(int64_t C, const double* y1, const double* y2, int nt, const double* t, int ns,
+               const double* s, const uint8_t* rule, const double* values, uint8_t* out, double* val)
+{
+    for (int64_t c = 0; c < C; ++c) {
+        int i = 0, j = 0;
+        for (int a = 0; a < nt; ++a)
+            if (y1[c] > t[a]) ++i;
+        for (int b = 0; b < ns; ++b)
+            if (y2[c] > s[b]) ++j;
+        const uint8_t f = rule[i * (ns + 1) + j];
+        out[c] = f;
+        if (values && val) val[c] = values[f];
+    }
+}
+
+/* Normal CDF of N(0, v) at x; +-infinity are handled by erfc. */
+static double orc_normal_cdf(double x, double v) { return 0.5 * erfc(-x / sqrt(2.0 * v)); }
+
+/*
+ * Proportion of each facies when Y1 ~ N(0, v1) and Y2 ~ N(0, v2) are independent
+ * (Sec. 3.1): bin (i, j) has probability [G1(t_i) - G1(t_{i-1})] [G2(s_j) - G2(s_{j-1})]
+ * with t_{-1} = -inf and t_nt = +inf (likewise s); bins of the same facies add up.
+ * p[0 .. nfac-1] is overwritten; rule entries must be < nfac.
+ */
+void orc_pluri_proportions(int nt, const double* t, double v1, int ns, const double* s, double v2,
+                           const uint8_t* rule, int nfac, double* p)
+{
+    for (int f = 0; f < nfac; ++f) p[f] = 0.0;
+    for (int i = 0; i <= nt; ++i) {
+        const double lo1 = i == 0 ? -INFINITY : t[i - 1], hi1 = i == nt ? INFINITY : t[i];
+        const double p1 = orc_normal_cdf(hi1, v1) - orc_normal_cdf(lo1, v1);
+        for (int j = 0; j <= ns; ++j) {
+            const double lo2 = j == 0 ? -INFINITY : s[j - 1], hi2 = j == ns ? INFINITY : s[j];
+            const double p2 = orc_normal_cdf(hi2, v2) - orc_normal_cdf(lo2, v2);
+            p[rule[i * (ns + 1) + j]] += p1 * p2;
+        }
+    }
+}
+
+/* ------------------------------------------------------------------ general anisotropy */
+
+/*
+ * The field with a general linear map of frequency space (Sec. 4.1: the per-axis rescaling
+ * "can be extended by including rotations, or more general transformation matrices"):
+ *   k_j = M z_j  (M is dim x dim, row-major; M = R diag(1/ell) rotates the principal
+ *   axes of the covariance onto the columns of R),
+ *   Y(x) = sqrt(2 sigma^2/N) sum_j cos(k_j . x + phi_j).
+ * With M = diag(1/ell) this is orc_field_points.
+ */
+void orc_field_points_mat(int dim, int64_t n, const double* z, const double* phi, double sigma,
+                          const double* M, int64_t P, const double* x, double* y)
+{
+    double amp = sigma * sqrt(2.0 / (double)n);
+    double* k = (double*)malloc(sizeof(double) * (size_t)(dim * n));
+    for (int a = 0; a < dim; ++a)
+        for (int64_t j = 0; j < n; ++j) {
+            double v = 0.0;
+            for (int b = 0; b < dim; ++b) v += M[a * dim + b] * z[b * n + j];
+            k[a * n + j] = v;
+        }
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t p = 0; p < P; ++p) {
+        const double* xp = x + p * dim;
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double th = phi[j];
+            for (int a = 0; a < dim; ++a) th += k[a * n + j] * xp[a];
+            s += cos(th);
+        }
+        y[p] = amp * s;
+    }
+    free(k);
+}
+
+/*
+ * Periodic option (App. B "periodic"): each wavevector is moved to the nearest point of
+ * the lattice of a box with periods L_a, k_a = 2 pi m_a / L_a with m_a = round(k_a L_a / 2 pi),
+ * for every axis with L_a > 0 (axes with L_a <= 0 are left alone).  k = R diag(1/ell) z
+ * before snapping (R = identity when rot == NULL, row-major dim x dim, orthonormal), and the
+ * snapped table is returned in the same standardised form: z' = diag(ell) R^T k'.
+ * The field then satisfies Y(x + L_a e_a) = Y(x).
+ */
+void orc_snap_periodic(int dim, int64_t n, const double* z, const double* ell, const double* rot,
+                       const double* period, double* z_out)
+{
+    for (int64_t j = 0; j < n; ++j) {
+        double zs[3], k[3];
+        for (int b = 0; b < dim; ++b) zs[b] = z[b * n + j] / ell[b];
+        for (int a = 0; a < dim; ++a) {
+            double v = 0.0;
+            for (int b = 0; b < dim; ++b) v += (rot ? rot[a * dim + b] : (a == b ? 1.0 : 0.0)) * zs[b];
+            if (period[a] > 0.0) v = 2.0 * ORC_PI * round(v * period[a] / (2.0 * ORC_PI)) / period[a];
+            k[a] = v;
+        }
+        for (int b = 0; b < dim; ++b) {
+            double v = 0.0;
+            for (int a = 0; a < dim; ++a) v += (rot ? rot[a * dim + b] : (a == b ? 1.0 : 0.0)) * k[a];
+            z_out[b * n + j] = v * ell[b];
+        }
+    }
+}
+
+/*
+ * Gradients through the rotated field k_j = R diag(1/ell) z_j (R row-major, orthonormal,
+ * dim x dim), given g[p] = dL/dY_p at points x:
+ *   dL/dphi_j, dL/dk_{a,j}, dL/dsigma as in orc_grad_points (k is the wavevector itself);
+ *   dL/dell_b = sum_j sum_a dL/dk_{a,j} R_ab (-z_{b,j} / ell_b^2)   (z and R fixed).
+ */
+void orc_grad_points_rot(int dim, int64_t n, const double* z, const double* phi, double sigma,
+                         const double* ell, const double* rot, int64_t P, const double* x, const double* g,
+                         double* dphi, double* dk, double* dsigma, double* dell)
+{
+    double M[9];
+    for (int a = 0; a < dim; ++a)
+        for (int b = 0; b < dim; ++b) M[a * dim + b] = rot[a * dim + b] / ell[b];
+    double amp = sigma * sqrt(2.0 / (double)n);
+    double* y = (double*)malloc(sizeof(double) * (size_t)(P > 0 ? P : 1));
+    orc_field_points_mat(dim, n, z, phi, sigma, M, P, x, y);
+    double ds = 0.0;
+    for (int64_t p = 0; p < P; ++p) ds += g[p] * y[p];
+    *dsigma = ds / sigma;
+    free(y);
+
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < n; ++j) {
+        double k[3];
+        for (int a = 0; a < dim; ++a) {
+            k[a] = 0.0;
+            for (int b = 0; b < dim; ++b) k[a] += M[a * dim + b] * z[b * n + j];
+        }
+        double s = 0.0, u[3] = {0.0, 0.0, 0.0};
+        for (int64_t p = 0; p < P; ++p) {
+            const double* xp = x + p * dim;
+            double th = phi[j];
+            for (int a = 0; a < dim; ++a) th += k[a] * xp[a];
+            double sn = sin(th);
+            s += g[p] * sn;
+            for (int a = 0; a < dim; ++a) u[a] += g[p] * xp[a] * sn;
+        }
+        dphi[j] = -amp * s;
+        for (int a = 0; a < dim; ++a) dk[a * n + j] = -amp * u[a];
+    }
+    for (int b = 0; b < dim; ++b) {
+        double acc = 0.0;
+        for (int64_t j = 0; j < n; ++j)
+            for (int a = 0; a < dim; ++a)
+                acc += dk[a * n + j] * rot[a * dim + b] * (-z[b * n + j] / (ell[b] * ell[b]));
+        dell[b] = acc;
+    }
+}

@@ -365,3 +365,185 @@ def test_gradient_fd_error_is_second_order(orc):
         d = (_loss(orc, zz_p, phi, 1.0, ell, x, g) - _loss(orc, zz_m, phi, 1.0, ell, x, g)) / (2 * h)
         errs.append(abs(d - gr["dk"][0, 3]))
     assert 3.0 < errs[0] / errs[1] < 5.0, errs
+
+
+# ------------------------------------------------------------------ pluri-Gaussian (bitruncated)
+
+def _golden_pluri():
+    t = s = None
+    rule, values, cases = [], None, []
+    for line in (GOLDEN / "pluri_rule_example.txt").read_text().splitlines():
+        f = line.split()
+        if not f or f[0].startswith("#"):
+            continue
+        if f[0] == "t":
+            t = [float(v) for v in f[1:]]
+        elif f[0] == "s":
+            s = [float(v) for v in f[1:]]
+        elif f[0] == "rule":
+            rule.append([int(v) for v in f[1:]])
+        elif f[0] == "values":
+            values = [float(v) for v in f[1:]]
+        elif f[0] == "case":
+            cases.append((float(f[1]), float(f[2]), int(f[3])))
+    return t, s, np.array(rule, dtype=np.uint8), np.array(values), cases
+
+
+def test_pluri_rule_worked_example(orc):
+    """Sec. 3.1 truncation-rule example: bins by strict thresholds, merged into four facies."""
+    t, s, rule, values, cases = _golden_pluri()
+    y1 = np.array([c[0] for c in cases])
+    y2 = np.array([c[1] for c in cases])
+    want = np.array([c[2] for c in cases], dtype=np.uint8)
+    fac, val = orc.pluri(y1, y2, t, s, rule, values)
+    np.testing.assert_array_equal(fac, want)
+    np.testing.assert_array_equal(val, values[want])
+
+
+def test_pluri_without_second_thresholds_is_single_truncation(orc):
+    y = np.random.default_rng(3).normal(size=2000) * 1.5
+    t = [-1.0, 0.2, 0.9]
+    fac, _ = orc.pluri(y, np.zeros_like(y), t, [], np.arange(4, dtype=np.uint8))
+    np.testing.assert_array_equal(fac, orc.facies(y, t))
+
+
+def test_pluri_proportions_closed_forms(orc):
+    t, s, rule, _, _ = _golden_pluri()
+    # median thresholds: four equally likely quadrants
+    np.testing.assert_allclose(orc.pluri_proportions([0.0], 1.0, [0.0], 3.0, [0, 1, 2, 3], 4), [0.25] * 4,
+                               rtol=0, atol=1e-15)
+    # the worked rule, against products of scipy's normal CDF
+    v1, v2 = 2.0, 0.5
+    e1 = np.diff(np.concatenate([[0.0], st.norm.cdf(np.array(t) / math.sqrt(v1)), [1.0]]))
+    e2 = np.diff(np.concatenate([[0.0], st.norm.cdf(np.array(s) / math.sqrt(v2)), [1.0]]))
+    want = np.zeros(4)
+    for i in range(4):
+        for j in range(3):
+            want[rule[i, j]] += e1[i] * e2[j]
+    got = orc.pluri_proportions(t, v1, s, v2, rule, 4)
+    np.testing.assert_allclose(got, want, rtol=1e-12, atol=1e-15)
+    assert abs(got.sum() - 1.0) < 1e-14
+
+
+def test_pluri_empirical_proportions(orc):
+    """Two independent fields thresholded by the worked rule reproduce the product formula
+    of Sec. 3.1 over realisations."""
+    t, s, rule, _, _ = _golden_pluri()
+    v1, v2 = 2.0, 0.5
+    shape, R = (96, 96), 24
+    fr = np.empty((R, 4))
+    for r in range(R):
+        z1, p1 = orc.sample_modes(2, wl.GAUSSIAN, 256, 30_000 + r)
+        z2, p2 = orc.sample_modes(2, wl.EXPONENTIAL, 256, 40_000 + r)
+        y1 = orc.field_grid(z1, p1, math.sqrt(v1), (6.0, 6.0), shape)
+        y2 = orc.field_grid(z2, p2, math.sqrt(v2), (4.0, 9.0), shape)
+        fac, _ = orc.pluri(y1, y2, t, s, rule)
+        fr[r] = np.bincount(fac, minlength=4) / fac.size
+    want = orc.pluri_proportions(t, v1, s, v2, rule, 4)
+    se = fr.std(axis=0) / math.sqrt(R)
+    assert np.all(np.abs(fr.mean(axis=0) - want) < 4.5 * se + 2e-3), (fr.mean(axis=0), want, se)
+
+
+# ------------------------------------------------------------------ rotations (general anisotropy)
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_rotated_field_is_field_at_rotated_points(orc, dim):
+    """k = R D z gives k.x = (D z).(R^T x): the rotated field is the axis-aligned one seen in
+    coordinates turned by R^T (a transposed R or a misplaced D breaks this)."""
+    z, phi = orc.sample_modes(dim, wl.EXPONENTIAL, 80, 801 + dim)
+    ell = np.array((5.0, 2.0, 1.0)[:dim])
+    R = orc.rotation_matrix(dim, (0.7, -0.4, 1.1))
+    np.testing.assert_allclose(R @ R.T, np.eye(dim), atol=1e-15)
+    x = wl.points_uniform(200, (30.0,) * dim, 802)
+    a = orc.field_points_mat(z, phi, 1.2, R @ np.diag(1.0 / ell), x)
+    b = orc.field_points(z, phi, 1.2, ell, x @ R)  # rows of x @ R are R^T x
+    np.testing.assert_allclose(a, b, rtol=0, atol=1e-12)
+    # and reduces to the per-axis rescaling when R = I
+    np.testing.assert_allclose(orc.field_points_mat(z, phi, 1.2, np.diag(1.0 / ell), x),
+                               orc.field_points(z, phi, 1.2, ell, x), rtol=0, atol=1e-13)
+
+
+def test_rotated_covariance_along_principal_axes(orc):
+    """Ensemble covariance along the rotated principal axis R e_a is sigma^2 rho(r / ell_a)."""
+    ell, sigma2, n, Rn = (4.0, 1.0), 1.5, 16, 6000
+    Rm = orc.rotation_matrix(2, (0.6,))
+    base = wl.points_uniform(3, (10.0, 10.0), 811)
+    lags = [1.0, 2.0]
+    pts = [base]
+    for a in range(2):
+        for f in lags:
+            pts.append(base + f * ell[a] * Rm[:, a])
+    pts = np.concatenate(pts)
+    nb = base.shape[0]
+    prods = np.empty((Rn, 1 + 2 * len(lags)))
+    M = Rm @ np.diag(1.0 / np.array(ell))
+    for r in range(Rn):
+        z, phi = orc.sample_modes(2, wl.GAUSSIAN, n, 50_000 + r)
+        y = orc.field_points_mat(z, phi, math.sqrt(sigma2), M, pts).reshape(-1, nb)
+        prods[r] = (y[0] * y).mean(axis=1)
+    mean, se = prods.mean(axis=0), prods.std(axis=0) / math.sqrt(Rn)
+    want = [sigma2] + [sigma2 * math.exp(-f * f) for a in range(2) for f in lags]
+    for m, s_, w in zip(mean, se, want):
+        assert abs(m - w) < 4.5 * s_, (mean, want, se)
+
+
+def test_rotated_gradients_match_finite_differences(orc):
+    z, phi = orc.sample_modes(3, wl.GAUSSIAN, 24, 821)
+    ell = np.array([3.0, 2.0, 1.5])
+    R = orc.rotation_matrix(3, (0.3, 0.5, -0.8))
+    x = wl.points_uniform(60, (8.0, 8.0, 4.0), 822)
+    g = np.random.default_rng(823).normal(size=60)
+    gr = orc.grad_points_rot(z, phi, 1.3, ell, R, x, g)
+
+    def loss(zz=z, pp=phi, sg=1.3, el=ell):
+        return float(np.dot(g, orc.field_points_mat(zz, pp, sg, R @ np.diag(1.0 / np.asarray(el)), x)))
+
+    h = 1e-5
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h * ell[a]
+        fd = (loss(el=ell + e) - loss(el=ell - e)) / (2 * e[a])
+        assert abs(fd - gr["dell"][a]) < 1e-6 * (1 + abs(fd)), (a, fd, gr["dell"][a])
+    for j in (0, 7, 23):
+        d = np.zeros_like(phi)
+        d[j] = h
+        fd = (loss(pp=phi + d) - loss(pp=phi - d)) / (2 * h)
+        assert abs(fd - gr["dphi"][j]) < 1e-6 * (1 + abs(fd))
+    # dL/dk through k = M z: perturb k_j along axis a, i.e. z_j along D^-1 R^T e_a
+    Dinv = np.diag(ell)
+    for j in (1, 12):
+        for a in range(3):
+            dz = np.zeros_like(z)
+            dz[:, j] = Dinv @ R.T[:, a] * h
+            fd = (loss(zz=z + dz) - loss(zz=z - dz)) / (2 * h)
+            assert abs(fd - gr["dk"][a, j]) < 1e-6 * (1 + abs(fd))
+    sg = (loss(sg=1.3 + h) - loss(sg=1.3 - h)) / (2 * h)
+    assert abs(sg - gr["dsigma"]) < 1e-7 * (1 + abs(sg))
+
+
+# ------------------------------------------------------------------ periodic option
+
+@pytest.mark.parametrize("rot", [False, True])
+def test_periodic_snap(orc, rot):
+    """App. B "periodic": snapped wavevectors lie on 2 pi m / L and the field repeats with
+    period L along each periodic axis."""
+    z, phi = orc.sample_modes(3, wl.EXPONENTIAL, 200, 831)
+    ell = np.array([10.0, 6.0, 2.0])
+    L = np.array([64.0, 48.0, 0.0])  # z not periodic
+    R = orc.rotation_matrix(3, (0.4, 0.0, 0.0)) if rot else np.eye(3)
+    zs = orc.snap_periodic(z, ell, L, rot=R if rot else None)
+    k = R @ np.diag(1.0 / ell) @ zs
+    m = k[:2] * L[:2, None] / (2 * np.pi)
+    np.testing.assert_allclose(m, np.round(m), atol=1e-9)
+    k0 = R @ np.diag(1.0 / ell) @ z
+    np.testing.assert_allclose(k[2], k0[2], rtol=1e-13, atol=1e-15)  # non-periodic axis untouched
+    assert np.all(np.abs(k[:2] - k0[:2]) <= np.pi / L[:2, None] * (1 + 1e-12))
+    M = R @ np.diag(1.0 / ell)
+    x = wl.points_uniform(50, (64.0, 48.0, 10.0), 832)
+    y0 = orc.field_points_mat(zs, phi, 1.0, M, x)
+    for a in range(2):
+        sh = x.copy()
+        sh[:, a] += L[a]
+        y1 = orc.field_points_mat(zs, phi, 1.0, M, sh)
+        # wavevectors reach |k| ~ 1e3 (heavy tails), so k.x rounds at ~1e-13 rad per term
+        np.testing.assert_allclose(y1, y0, rtol=0, atol=1e-9)
