@@ -67,8 +67,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline (oracle) leg")
     ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
     ap.add_argument("--only", default=None, help="time a single grid method (profiling runs)")
-    ap.add_argument("--extras", default="points,epilogue,adjoint,batch",
-                    help="comma-separated extra workloads to time (points, epilogue, adjoint, batch)")
+    ap.add_argument("--extras", default="points,epilogue,adjoint,pluri,batch",
+                    help="comma-separated extra workloads to time (points, epilogue, adjoint, pluri, batch)")
     ap.add_argument("--extras-only", action="store_true", help="skip the headline workload (profiling runs)")
     ap.add_argument("--spinup-ms", type=float, default=500.0,
                     help="untimed GPU work before the first timed loop (steady clocks)")
@@ -258,6 +258,8 @@ def extras(args, grf, wl, torch, np, dev):
         out.update(epilogue_extra(grf, wl, torch, np, dev))
     if "adjoint" in sel:
         out.update(adjoint_extra(grf, wl, torch, np, dev))
+    if "pluri" in sel:
+        out.update(pluri_extra(grf, wl, torch, np, dev))
     if "batch" in sel:
         try:
             out["batch512_2d"] = batch_extra(grf, wl, torch, np, dev)
@@ -329,6 +331,39 @@ def adjoint_extra(grf, wl, torch, np, dev):
                   "bwd_roofline": {"bound": "alu", "achieved": Cg * c["n_modes"] / (db_k * 1e-3), "peak": COS_PEAK,
                                    "unit": "mode·cell/s", "frac": Cg * c["n_modes"] / (db_k * 1e-3) / COS_PEAK}}}
     return out
+
+
+def pluri_extra(grf, wl, torch, np, dev):
+    # bitruncated (pluri-Gaussian) facies on the 1024x512 grid: two fields + the rule pass
+    c = wl.WORKLOADS["pluri_2d_1024x512"]
+    log("[bench] extras: pluri_2d_1024x512")
+    f1, f2 = c["fields"]
+    ms_ = []
+    for f in (f1, f2):
+        z, phi = grf.make_modes(2, f["cov"], c["n_modes"], f["seed"])
+        ms_.append(grf.modes_from_tables(z, phi, math.sqrt(f["sigma2"]), f["ell"], device=dev))
+    rule = grf.trunc2(c["t"], c["s"], c["rule"], c["values"])
+    C = int(np.prod(c["shape"]))
+    res = {"cells": C, "mode_cells": 2 * C * c["n_modes"]}
+    for meth in ("sep_f16", "direct_f32"):
+        o = {"facies": torch.empty(C, dtype=torch.uint8, device=dev), "value": torch.empty(C, device=dev)}
+        ws = torch.empty(1 << 28, dtype=torch.uint8, device=dev)
+        steps = 20 if meth.startswith("sep") else 5
+        ms, _ = _timed(torch, grf, lambda: grf.pluri_grid(ms_[0], ms_[1], c["shape"], rule, h=c["h"], method=meth,
+                                                          want_value=True, out=o, workspace=ws), steps, 3)
+        res[meth] = {"ms_per_call": ms, "mode_cells_per_s": 2 * C * c["n_modes"] / (ms * 1e-3),
+                     "facies_fractions": [float(v) for v in
+                                          (torch.bincount(o["facies"].long(), minlength=4).double() / C).cpu()]}
+    # the stand-alone rule pass over a 256^3 pair of fields: read 2 x 4 B, write 1 B facies + 4 B value
+    n = 256 ** 3
+    y1, y2 = torch.randn(n, device=dev), torch.randn(n, device=dev)
+    po = {"facies": torch.empty(n, dtype=torch.uint8, device=dev), "value": torch.empty(n, device=dev)}
+    ms, kms = _timed(torch, grf, lambda: grf.pluri_apply(y1, y2, rule, want_value=True, out=po), 20, 3)
+    nbytes = n * (4 + 4 + 1 + 4)
+    res["rule_pass_256^3"] = {"ms_per_call": ms, "roofline": {
+        "bound": "hbm", "achieved": nbytes / (kms * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+        "frac": nbytes / (kms * 1e-3) / HBM_PEAK, "algorithmic": "2 x 4 B read + 1 B facies + 4 B value per cell"}}
+    return {"pluri_2d_1024x512": res}
 
 
 def batch_extra(grf, wl, torch, np, dev):

@@ -62,6 +62,7 @@ extern "C" {
 #define GRF_SEP_F16_X3 5    /* fp16 hi+lo split tables, three passes */
 
 #define GRF_MAX_THRESHOLDS 15
+#define GRF_MAX_FACIES 64
 
 /* Generator options (App. B dictionary: correlation, Kmean, Ksigma, Lcorr, nu, nfreq,
  * disableY/disableZ as dim). */
@@ -184,6 +185,58 @@ int eval_field_points(const grf_modes* modes, const double* xyz, int64_t n_point
  */
 int epilogue_apply(const float* y, int64_t n, const grf_epi* epi, float* k, uint8_t* ind,
                    void* stream);
+
+/*
+ * Bitruncated (pluri-Gaussian) truncation rule, Sec. 3.1 and App. B ("bitruncated",
+ * "thresholds", "thresholds2", "values"): two independent fields Y1, Y2 are thresholded
+ * separately, cell c lies in bin (i, j) with i = #{a : t_a < Y1_c} and j = #{b : s_b < Y2_c}
+ * (strict: Y == t falls in the lower bin), and the rule merges the (n_t + 1) x (n_s + 1)
+ * bins into facies: facies_c = rule[i * (n_s + 1) + j]; value_c = values[facies_c].
+ * With n_s = 0 and rule[i] = i this is the single truncation of grf_epi.
+ */
+typedef struct grf_trunc2 {
+    int32_t n_t;                        /* thresholds on Y1, ascending, 0 .. GRF_MAX_THRESHOLDS */
+    float t[GRF_MAX_THRESHOLDS];
+    int32_t n_s;                        /* thresholds on Y2, ascending, 0 .. GRF_MAX_THRESHOLDS */
+    float s[GRF_MAX_THRESHOLDS];
+    uint8_t rule[(GRF_MAX_THRESHOLDS + 1) * (GRF_MAX_THRESHOLDS + 1)]; /* first (n_t+1)(n_s+1) used */
+    int32_t n_values;                   /* 0 .. GRF_MAX_FACIES; every used rule entry must be
+                                           < n_values when a value output is requested */
+    float values[GRF_MAX_FACIES];
+} grf_trunc2;
+
+/* Workspace of eval_pluri_grid when the caller keeps neither field (y1 == y2 == NULL); each
+ * field buffer the caller passes makes the need C * 4 bytes (rounded up to 256) smaller. */
+int eval_pluri_grid_ws_size(const grf_modes* m1, const grf_modes* m2, const grf_grid* grid, int method,
+                            size_t* bytes);
+
+/*
+ * eval_pluri_grid -- a pluri-Gaussian facies field on a structured grid: Y1 from m1 and Y2
+ * from m2 by `method` (as eval_field_grid), then the bitruncated rule over the two stored
+ * fields.  m1 and m2 must have the same dim (independent tables: different seeds).
+ *   facies  device uint8[C] or NULL;  value device float[C] or NULL (one of them required).
+ *   y1, y2  device float[C] or NULL: keep the fields; a field not kept lives in the workspace.
+ * The facies are decided in FP32 on each path's Y; they match the FP64 definition except
+ * in cells whose Y1 or Y2 lies within that path's error of a threshold.
+ */
+int eval_pluri_grid(const grf_modes* m1, const grf_modes* m2, const grf_grid* grid, int method,
+                    const grf_trunc2* rule, uint8_t* facies, float* value, float* y1, float* y2, void* ws,
+                    size_t ws_bytes, void* stream);
+
+/* The same at P arbitrary points (xyz device double[P][dim]); the workspace size is for
+ * y1 == y2 == NULL. */
+int eval_pluri_points_ws_size(const grf_modes* m1, const grf_modes* m2, int64_t n_points, int method,
+                              size_t* bytes);
+int eval_pluri_points(const grf_modes* m1, const grf_modes* m2, const double* xyz, int64_t n_points, int method,
+                      const grf_trunc2* rule, uint8_t* facies, float* value, float* y1, float* y2, void* ws,
+                      size_t ws_bytes, void* stream);
+
+/* Stand-alone bitruncated rule over two existing fields y1, y2 (device float[n]);
+ * facies device uint8[n] / value device float[n], either may be NULL (not both);
+ * ws: device workspace of at least GRF_PLURI_APPLY_WS_BYTES bytes (the rule's tables). */
+#define GRF_PLURI_APPLY_WS_BYTES 512
+int pluri_apply(const float* y1, const float* y2, int64_t n, const grf_trunc2* rule, uint8_t* facies,
+                float* value, void* ws, size_t ws_bytes, void* stream);
 
 /*
  * Gradients of a scalar loss L through Y at P points, given g = dL/dY (field_backward).

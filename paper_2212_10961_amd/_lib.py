@@ -15,6 +15,8 @@ GRF_COV_GAUSSIAN, GRF_COV_EXPONENTIAL, GRF_COV_MATERN = 0, 1, 2
 GRF_AUTO, GRF_DIRECT_F32, GRF_DIRECT_F64 = -1, 0, 1
 GRF_SEP_BF16, GRF_SEP_F16, GRF_SEP_BF16_X3, GRF_SEP_F16_X3 = 2, 3, 4, 5
 GRF_MAX_THRESHOLDS = 15
+GRF_MAX_FACIES = 64
+GRF_PLURI_APPLY_WS_BYTES = 512
 GRF_PLAN_GRAPH, GRF_PLAN_AUTOTUNE = 1, 2
 
 METHODS = {
@@ -27,6 +29,7 @@ METHODS = {
 EXPORTS = [
     "grf_version", "grf_last_error", "make_modes", "eval_field_grid_ws_size", "eval_field_grid",
     "eval_field_grid_tile", "grf_sep_tile_count", "grf_sep_tile_shape",
+    "eval_pluri_grid_ws_size", "eval_pluri_grid", "eval_pluri_points_ws_size", "eval_pluri_points", "pluri_apply",
     "eval_field_grid_f64", "eval_field_points_ws_size", "eval_field_points", "epilogue_apply",
     "field_backward_ws_size", "field_backward", "field_backward_grid_ws_size", "field_backward_grid",
     "grf_plan_create", "grf_plan_destroy", "eval_field_batch", "grf_plan_info",
@@ -53,6 +56,13 @@ class GrfGrid(ctypes.Structure):
 class GrfEpi(ctypes.Structure):
     _fields_ = [("mu", ctypes.c_float), ("n_thresholds", ctypes.c_int32),
                 ("thresholds", ctypes.c_float * GRF_MAX_THRESHOLDS)]
+
+
+class GrfTrunc2(ctypes.Structure):
+    _fields_ = [("n_t", ctypes.c_int32), ("t", ctypes.c_float * GRF_MAX_THRESHOLDS),
+                ("n_s", ctypes.c_int32), ("s", ctypes.c_float * GRF_MAX_THRESHOLDS),
+                ("rule", ctypes.c_uint8 * ((GRF_MAX_THRESHOLDS + 1) ** 2)),
+                ("n_values", ctypes.c_int32), ("values", ctypes.c_float * GRF_MAX_FACIES)]
 
 
 class GrfBatchItem(ctypes.Structure):
@@ -90,6 +100,13 @@ def load():
                                   vp, sz, vp], ctypes.c_int),
         "grf_sep_tile_count": ([], ctypes.c_int),
         "grf_sep_tile_shape": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, P(i32), P(i32), P(i32)], ctypes.c_int),
+        "eval_pluri_grid_ws_size": ([P(GrfModes), P(GrfModes), P(GrfGrid), ctypes.c_int, P(sz)], ctypes.c_int),
+        "eval_pluri_grid": ([P(GrfModes), P(GrfModes), P(GrfGrid), ctypes.c_int, P(GrfTrunc2), vp, vp, vp, vp, vp,
+                             sz, vp], ctypes.c_int),
+        "eval_pluri_points_ws_size": ([P(GrfModes), P(GrfModes), i64, ctypes.c_int, P(sz)], ctypes.c_int),
+        "eval_pluri_points": ([P(GrfModes), P(GrfModes), vp, i64, ctypes.c_int, P(GrfTrunc2), vp, vp, vp, vp, vp,
+                               sz, vp], ctypes.c_int),
+        "pluri_apply": ([vp, vp, i64, P(GrfTrunc2), vp, vp, vp, sz, vp], ctypes.c_int),
         "eval_field_grid_f64": ([P(GrfModes), P(GrfGrid), ctypes.c_double, vp, vp, vp, sz, vp], ctypes.c_int),
         "eval_field_points_ws_size": ([P(GrfModes), i64, ctypes.c_int, P(sz)], ctypes.c_int),
         "eval_field_points": ([P(GrfModes), vp, i64, ctypes.c_int, P(GrfEpi), vp, vp, vp, vp, sz, vp],

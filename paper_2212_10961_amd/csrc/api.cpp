@@ -1,4 +1,5 @@
 // C-ABI entry points: validation, workspace layout and dispatch to the kernels.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -269,25 +270,12 @@ int eval_field_grid_ws_size(const grf_modes* modes, const grf_grid* grid, int me
 
 namespace grf {
 
-static int grid_eval(const char* fn, const grf_modes* modes, const grf_grid* grid, int method, int tile,
-                     const grf_epi* epi, float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes, void* stream)
+// Tables and sum of one grid evaluation with a prepared epilogue; the caller has validated
+// the modes, grid, method (resolved), tile and outputs, and `ws` holds grid_ws(...) bytes.
+static int grid_launch(const grf_modes* modes, const grf_grid* grid, int method, int tile, const Epi& e, float* y,
+                       float* k, uint8_t* ind, void* ws, hipStream_t s)
 {
-    int rc;
-    if ((rc = check_modes(modes, fn))) return rc;
-    if ((rc = check_grid(grid, modes->dim, fn))) return rc;
-    if (!y && !k && !ind) return fail(GRF_EINVAL, "%s: no output requested", fn);
-    if ((rc = check_epi(epi, k, ind, fn))) return rc;
-    method = resolve_grid_method(method, grid);
-    if (method < GRF_DIRECT_F32 || method > GRF_SEP_F16_X3) return fail(GRF_EINVAL, "%s: unknown method %d", fn, method);
-    if (tile < -1 || tile >= sep_tile_count())
-        return fail(GRF_EINVAL, "%s: tile selector %d outside [-1, %d)", fn, tile, sep_tile_count());
-    if (tile >= 0 && !is_sep(method)) return fail(GRF_EINVAL, "%s: tile selectors apply to separable methods", fn);
-    const GridWs need = grid_ws(modes, grid, method, nullptr);
-    if (ws_bytes < need.bytes || (!ws && need.bytes))
-        return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need.bytes, ws_bytes);
-    hipStream_t s = static_cast<hipStream_t>(stream);
     const GridWs w = grid_ws(modes, grid, method, ws);
-    const Epi e = make_epi(epi);
     const float amp = static_cast<float>(modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n)));
     const int64_t ldp = padded_modes(modes->n);
 
@@ -326,7 +314,232 @@ static int grid_eval(const char* fn, const grf_modes* modes, const grf_grid* gri
     return GRF_OK;
 }
 
+static int check_grid_method(const char* fn, const grf_grid* grid, int* method, int tile)
+{
+    *method = resolve_grid_method(*method, grid);
+    if (*method < GRF_DIRECT_F32 || *method > GRF_SEP_F16_X3)
+        return fail(GRF_EINVAL, "%s: unknown method %d", fn, *method);
+    if (tile < -1 || tile >= sep_tile_count())
+        return fail(GRF_EINVAL, "%s: tile selector %d outside [-1, %d)", fn, tile, sep_tile_count());
+    if (tile >= 0 && !is_sep(*method)) return fail(GRF_EINVAL, "%s: tile selectors apply to separable methods", fn);
+    return GRF_OK;
+}
+
+static int grid_eval(const char* fn, const grf_modes* modes, const grf_grid* grid, int method, int tile,
+                     const grf_epi* epi, float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes, void* stream)
+{
+    int rc;
+    if ((rc = check_modes(modes, fn))) return rc;
+    if ((rc = check_grid(grid, modes->dim, fn))) return rc;
+    if (!y && !k && !ind) return fail(GRF_EINVAL, "%s: no output requested", fn);
+    if ((rc = check_epi(epi, k, ind, fn))) return rc;
+    if ((rc = check_grid_method(fn, grid, &method, tile))) return rc;
+    const GridWs need = grid_ws(modes, grid, method, nullptr);
+    if (ws_bytes < need.bytes || (!ws && need.bytes))
+        return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need.bytes, ws_bytes);
+    return grid_launch(modes, grid, method, tile, make_epi(epi), y, k, ind, ws, static_cast<hipStream_t>(stream));
+}
+
+// ---------------------------------------------------------------- bitruncated (pluri-Gaussian) rule
+
+static int check_trunc2(const grf_trunc2* r, bool want_value, const char* fn)
+{
+    if (!r) return fail(GRF_EINVAL, "%s: rule is NULL", fn);
+    if (r->n_t < 0 || r->n_t > GRF_MAX_THRESHOLDS || r->n_s < 0 || r->n_s > GRF_MAX_THRESHOLDS)
+        return fail(GRF_EINVAL, "%s: threshold counts must be in [0, %d]", fn, GRF_MAX_THRESHOLDS);
+    for (int i = 1; i < r->n_t; ++i)
+        if (!(r->t[i] >= r->t[i - 1])) return fail(GRF_EINVAL, "%s: thresholds t must be ascending", fn);
+    for (int i = 1; i < r->n_s; ++i)
+        if (!(r->s[i] >= r->s[i - 1])) return fail(GRF_EINVAL, "%s: thresholds s must be ascending", fn);
+    if (r->n_values < 0 || r->n_values > GRF_MAX_FACIES)
+        return fail(GRF_EINVAL, "%s: n_values must be in [0, %d]", fn, GRF_MAX_FACIES);
+    if (want_value) {
+        const int bins = (r->n_t + 1) * (r->n_s + 1);
+        for (int b = 0; b < bins; ++b)
+            if (r->rule[b] >= r->n_values)
+                return fail(GRF_EINVAL, "%s: rule entry %d names facies %d but only %d values are given", fn, b,
+                            r->rule[b], r->n_values);
+    }
+    return GRF_OK;
+}
+
+static_assert(kRuleBytes <= GRF_PLURI_APPLY_WS_BYTES, "pluri_apply workspace holds the rule tables");
+
+// `tables` is device memory holding the rule's lookup tables (launch_rule_tables).
+static PluriEpi make_pluri(const grf_trunc2* r, const void* tables)
+{
+    PluriEpi e{};
+    e.nt = r->n_t;
+    for (int i = 0; i < r->n_t; ++i) e.t[i] = r->t[i];
+    e.ns = r->n_s;
+    for (int i = 0; i < r->n_s; ++i) e.s[i] = r->s[i];
+    e.rule = static_cast<const uint8_t*>(tables);
+    e.values = reinterpret_cast<const float*>(static_cast<const uint8_t*>(tables) + 256);
+    return e;
+}
+
+static int check_pair(const grf_modes* m1, const grf_modes* m2, const char* fn)
+{
+    int rc;
+    if ((rc = check_modes(m1, fn)) || (rc = check_modes(m2, fn))) return rc;
+    if (m1->dim != m2->dim) return fail(GRF_EINVAL, "%s: both fields must have the same dim", fn);
+    return GRF_OK;
+}
+
+// Workspace of the bitruncated grid: the rule's tables, each field the caller does not keep,
+// and the larger of the two fields' table layouts (the two evaluations run one after the other).
+static size_t pluri_grid_ws(const grf_modes* m1, const grf_modes* m2, const grf_grid* g, int method, bool own_y1,
+                            bool own_y2)
+{
+    const int64_t C = g->n[0] * g->n[1] * g->n[2];
+    const size_t t = std::max(grid_ws(m1, g, method, nullptr).bytes, grid_ws(m2, g, method, nullptr).bytes);
+    const size_t f = align256(sizeof(float) * size_t(C));
+    return align256(kRuleBytes) + (own_y1 ? f : 0) + (own_y2 ? f : 0) + t;
+}
+
 }  // namespace grf
+
+extern "C" {
+
+int eval_pluri_grid_ws_size(const grf_modes* m1, const grf_modes* m2, const grf_grid* grid, int method,
+                            size_t* bytes)
+{
+    const char* fn = "eval_pluri_grid_ws_size";
+    int rc;
+    if ((rc = check_pair(m1, m2, fn))) return rc;
+    if ((rc = check_grid(grid, m1->dim, fn))) return rc;
+    if (!bytes) return fail(GRF_EINVAL, "%s: bytes is NULL", fn);
+    if ((rc = check_grid_method(fn, grid, &method, -1))) return rc;
+    *bytes = pluri_grid_ws(m1, m2, grid, method, true, true);
+    return GRF_OK;
+}
+
+int eval_pluri_grid(const grf_modes* m1, const grf_modes* m2, const grf_grid* grid, int method,
+                    const grf_trunc2* rule, uint8_t* facies, float* value, float* y1, float* y2, void* ws,
+                    size_t ws_bytes, void* stream)
+{
+    const char* fn = "eval_pluri_grid";
+    int rc;
+    if ((rc = check_pair(m1, m2, fn))) return rc;
+    if ((rc = check_grid(grid, m1->dim, fn))) return rc;
+    if (!facies && !value) return fail(GRF_EINVAL, "%s: facies or value output required", fn);
+    if ((rc = check_trunc2(rule, value != nullptr, fn))) return rc;
+    if ((rc = check_grid_method(fn, grid, &method, -1))) return rc;
+    const size_t need = pluri_grid_ws(m1, m2, grid, method, y1 == nullptr, y2 == nullptr);
+    if (!ws || ws_bytes < need) return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t C = grid->n[0] * grid->n[1] * grid->n[2];
+    Carve c(ws);
+    uint8_t* rt = c.take<uint8_t>(kRuleBytes);
+    float* f1 = y1 ? y1 : c.take<float>(size_t(C));
+    float* f2 = y2 ? y2 : c.take<float>(size_t(C));
+    void* tabs = c.base + c.used;
+    GRF_HIP(launch_rule_tables(*rule, rt, s));
+    if ((rc = grid_launch(m1, grid, method, -1, Epi{}, f1, nullptr, nullptr, tabs, s))) return rc;
+    if ((rc = grid_launch(m2, grid, method, -1, Epi{}, f2, nullptr, nullptr, tabs, s))) return rc;
+    GRF_HIP(launch_pluri_epilogue(f1, f2, C, make_pluri(rule, rt), facies, value, s));
+    return GRF_OK;
+}
+
+int pluri_apply(const float* y1, const float* y2, int64_t n, const grf_trunc2* rule, uint8_t* facies, float* value,
+                void* ws, size_t ws_bytes, void* stream)
+{
+    const char* fn = "pluri_apply";
+    if (n < 0) return fail(GRF_EINVAL, "%s: n < 0", fn);
+    int rc;
+    if ((rc = check_trunc2(rule, value != nullptr, fn))) return rc;
+    if (n == 0) return GRF_OK;
+    if (!facies && !value) return fail(GRF_EINVAL, "%s: facies or value output required", fn);
+    if (!y1 || !y2) return fail(GRF_EINVAL, "%s: y1 and y2 are required", fn);
+    if (!ws || ws_bytes < GRF_PLURI_APPLY_WS_BYTES)
+        return fail(GRF_ENOMEM, "%s: workspace of %d bytes needed, %zu given", fn, GRF_PLURI_APPLY_WS_BYTES, ws_bytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    GRF_HIP(launch_rule_tables(*rule, ws, s));
+    TimedScope timed(s);
+    GRF_HIP(launch_pluri_epilogue(y1, y2, n, make_pluri(rule, ws), facies, value, s));
+    return GRF_OK;
+}
+
+}  // extern "C"
+
+namespace grf {
+
+// Per-mode parameters and the point sum with a prepared epilogue (validated by the caller;
+// `ws` holds points_ws_bytes(...)).
+static int points_launch(const grf_modes* modes, const double* xyz, int64_t n_points, int method, const Epi& e,
+                         float* y, float* k, uint8_t* ind, void* ws, hipStream_t s)
+{
+    const int64_t ldp = padded_modes(modes->n);
+    Carve c(ws);
+    double* params = c.take<double>(4 * ldp);
+    float* partial = method == GRF_DIRECT_F32 ? c.take<float>(size_t(points_mode_slices(n_points, modes->n)) * n_points)
+                                              : nullptr;
+    GRF_HIP(launch_mode_params(modes->z, modes->phi, modes->dim, modes->n, ldp, modes->ell, params, s));
+    const float amp = static_cast<float>(modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n)));
+    TimedScope timed(s);
+    GRF_HIP(launch_direct_points(params, modes->n, modes->dim, xyz, n_points, method == GRF_DIRECT_F64, amp, e, y, k,
+                                 ind, partial, s));
+    return GRF_OK;
+}
+
+static int check_points_method(const char* fn, int* method)
+{
+    if (*method == GRF_AUTO) *method = GRF_DIRECT_F32;
+    if (is_sep(*method)) return fail(GRF_EUNSUPPORTED, "%s: separable methods need a structured grid", fn);
+    if (*method != GRF_DIRECT_F32 && *method != GRF_DIRECT_F64) return fail(GRF_EINVAL, "%s: unknown method %d", fn, *method);
+    return GRF_OK;
+}
+
+}  // namespace grf
+
+extern "C" {
+
+int eval_pluri_points_ws_size(const grf_modes* m1, const grf_modes* m2, int64_t n_points, int method,
+                              size_t* bytes)
+{
+    const char* fn = "eval_pluri_points_ws_size";
+    int rc;
+    if ((rc = check_pair(m1, m2, fn))) return rc;
+    if (!bytes) return fail(GRF_EINVAL, "%s: bytes is NULL", fn);
+    if (n_points < 0) return fail(GRF_EINVAL, "%s: n_points < 0", fn);
+    if ((rc = check_points_method(fn, &method))) return rc;
+    *bytes = align256(kRuleBytes) + 2 * align256(sizeof(float) * size_t(n_points)) +
+             std::max(points_ws_bytes(m1->n, n_points, method), points_ws_bytes(m2->n, n_points, method));
+    return GRF_OK;
+}
+
+int eval_pluri_points(const grf_modes* m1, const grf_modes* m2, const double* xyz, int64_t n_points, int method,
+                      const grf_trunc2* rule, uint8_t* facies, float* value, float* y1, float* y2, void* ws,
+                      size_t ws_bytes, void* stream)
+{
+    const char* fn = "eval_pluri_points";
+    int rc;
+    if ((rc = check_pair(m1, m2, fn))) return rc;
+    if (n_points < 0) return fail(GRF_EINVAL, "%s: n_points < 0", fn);
+    if (n_points > (int64_t(1) << 40)) return fail(GRF_EINVAL, "%s: too many points", fn);
+    if ((rc = check_points_method(fn, &method))) return rc;
+    if ((rc = check_trunc2(rule, value != nullptr, fn))) return rc;
+    if (n_points == 0) return GRF_OK;
+    if (!facies && !value) return fail(GRF_EINVAL, "%s: facies or value output required", fn);
+    if (!xyz) return fail(GRF_EINVAL, "%s: xyz is NULL", fn);
+    const size_t fb = align256(sizeof(float) * size_t(n_points));
+    const size_t need = align256(kRuleBytes) + (y1 ? 0 : fb) + (y2 ? 0 : fb) +
+                        std::max(points_ws_bytes(m1->n, n_points, method), points_ws_bytes(m2->n, n_points, method));
+    if (!ws || ws_bytes < need) return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    Carve c(ws);
+    uint8_t* rt = c.take<uint8_t>(kRuleBytes);
+    float* f1 = y1 ? y1 : c.take<float>(size_t(n_points));
+    float* f2 = y2 ? y2 : c.take<float>(size_t(n_points));
+    void* rest = c.base + c.used;
+    GRF_HIP(launch_rule_tables(*rule, rt, s));
+    if ((rc = points_launch(m1, xyz, n_points, method, Epi{}, f1, nullptr, nullptr, rest, s))) return rc;
+    if ((rc = points_launch(m2, xyz, n_points, method, Epi{}, f2, nullptr, nullptr, rest, s))) return rc;
+    GRF_HIP(launch_pluri_epilogue(f1, f2, n_points, make_pluri(rule, rt), facies, value, s));
+    return GRF_OK;
+}
+
+}  // extern "C"
 
 extern "C" {
 
@@ -404,27 +617,14 @@ int eval_field_points(const grf_modes* modes, const double* xyz, int64_t n_point
     if ((rc = check_modes(modes, fn))) return rc;
     if (n_points < 0) return fail(GRF_EINVAL, "%s: n_points < 0", fn);
     if (n_points > (int64_t(1) << 40)) return fail(GRF_EINVAL, "%s: too many points", fn);
-    if (method == GRF_AUTO) method = GRF_DIRECT_F32;
-    if (is_sep(method)) return fail(GRF_EUNSUPPORTED, "%s: separable methods need a structured grid", fn);
-    if (method != GRF_DIRECT_F32 && method != GRF_DIRECT_F64) return fail(GRF_EINVAL, "%s: unknown method %d", fn, method);
+    if ((rc = check_points_method(fn, &method))) return rc;
     if ((rc = check_epi(epi, k, ind, fn))) return rc;
     if (n_points == 0) return GRF_OK;
     if (!y && !k && !ind) return fail(GRF_EINVAL, "%s: no output requested", fn);
     if (!xyz) return fail(GRF_EINVAL, "%s: xyz is NULL", fn);
     const size_t need = points_ws_bytes(modes->n, n_points, method);
     if (!ws || ws_bytes < need) return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
-    hipStream_t s = static_cast<hipStream_t>(stream);
-    const int64_t ldp = padded_modes(modes->n);
-    Carve c(ws);
-    double* params = c.take<double>(4 * ldp);
-    float* partial = method == GRF_DIRECT_F32 ? c.take<float>(size_t(points_mode_slices(n_points, modes->n)) * n_points)
-                                              : nullptr;
-    GRF_HIP(launch_mode_params(modes->z, modes->phi, modes->dim, modes->n, ldp, modes->ell, params, s));
-    const float amp = static_cast<float>(modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n)));
-    TimedScope timed(s);
-    GRF_HIP(launch_direct_points(params, modes->n, modes->dim, xyz, n_points, method == GRF_DIRECT_F64, amp,
-                                 make_epi(epi), y, k, ind, partial, s));
-    return GRF_OK;
+    return points_launch(modes, xyz, n_points, method, make_epi(epi), y, k, ind, ws, static_cast<hipStream_t>(stream));
 }
 
 int epilogue_apply(const float* y, int64_t n, const grf_epi* epi, float* k, uint8_t* ind, void* stream)

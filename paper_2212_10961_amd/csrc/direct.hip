@@ -19,13 +19,7 @@ __device__ __forceinline__ float cos_rev(float r) { return __builtin_amdgcn_cosf
 __device__ __forceinline__ void store_out(int64_t c, float yv, const Epi& e, float* __restrict__ y,
                                           float* __restrict__ k, uint8_t* __restrict__ ind)
 {
-    if (y) y[c] = yv;
-    if (k) k[c] = expf(e.mu + yv);
-    if (ind) {
-        int f = 0;
-        for (int i = 0; i < e.nthr; ++i) f += (yv > e.thr[i]) ? 1 : 0;
-        ind[c] = static_cast<uint8_t>(f);
-    }
+    epi_store(c, yv, e, y, k, ind);
 }
 
 // ---------------------------------------------------------------------------- grid, FP32
@@ -39,6 +33,8 @@ constexpr int kDgRow = (kDgJ + 4) / 4;  // float4 per padded row
 static_assert(kDgB == kDirectTile, "tile side shared with the batch planner");
 
 // One 64 x 64 (x, (y,z)) tile; `sx`, `sq` are LDS arrays of kDgB * kDgRow float4.  Whole block.
+// Without EPI only Y is stored (batched ensembles).
+template <bool EPI>
 __device__ __forceinline__ void direct_tile(const float* __restrict__ tx, const float* __restrict__ ty,
                                             const float* __restrict__ tz, int n, int64_t ldp, int nx, int ny,
                                             int64_t nq, int x0, int64_t q0, float amp, const Epi& epi,
@@ -105,7 +101,10 @@ __device__ __forceinline__ void direct_tile(const float* __restrict__ tx, const 
 #pragma unroll
         for (int b = 0; b < 4; ++b) {
             const int64_t q = q0 + lq + 4 * b;
-            if (x < nx && q < nq) store_out(q * nx + x, amp * acc[a][b], epi, y, k, ind);
+            if (x < nx && q < nq) {
+                if constexpr (EPI) store_out(q * nx + x, amp * acc[a][b], epi, y, k, ind);
+                else y[q * nx + x] = amp * acc[a][b];
+            }
         }
     }
 }
@@ -119,8 +118,8 @@ __global__ __launch_bounds__(256, 2) void k_direct_grid(const float* __restrict_
     __shared__ float4 sx[kDgB * kDgRow];
     __shared__ float4 sq[kDgB * kDgRow];
     const int64_t bid = blockIdx.x;
-    direct_tile(tx, ty, tz, n, ldp, nx, ny, nq, static_cast<int>(bid % nxt) * kDgB, (bid / nxt) * kDgB, amp, epi, y,
-                k, ind, sx, sq);
+    direct_tile<true>(tx, ty, tz, n, ldp, nx, ny, nq, static_cast<int>(bid % nxt) * kDgB, (bid / nxt) * kDgB, amp, epi,
+                      y, k, ind, sx, sq);
 }
 
 // Persistent batched form: blocks pull (instance, tile) work items from one atomic counter
@@ -131,7 +130,6 @@ __global__ __launch_bounds__(256, 2) void k_direct_batch(const DirectBatchItem* 
     __shared__ float4 sx[kDgB * kDgRow];
     __shared__ float4 sq[kDgB * kDgRow];
     __shared__ unsigned long long s_item;
-    const Epi none{};
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1ull);
         __syncthreads();
@@ -146,8 +144,8 @@ __global__ __launch_bounds__(256, 2) void k_direct_batch(const DirectBatchItem* 
         }
         const DirectBatchItem& b = items[lo];
         const int64_t local = it - b.item0;
-        direct_tile(b.tx, b.ty, b.tz, b.n, b.ldp, b.nx, b.ny, b.nq, static_cast<int>(local % b.nxt) * kDgB,
-                    (local / b.nxt) * kDgB, b.amp, none, b.y, nullptr, nullptr, sx, sq);
+        direct_tile<false>(b.tx, b.ty, b.tz, b.n, b.ldp, b.nx, b.ny, b.nq, static_cast<int>(local % b.nxt) * kDgB,
+                           (local / b.nxt) * kDgB, b.amp, Epi{}, b.y, nullptr, nullptr, sx, sq);
     }
 }
 
@@ -289,6 +287,22 @@ __global__ __launch_bounds__(256) void k_epilogue(const float* __restrict__ y, i
     }
 }
 
+// Bitruncated rule over two stored fields: grid-stride, one cell per thread and step.
+__global__ __launch_bounds__(256) void k_pluri(const float* __restrict__ y1, const float* __restrict__ y2, int64_t n,
+                                              PluriEpi pe, uint8_t* __restrict__ facies, float* __restrict__ value)
+{
+    const int64_t stride = static_cast<int64_t>(gridDim.x) * blockDim.x;
+    for (int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; c < n; c += stride) {
+        const float a = y1[c], b = y2[c];
+        int i = 0, j = 0;
+        for (int q = 0; q < pe.nt; ++q) i += (a > pe.t[q]) ? 1 : 0;
+        for (int q = 0; q < pe.ns; ++q) j += (b > pe.s[q]) ? 1 : 0;
+        const int f = pe.rule[i * (pe.ns + 1) + j];
+        if (facies) facies[c] = static_cast<uint8_t>(f);
+        if (value) value[c] = pe.values[f];
+    }
+}
+
 __global__ __launch_bounds__(256) void k_epilogue_scalar(const float* __restrict__ y, int64_t n, Epi epi,
                                                         float* __restrict__ k, uint8_t* __restrict__ ind)
 {
@@ -385,6 +399,16 @@ int direct_batch_blocks_per_cu()
     int nb = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_direct_batch, 256, 0) != hipSuccess) return 1;
     return nb > 0 ? nb : 1;
+}
+
+hipError_t launch_pluri_epilogue(const float* y1, const float* y2, int64_t n, const PluriEpi& pe, uint8_t* facies,
+                                 float* value, hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    int64_t blocks = (n + 255) / 256;
+    if (blocks > 256 * 64) blocks = 256 * 64;
+    hipLaunchKernelGGL(k_pluri, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, y1, y2, n, pe, facies, value);
+    return hipGetLastError();
 }
 
 hipError_t launch_epilogue(const float* y, int64_t n, const Epi& epi, float* k, uint8_t* ind, hipStream_t s)

@@ -39,6 +39,8 @@ struct TimedScope {
 };
 
 // ---------------------------------------------------------------- epilogue
+// Applied to each cell's Y before the stores of the sum kernels (Sec. 4.1 scaling, Sec. 3.1
+// single truncation): K = exp(mu + Y), facies index #{q : thr[q] < Y}.
 struct Epi {
     float mu;
     int nthr;
@@ -46,6 +48,35 @@ struct Epi {
 };
 
 Epi make_epi(const grf_epi* e);
+
+__device__ __forceinline__ void epi_store(int64_t c, float yv, const Epi& e, float* __restrict__ y,
+                                          float* __restrict__ k, uint8_t* __restrict__ ind)
+{
+    if (y) y[c] = yv;
+    if (k) k[c] = expf(e.mu + yv);
+    if (ind) {
+        int f = 0;
+        for (int q = 0; q < e.nthr; ++q) f += (yv > e.thr[q]) ? 1 : 0;
+        ind[c] = static_cast<uint8_t>(f);
+    }
+}
+
+// Bitruncated (pluri-Gaussian) rule over two fields (Sec. 3.1), a pass of its own after both
+// fields are stored: facies rule[i * (ns + 1) + j], i = #{q : t[q] < Y1}, j = #{q : s[q] < Y2},
+// value values[facies].  The rule and the values sit in device memory.
+struct PluriEpi {
+    int nt, ns;
+    float t[GRF_MAX_THRESHOLDS];
+    float s[GRF_MAX_THRESHOLDS];
+    const uint8_t* rule;
+    const float* values;
+};
+
+// Device copy of a rule's lookup tables (bin -> facies bytes, then the facies values).
+constexpr size_t kRuleBytes = 256 + sizeof(float) * GRF_MAX_FACIES;
+hipError_t launch_rule_tables(const grf_trunc2& r, void* dst, hipStream_t s);
+hipError_t launch_pluri_epilogue(const float* y1, const float* y2, int64_t n, const PluriEpi& pe, uint8_t* facies,
+                                 float* value, hipStream_t s);
 
 // ---------------------------------------------------------------- sizes
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }

@@ -299,14 +299,7 @@ __device__ __forceinline__ void sep_tile_reg(const SepArgs& a, int64_t tx, int64
                 const int64_t y = y0 + (wm * TM + i) * 32 + 8 * (e >> 2) + 4 * (l >> 5) + (e & 3);
                 if (x < a.nx && y < a.ny) {
                     const int64_t c = plane + y * a.nx + x;
-                    const float yv = a.amp * acc[i][j][e];
-                    if (a.y) a.y[c] = yv;
-                    if (a.k) a.k[c] = expf(a.epi.mu + yv);
-                    if (a.ind) {
-                        int f = 0;
-                        for (int q = 0; q < a.epi.nthr; ++q) f += (yv > a.epi.thr[q]) ? 1 : 0;
-                        a.ind[c] = static_cast<uint8_t>(f);
-                    }
+                    epi_store(c, a.amp * acc[i][j][e], a.epi, a.y, a.k, a.ind);
                 }
             }
         }
@@ -639,13 +632,7 @@ __device__ __forceinline__ void sep_tile_dl(const SepArgs& a, int64_t tx, int64_
                     if (x < a.nx && y < a.ny) {
                         const int64_t c = plane + y * a.nx + x;
                         const float yv = a.amp * acc[zs][i][j][e];
-                        if (a.y) a.y[c] = yv;
-                        if (a.k) a.k[c] = expf(a.epi.mu + yv);
-                        if (a.ind) {
-                            int f = 0;
-                            for (int q = 0; q < a.epi.nthr; ++q) f += (yv > a.epi.thr[q]) ? 1 : 0;
-                            a.ind[c] = static_cast<uint8_t>(f);
-                        }
+                        epi_store(c, yv, a.epi, a.y, a.k, a.ind);
                     }
                 }
             }

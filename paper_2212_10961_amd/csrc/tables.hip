@@ -9,6 +9,8 @@
 // to the table format.
 #include <hip/hip_runtime.h>
 
+#include <cstring>
+
 #include "grf_internal.h"
 
 namespace grf {
@@ -157,6 +159,19 @@ __global__ __launch_bounds__(256) void k_axis_tables_batched(const AxisTableArgs
     axis_table_block(descs[w >> 40], static_cast<int64_t>(w & ((uint64_t(1) << 40) - 1)));
 }
 
+// Copies a bitruncated rule's bin -> facies table and facies values to device memory.
+struct RuleTables {
+    uint8_t rule[256];
+    float values[GRF_MAX_FACIES];
+};
+
+__global__ __launch_bounds__(256) void k_rule_tables(RuleTables r, uint8_t* rule, float* values)
+{
+    const int t = threadIdx.x;
+    rule[t] = r.rule[t];
+    if (t < GRF_MAX_FACIES) values[t] = r.values[t];
+}
+
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
@@ -209,6 +224,17 @@ hipError_t launch_axis_tables_batched(const AxisTableArgs* descs, const uint64_t
     if (total_blocks <= 0) return hipSuccess;
     if (total_blocks > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_axis_tables_batched, dim3(static_cast<unsigned>(total_blocks)), dim3(256), 0, s, descs, blk);
+    return hipGetLastError();
+}
+
+hipError_t launch_rule_tables(const grf_trunc2& r, void* dst, hipStream_t s)
+{
+    static_assert(sizeof(r.rule) <= 256, "rule table");
+    RuleTables t{};
+    std::memcpy(t.rule, r.rule, sizeof(r.rule));
+    for (int i = 0; i < r.n_values && i < GRF_MAX_FACIES; ++i) t.values[i] = r.values[i];
+    uint8_t* rule = static_cast<uint8_t*>(dst);
+    hipLaunchKernelGGL(k_rule_tables, dim3(1), dim3(256), 0, s, t, rule, reinterpret_cast<float*>(rule + 256));
     return hipGetLastError();
 }
 

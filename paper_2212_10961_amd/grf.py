@@ -26,6 +26,7 @@ from ._lib import GrfError, check
 __all__ = [
     "Modes", "make_modes", "modes_from_tables", "field_grid", "field_grid_f64", "field_points",
     "epilogue", "field_backward", "field_backward_grid", "GRFPoints", "Plan", "method_id", "sep_tiles",
+    "trunc2", "pluri_grid", "pluri_points", "pluri_apply",
     "GAUSSIAN", "EXPONENTIAL", "MATERN", "GrfError", "version", "paper_lambda_to_ell",
 ]
 
@@ -187,6 +188,89 @@ def sep_tiles(method, dim):
         check(lib.grf_sep_tile_shape(t, method_id(method), int(dim), ctypes.byref(r), ctypes.byref(c),
                                      ctypes.byref(z)))
         out.append((r.value, c.value, z.value))
+    return out
+
+
+def trunc2(t, s, rule, values=None) -> L.GrfTrunc2:
+    """Bitruncated rule (Sec. 3.1): thresholds t on Y1, s on Y2, rule[i][j] = facies of bin
+    (#{t < Y1}, #{s < Y2}) as a (len(t)+1) x (len(s)+1) array, optional facies values."""
+    r = L.GrfTrunc2()
+    t = [float(v) for v in np.atleast_1d(t)] if t is not None and len(np.atleast_1d(t)) else []
+    s = [float(v) for v in np.atleast_1d(s)] if s is not None and len(np.atleast_1d(s)) else []
+    rl = np.asarray(rule, dtype=np.uint8).reshape(-1)
+    if rl.size != (len(t) + 1) * (len(s) + 1):
+        raise ValueError("rule must have (len(t) + 1) * (len(s) + 1) entries")
+    r.n_t, r.n_s = len(t), len(s)
+    r.t = (ctypes.c_float * L.GRF_MAX_THRESHOLDS)(*(t + [0.0] * (L.GRF_MAX_THRESHOLDS - len(t))))
+    r.s = (ctypes.c_float * L.GRF_MAX_THRESHOLDS)(*(s + [0.0] * (L.GRF_MAX_THRESHOLDS - len(s))))
+    nb = (L.GRF_MAX_THRESHOLDS + 1) ** 2
+    r.rule = (ctypes.c_uint8 * nb)(*([int(v) for v in rl] + [0] * (nb - rl.size)))
+    vals = [] if values is None else [float(v) for v in np.atleast_1d(values)]
+    r.n_values = len(vals)
+    r.values = (ctypes.c_float * L.GRF_MAX_FACIES)(*(vals + [0.0] * (L.GRF_MAX_FACIES - len(vals))))
+    return r
+
+
+def _pluri_outputs(n, dev, want_facies, want_value, keep_fields, out):
+    out = dict(out or {})
+    if want_facies and "facies" not in out:
+        out["facies"] = torch.empty(n, dtype=torch.uint8, device=dev)
+    if want_value and "value" not in out:
+        out["value"] = torch.empty(n, dtype=torch.float32, device=dev)
+    if keep_fields:
+        for k in ("y1", "y2"):
+            if k not in out:
+                out[k] = torch.empty(n, dtype=torch.float32, device=dev)
+    return out
+
+
+def pluri_grid(m1: Modes, m2: Modes, shape, rule: L.GrfTrunc2, origin=None, h=None, method="direct_f32",
+               want_facies=True, want_value=False, keep_fields=False, out=None, workspace=None, stream=None):
+    """Pluri-Gaussian (bitruncated) facies on a structured grid from two independent fields."""
+    lib = L.load()
+    dev = m1.z.device
+    a, b, g = m1.c(), m2.c(), _grid(shape, origin, h)
+    meth = method_id(method)
+    cells = int(np.prod(list(shape)))
+    need = ctypes.c_size_t()
+    check(lib.eval_pluri_grid_ws_size(ctypes.byref(a), ctypes.byref(b), ctypes.byref(g), meth, ctypes.byref(need)))
+    ws = workspace if workspace is not None and workspace.numel() >= need.value else _workspace(need.value, dev)
+    out = _pluri_outputs(cells, dev, want_facies, want_value, keep_fields, out)
+    check(lib.eval_pluri_grid(ctypes.byref(a), ctypes.byref(b), ctypes.byref(g), meth, ctypes.byref(rule),
+                              _ptr(out.get("facies")), _ptr(out.get("value")), _ptr(out.get("y1")),
+                              _ptr(out.get("y2")), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+    return out
+
+
+def pluri_points(m1: Modes, m2: Modes, xyz: torch.Tensor, rule: L.GrfTrunc2, method="direct_f32",
+                 want_facies=True, want_value=False, keep_fields=False, out=None, workspace=None, stream=None):
+    """Pluri-Gaussian facies at arbitrary points xyz[P][dim] (float64, device)."""
+    lib = L.load()
+    dev = m1.z.device
+    a, b = m1.c(), m2.c()
+    meth = method_id(method)
+    xyz = xyz.contiguous()
+    P = int(xyz.shape[0])
+    need = ctypes.c_size_t()
+    check(lib.eval_pluri_points_ws_size(ctypes.byref(a), ctypes.byref(b), P, meth, ctypes.byref(need)))
+    ws = workspace if workspace is not None and workspace.numel() >= need.value else _workspace(need.value, dev)
+    out = _pluri_outputs(P, dev, want_facies, want_value, keep_fields, out)
+    check(lib.eval_pluri_points(ctypes.byref(a), ctypes.byref(b), ctypes.c_void_p(xyz.data_ptr()), P, meth,
+                                ctypes.byref(rule), _ptr(out.get("facies")), _ptr(out.get("value")),
+                                _ptr(out.get("y1")), _ptr(out.get("y2")), ctypes.c_void_p(ws.data_ptr()),
+                                ws.numel(), _stream(stream)))
+    return out
+
+
+def pluri_apply(y1: torch.Tensor, y2: torch.Tensor, rule: L.GrfTrunc2, want_facies=True, want_value=False,
+                out=None, stream=None):
+    """The bitruncated rule over two existing fields (stand-alone, memory-bound form)."""
+    lib = L.load()
+    n = int(y1.numel())
+    out = _pluri_outputs(n, y1.device, want_facies, want_value, False, out)
+    ws = _workspace(L.GRF_PLURI_APPLY_WS_BYTES, y1.device)
+    check(lib.pluri_apply(_ptr(y1), _ptr(y2), n, ctypes.byref(rule), _ptr(out.get("facies")),
+                          _ptr(out.get("value")), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
     return out
 
 

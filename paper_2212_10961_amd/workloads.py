@@ -20,6 +20,12 @@ truncated fields, Sec. 3.1; anisotropic correlation lengths, Sec. 4.1):
                       master seed 4, modes seed 4000+i
 ``adjoint_grid3d_128`` 3-D 128^3, exponential ell=(12,12,3), sigma^2=1, N=4096,
                       model seed 5, target seed 50, 10,000 distinct observation cells (seed 51)
+``pluri_2d_1024x512`` bitruncated (pluri-Gaussian) facies on the 1024x512 grid of a 2x1
+                      domain (the grid of the paper's Horton-Rogers-Lapwood case, Sec. 5.3):
+                      Y1 Gaussian ell=(0.2,0.05), sigma^2=2 (that case's log-normal field),
+                      Y2 exponential ell=(0.1,0.1), sigma^2=1, N=4096 each, seeds 6 and 7;
+                      thresholds t=(-1,0,1) on Y1, s=(-0.5,0.5) on Y2, the 4 x 3 bins merged
+                      into four facies as in the truncation-rule example of Sec. 3.1
 """
 from __future__ import annotations
 
@@ -38,6 +44,12 @@ WORKLOADS = {
                             point_seed=31, threshold=0.5),
     "batch512_2d": dict(dim=2, n_instances=512, side_lo=64, side_hi=1024, ell_lo=4.0, ell_hi=64.0,
                         sigma2=1.0, mu=0.0, n_modes=2048, seed=4),
+    "pluri_2d_1024x512": dict(dim=2, shape=(1024, 512), h=(2.0 / 1024, 1.0 / 512), origin=(0.0, 0.0),
+                              fields=(dict(cov=GAUSSIAN, ell=(0.2, 0.05), sigma2=2.0, seed=6),
+                                      dict(cov=EXPONENTIAL, ell=(0.1, 0.1), sigma2=1.0, seed=7)),
+                              n_modes=4096, t=(-1.0, 0.0, 1.0), s=(-0.5, 0.5),
+                              rule=((0, 0, 1), (2, 3, 1), (2, 3, 1), (2, 2, 1)),
+                              values=(1e-12, 5e-11, 2e-13, 7e-10)),
     "adjoint_grid3d_128": dict(dim=3, shape=(128, 128, 128), h=(1.0, 1.0, 1.0), origin=(0.0, 0.0, 0.0),
                                cov=EXPONENTIAL, ell=(12.0, 12.0, 3.0), sigma2=1.0, mu=0.0,
                                n_modes=4096, seed=5, target_seed=50, obs_seed=51, n_obs=10_000),

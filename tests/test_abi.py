@@ -274,3 +274,55 @@ def test_epilogue_and_backward_validation(lib):
     assert lib.field_backward(ctypes.byref(m), ctypes.c_void_p(16), 1000, ctypes.c_void_p(16), None,
                               ctypes.c_void_p(16), None, None, None, ctypes.c_void_p(16), b.value - 1,
                               None) == L.GRF_ENOMEM
+
+
+def _trunc(nt=1, ns=1, rule=None, nv=0, **kw):
+    r = L.GrfTrunc2()
+    r.n_t, r.n_s, r.n_values = nt, ns, nv
+    for i in range(min(nt, L.GRF_MAX_THRESHOLDS)):
+        r.t[i] = float(i)
+    for i in range(min(ns, L.GRF_MAX_THRESHOLDS)):
+        r.s[i] = float(i)
+    for i, v in enumerate(rule if rule is not None else range(min((nt + 1) * (ns + 1), 256))):
+        r.rule[i] = v % 256
+    for k, v in kw.items():
+        setattr(r, k, v)
+    return r
+
+
+def test_pluri_validation(lib):
+    m1, m2, g = _modes(), _modes(), _grid()
+    need = ctypes.c_size_t()
+    assert lib.eval_pluri_grid_ws_size(ctypes.byref(m1), ctypes.byref(m2), ctypes.byref(g), 0,
+                                       ctypes.byref(need)) == 0
+    single = ctypes.c_size_t()
+    assert lib.eval_field_grid_ws_size(ctypes.byref(m1), ctypes.byref(g), 0, ctypes.byref(single)) == 0
+    assert need.value >= single.value + 8 * 8 * 8 * 4  # tables + the first field + the rule
+    dev, big = ctypes.c_void_p(16), 1 << 30
+    r = _trunc()
+
+    def call(a=m1, b=m2, rule=r, fac=dev, val=None, ws=dev, wsb=big, meth=0):
+        return lib.eval_pluri_grid(ctypes.byref(a), ctypes.byref(b), ctypes.byref(g), meth,
+                                   ctypes.byref(rule) if rule is not None else None, fac, val, None, None, ws, wsb,
+                                   None)
+
+    assert call(b=_modes(dim=2)) == L.GRF_EINVAL                  # dims differ
+    assert call(fac=None, val=None) == L.GRF_EINVAL                # no output
+    assert call(rule=None) == L.GRF_EINVAL
+    assert call(rule=_trunc(nt=16)) == L.GRF_EINVAL
+    bad = _trunc(nt=2)
+    bad.t[0], bad.t[1] = 1.0, 0.0
+    assert call(rule=bad) == L.GRF_EINVAL                          # unsorted
+    assert call(rule=_trunc(nv=2), val=dev) == L.GRF_EINVAL        # rule names facies 3 > 2 values
+    assert call(rule=_trunc(nv=65)) == L.GRF_EINVAL
+    assert call(wsb=need.value - 1) == L.GRF_ENOMEM
+    assert call(meth=9) == L.GRF_EINVAL
+    # points and the stand-alone rule
+    assert lib.eval_pluri_points(ctypes.byref(m1), ctypes.byref(m2), dev, 10, 2, ctypes.byref(r), dev, None, None,
+                                 None, dev, big, None) == L.GRF_EUNSUPPORTED
+    assert lib.eval_pluri_points(ctypes.byref(m1), ctypes.byref(m2), dev, 0, 0, ctypes.byref(r), dev, None, None,
+                                 None, dev, big, None) == 0
+    assert lib.pluri_apply(dev, dev, 10, ctypes.byref(r), dev, None, dev, L.GRF_PLURI_APPLY_WS_BYTES - 1,
+                           None) == L.GRF_ENOMEM
+    assert lib.pluri_apply(dev, None, 10, ctypes.byref(r), dev, None, dev, 4096, None) == L.GRF_EINVAL
+    assert lib.pluri_apply(dev, dev, 0, ctypes.byref(r), dev, None, None, 0, None) == 0

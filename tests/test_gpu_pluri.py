@@ -1,0 +1,142 @@
+"""GPU parity of the bitruncated (pluri-Gaussian) facies path (Sec. 3.1) against the oracle.
+
+Both fields come from each side's own sampler (same seeds); facies must equal the oracle's
+exactly except in cells where Y1 or Y2 lies within the path's stated error band of a
+threshold (there, the facies of any bin the band reaches is accepted).
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import TOL, assert_field, modes_pair, to_np
+from paper_2212_10961_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+T, S = [-1.0, 0.0, 1.0], [-0.5, 0.5]
+RULE = np.array([[0, 0, 1], [2, 3, 1], [2, 3, 1], [2, 2, 1]], dtype=np.uint8)
+VALUES = np.array([1e-12, 5e-11, 2e-13, 7e-10], dtype=np.float32)
+
+
+@pytest.fixture(scope="module")
+def grf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2212_10961_amd.grf as g
+    return g
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _check_facies(orc, fac, val, r1, r2, s1, s2, meth):
+    """Exact outside the band; inside, the facies of one of the bins the band reaches."""
+    want, _ = orc.pluri(r1, r2, T, S, RULE)
+    b1, b2 = TOL[meth]["band"] * s1, TOL[meth]["band"] * s2
+    ok = fac == want
+    cand = np.zeros_like(ok)
+    for d1 in (-b1, 0.0, b1):
+        for d2 in (-b2, 0.0, b2):
+            f, _ = orc.pluri(r1 + d1, r2 + d2, T, S, RULE)
+            cand |= fac == f
+    near = (np.min(np.abs(r1[:, None] - np.array(T)[None, :]), axis=1) <= b1) | \
+           (np.min(np.abs(r2[:, None] - np.array(S)[None, :]), axis=1) <= b2)
+    assert np.all(ok | (near & cand)), f"{np.sum(~ok & ~near)} mismatches outside the band"
+    if val is not None:
+        np.testing.assert_array_equal(val, VALUES[fac])
+    return int(np.sum(~ok))
+
+
+@pytest.mark.parametrize("meth", ["direct_f32", "sep_f16", "sep_f16_x3"])
+def test_pluri_grid2d_ragged(orc, grf, meth):
+    shape, h, o = (300, 170), (0.01, 0.02), (0.5, -1.0)
+    s1, s2 = math.sqrt(2.0), 1.0
+    _say(f"case pluri_grid2d {shape} {meth}")
+    (z1o, p1o), m1 = modes_pair(orc, grf, 2, wl.GAUSSIAN, 300, 61, s1, (0.2, 0.05))
+    (z2o, p2o), m2 = modes_pair(orc, grf, 2, wl.EXPONENTIAL, 300, 62, s2, (0.1, 0.1))
+    r1 = orc.field_grid(z1o, p1o, s1, (0.2, 0.05), shape, origin=o, h=h)
+    r2 = orc.field_grid(z2o, p2o, s2, (0.1, 0.1), shape, origin=o, h=h)
+    rule = grf.trunc2(T, S, RULE, VALUES)
+    out = grf.pluri_grid(m1, m2, shape, rule, origin=o, h=h, method=meth, want_value=True, keep_fields=True)
+    assert_field(to_np(out["y1"]), r1, s1, meth, "pluri y1")
+    assert_field(to_np(out["y2"]), r2, s2, meth, "pluri y2")
+    nb = _check_facies(orc, to_np(out["facies"]), to_np(out["value"]), r1, r2, s1, s2, meth)
+    _say(f"  in-band differences: {nb}")
+    # without keeping the fields (workspace path) the facies are identical
+    out2 = grf.pluri_grid(m1, m2, shape, rule, origin=o, h=h, method=meth)
+    np.testing.assert_array_equal(to_np(out2["facies"]), to_np(out["facies"]))
+
+
+def test_pluri_grid3d_sep(orc, grf):
+    shape, ell = (70, 45, 9), (6.0, 5.0, 2.0)
+    _say(f"case pluri_grid3d {shape} sep_f16")
+    (z1o, p1o), m1 = modes_pair(orc, grf, 3, wl.EXPONENTIAL, 128, 63, 1.0, ell)
+    (z2o, p2o), m2 = modes_pair(orc, grf, 3, wl.GAUSSIAN, 128, 64, 1.0, ell)
+    r1 = orc.field_grid(z1o, p1o, 1.0, ell, shape)
+    r2 = orc.field_grid(z2o, p2o, 1.0, ell, shape)
+    out = grf.pluri_grid(m1, m2, shape, grf.trunc2(T, S, RULE), method="sep_f16")
+    _check_facies(orc, to_np(out["facies"]), None, r1, r2, 1.0, 1.0, "sep_f16")
+
+
+def test_pluri_points(orc, grf):
+    _say("case pluri_points 5000 direct_f32")
+    x = wl.points_uniform(5000, (100.0, 100.0, 10.0), 65)
+    (z1o, p1o), m1 = modes_pair(orc, grf, 3, wl.GAUSSIAN, 256, 66, 1.2, (10.0, 10.0, 2.0))
+    (z2o, p2o), m2 = modes_pair(orc, grf, 3, wl.EXPONENTIAL, 256, 67, 0.8, (5.0, 20.0, 1.0))
+    r1 = orc.field_points(z1o, p1o, 1.2, (10.0, 10.0, 2.0), x)
+    r2 = orc.field_points(z2o, p2o, 0.8, (5.0, 20.0, 1.0), x)
+    out = grf.pluri_points(m1, m2, torch.from_numpy(x).cuda(), grf.trunc2(T, S, RULE, VALUES), want_value=True,
+                           keep_fields=True)
+    assert_field(to_np(out["y1"]), r1, 1.2, "direct_f32", "pluri points y1")
+    _check_facies(orc, to_np(out["facies"]), to_np(out["value"]), r1, r2, 1.2, 0.8, "direct_f32")
+
+
+@pytest.mark.parametrize("n", [0, 1, 7, 4099, 1_000_003])
+def test_pluri_apply_exact(orc, grf, n):
+    """The stand-alone rule decides in FP32 on the given values: bit-exact with the definition
+    evaluated on the same FP32 numbers (thresholds are exact in FP32)."""
+    _say(f"case pluri_apply n={n}")
+    g = torch.Generator().manual_seed(n + 5)
+    y1 = (torch.randn(n, generator=g) * 1.5).cuda()
+    y2 = torch.randn(n, generator=g).cuda()
+    if n > 10:  # values exactly on thresholds go to the lower bin
+        y1[:3] = torch.tensor([-1.0, 0.0, 1.0])
+        y2[3:5] = torch.tensor([-0.5, 0.5])
+    out = grf.pluri_apply(y1, y2, grf.trunc2(T, S, RULE, VALUES), want_value=True)
+    want, _ = orc.pluri(to_np(y1).astype(np.float64), to_np(y2).astype(np.float64), T, S, RULE)
+    np.testing.assert_array_equal(to_np(out["facies"]), want)
+    np.testing.assert_array_equal(to_np(out["value"]), VALUES[want])
+
+
+def test_single_truncation_through_the_rule(orc, grf):
+    """With no second thresholds the rule is the single truncation of the field epilogue."""
+    _say("case pluri single truncation")
+    (zo, po), m = modes_pair(orc, grf, 2, wl.GAUSSIAN, 200, 68, 1.0, (8.0, 8.0))
+    shape = (128, 96)
+    ind = to_np(grf.field_grid(m, shape, method="direct_f32", thresholds=T, want_y=False, want_ind=True)["ind"])
+    out = grf.pluri_grid(m, m, shape, grf.trunc2(T, [], [0, 1, 2, 3]), method="direct_f32")
+    np.testing.assert_array_equal(to_np(out["facies"]), ind)
+
+
+def test_pluri_proportions_workload(orc, grf):
+    """Facies proportions of the 1024x512 workload over realisations match the product formula
+    of Sec. 3.1 (independent fields, thresholds on N(0, sigma^2))."""
+    c = wl.WORKLOADS["pluri_2d_1024x512"]
+    f1, f2 = c["fields"]
+    rule = grf.trunc2(c["t"], c["s"], c["rule"], c["values"])
+    R = 16
+    fr = np.empty((R, 4))
+    for r in range(R):
+        z1, p1 = grf.make_modes(2, f1["cov"], c["n_modes"], f1["seed"] + 1000 * r)
+        z2, p2 = grf.make_modes(2, f2["cov"], c["n_modes"], f2["seed"] + 1000 * r)
+        m1 = grf.modes_from_tables(z1, p1, math.sqrt(f1["sigma2"]), f1["ell"])
+        m2 = grf.modes_from_tables(z2, p2, math.sqrt(f2["sigma2"]), f2["ell"])
+        fac = grf.pluri_grid(m1, m2, c["shape"], rule, h=c["h"], method="sep_f16")["facies"]
+        fr[r] = to_np(torch.bincount(fac.long(), minlength=4).double() / fac.numel())
+    want = orc.pluri_proportions(c["t"], f1["sigma2"], c["s"], f2["sigma2"], np.array(c["rule"]), 4)
+    se = fr.std(axis=0) / math.sqrt(R)
+    _say(f"  proportions {fr.mean(axis=0)} vs {want} (se {se})")
+    assert np.all(np.abs(fr.mean(axis=0) - want) < 4.5 * se + 3e-3)
