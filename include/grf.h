@@ -79,15 +79,24 @@ typedef struct grf_spec {
     double nu;              /* Matern smoothness; 2*nu must be an integer in [1, 64] */
 } grf_spec;
 
-/* A mode table in device memory plus the scalars that enter the field. */
+/* A mode table in device memory plus the scalars that enter the field.
+ * Anisotropy: k_j = z_j / ell per axis (Sec. 4.1), or with rotated = 1 the general map
+ * k_j = rot diag(1/ell) z_j (the extension to rotations and general transformation
+ * matrices named in Sec. 4.1 and in the conclusions, Sec. 6).  With an orthonormal rot the
+ * covariance's principal axes are the columns of rot, with correlation lengths ell.
+ * Evaluations of a rotated table need dim * n * 8 more workspace bytes (included in every
+ * *_ws_size); the batched path does not take rotated tables (GRF_EUNSUPPORTED). */
 typedef struct grf_modes {
     int32_t dim;        /* 2 or 3 */
     int32_t pad_;
     int64_t n;          /* number of modes N >= 1 */
-    const double* z;    /* device, [dim][n]: standardised wavevectors, k = z / ell */
+    const double* z;    /* device, [dim][n]: standardised wavevectors */
     const double* phi;  /* device, [n]: phases in radians */
     double sigma;       /* standard deviation, amplitude = sigma * sqrt(2 / N) */
     double ell[3];      /* correlation lengths (> 0) */
+    int32_t rotated;    /* 0 or 1 */
+    int32_t pad2_;
+    double rot[9];      /* row-major 3 x 3 (dim 2 uses the upper-left 2 x 2 block); finite */
 } grf_modes;
 
 /* Structured grid: centres origin + (i + 1/2) h, x index fastest; n[2] = 1 for dim 2. */
@@ -122,6 +131,19 @@ const char* grf_last_error(void);
  * shorter table.  Does not touch the GPU.
  */
 int make_modes(const grf_spec* spec, double* z_out, double* phi_out);
+
+/*
+ * snap_periodic -- the "periodic" option of App. B: every wavevector is moved to the nearest
+ * point of the lattice of a box with periods L_a, k_a = 2 pi m_a / L_a with
+ * m_a = round(k_a L_a / (2 pi)) (halves away from zero), along each axis with
+ * period[a] > 0 (other axes untouched), where k = rot diag(1/ell) z (rot = NULL: identity;
+ * else row-major 3 x 3, dim 2 uses the upper-left block, orthonormal to 1e-9).  The result
+ * is returned standardised, z_out = diag(ell) rot^T k, so that a table with these ell and
+ * rot evaluates the snapped k; the field then repeats with period L_a along axis a.
+ * Host arrays: z, z_out [dim][n] (may alias), ell [dim] > 0, period [dim].  No GPU work.
+ */
+int snap_periodic(int dim, int64_t n, const double* z, const double* ell, const double* rot, const double* period,
+                  double* z_out);
 
 /* Device workspace (bytes) that eval_field_grid needs for this problem and method. */
 int eval_field_grid_ws_size(const grf_modes* modes, const grf_grid* grid, int method, size_t* bytes);

@@ -84,9 +84,15 @@ __device__ inline float block_sum(float v, float* sh)
 }
 
 // Per-mode reduction over chunks (fixed order) and per-block partials of the scalar sums.
+// ell-gradient weights: dk_a / dell_b = -R_ab z_b / ell_b^2 (R = identity for axis-aligned tables).
+struct EllMap {
+    double r[9];  // row-major 3 x 3
+    double ell[3];
+};
+
 __global__ __launch_bounds__(256) void k_bwd_reduce(const float* __restrict__ partial, int64_t nch, int64_t n,
                                                    int64_t ldp, int dim, float amp, const double* __restrict__ z,
-                                                   double ell0, double ell1, double ell2, float* __restrict__ gphi,
+                                                   EllMap em, float* __restrict__ gphi,
                                                    float* __restrict__ gk, float* __restrict__ scal)
 {
     __shared__ float sh[4];
@@ -103,11 +109,21 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(const float* __restrict__ pa
             C += pc[4 * ldp + j];
         }
         if (gphi) gphi[j] = -amp * S;
-        const double ell[3] = {ell0, ell1, ell2};
-        for (int a = 0; a < dim; ++a) {
-            const float gka = -amp * U[a];
-            if (gk) gk[a * n + j] = gka;
-            tl[a] = static_cast<float>(static_cast<double>(gka) * (-z[a * n + j] / (ell[a] * ell[a])));
+        float gka[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            if (a >= dim) break;
+            gka[a] = -amp * U[a];
+            if (gk) gk[a * n + j] = gka[a];
+        }
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            if (b >= dim) break;
+            double w = 0.0;
+#pragma unroll
+            for (int a = 0; a < 3; ++a)
+                if (a < dim) w += static_cast<double>(gka[a]) * em.r[3 * a + b];
+            tl[b] = static_cast<float>(w * (-z[b * n + j] / (em.ell[b] * em.ell[b])));
         }
         tc = C;
     }
@@ -290,8 +306,11 @@ hipError_t launch_backward(const BwdArgs& a, hipStream_t s)
     if (e != hipSuccess) return e;
 
     const int nblk = static_cast<int>((a.n + 255) / 256);
+    EllMap em{};
+    for (int i = 0; i < 9; ++i) em.r[i] = a.rot ? a.rot[i] : (i % 4 == 0 ? 1.0 : 0.0);
+    for (int b = 0; b < 3; ++b) em.ell[b] = b < a.dim ? a.ell[b] : 1.0;
     hipLaunchKernelGGL(k_bwd_reduce, dim3(nblk), dim3(256), 0, s, a.partial, a.nchunks, a.n, a.ldp, a.dim, a.amp, a.z,
-                       a.ell[0], a.ell[1], a.dim == 3 ? a.ell[2] : 1.0, a.gphi, a.gk, a.scal_partial);
+                       em, a.gphi, a.gk, a.scal_partial);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const float* dotp = nullptr;

@@ -78,7 +78,24 @@ int check_modes(const grf_modes* m, const char* fn)
     for (int a = 0; a < m->dim; ++a)
         if (!(m->ell[a] > 0.0) || !std::isfinite(m->ell[a]))
             return fail(GRF_EINVAL, "%s: ell[%d] must be finite and > 0", fn, a);
+    if (m->rotated != 0 && m->rotated != 1) return fail(GRF_EINVAL, "%s: rotated must be 0 or 1", fn);
+    if (m->rotated)
+        for (int i = 0; i < 9; ++i)
+            if (!std::isfinite(m->rot[i])) return fail(GRF_EINVAL, "%s: rot must be finite", fn);
     return GRF_OK;
+}
+
+// Axis-aligned view of a table: a rotated table's wavevectors k = R diag(1/ell) z go to
+// `kbuf` (rot_ws_bytes(m) bytes of device workspace) and are evaluated as z' = k, ell' = 1.
+hipError_t aligned_modes(const grf_modes* m, void* kbuf, hipStream_t s, grf_modes* out)
+{
+    *out = *m;
+    if (!m->rotated) return hipSuccess;
+    const hipError_t e = launch_rotate_modes(m->z, m->dim, m->n, m->rot, m->ell, static_cast<double*>(kbuf), s);
+    out->z = static_cast<const double*>(kbuf);
+    out->ell[0] = out->ell[1] = out->ell[2] = 1.0;
+    out->rotated = 0;
+    return e;
 }
 
 int check_grid(const grf_grid* g, int dim, const char* fn)
@@ -262,7 +279,7 @@ int eval_field_grid_ws_size(const grf_modes* modes, const grf_grid* grid, int me
     method = resolve_grid_method(method, grid);
     if (method < GRF_DIRECT_F32 || method > GRF_SEP_F16_X3)
         return fail(GRF_EINVAL, "eval_field_grid_ws_size: unknown method %d", method);
-    *bytes = grid_ws(modes, grid, method, nullptr).bytes;
+    *bytes = rot_ws_bytes(modes) + grid_ws(modes, grid, method, nullptr).bytes;
     return GRF_OK;
 }
 
@@ -334,10 +351,14 @@ static int grid_eval(const char* fn, const grf_modes* modes, const grf_grid* gri
     if (!y && !k && !ind) return fail(GRF_EINVAL, "%s: no output requested", fn);
     if ((rc = check_epi(epi, k, ind, fn))) return rc;
     if ((rc = check_grid_method(fn, grid, &method, tile))) return rc;
-    const GridWs need = grid_ws(modes, grid, method, nullptr);
-    if (ws_bytes < need.bytes || (!ws && need.bytes))
-        return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need.bytes, ws_bytes);
-    return grid_launch(modes, grid, method, tile, make_epi(epi), y, k, ind, ws, static_cast<hipStream_t>(stream));
+    const size_t rb = rot_ws_bytes(modes);
+    const size_t need = rb + grid_ws(modes, grid, method, nullptr).bytes;
+    if (ws_bytes < need || (!ws && need))
+        return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    grf_modes am;
+    GRF_HIP(aligned_modes(modes, ws, s, &am));
+    return grid_launch(&am, grid, method, tile, make_epi(epi), y, k, ind, static_cast<char*>(ws) + rb, s);
 }
 
 // ---------------------------------------------------------------- bitruncated (pluri-Gaussian) rule
@@ -394,7 +415,7 @@ static size_t pluri_grid_ws(const grf_modes* m1, const grf_modes* m2, const grf_
     const int64_t C = g->n[0] * g->n[1] * g->n[2];
     const size_t t = std::max(grid_ws(m1, g, method, nullptr).bytes, grid_ws(m2, g, method, nullptr).bytes);
     const size_t f = align256(sizeof(float) * size_t(C));
-    return align256(kRuleBytes) + (own_y1 ? f : 0) + (own_y2 ? f : 0) + t;
+    return align256(kRuleBytes) + rot_ws_bytes(m1) + rot_ws_bytes(m2) + (own_y1 ? f : 0) + (own_y2 ? f : 0) + t;
 }
 
 }  // namespace grf
@@ -431,12 +452,19 @@ int eval_pluri_grid(const grf_modes* m1, const grf_modes* m2, const grf_grid* gr
     const int64_t C = grid->n[0] * grid->n[1] * grid->n[2];
     Carve c(ws);
     uint8_t* rt = c.take<uint8_t>(kRuleBytes);
+    void* k1 = c.base + c.used;
+    c.used += rot_ws_bytes(m1);
+    void* k2 = c.base + c.used;
+    c.used += rot_ws_bytes(m2);
     float* f1 = y1 ? y1 : c.take<float>(size_t(C));
     float* f2 = y2 ? y2 : c.take<float>(size_t(C));
     void* tabs = c.base + c.used;
+    grf_modes a1, a2;
+    GRF_HIP(aligned_modes(m1, k1, s, &a1));
+    GRF_HIP(aligned_modes(m2, k2, s, &a2));
     GRF_HIP(launch_rule_tables(*rule, rt, s));
-    if ((rc = grid_launch(m1, grid, method, -1, Epi{}, f1, nullptr, nullptr, tabs, s))) return rc;
-    if ((rc = grid_launch(m2, grid, method, -1, Epi{}, f2, nullptr, nullptr, tabs, s))) return rc;
+    if ((rc = grid_launch(&a1, grid, method, -1, Epi{}, f1, nullptr, nullptr, tabs, s))) return rc;
+    if ((rc = grid_launch(&a2, grid, method, -1, Epi{}, f2, nullptr, nullptr, tabs, s))) return rc;
     GRF_HIP(launch_pluri_epilogue(f1, f2, C, make_pluri(rule, rt), facies, value, s));
     return GRF_OK;
 }
@@ -503,7 +531,7 @@ int eval_pluri_points_ws_size(const grf_modes* m1, const grf_modes* m2, int64_t 
     if (!bytes) return fail(GRF_EINVAL, "%s: bytes is NULL", fn);
     if (n_points < 0) return fail(GRF_EINVAL, "%s: n_points < 0", fn);
     if ((rc = check_points_method(fn, &method))) return rc;
-    *bytes = align256(kRuleBytes) + 2 * align256(sizeof(float) * size_t(n_points)) +
+    *bytes = align256(kRuleBytes) + rot_ws_bytes(m1) + rot_ws_bytes(m2) + 2 * align256(sizeof(float) * size_t(n_points)) +
              std::max(points_ws_bytes(m1->n, n_points, method), points_ws_bytes(m2->n, n_points, method));
     return GRF_OK;
 }
@@ -523,18 +551,25 @@ int eval_pluri_points(const grf_modes* m1, const grf_modes* m2, const double* xy
     if (!facies && !value) return fail(GRF_EINVAL, "%s: facies or value output required", fn);
     if (!xyz) return fail(GRF_EINVAL, "%s: xyz is NULL", fn);
     const size_t fb = align256(sizeof(float) * size_t(n_points));
-    const size_t need = align256(kRuleBytes) + (y1 ? 0 : fb) + (y2 ? 0 : fb) +
+    const size_t need = align256(kRuleBytes) + rot_ws_bytes(m1) + rot_ws_bytes(m2) + (y1 ? 0 : fb) + (y2 ? 0 : fb) +
                         std::max(points_ws_bytes(m1->n, n_points, method), points_ws_bytes(m2->n, n_points, method));
     if (!ws || ws_bytes < need) return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
     hipStream_t s = static_cast<hipStream_t>(stream);
     Carve c(ws);
     uint8_t* rt = c.take<uint8_t>(kRuleBytes);
+    void* k1 = c.base + c.used;
+    c.used += rot_ws_bytes(m1);
+    void* k2 = c.base + c.used;
+    c.used += rot_ws_bytes(m2);
     float* f1 = y1 ? y1 : c.take<float>(size_t(n_points));
     float* f2 = y2 ? y2 : c.take<float>(size_t(n_points));
     void* rest = c.base + c.used;
+    grf_modes a1, a2;
+    GRF_HIP(aligned_modes(m1, k1, s, &a1));
+    GRF_HIP(aligned_modes(m2, k2, s, &a2));
     GRF_HIP(launch_rule_tables(*rule, rt, s));
-    if ((rc = points_launch(m1, xyz, n_points, method, Epi{}, f1, nullptr, nullptr, rest, s))) return rc;
-    if ((rc = points_launch(m2, xyz, n_points, method, Epi{}, f2, nullptr, nullptr, rest, s))) return rc;
+    if ((rc = points_launch(&a1, xyz, n_points, method, Epi{}, f1, nullptr, nullptr, rest, s))) return rc;
+    if ((rc = points_launch(&a2, xyz, n_points, method, Epi{}, f2, nullptr, nullptr, rest, s))) return rc;
     GRF_HIP(launch_pluri_epilogue(f1, f2, n_points, make_pluri(rule, rt), facies, value, s));
     return GRF_OK;
 }
@@ -581,12 +616,15 @@ int eval_field_grid_f64(const grf_modes* modes, const grf_grid* grid, double mu,
     if ((rc = check_grid(grid, modes->dim, fn))) return rc;
     if (!y64 && !k64) return fail(GRF_EINVAL, "%s: no output requested", fn);
     if (!std::isfinite(mu)) return fail(GRF_EINVAL, "%s: mu must be finite", fn);
-    const GridWs need = grid_ws(modes, grid, GRF_DIRECT_F64, nullptr);
-    if (ws_bytes < need.bytes || !ws)
-        return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need.bytes, ws_bytes);
+    const size_t rb = rot_ws_bytes(modes);
+    const size_t need = rb + grid_ws(modes, grid, GRF_DIRECT_F64, nullptr).bytes;
+    if (ws_bytes < need || !ws)
+        return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
     hipStream_t s = static_cast<hipStream_t>(stream);
-    const GridWs w = grid_ws(modes, grid, GRF_DIRECT_F64, ws);
-    GRF_HIP(build_tables(modes, grid, GRF_DIRECT_F64, w, s));
+    grf_modes am;
+    GRF_HIP(aligned_modes(modes, ws, s, &am));
+    const GridWs w = grid_ws(&am, grid, GRF_DIRECT_F64, static_cast<char*>(ws) + rb);
+    GRF_HIP(build_tables(&am, grid, GRF_DIRECT_F64, w, s));
     const double amp64 = modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n));
     GRF_HIP(launch_direct_grid_f64(static_cast<const double*>(w.t[0]), static_cast<const double*>(w.t[1]),
                                    static_cast<const double*>(w.t[2]), modes->n, padded_modes(modes->n),
@@ -604,7 +642,7 @@ int eval_field_points_ws_size(const grf_modes* modes, int64_t n_points, int meth
     if (is_sep(method)) return fail(GRF_EUNSUPPORTED, "eval_field_points_ws_size: separable methods need a grid");
     if (method != GRF_DIRECT_F32 && method != GRF_DIRECT_F64)
         return fail(GRF_EINVAL, "eval_field_points_ws_size: unknown method %d", method);
-    *bytes = points_ws_bytes(modes->n, n_points, method);
+    *bytes = rot_ws_bytes(modes) + points_ws_bytes(modes->n, n_points, method);
     return GRF_OK;
 }
 
@@ -622,9 +660,13 @@ int eval_field_points(const grf_modes* modes, const double* xyz, int64_t n_point
     if (n_points == 0) return GRF_OK;
     if (!y && !k && !ind) return fail(GRF_EINVAL, "%s: no output requested", fn);
     if (!xyz) return fail(GRF_EINVAL, "%s: xyz is NULL", fn);
-    const size_t need = points_ws_bytes(modes->n, n_points, method);
+    const size_t rb = rot_ws_bytes(modes);
+    const size_t need = rb + points_ws_bytes(modes->n, n_points, method);
     if (!ws || ws_bytes < need) return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
-    return points_launch(modes, xyz, n_points, method, make_epi(epi), y, k, ind, ws, static_cast<hipStream_t>(stream));
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    grf_modes am;
+    GRF_HIP(aligned_modes(modes, ws, s, &am));
+    return points_launch(&am, xyz, n_points, method, make_epi(epi), y, k, ind, static_cast<char*>(ws) + rb, s);
 }
 
 int epilogue_apply(const float* y, int64_t n, const grf_epi* epi, float* k, uint8_t* ind, void* stream)
@@ -650,7 +692,7 @@ int field_backward_ws_size(const grf_modes* modes, int64_t n_points, size_t* byt
     if (n_points < 0) return fail(GRF_EINVAL, "field_backward_ws_size: n_points < 0");
     const int64_t ldp = padded_modes(modes->n);
     const int64_t nch = bwd_chunks(n_points);
-    *bytes = align256(sizeof(double) * 4 * ldp) + align256(sizeof(float) * 5 * ldp * nch) +
+    *bytes = rot_ws_bytes(modes) + align256(sizeof(double) * 4 * ldp) + align256(sizeof(float) * 5 * ldp * nch) +
              align256(sizeof(float) * bwd_scal_floats(modes->n));
     return GRF_OK;
 }
@@ -670,14 +712,18 @@ static int backward_common(const char* fn, const grf_modes* modes, const double*
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int64_t ldp = padded_modes(modes->n);
     Carve c(ws);
+    void* kbuf = c.base;
+    c.used += rot_ws_bytes(modes);
     double* params = c.take<double>(4 * ldp);
     float* partial = c.take<float>(5 * ldp * bwd_chunks(P));
     float* scal = c.take<float>(bwd_scal_floats(modes->n));
-    GRF_HIP(launch_mode_params(modes->z, modes->phi, modes->dim, modes->n, ldp, modes->ell, params, s));
+    grf_modes am;  // sums run on k itself; grad_ell maps back through the original table
+    GRF_HIP(aligned_modes(modes, kbuf, s, &am));
+    GRF_HIP(launch_mode_params(am.z, am.phi, am.dim, am.n, ldp, am.ell, params, s));
     GridWs tabs;
     if (grid) {  // per-axis FP32 revolution tables of the direct method
-        tabs = grid_ws(modes, grid, GRF_DIRECT_F32, c.base + c.used);
-        GRF_HIP(build_tables(modes, grid, GRF_DIRECT_F32, tabs, s));
+        tabs = grid_ws(&am, grid, GRF_DIRECT_F32, c.base + c.used);
+        GRF_HIP(build_tables(&am, grid, GRF_DIRECT_F32, tabs, s));
     }
     BwdArgs a{};
     a.tx = static_cast<const float*>(tabs.t[0]);
@@ -698,6 +744,7 @@ static int backward_common(const char* fn, const grf_modes* modes, const double*
     a.sigma = static_cast<float>(modes->sigma);
     a.ell = modes->ell;
     a.z = modes->z;
+    a.rot = modes->rotated ? modes->rot : nullptr;
     a.gphi = grad_phi;
     a.gk = grad_k;
     a.gsigma = grad_sigma;

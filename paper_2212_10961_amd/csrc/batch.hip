@@ -460,6 +460,9 @@ int eval_field_batch(grf_plan* p, const grf_batch_item* items, int32_t n, void* 
         if ((rc = check_modes(&items[i].modes, fn))) return rc;
         if ((rc = check_grid(&items[i].grid, items[i].modes.dim, fn))) return rc;
         if (!items[i].y) return fail(GRF_EINVAL, "%s: item %d has no output", fn, i);
+        if (items[i].modes.rotated)
+            return fail(GRF_EUNSUPPORTED, "%s: item %d: rotated tables are not batched (pass k = rot diag(1/ell) z "
+                        "as an axis-aligned table with ell = 1)", fn, i);
         if (is_sep(p->method) && items[i].modes.dim != items[0].modes.dim)
             return fail(GRF_EUNSUPPORTED, "%s: separable batches must not mix 2-D and 3-D grids", fn);
         if (items[i].grid.n[0] > 0x7fffffff || items[i].grid.n[1] > 0x7fffffff)

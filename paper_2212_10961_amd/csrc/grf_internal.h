@@ -25,6 +25,8 @@ int fail_hip(hipError_t e, const char* what);
 // ---------------------------------------------------------------- validation (host)
 int check_modes(const grf_modes* m, const char* fn);
 int check_grid(const grf_grid* g, int dim, const char* fn);
+// Axis-aligned view of a table (a rotated table's k written to kbuf; see grf_modes).
+hipError_t aligned_modes(const grf_modes* m, void* kbuf, hipStream_t s, grf_modes* out);
 inline bool is_sep(int m) { return m >= GRF_SEP_BF16 && m <= GRF_SEP_F16_X3; }
 inline bool is_hilo(int m) { return m == GRF_SEP_BF16_X3 || m == GRF_SEP_F16_X3; }
 inline bool is_bf16(int m) { return m == GRF_SEP_BF16 || m == GRF_SEP_BF16_X3; }
@@ -150,6 +152,15 @@ struct GridWs {
 GridWs grid_ws(const grf_modes* m, const grf_grid* g, int method, void* base);
 int grid_table_descs(const grf_modes* m, const grf_grid* g, int method, const GridWs& w, AxisTableArgs* out);
 
+// Rotated tables: out[a * n + j] = sum_b rot[3a + b] z[b * n + j] / ell[b] (device, FP64).
+hipError_t launch_rotate_modes(const double* z, int dim, int64_t n, const double* rot, const double* ell, double* out,
+                               hipStream_t s);
+// Workspace of the axis-aligned copy of a rotated table (0 for axis-aligned tables).
+inline size_t rot_ws_bytes(const grf_modes* m)
+{
+    return m->rotated ? align256(sizeof(double) * size_t(m->dim) * size_t(m->n)) : 0;
+}
+
 // Per-mode parameters in revolutions: (a_x, a_y, a_z, psi) as double4, [ldp] rows,
 // padded modes get a = 0, psi = 0.
 hipError_t launch_mode_params(const double* z, const double* phi, int dim, int64_t n, int64_t ldp,
@@ -255,6 +266,8 @@ struct BwdArgs {
     float* gk;
     float* gsigma;
     float* gell;
+    const double* rot;     // host row-major 3 x 3 when the table is rotated (z, ell are the
+                           // original table's; params hold k = rot diag(1/ell) z), else nullptr
     const float* tx;       // grid path: FP32 revolution tables (psi in ty), or nullptr
     const float* ty;
     const float* tz;

@@ -122,3 +122,44 @@ extern "C" int make_modes(const grf_spec* spec, double* z_out, double* phi_out)
     }
     return GRF_OK;
 }
+
+extern "C" int snap_periodic(int dim, int64_t n, const double* z, const double* ell, const double* rot,
+                             const double* period, double* z_out)
+{
+    using grf::fail;
+    if (dim != 2 && dim != 3) return fail(GRF_EINVAL, "snap_periodic: dim must be 2 or 3 (got %d)", dim);
+    if (n < 0) return fail(GRF_EINVAL, "snap_periodic: n < 0");
+    if (!z || !ell || !period || !z_out) return fail(GRF_EINVAL, "snap_periodic: NULL argument");
+    for (int a = 0; a < dim; ++a) {
+        if (!(ell[a] > 0.0) || !std::isfinite(ell[a])) return fail(GRF_EINVAL, "snap_periodic: ell[%d] must be > 0", a);
+        if (!std::isfinite(period[a])) return fail(GRF_EINVAL, "snap_periodic: period[%d] must be finite", a);
+    }
+    double R[3][3];
+    for (int a = 0; a < 3; ++a)
+        for (int b = 0; b < 3; ++b) R[a][b] = rot ? rot[3 * a + b] : (a == b ? 1.0 : 0.0);
+    if (rot) {  // orthonormal: rot rot^T = I on the used block
+        for (int a = 0; a < dim; ++a)
+            for (int b = 0; b < dim; ++b) {
+                double d = 0.0;
+                for (int c = 0; c < dim; ++c) d += R[a][c] * R[b][c];
+                if (!(std::fabs(d - (a == b ? 1.0 : 0.0)) <= 1e-9))
+                    return fail(GRF_EINVAL, "snap_periodic: rot must be orthonormal");
+            }
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        double u[3], k[3];
+        for (int b = 0; b < dim; ++b) u[b] = z[static_cast<int64_t>(b) * n + j] / ell[b];
+        for (int a = 0; a < dim; ++a) {
+            double v = 0.0;
+            for (int b = 0; b < dim; ++b) v += R[a][b] * u[b];
+            if (period[a] > 0.0) v = kTwoPi * std::round(v * period[a] / kTwoPi) / period[a];
+            k[a] = v;
+        }
+        for (int b = 0; b < dim; ++b) {
+            double v = 0.0;
+            for (int a = 0; a < dim; ++a) v += R[a][b] * k[a];
+            z_out[static_cast<int64_t>(b) * n + j] = v * ell[b];
+        }
+    }
+    return GRF_OK;
+}

@@ -172,6 +172,30 @@ __global__ __launch_bounds__(256) void k_rule_tables(RuleTables r, uint8_t* rule
     if (t < GRF_MAX_FACIES) values[t] = r.values[t];
 }
 
+// Wavevectors of a rotated table, k_j = R diag(1/ell) z_j, written as an axis-aligned table.
+struct RotArgs {
+    double r[9];  // row-major 3 x 3
+    double ell[3];
+};
+
+template <int DIM>
+__global__ __launch_bounds__(256) void k_rotate_modes(const double* __restrict__ z, int64_t n, RotArgs ra,
+                                                      double* __restrict__ out)
+{
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    double u[DIM];
+#pragma unroll
+    for (int b = 0; b < DIM; ++b) u[b] = z[b * n + j] / ra.ell[b];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        double v = 0.0;
+#pragma unroll
+        for (int b = 0; b < DIM; ++b) v += ra.r[3 * a + b] * u[b];
+        out[a * n + j] = v;
+    }
+}
+
 __global__ void k_fill_u64(unsigned long long* p, unsigned long long v)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
@@ -235,6 +259,21 @@ hipError_t launch_rule_tables(const grf_trunc2& r, void* dst, hipStream_t s)
     for (int i = 0; i < r.n_values && i < GRF_MAX_FACIES; ++i) t.values[i] = r.values[i];
     uint8_t* rule = static_cast<uint8_t*>(dst);
     hipLaunchKernelGGL(k_rule_tables, dim3(1), dim3(256), 0, s, t, rule, reinterpret_cast<float*>(rule + 256));
+    return hipGetLastError();
+}
+
+hipError_t launch_rotate_modes(const double* z, int dim, int64_t n, const double* rot, const double* ell, double* out,
+                               hipStream_t s)
+{
+    RotArgs ra{};
+    for (int i = 0; i < 9; ++i) ra.r[i] = rot[i];
+    for (int a = 0; a < 3; ++a) ra.ell[a] = a < dim ? ell[a] : 1.0;
+    const int64_t blocks = (n + 255) / 256;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (dim == 3)
+        hipLaunchKernelGGL(k_rotate_modes<3>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, z, n, ra, out);
+    else
+        hipLaunchKernelGGL(k_rotate_modes<2>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, z, n, ra, out);
     return hipGetLastError();
 }
 

@@ -26,7 +26,7 @@ from ._lib import GrfError, check
 __all__ = [
     "Modes", "make_modes", "modes_from_tables", "field_grid", "field_grid_f64", "field_points",
     "epilogue", "field_backward", "field_backward_grid", "GRFPoints", "Plan", "method_id", "sep_tiles",
-    "trunc2", "pluri_grid", "pluri_points", "pluri_apply",
+    "trunc2", "pluri_grid", "pluri_points", "pluri_apply", "snap_periodic",
     "GAUSSIAN", "EXPONENTIAL", "MATERN", "GrfError", "version", "paper_lambda_to_ell",
 ]
 
@@ -68,11 +68,15 @@ def paper_lambda_to_ell(lam: float) -> float:
 
 @dataclass
 class Modes:
-    """A device-resident mode table plus the scalars of the field."""
+    """A device-resident mode table plus the scalars of the field.
+
+    ``rot`` (optional dim x dim matrix) gives the general anisotropy k = rot diag(1/ell) z;
+    with an orthonormal rot the covariance's principal axes are its columns."""
     z: torch.Tensor      # float64 [dim][n] on the GPU
     phi: torch.Tensor    # float64 [n] on the GPU
     sigma: float
     ell: Sequence[float]
+    rot: Optional[np.ndarray] = None
 
     @property
     def dim(self) -> int:
@@ -91,6 +95,12 @@ class Modes:
         m.sigma = float(self.sigma)
         e = list(self.ell) + [1.0] * (3 - len(self.ell))
         m.ell = (ctypes.c_double * 3)(*[float(v) for v in e[:3]])
+        if self.rot is not None:
+            r = np.eye(3)
+            rr = np.asarray(self.rot, dtype=np.float64)
+            r[:rr.shape[0], :rr.shape[1]] = rr
+            m.rotated = 1
+            m.rot = (ctypes.c_double * 9)(*[float(v) for v in r.reshape(-1)])
         return m
 
 
@@ -106,10 +116,31 @@ def make_modes(dim: int, cov: int, n_modes: int, seed: int, nu: float = 0.5):
     return z, phi
 
 
-def modes_from_tables(z, phi, sigma: float, ell, device="cuda") -> Modes:
+def modes_from_tables(z, phi, sigma: float, ell, device="cuda", rot=None) -> Modes:
     zt = torch.as_tensor(np.ascontiguousarray(z), dtype=torch.float64).to(device).contiguous()
     pt = torch.as_tensor(np.ascontiguousarray(phi), dtype=torch.float64).to(device).contiguous()
-    return Modes(zt, pt, float(sigma), [float(v) for v in ell])
+    return Modes(zt, pt, float(sigma), [float(v) for v in ell], None if rot is None else np.asarray(rot, float))
+
+
+def snap_periodic(z, ell, period, rot=None):
+    """Host table whose wavevectors rot diag(1/ell) z lie on the lattice 2 pi m / L along every
+    axis with L > 0 (App. B "periodic"); z is [dim][n] float64."""
+    z = np.ascontiguousarray(z, dtype=np.float64)
+    dim, n = z.shape
+    e = np.ones(3)
+    e[:dim] = np.asarray(ell, dtype=np.float64)[:dim]
+    per = np.zeros(3)
+    per[:dim] = np.asarray(period, dtype=np.float64)[:dim]
+    r = None
+    if rot is not None:
+        r = np.eye(3)
+        rr = np.asarray(rot, dtype=np.float64)
+        r[:rr.shape[0], :rr.shape[1]] = rr
+        r = np.ascontiguousarray(r)
+    out = np.empty_like(z)
+    check(L.load().snap_periodic(dim, n, z.ctypes.data, e.ctypes.data, None if r is None else r.ctypes.data,
+                                 per.ctypes.data, out.ctypes.data))
+    return out
 
 
 def _grid(shape, origin=None, h=None) -> L.GrfGrid:
@@ -387,23 +418,27 @@ class GRFPoints(torch.autograd.Function):
     """
 
     @staticmethod
-    def forward(ctx, phi, z, sigma, ell, xyz):
+    def forward(ctx, phi, z, sigma, ell, xyz, rot=None):
         modes = Modes(z.detach().contiguous(), phi.detach().contiguous(), float(sigma),
-                      [float(v) for v in ell.detach().cpu()])
+                      [float(v) for v in ell.detach().cpu()], None if rot is None else np.asarray(rot, float))
         y = field_points(modes, xyz, method="direct_f32")["y"]
         ctx.save_for_backward(phi, z, sigma, ell, xyz, y)
+        ctx.rot = modes.rot
         return y
 
     @staticmethod
     def backward(ctx, gy):
         phi, z, sigma, ell, xyz, y = ctx.saved_tensors
         modes = Modes(z.detach().contiguous(), phi.detach().contiguous(), float(sigma),
-                      [float(v) for v in ell.detach().cpu()])
+                      [float(v) for v in ell.detach().cpu()], ctx.rot)
         g = field_backward(modes, xyz, gy.detach().to(torch.float32).contiguous(), y_saved=y)
         ellv = ell.detach().to(torch.float64).reshape(-1, 1)
-        dz = g["dk"].to(torch.float64) / ellv
+        dk = g["dk"].to(torch.float64)
+        if ctx.rot is not None:  # k = rot diag(1/ell) z: dL/dz = diag(1/ell) rot^T dL/dk
+            dk = torch.as_tensor(ctx.rot, dtype=torch.float64, device=dk.device).T @ dk
+        dz = dk / ellv
         return (g["dphi"].to(phi.dtype), dz.to(z.dtype), g["dsigma"].reshape(()).to(sigma.dtype),
-                g["dell"].to(ell.dtype), None)
+                g["dell"].to(ell.dtype), None, None)
 
 
 class Plan:

@@ -326,3 +326,67 @@ def test_pluri_validation(lib):
                            None) == L.GRF_ENOMEM
     assert lib.pluri_apply(dev, None, 10, ctypes.byref(r), dev, None, dev, 4096, None) == L.GRF_EINVAL
     assert lib.pluri_apply(dev, dev, 0, ctypes.byref(r), dev, None, None, 0, None) == 0
+
+
+def test_rotated_table_validation_and_workspace(lib):
+    g = _grid((8, 8, 8))
+    plain, rot = _modes(n=100), _modes(n=100)
+    rot.rotated = 1
+    for i in range(9):
+        rot.rot[i] = 1.0 if i % 4 == 0 else 0.0
+    b0, b1 = ctypes.c_size_t(), ctypes.c_size_t()
+    for meth in (0, 1, 3, 5):
+        assert lib.eval_field_grid_ws_size(ctypes.byref(plain), ctypes.byref(g), meth, ctypes.byref(b0)) == 0
+        assert lib.eval_field_grid_ws_size(ctypes.byref(rot), ctypes.byref(g), meth, ctypes.byref(b1)) == 0
+        assert b1.value - b0.value == 256 * ((3 * 100 * 8 + 255) // 256)  # the axis-aligned copy of k
+    assert lib.field_backward_ws_size(ctypes.byref(rot), 10, ctypes.byref(b1)) == 0
+    assert lib.field_backward_ws_size(ctypes.byref(plain), 10, ctypes.byref(b0)) == 0
+    assert b1.value > b0.value
+    bad = _modes(n=100)
+    bad.rotated = 2
+    assert lib.eval_field_grid_ws_size(ctypes.byref(bad), ctypes.byref(g), 0, ctypes.byref(b0)) == L.GRF_EINVAL
+    bad.rotated = 1
+    bad.rot[4] = float("nan")
+    assert lib.eval_field_grid_ws_size(ctypes.byref(bad), ctypes.byref(g), 0, ctypes.byref(b0)) == L.GRF_EINVAL
+    # batches take axis-aligned tables only
+    h = ctypes.c_void_p()
+    assert lib.grf_plan_create(ctypes.byref(h), L.GRF_SEP_F16, 0, None) == 0
+    items = (L.GrfBatchItem * 1)()
+    items[0].modes = rot
+    items[0].grid = g
+    items[0].y = 16
+    assert lib.eval_field_batch(h, items, 1, None) == L.GRF_EUNSUPPORTED
+    assert lib.grf_plan_destroy(h) == 0
+
+
+@pytest.mark.parametrize("dim,rot", [(3, False), (3, True), (2, True)])
+def test_snap_periodic_matches_oracle(lib, orc, dim, rot):
+    import paper_2212_10961_amd.grf as grf
+    z, _ = orc.sample_modes(dim, wl.EXPONENTIAL, 300, 841 + dim)
+    ell = np.array((12.0, 5.0, 2.0)[:dim])
+    per = np.array((64.0, 40.0, 0.0)[:dim])
+    R = orc.rotation_matrix(dim, (0.35, -0.2, 0.6)) if rot else None
+    want = orc.snap_periodic(z, ell, per, rot=R)
+    got = grf.snap_periodic(z, ell, per, rot=R)
+    np.testing.assert_allclose(got, want, rtol=1e-14, atol=1e-300)
+    # and the lattice property from the library's own output
+    Rm = np.eye(dim) if R is None else R
+    k = Rm @ np.diag(1.0 / ell) @ got
+    for a in range(dim):
+        if per[a] > 0:
+            m = k[a] * per[a] / (2 * np.pi)
+            np.testing.assert_allclose(m, np.round(m), atol=1e-9)
+
+
+def test_snap_periodic_validation(lib):
+    z = np.ones((2, 4))
+    out = np.empty_like(z)
+    ell, per = np.array([1.0, 1.0, 1.0]), np.array([10.0, 10.0, 0.0])
+    bad_rot = np.eye(3)
+    bad_rot[0, 1] = 0.5
+    assert lib.snap_periodic(2, 4, z.ctypes.data, ell.ctypes.data, bad_rot.ctypes.data, per.ctypes.data,
+                             out.ctypes.data) == L.GRF_EINVAL
+    assert lib.snap_periodic(4, 4, z.ctypes.data, ell.ctypes.data, None, per.ctypes.data, out.ctypes.data) == L.GRF_EINVAL
+    e0 = np.array([1.0, 0.0, 1.0])
+    assert lib.snap_periodic(2, 4, z.ctypes.data, e0.ctypes.data, None, per.ctypes.data, out.ctypes.data) == L.GRF_EINVAL
+    assert lib.snap_periodic(2, 4, z.ctypes.data, ell.ctypes.data, None, per.ctypes.data, None) == L.GRF_EINVAL
