@@ -24,7 +24,9 @@ the passage of Icardi et al. (2022) that it follows:
   Sec. 3.1 and its facies proportions for independent fields (the product formula there);
 - ``field_points_mat`` / ``grad_points_rot``: general anisotropy (rotations) of frequency
   space, named as the extension of the per-axis rescaling in Sec. 4.1;
-- ``snap_periodic``: the "periodic" option of App. B as wavevectors on the box's lattice.
+- ``snap_periodic``: the "periodic" option of App. B as wavevectors on the box's lattice;
+- ``lattice_modes`` / ``field_points_w``: the fixed-frequency, Gaussian-weight form of
+  Sec. 4.1 eq. DiscreteFT (frequencies on a lattice, weights W, W') and the weighted sum.
 
 Parity pins for this module are the ``-m "not gpu"`` tests in
 ``tests/test_oracle_pins.py``; none of them re-types the formulas above.
@@ -88,6 +90,10 @@ def _load():
         lib.orc_snap_periodic.argtypes = [ctypes.c_int, i64, d, d, d, d, d]
         lib.orc_grad_points_rot.argtypes = [ctypes.c_int, i64, d, d, ctypes.c_double, d, d, i64, d, d,
                                             d, d, d, d]
+        lib.orc_lattice_modes.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int,
+                                          ctypes.c_double, ctypes.c_uint64, d, d, d, d, d]
+        lib.orc_lattice_modes.restype = i64
+        lib.orc_field_points_w.argtypes = [ctypes.c_int, i64, d, d, d, ctypes.c_double, d, i64, d, d]
         _lib = lib
     return _lib
 
@@ -354,6 +360,38 @@ def grad_points_rot(z, phi, sigma, ell, rot, x, g):
     lib.orc_grad_points_rot(dim, n, _dp(z), _dp(phi), float(sigma), _dp(_ell(ell, dim)), _dp(r), x.shape[0],
                             _dp(x), _dp(g), _dp(dphi), _dp(dk), _dp(dsig), _dp(dell))
     return {"dphi": dphi, "dk": dk, "dsigma": float(dsig[0]), "dell": dell[:dim].copy()}
+
+
+def lattice_modes(dim: int, cov: int, m: int, du: float, seed: int, nu: float = 0.5):
+    """Fixed-frequency Gaussian-weight estimator (Sec. 4.1 eq. DiscreteFT, real reading) on
+    the half-space lattice of m^dim / 2 points with spacing du (standardised units).
+
+    Returns dict(z [dim][N], phi [N], w [N], W [N], Wp [N]) with
+    Y = sigma sqrt(2/N) sum_j w_j cos(k_j.x + phi_j) = sum_j c_j (W_j cos k_j.x + Wp_j sin k_j.x).
+    """
+    lib = _load()
+    n = (m // 2) * m ** (dim - 1)
+    z = np.empty((dim, n))
+    phi, w, W, Wp = np.empty(n), np.empty(n), np.empty(n), np.empty(n)
+    got = lib.orc_lattice_modes(dim, cov, float(nu), m, float(du), ctypes.c_uint64(seed), _dp(z), _dp(phi), _dp(w),
+                                _dp(W), _dp(Wp))
+    if got != n:
+        raise ValueError("orc_lattice_modes: bad arguments")
+    return {"z": z, "phi": phi, "w": w, "W": W, "Wp": Wp}
+
+
+def field_points_w(z, phi, w, sigma, ell, x):
+    """Y = sigma sqrt(2/N) sum_j w_j cos(k_j.x + phi_j) at points x (k = z / ell)."""
+    lib = _load()
+    z = _f64(z)
+    phi = _f64(phi)
+    w = _f64(w)
+    dim, n = z.shape
+    x = _f64(x).reshape(-1, dim)
+    y = np.empty(x.shape[0])
+    lib.orc_field_points_w(dim, n, _dp(z), _dp(phi), _dp(w), float(sigma), _dp(_ell(ell, dim)), x.shape[0],
+                           _dp(x), _dp(y))
+    return y
 
 
 def grid_centres(shape, origin=None, h=None):

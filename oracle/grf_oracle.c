@@ -485,3 +485,80 @@ void orc_grad_points_rot(int dim, int64_t n, const double* z, const double* phi,
         dell[b] = acc;
     }
 }
+
+/* ------------------------------------------------------------------ fixed-frequency estimator */
+
+/* Standardised spectral shape (ell = 1, angular frequency) of the covariance, up to a
+ * constant (App. A): Gaussian exp(-|u|^2/4), exponential (1 + |u|^2)^(-(d+1)/2), Matern
+ * (1 + |u|^2 / (2 nu))^(-(2 nu + d)/2). */
+static double orc_spectral_shape(int dim, int cov, double nu, const double* u)
+{
+    double r2 = 0.0;
+    for (int a = 0; a < dim; ++a) r2 += u[a] * u[a];
+    if (cov == 0) return exp(-r2 / 4.0);
+    if (cov == 1) return pow(1.0 + r2, -0.5 * (dim + 1));
+    return pow(1.0 + r2 / (2.0 * nu), -0.5 * (2.0 * nu + dim));
+}
+
+/*
+ * The discrete spectral sum of Sec. 4.1 eq. DiscreteFT with fixed frequencies and Gaussian
+ * weights, in its real reading
+ *   Y(x) = sum_j c_j [W_j cos(k_j . x) + W'_j sin(k_j . x)],  c_j = sigma sqrt(p_j),
+ *   p_j = S(u_j) / sum_i S(u_i),  k_j = u_j / ell,  W, W' independent N(0, 1),
+ * over the half-space lattice u_j of m^dim / 2 points (m even, spacing du): mode
+ * j = i0 + (m/2) (i1 + m i2) has u_0 = du (i0 + 1/2), u_a = du (i_a - m/2 + 1/2) for a > 0.
+ * (W_j, W'_j) is the Box-Muller pair of draw slot 1 of counter j.  Written in the
+ * random-phase form sigma sqrt(2/N) sum_j w_j cos(k_j . x + phi_j):
+ *   w_j = sqrt(p_j (W_j^2 + W'_j^2) N / 2),  phi_j = -atan2(W'_j, W_j) mod 2 pi.
+ * Outputs z [dim][N] (= u), phi [N], w [N]; W, Wp [N] when not NULL.  Returns N, or -1.
+ */
+int64_t orc_lattice_modes(int dim, int cov, double nu, int m, double du, uint64_t seed, double* z, double* phi,
+                          double* w, double* W, double* Wp)
+{
+    if ((dim != 2 && dim != 3) || m < 2 || (m % 2) != 0 || !(du > 0.0) || cov < 0 || cov > 2) return -1;
+    int64_t n = (int64_t)(m / 2) * m;
+    if (dim == 3) n *= m;
+    double* S = (double*)malloc(sizeof(double) * (size_t)n);
+    double tot = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        int64_t r = j;
+        int64_t i0 = r % (m / 2);
+        r /= (m / 2);
+        int64_t i1 = r % m;
+        int64_t i2 = r / m;
+        double u[3] = {du * ((double)i0 + 0.5), du * ((double)i1 - m / 2 + 0.5), du * ((double)i2 - m / 2 + 0.5)};
+        for (int a = 0; a < dim; ++a) z[a * n + j] = u[a];
+        S[j] = orc_spectral_shape(dim, cov, nu, u);
+        tot += S[j];
+    }
+    for (int64_t j = 0; j < n; ++j) {
+        double g[2];
+        orc_normal_pair(seed, j, 1u, g);
+        double a = -atan2(g[1], g[0]);
+        if (a < 0.0) a += 2.0 * ORC_PI;
+        phi[j] = a;
+        w[j] = sqrt(S[j] / tot * (g[0] * g[0] + g[1] * g[1]) * (double)n / 2.0);
+        if (W) W[j] = g[0];
+        if (Wp) Wp[j] = g[1];
+    }
+    free(S);
+    return n;
+}
+
+/* Weighted random-phase sum Y(x) = sigma sqrt(2/N) sum_j w_j cos(k_j . x + phi_j), k = z / ell. */
+void orc_field_points_w(int dim, int64_t n, const double* z, const double* phi, const double* w, double sigma,
+                        const double* ell, int64_t P, const double* x, double* y)
+{
+    double amp = sigma * sqrt(2.0 / (double)n);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t p = 0; p < P; ++p) {
+        const double* xp = x + p * dim;
+        double s = 0.0;
+        for (int64_t j = 0; j < n; ++j) {
+            double th = phi[j];
+            for (int a = 0; a < dim; ++a) th += z[a * n + j] / ell[a] * xp[a];
+            s += w[j] * cos(th);
+        }
+        y[p] = amp * s;
+    }
+}

@@ -547,3 +547,66 @@ def test_periodic_snap(orc, rot):
         y1 = orc.field_points_mat(zs, phi, 1.0, M, sh)
         # wavevectors reach |k| ~ 1e3 (heavy tails), so k.x rounds at ~1e-13 rad per term
         np.testing.assert_allclose(y1, y0, rtol=0, atol=1e-9)
+
+
+# ------------------------------------------------------------------ fixed-frequency Gaussian-weight form
+
+@pytest.mark.parametrize("dim,cov", [(2, wl.GAUSSIAN), (3, wl.EXPONENTIAL), (2, wl.MATERN)])
+def test_lattice_form_is_the_paper_sum(orc, dim, cov):
+    """The weighted random-phase form equals eq. DiscreteFT's real sum
+    sum_j c_j (W_j cos k.x + W'_j sin k.x) with c_j^2 = sigma^2 S(u_j) / sum S, S taken from
+    scipy's multivariate densities (normal with covariance 2I; t with 1 or 2 nu dof)."""
+    m, du, sigma = 8, 0.6, 1.3
+    L = orc.lattice_modes(dim, cov, m, du, 901 + dim, nu=1.0)
+    z = L["z"]
+    n = z.shape[1]
+    assert n == m ** dim // 2
+    assert np.all(z[0] > 0)  # half space
+    u = z.T
+    if cov == wl.GAUSSIAN:
+        S = st.multivariate_normal(mean=np.zeros(dim), cov=2 * np.eye(dim)).pdf(u)
+    elif cov == wl.EXPONENTIAL:
+        S = st.multivariate_t(loc=np.zeros(dim), shape=np.eye(dim), df=1).pdf(u)
+    else:  # Matern nu = 1 -> t with 2 dof
+        S = st.multivariate_t(loc=np.zeros(dim), shape=np.eye(dim), df=2).pdf(u)
+    c = sigma * np.sqrt(S / S.sum())
+    ell = np.array((4.0, 2.0, 1.0)[:dim])
+    x = wl.points_uniform(300, (20.0,) * dim, 902)
+    k = (z / ell[:, None]).T
+    th = x @ k.T
+    want = (np.cos(th) * (c * L["W"]) + np.sin(th) * (c * L["Wp"])).sum(axis=1)
+    got = orc.field_points_w(z, L["phi"], L["w"], sigma, ell, x)
+    np.testing.assert_allclose(got, want, rtol=0, atol=1e-12)
+    assert np.all((L["phi"] >= 0) & (L["phi"] < 2 * np.pi))
+
+
+def test_lattice_covariance_and_riemann_limit(orc):
+    """Over weight draws the covariance is sigma^2 sum_j p_j cos(k_j . r) exactly; for a fine,
+    wide Gaussian lattice that sum is the analytic exp(-r^2/ell^2) (Bochner, App. A)."""
+    sigma2, ell = 2.0, np.array([3.0, 1.5])
+    m, du = 40, 0.4  # |u| up to 8: the Gaussian shape exp(-|u|^2/4) is ~1e-7 there
+    L0 = orc.lattice_modes(2, wl.GAUSSIAN, m, du, 0)
+    k = L0["z"] / ell[:, None]
+    S = np.exp(-(L0["z"] ** 2).sum(axis=0) / 4.0)
+    p = S / S.sum()
+    for r in [np.array([0.0, 0.0]), np.array([1.5, 0.0]), np.array([0.0, 1.5]), np.array([2.0, 1.0])]:
+        lat = float(np.dot(p, np.cos(r @ k)))
+        assert abs(lat - math.exp(-float(((r / ell) ** 2).sum()))) < 1e-6
+    # ensemble over seeds, coarse lattice: exact lattice covariance
+    m, du, R = 6, 0.9, 4000
+    base = wl.points_uniform(2, (10.0, 10.0), 903)
+    lags = [np.array([1.0, 0.0]), np.array([0.0, 0.7])]
+    pts = np.concatenate([base] + [base + lg for lg in lags])
+    prods = np.empty((R, 1 + len(lags)))
+    for s in range(R):
+        L = orc.lattice_modes(2, wl.GAUSSIAN, m, du, 10_000 + s)
+        y = orc.field_points_w(L["z"], L["phi"], L["w"], math.sqrt(sigma2), ell, pts).reshape(-1, 2)
+        prods[s] = (y[0] * y).mean(axis=1)
+    L = orc.lattice_modes(2, wl.GAUSSIAN, m, du, 0)
+    kk = L["z"] / ell[:, None]
+    pp = np.exp(-(L["z"] ** 2).sum(axis=0) / 4.0)
+    pp /= pp.sum()
+    want = [sigma2] + [sigma2 * float(np.dot(pp, np.cos(lg @ kk))) for lg in lags]
+    mean, se = prods.mean(axis=0), prods.std(axis=0) / math.sqrt(R)
+    for a, b, e in zip(mean, want, se):
+        assert abs(a - b) < 4.5 * e, (mean, want, se)
