@@ -97,6 +97,8 @@ typedef struct grf_modes {
     int32_t rotated;    /* 0 or 1 */
     int32_t pad2_;
     double rot[9];      /* row-major 3 x 3 (dim 2 uses the upper-left 2 x 2 block); finite */
+    const double* w;    /* device, [n] per-mode weights, or NULL (all 1):
+                           Y = sigma sqrt(2/N) sum_j w_j cos(k_j . x + phi_j) */
 } grf_modes;
 
 /* Structured grid: centres origin + (i + 1/2) h, x index fastest; n[2] = 1 for dim 2. */
@@ -131,6 +133,22 @@ const char* grf_last_error(void);
  * shorter table.  Does not touch the GPU.
  */
 int make_modes(const grf_spec* spec, double* z_out, double* phi_out);
+
+/*
+ * make_modes_lattice -- the fixed-frequency, Gaussian-weight form of Sec. 4.1 eq. DiscreteFT
+ * (read as the real sum sum_j c_j [W_j cos(k_j . x) + W'_j sin(k_j . x)], W, W' independent
+ * N(0,1), c_j^2 = sigma^2 S(u_j) / sum_i S(u_i), S the standardised spectral density of App. A):
+ * frequencies on the half-space lattice of N = m^dim / 2 points with spacing du
+ * (standardised units; k = u / ell): mode j = i0 + (m/2)(i1 + m i2) has u_0 = du (i0 + 1/2),
+ * u_a = du (i_a - m/2 + 1/2) for a > 0.  (W_j, W'_j) is the Box-Muller pair of draw slot 1
+ * of Philox counter j.  Written as a weighted table: z = u, phi_j = -atan2(W'_j, W_j) mod 2 pi,
+ * w_j = sqrt(N/2 * p_j * (W_j^2 + W'_j^2)), so that grf_modes{z, phi, sigma, ell, w}
+ * evaluates the sum exactly.
+ *   spec     host: dim, cov (nu for Matern), seed; spec->n_modes must equal m^dim / 2.
+ *   m        even, >= 2;  du > 0.
+ *   z_out [dim][N], phi_out [N], w_out [N]: host arrays, written.
+ */
+int make_modes_lattice(const grf_spec* spec, int32_t m, double du, double* z_out, double* phi_out, double* w_out);
 
 /*
  * snap_periodic -- the "periodic" option of App. B: every wavevector is moved to the nearest

@@ -27,7 +27,7 @@ METHODS = {
 
 # Every symbol include/grf.h declares.
 EXPORTS = [
-    "grf_version", "grf_last_error", "make_modes", "snap_periodic", "eval_field_grid_ws_size", "eval_field_grid",
+    "grf_version", "grf_last_error", "make_modes", "make_modes_lattice", "snap_periodic", "eval_field_grid_ws_size", "eval_field_grid",
     "eval_field_grid_tile", "grf_sep_tile_count", "grf_sep_tile_shape",
     "eval_pluri_grid_ws_size", "eval_pluri_grid", "eval_pluri_points_ws_size", "eval_pluri_points", "pluri_apply",
     "eval_field_grid_f64", "eval_field_points_ws_size", "eval_field_points", "epilogue_apply",
@@ -47,7 +47,7 @@ class GrfModes(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("pad_", ctypes.c_int32), ("n", ctypes.c_int64),
                 ("z", ctypes.c_void_p), ("phi", ctypes.c_void_p), ("sigma", ctypes.c_double),
                 ("ell", ctypes.c_double * 3), ("rotated", ctypes.c_int32), ("pad2_", ctypes.c_int32),
-                ("rot", ctypes.c_double * 9)]
+                ("rot", ctypes.c_double * 9), ("w", ctypes.c_void_p)]
 
 
 class GrfGrid(ctypes.Structure):
@@ -95,6 +95,7 @@ def load():
         "grf_last_error": ([], ctypes.c_char_p),
         "make_modes": ([P(GrfSpec), vp, vp], ctypes.c_int),
         "snap_periodic": ([ctypes.c_int, i64, vp, vp, vp, vp, vp], ctypes.c_int),
+        "make_modes_lattice": ([P(GrfSpec), i32, ctypes.c_double, vp, vp, vp], ctypes.c_int),
         "eval_field_grid_ws_size": ([P(GrfModes), P(GrfGrid), ctypes.c_int, P(sz)], ctypes.c_int),
         "eval_field_grid": ([P(GrfModes), P(GrfGrid), ctypes.c_int, P(GrfEpi), vp, vp, vp, vp, sz, vp],
                             ctypes.c_int),

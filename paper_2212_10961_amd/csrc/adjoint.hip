@@ -90,9 +90,11 @@ struct EllMap {
     double ell[3];
 };
 
+// Per-mode weights w_j (when given) scale every per-mode sum: the term of mode j is
+// w_j cos(theta_jp).
 __global__ __launch_bounds__(256) void k_bwd_reduce(const float* __restrict__ partial, int64_t nch, int64_t n,
                                                    int64_t ldp, int dim, float amp, const double* __restrict__ z,
-                                                   EllMap em, float* __restrict__ gphi,
+                                                   const double* __restrict__ wt, EllMap em, float* __restrict__ gphi,
                                                    float* __restrict__ gk, float* __restrict__ scal)
 {
     __shared__ float sh[4];
@@ -108,12 +110,13 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(const float* __restrict__ pa
             U[2] += pc[3 * ldp + j];
             C += pc[4 * ldp + j];
         }
-        if (gphi) gphi[j] = -amp * S;
+        const float wj = wt ? static_cast<float>(wt[j]) : 1.f;
+        if (gphi) gphi[j] = -amp * (wj * S);
         float gka[3] = {0.f, 0.f, 0.f};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             if (a >= dim) break;
-            gka[a] = -amp * U[a];
+            gka[a] = -amp * (wj * U[a]);
             if (gk) gk[a * n + j] = gka[a];
         }
 #pragma unroll
@@ -125,7 +128,7 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(const float* __restrict__ pa
                 if (a < dim) w += static_cast<double>(gka[a]) * em.r[3 * a + b];
             tl[b] = static_cast<float>(w * (-z[b * n + j] / (em.ell[b] * em.ell[b])));
         }
-        tc = C;
+        tc = wj * C;
     }
     const float r0 = block_sum(tl[0], sh);
     const float r1 = block_sum(tl[1], sh);
@@ -310,7 +313,7 @@ hipError_t launch_backward(const BwdArgs& a, hipStream_t s)
     for (int i = 0; i < 9; ++i) em.r[i] = a.rot ? a.rot[i] : (i % 4 == 0 ? 1.0 : 0.0);
     for (int b = 0; b < 3; ++b) em.ell[b] = b < a.dim ? a.ell[b] : 1.0;
     hipLaunchKernelGGL(k_bwd_reduce, dim3(nblk), dim3(256), 0, s, a.partial, a.nchunks, a.n, a.ldp, a.dim, a.amp, a.z,
-                       em, a.gphi, a.gk, a.scal_partial);
+                       a.w, em, a.gphi, a.gk, a.scal_partial);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     const float* dotp = nullptr;

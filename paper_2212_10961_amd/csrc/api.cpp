@@ -195,6 +195,7 @@ int grid_table_descs(const grf_modes* m, const grf_grid* g, int method, const Gr
         t.conj = false;
         t.out = w.t[a];
         t.out_lo = w.tlo[a];
+        t.w = nullptr;
         if (a >= m->dim) t.z = nullptr;  // axis absent: zero phase
         if (method == GRF_DIRECT_F32) {
             t.format = TF_REV_F32;
@@ -209,6 +210,7 @@ int grid_table_descs(const grf_modes* m, const grf_grid* g, int method, const Gr
                 t.format = bf ? (hilo ? TF_BF16_HILO : TF_BF16) : (hilo ? TF_F16_HILO : TF_F16);
                 t.conj = (a == 0);
                 t.blocked = true;
+                if (a == 1) t.w = m->w;  // per-mode weights ride on the y operand (with the phase)
             } else if (a == 0) {  // 3-D x axis: (Re, -Im) Ex for the product with Ez
                 t.format = hilo ? TF_CPLX_F32 : (bf ? TF_BF16 : TF_F16);
                 t.conj = true;
@@ -300,12 +302,12 @@ static int grid_launch(const grf_modes* modes, const grf_grid* grid, int method,
     TimedScope timed(s);
     if (method == GRF_DIRECT_F32) {
         GRF_HIP(launch_direct_grid_f32(static_cast<const float*>(w.t[0]), static_cast<const float*>(w.t[1]),
-                                       static_cast<const float*>(w.t[2]), modes->n, ldp, grid->n, amp, e,
+                                       static_cast<const float*>(w.t[2]), modes->w, modes->n, ldp, grid->n, amp, e,
                                        y, k, ind, s));
     } else if (method == GRF_DIRECT_F64) {
         const double amp64 = modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n));
         GRF_HIP(launch_direct_grid_f64(static_cast<const double*>(w.t[0]), static_cast<const double*>(w.t[1]),
-                                       static_cast<const double*>(w.t[2]), modes->n, ldp, grid->n, amp64, e,
+                                       static_cast<const double*>(w.t[2]), modes->w, modes->n, ldp, grid->n, amp64, e,
                                        0.0, y, k, ind, nullptr, nullptr, s));
     } else {
         SepArgs a{};
@@ -505,8 +507,8 @@ static int points_launch(const grf_modes* modes, const double* xyz, int64_t n_po
     GRF_HIP(launch_mode_params(modes->z, modes->phi, modes->dim, modes->n, ldp, modes->ell, params, s));
     const float amp = static_cast<float>(modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n)));
     TimedScope timed(s);
-    GRF_HIP(launch_direct_points(params, modes->n, modes->dim, xyz, n_points, method == GRF_DIRECT_F64, amp, e, y, k,
-                                 ind, partial, s));
+    GRF_HIP(launch_direct_points(params, modes->w, modes->n, modes->dim, xyz, n_points, method == GRF_DIRECT_F64, amp,
+                                 e, y, k, ind, partial, s));
     return GRF_OK;
 }
 
@@ -627,7 +629,7 @@ int eval_field_grid_f64(const grf_modes* modes, const grf_grid* grid, double mu,
     GRF_HIP(build_tables(&am, grid, GRF_DIRECT_F64, w, s));
     const double amp64 = modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n));
     GRF_HIP(launch_direct_grid_f64(static_cast<const double*>(w.t[0]), static_cast<const double*>(w.t[1]),
-                                   static_cast<const double*>(w.t[2]), modes->n, padded_modes(modes->n),
+                                   static_cast<const double*>(w.t[2]), modes->w, modes->n, padded_modes(modes->n),
                                    grid->n, amp64, Epi{}, mu, nullptr, nullptr, nullptr, y64, k64, s));
     return GRF_OK;
 }
@@ -744,6 +746,7 @@ static int backward_common(const char* fn, const grf_modes* modes, const double*
     a.sigma = static_cast<float>(modes->sigma);
     a.ell = modes->ell;
     a.z = modes->z;
+    a.w = modes->w;
     a.rot = modes->rotated ? modes->rot : nullptr;
     a.gphi = grad_phi;
     a.gk = grad_k;

@@ -257,6 +257,7 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
             d.tx = static_cast<const float*>(ws[i].t[0]);
             d.ty = static_cast<const float*>(ws[i].t[1]);
             d.tz = static_cast<const float*>(ws[i].t[2]);
+            d.w = it.modes.w;
             d.y = it.y;
             d.ldp = padded_modes(it.modes.n);
             d.nq = it.grid.n[1] * it.grid.n[2];

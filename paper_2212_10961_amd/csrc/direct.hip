@@ -25,8 +25,9 @@ __device__ __forceinline__ void store_out(int64_t c, float yv, const Epi& e, flo
 // ---------------------------------------------------------------------------- grid, FP32
 // Block tile: 64 x-cells by 64 (y,z) pairs; 256 threads; each lane owns 4 x 4 cells
 // (x = x0 + lx + 16 rx, q = q0 + 16 w + ly + 4 rq).  Mode chunks of 64 are staged in
-// LDS: sx[x][j] = Tx, sq[q][j] = Ty + Tz (psi folded in Ty).  Rows are padded to 68
-// floats so the 16 distinct x rows of a wave's 128-bit reads hit distinct banks.
+// LDS: sx[x][j] = Tx, sq[q][j] = Ty + Tz (psi folded in Ty), sw[j] = per-mode weight (1
+// without weights).  Rows are padded to 68 floats so the 16 distinct x rows of a wave's
+// 128-bit reads hit distinct banks.
 constexpr int kDgB = 64;
 constexpr int kDgJ = 64;
 constexpr int kDgRow = (kDgJ + 4) / 4;  // float4 per padded row
@@ -36,10 +37,10 @@ static_assert(kDgB == kDirectTile, "tile side shared with the batch planner");
 // Without EPI only Y is stored (batched ensembles).
 template <bool EPI>
 __device__ __forceinline__ void direct_tile(const float* __restrict__ tx, const float* __restrict__ ty,
-                                            const float* __restrict__ tz, int n, int64_t ldp, int nx, int ny,
-                                            int64_t nq, int x0, int64_t q0, float amp, const Epi& epi,
-                                            float* __restrict__ y, float* __restrict__ k, uint8_t* __restrict__ ind,
-                                            float4* sx, float4* sq)
+                                            const float* __restrict__ tz, const double* __restrict__ wt, int n,
+                                            int64_t ldp, int nx, int ny, int64_t nq, int x0, int64_t q0, float amp,
+                                            const Epi& epi, float* __restrict__ y, float* __restrict__ k,
+                                            uint8_t* __restrict__ ind, float4* sx, float4* sq, float4* sw)
 {
     const int t = threadIdx.x;
     const int w = t >> 6, l = t & 63;
@@ -64,6 +65,16 @@ __device__ __forceinline__ void direct_tile(const float* __restrict__ tx, const 
             const float4 b = *reinterpret_cast<const float4*>(tz + zz * ldp + j0 + 4 * c4);
             sq[row * kDgRow + c4] = make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
         }
+        if (t < kDgJ / 4) {
+            float4 wv = make_float4(1.f, 1.f, 1.f, 1.f);
+            if (wt) {
+                const int j = j0 + 4 * t;  // modes past n carry no weight (their terms are not summed)
+                wv = make_float4(j < n ? static_cast<float>(wt[j]) : 0.f, j + 1 < n ? static_cast<float>(wt[j + 1]) : 0.f,
+                                 j + 2 < n ? static_cast<float>(wt[j + 2]) : 0.f,
+                                 j + 3 < n ? static_cast<float>(wt[j + 3]) : 0.f);
+            }
+            sw[t] = wv;
+        }
         __syncthreads();
         const int jn = min(kDgJ, n - j0);
         const int j4 = jn >> 2;
@@ -73,24 +84,27 @@ __device__ __forceinline__ void direct_tile(const float* __restrict__ tx, const 
             for (int r = 0; r < 4; ++r) vx[r] = sx[(lx + 16 * r) * kDgRow + m];
 #pragma unroll
             for (int r = 0; r < 4; ++r) vq[r] = sq[(lq + 4 * r) * kDgRow + m];
+            const float4 wv = sw[m];
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b) {
-                    acc[a][b] += cos_rev(vx[a].x + vq[b].x);
-                    acc[a][b] += cos_rev(vx[a].y + vq[b].y);
-                    acc[a][b] += cos_rev(vx[a].z + vq[b].z);
-                    acc[a][b] += cos_rev(vx[a].w + vq[b].w);
+                    acc[a][b] = fmaf(wv.x, cos_rev(vx[a].x + vq[b].x), acc[a][b]);
+                    acc[a][b] = fmaf(wv.y, cos_rev(vx[a].y + vq[b].y), acc[a][b]);
+                    acc[a][b] = fmaf(wv.z, cos_rev(vx[a].z + vq[b].z), acc[a][b]);
+                    acc[a][b] = fmaf(wv.w, cos_rev(vx[a].w + vq[b].w), acc[a][b]);
                 }
         }
         const float* sxf = reinterpret_cast<const float*>(sx);
         const float* sqf = reinterpret_cast<const float*>(sq);
+        const float* swf = reinterpret_cast<const float*>(sw);
         for (int m = j4 * 4; m < jn; ++m) {
 #pragma unroll
             for (int a = 0; a < 4; ++a)
 #pragma unroll
                 for (int b = 0; b < 4; ++b)
-                    acc[a][b] += cos_rev(sxf[(lx + 16 * a) * kDgRow * 4 + m] + sqf[(lq + 4 * b) * kDgRow * 4 + m]);
+                    acc[a][b] = fmaf(swf[m], cos_rev(sxf[(lx + 16 * a) * kDgRow * 4 + m] + sqf[(lq + 4 * b) * kDgRow * 4 + m]),
+                                     acc[a][b]);
         }
         __syncthreads();
     }
@@ -110,16 +124,17 @@ __device__ __forceinline__ void direct_tile(const float* __restrict__ tx, const 
 }
 
 __global__ __launch_bounds__(256, 2) void k_direct_grid(const float* __restrict__ tx, const float* __restrict__ ty,
-                                                       const float* __restrict__ tz, int n, int64_t ldp, int nx,
-                                                       int ny, int64_t nq, int nxt, float amp, Epi epi,
-                                                       float* __restrict__ y, float* __restrict__ k,
-                                                       uint8_t* __restrict__ ind)
+                                                       const float* __restrict__ tz, const double* __restrict__ wt,
+                                                       int n, int64_t ldp, int nx, int ny, int64_t nq, int nxt,
+                                                       float amp, Epi epi, float* __restrict__ y,
+                                                       float* __restrict__ k, uint8_t* __restrict__ ind)
 {
     __shared__ float4 sx[kDgB * kDgRow];
     __shared__ float4 sq[kDgB * kDgRow];
+    __shared__ float4 sw[kDgJ / 4];
     const int64_t bid = blockIdx.x;
-    direct_tile<true>(tx, ty, tz, n, ldp, nx, ny, nq, static_cast<int>(bid % nxt) * kDgB, (bid / nxt) * kDgB, amp, epi,
-                      y, k, ind, sx, sq);
+    direct_tile<true>(tx, ty, tz, wt, n, ldp, nx, ny, nq, static_cast<int>(bid % nxt) * kDgB, (bid / nxt) * kDgB, amp,
+                      epi, y, k, ind, sx, sq, sw);
 }
 
 // Persistent batched form: blocks pull (instance, tile) work items from one atomic counter
@@ -129,6 +144,7 @@ __global__ __launch_bounds__(256, 2) void k_direct_batch(const DirectBatchItem* 
 {
     __shared__ float4 sx[kDgB * kDgRow];
     __shared__ float4 sq[kDgB * kDgRow];
+    __shared__ float4 sw[kDgJ / 4];
     __shared__ unsigned long long s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1ull);
@@ -144,8 +160,8 @@ __global__ __launch_bounds__(256, 2) void k_direct_batch(const DirectBatchItem* 
         }
         const DirectBatchItem& b = items[lo];
         const int64_t local = it - b.item0;
-        direct_tile<false>(b.tx, b.ty, b.tz, b.n, b.ldp, b.nx, b.ny, b.nq, static_cast<int>(local % b.nxt) * kDgB,
-                           (local / b.nxt) * kDgB, b.amp, Epi{}, b.y, nullptr, nullptr, sx, sq);
+        direct_tile<false>(b.tx, b.ty, b.tz, b.w, b.n, b.ldp, b.nx, b.ny, b.nq, static_cast<int>(local % b.nxt) * kDgB,
+                           (local / b.nxt) * kDgB, b.amp, Epi{}, b.y, nullptr, nullptr, sx, sq, sw);
     }
 }
 
@@ -153,7 +169,8 @@ __global__ __launch_bounds__(256, 2) void k_direct_batch(const DirectBatchItem* 
 // One thread per cell, FP64 per-axis fractions summed and reduced in FP64, cos by
 // the device library's cospi.  For small problems and as a reference-grade path.
 __global__ __launch_bounds__(256) void k_direct_grid_f64(const double* __restrict__ tx, const double* __restrict__ ty,
-                                                        const double* __restrict__ tz, int n, int64_t ldp, int nx,
+                                                        const double* __restrict__ tz, const double* __restrict__ wt,
+                                                        int n, int64_t ldp, int nx,
                                                         int ny, int64_t C, double amp, Epi epi, double mu64,
                                                         float* __restrict__ y, float* __restrict__ k,
                                                         uint8_t* __restrict__ ind, double* __restrict__ y64,
@@ -170,7 +187,7 @@ __global__ __launch_bounds__(256) void k_direct_grid_f64(const double* __restric
     for (int j = 0; j < n; ++j) {
         double f = rx[j] + ry[j] + rz[j];
         f -= floor(f);
-        s += cospi(2.0 * f);
+        s += (wt ? wt[j] : 1.0) * cospi(2.0 * f);
     }
     const double yv = amp * s;
     if (y64) y64[c] = yv;
@@ -197,8 +214,8 @@ __global__ __launch_bounds__(256) void k_points_reduce(const float* __restrict__
 // every slice writes its raw partial sums to partial[slice][P] and k_points_reduce adds
 // them in slice order and applies the epilogue.
 template <int DIM, int R>
-__global__ __launch_bounds__(256) void k_direct_points(const double4* __restrict__ prm, int n,
-                                                      const double* __restrict__ xyz, int64_t P, float amp,
+__global__ __launch_bounds__(256) void k_direct_points(const double4* __restrict__ prm, const double* __restrict__ wt,
+                                                      int n, const double* __restrict__ xyz, int64_t P, float amp,
                                                       Epi epi, float* __restrict__ y, float* __restrict__ k,
                                                       uint8_t* __restrict__ ind, int mslice,
                                                       float* __restrict__ partial)
@@ -218,13 +235,14 @@ __global__ __launch_bounds__(256) void k_direct_points(const double4* __restrict
     }
     for (int j = j0; j < j1; ++j) {
         const double4 m = prm[j];
+        const float wj = wt ? static_cast<float>(wt[j]) : 1.f;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             double ph = DIM == 3 ? fma(m.z, pz[r], m.w) : m.w;
             ph = fma(m.y, py[r], ph);
             ph = fma(m.x, px[r], ph);
             ph -= floor(ph);
-            acc[r] += cos_rev(static_cast<float>(ph));
+            acc[r] = fmaf(wj, cos_rev(static_cast<float>(ph)), acc[r]);
         }
     }
 #pragma unroll
@@ -237,7 +255,8 @@ __global__ __launch_bounds__(256) void k_direct_points(const double4* __restrict
 }
 
 template <int DIM>
-__global__ __launch_bounds__(256) void k_direct_points_f64(const double4* __restrict__ prm, int n,
+__global__ __launch_bounds__(256) void k_direct_points_f64(const double4* __restrict__ prm,
+                                                          const double* __restrict__ wt, int n,
                                                           const double* __restrict__ xyz, int64_t P, double amp,
                                                           Epi epi, float* __restrict__ y, float* __restrict__ k,
                                                           uint8_t* __restrict__ ind)
@@ -250,7 +269,7 @@ __global__ __launch_bounds__(256) void k_direct_points_f64(const double4* __rest
         const double4 m = prm[j];
         double ph = fma(m.x, px, fma(m.y, py, fma(m.z, pz, m.w)));
         ph -= floor(ph);
-        s += cospi(2.0 * ph);
+        s += (wt ? wt[j] : 1.0) * cospi(2.0 * ph);
     }
     store_out(p, static_cast<float>(amp * s), epi, y, k, ind);
 }
@@ -313,46 +332,46 @@ __global__ __launch_bounds__(256) void k_epilogue_scalar(const float* __restrict
 
 }  // namespace
 
-hipError_t launch_direct_grid_f32(const float* tx, const float* ty, const float* tz, int64_t n, int64_t ldp,
-                                  const int64_t* gn, float amp, const Epi& epi, float* y, float* k, uint8_t* ind,
-                                  hipStream_t s)
+hipError_t launch_direct_grid_f32(const float* tx, const float* ty, const float* tz, const double* w, int64_t n,
+                                  int64_t ldp, const int64_t* gn, float amp, const Epi& epi, float* y, float* k,
+                                  uint8_t* ind, hipStream_t s)
 {
     const int nx = static_cast<int>(gn[0]), ny = static_cast<int>(gn[1]);
     const int64_t nq = gn[1] * gn[2];
     const int nxt = (nx + kDgB - 1) / kDgB;
     const int64_t blocks = static_cast<int64_t>(nxt) * ((nq + kDgB - 1) / kDgB);
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_direct_grid, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, tx, ty, tz,
+    hipLaunchKernelGGL(k_direct_grid, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, tx, ty, tz, w,
                        static_cast<int>(n), ldp, nx, ny, nq, nxt, amp, epi, y, k, ind);
     return hipGetLastError();
 }
 
-hipError_t launch_direct_grid_f64(const double* tx, const double* ty, const double* tz, int64_t n, int64_t ldp,
-                                  const int64_t* gn, double amp, const Epi& epi, double mu64, float* y, float* k,
-                                  uint8_t* ind, double* y64, double* k64, hipStream_t s)
+hipError_t launch_direct_grid_f64(const double* tx, const double* ty, const double* tz, const double* w, int64_t n,
+                                  int64_t ldp, const int64_t* gn, double amp, const Epi& epi, double mu64, float* y,
+                                  float* k, uint8_t* ind, double* y64, double* k64, hipStream_t s)
 {
     const int64_t C = gn[0] * gn[1] * gn[2];
     const int64_t blocks = (C + 255) / 256;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_direct_grid_f64, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, tx, ty, tz,
+    hipLaunchKernelGGL(k_direct_grid_f64, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, tx, ty, tz, w,
                        static_cast<int>(n), ldp, static_cast<int>(gn[0]), static_cast<int>(gn[1]), C, amp, epi, mu64,
                        y, k, ind, y64, k64);
     return hipGetLastError();
 }
 
-hipError_t launch_direct_points(const double* params, int64_t n, int dim, const double* xyz, int64_t P, bool fp64,
-                                float amp, const Epi& epi, float* y, float* k, uint8_t* ind, float* partial,
-                                hipStream_t s)
+hipError_t launch_direct_points(const double* params, const double* w, int64_t n, int dim, const double* xyz,
+                                int64_t P, bool fp64, float amp, const Epi& epi, float* y, float* k, uint8_t* ind,
+                                float* partial, hipStream_t s)
 {
     const double4* prm = reinterpret_cast<const double4*>(params);
     if (fp64) {
         const int64_t blocks = (P + 255) / 256;
         if (blocks > 0x7fffffff) return hipErrorInvalidValue;
         if (dim == 3)
-            hipLaunchKernelGGL(k_direct_points_f64<3>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, prm,
+            hipLaunchKernelGGL(k_direct_points_f64<3>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, prm, w,
                                static_cast<int>(n), xyz, P, static_cast<double>(amp), epi, y, k, ind);
         else
-            hipLaunchKernelGGL(k_direct_points_f64<2>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, prm,
+            hipLaunchKernelGGL(k_direct_points_f64<2>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, prm, w,
                                static_cast<int>(n), xyz, P, static_cast<double>(amp), epi, y, k, ind);
         return hipGetLastError();
     }
@@ -364,11 +383,11 @@ hipError_t launch_direct_points(const double* params, int64_t n, int dim, const 
     float* part = slices > 1 ? partial : nullptr;
     const dim3 g(static_cast<unsigned>(blocks), static_cast<unsigned>(slices));
     if (dim == 3)
-        hipLaunchKernelGGL((k_direct_points<3, R>), g, dim3(256), 0, s, prm, static_cast<int>(n), xyz, P, amp, epi, y,
-                           k, ind, mslice, part);
+        hipLaunchKernelGGL((k_direct_points<3, R>), g, dim3(256), 0, s, prm, w, static_cast<int>(n), xyz, P, amp, epi,
+                           y, k, ind, mslice, part);
     else
-        hipLaunchKernelGGL((k_direct_points<2, R>), g, dim3(256), 0, s, prm, static_cast<int>(n), xyz, P, amp, epi, y,
-                           k, ind, mslice, part);
+        hipLaunchKernelGGL((k_direct_points<2, R>), g, dim3(256), 0, s, prm, w, static_cast<int>(n), xyz, P, amp, epi,
+                           y, k, ind, mslice, part);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess || slices == 1) return e;
     hipLaunchKernelGGL(k_points_reduce, dim3(static_cast<unsigned>((P + 255) / 256)), dim3(256), 0, s, partial, slices,

@@ -137,6 +137,7 @@ struct AxisTableArgs {
     int format;
     void* out;      // primary table
     void* out_lo;   // lo table for *_HILO formats
+    const double* w;  // per-mode weights folded into complex entries (exp(i 2 pi f) * w_j), or nullptr
 };
 hipError_t launch_axis_table(const AxisTableArgs& a, hipStream_t s);
 hipError_t launch_axis_tables(const AxisTableArgs* d, int nd, hipStream_t s);  // nd <= 3, one launch
@@ -167,16 +168,17 @@ hipError_t launch_mode_params(const double* z, const double* phi, int dim, int64
                               const double* ell, double* out, hipStream_t s);
 
 // ---------------------------------------------------------------- direct kernels
-hipError_t launch_direct_grid_f32(const float* tx, const float* ty, const float* tz, int64_t n,
+// `w`: device per-mode weights [n] or nullptr (all 1).
+hipError_t launch_direct_grid_f32(const float* tx, const float* ty, const float* tz, const double* w, int64_t n,
                                   int64_t ldp, const int64_t* gn, float amp, const Epi& epi,
                                   float* y, float* k, uint8_t* ind, hipStream_t s);
-hipError_t launch_direct_grid_f64(const double* tx, const double* ty, const double* tz, int64_t n,
+hipError_t launch_direct_grid_f64(const double* tx, const double* ty, const double* tz, const double* w, int64_t n,
                                   int64_t ldp, const int64_t* gn, double amp, const Epi& epi,
                                   double mu64, float* y, float* k, uint8_t* ind, double* y64,
                                   double* k64, hipStream_t s);
 // `partial` (workspace, points_mode_slices(P, n) * P floats when that is > 1) receives the
 // per-slice sums when the modes are split across blocks.
-hipError_t launch_direct_points(const double* params, int64_t n, int dim, const double* xyz,
+hipError_t launch_direct_points(const double* params, const double* w, int64_t n, int dim, const double* xyz,
                                 int64_t P, bool fp64, float amp, const Epi& epi, float* y, float* k,
                                 uint8_t* ind, float* partial, hipStream_t s);
 constexpr int kPointsPerLane = 4;
@@ -227,6 +229,7 @@ struct DirectBatchItem {
     const float* tx;
     const float* ty;
     const float* tz;
+    const double* w;  // per-mode weights or nullptr
     float* y;
     int64_t ldp;
     int64_t nq;       // ny * nz
@@ -266,6 +269,7 @@ struct BwdArgs {
     float* gk;
     float* gsigma;
     float* gell;
+    const double* w;       // device per-mode weights or nullptr
     const double* rot;     // host row-major 3 x 3 when the table is rotated (z, ell are the
                            // original table's; params hold k = rot diag(1/ell) z), else nullptr
     const float* tx;       // grid path: FP32 revolution tables (psi in ty), or nullptr

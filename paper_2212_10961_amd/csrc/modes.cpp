@@ -163,3 +163,72 @@ extern "C" int snap_periodic(int dim, int64_t n, const double* z, const double* 
     }
     return GRF_OK;
 }
+
+namespace {
+
+// Standardised spectral shape (ell = 1, angular frequency, up to a constant) of App. A:
+// Gaussian exp(-|u|^2 / 4), exponential (1 + |u|^2)^(-(d+1)/2), Matern with 2 nu = dof
+// (1 + |u|^2 / dof)^(-(dof + d)/2).
+double spectral_shape(int cov, int dim, int dof, double r2)
+{
+    if (cov == GRF_COV_GAUSSIAN) return std::exp(-0.25 * r2);
+    if (cov == GRF_COV_EXPONENTIAL) return std::pow(1.0 + r2, -0.5 * (dim + 1));
+    return std::pow(1.0 + r2 / dof, -0.5 * (dof + dim));
+}
+
+}  // namespace
+
+extern "C" int make_modes_lattice(const grf_spec* spec, int32_t m, double du, double* z_out, double* phi_out,
+                                  double* w_out)
+{
+    using grf::fail;
+    if (!spec) return fail(GRF_EINVAL, "make_modes_lattice: spec is NULL");
+    const int dim = spec->dim;
+    if (dim != 2 && dim != 3) return fail(GRF_EINVAL, "make_modes_lattice: dim must be 2 or 3 (got %d)", dim);
+    if (m < 2 || (m & 1) || m > (1 << 20)) return fail(GRF_EINVAL, "make_modes_lattice: m must be even, 2 .. 2^20");
+    if (!(du > 0.0) || !std::isfinite(du)) return fail(GRF_EINVAL, "make_modes_lattice: du must be finite and > 0");
+    if (!z_out || !phi_out || !w_out) return fail(GRF_EINVAL, "make_modes_lattice: output pointer is NULL");
+    const int64_t half = m / 2;
+    const int64_t n = dim == 3 ? half * m * m : half * m;
+    if (spec->n_modes != n)
+        return fail(GRF_EINVAL, "make_modes_lattice: n_modes must be m^dim / 2 = %lld", static_cast<long long>(n));
+    int dof = 0;
+    switch (spec->cov) {
+    case GRF_COV_GAUSSIAN:
+    case GRF_COV_EXPONENTIAL: break;
+    case GRF_COV_MATERN: {
+        const double t = 2.0 * spec->nu;
+        dof = static_cast<int>(std::lround(t));
+        if (!(t > 0.0) || std::fabs(t - dof) > 1e-12 || dof < 1 || dof > 64)
+            return fail(GRF_EINVAL, "make_modes_lattice: Matern needs 2*nu an integer in [1, 64] (nu = %g)", spec->nu);
+        break;
+    }
+    default: return fail(GRF_EINVAL, "make_modes_lattice: unknown covariance %d", spec->cov);
+    }
+
+    // lattice coordinates and the normalisation of p_j = S(u_j) / sum S (w_out holds S first)
+    double total = 0.0;
+    for (int64_t j = 0; j < n; ++j) {
+        const int64_t i0 = j % half, rest = j / half;
+        const int64_t i1 = rest % m, i2 = rest / m;
+        const double u0 = du * (static_cast<double>(i0) + 0.5);
+        const double u1 = du * (static_cast<double>(i1 - half) + 0.5);
+        const double u2 = dim == 3 ? du * (static_cast<double>(i2 - half) + 0.5) : 0.0;
+        z_out[j] = u0;
+        z_out[n + j] = u1;
+        if (dim == 3) z_out[2 * n + j] = u2;
+        const double s = spectral_shape(spec->cov, dim, dof, u0 * u0 + u1 * u1 + u2 * u2);
+        w_out[j] = s;
+        total += s;
+    }
+    const Philox gen{static_cast<uint32_t>(spec->seed), static_cast<uint32_t>(spec->seed >> 32)};
+    for (int64_t j = 0; j < n; ++j) {
+        double g[2];
+        box_muller(gen, static_cast<uint64_t>(j), 1u, g);  // (W_j, W'_j)
+        double ph = -std::atan2(g[1], g[0]);
+        if (ph < 0.0) ph += kTwoPi;
+        phi_out[j] = ph;
+        w_out[j] = std::sqrt(w_out[j] / total * (g[0] * g[0] + g[1] * g[1]) * 0.5 * static_cast<double>(n));
+    }
+    return GRF_OK;
+}

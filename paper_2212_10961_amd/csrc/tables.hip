@@ -45,7 +45,7 @@ constexpr int kTabRows = 16;
 // so no field is re-read from memory between the stores.
 template <int FMT, bool FAST, bool BLOCKED>
 __device__ __forceinline__ void axis_table_rows(const AxisTableArgs a, int64_t i0, int64_t i1, int64_t j, double az,
-                                                double ps, bool zero)
+                                                double ps, double wj, bool zero)
 {
     const double sgn = a.conj ? -1.0 : 1.0;
     for (int64_t i = i0; i < i1; ++i) {
@@ -63,8 +63,9 @@ __device__ __forceinline__ void axis_table_rows(const AxisTableArgs a, int64_t i
             // one rounding to the table format: the hardware cos/sin of the FP64-reduced
             // fraction in revolutions (|err| ~1e-7) is far below it
             const float fr = static_cast<float>(f);
-            const float cs = zero ? 0.f : __builtin_amdgcn_cosf(fr);
-            const float sn = zero ? 0.f : __builtin_amdgcn_sinf(fr) * static_cast<float>(sgn);
+            const float wf = static_cast<float>(wj);
+            const float cs = zero ? 0.f : __builtin_amdgcn_cosf(fr) * wf;
+            const float sn = zero ? 0.f : __builtin_amdgcn_sinf(fr) * static_cast<float>(sgn) * wf;
             if constexpr (FMT == TF_CPLX_F32) static_cast<float2*>(a.out)[e] = make_float2(cs, sn);
             else if constexpr (FMT == TF_F16) static_cast<uint32_t*>(a.out)[e] = pack_half2(cs, sn);
             else static_cast<uint32_t*>(a.out)[e] = pack_bf162(cs, sn);
@@ -72,7 +73,8 @@ __device__ __forceinline__ void axis_table_rows(const AxisTableArgs a, int64_t i
             double sn, cs;
             sincospi(2.0 * f, &sn, &cs);
             if (zero) { sn = 0.0; cs = 0.0; }
-            sn *= sgn;
+            sn *= sgn * wj;
+            cs *= wj;
             if constexpr (FMT == TF_CPLX_F32) {
                 static_cast<float2*>(a.out)[e] = make_float2(static_cast<float>(cs), static_cast<float>(sn));
             } else if constexpr (FMT == TF_F16 || FMT == TF_F16_HILO) {
@@ -98,14 +100,14 @@ __device__ __forceinline__ void axis_table_rows(const AxisTableArgs a, int64_t i
 
 template <int FMT>
 __device__ __forceinline__ void axis_table_rows_t(const AxisTableArgs& a, int64_t i0, int64_t i1, int64_t j,
-                                                  double az, double ps, bool zero)
+                                                  double az, double ps, double wj, bool zero)
 {
     if (a.blocked) {
-        if (a.fast_trig) axis_table_rows<FMT, true, true>(a, i0, i1, j, az, ps, zero);
-        else axis_table_rows<FMT, false, true>(a, i0, i1, j, az, ps, zero);
+        if (a.fast_trig) axis_table_rows<FMT, true, true>(a, i0, i1, j, az, ps, wj, zero);
+        else axis_table_rows<FMT, false, true>(a, i0, i1, j, az, ps, wj, zero);
     } else {
-        if (a.fast_trig) axis_table_rows<FMT, true, false>(a, i0, i1, j, az, ps, zero);
-        else axis_table_rows<FMT, false, false>(a, i0, i1, j, az, ps, zero);
+        if (a.fast_trig) axis_table_rows<FMT, true, false>(a, i0, i1, j, az, ps, wj, zero);
+        else axis_table_rows<FMT, false, false>(a, i0, i1, j, az, ps, wj, zero);
     }
 }
 
@@ -117,21 +119,22 @@ __device__ __forceinline__ void axis_table_block(const AxisTableArgs a, int64_t 
     const int64_t j = (w - rg * jchunks) * 256 + threadIdx.x;
     if (j >= a.ldp) return;
     const bool zero = j >= a.n;
-    double az = 0.0, ps = 0.0;
+    double az = 0.0, ps = 0.0, wj = 1.0;
     if (!zero) {
         if (a.z) az = a.z[static_cast<int64_t>(a.axis) * a.n + j] * a.freq_scale;
         if (a.with_psi) ps = a.phi[j] * kInvTwoPi;
+        if (a.w) wj = a.w[j];
     }
     const int64_t i0 = rg * kTabRows;
     const int64_t i1 = min(i0 + kTabRows, a.count);
     switch (a.format) {
-    case TF_REV_F32: axis_table_rows<TF_REV_F32, true, false>(a, i0, i1, j, az, ps, zero); break;
-    case TF_REV_F64: axis_table_rows<TF_REV_F64, true, false>(a, i0, i1, j, az, ps, zero); break;
-    case TF_CPLX_F32: axis_table_rows_t<TF_CPLX_F32>(a, i0, i1, j, az, ps, zero); break;
-    case TF_F16: axis_table_rows_t<TF_F16>(a, i0, i1, j, az, ps, zero); break;
-    case TF_F16_HILO: axis_table_rows_t<TF_F16_HILO>(a, i0, i1, j, az, ps, zero); break;
-    case TF_BF16: axis_table_rows_t<TF_BF16>(a, i0, i1, j, az, ps, zero); break;
-    default: axis_table_rows_t<TF_BF16_HILO>(a, i0, i1, j, az, ps, zero); break;
+    case TF_REV_F32: axis_table_rows<TF_REV_F32, true, false>(a, i0, i1, j, az, ps, wj, zero); break;
+    case TF_REV_F64: axis_table_rows<TF_REV_F64, true, false>(a, i0, i1, j, az, ps, wj, zero); break;
+    case TF_CPLX_F32: axis_table_rows_t<TF_CPLX_F32>(a, i0, i1, j, az, ps, wj, zero); break;
+    case TF_F16: axis_table_rows_t<TF_F16>(a, i0, i1, j, az, ps, wj, zero); break;
+    case TF_F16_HILO: axis_table_rows_t<TF_F16_HILO>(a, i0, i1, j, az, ps, wj, zero); break;
+    case TF_BF16: axis_table_rows_t<TF_BF16>(a, i0, i1, j, az, ps, wj, zero); break;
+    default: axis_table_rows_t<TF_BF16_HILO>(a, i0, i1, j, az, ps, wj, zero); break;
     }
 }
 

@@ -26,7 +26,7 @@ from ._lib import GrfError, check
 __all__ = [
     "Modes", "make_modes", "modes_from_tables", "field_grid", "field_grid_f64", "field_points",
     "epilogue", "field_backward", "field_backward_grid", "GRFPoints", "Plan", "method_id", "sep_tiles",
-    "trunc2", "pluri_grid", "pluri_points", "pluri_apply", "snap_periodic",
+    "trunc2", "pluri_grid", "pluri_points", "pluri_apply", "snap_periodic", "make_modes_lattice",
     "GAUSSIAN", "EXPONENTIAL", "MATERN", "GrfError", "version", "paper_lambda_to_ell",
 ]
 
@@ -71,12 +71,14 @@ class Modes:
     """A device-resident mode table plus the scalars of the field.
 
     ``rot`` (optional dim x dim matrix) gives the general anisotropy k = rot diag(1/ell) z;
-    with an orthonormal rot the covariance's principal axes are its columns."""
+    with an orthonormal rot the covariance's principal axes are its columns.  ``w`` (optional
+    float64 [n] device tensor) weights each mode: Y = sigma sqrt(2/N) sum_j w_j cos(...)."""
     z: torch.Tensor      # float64 [dim][n] on the GPU
     phi: torch.Tensor    # float64 [n] on the GPU
     sigma: float
     ell: Sequence[float]
     rot: Optional[np.ndarray] = None
+    w: Optional[torch.Tensor] = None
 
     @property
     def dim(self) -> int:
@@ -95,6 +97,10 @@ class Modes:
         m.sigma = float(self.sigma)
         e = list(self.ell) + [1.0] * (3 - len(self.ell))
         m.ell = (ctypes.c_double * 3)(*[float(v) for v in e[:3]])
+        if self.w is not None:
+            if self.w.dtype != torch.float64 or self.w.numel() != self.n or not self.w.is_contiguous():
+                raise ValueError("w must be a contiguous float64 [n] device tensor")
+            m.w = self.w.data_ptr()
         if self.rot is not None:
             r = np.eye(3)
             rr = np.asarray(self.rot, dtype=np.float64)
@@ -116,10 +122,26 @@ def make_modes(dim: int, cov: int, n_modes: int, seed: int, nu: float = 0.5):
     return z, phi
 
 
-def modes_from_tables(z, phi, sigma: float, ell, device="cuda", rot=None) -> Modes:
+def modes_from_tables(z, phi, sigma: float, ell, device="cuda", rot=None, w=None) -> Modes:
     zt = torch.as_tensor(np.ascontiguousarray(z), dtype=torch.float64).to(device).contiguous()
     pt = torch.as_tensor(np.ascontiguousarray(phi), dtype=torch.float64).to(device).contiguous()
-    return Modes(zt, pt, float(sigma), [float(v) for v in ell], None if rot is None else np.asarray(rot, float))
+    wt = None if w is None else torch.as_tensor(np.ascontiguousarray(w), dtype=torch.float64).to(device).contiguous()
+    return Modes(zt, pt, float(sigma), [float(v) for v in ell], None if rot is None else np.asarray(rot, float), wt)
+
+
+def make_modes_lattice(dim: int, cov: int, m: int, du: float, seed: int, nu: float = 0.5):
+    """Fixed-frequency Gaussian-weight table (z, phi, w) on the half-space lattice of
+    m^dim / 2 points with spacing du (library sampler, host numpy arrays)."""
+    n = (m // 2) * m ** (dim - 1)
+    spec = L.GrfSpec()
+    spec.dim, spec.cov, spec.n_modes, spec.seed, spec.nu = dim, cov, n, seed, float(nu)
+    spec.sigma2 = 1.0
+    spec.ell = (ctypes.c_double * 3)(1.0, 1.0, 1.0)
+    z = np.empty((dim, n))
+    phi, w = np.empty(n), np.empty(n)
+    check(L.load().make_modes_lattice(ctypes.byref(spec), m, float(du), z.ctypes.data, phi.ctypes.data,
+                                      w.ctypes.data))
+    return z, phi, w
 
 
 def snap_periodic(z, ell, period, rot=None):

@@ -390,3 +390,25 @@ def test_snap_periodic_validation(lib):
     e0 = np.array([1.0, 0.0, 1.0])
     assert lib.snap_periodic(2, 4, z.ctypes.data, e0.ctypes.data, None, per.ctypes.data, out.ctypes.data) == L.GRF_EINVAL
     assert lib.snap_periodic(2, 4, z.ctypes.data, ell.ctypes.data, None, per.ctypes.data, None) == L.GRF_EINVAL
+
+
+@pytest.mark.parametrize("dim,cov,nu", [(2, wl.GAUSSIAN, 0.5), (3, wl.EXPONENTIAL, 0.5), (2, wl.MATERN, 1.5)])
+def test_make_modes_lattice_matches_oracle(lib, orc, dim, cov, nu):
+    import paper_2212_10961_amd.grf as grf
+    m, du, seed = 10, 0.45, 77 + dim
+    z, phi, w = grf.make_modes_lattice(dim, cov, m, du, seed, nu=nu)
+    ref = orc.lattice_modes(dim, cov, m, du, seed, nu=nu)
+    np.testing.assert_array_equal(z, ref["z"])
+    np.testing.assert_allclose(phi, ref["phi"], rtol=2e-15, atol=0)
+    np.testing.assert_allclose(w, ref["w"], rtol=1e-13, atol=0)
+
+
+def test_make_modes_lattice_validation(lib):
+    z, p, w = np.empty(64), np.empty(32), np.empty(32)
+    s = _spec(dim=2, n_modes=32)
+    assert lib.make_modes_lattice(ctypes.byref(s), 8, 0.5, z.ctypes.data, p.ctypes.data, w.ctypes.data) == 0
+    assert lib.make_modes_lattice(ctypes.byref(s), 7, 0.5, z.ctypes.data, p.ctypes.data, w.ctypes.data) == L.GRF_EINVAL
+    assert lib.make_modes_lattice(ctypes.byref(s), 8, 0.0, z.ctypes.data, p.ctypes.data, w.ctypes.data) == L.GRF_EINVAL
+    s2 = _spec(dim=2, n_modes=33)
+    assert lib.make_modes_lattice(ctypes.byref(s2), 8, 0.5, z.ctypes.data, p.ctypes.data, w.ctypes.data) == L.GRF_EINVAL
+    assert lib.make_modes_lattice(ctypes.byref(s), 8, 0.5, None, p.ctypes.data, w.ctypes.data) == L.GRF_EINVAL
