@@ -26,7 +26,10 @@ the passage of Icardi et al. (2022) that it follows:
   space, named as the extension of the per-axis rescaling in Sec. 4.1;
 - ``snap_periodic``: the "periodic" option of App. B as wavevectors on the box's lattice;
 - ``lattice_modes`` / ``field_points_w``: the fixed-frequency, Gaussian-weight form of
-  Sec. 4.1 eq. DiscreteFT (frequencies on a lattice, weights W, W') and the weighted sum.
+  Sec. 4.1 eq. DiscreteFT (frequencies on a lattice, weights W, W') and the weighted sum;
+- ``correlation`` / ``krige_weights`` / ``krige_correction``: conditioning a realisation on
+  observations by kriging its residuals (named as future work in Sec. 6), written in numpy
+  with a library linear solve.
 
 Parity pins for this module are the ``-m "not gpu"`` tests in
 ``tests/test_oracle_pins.py``; none of them re-types the formulas above.
@@ -34,6 +37,7 @@ Parity pins for this module are the ``-m "not gpu"`` tests in
 from __future__ import annotations
 
 import ctypes
+import math
 import os
 import subprocess
 from pathlib import Path
@@ -392,6 +396,55 @@ def field_points_w(z, phi, w, sigma, ell, x):
     lib.orc_field_points_w(dim, n, _dp(z), _dp(phi), _dp(w), float(sigma), _dp(_ell(ell, dim)), x.shape[0],
                            _dp(x), _dp(y))
     return y
+
+
+def correlation(cov: int, r, nu: float = 0.5):
+    """Correlation rho(r) of the standardised covariance (App. A; r = |M^T dx|, ell = 1):
+    Gaussian exp(-r^2), exponential exp(-r), Matern nu = 3/2: (1 + sqrt3 r) exp(-sqrt3 r),
+    nu = 5/2: (1 + sqrt5 r + 5 r^2 / 3) exp(-sqrt5 r) (the closed forms of the Matern family
+    whose spectrum the sampler draws: a Student t with 2 nu degrees of freedom)."""
+    r = np.asarray(r, dtype=np.float64)
+    if cov == GAUSSIAN:
+        return np.exp(-r * r)
+    if cov == EXPONENTIAL or (cov == MATERN and nu == 0.5):
+        return np.exp(-r)
+    if cov == MATERN and nu == 1.5:
+        a = math.sqrt(3.0) * r
+        return (1.0 + a) * np.exp(-a)
+    if cov == MATERN and nu == 2.5:
+        a = math.sqrt(5.0) * r
+        return (1.0 + a + a * a / 3.0) * np.exp(-a)
+    raise ValueError("correlation: Gaussian, exponential or Matern nu in {1/2, 3/2, 5/2}")
+
+
+def _lag_norm(dx, ell, rot):
+    """|M^T dx| with M = R diag(1/ell): the standardised lag of k = M z (Sec. 4.1 anisotropy)."""
+    dim = dx.shape[-1]
+    R = np.eye(dim) if rot is None else np.asarray(rot, dtype=np.float64)[:dim, :dim]
+    u = (dx @ R) / np.asarray(ell, dtype=np.float64)[:dim]
+    return np.sqrt((u * u).sum(axis=-1))
+
+
+def krige_weights(cov, sigma, ell, xobs, resid, nugget=0.0, rot=None, nu=0.5):
+    """Simple-kriging weights alpha = (C(X,X) + nugget sigma^2 I)^-1 r of the residuals r = d - Y(X),
+    C(x, x') = sigma^2 rho(|M^T (x - x')|) (conditioning by kriging; the paper lists conditioning
+    on data as future work, Sec. 6).  numpy.linalg.solve is the library step."""
+    xobs = _f64(xobs)
+    d = xobs[:, None, :] - xobs[None, :, :]
+    C = sigma * sigma * correlation(cov, _lag_norm(d, ell, rot), nu)
+    C[np.diag_indices_from(C)] += nugget * sigma * sigma
+    return np.linalg.solve(C, _f64(resid))
+
+
+def krige_correction(cov, sigma, ell, xobs, alpha, x, rot=None, nu=0.5):
+    """sum_i alpha_i C(x - x_i) at points x[P][dim] (added to the unconditional field)."""
+    x = _f64(x)
+    xobs = _f64(xobs)
+    out = np.empty(x.shape[0])
+    for s0 in range(0, x.shape[0], 4096):
+        d = x[s0:s0 + 4096, None, :] - xobs[None, :, :]
+        out[s0:s0 + 4096] = (sigma * sigma * correlation(cov, _lag_norm(d, ell, rot), nu)) @ _f64(alpha)
+    return out
 
 
 def grid_centres(shape, origin=None, h=None):

@@ -610,3 +610,67 @@ def test_lattice_covariance_and_riemann_limit(orc):
     mean, se = prods.mean(axis=0), prods.std(axis=0) / math.sqrt(R)
     for a, b, e in zip(mean, want, se):
         assert abs(a - b) < 4.5 * e, (mean, want, se)
+
+
+# ------------------------------------------------------------------ conditioning by kriging
+
+@pytest.mark.parametrize("nu", [1.5, 2.5])
+def test_matern_closed_forms_match_bessel(orc, nu):
+    """Matern correlation of the t_{2 nu} spectrum: 2^(1-nu)/Gamma(nu) (sqrt(2nu) r)^nu K_nu(sqrt(2nu) r)."""
+    r = np.linspace(1e-6, 6.0, 200)
+    a = math.sqrt(2 * nu) * r
+    want = 2 ** (1 - nu) / sps.gamma(nu) * a ** nu * sps.kv(nu, a)
+    np.testing.assert_allclose(orc.correlation(wl.MATERN, r, nu), want, rtol=1e-12, atol=1e-15)
+    np.testing.assert_allclose(orc.correlation(wl.MATERN, r, 0.5), np.exp(-r), rtol=1e-15)
+
+
+def test_matern_closed_form_is_the_sampler_covariance(orc):
+    """The empirical characteristic function of the nu = 3/2 sampler equals the closed form."""
+    z, _ = orc.sample_modes(2, wl.MATERN, 200_000, 951, nu=1.5)
+    for r in (0.3, 1.0, 2.0):
+        emp = np.mean(np.cos(r * z[0]))
+        assert abs(emp - float(orc.correlation(wl.MATERN, r, 1.5))) < 5e-3
+
+
+def test_kriging_interpolates_and_single_observation_closed_form(orc):
+    z, phi = orc.sample_modes(2, wl.EXPONENTIAL, 200, 952)
+    ell, sigma = np.array([8.0, 4.0]), 1.3
+    R = orc.rotation_matrix(2, (0.4,))
+    xo = wl.points_uniform(12, (60.0, 60.0), 953)
+    d = np.random.default_rng(954).normal(size=12)
+    yu = orc.field_points_mat(z, phi, sigma, R @ np.diag(1 / ell), xo)
+    a = orc.krige_weights(wl.EXPONENTIAL, sigma, ell, xo, d - yu, rot=R)
+    yc = yu + orc.krige_correction(wl.EXPONENTIAL, sigma, ell, xo, a, xo, rot=R)
+    np.testing.assert_allclose(yc, d, rtol=0, atol=1e-10)  # honours the data
+    # one observation: Y_c(x) = Y_u(x) + rho(x - x1) (d1 - Y_u(x1))
+    x = wl.points_uniform(50, (60.0, 60.0), 955)
+    a1 = orc.krige_weights(wl.GAUSSIAN, sigma, ell, xo[:1], d[:1] - yu[:1], rot=R)
+    corr = orc.krige_correction(wl.GAUSSIAN, sigma, ell, xo[:1], a1, x, rot=R)
+    u = ((x - xo[0]) @ R) / ell
+    want = np.exp(-(u * u).sum(axis=1)) * (d[0] - yu[0])
+    np.testing.assert_allclose(corr, want, rtol=1e-12, atol=1e-14)
+
+
+def test_kriging_conditional_variance(orc):
+    """Over realisations of the unconditional field, the conditioned field at x has variance
+    sigma^2 - c(x)^T C^-1 c(x) (simple kriging variance) and zero variance at the data."""
+    ell, sigma, R = np.array([5.0, 5.0]), 1.0, 3000
+    xo = np.array([[10.0, 10.0], [14.0, 11.0], [9.0, 16.0]])
+    x = np.array([[12.0, 12.0], [30.0, 30.0], [10.0, 10.0]])
+    d = np.array([0.5, -0.2, 1.0])
+    vals = np.empty((R, 3))
+    for r in range(R):
+        z, phi = orc.sample_modes(2, wl.GAUSSIAN, 64, 60_000 + r)
+        yu_o = orc.field_points(z, phi, sigma, ell, xo)
+        a = orc.krige_weights(wl.GAUSSIAN, sigma, ell, xo, d - yu_o)
+        vals[r] = orc.field_points(z, phi, sigma, ell, x) + orc.krige_correction(wl.GAUSSIAN, sigma, ell, xo, a, x)
+    Cm = np.exp(-(((xo[:, None] - xo[None]) / ell) ** 2).sum(-1))
+    for i in range(3):
+        c = np.exp(-(((x[i] - xo) / ell) ** 2).sum(-1))
+        var = sigma ** 2 * (1 - c @ np.linalg.solve(Cm, c))
+        v = vals[:, i].var()
+        if var < 1e-12:
+            assert v < 1e-20
+        else:
+            # sampling error of a variance: sd ~ var sqrt(2/R) (kurtosis of the finite-mode field)
+            assert abs(v - var) < 5 * var * math.sqrt(2.0 / R) + 1e-3, (i, v, var)
