@@ -67,8 +67,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline (oracle) leg")
     ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
     ap.add_argument("--only", default=None, help="time a single grid method (profiling runs)")
-    ap.add_argument("--extras", default="points,epilogue,adjoint,pluri,batch",
-                    help="comma-separated extra workloads to time (points, epilogue, adjoint, pluri, batch)")
+    ap.add_argument("--extras", default="points,epilogue,adjoint,pluri,krige,batch",
+                    help="comma-separated extra workloads to time (points, epilogue, adjoint, pluri, krige, batch)")
     ap.add_argument("--extras-only", action="store_true", help="skip the headline workload (profiling runs)")
     ap.add_argument("--spinup-ms", type=float, default=500.0,
                     help="untimed GPU work before the first timed loop (steady clocks)")
@@ -260,6 +260,8 @@ def extras(args, grf, wl, torch, np, dev):
         out.update(adjoint_extra(grf, wl, torch, np, dev))
     if "pluri" in sel:
         out.update(pluri_extra(grf, wl, torch, np, dev))
+    if "krige" in sel:
+        out.update(krige_extra(grf, wl, torch, np, dev))
     if "batch" in sel:
         try:
             out["batch512_2d"] = batch_extra(grf, wl, torch, np, dev)
@@ -364,6 +366,37 @@ def pluri_extra(grf, wl, torch, np, dev):
         "bound": "hbm", "achieved": nbytes / (kms * 1e-3) / 1e9, "peak": HBM_PEAK / 1e9, "unit": "GB/s",
         "frac": nbytes / (kms * 1e-3) / HBM_PEAK, "algorithmic": "2 x 4 B read + 1 B facies + 4 B value per cell"}}
     return {"pluri_2d_1024x512": res}
+
+
+def krige_extra(grf, wl, torch, np, dev):
+    # conditioning the 128^3 model field (seed 5) on 2,000 of the adjoint workload's observation
+    # cells, valued from the target field (seed 50): FP64 Cholesky of the 2000 x 2000 system and
+    # the FP32 correction sum over every cell (one sqrt and one exp2 per cell-observation pair)
+    c = wl.WORKLOADS["adjoint_grid3d_128"]
+    log("[bench] extras: krige_grid3d_128")
+    sg = math.sqrt(c["sigma2"])
+    z, phi = grf.make_modes(3, c["cov"], c["n_modes"], c["seed"])
+    m = grf.modes_from_tables(z, phi, sg, c["ell"], device=dev)
+    zt, pt = grf.make_modes(3, c["cov"], c["n_modes"], c["target_seed"])
+    mt = grf.modes_from_tables(zt, pt, sg, c["ell"], device=dev)
+    Cg = int(np.prod(c["shape"]))
+    M = 2000
+    cells = wl.distinct_cells(Cg, c["n_obs"], c["obs_seed"])[:M]
+    ii = np.stack([cells % 128, (cells // 128) % 128, cells // (128 * 128)], axis=1)
+    xo = torch.from_numpy(np.ascontiguousarray(ii + 0.5)).to(dev)
+    dobs = grf.field_points(mt, xo)["y"]
+    y = grf.field_grid(m, c["shape"], method="direct_f32")["y"]
+    w_ms, w_k = _timed(torch, grf, lambda: grf.krige_weights(m, xo, dobs, c["cov"]), 5, 1)
+    alpha, info = grf.krige_weights(m, xo, dobs, c["cov"])
+    yc = y.clone()
+    a_ms, a_k = _timed(torch, grf, lambda: grf.krige_apply_grid(m, xo, alpha, c["shape"], yc, c["cov"]), 5, 1)
+    pairs = Cg * M
+    trans_peak = COS_PEAK / 2.0  # two transcendentals (sqrt, exp2) per pair at half rate
+    return {"krige_grid3d_128": {
+        "n_obs": M, "cholesky_info": int(info.item()), "weights_ms": w_ms, "cholesky_and_solve_ms": w_k,
+        "apply_ms": a_ms, "apply_pairs_per_s": pairs / (a_k * 1e-3),
+        "apply_roofline": {"bound": "alu", "achieved": pairs / (a_k * 1e-3), "peak": trans_peak,
+                           "unit": "cell·obs pair/s", "frac": pairs / (a_k * 1e-3) / trans_peak}}}
 
 
 def batch_extra(grf, wl, torch, np, dev):

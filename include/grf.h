@@ -305,6 +305,51 @@ int field_backward_grid(const grf_modes* modes, const grf_grid* grid, const floa
                         float* grad_ell, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * Conditioning on observations by kriging the residuals (the paper lists conditioning on
+ * data as future work, Sec. 6): with observations d_i at x_i (i < M) and a realisation Y,
+ *   alpha = (C(X, X) + nugget sigma^2 I)^-1 (d - Y(X)),   Y_c(x) = Y(x) + sum_i alpha_i C(x - x_i),
+ * where C(dx) = sigma^2 rho(|M^T dx|) is the model covariance of the table's field
+ * (M = diag(1/ell), or rot diag(1/ell) for rotated tables; rho of App. A).  Y_c honours the
+ * data (exactly for nugget 0, up to the forward path's error) and, over realisations, has the
+ * simple-kriging conditional covariance.
+ */
+typedef struct grf_krige {
+    int32_t cov;     /* GRF_COV_GAUSSIAN, GRF_COV_EXPONENTIAL, or GRF_COV_MATERN with nu 1/2, 3/2, 5/2 */
+    int32_t pad_;
+    double nu;       /* Matern smoothness (ignored otherwise) */
+    double nugget;   /* >= 0: nugget * sigma^2 is added to the diagonal of C(X, X) */
+} grf_krige;
+
+/* Workspace of krige_weights: the FP64 M x M matrix, residuals, and the point evaluation of Y. */
+int krige_weights_ws_size(const grf_modes* modes, int64_t n_obs, size_t* bytes);
+
+/*
+ * krige_weights -- alpha for M observations (M >= 1, at most 1,048,560).
+ *   xobs   device double[M][dim];  dobs device float[M] (observed values of Y, i.e. ln K - mu).
+ *   alpha  device double[M], written.
+ *   info   device int32 or NULL: 0, or the 1-based index of the first non-positive pivot of
+ *          the Cholesky factorisation (C(X, X) + nugget not positive definite: alpha is NaN).
+ * Y(X) is evaluated by the FP32 direct point sum of `modes`; the system is factorised in FP64.
+ */
+int krige_weights(const grf_modes* modes, const grf_krige* kp, const double* xobs, const float* dobs, int64_t n_obs,
+                  double* alpha, int32_t* info, void* ws, size_t ws_bytes, void* stream);
+
+/* Workspace of krige_apply_grid / krige_apply_points: 16 bytes per observation. */
+int krige_apply_ws_size(int64_t n_obs, size_t* bytes);
+
+/*
+ * krige_apply_grid / krige_apply_points -- y += sum_i alpha_i C(x - x_i) at every cell centre
+ * of `grid` (y device float[C], x fastest) or at points xyz (device double[P][dim], y float[P]).
+ * Run after eval_field_grid / eval_field_points of the same table for Y_c.  Lags are formed in
+ * FP64 from the first observation and summed in FP32.
+ */
+int krige_apply_grid(const grf_modes* modes, const grf_krige* kp, const double* xobs, const double* alpha,
+                     int64_t n_obs, const grf_grid* grid, float* y, void* ws, size_t ws_bytes, void* stream);
+int krige_apply_points(const grf_modes* modes, const grf_krige* kp, const double* xobs, const double* alpha,
+                       int64_t n_obs, const double* xyz, int64_t n_points, float* y, void* ws, size_t ws_bytes,
+                       void* stream);
+
+/*
  * Batched ensembles of independent realisations on grids of uneven size, evaluated
  * in one persistent launch (plus the per-axis table build) captured in a hipGraph.
  */

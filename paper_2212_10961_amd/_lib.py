@@ -30,6 +30,7 @@ EXPORTS = [
     "grf_version", "grf_last_error", "make_modes", "make_modes_lattice", "snap_periodic", "eval_field_grid_ws_size", "eval_field_grid",
     "eval_field_grid_tile", "grf_sep_tile_count", "grf_sep_tile_shape",
     "eval_pluri_grid_ws_size", "eval_pluri_grid", "eval_pluri_points_ws_size", "eval_pluri_points", "pluri_apply",
+    "krige_weights_ws_size", "krige_weights", "krige_apply_ws_size", "krige_apply_grid", "krige_apply_points",
     "eval_field_grid_f64", "eval_field_points_ws_size", "eval_field_points", "epilogue_apply",
     "field_backward_ws_size", "field_backward", "field_backward_grid_ws_size", "field_backward_grid",
     "grf_plan_create", "grf_plan_destroy", "eval_field_batch", "grf_plan_info",
@@ -64,6 +65,11 @@ class GrfTrunc2(ctypes.Structure):
                 ("n_s", ctypes.c_int32), ("s", ctypes.c_float * GRF_MAX_THRESHOLDS),
                 ("rule", ctypes.c_uint8 * ((GRF_MAX_THRESHOLDS + 1) ** 2)),
                 ("n_values", ctypes.c_int32), ("values", ctypes.c_float * GRF_MAX_FACIES)]
+
+
+class GrfKrige(ctypes.Structure):
+    _fields_ = [("cov", ctypes.c_int32), ("pad_", ctypes.c_int32), ("nu", ctypes.c_double),
+                ("nugget", ctypes.c_double)]
 
 
 class GrfBatchItem(ctypes.Structure):
@@ -110,6 +116,11 @@ def load():
         "eval_pluri_points": ([P(GrfModes), P(GrfModes), vp, i64, ctypes.c_int, P(GrfTrunc2), vp, vp, vp, vp, vp,
                                sz, vp], ctypes.c_int),
         "pluri_apply": ([vp, vp, i64, P(GrfTrunc2), vp, vp, vp, sz, vp], ctypes.c_int),
+        "krige_weights_ws_size": ([P(GrfModes), i64, P(sz)], ctypes.c_int),
+        "krige_weights": ([P(GrfModes), P(GrfKrige), vp, vp, i64, vp, vp, vp, sz, vp], ctypes.c_int),
+        "krige_apply_ws_size": ([i64, P(sz)], ctypes.c_int),
+        "krige_apply_grid": ([P(GrfModes), P(GrfKrige), vp, vp, i64, P(GrfGrid), vp, vp, sz, vp], ctypes.c_int),
+        "krige_apply_points": ([P(GrfModes), P(GrfKrige), vp, vp, i64, vp, i64, vp, vp, sz, vp], ctypes.c_int),
         "eval_field_grid_f64": ([P(GrfModes), P(GrfGrid), ctypes.c_double, vp, vp, vp, sz, vp], ctypes.c_int),
         "eval_field_points_ws_size": ([P(GrfModes), i64, ctypes.c_int, P(sz)], ctypes.c_int),
         "eval_field_points": ([P(GrfModes), vp, i64, ctypes.c_int, P(GrfEpi), vp, vp, vp, vp, sz, vp],

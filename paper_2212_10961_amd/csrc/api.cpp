@@ -671,6 +671,160 @@ int eval_field_points(const grf_modes* modes, const double* xyz, int64_t n_point
     return points_launch(&am, xyz, n_points, method, make_epi(epi), y, k, ind, static_cast<char*>(ws) + rb, s);
 }
 
+}  // extern "C"
+
+// ---------------------------------------------------------------- conditioning (kriging)
+namespace grf {
+
+constexpr int64_t kMaxObs = 65535 * 16;
+
+static int make_krige_model(const grf_modes* m, const grf_krige* kp, const char* fn, KrigeModel* km)
+{
+    if (!kp) return fail(GRF_EINVAL, "%s: kriging parameters are NULL", fn);
+    KrigeModel r{};
+    if (kp->cov == GRF_COV_GAUSSIAN) r.kind = KR_GAUSS;
+    else if (kp->cov == GRF_COV_EXPONENTIAL) r.kind = KR_EXP;
+    else if (kp->cov == GRF_COV_MATERN) {
+        if (std::fabs(kp->nu - 0.5) < 1e-12) r.kind = KR_EXP;
+        else if (std::fabs(kp->nu - 1.5) < 1e-12) r.kind = KR_M32;
+        else if (std::fabs(kp->nu - 2.5) < 1e-12) r.kind = KR_M52;
+        else return fail(GRF_EUNSUPPORTED, "%s: Matern kriging needs nu = 1/2, 3/2 or 5/2 (got %g)", fn, kp->nu);
+    } else {
+        return fail(GRF_EINVAL, "%s: unknown covariance %d", fn, kp->cov);
+    }
+    if (!(kp->nugget >= 0.0) || !std::isfinite(kp->nugget)) return fail(GRF_EINVAL, "%s: nugget must be >= 0", fn);
+    r.s2 = m->sigma * m->sigma;
+    r.nugget_abs = kp->nugget * r.s2;
+    // M^T with M = R diag(1/ell): (M^T)[b][a] = R[a][b] / ell_b
+    for (int b = 0; b < 3; ++b)
+        for (int a = 0; a < 3; ++a) {
+            double v = 0.0;
+            if (a < m->dim && b < m->dim) v = (m->rotated ? m->rot[3 * a + b] : (a == b ? 1.0 : 0.0)) / m->ell[b];
+            r.mt[3 * b + a] = v;
+        }
+    *km = r;
+    return GRF_OK;
+}
+
+static size_t krige_ws(const grf_modes* m, int64_t M)
+{
+    return align256(sizeof(double) * size_t(M) * size_t(M)) + align256(sizeof(double) * size_t(M)) +
+           align256(sizeof(float) * size_t(M)) + rot_ws_bytes(m) + points_ws_bytes(m->n, M, GRF_DIRECT_F32);
+}
+
+}  // namespace grf
+
+extern "C" {
+
+int krige_weights_ws_size(const grf_modes* modes, int64_t n_obs, size_t* bytes)
+{
+    const char* fn = "krige_weights_ws_size";
+    int rc;
+    if ((rc = check_modes(modes, fn))) return rc;
+    if (!bytes) return fail(GRF_EINVAL, "%s: bytes is NULL", fn);
+    if (n_obs < 1 || n_obs > kMaxObs) return fail(GRF_EINVAL, "%s: n_obs must be in [1, %lld]", fn, (long long)kMaxObs);
+    *bytes = krige_ws(modes, n_obs);
+    return GRF_OK;
+}
+
+int krige_weights(const grf_modes* modes, const grf_krige* kp, const double* xobs, const float* dobs, int64_t n_obs,
+                  double* alpha, int32_t* info, void* ws, size_t ws_bytes, void* stream)
+{
+    const char* fn = "krige_weights";
+    int rc;
+    if ((rc = check_modes(modes, fn))) return rc;
+    KrigeModel km;
+    if ((rc = make_krige_model(modes, kp, fn, &km))) return rc;
+    if (n_obs < 1 || n_obs > kMaxObs) return fail(GRF_EINVAL, "%s: n_obs must be in [1, %lld]", fn, (long long)kMaxObs);
+    if (!xobs || !dobs || !alpha) return fail(GRF_EINVAL, "%s: xobs, dobs and alpha are required", fn);
+    if (!(modes->sigma > 0.0)) return fail(GRF_EINVAL, "%s: sigma must be > 0", fn);
+    const size_t need = krige_ws(modes, n_obs);
+    if (!ws || ws_bytes < need) return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t M = n_obs;
+    Carve c(ws);
+    double* C = c.take<double>(size_t(M) * size_t(M));
+    double* resid = c.take<double>(size_t(M));
+    float* yu = c.take<float>(size_t(M));
+    void* kbuf = c.base + c.used;
+    c.used += rot_ws_bytes(modes);
+    void* pws = c.base + c.used;
+    if (info) GRF_HIP(launch_fill_i32(info, 0, s));
+    grf_modes am;
+    GRF_HIP(aligned_modes(modes, kbuf, s, &am));
+    if ((rc = points_launch(&am, xobs, M, GRF_DIRECT_F32, Epi{}, yu, nullptr, nullptr, pws, s))) return rc;
+    GRF_HIP(launch_residual(dobs, yu, M, resid, s));
+    GRF_HIP(launch_cov_matrix(xobs, M, modes->dim, km, C, M, s));
+    TimedScope timed(s);
+    GRF_HIP(launch_cholesky(C, M, M, info, s));
+    GRF_HIP(launch_chol_solve(C, M, M, resid, alpha, s));
+    return GRF_OK;
+}
+
+int krige_apply_ws_size(int64_t n_obs, size_t* bytes)
+{
+    if (!bytes) return fail(GRF_EINVAL, "krige_apply_ws_size: bytes is NULL");
+    if (n_obs < 1 || n_obs > kMaxObs) return fail(GRF_EINVAL, "krige_apply_ws_size: n_obs out of range");
+    *bytes = align256(sizeof(float) * 4 * size_t(n_obs));
+    return GRF_OK;
+}
+
+static int krige_apply(const char* fn, const grf_modes* modes, const grf_krige* kp, const double* xobs,
+                       const double* alpha, int64_t n_obs, const KrigeTarget& tg, float* y, void* ws, size_t ws_bytes,
+                       void* stream)
+{
+    int rc;
+    KrigeModel km;
+    if ((rc = make_krige_model(modes, kp, fn, &km))) return rc;
+    if (n_obs < 1 || n_obs > kMaxObs) return fail(GRF_EINVAL, "%s: n_obs must be in [1, %lld]", fn, (long long)kMaxObs);
+    if (!xobs || !alpha || !y) return fail(GRF_EINVAL, "%s: xobs, alpha and y are required", fn);
+    const size_t need = align256(sizeof(float) * 4 * size_t(n_obs));
+    if (!ws || ws_bytes < need) return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float4* staged = static_cast<float4*>(ws);
+    GRF_HIP(launch_krige_stage(xobs, alpha, n_obs, modes->dim, km, staged, s));
+    TimedScope timed(s);
+    GRF_HIP(launch_krige_apply(staged, xobs, n_obs, km, tg, y, s));
+    return GRF_OK;
+}
+
+int krige_apply_grid(const grf_modes* modes, const grf_krige* kp, const double* xobs, const double* alpha,
+                     int64_t n_obs, const grf_grid* grid, float* y, void* ws, size_t ws_bytes, void* stream)
+{
+    const char* fn = "krige_apply_grid";
+    int rc;
+    if ((rc = check_modes(modes, fn))) return rc;
+    if ((rc = check_grid(grid, modes->dim, fn))) return rc;
+    KrigeTarget tg{};
+    tg.grid = true;
+    tg.dim = modes->dim;
+    tg.count = grid->n[0] * grid->n[1] * grid->n[2];
+    for (int a = 0; a < 3; ++a) {
+        tg.n[a] = grid->n[a];
+        tg.o[a] = grid->origin[a];
+        tg.h[a] = grid->h[a];
+    }
+    return krige_apply(fn, modes, kp, xobs, alpha, n_obs, tg, y, ws, ws_bytes, stream);
+}
+
+int krige_apply_points(const grf_modes* modes, const grf_krige* kp, const double* xobs, const double* alpha,
+                       int64_t n_obs, const double* xyz, int64_t n_points, float* y, void* ws, size_t ws_bytes,
+                       void* stream)
+{
+    const char* fn = "krige_apply_points";
+    int rc;
+    if ((rc = check_modes(modes, fn))) return rc;
+    if (n_points < 0 || n_points > (int64_t(1) << 40)) return fail(GRF_EINVAL, "%s: n_points out of range", fn);
+    if (n_points == 0) return GRF_OK;
+    if (!xyz) return fail(GRF_EINVAL, "%s: xyz is NULL", fn);
+    KrigeTarget tg{};
+    tg.grid = false;
+    tg.dim = modes->dim;
+    tg.count = n_points;
+    tg.xyz = xyz;
+    return krige_apply(fn, modes, kp, xobs, alpha, n_obs, tg, y, ws, ws_bytes, stream);
+}
+
 int epilogue_apply(const float* y, int64_t n, const grf_epi* epi, float* k, uint8_t* ind, void* stream)
 {
     const char* fn = "epilogue_apply";

@@ -284,4 +284,31 @@ int64_t bwd_chunks(int64_t P);
 inline int64_t bwd_scal_floats(int64_t n) { return 4 * ((n + 255) / 256) + 1024; }
 hipError_t launch_backward(const BwdArgs& a, hipStream_t s);
 
+// ---------------------------------------------------------------- conditioning (kriging)
+enum KrigeKind : int { KR_GAUSS = 0, KR_EXP = 1, KR_M32 = 2, KR_M52 = 3 };
+struct KrigeModel {
+    int kind;           // KrigeKind
+    double s2;          // sigma^2
+    double nugget_abs;  // nugget * sigma^2 on the diagonal
+    double mt[9];       // M^T row-major, M = R diag(1/ell) (dim 2: zero third row/column)
+};
+struct KrigeTarget {
+    bool grid;
+    int dim;
+    int64_t count;      // cells or points
+    int64_t n[3];       // grid
+    double o[3], h[3];
+    const double* xyz;  // points [count][dim]
+};
+hipError_t launch_cov_matrix(const double* x, int64_t m, int dim, const KrigeModel& km, double* C, int64_t lda,
+                             hipStream_t s);
+hipError_t launch_cholesky(double* A, int64_t m, int64_t lda, int32_t* info, hipStream_t s);
+hipError_t launch_chol_solve(const double* L, int64_t m, int64_t lda, const double* b, double* x, hipStream_t s);
+hipError_t launch_residual(const float* d, const float* y, int64_t m, double* r, hipStream_t s);
+hipError_t launch_krige_stage(const double* x, const double* alpha, int64_t m, int dim, const KrigeModel& km,
+                              float4* out, hipStream_t s);
+hipError_t launch_krige_apply(const float4* obs, const double* xobs, int64_t m, const KrigeModel& km,
+                              const KrigeTarget& tg, float* y, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, hipStream_t s);
+
 }  // namespace grf

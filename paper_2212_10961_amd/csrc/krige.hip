@@ -1,0 +1,370 @@
+// Conditioning a realisation on observations by kriging its residuals (the paper names
+// conditioning on data as future work, Sec. 6):
+//   alpha = (C(X, X) + nugget sigma^2 I)^-1 (d - Y(X)),   Y_c(x) = Y(x) + sum_i alpha_i C(x - x_i),
+// with the model covariance C(dx) = sigma^2 rho(|M^T dx|), M = R diag(1/ell) (the same
+// anisotropy as the field's wavevectors k = M z; App. A correlations).
+//
+// The M x M system is factorised in FP64 by a blocked right-looking Cholesky (diagonal block
+// in LDS, panel triangular solve, trailing update), solved by a one-workgroup blocked
+// substitution, and the correction is summed in FP32 with observation chunks staged in LDS.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "grf_internal.h"
+
+namespace grf {
+
+namespace {
+
+constexpr int kNb = 32;  // Cholesky block
+
+// rho(r^2) of the standardised covariance (App. A): Gaussian exp(-r^2), exponential exp(-r),
+// Matern 3/2 (1 + sqrt3 r) exp(-sqrt3 r), Matern 5/2 (1 + sqrt5 r + 5 r^2/3) exp(-sqrt5 r).
+template <class T>
+__device__ __forceinline__ T corr_r2(int kind, T r2)
+{
+    if (kind == KR_GAUSS) return exp(-r2);
+    const T r = sqrt(r2);
+    if (kind == KR_EXP) return exp(-r);
+    if (kind == KR_M32) {
+        const T a = T(1.7320508075688772935) * r;
+        return (T(1) + a) * exp(-a);
+    }
+    const T a = T(2.2360679774997896964) * r;
+    return (T(1) + a + a * a * T(1.0 / 3.0)) * exp(-a);
+}
+
+__device__ __forceinline__ float corr_r2f(int kind, float r2)
+{
+    constexpr float kLog2e = 1.4426950408889634f;
+    if (kind == KR_GAUSS) return exp2f(-r2 * kLog2e);
+    const float r = sqrtf(r2);
+    if (kind == KR_EXP) return exp2f(-r * kLog2e);
+    if (kind == KR_M32) {
+        const float a = 1.7320508f * r;
+        return (1.f + a) * exp2f(-a * kLog2e);
+    }
+    const float a = 2.2360680f * r;
+    return (1.f + a + a * a * (1.f / 3.f)) * exp2f(-a * kLog2e);
+}
+
+// Standardised lag u = M^T dx (M^T given row-major 3 x 3 in `mt`).
+template <class T>
+__device__ __forceinline__ T lag_r2(const KrigeModel& km, T d0, T d1, T d2)
+{
+    const T u0 = T(km.mt[0]) * d0 + T(km.mt[1]) * d1 + T(km.mt[2]) * d2;
+    const T u1 = T(km.mt[3]) * d0 + T(km.mt[4]) * d1 + T(km.mt[5]) * d2;
+    const T u2 = T(km.mt[6]) * d0 + T(km.mt[7]) * d1 + T(km.mt[8]) * d2;
+    return u0 * u0 + u1 * u1 + u2 * u2;
+}
+
+// C[i][j] (lower triangle and diagonal; row-major, leading dimension lda).
+__global__ __launch_bounds__(256) void k_cov_matrix(const double* __restrict__ x, int64_t m, int dim, KrigeModel km,
+                                                   double* __restrict__ C, int64_t lda)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.y) * 16 + (threadIdx.x >> 4);
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * 16 + (threadIdx.x & 15);
+    if (i >= m || j >= m || j > i) return;
+    const double* xi = x + i * dim;
+    const double* xj = x + j * dim;
+    const double d0 = xi[0] - xj[0], d1 = xi[1] - xj[1], d2 = dim == 3 ? xi[2] - xj[2] : 0.0;
+    double c = km.s2 * corr_r2<double>(km.kind, lag_r2<double>(km, d0, d1, d2));
+    if (i == j) c += km.nugget_abs;
+    C[i * lda + j] = c;
+}
+
+// Unblocked Cholesky of the diagonal block [k0, k0 + nb) in LDS; info records the first
+// non-positive pivot (1-based) and the factor then carries NaN.
+__global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ A, int64_t m, int64_t lda, int64_t k0,
+                                                   int32_t* __restrict__ info)
+{
+    __shared__ double L[kNb][kNb + 1];
+    const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+        const int r = e / nb, c = e % nb;
+        L[r][c] = c <= r ? A[(k0 + r) * lda + k0 + c] : 0.0;
+    }
+    __syncthreads();
+    for (int j = 0; j < nb; ++j) {
+        const double d = L[j][j];
+        __syncthreads();
+        const double sd = d > 0.0 ? sqrt(d) : __builtin_nan("");
+        if (threadIdx.x == 0) {
+            L[j][j] = sd;
+            if (!(d > 0.0) && info && *info == 0) *info = static_cast<int32_t>(k0 + j + 1);
+        }
+        for (int r = j + 1 + threadIdx.x; r < nb; r += blockDim.x) L[r][j] /= sd;
+        __syncthreads();
+        const int rem = nb - j - 1;
+        for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
+            const int r = j + 1 + e / rem, c = j + 1 + e % rem;
+            if (c <= r) L[r][c] -= L[r][j] * L[c][j];
+        }
+        __syncthreads();
+    }
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+        const int r = e / nb, c = e % nb;
+        if (c <= r) A[(k0 + r) * lda + k0 + c] = L[r][c];
+    }
+}
+
+// Panel rows i >= k0 + nb: L[i][k0 .. k0+nb) = A[i][...] L_kk^-T (one thread per row).
+__global__ __launch_bounds__(64) void k_trsm_panel(double* __restrict__ A, int64_t m, int64_t lda, int64_t k0)
+{
+    __shared__ double L[kNb][kNb + 1];
+    const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+        const int r = e / nb, c = e % nb;
+        L[r][c] = c <= r ? A[(k0 + r) * lda + k0 + c] : 0.0;
+    }
+    __syncthreads();
+    const int64_t i = k0 + nb + static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    double* row = A + i * lda + k0;
+    double x[kNb];
+#pragma unroll
+    for (int j = 0; j < kNb; ++j) {
+        if (j < nb) {
+            double v = row[j];
+            for (int l = 0; l < j; ++l) v -= x[l] * L[j][l];
+            x[j] = v / L[j][j];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kNb; ++j)
+        if (j < nb) row[j] = x[j];
+}
+
+// Trailing update A[i][j] -= sum_l L[i][l] L[j][l] over the panel columns [k0, k0 + nb), for
+// rows and columns past the panel, lower triangle; 32 x 32 output tiles, 4 entries per thread.
+__global__ __launch_bounds__(256) void k_syrk_update(double* __restrict__ A, int64_t m, int64_t lda, int64_t k0)
+{
+    __shared__ double Li[32][kNb + 1];
+    __shared__ double Lj[32][kNb + 1];
+    const int64_t s0 = k0 + kNb;  // first trailing row/column (only called when a full panel precedes it)
+    const int64_t ti = blockIdx.y, tj = blockIdx.x;
+    if (tj > ti) return;
+    const int64_t i0 = s0 + ti * 32, j0 = s0 + tj * 32;
+    for (int e = threadIdx.x; e < 32 * kNb; e += blockDim.x) {
+        const int r = e / kNb, c = e % kNb;
+        Li[r][c] = i0 + r < m ? A[(i0 + r) * lda + k0 + c] : 0.0;
+        Lj[r][c] = j0 + r < m ? A[(j0 + r) * lda + k0 + c] : 0.0;
+    }
+    __syncthreads();
+    const int c = threadIdx.x & 31, r0 = threadIdx.x >> 5;  // rows r0, r0 + 8, r0 + 16, r0 + 24
+    double acc[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 8
+    for (int l = 0; l < kNb; ++l) {
+        const double b = Lj[c][l];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) acc[q] += Li[r0 + 8 * q][l] * b;
+    }
+    const int64_t j = j0 + c;
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const int64_t i = i0 + r0 + 8 * q;
+        if (i < m && j < m && j <= i) A[i * lda + j] -= acc[q];
+    }
+}
+
+// x = (L L^T)^-1 b by blocked forward and backward substitution in one workgroup.
+__global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ L, int64_t m, int64_t lda,
+                                                    const double* __restrict__ b, double* __restrict__ x)
+{
+    __shared__ double xb[kNb];
+    const int t = threadIdx.x;
+    for (int64_t i = t; i < m; i += blockDim.x) x[i] = b[i];
+    __syncthreads();
+    // forward: L y = b
+    for (int64_t k0 = 0; k0 < m; k0 += kNb) {
+        const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
+        if (t == 0) {
+            for (int j = 0; j < nb; ++j) {
+                double v = x[k0 + j];
+                for (int l = 0; l < j; ++l) v -= L[(k0 + j) * lda + k0 + l] * xb[l];
+                xb[j] = v / L[(k0 + j) * lda + k0 + j];
+                x[k0 + j] = xb[j];
+            }
+        }
+        __syncthreads();
+        for (int64_t i = k0 + nb + t; i < m; i += blockDim.x) {
+            double v = 0.0;
+            for (int l = 0; l < nb; ++l) v += L[i * lda + k0 + l] * xb[l];
+            x[i] -= v;
+        }
+        __syncthreads();
+    }
+    // backward: L^T x = y, block rows from the end
+    for (int64_t k0 = ((m - 1) / kNb) * kNb; k0 >= 0; k0 -= kNb) {
+        const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
+        if (t == 0) {
+            for (int j = nb - 1; j >= 0; --j) {
+                double v = x[k0 + j];
+                for (int l = j + 1; l < nb; ++l) v -= L[(k0 + l) * lda + k0 + j] * xb[l];
+                xb[j] = v / L[(k0 + j) * lda + k0 + j];
+                x[k0 + j] = xb[j];
+            }
+        }
+        __syncthreads();
+        for (int64_t i = t; i < k0; i += blockDim.x) {
+            double v = 0.0;
+            for (int l = 0; l < nb; ++l) v += L[(k0 + l) * lda + i] * xb[l];
+            x[i] -= v;
+        }
+        __syncthreads();
+    }
+}
+
+// r = d - y (FP64 residuals).
+__global__ __launch_bounds__(256) void k_residual(const float* __restrict__ d, const float* __restrict__ y, int64_t m,
+                                                 double* __restrict__ r)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i < m) r[i] = static_cast<double>(d[i]) - static_cast<double>(y[i]);
+}
+
+// Observation staging for the correction: (u = M^T (x_i - x_0) as FP32, w_i = sigma^2 alpha_i);
+// lags are taken from the first observation so that the FP32 differences stay small.
+__global__ __launch_bounds__(256) void k_krige_stage(const double* __restrict__ x, const double* __restrict__ alpha,
+                                                    int64_t m, int dim, KrigeModel km, float4* __restrict__ out)
+{
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (i >= m) return;
+    const double* xi = x + i * dim;
+    const double d0 = xi[0] - x[0], d1 = xi[1] - x[1], d2 = dim == 3 ? xi[2] - x[2] : 0.0;
+    const double u0 = km.mt[0] * d0 + km.mt[1] * d1 + km.mt[2] * d2;
+    const double u1 = km.mt[3] * d0 + km.mt[4] * d1 + km.mt[5] * d2;
+    const double u2 = km.mt[6] * d0 + km.mt[7] * d1 + km.mt[8] * d2;
+    out[i] = make_float4(static_cast<float>(u0), static_cast<float>(u1), static_cast<float>(u2),
+                         static_cast<float>(km.s2 * alpha[i]));
+}
+
+constexpr int kKc = 256;  // observations per LDS chunk
+constexpr int kKr = 4;    // cells per lane
+
+// y[c] += sum_i w_i rho(|u(c) - u_i|) for cells of a grid (grid != nullptr) or points.
+template <bool GRID>
+__global__ __launch_bounds__(256) void k_krige_apply(const float4* __restrict__ obs, const double* __restrict__ ref,
+                                                    int64_t m, KrigeModel km, KrigeTarget tg, float* __restrict__ y)
+{
+    __shared__ float4 so[kKc];
+    const int64_t base = static_cast<int64_t>(blockIdx.x) * (256 * kKr) + threadIdx.x;
+    float v0[kKr], v1[kKr], v2[kKr], acc[kKr];
+#pragma unroll
+    for (int r = 0; r < kKr; ++r) {
+        const int64_t c = min(base + 256 * r, tg.count - 1);
+        double x0, x1, x2 = 0.0;
+        if constexpr (GRID) {
+            const int64_t i = c % tg.n[0], q = c / tg.n[0];
+            const int64_t j = q % tg.n[1], k = q / tg.n[1];
+            x0 = tg.o[0] + (static_cast<double>(i) + 0.5) * tg.h[0];
+            x1 = tg.o[1] + (static_cast<double>(j) + 0.5) * tg.h[1];
+            if (tg.dim == 3) x2 = tg.o[2] + (static_cast<double>(k) + 0.5) * tg.h[2];
+        } else {
+            x0 = tg.xyz[c * tg.dim];
+            x1 = tg.xyz[c * tg.dim + 1];
+            if (tg.dim == 3) x2 = tg.xyz[c * tg.dim + 2];
+        }
+        const double d0 = x0 - ref[0], d1 = x1 - ref[1], d2 = tg.dim == 3 ? x2 - ref[2] : 0.0;
+        v0[r] = static_cast<float>(km.mt[0] * d0 + km.mt[1] * d1 + km.mt[2] * d2);
+        v1[r] = static_cast<float>(km.mt[3] * d0 + km.mt[4] * d1 + km.mt[5] * d2);
+        v2[r] = static_cast<float>(km.mt[6] * d0 + km.mt[7] * d1 + km.mt[8] * d2);
+        acc[r] = 0.f;
+    }
+    for (int64_t i0 = 0; i0 < m; i0 += kKc) {
+        const int nc = static_cast<int>(min<int64_t>(kKc, m - i0));
+        __syncthreads();
+        if (threadIdx.x < nc) so[threadIdx.x] = obs[i0 + threadIdx.x];
+        __syncthreads();
+        for (int q = 0; q < nc; ++q) {
+            const float4 o = so[q];
+#pragma unroll
+            for (int r = 0; r < kKr; ++r) {
+                const float a = v0[r] - o.x, b = v1[r] - o.y, e = v2[r] - o.z;
+                acc[r] = fmaf(o.w, corr_r2f(km.kind, a * a + b * b + e * e), acc[r]);
+            }
+        }
+    }
+#pragma unroll
+    for (int r = 0; r < kKr; ++r) {
+        const int64_t c = base + 256 * r;
+        if (c < tg.count) y[c] += acc[r];
+    }
+}
+
+}  // namespace
+
+hipError_t launch_cov_matrix(const double* x, int64_t m, int dim, const KrigeModel& km, double* C, int64_t lda,
+                             hipStream_t s)
+{
+    const int64_t t = (m + 15) / 16;
+    if (t > 65535) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_cov_matrix, dim3(static_cast<unsigned>(t), static_cast<unsigned>(t)), dim3(256), 0, s, x, m,
+                       dim, km, C, lda);
+    return hipGetLastError();
+}
+
+hipError_t launch_cholesky(double* A, int64_t m, int64_t lda, int32_t* info, hipStream_t s)
+{
+    for (int64_t k0 = 0; k0 < m; k0 += kNb) {
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, m, lda, k0, info);
+        const int64_t rest = m - k0 - kNb;
+        if (rest <= 0) break;
+        hipLaunchKernelGGL(k_trsm_panel, dim3(static_cast<unsigned>((rest + 63) / 64)), dim3(64), 0, s, A, m, lda, k0);
+        const int64_t tiles = (rest + 31) / 32;
+        hipLaunchKernelGGL(k_syrk_update, dim3(static_cast<unsigned>(tiles), static_cast<unsigned>(tiles)), dim3(256),
+                           0, s, A, m, lda, k0);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_chol_solve(const double* L, int64_t m, int64_t lda, const double* b, double* x, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, s, L, m, lda, b, x);
+    return hipGetLastError();
+}
+
+hipError_t launch_residual(const float* d, const float* y, int64_t m, double* r, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_residual, dim3(static_cast<unsigned>((m + 255) / 256)), dim3(256), 0, s, d, y, m, r);
+    return hipGetLastError();
+}
+
+hipError_t launch_krige_stage(const double* x, const double* alpha, int64_t m, int dim, const KrigeModel& km,
+                              float4* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_krige_stage, dim3(static_cast<unsigned>((m + 255) / 256)), dim3(256), 0, s, x, alpha, m, dim,
+                       km, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_krige_apply(const float4* obs, const double* xobs, int64_t m, const KrigeModel& km,
+                              const KrigeTarget& tg, float* y, hipStream_t s)
+{
+    const int64_t blocks = (tg.count + 256 * kKr - 1) / (256 * kKr);
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
+    if (tg.grid)
+        hipLaunchKernelGGL(k_krige_apply<true>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, obs, xobs, m, km,
+                           tg, y);
+    else
+        hipLaunchKernelGGL(k_krige_apply<false>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, obs, xobs, m, km,
+                           tg, y);
+    return hipGetLastError();
+}
+
+__global__ void k_fill_i32(int32_t* p, int32_t v)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, p, v);
+    return hipGetLastError();
+}
+
+}  // namespace grf

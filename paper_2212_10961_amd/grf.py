@@ -27,6 +27,7 @@ __all__ = [
     "Modes", "make_modes", "modes_from_tables", "field_grid", "field_grid_f64", "field_points",
     "epilogue", "field_backward", "field_backward_grid", "GRFPoints", "Plan", "method_id", "sep_tiles",
     "trunc2", "pluri_grid", "pluri_points", "pluri_apply", "snap_periodic", "make_modes_lattice",
+    "krige_weights", "krige_apply_grid", "krige_apply_points", "condition_grid", "condition_points",
     "GAUSSIAN", "EXPONENTIAL", "MATERN", "GrfError", "version", "paper_lambda_to_ell",
 ]
 
@@ -325,6 +326,75 @@ def pluri_apply(y1: torch.Tensor, y2: torch.Tensor, rule: L.GrfTrunc2, want_faci
     check(lib.pluri_apply(_ptr(y1), _ptr(y2), n, ctypes.byref(rule), _ptr(out.get("facies")),
                           _ptr(out.get("value")), ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
     return out
+
+
+def _krige(cov, nu, nugget) -> L.GrfKrige:
+    k = L.GrfKrige()
+    k.cov, k.nu, k.nugget = int(cov), float(nu), float(nugget)
+    return k
+
+
+def krige_weights(modes: Modes, xobs: torch.Tensor, dobs: torch.Tensor, cov, nu=0.5, nugget=0.0, stream=None):
+    """Kriging weights alpha of the residuals dobs - Y(xobs) (float64 [M] device tensor) and the
+    factorisation status (int32 [1]: 0, or the first non-positive pivot)."""
+    lib = L.load()
+    dev = modes.z.device
+    M = int(xobs.shape[0])
+    need = ctypes.c_size_t()
+    check(lib.krige_weights_ws_size(ctypes.byref(modes.c()), M, ctypes.byref(need)))
+    ws = _workspace(need.value, dev)
+    alpha = torch.empty(M, dtype=torch.float64, device=dev)
+    info = torch.empty(1, dtype=torch.int32, device=dev)
+    kp = _krige(cov, nu, nugget)
+    check(lib.krige_weights(ctypes.byref(modes.c()), ctypes.byref(kp), _ptr(xobs.contiguous()),
+                            _ptr(dobs.to(torch.float32).contiguous()), M, _ptr(alpha), _ptr(info),
+                            ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+    return alpha, info
+
+
+def krige_apply_grid(modes: Modes, xobs, alpha, shape, y, cov, nu=0.5, origin=None, h=None, stream=None):
+    """y += sum_i alpha_i C(x - x_i) over the grid's cell centres (in place)."""
+    lib = L.load()
+    M = int(xobs.shape[0])
+    need = ctypes.c_size_t()
+    check(lib.krige_apply_ws_size(M, ctypes.byref(need)))
+    ws = _workspace(need.value, y.device)
+    kp = _krige(cov, nu, 0.0)
+    check(lib.krige_apply_grid(ctypes.byref(modes.c()), ctypes.byref(kp), _ptr(xobs.contiguous()), _ptr(alpha), M,
+                               ctypes.byref(_grid(shape, origin, h)), _ptr(y), ctypes.c_void_p(ws.data_ptr()),
+                               ws.numel(), _stream(stream)))
+    return y
+
+
+def krige_apply_points(modes: Modes, xobs, alpha, xyz, y, cov, nu=0.5, stream=None):
+    """y += sum_i alpha_i C(x - x_i) at points xyz (in place)."""
+    lib = L.load()
+    M = int(xobs.shape[0])
+    need = ctypes.c_size_t()
+    check(lib.krige_apply_ws_size(M, ctypes.byref(need)))
+    ws = _workspace(need.value, y.device)
+    kp = _krige(cov, nu, 0.0)
+    check(lib.krige_apply_points(ctypes.byref(modes.c()), ctypes.byref(kp), _ptr(xobs.contiguous()), _ptr(alpha), M,
+                                 _ptr(xyz.contiguous()), int(xyz.shape[0]), _ptr(y), ctypes.c_void_p(ws.data_ptr()),
+                                 ws.numel(), _stream(stream)))
+    return y
+
+
+def condition_grid(modes: Modes, shape, xobs, dobs, cov, nu=0.5, nugget=0.0, method="direct_f32", origin=None,
+                   h=None):
+    """The realisation of `modes` on a grid conditioned on observations (kriging of residuals)."""
+    y = field_grid(modes, shape, origin=origin, h=h, method=method)["y"]
+    alpha, info = krige_weights(modes, xobs, dobs, cov, nu, nugget)
+    krige_apply_grid(modes, xobs, alpha, shape, y, cov, nu, origin=origin, h=h)
+    return y, alpha, info
+
+
+def condition_points(modes: Modes, xyz, xobs, dobs, cov, nu=0.5, nugget=0.0, method="direct_f32"):
+    """The realisation of `modes` at points conditioned on observations (kriging of residuals)."""
+    y = field_points(modes, xyz, method=method)["y"]
+    alpha, info = krige_weights(modes, xobs, dobs, cov, nu, nugget)
+    krige_apply_points(modes, xobs, alpha, xyz, y, cov, nu)
+    return y, alpha, info
 
 
 def grid_workspace_bytes(modes: Modes, shape, method) -> int:

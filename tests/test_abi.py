@@ -412,3 +412,35 @@ def test_make_modes_lattice_validation(lib):
     s2 = _spec(dim=2, n_modes=33)
     assert lib.make_modes_lattice(ctypes.byref(s2), 8, 0.5, z.ctypes.data, p.ctypes.data, w.ctypes.data) == L.GRF_EINVAL
     assert lib.make_modes_lattice(ctypes.byref(s), 8, 0.5, None, p.ctypes.data, w.ctypes.data) == L.GRF_EINVAL
+
+
+def test_krige_validation(lib):
+    m = _modes(dim=2, n=64)
+    dev = ctypes.c_void_p(16)
+    b = ctypes.c_size_t()
+    assert lib.krige_weights_ws_size(ctypes.byref(m), 100, ctypes.byref(b)) == 0
+    assert b.value >= 100 * 100 * 8
+    assert lib.krige_weights_ws_size(ctypes.byref(m), 0, ctypes.byref(b)) == L.GRF_EINVAL
+
+    def kp(cov=0, nu=0.5, nugget=0.0):
+        k = L.GrfKrige()
+        k.cov, k.nu, k.nugget = cov, nu, nugget
+        return k
+
+    def w(k, n=100, wsb=1 << 30):
+        return lib.krige_weights(ctypes.byref(m), ctypes.byref(k), dev, dev, n, dev, None, dev, wsb, None)
+
+    assert w(kp(cov=7)) == L.GRF_EINVAL
+    assert w(kp(cov=2, nu=1.0)) == L.GRF_EUNSUPPORTED
+    assert w(kp(nugget=-1.0)) == L.GRF_EINVAL
+    assert w(kp(), n=0) == L.GRF_EINVAL
+    assert w(kp(), wsb=b.value - 1) == L.GRF_ENOMEM
+    assert lib.krige_weights(ctypes.byref(m), None, dev, dev, 10, dev, None, dev, 1 << 30, None) == L.GRF_EINVAL
+    assert lib.krige_apply_ws_size(100, ctypes.byref(b)) == 0 and b.value == 1792
+    g = _grid((8, 8, 1))
+    k = kp()
+    assert lib.krige_apply_grid(ctypes.byref(m), ctypes.byref(k), dev, dev, 100, ctypes.byref(g), dev, dev, 1791,
+                                None) == L.GRF_ENOMEM
+    assert lib.krige_apply_grid(ctypes.byref(m), ctypes.byref(k), dev, dev, 100, ctypes.byref(g), None, dev, 4096,
+                                None) == L.GRF_EINVAL
+    assert lib.krige_apply_points(ctypes.byref(m), ctypes.byref(k), dev, dev, 100, dev, 0, dev, dev, 4096, None) == 0

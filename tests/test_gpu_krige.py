@@ -1,0 +1,114 @@
+"""GPU parity of conditioning by kriging (weights, correction on grids and points) against the
+oracle's numpy kriging of the residuals."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from gpu_common import modes_pair, to_np
+from paper_2212_10961_amd import workloads as wl
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def grf():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2212_10961_amd.grf as g
+    return g
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _separated(n, box, min_dist, seed):
+    """n points in the box, greedily thinned to a minimum spacing (well-conditioned systems)."""
+    cand = wl.points_uniform(20 * n, box, seed)
+    keep = []
+    for p in cand:
+        if all(np.linalg.norm(p - q) >= min_dist for q in keep):
+            keep.append(p)
+        if len(keep) == n:
+            break
+    return np.array(keep)
+
+
+@pytest.mark.parametrize("cov,nu,nugget", [(wl.EXPONENTIAL, 0.5, 0.0), (wl.GAUSSIAN, 0.5, 1e-6),
+                                           (wl.MATERN, 1.5, 0.0), (wl.MATERN, 2.5, 1e-8)])
+def test_conditioned_grid2d(orc, grf, cov, nu, nugget):
+    shape, ell, sigma = (96, 80), (10.0, 6.0), 1.3
+    _say(f"case krige grid2d cov={cov} nu={nu}")
+    (zo, po), m = modes_pair(orc, grf, 2, wl.EXPONENTIAL, 300, 961, sigma, ell)
+    xo = _separated(150, (96.0, 80.0), 3.0, 962)
+    d = np.random.default_rng(963).normal(size=xo.shape[0]) * sigma
+    x = orc.grid_centres(shape)
+    yu = orc.field_points(zo, po, sigma, ell, x)
+    yuo = orc.field_points(zo, po, sigma, ell, xo)
+    a = orc.krige_weights(cov, sigma, ell, xo, d - yuo, nugget=nugget, nu=nu)
+    want = yu + orc.krige_correction(cov, sigma, ell, xo, a, x, nu=nu)
+    y, alpha, info = grf.condition_grid(m, shape, torch.from_numpy(xo).cuda(), torch.from_numpy(d).float().cuda(), cov,
+                                        nu=nu, nugget=nugget)
+    assert int(to_np(info)[0]) == 0
+    err = np.max(np.abs(to_np(y) - want))
+    _say(f"  max |Y_c - ref| / sigma = {err / sigma:.3e}")
+    assert err <= 2e-4 * sigma
+
+
+def test_conditioned_points_interpolate_rotated(orc, grf):
+    _say("case krige points rotated, interpolation")
+    ell, sigma = np.array([20.0, 8.0, 3.0]), 0.9
+    (zo, po), m = modes_pair(orc, grf, 3, wl.GAUSSIAN, 256, 964, sigma, ell)
+    R = orc.rotation_matrix(3, (0.5, 0.2, -0.3))
+    m.rot = R
+    xo = _separated(200, (100.0, 100.0, 20.0), 6.0, 965)
+    d = np.random.default_rng(966).normal(size=xo.shape[0]) * sigma
+    xq = np.concatenate([xo, wl.points_uniform(3000, (100.0, 100.0, 20.0), 967)])
+    y, _, info = grf.condition_points(m, torch.from_numpy(xq).cuda(), torch.from_numpy(xo).cuda(),
+                                      torch.from_numpy(d).float().cuda(), wl.EXPONENTIAL)
+    assert int(to_np(info)[0]) == 0
+    yy = to_np(y)
+    assert np.max(np.abs(yy[:xo.shape[0]] - d.astype(np.float32))) <= 1e-4 * sigma  # honours the data
+    M = R @ np.diag(1.0 / ell)
+    yu = orc.field_points_mat(zo, po, sigma, M, xq)
+    yuo = orc.field_points_mat(zo, po, sigma, M, xo)
+    a = orc.krige_weights(wl.EXPONENTIAL, sigma, ell, xo, d - yuo, rot=R)
+    want = yu + orc.krige_correction(wl.EXPONENTIAL, sigma, ell, xo, a, xq, rot=R)
+    assert np.max(np.abs(yy - want)) <= 2e-4 * sigma
+
+
+def test_krige_weights_match_oracle_and_report_singular(orc, grf):
+    _say("case krige weights vs oracle, singular system")
+    ell, sigma = (15.0, 15.0), 1.0
+    (zo, po), m = modes_pair(orc, grf, 2, wl.GAUSSIAN, 128, 968, sigma, ell)
+    xo = _separated(400, (300.0, 300.0), 12.0, 969)
+    d = np.random.default_rng(970).normal(size=xo.shape[0])
+    yuo = orc.field_points(zo, po, sigma, ell, xo)
+    want = orc.krige_weights(wl.EXPONENTIAL, sigma, ell, xo, d - yuo)
+    alpha, info = grf.krige_weights(m, torch.from_numpy(xo).cuda(), torch.from_numpy(d).float().cuda(), wl.EXPONENTIAL)
+    assert int(to_np(info)[0]) == 0
+    rel = np.linalg.norm(to_np(alpha) - want) / np.linalg.norm(want)
+    _say(f"  alpha rel-L2 {rel:.2e}")
+    assert rel <= 1e-4
+    # two identical observation points with no nugget: C is singular, the second pivot is 0
+    xs = np.array([[5.0, 5.0], [5.0, 5.0], [40.0, 3.0]])
+    _, info = grf.krige_weights(m, torch.from_numpy(xs).cuda(), torch.zeros(3, device="cuda"), wl.EXPONENTIAL)
+    assert int(to_np(info)[0]) == 2
+
+
+@pytest.mark.parametrize("M", [1, 31, 32, 33, 97, 1000])
+def test_cholesky_block_edges(orc, grf, M):
+    """Sizes below, at and across the 32-row factorisation blocks."""
+    _say(f"case krige weights M={M}")
+    ell, sigma = (6.0, 6.0, 2.0), 1.0
+    (zo, po), m = modes_pair(orc, grf, 3, wl.EXPONENTIAL, 64, 971, sigma, ell)
+    xo = wl.points_uniform(M, (200.0, 200.0, 40.0), 972 + M)
+    d = np.random.default_rng(973).normal(size=M)
+    yuo = orc.field_points(zo, po, sigma, ell, xo)
+    want = orc.krige_weights(wl.EXPONENTIAL, sigma, ell, xo, d - yuo, nugget=1e-3)
+    alpha, info = grf.krige_weights(m, torch.from_numpy(xo).cuda(), torch.from_numpy(d).float().cuda(),
+                                    wl.EXPONENTIAL, nugget=1e-3)
+    assert int(to_np(info)[0]) == 0
+    assert np.linalg.norm(to_np(alpha) - want) / np.linalg.norm(want) <= 1e-4
