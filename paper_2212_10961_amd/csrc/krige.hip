@@ -35,18 +35,21 @@ __device__ __forceinline__ T corr_r2(int kind, T r2)
     return (T(1) + a + a * a * T(1.0 / 3.0)) * exp(-a);
 }
 
-__device__ __forceinline__ float corr_r2f(int kind, float r2)
+// FP32 correlation for the correction sum, on the hardware square root and base-2 exponential
+// (about 1 ulp each; the sum is FP32 anyway).
+template <int KIND>
+__device__ __forceinline__ float corr_r2f(float r2)
 {
     constexpr float kLog2e = 1.4426950408889634f;
-    if (kind == KR_GAUSS) return exp2f(-r2 * kLog2e);
-    const float r = sqrtf(r2);
-    if (kind == KR_EXP) return exp2f(-r * kLog2e);
-    if (kind == KR_M32) {
+    if constexpr (KIND == KR_GAUSS) return __builtin_amdgcn_exp2f(-r2 * kLog2e);
+    const float r = __builtin_amdgcn_sqrtf(r2);
+    if constexpr (KIND == KR_EXP) return __builtin_amdgcn_exp2f(-r * kLog2e);
+    if constexpr (KIND == KR_M32) {
         const float a = 1.7320508f * r;
-        return (1.f + a) * exp2f(-a * kLog2e);
+        return (1.f + a) * __builtin_amdgcn_exp2f(-a * kLog2e);
     }
     const float a = 2.2360680f * r;
-    return (1.f + a + a * a * (1.f / 3.f)) * exp2f(-a * kLog2e);
+    return (1.f + a + a * a * (1.f / 3.f)) * __builtin_amdgcn_exp2f(-a * kLog2e);
 }
 
 // Standardised lag u = M^T dx (M^T given row-major 3 x 3 in `mt`).
@@ -74,38 +77,41 @@ __global__ __launch_bounds__(256) void k_cov_matrix(const double* __restrict__ x
     C[i * lda + j] = c;
 }
 
-// Unblocked Cholesky of the diagonal block [k0, k0 + nb) in LDS; info records the first
-// non-positive pivot (1-based) and the factor then carries NaN.
-__global__ __launch_bounds__(256) void k_potrf_diag(double* __restrict__ A, int64_t m, int64_t lda, int64_t k0,
-                                                   int32_t* __restrict__ info)
+// Unblocked Cholesky of the diagonal block [k0, k0 + nb) by one wave: lane r keeps row r in
+// registers; column j's entries below the pivot go through LDS for the rank-1 update.  info
+// records the first non-positive pivot (1-based); the factor then carries NaN.
+__global__ __launch_bounds__(64) void k_potrf_diag(double* __restrict__ A, int64_t m, int64_t lda, int64_t k0,
+                                                  int32_t* __restrict__ info)
 {
-    __shared__ double L[kNb][kNb + 1];
+    __shared__ double col[kNb];
     const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-        const int r = e / nb, c = e % nb;
-        L[r][c] = c <= r ? A[(k0 + r) * lda + k0 + c] : 0.0;
-    }
-    __syncthreads();
-    for (int j = 0; j < nb; ++j) {
-        const double d = L[j][j];
-        __syncthreads();
-        const double sd = d > 0.0 ? sqrt(d) : __builtin_nan("");
-        if (threadIdx.x == 0) {
-            L[j][j] = sd;
-            if (!(d > 0.0) && info && *info == 0) *info = static_cast<int32_t>(k0 + j + 1);
+    const int r = threadIdx.x;
+    double row[kNb];
+#pragma unroll
+    for (int c = 0; c < kNb; ++c) row[c] = (r < nb && c <= r) ? A[(k0 + r) * lda + k0 + c] : 0.0;
+    int bad = 0;
+#pragma unroll
+    for (int j = 0; j < kNb; ++j) {
+        if (j < nb) {
+            // pivot of column j, from lane j
+            const double d = __shfl(row[j], j, 64);
+            const double sd = d > 0.0 ? sqrt(d) : __builtin_nan("");
+            if (!(d > 0.0) && bad == 0) bad = static_cast<int>(k0 + j + 1);
+            if (r == j) row[j] = sd;
+            if (r > j && r < nb) row[j] /= sd;
+            if (r < kNb) col[r] = row[j];
+            __syncthreads();
+#pragma unroll
+            for (int c = j + 1; c < kNb; ++c)
+                if (c <= r && r < nb) row[c] -= row[j] * col[c];
+            __syncthreads();
         }
-        for (int r = j + 1 + threadIdx.x; r < nb; r += blockDim.x) L[r][j] /= sd;
-        __syncthreads();
-        const int rem = nb - j - 1;
-        for (int e = threadIdx.x; e < rem * rem; e += blockDim.x) {
-            const int r = j + 1 + e / rem, c = j + 1 + e % rem;
-            if (c <= r) L[r][c] -= L[r][j] * L[c][j];
-        }
-        __syncthreads();
     }
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-        const int r = e / nb, c = e % nb;
-        if (c <= r) A[(k0 + r) * lda + k0 + c] = L[r][c];
+    if (r == 0 && bad && info && *info == 0) *info = bad;
+    if (r < nb) {
+#pragma unroll
+        for (int c = 0; c < kNb; ++c)
+            if (c <= r) A[(k0 + r) * lda + k0 + c] = row[c];
     }
 }
 
@@ -168,10 +174,13 @@ __global__ __launch_bounds__(256) void k_syrk_update(double* __restrict__ A, int
     }
 }
 
-// x = (L L^T)^-1 b by blocked forward and backward substitution in one workgroup.
+// x = (L L^T)^-1 b by blocked forward and backward substitution in one workgroup.  Each
+// 32-row diagonal block is staged in LDS and solved by one wave (lane-parallel column
+// updates); the rest of the vector is then updated by all threads.
 __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ L, int64_t m, int64_t lda,
                                                     const double* __restrict__ b, double* __restrict__ x)
 {
+    __shared__ double D[kNb][kNb + 1];
     __shared__ double xb[kNb];
     const int t = threadIdx.x;
     for (int64_t i = t; i < m; i += blockDim.x) x[i] = b[i];
@@ -179,13 +188,20 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ 
     // forward: L y = b
     for (int64_t k0 = 0; k0 < m; k0 += kNb) {
         const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
-        if (t == 0) {
+        for (int e = t; e < nb * nb; e += blockDim.x) {
+            const int r = e / nb, c = e % nb;
+            D[r][c] = c <= r ? L[(k0 + r) * lda + k0 + c] : 0.0;
+        }
+        if (t < nb) xb[t] = x[k0 + t];
+        __syncthreads();
+        if (t < 64) {
             for (int j = 0; j < nb; ++j) {
-                double v = x[k0 + j];
-                for (int l = 0; l < j; ++l) v -= L[(k0 + j) * lda + k0 + l] * xb[l];
-                xb[j] = v / L[(k0 + j) * lda + k0 + j];
-                x[k0 + j] = xb[j];
+                const double xj = xb[j] / D[j][j];
+                if (t > j && t < nb) xb[t] -= D[t][j] * xj;
+                if (t == j) xb[j] = xj;
+                __builtin_amdgcn_wave_barrier();
             }
+            if (t < nb) x[k0 + t] = xb[t];
         }
         __syncthreads();
         for (int64_t i = k0 + nb + t; i < m; i += blockDim.x) {
@@ -198,13 +214,20 @@ __global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ 
     // backward: L^T x = y, block rows from the end
     for (int64_t k0 = ((m - 1) / kNb) * kNb; k0 >= 0; k0 -= kNb) {
         const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
-        if (t == 0) {
+        for (int e = t; e < nb * nb; e += blockDim.x) {
+            const int r = e / nb, c = e % nb;
+            D[r][c] = c <= r ? L[(k0 + r) * lda + k0 + c] : 0.0;
+        }
+        if (t < nb) xb[t] = x[k0 + t];
+        __syncthreads();
+        if (t < 64) {
             for (int j = nb - 1; j >= 0; --j) {
-                double v = x[k0 + j];
-                for (int l = j + 1; l < nb; ++l) v -= L[(k0 + l) * lda + k0 + j] * xb[l];
-                xb[j] = v / L[(k0 + j) * lda + k0 + j];
-                x[k0 + j] = xb[j];
+                const double xj = xb[j] / D[j][j];
+                if (t < j) xb[t] -= D[j][t] * xj;
+                if (t == j) xb[j] = xj;
+                __builtin_amdgcn_wave_barrier();
             }
+            if (t < nb) x[k0 + t] = xb[t];
         }
         __syncthreads();
         for (int64_t i = t; i < k0; i += blockDim.x) {
@@ -244,7 +267,7 @@ constexpr int kKc = 256;  // observations per LDS chunk
 constexpr int kKr = 4;    // cells per lane
 
 // y[c] += sum_i w_i rho(|u(c) - u_i|) for cells of a grid (grid != nullptr) or points.
-template <bool GRID>
+template <bool GRID, int KIND>
 __global__ __launch_bounds__(256) void k_krige_apply(const float4* __restrict__ obs, const double* __restrict__ ref,
                                                     int64_t m, KrigeModel km, KrigeTarget tg, float* __restrict__ y)
 {
@@ -282,7 +305,7 @@ __global__ __launch_bounds__(256) void k_krige_apply(const float4* __restrict__ 
 #pragma unroll
             for (int r = 0; r < kKr; ++r) {
                 const float a = v0[r] - o.x, b = v1[r] - o.y, e = v2[r] - o.z;
-                acc[r] = fmaf(o.w, corr_r2f(km.kind, a * a + b * b + e * e), acc[r]);
+                acc[r] = fmaf(o.w, corr_r2f<KIND>(a * a + b * b + e * e), acc[r]);
             }
         }
     }
@@ -308,7 +331,7 @@ hipError_t launch_cov_matrix(const double* x, int64_t m, int dim, const KrigeMod
 hipError_t launch_cholesky(double* A, int64_t m, int64_t lda, int32_t* info, hipStream_t s)
 {
     for (int64_t k0 = 0; k0 < m; k0 += kNb) {
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(256), 0, s, A, m, lda, k0, info);
+        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, A, m, lda, k0, info);
         const int64_t rest = m - k0 - kNb;
         if (rest <= 0) break;
         hipLaunchKernelGGL(k_trsm_panel, dim3(static_cast<unsigned>((rest + 63) / 64)), dim3(64), 0, s, A, m, lda, k0);
@@ -347,12 +370,17 @@ hipError_t launch_krige_apply(const float4* obs, const double* xobs, int64_t m, 
     const int64_t blocks = (tg.count + 256 * kKr - 1) / (256 * kKr);
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    if (tg.grid)
-        hipLaunchKernelGGL(k_krige_apply<true>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, obs, xobs, m, km,
-                           tg, y);
-    else
-        hipLaunchKernelGGL(k_krige_apply<false>, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, obs, xobs, m, km,
-                           tg, y);
+    const dim3 g(static_cast<unsigned>(blocks));
+    switch (km.kind * 2 + (tg.grid ? 1 : 0)) {
+    case KR_GAUSS * 2 + 1: hipLaunchKernelGGL((k_krige_apply<true, KR_GAUSS>), g, dim3(256), 0, s, obs, xobs, m, km, tg, y); break;
+    case KR_GAUSS * 2: hipLaunchKernelGGL((k_krige_apply<false, KR_GAUSS>), g, dim3(256), 0, s, obs, xobs, m, km, tg, y); break;
+    case KR_EXP * 2 + 1: hipLaunchKernelGGL((k_krige_apply<true, KR_EXP>), g, dim3(256), 0, s, obs, xobs, m, km, tg, y); break;
+    case KR_EXP * 2: hipLaunchKernelGGL((k_krige_apply<false, KR_EXP>), g, dim3(256), 0, s, obs, xobs, m, km, tg, y); break;
+    case KR_M32 * 2 + 1: hipLaunchKernelGGL((k_krige_apply<true, KR_M32>), g, dim3(256), 0, s, obs, xobs, m, km, tg, y); break;
+    case KR_M32 * 2: hipLaunchKernelGGL((k_krige_apply<false, KR_M32>), g, dim3(256), 0, s, obs, xobs, m, km, tg, y); break;
+    case KR_M52 * 2 + 1: hipLaunchKernelGGL((k_krige_apply<true, KR_M52>), g, dim3(256), 0, s, obs, xobs, m, km, tg, y); break;
+    default: hipLaunchKernelGGL((k_krige_apply<false, KR_M52>), g, dim3(256), 0, s, obs, xobs, m, km, tg, y); break;
+    }
     return hipGetLastError();
 }
 
