@@ -94,14 +94,15 @@ def test_pluri_points(orc, grf):
     _check_facies(orc, to_np(out["facies"]), to_np(out["value"]), r1, r2, 1.2, 0.8, "direct_f32")
 
 
-@pytest.mark.parametrize("n", [0, 1, 7, 4099, 1_000_003])
-def test_pluri_apply_exact(orc, grf, n):
+@pytest.mark.parametrize("n,off", [(0, 0), (1, 0), (7, 0), (4099, 0), (1_000_003, 0), (4099, 1), (1001, 3)])
+def test_pluri_apply_exact(orc, grf, n, off):
     """The stand-alone rule decides in FP32 on the given values: bit-exact with the definition
-    evaluated on the same FP32 numbers (thresholds are exact in FP32)."""
-    _say(f"case pluri_apply n={n}")
+    evaluated on the same FP32 numbers (thresholds are exact in FP32).  off > 0 passes views
+    that start off a 16-byte boundary (the per-cell form)."""
+    _say(f"case pluri_apply n={n} offset={off}")
     g = torch.Generator().manual_seed(n + 5)
-    y1 = (torch.randn(n, generator=g) * 1.5).cuda()
-    y2 = torch.randn(n, generator=g).cuda()
+    y1 = (torch.randn(n + off, generator=g) * 1.5).cuda()[off:]
+    y2 = torch.randn(n + off, generator=g).cuda()[off:]
     if n > 10:  # values exactly on thresholds go to the lower bin
         y1[:3] = torch.tensor([-1.0, 0.0, 1.0])
         y2[3:5] = torch.tensor([-0.5, 0.5])
