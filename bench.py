@@ -410,6 +410,12 @@ def batch_extra(grf, wl, torch, np, dev):
         total += cells
         items.append((m, p["shape"], torch.empty(cells, device=dev)))
     res = {"instances": len(inst), "cells": total, "mode_cells": total * 2048}
+    # the same 512 evaluations as separate eval_field_grid calls (one workspace, sized for the largest)
+    wsb = max(grf.grid_workspace_bytes(m, shape, "sep_f16") for m, shape, _ in items)
+    wsp = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    sep_ms, _ = _timed(torch, grf, lambda: [grf.field_grid(m, shape, method="sep_f16", out={"y": y}, workspace=wsp)
+                                            for m, shape, y in items], 3, 1)
+    res["sep_f16_separate_calls"] = {"ms_per_batch": sep_ms, "mode_cells_per_s": total * 2048 / (sep_ms * 1e-3)}
     for meth in ("sep_f16", "direct_f32"):
         plan = grf.Plan(meth, graph=True, autotune=True,
                         tune_cache=str(ROOT / "gpurun_out" / "tune_cache.txt") if (ROOT / "gpurun_out").exists() else None)

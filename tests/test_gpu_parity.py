@@ -240,3 +240,37 @@ def test_bitwise_reproducible(orc, grf):
         a = to_np(grf.field_grid(m, (96, 80, 7), method=meth)["y"])
         b = to_np(grf.field_grid(m, (96, 80, 7), method=meth)["y"])
         np.testing.assert_array_equal(a, b)
+
+
+@pytest.mark.parametrize("meth", ["sep_f16", "direct_f32", "sep_f16_x3"])
+def test_grid_call_captured_in_a_graph(orc, grf, meth):
+    """eval_field_grid enqueues kernels only (no allocation, no synchronisation, no memset), so a
+    caller can capture it in a HIP graph: every replay, with eager work in between, equals the
+    eager evaluation bit for bit."""
+    shape, ell, sigma = (130, 70, 11), (7.0, 5.0, 2.0), 1.1
+    _say(f"case graph capture {meth}")
+    (zo, po), m = modes_pair(orc, grf, 3, wl.EXPONENTIAL, 200, 87, sigma, ell)
+    C = int(np.prod(shape))
+    ws = torch.empty(grf.grid_workspace_bytes(m, shape, meth), dtype=torch.uint8, device="cuda")
+    eager = to_np(grf.field_grid(m, shape, method=meth, mu=0.2, want_k=True, workspace=ws)["y"]).copy()
+    out = {"y": torch.empty(C, device="cuda"), "k": torch.empty(C, device="cuda")}
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):  # warm-up on the capture stream
+        grf.field_grid(m, shape, method=meth, mu=0.2, want_k=True, out=out, workspace=ws)
+    torch.cuda.current_stream().wait_stream(s)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        grf.field_grid(m, shape, method=meth, mu=0.2, want_k=True, out=out, workspace=ws)
+    kref = np.exp(0.2 + eager.astype(np.float64))
+    for r in range(3):
+        out["y"].fill_(float("nan"))
+        out["k"].zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        np.testing.assert_array_equal(to_np(out["y"]), eager)
+        assert np.max(np.abs(to_np(out["k"]) - kref) / kref) < 1e-5
+        grf.field_grid(m, (8, 8, 8), method="direct_f32")  # eager work between replays
+        torch.cuda.synchronize()
