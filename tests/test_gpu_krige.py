@@ -112,3 +112,31 @@ def test_cholesky_block_edges(orc, grf, M):
                                     wl.EXPONENTIAL, nugget=1e-3)
     assert int(to_np(info)[0]) == 0
     assert np.linalg.norm(to_np(alpha) - want) / np.linalg.norm(want) <= 1e-4
+
+
+def test_krige_workload_full_size_sampled(orc, grf):
+    """The benchmarked conditioning workload: the 128^3 exponential field (seed 5) conditioned on
+    2,000 observation cells valued from the target field (seed 50), sampled cells vs the oracle."""
+    c = wl.WORKLOADS["adjoint_grid3d_128"]
+    sg = math.sqrt(c["sigma2"])
+    _say("case krige 128^3, 2000 observations")
+    (zo, po), m = modes_pair(orc, grf, 3, c["cov"], c["n_modes"], c["seed"], sg, c["ell"])
+    (zt, pt), mt = modes_pair(orc, grf, 3, c["cov"], c["n_modes"], c["target_seed"], sg, c["ell"])
+    Cg = int(np.prod(c["shape"]))
+    cells = wl.distinct_cells(Cg, c["n_obs"], c["obs_seed"])[:2000]
+    ii = np.stack([cells % 128, (cells // 128) % 128, cells // (128 * 128)], axis=1)
+    xo = np.ascontiguousarray(ii + 0.5)
+    xot = torch.from_numpy(xo).cuda()
+    dobs = grf.field_points(mt, xot)["y"]
+    y, alpha, info = grf.condition_grid(m, c["shape"], xot, dobs, c["cov"])
+    assert int(to_np(info)[0]) == 0
+    d = to_np(dobs).astype(np.float64)
+    a = orc.krige_weights(c["cov"], sg, c["ell"], xo, d - orc.field_points(zo, po, sg, c["ell"], xo))
+    sample = wl.sample_cells(Cg, 3000, 974)
+    xs = orc.grid_centres(c["shape"])[sample]
+    want = orc.field_points(zo, po, sg, c["ell"], xs) + orc.krige_correction(c["cov"], sg, c["ell"], xo, a, xs)
+    err = np.max(np.abs(to_np(y)[sample] - want))
+    _say(f"  max |Y_c - ref| / sigma = {err / sg:.3e}")
+    assert err <= 2e-4 * sg
+    # the observed cells take the observed values
+    assert np.max(np.abs(to_np(y)[cells] - d)) <= 2e-4 * sg

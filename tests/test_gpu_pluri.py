@@ -141,3 +141,28 @@ def test_pluri_proportions_workload(orc, grf):
     se = fr.std(axis=0) / math.sqrt(R)
     _say(f"  proportions {fr.mean(axis=0)} vs {want} (se {se})")
     assert np.all(np.abs(fr.mean(axis=0) - want) < 4.5 * se + 3e-3)
+
+
+def test_pluri_workload_full_size_sampled(orc, grf):
+    """The 1024x512 bitruncated workload in the benchmarked configuration (separable fp16):
+    fields and facies at sampled cells against the oracle."""
+    c = wl.WORKLOADS["pluri_2d_1024x512"]
+    f1, f2 = c["fields"]
+    _say("case pluri_2d_1024x512 full size sep_f16")
+    (z1o, p1o), m1 = modes_pair(orc, grf, 2, f1["cov"], c["n_modes"], f1["seed"], math.sqrt(f1["sigma2"]), f1["ell"])
+    (z2o, p2o), m2 = modes_pair(orc, grf, 2, f2["cov"], c["n_modes"], f2["seed"], math.sqrt(f2["sigma2"]), f2["ell"])
+    rule = grf.trunc2(c["t"], c["s"], c["rule"], c["values"])
+    out = grf.pluri_grid(m1, m2, c["shape"], rule, h=c["h"], method="sep_f16", want_value=True, keep_fields=True)
+    C = int(np.prod(c["shape"]))
+    cells = wl.sample_cells(C, 20_000, 904)
+    r1 = orc.field_cells(z1o, p1o, math.sqrt(f1["sigma2"]), f1["ell"], c["shape"], cells, h=c["h"])
+    r2 = orc.field_cells(z2o, p2o, math.sqrt(f2["sigma2"]), f2["ell"], c["shape"], cells, h=c["h"])
+    assert_field(to_np(out["y1"])[cells], r1, math.sqrt(f1["sigma2"]), "sep_f16", "pluri y1 full")
+    assert_field(to_np(out["y2"])[cells], r2, math.sqrt(f2["sigma2"]), "sep_f16", "pluri y2 full")
+    fac = to_np(out["facies"])[cells]
+    want, _ = orc.pluri(r1, r2, c["t"], c["s"], np.array(c["rule"], dtype=np.uint8))
+    b1, b2 = TOL["sep_f16"]["band"] * math.sqrt(f1["sigma2"]), TOL["sep_f16"]["band"] * math.sqrt(f2["sigma2"])
+    near = (np.min(np.abs(r1[:, None] - np.array(c["t"])[None, :]), axis=1) <= b1) | \
+           (np.min(np.abs(r2[:, None] - np.array(c["s"])[None, :]), axis=1) <= b2)
+    assert np.all((fac == want) | near), int(np.sum((fac != want) & ~near))
+    np.testing.assert_array_equal(to_np(out["value"])[cells], np.array(c["values"], dtype=np.float32)[fac])
