@@ -52,7 +52,7 @@ __global__ __launch_bounds__(256) void k_bwd(const double4* __restrict__ prm, in
         double ph = DIM == 3 ? fma(m.z, z, m.w) : m.w;
         ph = fma(m.y, y, ph);
         ph = fma(m.x, x, ph);
-        ph -= floor(ph);
+        ph = __builtin_amdgcn_fract(ph);  // x - floor(x) in one FP64 instruction
         const float f = static_cast<float>(ph);
         const float sn = __builtin_amdgcn_sinf(f);
         s = fmaf(g, sn, s);

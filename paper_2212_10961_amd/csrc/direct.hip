@@ -186,7 +186,7 @@ __global__ __launch_bounds__(256) void k_direct_grid_f64(const double* __restric
     double s = 0.0;
     for (int j = 0; j < n; ++j) {
         double f = rx[j] + ry[j] + rz[j];
-        f -= floor(f);
+        f = __builtin_amdgcn_fract(f);  // x - floor(x) in one FP64 instruction
         s += (wt ? wt[j] : 1.0) * cospi(2.0 * f);
     }
     const double yv = amp * s;
@@ -241,7 +241,7 @@ __global__ __launch_bounds__(256) void k_direct_points(const double4* __restrict
             double ph = DIM == 3 ? fma(m.z, pz[r], m.w) : m.w;
             ph = fma(m.y, py[r], ph);
             ph = fma(m.x, px[r], ph);
-            ph -= floor(ph);
+            ph = __builtin_amdgcn_fract(ph);  // x - floor(x) in one FP64 instruction
             acc[r] = fmaf(wj, cos_rev(static_cast<float>(ph)), acc[r]);
         }
     }
@@ -268,7 +268,7 @@ __global__ __launch_bounds__(256) void k_direct_points_f64(const double4* __rest
     for (int j = 0; j < n; ++j) {
         const double4 m = prm[j];
         double ph = fma(m.x, px, fma(m.y, py, fma(m.z, pz, m.w)));
-        ph -= floor(ph);
+        ph = __builtin_amdgcn_fract(ph);  // x - floor(x) in one FP64 instruction
         s += (wt ? wt[j] : 1.0) * cospi(2.0 * ph);
     }
     store_out(p, static_cast<float>(amp * s), epi, y, k, ind);
