@@ -38,7 +38,7 @@
 extern "C" {
 #endif
 
-#define GRF_VERSION 10000 /* 1.0.0 */
+#define GRF_VERSION 10100 /* 1.1.0: rotated and weighted tables, bitruncated rule, kriging */
 
 /* status codes */
 #define GRF_OK 0

@@ -181,7 +181,7 @@ hipError_t launch_direct_grid_f64(const double* tx, const double* ty, const doub
 hipError_t launch_direct_points(const double* params, const double* w, int64_t n, int dim, const double* xyz,
                                 int64_t P, bool fp64, float amp, const Epi& epi, float* y, float* k,
                                 uint8_t* ind, float* partial, hipStream_t s);
-constexpr int kPointsPerLane = 4;
+constexpr int kPointsPerLane = 8;
 int points_mode_slices(int64_t P, int64_t n);
 hipError_t launch_epilogue(const float* y, int64_t n, const Epi& epi, float* k, uint8_t* ind,
                            hipStream_t s);

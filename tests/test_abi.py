@@ -37,7 +37,7 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_version_and_error_string(lib):
-    assert lib.grf_version() == 10000
+    assert lib.grf_version() == 10100
     assert isinstance(lib.grf_last_error(), bytes)
 
 
