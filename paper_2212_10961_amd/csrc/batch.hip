@@ -48,7 +48,9 @@ struct grf_plan {
     AxisTableArgs* d_tdesc = nullptr;
     uint64_t* d_tblk = nullptr;  // per work block: (descriptor << 40) | local block
     size_t cap_tdesc = 0;
-    unsigned long long* d_counter = nullptr;
+    unsigned long long* d_counter = nullptr;  // kMaxQueues counters, kQueueStride apart
+    BatchQueue* d_queues = nullptr;           // in the same allocation, after the counters
+    int nq = 1;
 
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -157,16 +159,19 @@ void destroy_graph(grf_plan* p)
 // The three launches of one batch evaluation.
 hipError_t enqueue(grf_plan* p, hipStream_t s, const void* items, int n_items_desc, int64_t total)
 {
-    hipError_t e = launch_fill_u64(p->d_counter, 0ull, s);
+    const bool sep = is_sep(p->method);
+    hipError_t e = launch_fill_u64(p->d_counter, 0ull, sep ? p->nq : 1, kQueueStride, s);
     if (e != hipSuccess) return e;
     e = launch_axis_tables_batched(p->d_tdesc, p->d_tblk, p->table_blocks, s);
     if (e != hipSuccess) return e;
-    if (is_sep(p->method))
-        return launch_sep_batch(p->method, p->d3, static_cast<const SepBatchItem*>(items), n_items_desc, total,
-                                p->d_counter, p->grid, s);
+    if (sep)
+        return launch_sep_batch(p->method, p->d3, static_cast<const SepBatchItem*>(items), n_items_desc, p->d_queues,
+                                p->nq, p->d_counter, p->grid, s);
     return launch_direct_batch(static_cast<const DirectBatchItem*>(items), n_items_desc, total, p->d_counter, p->grid,
                                s);
 }
+
+constexpr size_t kCounterBytes = sizeof(unsigned long long) * kQueueStride * kMaxQueues;
 
 int device_cus()
 {
@@ -233,8 +238,9 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
     GRF_HIP(hipMemcpy(p->d_tblk, blk.data(), blk.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
     if (!p->d_counter) {
         void* q = nullptr;
-        GRF_HIP(hipMalloc(&q, 256));
+        GRF_HIP(hipMalloc(&q, kCounterBytes + kMaxQueues * sizeof(BatchQueue)));
         p->d_counter = static_cast<unsigned long long*>(q);
+        p->d_queues = reinterpret_cast<BatchQueue*>(static_cast<char*>(q) + kCounterBytes);
     }
     if (!p->cap) GRF_HIP(hipStreamCreateWithFlags(&p->cap, hipStreamNonBlocking));
 
@@ -344,12 +350,15 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
                     }
                     GRF_HIP(ensure(p->d_items, p->cap_items, sub.size() * sizeof(SepBatchItem)));
                     GRF_HIP(hipMemcpy(p->d_items, sub.data(), sub.size() * sizeof(SepBatchItem), hipMemcpyHostToDevice));
+                    const BatchQueue one{0, item};
+                    GRF_HIP(hipMemcpy(p->d_queues, &one, sizeof(one), hipMemcpyHostToDevice));
                     float tot = 0.f;
                     for (int rep = 0; rep < 3; ++rep) {
-                        GRF_HIP(launch_fill_u64(p->d_counter, 0ull, p->cap));
+                        GRF_HIP(launch_fill_u64(p->d_counter, 0ull, 1, kQueueStride, p->cap));
                         GRF_HIP(hipEventRecord(e0, p->cap));
                         GRF_HIP(launch_sep_batch(p->method, p->d3, static_cast<const SepBatchItem*>(p->d_items),
-                                                 static_cast<int>(sub.size()), item, p->d_counter, p->grid, p->cap));
+                                                 static_cast<int>(sub.size()), p->d_queues, 1, p->d_counter, p->grid,
+                                                 p->cap));
                         GRF_HIP(hipEventRecord(e1, p->cap));
                         GRF_HIP(hipEventSynchronize(e1));
                         float ms = 0.f;
@@ -369,26 +378,48 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
             for (int32_t i = 0; i < n; ++i) si[i].variant = p->tuned[keys[i]];
         }
 
-        // ---- queue order: larger tiles first, then larger instances
-        std::vector<int32_t> order(n);
-        std::iota(order.begin(), order.end(), 0);
-        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
-            if (si[a].variant != si[b].variant) return si[a].variant < si[b].variant;
-            return si[a].a.nx * si[a].a.ny * si[a].a.nz > si[b].a.nx * si[b].a.ny * si[b].a.nz;
-        });
-        std::vector<SepBatchItem> sorted(n);
+        // ---- queues: instances spread over the XCD queues by longest-processing-time-first
+        // (cost in 64x64-tile units), then within a queue larger tiles first, then larger
+        // instances; item0 runs over queue 0's instances, then queue 1's, ...
+        std::vector<int64_t> cost(n);
+        for (int32_t i = 0; i < n; ++i) cost[i] = tiles_of(si[i]) * (si[i].variant == 0 ? 4 : 1);
+        std::vector<int32_t> by_cost(n);
+        std::iota(by_cost.begin(), by_cost.end(), 0);
+        std::stable_sort(by_cost.begin(), by_cost.end(), [&](int32_t a, int32_t b) { return cost[a] > cost[b]; });
+        p->nq = kMaxQueues;
+        std::vector<int64_t> load(p->nq, 0);
+        std::vector<std::vector<int32_t>> members(p->nq);
+        for (const int32_t i : by_cost) {
+            const int g = static_cast<int>(std::min_element(load.begin(), load.end()) - load.begin());
+            members[g].push_back(i);
+            load[g] += cost[i];
+        }
+        std::vector<SepBatchItem> sorted;
+        sorted.reserve(n);
+        std::vector<BatchQueue> queues(p->nq);
         int64_t item = 0, big = 0;
-        for (int32_t r = 0; r < n; ++r) {
-            sorted[r] = si[order[r]];
-            sorted[r].item0 = item;
-            const int64_t t = tiles_of(sorted[r]);
-            item += t;
-            if (sorted[r].variant == 0) big += t * 4;  // in 64x64-tile units
-            else big -= t;
+        for (int g = 0; g < p->nq; ++g) {
+            std::vector<int32_t>& order = members[g];
+            std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t b) {
+                if (si[a].variant != si[b].variant) return si[a].variant < si[b].variant;
+                return si[a].a.nx * si[a].a.ny * si[a].a.nz > si[b].a.nx * si[b].a.ny * si[b].a.nz;
+            });
+            queues[g].start = item;
+            for (const int32_t i : order) {
+                SepBatchItem b = si[i];
+                b.item0 = item;
+                const int64_t t = tiles_of(b);
+                item += t;
+                if (b.variant == 0) big += t * 4;  // in 64x64-tile units
+                else big -= t;
+                sorted.push_back(b);
+            }
+            queues[g].count = item - queues[g].start;
         }
         p->total_items = item;
         GRF_HIP(ensure(p->d_items, p->cap_items, sorted.size() * sizeof(SepBatchItem)));
         GRF_HIP(hipMemcpy(p->d_items, sorted.data(), sorted.size() * sizeof(SepBatchItem), hipMemcpyHostToDevice));
+        GRF_HIP(hipMemcpy(p->d_queues, queues.data(), queues.size() * sizeof(BatchQueue), hipMemcpyHostToDevice));
         p->tile_m = p->tile_n = big >= 0 ? 128 : 64;
     }
     p->n_inst = n;

@@ -221,8 +221,18 @@ struct SepBatchItem {
     int32_t variant;  // 0: 128x128 tiles, 1: 64x64 tiles
     int32_t pad_;
 };
-hipError_t launch_sep_batch(int method, bool d3, const SepBatchItem* items, int n_inst, int64_t total,
-                            unsigned long long* counter, int grid, hipStream_t s);
+// Work queues of the separable persistent launch: queue q holds the work items
+// [start, start + count) and counts them on counters[q * kQueueStride].  Each block starts on
+// the queue of the accelerator complex (XCD, with its own L2) it runs on, so that the tiles
+// of one instance, which share operand rows, run side by side under one L2; once its queue
+// is drained it takes work from the next queues in turn.
+constexpr int kMaxQueues = 8;     // XCDs of the device
+constexpr int kQueueStride = 32;  // counters 256 B apart
+struct BatchQueue {
+    int64_t start, count;
+};
+hipError_t launch_sep_batch(int method, bool d3, const SepBatchItem* items, int n_inst, const BatchQueue* queues,
+                            int nq, unsigned long long* counters, int grid, hipStream_t s);
 int sep_batch_blocks_per_cu(int method, bool d3);
 
 struct DirectBatchItem {
@@ -248,7 +258,8 @@ constexpr int kDirectTile = 64;  // cells per tile side of the direct grid kerne
 // work blocks 0 .. axis_table_blocks(descriptor) - 1 of every descriptor.
 hipError_t launch_axis_tables_batched(const AxisTableArgs* descs, const uint64_t* blk, int64_t total_blocks,
                                       hipStream_t s);
-hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, hipStream_t s);
+// p[i * stride] = v for i < n (n <= 64).
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, int stride, hipStream_t s);
 
 // ---------------------------------------------------------------- adjoint
 struct BwdArgs {

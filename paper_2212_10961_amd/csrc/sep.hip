@@ -29,6 +29,20 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef _Float16 h2 __attribute__((ext_vector_type(2)));
 
+// P' = (Re P, -Im P) of P = Ex Ez in packed fp16, from e = (Re Ex, -Im Ex) and z = (Re Ez, Im Ez):
+// (ex zr + ey zi, ey zr - ex zi) = (ex, -ex) * z + (ey, ey) * (zi, zr), written with vector
+// shuffles so that the broadcasts, the sign and the swap become operand modifiers of one
+// v_pk_mul_f16 and one v_pk_fma_f16.
+__device__ __forceinline__ uint32_t ez_prod(uint32_t ew, uint32_t zw)
+{
+    const h2 e = __builtin_bit_cast(h2, ew);
+    const h2 z = __builtin_bit_cast(h2, zw);
+    const h2 ne = -e;
+    const h2 t = __builtin_shufflevector(e, ne, 0, 2) * z;
+    const h2 zs = __builtin_shufflevector(z, z, 1, 0);
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_fma(__builtin_shufflevector(e, e, 1, 1), zs, t));
+}
+
 constexpr int kJC = 32;         // modes per LDS stage (64 reals of K)
 constexpr int kRowW = kJC + 4;  // padded LDS row, in 32-bit words
 
@@ -170,30 +184,14 @@ __device__ __forceinline__ void sep_tile_reg(const SepArgs& a, int64_t tx, int64
             *reinterpret_cast<uint4*>(sA + row * kRowW + 4 * c4) = ra[i];
             if constexpr (X3) *reinterpret_cast<uint4*>(sA + (BM + row) * kRowW + 4 * c4) = ral[i];
         }
-        // packed fp16 factors of this thread's Ez chunk: P' = er (zr, -zi) + ei (zi, zr)
-        h2 z1[4], z2[4];
-        if constexpr (PK) {
-            const uint32_t zw[4] = {rezh.x, rezh.y, rezh.z, rezh.w};
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const h2 z = __builtin_bit_cast(h2, zw[m]);
-                z1[m] = h2{z.x, static_cast<_Float16>(-z.y)};
-                z2[m] = h2{z.y, z.x};
-            }
-        }
 #pragma unroll
         for (int i = 0; i < CB; ++i) {
             const int row = rowb[i];
             if constexpr (PK) {
-                const uint32_t w[4] = {rb[i].x, rb[i].y, rb[i].z, rb[i].w};
-                uint32_t h[4];
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const h2 e = __builtin_bit_cast(h2, w[m]);  // (Re Ex, -Im Ex)
-                    const h2 p = h2{e.x, e.x} * z1[m] + h2{e.y, e.y} * z2[m];
-                    h[m] = __builtin_bit_cast(uint32_t, p);
-                }
-                *reinterpret_cast<uint4*>(sB + row * kRowW + 4 * c4) = make_uint4(h[0], h[1], h[2], h[3]);
+                // packed fp16 product with this thread's Ez chunk
+                *reinterpret_cast<uint4*>(sB + row * kRowW + 4 * c4) =
+                    make_uint4(ez_prod(rb[i].x, rezh.x), ez_prod(rb[i].y, rezh.y), ez_prod(rb[i].z, rezh.z),
+                               ez_prod(rb[i].w, rezh.w));
             } else if constexpr (D3) {
                 // P = Ex * Ez, stored as (Re P, -Im P); Ex arrives as (Re, -Im)
                 float er[4], ei[4];
@@ -475,27 +473,13 @@ __device__ __forceinline__ void sep_tile_dl(const SepArgs& a, int64_t tx, int64_
         if constexpr (D3) {
 #pragma unroll
             for (int zs = 0; zs < ZS; ++zs) {
-                // P' = (Re P, -Im P) = e.x (zr, -zi) + e.y (zi, zr), with e = (Re Ex, -Im Ex)
-                const uint32_t zw[4] = {f.ez[zs].x, f.ez[zs].y, f.ez[zs].z, f.ez[zs].w};
-                h2 z1[4], z2[4];
-#pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const h2 z = __builtin_bit_cast(h2, zw[m]);
-                    z1[m] = h2{z.x, static_cast<_Float16>(-z.y)};
-                    z2[m] = h2{z.y, z.x};
-                }
+                // P' = (Re P, -Im P) of P = Ex Ez on the B fragments
+                const uint4 z = f.ez[zs];
                 uint4 fp[TN];
 #pragma unroll
-                for (int j = 0; j < TN; ++j) {
-                    const uint32_t w[4] = {f.b[j].x, f.b[j].y, f.b[j].z, f.b[j].w};
-                    uint32_t p[4];
-#pragma unroll
-                    for (int m = 0; m < 4; ++m) {
-                        const h2 e = __builtin_bit_cast(h2, w[m]);
-                        p[m] = __builtin_bit_cast(uint32_t, h2{e.x, e.x} * z1[m] + h2{e.y, e.y} * z2[m]);
-                    }
-                    fp[j] = make_uint4(p[0], p[1], p[2], p[3]);
-                }
+                for (int j = 0; j < TN; ++j)
+                    fp[j] = make_uint4(ez_prod(f.b[j].x, z.x), ez_prod(f.b[j].y, z.y), ez_prod(f.b[j].z, z.z),
+                                       ez_prod(f.b[j].w, z.w));
 #pragma unroll
                 for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -520,26 +504,12 @@ __device__ __forceinline__ void sep_tile_dl(const SepArgs& a, int64_t tx, int64_
     // and the Ez products of the next k-step along the MFMAs of slice 1.
     constexpr bool PIPE = D3 && NW == 4 && ZS == 2 && TM * TN == 8;
     auto prod = [&](const Frag& f, int zs, uint4(&fp)[TN]) {
-        // P' = (Re P, -Im P) = e.x (zr, -zi) + e.y (zi, zr), with e = (Re Ex, -Im Ex)
-        const uint32_t zw[4] = {f.ez[zs].x, f.ez[zs].y, f.ez[zs].z, f.ez[zs].w};
-        h2 z1[4], z2[4];
+        // P' = (Re P, -Im P) of P = Ex Ez on the B fragments
+        const uint4 z = f.ez[zs];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const h2 z = __builtin_bit_cast(h2, zw[m]);
-            z1[m] = h2{z.x, static_cast<_Float16>(-z.y)};
-            z2[m] = h2{z.y, z.x};
-        }
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            const uint32_t w[4] = {f.b[j].x, f.b[j].y, f.b[j].z, f.b[j].w};
-            uint32_t p[4];
-#pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const h2 e = __builtin_bit_cast(h2, w[m]);
-                p[m] = __builtin_bit_cast(uint32_t, h2{e.x, e.x} * z1[m] + h2{e.y, e.y} * z2[m]);
-            }
-            fp[j] = make_uint4(p[0], p[1], p[2], p[3]);
-        }
+        for (int j = 0; j < TN; ++j)
+            fp[j] = make_uint4(ez_prod(f.b[j].x, z.x), ez_prod(f.b[j].y, z.y), ez_prod(f.b[j].z, z.z),
+                               ez_prod(f.b[j].w, z.w));
     };
     auto compute_pipe = [&](const char* buf) {
         if constexpr (PIPE) {
@@ -673,9 +643,18 @@ using BigT3 = SepShape<2, 2, 2, 2, true>;
 using SmallT = SepShape<2, 2, 1, 1, false>;
 using SmallT3 = SepShape<2, 2, 1, 1, true>;
 
+// Index of the accelerator complex (XCD) this wave runs on (hardware register XCC_ID).
+__device__ __forceinline__ unsigned xcc_id()
+{
+    unsigned v;
+    asm volatile("s_getreg_b32 %0, hwreg(HW_REG_XCC_ID)" : "=s"(v));
+    return v & 15u;
+}
+
 template <bool BF, bool X3, bool D3>
-__global__ __launch_bounds__(256) void k_sep_batch(const SepBatchItem* __restrict__ items, int n_inst, int64_t total,
-                                                   unsigned long long* counter)
+__global__ __launch_bounds__(256) void k_sep_batch(const SepBatchItem* __restrict__ items, int n_inst,
+                                                   const BatchQueue* __restrict__ queues, int nq,
+                                                   unsigned long long* counters)
 {
     constexpr bool DL = use_dl<2, 2, 2, 2, 1, BF, X3, D3>();
     static_assert(DL == use_dl<2, 2, 1, 1, 1, BF, X3, D3>(), "both batch tiles stage the same way");
@@ -686,12 +665,21 @@ __global__ __launch_bounds__(256) void k_sep_batch(const SepBatchItem* __restric
     __shared__ uint4 lds0[Q0];
     __shared__ uint4 lds1[DL ? QD : 1];
     __shared__ unsigned long long s_item;
-    for (;;) {
-        if (threadIdx.x == 0) s_item = atomicAdd(counter, 1ull);
+    // Own queue first, then the others in turn; every queue is finite, so every block ends
+    // after at most nq exhausted pulls.
+    int q = static_cast<int>(xcc_id() % static_cast<unsigned>(nq));
+    for (int drained = 0; drained < nq;) {
+        if (threadIdx.x == 0) s_item = atomicAdd(counters + q * kQueueStride, 1ull);
         __syncthreads();
-        const int64_t it = static_cast<int64_t>(s_item);
+        const int64_t loc = static_cast<int64_t>(s_item);
         __syncthreads();
-        if (it >= total) break;
+        const BatchQueue bq = queues[q];
+        if (loc >= bq.count) {
+            q = q + 1 == nq ? 0 : q + 1;
+            ++drained;
+            continue;
+        }
+        const int64_t it = bq.start + loc;
         int lo = 0, hi = n_inst - 1;
         while (lo < hi) {
             const int mid = (lo + hi + 1) >> 1;
@@ -718,10 +706,10 @@ __global__ __launch_bounds__(256) void k_sep_batch(const SepBatchItem* __restric
 }
 
 template <bool BF, bool X3, bool D3>
-hipError_t launch_batch_t(const SepBatchItem* items, int n_inst, int64_t total, unsigned long long* counter, int grid,
-                          hipStream_t s)
+hipError_t launch_batch_t(const SepBatchItem* items, int n_inst, const BatchQueue* queues, int nq,
+                          unsigned long long* counters, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sep_batch<BF, X3, D3>), dim3(grid), dim3(256), 0, s, items, n_inst, total, counter);
+    hipLaunchKernelGGL((k_sep_batch<BF, X3, D3>), dim3(grid), dim3(256), 0, s, items, n_inst, queues, nq, counters);
     return hipGetLastError();
 }
 
@@ -832,22 +820,23 @@ int sep_default_tile(int method, int64_t nx, int64_t ny, int64_t nz)
     return 2;
 }
 
-hipError_t launch_sep_batch(int method, bool d3, const SepBatchItem* items, int n_inst, int64_t total,
-                            unsigned long long* counter, int grid, hipStream_t s)
+hipError_t launch_sep_batch(int method, bool d3, const SepBatchItem* items, int n_inst, const BatchQueue* queues,
+                            int nq, unsigned long long* counters, int grid, hipStream_t s)
 {
+    if (nq < 1 || nq > kMaxQueues || n_inst < 1) return hipErrorInvalidValue;
     switch (method) {
     case GRF_SEP_BF16:
-        return d3 ? launch_batch_t<true, false, true>(items, n_inst, total, counter, grid, s)
-                  : launch_batch_t<true, false, false>(items, n_inst, total, counter, grid, s);
+        return d3 ? launch_batch_t<true, false, true>(items, n_inst, queues, nq, counters, grid, s)
+                  : launch_batch_t<true, false, false>(items, n_inst, queues, nq, counters, grid, s);
     case GRF_SEP_F16:
-        return d3 ? launch_batch_t<false, false, true>(items, n_inst, total, counter, grid, s)
-                  : launch_batch_t<false, false, false>(items, n_inst, total, counter, grid, s);
+        return d3 ? launch_batch_t<false, false, true>(items, n_inst, queues, nq, counters, grid, s)
+                  : launch_batch_t<false, false, false>(items, n_inst, queues, nq, counters, grid, s);
     case GRF_SEP_BF16_X3:
-        return d3 ? launch_batch_t<true, true, true>(items, n_inst, total, counter, grid, s)
-                  : launch_batch_t<true, true, false>(items, n_inst, total, counter, grid, s);
+        return d3 ? launch_batch_t<true, true, true>(items, n_inst, queues, nq, counters, grid, s)
+                  : launch_batch_t<true, true, false>(items, n_inst, queues, nq, counters, grid, s);
     case GRF_SEP_F16_X3:
-        return d3 ? launch_batch_t<false, true, true>(items, n_inst, total, counter, grid, s)
-                  : launch_batch_t<false, true, false>(items, n_inst, total, counter, grid, s);
+        return d3 ? launch_batch_t<false, true, true>(items, n_inst, queues, nq, counters, grid, s)
+                  : launch_batch_t<false, true, false>(items, n_inst, queues, nq, counters, grid, s);
     default: return hipErrorInvalidValue;
     }
 }

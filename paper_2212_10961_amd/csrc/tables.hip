@@ -199,9 +199,9 @@ __global__ __launch_bounds__(256) void k_rotate_modes(const double* __restrict__
     }
 }
 
-__global__ void k_fill_u64(unsigned long long* p, unsigned long long v)
+__global__ void k_fill_u64(unsigned long long* p, unsigned long long v, int n, int stride)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+    if (blockIdx.x == 0 && static_cast<int>(threadIdx.x) < n) p[threadIdx.x * stride] = v;
 }
 
 __global__ __launch_bounds__(256) void k_mode_params(const double* z, const double* phi, int dim, int64_t n,
@@ -280,9 +280,10 @@ hipError_t launch_rotate_modes(const double* z, int dim, int64_t n, const double
     return hipGetLastError();
 }
 
-hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, hipStream_t s)
+hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, int stride, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, p, v);
+    if (n < 1 || n > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_fill_u64, dim3(1), dim3(64), 0, s, p, v, n, stride);
     return hipGetLastError();
 }
 

@@ -29,7 +29,7 @@ def _instances(orc, grf, count, side_hi, n_modes, seed, dim=2):
         ell = p["ell"] if dim == 2 else (p["ell"][0], p["ell"][1], 2.0)
         (zo, po), m = modes_pair(orc, grf, dim, p["cov"], n_modes, p["seed"], math.sqrt(p["sigma2"]), ell)
         out.append(dict(shape=shape, ell=ell, sigma=math.sqrt(p["sigma2"]), zo=zo, po=po, m=m,
-                        y=torch.empty(int(np.prod(shape)), device="cuda")))
+                        y=torch.full((int(np.prod(shape)),), float("nan"), device="cuda")))
     return out
 
 
@@ -49,6 +49,11 @@ def test_batch_matches_solo_and_oracle(orc, grf, meth):
         else:
             rel = np.sqrt(np.mean((y - solo) ** 2) / np.mean(solo ** 2))
             assert rel <= 2 * TOL[meth]["rel"], (i, rel)
+            # without tuning a slice of at least 192 x 192 takes 128x128 tiles (selector 1),
+            # else 64x64 (selector 2): the same tile code as the solo call with that selector
+            tile = 1 if d["shape"][0] >= 192 and d["shape"][1] >= 192 else 2
+            same = to_np(grf.field_grid(d["m"], d["shape"], method=meth, tile=tile)["y"])
+            np.testing.assert_array_equal(y, same, err_msg=f"batch[{i}] {d['shape']} tile {tile}")
         if i % 6 == 0:
             cells = wl.sample_cells(y.size, 200, 500 + i)
             ref = orc.field_cells(d["zo"], d["po"], d["sigma"], d["ell"], d["shape"], cells)
