@@ -162,8 +162,10 @@ hipError_t enqueue(grf_plan* p, hipStream_t s, const void* items, int n_items_de
     const bool sep = is_sep(p->method);
     hipError_t e = launch_fill_u64(p->d_counter, 0ull, sep ? p->nq : 1, kQueueStride, s);
     if (e != hipSuccess) return e;
-    e = launch_axis_tables_batched(p->d_tdesc, p->d_tblk, p->table_blocks, s);
-    if (e != hipSuccess) return e;
+    if (p->table_blocks > 0) {
+        e = launch_axis_tables_batched(p->d_tdesc, p->d_tblk, p->table_blocks, s);
+        if (e != hipSuccess) return e;
+    }
     if (sep)
         return launch_sep_batch(p->method, p->d3, static_cast<const SepBatchItem*>(items), n_items_desc, p->d_queues,
                                 p->nq, p->d_counter, p->grid, s);
@@ -194,20 +196,24 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
 
     const bool sep = is_sep(p->method);
     p->d3 = items[0].modes.dim == 3;
+    const bool gen = sep && sep_batch_generates(p->method, p->d3);  // operands made on chip
 
-    // ---- table layout and descriptors (same tables as eval_field_grid would build)
+    // ---- table layout and descriptors (same tables as eval_field_grid would build); none
+    // when the kernel generates its operands
     std::vector<GridWs> ws(n);
     std::vector<size_t> toff(n);
     size_t tbytes = 0;
-    for (int32_t i = 0; i < n; ++i) {
-        ws[i] = grid_ws(&items[i].modes, &items[i].grid, p->method, nullptr);
-        toff[i] = tbytes;
-        tbytes += ws[i].bytes;
+    if (!gen) {
+        for (int32_t i = 0; i < n; ++i) {
+            ws[i] = grid_ws(&items[i].modes, &items[i].grid, p->method, nullptr);
+            toff[i] = tbytes;
+            tbytes += ws[i].bytes;
+        }
+        GRF_HIP(ensure(p->d_tables, p->cap_tables, tbytes));
     }
-    GRF_HIP(ensure(p->d_tables, p->cap_tables, tbytes));
     std::vector<AxisTableArgs> td;
     std::vector<uint64_t> blk;
-    {
+    if (!gen) {
         int64_t total = 0;
         for (int32_t i = 0; i < n; ++i) {
             AxisTableArgs d[3];
@@ -216,16 +222,16 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
         }
         if (total > 0x7fffffff) return fail(GRF_EINVAL, "%s: batch tables too large for one launch", fn);
         blk.reserve(static_cast<size_t>(total));
-    }
-    for (int32_t i = 0; i < n; ++i) {
-        ws[i] = grid_ws(&items[i].modes, &items[i].grid, p->method, static_cast<char*>(p->d_tables) + toff[i]);
-        AxisTableArgs d[3];
-        const int nd = grid_table_descs(&items[i].modes, &items[i].grid, p->method, ws[i], d);
-        for (int k = 0; k < nd; ++k) {
-            const uint64_t di = td.size();
-            td.push_back(d[k]);
-            const int64_t nb = axis_table_blocks(d[k]);
-            for (int64_t w = 0; w < nb; ++w) blk.push_back((di << 40) | static_cast<uint64_t>(w));
+        for (int32_t i = 0; i < n; ++i) {
+            ws[i] = grid_ws(&items[i].modes, &items[i].grid, p->method, static_cast<char*>(p->d_tables) + toff[i]);
+            AxisTableArgs d[3];
+            const int nd2 = grid_table_descs(&items[i].modes, &items[i].grid, p->method, ws[i], d);
+            for (int k = 0; k < nd2; ++k) {
+                const uint64_t di = td.size();
+                td.push_back(d[k]);
+                const int64_t nb = axis_table_blocks(d[k]);
+                for (int64_t w = 0; w < nb; ++w) blk.push_back((di << 40) | static_cast<uint64_t>(w));
+            }
         }
     }
     if (td.size() >= (size_t(1) << 23)) return fail(GRF_EINVAL, "%s: too many tables in one batch", fn);
@@ -234,8 +240,10 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
     GRF_HIP(ensure(p->d_tdesc, p->cap_tdesc, align256(td.size() * sizeof(AxisTableArgs)) + blk.size() * sizeof(uint64_t)));
     p->d_tblk = reinterpret_cast<uint64_t*>(reinterpret_cast<char*>(p->d_tdesc) +
                                             align256(td.size() * sizeof(AxisTableArgs)));
-    GRF_HIP(hipMemcpy(p->d_tdesc, td.data(), td.size() * sizeof(AxisTableArgs), hipMemcpyHostToDevice));
-    GRF_HIP(hipMemcpy(p->d_tblk, blk.data(), blk.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    if (!td.empty()) {
+        GRF_HIP(hipMemcpy(p->d_tdesc, td.data(), td.size() * sizeof(AxisTableArgs), hipMemcpyHostToDevice));
+        GRF_HIP(hipMemcpy(p->d_tblk, blk.data(), blk.size() * sizeof(uint64_t), hipMemcpyHostToDevice));
+    }
     if (!p->d_counter) {
         void* q = nullptr;
         GRF_HIP(hipMalloc(&q, kCounterBytes + kMaxQueues * sizeof(BatchQueue)));
@@ -301,6 +309,20 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
             a.amp = static_cast<float>(it.modes.sigma * std::sqrt(2.0 / static_cast<double>(it.modes.n)));
             a.y = it.y;
             a.tile = -1;
+            GenArgs& g = si[i].g;
+            g = GenArgs{};
+            if (gen) {
+                constexpr double kTwoPi = 6.283185307179586476925286766559;
+                g.z = it.modes.z;
+                g.phi = it.modes.phi;
+                g.w = it.modes.w;
+                g.fsx = 1.0 / (kTwoPi * it.modes.ell[0]);
+                g.fsy = 1.0 / (kTwoPi * it.modes.ell[1]);
+                g.ox = it.grid.origin[0];
+                g.oy = it.grid.origin[1];
+                g.hx = it.grid.h[0];
+                g.hy = it.grid.h[1];
+            }
             keys[i] = class_key(p->method, a.ldp, it.grid);
             auto f = p->tuned.find(keys[i]);
             si[i].variant = f != p->tuned.end() ? f->second : default_variant(it.grid);
@@ -320,7 +342,8 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
                 if (!p->tuned.count(keys[i]) && std::find(pending.begin(), pending.end(), keys[i]) == pending.end())
                     pending.push_back(keys[i]);
         if (!pending.empty()) {
-            GRF_HIP(launch_axis_tables_batched(p->d_tdesc, p->d_tblk, p->table_blocks, p->cap));
+            if (p->table_blocks > 0)
+                GRF_HIP(launch_axis_tables_batched(p->d_tdesc, p->d_tblk, p->table_blocks, p->cap));
             hipEvent_t e0, e1;
             GRF_HIP(hipEventCreate(&e0));
             GRF_HIP(hipEventCreate(&e1));

@@ -213,9 +213,21 @@ int sep_tile_slices(int tile, int method, bool d3);  // z-slices per block
 int sep_default_tile(int method, int64_t nx, int64_t ny, int64_t nz);
 
 // ---------------------------------------------------------------- batched (persistent) launches
+// Per-mode inputs of a 2-D one-pass separable tile whose operands are generated on chip
+// (no per-axis tables in memory): a_{j,x} = z[0][j] fsx, a_{j,y} = z[1][j] fsy revolutions
+// per unit length, psi_j = phi_j / 2 pi and the weight w_j ride on the y operand.
+struct GenArgs {
+    const double* z;    // [2][n]
+    const double* phi;  // [n]
+    const double* w;    // [n] or nullptr
+    double fsx, fsy;    // 1 / (2 pi ell_x), 1 / (2 pi ell_y)
+    double ox, oy, hx, hy;
+};
+
 // One descriptor per instance; work items [item0, item0 + tiles_x * tiles_y * nz) belong to it.
 struct SepBatchItem {
     SepArgs a;
+    GenArgs g;        // used when the launch generates its operands (2-D one-pass forms)
     int64_t item0;
     int32_t tiles_x, tiles_y;
     int32_t variant;  // 0: 128x128 tiles, 1: 64x64 tiles
@@ -234,6 +246,11 @@ struct BatchQueue {
 hipError_t launch_sep_batch(int method, bool d3, const SepBatchItem* items, int n_inst, const BatchQueue* queues,
                             int nq, unsigned long long* counters, int grid, hipStream_t s);
 int sep_batch_blocks_per_cu(int method, bool d3);
+// The 2-D one-pass forms (SEP_F16, SEP_BF16) generate their operands on chip in the batch.
+inline bool sep_batch_generates(int method, bool d3)
+{
+    return !d3 && (method == GRF_SEP_F16 || method == GRF_SEP_BF16);
+}
 
 struct DirectBatchItem {
     const float* tx;

@@ -643,6 +643,185 @@ using BigT3 = SepShape<2, 2, 2, 2, true>;
 using SmallT = SepShape<2, 2, 1, 1, false>;
 using SmallT3 = SepShape<2, 2, 1, 1, true>;
 
+// ---- operands generated on chip (2-D one-pass fp16/bf16, batched ensembles) ------------
+//
+// On a 2-D grid the per-axis tables hold (nx + ny) N complex entries against nx ny cells:
+// for the grids of an ensemble (sides of a few hundred) they are several times larger than
+// the field, and writing them to memory and streaming them back dominates.  Here a block
+// generates each operand stage in LDS itself.  Thread (quad q, segment) owns modes
+// 4q .. 4q + 3 of the stage and RPT consecutive rows of one operand: the first row's phase is
+// formed and reduced in FP64 exactly as the tables are (frac(a x + psi), hardware cos/sin of
+// the fraction in revolutions, times w), and each further row is one FP32 complex product
+// with the step e^{2 pi i frac(a h)} (at most 7 of them: a relative error ~1e-6, far below
+// the fp16/bf16 rounding of the operand).  Stage s + 1 is generated while the MFMAs consume
+// stage s; the LDS layout and the fragment reads are those of the staged tiles.
+constexpr double kInvTwoPiD = 0.15915494309189533576888376337251;
+
+template <bool BF>
+__device__ __forceinline__ uint32_t pack2(float re, float im)
+{
+    if constexpr (BF) {
+        typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+        return __builtin_bit_cast(uint32_t, b2{static_cast<__bf16>(re), static_cast<__bf16>(im)});
+    } else {
+        return __builtin_bit_cast(uint32_t, h2{static_cast<_Float16>(re), static_cast<_Float16>(im)});
+    }
+}
+
+// One 2-D output tile of a 4-wave block (2 x 2 waves of TM x TN fragments of 32 x 32):
+// rows y0 = ty BM .., columns x0 = tx BN ..  `lds0`, `lds1`: (BM + BN) x 128 bytes each.
+template <int TM, int TN, bool BF>
+__device__ __forceinline__ void sep_tile_gen(const SepArgs& a, const GenArgs& g, int64_t tx, int64_t ty,
+                                             uint4* lds0, uint4* lds1)
+{
+    constexpr int WN = 2;
+    constexpr int BM = 2 * TM * 32, BN = WN * TN * 32;
+    constexpr int ROW_B = kJC * 4;
+    constexpr int RPT = (BM + BN) / 32;  // rows per thread: 256 threads = 8 quads x 32 segments
+    static_assert(BM % RPT == 0 && RPT <= 8, "a segment lies in one operand");
+    const int t = threadIdx.x;
+    const int l = t & 63, h = l >> 5;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wm = wave / WN, wn = wave % WN;
+    const int64_t x0 = tx * BN, y0 = ty * BM;
+
+    // generation role: quad q of every stage, rows r0 .. r0 + RPT - 1 of the y operand (A) or
+    // of the x operand (B, stored conjugated)
+    // (the first two waves make the y operand, the last two the x operand: a wave-uniform role)
+    typedef const double __attribute__((address_space(1)))* gptr;
+    const int q = t & 7, seg = t >> 3;
+    const bool ya = __builtin_amdgcn_readfirstlane(static_cast<int>(seg * RPT < BM)) != 0;
+    const int r0 = ya ? seg * RPT : seg * RPT - BM;
+    const int lbase = ya ? 0 : BM * ROW_B;
+    const double hh = ya ? g.hy : g.hx, fs = ya ? g.fsy : g.fsx;
+    const double xr0 = (ya ? g.oy : g.ox) + (static_cast<double>((ya ? y0 : x0) + r0) + 0.5) * hh;
+    const gptr za = (gptr)(g.z + (ya ? a.n : 0));  // address-space cast: global loads
+    const gptr gphi = (gptr)(g.phi);
+    const gptr gw = (gptr)(g.w);
+    const bool use_w = ya && g.w != nullptr;
+    const float sg = ya ? 1.f : -1.f;
+    int soff[RPT];
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) soff[r] = lbase + (r0 + r) * ROW_B + ((q ^ swz(r0 + r)) << 4);
+
+    // per-mode inputs of one stage for this thread's quad, loaded a stage ahead of their use
+    // (padding modes j >= n load mode 0 and are zeroed by selects)
+    struct Params {
+        double z[4], p[4];
+        float w[4];
+    };
+    auto load = [&](int64_t j0, Params& pr) {
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const int64_t j = j0 + 4 * q + m;
+            const int64_t jc = j < a.n ? j : 0;
+            pr.z[m] = za[jc];
+            pr.p[m] = ya ? gphi[jc] : 0.0;
+            pr.w[m] = use_w ? static_cast<float>(gw[jc]) : 1.f;
+        }
+    };
+    auto gen = [&](int64_t j0, const Params& pr, char* buf) {
+        float er[4], ei[4], rr[4], ri[4];
+#pragma unroll
+        for (int m = 0; m < 4; ++m) {
+            const bool on = j0 + 4 * q + m < a.n;
+            const double am = pr.z[m] * (on ? fs : 0.0);
+            const double ps = pr.p[m] * (on ? kInvTwoPiD : 0.0);
+            const float wj = on ? pr.w[m] : 0.f;
+            const double t0 = am * xr0 + ps;
+            const double th = am * hh;
+            const float f0 = static_cast<float>(t0 - floor(t0));  // exact in FP64
+            const float fh = static_cast<float>(th - floor(th));
+            er[m] = __builtin_amdgcn_cosf(f0) * wj;
+            ei[m] = __builtin_amdgcn_sinf(f0) * sg * wj;
+            rr[m] = __builtin_amdgcn_cosf(fh);
+            ri[m] = __builtin_amdgcn_sinf(fh) * sg;
+        }
+#pragma unroll
+        for (int r = 0; r < RPT; ++r) {
+            *reinterpret_cast<uint4*>(buf + soff[r]) = make_uint4(pack2<BF>(er[0], ei[0]), pack2<BF>(er[1], ei[1]),
+                                                                  pack2<BF>(er[2], ei[2]), pack2<BF>(er[3], ei[3]));
+            if (r + 1 < RPT) {
+#pragma unroll
+                for (int m = 0; m < 4; ++m) {
+                    const float nr = er[m] * rr[m] - ei[m] * ri[m];
+                    ei[m] = er[m] * ri[m] + ei[m] * rr[m];
+                    er[m] = nr;
+                }
+            }
+        }
+    };
+
+    int fra[TM], ga[TM], frb[TN], gb[TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int row = (wm * TM + i) * 32 + (l & 31);
+        fra[i] = row * ROW_B;
+        ga[i] = swz(row) ^ h;
+    }
+#pragma unroll
+    for (int j = 0; j < TN; ++j) {
+        const int col = (wn * TN + j) * 32 + (l & 31);
+        frb[j] = BM * ROW_B + col * ROW_B;
+        gb[j] = swz(col) ^ h;
+    }
+    f32x16 acc[TM][TN];
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.f;
+    auto compute = [&](const char* buf) {
+#pragma unroll
+        for (int ks = 0; ks < kJC / 8; ++ks) {
+            uint4 fa[TM], fb[TN];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) fa[i] = *reinterpret_cast<const uint4*>(buf + fra[i] + (((2 * ks) ^ ga[i]) << 4));
+#pragma unroll
+            for (int j = 0; j < TN; ++j) fb[j] = *reinterpret_cast<const uint4*>(buf + frb[j] + (((2 * ks) ^ gb[j]) << 4));
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j) acc[i][j] = mfma<BF>(fa[i], fb[j], acc[i][j]);
+        }
+    };
+
+    // two stages per iteration (ldp is a multiple of 64): stage s + 1 is generated into the
+    // other buffer while stage s feeds the MFMAs; the barrier after each half hands it over
+    char* b0 = reinterpret_cast<char*>(lds0);
+    char* b1 = reinterpret_cast<char*>(lds1);
+    const int64_t nstage = a.ldp / kJC;
+    Params p0, p1;
+    load(0, p0);
+    load(kJC, p1);
+    gen(0, p0, b0);
+    __syncthreads();
+    for (int64_t s = 0; s < nstage; s += 2) {
+        if (s + 2 < nstage) load((s + 2) * kJC, p0);
+        gen((s + 1) * kJC, p1, b1);
+        compute(b0);
+        __syncthreads();
+        if (s + 3 < nstage) load((s + 3) * kJC, p1);
+        if (s + 2 < nstage) gen((s + 2) * kJC, p0, b0);
+        compute(b1);
+        __syncthreads();
+    }
+
+    // epilogue: D[row][col], lane holds rows 8(e/4) + 4(l/32) + e%4, col l%32
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int64_t x = x0 + (wn * TN + j) * 32 + (l & 31);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int64_t y = y0 + (wm * TM + i) * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                if (x < a.nx && y < a.ny) epi_store(y * a.nx + x, a.amp * acc[i][j][e], a.epi, a.y, a.k, a.ind);
+            }
+        }
+}
+
 // Index of the accelerator complex (XCD) this wave runs on (hardware register XCC_ID).
 __device__ __forceinline__ unsigned xcc_id()
 {
@@ -651,19 +830,20 @@ __device__ __forceinline__ unsigned xcc_id()
     return v & 15u;
 }
 
-template <bool BF, bool X3, bool D3>
+template <bool BF, bool X3, bool D3, bool GEN>
 __global__ __launch_bounds__(256) void k_sep_batch(const SepBatchItem* __restrict__ items, int n_inst,
                                                    const BatchQueue* __restrict__ queues, int nq,
                                                    unsigned long long* counters)
 {
-    constexpr bool DL = use_dl<2, 2, 2, 2, 1, BF, X3, D3>();
-    static_assert(DL == use_dl<2, 2, 1, 1, 1, BF, X3, D3>(), "both batch tiles stage the same way");
-    constexpr int QD = DlShape<2, 2, 2, 2, X3, D3 ? 1 : 0>::STAGE_B / 16;
+    static_assert(!GEN || (!X3 && !D3), "generated operands: 2-D one-pass forms");
+    constexpr bool DL = !GEN && use_dl<2, 2, 2, 2, 1, BF, X3, D3>();
+    static_assert(GEN || DL == use_dl<2, 2, 1, 1, 1, BF, X3, D3>(), "both batch tiles stage the same way");
+    constexpr int QD = GEN ? (128 + 128) * kJC * 4 / 16 : DlShape<2, 2, 2, 2, X3, D3 ? 1 : 0>::STAGE_B / 16;
     constexpr int W0 = X3 ? BigT3::LDS_WORDS : BigT::LDS_WORDS;
     constexpr int W1 = X3 ? SmallT3::LDS_WORDS : SmallT::LDS_WORDS;
-    constexpr int Q0 = DL ? QD : (W0 > W1 ? W0 : W1) / 4;
+    constexpr int Q0 = (DL || GEN) ? QD : (W0 > W1 ? W0 : W1) / 4;
     __shared__ uint4 lds0[Q0];
-    __shared__ uint4 lds1[DL ? QD : 1];
+    __shared__ uint4 lds1[(DL || GEN) ? QD : 1];
     __shared__ unsigned long long s_item;
     // Own queue first, then the others in turn; every queue is finite, so every block ends
     // after at most nq exhausted pulls.
@@ -689,7 +869,10 @@ __global__ __launch_bounds__(256) void k_sep_batch(const SepBatchItem* __restric
         const SepBatchItem& b = items[lo];
         const int64_t local = it - b.item0;
         const int64_t rest = local / b.tiles_x;
-        if constexpr (DL) {
+        if constexpr (GEN) {
+            if (b.variant == 0) sep_tile_gen<2, 2, BF>(b.a, b.g, local % b.tiles_x, rest, lds0, lds1);
+            else sep_tile_gen<1, 1, BF>(b.a, b.g, local % b.tiles_x, rest, lds0, lds1);
+        } else if constexpr (DL) {
             if (b.variant == 0)
                 sep_tile_dl<2, 2, 2, 2, 1, BF, X3, D3>(b.a, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0,
                                                        lds1);
@@ -705,19 +888,21 @@ __global__ __launch_bounds__(256) void k_sep_batch(const SepBatchItem* __restric
     }
 }
 
-template <bool BF, bool X3, bool D3>
+template <bool BF, bool X3, bool D3, bool GEN = !X3 && !D3>
 hipError_t launch_batch_t(const SepBatchItem* items, int n_inst, const BatchQueue* queues, int nq,
                           unsigned long long* counters, int grid, hipStream_t s)
 {
-    hipLaunchKernelGGL((k_sep_batch<BF, X3, D3>), dim3(grid), dim3(256), 0, s, items, n_inst, queues, nq, counters);
+    hipLaunchKernelGGL((k_sep_batch<BF, X3, D3, GEN>), dim3(grid), dim3(256), 0, s, items, n_inst, queues, nq,
+                       counters);
     return hipGetLastError();
 }
 
-template <bool BF, bool X3, bool D3>
+template <bool BF, bool X3, bool D3, bool GEN = !X3 && !D3>
 int batch_occupancy_t()
 {
     int nb = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sep_batch<BF, X3, D3>, 256, 0) != hipSuccess) return 1;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_sep_batch<BF, X3, D3, GEN>, 256, 0) != hipSuccess)
+        return 1;
     return nb > 0 ? nb : 1;
 }
 
