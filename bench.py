@@ -78,7 +78,7 @@ def main():
 
     if args.gpus != 1:
         print(f"bench.py: this build targets one GPU; --gpus {args.gpus} is not supported "
-              "(the path shards by cells/instances with no exchange; see the design notes)", file=sys.stderr)
+              "(the path shards by cells or instances, with no exchange)", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

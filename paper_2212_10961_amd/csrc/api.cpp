@@ -708,8 +708,10 @@ static int make_krige_model(const grf_modes* m, const grf_krige* kp, const char*
 
 static size_t krige_ws(const grf_modes* m, int64_t M)
 {
+    const size_t nblk = size_t((M + 31) / 32);
     return align256(sizeof(double) * size_t(M) * size_t(M)) + align256(sizeof(double) * size_t(M)) +
-           align256(sizeof(float) * size_t(M)) + rot_ws_bytes(m) + points_ws_bytes(m->n, M, GRF_DIRECT_F32);
+           align256(sizeof(float) * size_t(M)) + align256(sizeof(double) * nblk * 32 * 32) + rot_ws_bytes(m) +
+           points_ws_bytes(m->n, M, GRF_DIRECT_F32);
 }
 
 }  // namespace grf
@@ -746,6 +748,7 @@ int krige_weights(const grf_modes* modes, const grf_krige* kp, const double* xob
     double* C = c.take<double>(size_t(M) * size_t(M));
     double* resid = c.take<double>(size_t(M));
     float* yu = c.take<float>(size_t(M));
+    double* diag = c.take<double>(size_t((M + 31) / 32) * 32 * 32);
     void* kbuf = c.base + c.used;
     c.used += rot_ws_bytes(modes);
     void* pws = c.base + c.used;
@@ -756,8 +759,8 @@ int krige_weights(const grf_modes* modes, const grf_krige* kp, const double* xob
     GRF_HIP(launch_residual(dobs, yu, M, resid, s));
     GRF_HIP(launch_cov_matrix(xobs, M, modes->dim, km, C, M, s));
     TimedScope timed(s);
-    GRF_HIP(launch_cholesky(C, M, M, info, s));
-    GRF_HIP(launch_chol_solve(C, M, M, resid, alpha, s));
+    GRF_HIP(launch_cholesky(C, M, M, diag, info, s));
+    GRF_HIP(launch_chol_solve(C, diag, M, M, resid, alpha, s));
     return GRF_OK;
 }
 

@@ -330,8 +330,12 @@ struct KrigeTarget {
 };
 hipError_t launch_cov_matrix(const double* x, int64_t m, int dim, const KrigeModel& km, double* C, int64_t lda,
                              hipStream_t s);
-hipError_t launch_cholesky(double* A, int64_t m, int64_t lda, int32_t* info, hipStream_t s);
-hipError_t launch_chol_solve(const double* L, int64_t m, int64_t lda, const double* b, double* x, hipStream_t s);
+// Lower Cholesky factor of A in place (below the diagonal blocks); the factored 32 x 32
+// diagonal blocks go to `diag` (ceil(m / 32) blocks of 32 x 32 doubles).
+hipError_t launch_cholesky(double* A, int64_t m, int64_t lda, double* diag, int32_t* info, hipStream_t s);
+// x = (L L^T)^-1 b with the factor of launch_cholesky; b (m doubles) is overwritten.
+hipError_t launch_chol_solve(const double* L, const double* diag, int64_t m, int64_t lda, double* b, double* x,
+                             hipStream_t s);
 hipError_t launch_residual(const float* d, const float* y, int64_t m, double* r, hipStream_t s);
 hipError_t launch_krige_stage(const double* x, const double* alpha, int64_t m, int dim, const KrigeModel& km,
                               float4* out, hipStream_t s);

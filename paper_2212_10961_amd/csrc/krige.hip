@@ -5,8 +5,10 @@
 // anisotropy as the field's wavevectors k = M z; App. A correlations).
 //
 // The M x M system is factorised in FP64 by a blocked right-looking Cholesky (diagonal block
-// in LDS, panel triangular solve, trailing update), solved by a one-workgroup blocked
-// substitution, and the correction is summed in FP32 with observation chunks staged in LDS.
+// factored by every panel workgroup, panel triangular solve, trailing update), solved by
+// blocked substitution (one launch
+// per block and direction, the right-hand side updated by many workgroups), and the
+// correction is summed in FP32 with observation chunks staged in LDS.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -77,13 +79,18 @@ __global__ __launch_bounds__(256) void k_cov_matrix(const double* __restrict__ x
     C[i * lda + j] = c;
 }
 
-// Unblocked Cholesky of the diagonal block [k0, k0 + nb) by one wave: lane r keeps row r in
-// registers; column j's entries below the pivot go through LDS for the rank-1 update.  info
-// records the first non-positive pivot (1-based); the factor then carries NaN.
-__global__ __launch_bounds__(64) void k_potrf_diag(double* __restrict__ A, int64_t m, int64_t lda, int64_t k0,
-                                                  int32_t* __restrict__ info)
+// One panel step of the Cholesky factorisation: every workgroup (one wave) factors the
+// diagonal block [k0, k0 + nb) itself, unblocked, from A (lane r keeps row r in registers;
+// column j goes through LDS for the rank-1 update), then solves its panel rows
+// i >= k0 + nb: L[i][k0 ..] = A[i][k0 ..] L_kk^-T.  A's diagonal block is only read, so the
+// redundant factorisations never race; workgroup 0 stores the factor in `dk` (32 x 32,
+// row-major) and the first non-positive pivot (1-based) in `info` (the factor then carries
+// NaN).
+__global__ __launch_bounds__(64) void k_potrf_trsm(double* __restrict__ A, int64_t m, int64_t lda, int64_t k0,
+                                                  double* __restrict__ dk, int32_t* __restrict__ info)
 {
     __shared__ double col[kNb];
+    __shared__ double L[kNb][kNb + 1];
     const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
     const int r = threadIdx.x;
     double row[kNb];
@@ -107,39 +114,33 @@ __global__ __launch_bounds__(64) void k_potrf_diag(double* __restrict__ A, int64
             __syncthreads();
         }
     }
-    if (r == 0 && bad && info && *info == 0) *info = bad;
-    if (r < nb) {
+    if (r < kNb) {
 #pragma unroll
-        for (int c = 0; c < kNb; ++c)
-            if (c <= r) A[(k0 + r) * lda + k0 + c] = row[c];
+        for (int c = 0; c < kNb; ++c) L[r][c] = c <= r ? row[c] : 0.0;
     }
-}
-
-// Panel rows i >= k0 + nb: L[i][k0 .. k0+nb) = A[i][...] L_kk^-T (one thread per row).
-__global__ __launch_bounds__(64) void k_trsm_panel(double* __restrict__ A, int64_t m, int64_t lda, int64_t k0)
-{
-    __shared__ double L[kNb][kNb + 1];
-    const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-        const int r = e / nb, c = e % nb;
-        L[r][c] = c <= r ? A[(k0 + r) * lda + k0 + c] : 0.0;
+    if (blockIdx.x == 0) {
+        if (r == 0 && bad && info && *info == 0) *info = bad;
+        if (r < kNb) {
+#pragma unroll
+            for (int c = 0; c < kNb; ++c) dk[r * kNb + c] = L[r][c];
+        }
     }
     __syncthreads();
-    const int64_t i = k0 + nb + static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    const int64_t i = k0 + nb + static_cast<int64_t>(blockIdx.x) * blockDim.x + r;
     if (i >= m) return;
-    double* row = A + i * lda + k0;
+    double* prow = A + i * lda + k0;
     double x[kNb];
 #pragma unroll
     for (int j = 0; j < kNb; ++j) {
         if (j < nb) {
-            double v = row[j];
+            double v = prow[j];
             for (int l = 0; l < j; ++l) v -= x[l] * L[j][l];
             x[j] = v / L[j][j];
         }
     }
 #pragma unroll
     for (int j = 0; j < kNb; ++j)
-        if (j < nb) row[j] = x[j];
+        if (j < nb) prow[j] = x[j];
 }
 
 // Trailing update A[i][j] -= sum_l L[i][l] L[j][l] over the panel columns [k0, k0 + nb), for
@@ -174,68 +175,77 @@ __global__ __launch_bounds__(256) void k_syrk_update(double* __restrict__ A, int
     }
 }
 
-// x = (L L^T)^-1 b by blocked forward and backward substitution in one workgroup.  Each
-// 32-row diagonal block is staged in LDS and solved by one wave (lane-parallel column
-// updates); the rest of the vector is then updated by all threads.
-__global__ __launch_bounds__(1024) void k_chol_solve(const double* __restrict__ L, int64_t m, int64_t lda,
-                                                    const double* __restrict__ b, double* __restrict__ x)
+// x = (L L^T)^-1 b by blocked substitution, one launch per 32-row block and direction.  In
+// every launch each workgroup stages the diagonal block in LDS and solves it with one wave
+// (the same small solve, redundantly), then updates its share of the remaining right-hand
+// side; workgroup 0 stores the block's solution.  A step reads only the block's right-hand
+// side and writes only the solution and the rows past the block, so workgroups never race.
+__device__ __forceinline__ void stage_diag(const double* __restrict__ dk, int nb, double (&D)[kNb][kNb + 1])
+{
+    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
+        const int r = e / nb, c = e % nb;
+        D[r][c] = c <= r ? dk[r * kNb + c] : 0.0;
+    }
+}
+
+// Forward step: z_k = L_kk^-1 r_k; r_i -= L_ik z_k for rows i >= k0 + nb.
+__global__ __launch_bounds__(256) void k_trsv_fwd(const double* __restrict__ L, const double* __restrict__ diag,
+                                                  int64_t m, int64_t lda, int64_t k0, double* __restrict__ r,
+                                                  double* __restrict__ z)
 {
     __shared__ double D[kNb][kNb + 1];
     __shared__ double xb[kNb];
     const int t = threadIdx.x;
-    for (int64_t i = t; i < m; i += blockDim.x) x[i] = b[i];
+    const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
+    stage_diag(diag + (k0 / kNb) * kNb * kNb, nb, D);
+    if (t < nb) xb[t] = r[k0 + t];
     __syncthreads();
-    // forward: L y = b
-    for (int64_t k0 = 0; k0 < m; k0 += kNb) {
-        const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
-        for (int e = t; e < nb * nb; e += blockDim.x) {
-            const int r = e / nb, c = e % nb;
-            D[r][c] = c <= r ? L[(k0 + r) * lda + k0 + c] : 0.0;
+    if (t < 64) {
+        for (int j = 0; j < nb; ++j) {
+            const double xj = xb[j] / D[j][j];
+            if (t > j && t < nb) xb[t] -= D[t][j] * xj;
+            if (t == j) xb[j] = xj;
+            __builtin_amdgcn_wave_barrier();
         }
-        if (t < nb) xb[t] = x[k0 + t];
-        __syncthreads();
-        if (t < 64) {
-            for (int j = 0; j < nb; ++j) {
-                const double xj = xb[j] / D[j][j];
-                if (t > j && t < nb) xb[t] -= D[t][j] * xj;
-                if (t == j) xb[j] = xj;
-                __builtin_amdgcn_wave_barrier();
-            }
-            if (t < nb) x[k0 + t] = xb[t];
-        }
-        __syncthreads();
-        for (int64_t i = k0 + nb + t; i < m; i += blockDim.x) {
-            double v = 0.0;
-            for (int l = 0; l < nb; ++l) v += L[i * lda + k0 + l] * xb[l];
-            x[i] -= v;
-        }
-        __syncthreads();
     }
-    // backward: L^T x = y, block rows from the end
-    for (int64_t k0 = ((m - 1) / kNb) * kNb; k0 >= 0; k0 -= kNb) {
-        const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
-        for (int e = t; e < nb * nb; e += blockDim.x) {
-            const int r = e / nb, c = e % nb;
-            D[r][c] = c <= r ? L[(k0 + r) * lda + k0 + c] : 0.0;
+    __syncthreads();
+    if (blockIdx.x == 0 && t < nb) z[k0 + t] = xb[t];
+    const int64_t i = k0 + nb + static_cast<int64_t>(blockIdx.x) * blockDim.x + t;
+    if (i < m) {
+        const double* row = L + i * lda + k0;
+        double v = 0.0;
+        for (int l = 0; l < nb; ++l) v += row[l] * xb[l];
+        r[i] -= v;
+    }
+}
+
+// Backward step: x_k = L_kk^-T z_k; z_i -= L_ki^T x_k for rows i < k0.
+__global__ __launch_bounds__(256) void k_trsv_bwd(const double* __restrict__ L, const double* __restrict__ diag,
+                                                  int64_t m, int64_t lda, int64_t k0, double* __restrict__ z,
+                                                  double* __restrict__ x)
+{
+    __shared__ double D[kNb][kNb + 1];
+    __shared__ double xb[kNb];
+    const int t = threadIdx.x;
+    const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
+    stage_diag(diag + (k0 / kNb) * kNb * kNb, nb, D);
+    if (t < nb) xb[t] = z[k0 + t];
+    __syncthreads();
+    if (t < 64) {
+        for (int j = nb - 1; j >= 0; --j) {
+            const double xj = xb[j] / D[j][j];
+            if (t < j) xb[t] -= D[j][t] * xj;
+            if (t == j) xb[j] = xj;
+            __builtin_amdgcn_wave_barrier();
         }
-        if (t < nb) xb[t] = x[k0 + t];
-        __syncthreads();
-        if (t < 64) {
-            for (int j = nb - 1; j >= 0; --j) {
-                const double xj = xb[j] / D[j][j];
-                if (t < j) xb[t] -= D[j][t] * xj;
-                if (t == j) xb[j] = xj;
-                __builtin_amdgcn_wave_barrier();
-            }
-            if (t < nb) x[k0 + t] = xb[t];
-        }
-        __syncthreads();
-        for (int64_t i = t; i < k0; i += blockDim.x) {
-            double v = 0.0;
-            for (int l = 0; l < nb; ++l) v += L[(k0 + l) * lda + i] * xb[l];
-            x[i] -= v;
-        }
-        __syncthreads();
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && t < nb) x[k0 + t] = xb[t];
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + t;
+    if (i < k0) {
+        double v = 0.0;
+        for (int l = 0; l < nb; ++l) v += L[(k0 + l) * lda + i] * xb[l];
+        z[i] -= v;
     }
 }
 
@@ -328,13 +338,14 @@ hipError_t launch_cov_matrix(const double* x, int64_t m, int dim, const KrigeMod
     return hipGetLastError();
 }
 
-hipError_t launch_cholesky(double* A, int64_t m, int64_t lda, int32_t* info, hipStream_t s)
+hipError_t launch_cholesky(double* A, int64_t m, int64_t lda, double* diag, int32_t* info, hipStream_t s)
 {
     for (int64_t k0 = 0; k0 < m; k0 += kNb) {
-        hipLaunchKernelGGL(k_potrf_diag, dim3(1), dim3(64), 0, s, A, m, lda, k0, info);
         const int64_t rest = m - k0 - kNb;
+        const unsigned blocks = static_cast<unsigned>(rest > 0 ? (rest + 63) / 64 : 1);
+        hipLaunchKernelGGL(k_potrf_trsm, dim3(blocks), dim3(64), 0, s, A, m, lda, k0, diag + (k0 / kNb) * kNb * kNb,
+                           info);
         if (rest <= 0) break;
-        hipLaunchKernelGGL(k_trsm_panel, dim3(static_cast<unsigned>((rest + 63) / 64)), dim3(64), 0, s, A, m, lda, k0);
         const int64_t tiles = (rest + 31) / 32;
         hipLaunchKernelGGL(k_syrk_update, dim3(static_cast<unsigned>(tiles), static_cast<unsigned>(tiles)), dim3(256),
                            0, s, A, m, lda, k0);
@@ -344,10 +355,23 @@ hipError_t launch_cholesky(double* A, int64_t m, int64_t lda, int32_t* info, hip
     return hipGetLastError();
 }
 
-hipError_t launch_chol_solve(const double* L, int64_t m, int64_t lda, const double* b, double* x, hipStream_t s)
+hipError_t launch_chol_solve(const double* L, const double* diag, int64_t m, int64_t lda, double* b, double* x,
+                             hipStream_t s)
 {
-    hipLaunchKernelGGL(k_chol_solve, dim3(1), dim3(1024), 0, s, L, m, lda, b, x);
-    return hipGetLastError();
+    // forward: right-hand side b (updated in place), solution z in x; backward: right-hand
+    // side z (x, updated in place), solution in b; then b -> x
+    for (int64_t k0 = 0; k0 < m; k0 += kNb) {
+        const int64_t below = m - k0 - kNb;
+        const unsigned blocks = static_cast<unsigned>(below > 0 ? (below + 255) / 256 : 1);
+        hipLaunchKernelGGL(k_trsv_fwd, dim3(blocks), dim3(256), 0, s, L, diag, m, lda, k0, b, x);
+    }
+    for (int64_t k0 = ((m - 1) / kNb) * kNb; k0 >= 0; k0 -= kNb) {
+        const unsigned blocks = static_cast<unsigned>(k0 > 0 ? (k0 + 255) / 256 : 1);
+        hipLaunchKernelGGL(k_trsv_bwd, dim3(blocks), dim3(256), 0, s, L, diag, m, lda, k0, x, b);
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(x, b, static_cast<size_t>(m) * sizeof(double), hipMemcpyDeviceToDevice, s);
 }
 
 hipError_t launch_residual(const float* d, const float* y, int64_t m, double* r, hipStream_t s)
