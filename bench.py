@@ -329,6 +329,9 @@ def adjoint_extra(grf, wl, torch, np, dev):
     gd = torch.randn(Cg, device=dev) / Cg
     df_ms, df_k = _timed(torch, grf, lambda: grf.field_grid(m, c["shape"], method="direct_f32"), 3, 1)
     db_ms, db_k = _timed(torch, grf, lambda: grf.field_backward_grid(m, c["shape"], gd), 3, 1)
+    # the same with the forward's Y handed back (dL/dsigma = sum g Y / sigma, no cosines)
+    yd = grf.field_grid(m, c["shape"], method="direct_f32")["y"]
+    ds_ms, ds_k = _timed(torch, grf, lambda: grf.field_backward_grid(m, c["shape"], gd, y_saved=yd), 3, 1)
     sf_ms, sf_k = _timed(torch, grf, lambda: grf.field_grid(m, c["shape"], method="sep_f16"), 10, 2)
     out["adjoint_grid3d_128"] = {
         "obs": {"fwd_ms": f_ms, "bwd_ms": b_ms, "bwd_over_fwd": b_ms / f_ms,
@@ -336,7 +339,11 @@ def adjoint_extra(grf, wl, torch, np, dev):
         "dense": {"fwd_direct_ms": df_ms, "fwd_sep_f16_ms": sf_ms, "bwd_ms": db_ms,
                   "bwd_over_fwd_direct": db_ms / df_ms,
                   "bwd_roofline": {"bound": "alu", "achieved": Cg * c["n_modes"] / (db_k * 1e-3), "peak": COS_PEAK,
-                                   "unit": "mode·cell/s", "frac": Cg * c["n_modes"] / (db_k * 1e-3) / COS_PEAK}}}
+                                   "unit": "mode·cell/s", "frac": Cg * c["n_modes"] / (db_k * 1e-3) / COS_PEAK},
+                  "bwd_saved_y_ms": ds_ms,
+                  "bwd_saved_y_roofline": {"bound": "alu", "achieved": Cg * c["n_modes"] / (ds_k * 1e-3),
+                                           "peak": COS_PEAK, "unit": "mode·cell/s",
+                                           "frac": Cg * c["n_modes"] / (ds_k * 1e-3) / COS_PEAK}}}
     return out
 
 

@@ -178,9 +178,10 @@ __global__ __launch_bounds__(256) void k_bwd_final(const float* __restrict__ sca
 // Dense adjoint on a structured grid from the per-axis revolution tables (FP64-reduced,
 // psi folded into the y table): theta_jc / 2 pi = Tx[i][j] + Ty[y][j] + Tz[z][j].
 // One lane per mode; the block walks a chunk of 16 x 16 (x, (y,z)) cell tiles.  Each lane
-// keeps its mode's 16 + 16 table entries of the tile in registers, and the per-cell
-// weights (g, g x, g y, g z) are shared through LDS (broadcast reads).  Cells outside the
-// grid get g = 0.
+// keeps its mode's 16 + 16 table entries of the tile in registers, and the per-cell weights
+// (g, g x) are shared through LDS (broadcast reads).  Along one tile row y and z are fixed,
+// so the row sums r = sum_x g sin and r_x = sum_x g x sin give s += r, u_x += r_x,
+// u_y += y r, u_z += z r: one sine and two FMAs per cell.  Cells outside the grid get g = 0.
 constexpr int kBT = 16;
 
 template <bool WANT_C>
@@ -189,7 +190,8 @@ __global__ __launch_bounds__(256) void k_bwd_grid_tab(const float* __restrict__ 
                                                      int nxt, int64_t ntiles, int64_t tiles_per_chunk,
                                                      const float* __restrict__ gy, float* __restrict__ partial)
 {
-    __shared__ float4 sw[kBT * kBT];
+    __shared__ float2 sw[kBT * kBT];
+    __shared__ float2 syz[kBT];
     const int t = threadIdx.x;
     const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + t;
     const int64_t jc = min(j, ldp - 1);
@@ -209,30 +211,37 @@ __global__ __launch_bounds__(256) void k_bwd_grid_tab(const float* __restrict__ 
         __syncthreads();  // previous tile's weights are no longer read
         {
             const int64_t xi = x0 + (t % kBT), q = q0 + (t / kBT);
-            float4 w = make_float4(0.f, 0.f, 0.f, 0.f);
+            float2 w = make_float2(0.f, 0.f);
             if (xi < geo.nx && q < nq) {
                 const float g = gy[q * geo.nx + xi];
                 const float x = static_cast<float>(geo.ox + (static_cast<double>(xi) + 0.5) * geo.hx);
-                const float y = static_cast<float>(geo.oy + (static_cast<double>(q % geo.ny) + 0.5) * geo.hy);
-                const float z = static_cast<float>(geo.oz + (static_cast<double>(q / geo.ny) + 0.5) * geo.hz);
-                w = make_float4(g, g * x, g * y, g * z);
+                w = make_float2(g, g * x);
             }
             sw[t] = w;
+            if (t < kBT) {
+                const int64_t qr = min(q0 + t, nq - 1);
+                syz[t] = make_float2(static_cast<float>(geo.oy + (static_cast<double>(qr % geo.ny) + 0.5) * geo.hy),
+                                     static_cast<float>(geo.oz + (static_cast<double>(qr / geo.ny) + 0.5) * geo.hz));
+            }
         }
         __syncthreads();
 #pragma unroll 4
         for (int b = 0; b < kBT; ++b) {
+            float rs = 0.f, rx = 0.f;
 #pragma unroll
             for (int a = 0; a < kBT; ++a) {
-                const float4 w = sw[b * kBT + a];
+                const float2 w = sw[b * kBT + a];
                 const float p = vx[a] + vq[b];
                 const float sn = __builtin_amdgcn_sinf(p);
-                s = fmaf(w.x, sn, s);
-                ux = fmaf(w.y, sn, ux);
-                uy = fmaf(w.z, sn, uy);
-                uz = fmaf(w.w, sn, uz);
+                rs = fmaf(w.x, sn, rs);
+                rx = fmaf(w.y, sn, rx);
                 if (WANT_C) cc = fmaf(w.x, __builtin_amdgcn_cosf(p), cc);
             }
+            const float2 yz = syz[b];
+            s += rs;
+            ux += rx;
+            uy = fmaf(yz.x, rs, uy);
+            uz = fmaf(yz.y, rs, uz);
         }
     }
     if (j < ldp) {
