@@ -305,6 +305,21 @@ int field_backward_grid(const grf_modes* modes, const grf_grid* grid, const floa
                         float* grad_ell, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * field_backward_grid_method -- the same with the method chosen:
+ *   GRF_DIRECT_F32   per mode and cell from FP32 revolution tables (one sine per mode-cell);
+ *   GRF_SEP_BF16_X3  separable form: the per-mode sums factor over the axes like the forward
+ *                    sum (eq. DiscreteFT with k.x split per axis), S_j = sum_{y,z}
+ *                    [sum_x g Ex] Ey Ez, the bracket a bf16 hi+lo matrix product (relative
+ *                    error ~2^-16) reduced with Ey Ez in FP32; needs n[0] <= 128
+ *                    (GRF_EUNSUPPORTED otherwise);
+ *   GRF_AUTO         the separable form when it applies (what field_backward_grid does).
+ * The workspace of field_backward_grid_ws_size fits every method.
+ */
+int field_backward_grid_method(const grf_modes* modes, const grf_grid* grid, int method, const float* grad_y,
+                               const float* y_saved, float* grad_phi, float* grad_k, float* grad_sigma,
+                               float* grad_ell, void* ws, size_t ws_bytes, void* stream);
+
+/*
  * Conditioning on observations by kriging the residuals (the paper lists conditioning on
  * data as future work, Sec. 6): with observations d_i at x_i (i < M) and a realisation Y,
  *   alpha = (C(X, X) + nugget sigma^2 I)^-1 (d - Y(X)),   Y_c(x) = Y(x) + sum_i alpha_i C(x - x_i),

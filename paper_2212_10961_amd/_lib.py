@@ -33,6 +33,7 @@ EXPORTS = [
     "krige_weights_ws_size", "krige_weights", "krige_apply_ws_size", "krige_apply_grid", "krige_apply_points",
     "eval_field_grid_f64", "eval_field_points_ws_size", "eval_field_points", "epilogue_apply",
     "field_backward_ws_size", "field_backward", "field_backward_grid_ws_size", "field_backward_grid",
+    "field_backward_grid_method",
     "grf_plan_create", "grf_plan_destroy", "eval_field_batch", "grf_plan_info",
     "grf_kernel_timer_enable", "grf_kernel_timer_read",
 ]
@@ -130,6 +131,8 @@ def load():
         "field_backward": ([P(GrfModes), vp, i64, vp, vp, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
         "field_backward_grid_ws_size": ([P(GrfModes), P(GrfGrid), P(sz)], ctypes.c_int),
         "field_backward_grid": ([P(GrfModes), P(GrfGrid), vp, vp, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
+        "field_backward_grid_method": ([P(GrfModes), P(GrfGrid), ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, sz, vp],
+                                       ctypes.c_int),
         "grf_plan_create": ([P(vp), ctypes.c_int, ctypes.c_int, ctypes.c_char_p], ctypes.c_int),
         "grf_plan_destroy": ([vp], ctypes.c_int),
         "eval_field_batch": ([vp, P(GrfBatchItem), i32, vp], ctypes.c_int),

@@ -267,6 +267,167 @@ void launch_bwd_main(const BwdArgs& a, int64_t chunk, const Geo& geo, bool want_
                            a.partial);
 }
 
+
+// ---- separable dense adjoint (grid path, x extent <= kBwdSepK) ---------------------------
+//
+// On a structured grid the per-mode sums factor like the forward sum: with rows q = (y, z)
+// and U_j[q] = sum_x g[q][x] Ex[x][j] (and its x-weighted twin U^x),
+//   S_j = sum_c g_c e^{i theta_jc} = sum_q U_j[q] W_j[q],  W_j[q] = Ey[y_q][j] Ez[z_q][j],
+// so s = Im S, c = Re S, u_x = Im sum_q U^x W, u_y = Im sum_q y_q U W, u_z = Im sum_q z_q U W.
+// The products U are a real matrix product (rows q, K = x, columns 4 j + (Re Ex, Im Ex,
+// x Re Ex, x Im Ex)) on bf16 matrix cores with hi+lo operands (three passes: hi hi, hi lo,
+// lo hi, ~2^-16 relative), and the reduction over q with W runs in the epilogue of every
+// 32 x 32 output tile, in FP32.
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+__device__ __forceinline__ void split_bf16(float v, uint16_t* hi, uint16_t* lo, int64_t e)
+{
+    const __bf16 h = static_cast<__bf16>(v);
+    const __bf16 l = static_cast<__bf16>(v - static_cast<float>(h));
+    hi[e] = __builtin_bit_cast(uint16_t, h);
+    lo[e] = __builtin_bit_cast(uint16_t, l);
+}
+
+// dL/dY rows (x fastest) as bf16 hi + lo, x padded to kBwdSepK and rows to qp with zeros.
+__global__ __launch_bounds__(256) void k_bwd_sep_ga(const float* __restrict__ g, int64_t q, int64_t nx, int64_t qp,
+                                                   uint16_t* __restrict__ hi, uint16_t* __restrict__ lo)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= qp * kBwdSepK) return;
+    const int64_t r = e / kBwdSepK, x = e % kBwdSepK;
+    split_bf16((r < q && x < nx) ? g[r * nx + x] : 0.f, hi, lo, e);
+}
+
+// x operand rows 4 j + (Re Ex, Im Ex, x Re Ex, x Im Ex) at x = ox + (i + 1/2) hx, phase
+// frac(a_j x) formed and reduced in FP64, then split into bf16 hi + lo; zero for j >= n and
+// i >= nx.
+__global__ __launch_bounds__(256) void k_bwd_sep_ex(const double* __restrict__ zx, double fs, double ox, double hx,
+                                                   int64_t n, int64_t ldp, int64_t nx, uint16_t* __restrict__ hi,
+                                                   uint16_t* __restrict__ lo)
+{
+    const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (e >= ldp * kBwdSepK) return;
+    const int64_t j = e / kBwdSepK, i = e % kBwdSepK;
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    if (j < n && i < nx) {
+        const double x = ox + (static_cast<double>(i) + 0.5) * hx;
+        const double t = zx[j] * fs * x;
+        double sn, cs;
+        sincospi(2.0 * (t - floor(t)), &sn, &cs);
+        v[0] = cs;
+        v[1] = sn;
+        v[2] = x * cs;
+        v[3] = x * sn;
+    }
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+        const __bf16 h = static_cast<__bf16>(static_cast<float>(v[c]));
+        const __bf16 l = static_cast<__bf16>(static_cast<float>(v[c] - static_cast<double>(static_cast<float>(h))));
+        const int64_t o = (4 * j + c) * kBwdSepK + i;
+        hi[o] = __builtin_bit_cast(uint16_t, h);
+        lo[o] = __builtin_bit_cast(uint16_t, l);
+    }
+}
+
+__device__ __forceinline__ float swap_pair(float v)
+{
+    // quad_perm [1, 0, 3, 2]: lanes 4m <-> 4m + 1, 4m + 2 <-> 4m + 3
+    return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0xB1, 0xF, 0xF, false));
+}
+
+struct BwdSepK {
+    const uint16_t* ga_hi;
+    const uint16_t* ga_lo;
+    const uint16_t* ex_hi;
+    const uint16_t* ex_lo;
+    const float2* ey;
+    const float2* ez;
+    int64_t ldp, qp, ny, nz;
+    float oy, hy, oz, hz;
+};
+
+// Block: 4 waves, 32 modes (8 per wave: columns 4 j + comp of the wave's 32); grid.y splits
+// the rows q.  Each wave keeps its x-operand fragments (all K) in registers and walks 32-row
+// tiles: 8 k-steps x 3 bf16 MFMAs, then the epilogue.  In the epilogue the lane of column
+// (j, comp) holds 16 rows of that component; it takes the partner component (Re <-> Im) from
+// the neighbouring lane and accumulates: comp 0 -> Re(U W), comp 1 -> Im(U W) with y and z
+// weights, comp 2 -> Im(U^x W).  The two half-waves (rows 4h ..) are added at the end.
+__global__ __launch_bounds__(256) void k_bwd_sep(BwdSepK p, float* __restrict__ partial)
+{
+    const int t = threadIdx.x, l = t & 63, h = l >> 5;
+    const int w = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int col = l & 31, c = col & 3;
+    const int64_t jb = static_cast<int64_t>(blockIdx.x) * 32 + w * 8;
+    const int64_t j = jb + (col >> 2);
+    constexpr int KS = kBwdSepK / 16;
+    uint4 bh[KS], bl[KS];
+    const int64_t brow = (4 * jb + col) * kBwdSepK + 8 * h;
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        bh[ks] = *reinterpret_cast<const uint4*>(p.ex_hi + brow + 16 * ks);
+        bl[ks] = *reinterpret_cast<const uint4*>(p.ex_lo + brow + 16 * ks);
+    }
+    float sIm = 0.f, sRe = 0.f, sY = 0.f, sZ = 0.f;
+    const int64_t ntile = p.qp / 32;
+    const int64_t per = (ntile + gridDim.y - 1) / gridDim.y;
+    const int64_t t0 = static_cast<int64_t>(blockIdx.y) * per, t1 = min(ntile, t0 + per);
+    for (int64_t tile = t0; tile < t1; ++tile) {
+        const int64_t q0 = tile * 32;
+        const int64_t arow = (q0 + col) * kBwdSepK + 8 * h;
+        f32x16 acc;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+#pragma unroll
+        for (int ks = 0; ks < KS; ++ks) {
+            const uint4 ah = *reinterpret_cast<const uint4*>(p.ga_hi + arow + 16 * ks);
+            const uint4 al = *reinterpret_cast<const uint4*>(p.ga_lo + arow + 16 * ks);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bh[ks]),
+                                                          acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bl[ks]),
+                                                          acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al), __builtin_bit_cast(bf16x8, bh[ks]),
+                                                          acc, 0, 0, 0);
+        }
+        // lane holds rows 8 (e / 4) + 4 h + e % 4 of the tile, column col
+        const int64_t y0 = q0 % p.ny, z0 = q0 / p.ny;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+            int64_t yi = y0 + 8 * (e >> 2) + 4 * h + (e & 3), zi = z0;
+            while (yi >= p.ny) {  // at most 32 / ny + 1 steps
+                yi -= p.ny;
+                ++zi;
+            }
+            zi = min(zi, p.nz - 1);  // padded rows (their U is zero)
+            const float2 wy = p.ey[yi * p.ldp + j], wz = p.ez[zi * p.ldp + j];
+            const float wr = wy.x * wz.x - wy.y * wz.y, wi = wy.x * wz.y + wy.y * wz.x;
+            const float own = acc[e], oth = swap_pair(own);
+            const float re = (c & 1) ? oth : own, im = (c & 1) ? own : oth;
+            const float ix = re * wi + im * wr;
+            sIm += ix;
+            sRe = fmaf(re, wr, fmaf(-im, wi, sRe));
+            sY = fmaf(p.oy + (static_cast<float>(yi) + 0.5f) * p.hy, ix, sY);
+            sZ = fmaf(p.oz + (static_cast<float>(zi) + 0.5f) * p.hz, ix, sZ);
+        }
+    }
+    sIm += __shfl_xor(sIm, 32);
+    sRe += __shfl_xor(sRe, 32);
+    sY += __shfl_xor(sY, 32);
+    sZ += __shfl_xor(sZ, 32);
+    if (h == 0) {
+        float* out = partial + static_cast<int64_t>(blockIdx.y) * 5 * p.ldp;
+        if (c == 1) {
+            out[j] = sIm;
+            out[2 * p.ldp + j] = sY;
+            out[3 * p.ldp + j] = sZ;
+        } else if (c == 0) {
+            out[4 * p.ldp + j] = sRe;
+        } else if (c == 2) {
+            out[p.ldp + j] = sIm;
+        }
+    }
+}
+
 }  // namespace
 
 int64_t bwd_chunks(int64_t P)
@@ -275,6 +436,16 @@ int64_t bwd_chunks(int64_t P)
     if (c < 1) c = 1;
     if (c > 256) c = 256;
     return c;
+}
+
+// Row chunks of the separable adjoint: about 2048 blocks, at most 256 (the partial sums'
+// workspace) and at most one per 32-row tile.
+int64_t bwd_sep_chunks(int64_t ldp, int64_t qp)
+{
+    int64_t c = 2048 / (ldp / 32);
+    c = c < 1 ? 1 : c;
+    c = c > 256 ? 256 : c;
+    return c < qp / 32 ? c : qp / 32;
 }
 
 hipError_t launch_backward(const BwdArgs& a, hipStream_t s)
@@ -293,8 +464,27 @@ hipError_t launch_backward(const BwdArgs& a, hipStream_t s)
         geo.hz = a.dim == 3 ? a.gh[2] : 0.0;
     }
     const bool want_c = a.gsigma != nullptr && a.ysaved == nullptr;
+    if (grid && a.sep) {
+        const BwdSep& b = *a.sep;
+        const int64_t ng = b.qp * kBwdSepK, ne = a.ldp * kBwdSepK;
+        hipLaunchKernelGGL(k_bwd_sep_ga, dim3(static_cast<unsigned>((ng + 255) / 256)), dim3(256), 0, s, a.gy, b.q,
+                           a.gn[0], b.qp, b.ga_hi, b.ga_lo);
+        hipLaunchKernelGGL(k_bwd_sep_ex, dim3(static_cast<unsigned>((ne + 255) / 256)), dim3(256), 0, s, b.zx, b.fsx,
+                           a.go[0], a.gh[0], a.n, a.ldp, a.gn[0], b.ex_hi, b.ex_lo);
+    }
     timer_mark(s, true);
-    if (grid && a.tx) {
+    if (grid && a.sep) {
+        const BwdSep& b = *a.sep;
+        BwdSepK k{b.ga_hi, b.ga_lo, b.ex_hi, b.ex_lo, b.ey, b.ez, a.ldp, b.qp, b.ny, b.nz,
+                  static_cast<float>(geo.oy), static_cast<float>(geo.hy), static_cast<float>(geo.oz),
+                  static_cast<float>(geo.hz)};
+        if (a.dim != 3) {
+            k.oz = 0.f;
+            k.hz = 0.f;
+        }
+        hipLaunchKernelGGL(k_bwd_sep, dim3(static_cast<unsigned>(a.ldp / 32), static_cast<unsigned>(b.chunks)),
+                           dim3(256), 0, s, k, a.partial);
+    } else if (grid && a.tx) {
         const int64_t nq = a.gn[1] * a.gn[2];
         const int nxt = static_cast<int>((a.gn[0] + kBT - 1) / kBT);
         const int64_t ntiles = static_cast<int64_t>(nxt) * ((nq + kBT - 1) / kBT);

@@ -856,14 +856,35 @@ int field_backward_ws_size(const grf_modes* modes, int64_t n_points, size_t* byt
     return GRF_OK;
 }
 
+// The separable dense adjoint applies to grids whose x extent fits one operand (K axis).
+static bool bwd_sep_ok(const grf_grid* g) { return g->n[0] >= 1 && g->n[0] <= kBwdSepK; }
+
+static int64_t bwd_sep_rows(const grf_grid* g) { return g->n[1] * g->n[2]; }
+
+static int64_t round_up32(int64_t v) { return (v + 31) / 32 * 32; }
+
+// Workspace of the separable path: mode parameters, partial sums, scalars, the operands and
+// the y and z tables.
+static size_t bwd_sep_ws(const grf_modes* m, const grf_grid* g)
+{
+    const int64_t ldp = padded_modes(m->n), qp = round_up32(bwd_sep_rows(g));
+    const int64_t nz = m->dim == 3 ? g->n[2] : 1;
+    const int64_t nch = bwd_sep_chunks(ldp, qp);
+    return rot_ws_bytes(m) + align256(sizeof(double) * 4 * ldp) + align256(sizeof(float) * 5 * ldp * nch) +
+           align256(sizeof(float) * bwd_scal_floats(m->n)) + 2 * align256(sizeof(uint16_t) * qp * kBwdSepK) +
+           2 * align256(sizeof(uint16_t) * 4 * ldp * kBwdSepK) + align256(sizeof(float2) * g->n[1] * ldp) +
+           align256(sizeof(float2) * nz * ldp);
+}
+
 static int backward_common(const char* fn, const grf_modes* modes, const double* xyz, const grf_grid* grid,
                            int64_t P, const float* grad_y, const float* y_saved, float* grad_phi,
                            float* grad_k, float* grad_sigma, float* grad_ell, void* ws, size_t ws_bytes,
-                           void* stream)
+                           void* stream, int method = GRF_AUTO)
 {
     size_t need = 0;
     int rc = grid ? field_backward_grid_ws_size(modes, grid, &need) : field_backward_ws_size(modes, P, &need);
     if (rc) return rc;
+    const bool sep = grid && method != GRF_DIRECT_F32 && bwd_sep_ok(grid);
     if (!grad_phi && !grad_k && !grad_sigma && !grad_ell) return fail(GRF_EINVAL, "%s: no output requested", fn);
     if (P > 0 && !grad_y) return fail(GRF_EINVAL, "%s: grad_y is NULL", fn);
     if (P > 0 && !xyz && !grid) return fail(GRF_EINVAL, "%s: xyz is NULL", fn);
@@ -874,13 +895,54 @@ static int backward_common(const char* fn, const grf_modes* modes, const double*
     void* kbuf = c.base;
     c.used += rot_ws_bytes(modes);
     double* params = c.take<double>(4 * ldp);
-    float* partial = c.take<float>(5 * ldp * bwd_chunks(P));
+    const int64_t qp = grid ? round_up32(bwd_sep_rows(grid)) : 0;
+    const int64_t nch = sep ? bwd_sep_chunks(ldp, qp) : bwd_chunks(P);
+    float* partial = c.take<float>(5 * ldp * nch);
     float* scal = c.take<float>(bwd_scal_floats(modes->n));
     grf_modes am;  // sums run on k itself; grad_ell maps back through the original table
     GRF_HIP(aligned_modes(modes, kbuf, s, &am));
     GRF_HIP(launch_mode_params(am.z, am.phi, am.dim, am.n, ldp, am.ell, params, s));
     GridWs tabs;
-    if (grid) {  // per-axis FP32 revolution tables of the direct method
+    BwdSep bs{};
+    if (sep) {
+        // bf16 hi + lo operands, then complex FP32 y and z tables (FP64 phases, psi in y)
+        const int64_t nz = modes->dim == 3 ? grid->n[2] : 1;
+        bs.ga_hi = c.take<uint16_t>(qp * kBwdSepK);
+        bs.ga_lo = c.take<uint16_t>(qp * kBwdSepK);
+        bs.ex_hi = c.take<uint16_t>(4 * ldp * kBwdSepK);
+        bs.ex_lo = c.take<uint16_t>(4 * ldp * kBwdSepK);
+        float2* ey = c.take<float2>(grid->n[1] * ldp);
+        float2* ez = c.take<float2>(nz * ldp);
+        AxisTableArgs d[2];
+        for (int k = 0; k < 2; ++k) {
+            const int a = k + 1;
+            AxisTableArgs& t = d[k];
+            t = AxisTableArgs{};
+            t.z = a < am.dim ? am.z : nullptr;  // 2-D: no z axis, one row of zero phase
+            t.phi = am.phi;
+            t.n = am.n;
+            t.ldp = ldp;
+            t.axis = a;
+            t.ell = a < am.dim ? am.ell[a] : 1.0;
+            t.freq_scale = 1.0 / (6.283185307179586476925286766559 * t.ell);
+            t.origin = grid->origin[a];
+            t.h = grid->h[a];
+            t.count = a == 1 ? grid->n[1] : nz;
+            t.with_psi = a == 1;
+            t.format = TF_CPLX_F32;
+            t.out = a == 1 ? static_cast<void*>(ey) : static_cast<void*>(ez);
+        }
+        GRF_HIP(launch_axis_tables(d, 2, s));
+        bs.ey = ey;
+        bs.ez = ez;
+        bs.zx = am.z;
+        bs.fsx = 1.0 / (6.283185307179586476925286766559 * am.ell[0]);
+        bs.q = bwd_sep_rows(grid);
+        bs.qp = qp;
+        bs.ny = grid->n[1];
+        bs.nz = nz;
+        bs.chunks = nch;
+    } else if (grid) {  // per-axis FP32 revolution tables of the direct method
         tabs = grid_ws(&am, grid, GRF_DIRECT_F32, c.base + c.used);
         GRF_HIP(build_tables(&am, grid, GRF_DIRECT_F32, tabs, s));
     }
@@ -911,7 +973,8 @@ static int backward_common(const char* fn, const grf_modes* modes, const double*
     a.gell = grad_ell;
     a.partial = partial;
     a.scal_partial = scal;
-    a.nchunks = bwd_chunks(P);
+    a.nchunks = nch;
+    a.sep = sep ? &bs : nullptr;
     GRF_HIP(launch_backward(a, s));
     return GRF_OK;
 }
@@ -935,6 +998,7 @@ int field_backward_grid_ws_size(const grf_modes* modes, const grf_grid* grid, si
     if ((rc = check_grid(grid, modes->dim, "field_backward_grid_ws_size"))) return rc;
     if ((rc = field_backward_ws_size(modes, grid->n[0] * grid->n[1] * grid->n[2], bytes))) return rc;
     *bytes += grid_ws(modes, grid, GRF_DIRECT_F32, nullptr).bytes;  // revolution tables
+    if (bwd_sep_ok(grid)) *bytes = std::max(*bytes, bwd_sep_ws(modes, grid));  // either method fits
     return GRF_OK;
 }
 
@@ -948,6 +1012,23 @@ int field_backward_grid(const grf_modes* modes, const grf_grid* grid, const floa
     if (modes->sigma <= 0.0 && grad_sigma) return fail(GRF_EINVAL, "field_backward_grid: sigma must be > 0 for grad_sigma");
     return backward_common("field_backward_grid", modes, nullptr, grid, grid->n[0] * grid->n[1] * grid->n[2],
                            grad_y, y_saved, grad_phi, grad_k, grad_sigma, grad_ell, ws, ws_bytes, stream);
+}
+
+int field_backward_grid_method(const grf_modes* modes, const grf_grid* grid, int method, const float* grad_y,
+                               const float* y_saved, float* grad_phi, float* grad_k, float* grad_sigma,
+                               float* grad_ell, void* ws, size_t ws_bytes, void* stream)
+{
+    const char* fn = "field_backward_grid_method";
+    int rc = check_modes(modes, fn);
+    if (rc) return rc;
+    if ((rc = check_grid(grid, modes->dim, fn))) return rc;
+    if (method != GRF_AUTO && method != GRF_DIRECT_F32 && method != GRF_SEP_BF16_X3)
+        return fail(GRF_EINVAL, "%s: method must be GRF_AUTO, GRF_DIRECT_F32 or GRF_SEP_BF16_X3", fn);
+    if (method == GRF_SEP_BF16_X3 && !bwd_sep_ok(grid))
+        return fail(GRF_EUNSUPPORTED, "%s: the separable adjoint needs an x extent of at most %d cells", fn, kBwdSepK);
+    if (modes->sigma <= 0.0 && grad_sigma) return fail(GRF_EINVAL, "%s: sigma must be > 0 for grad_sigma", fn);
+    return backward_common(fn, modes, nullptr, grid, grid->n[0] * grid->n[1] * grid->n[2], grad_y, y_saved, grad_phi,
+                           grad_k, grad_sigma, grad_ell, ws, ws_bytes, stream, method);
 }
 
 }  // extern "C"

@@ -279,6 +279,24 @@ hipError_t launch_axis_tables_batched(const AxisTableArgs* descs, const uint64_t
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, int stride, hipStream_t s);
 
 // ---------------------------------------------------------------- adjoint
+// Separable dense adjoint on a grid whose x extent is at most kBwdSepK: per mode j,
+// S_j = sum_c g_c e^{i theta_jc} = sum_q [sum_x g[q][x] Ex[x][j]] Ey[y_q][j] Ez[z_q][j] over the
+// rows q = (y, z), the bracket (and its x-weighted twin) as a bf16 hi+lo matrix product.
+constexpr int kBwdSepK = 128;
+struct BwdSep {
+    uint16_t* ga_hi;       // [qp][kBwdSepK] bf16 hi / lo of dL/dY rows (x padded with zeros)
+    uint16_t* ga_lo;
+    uint16_t* ex_hi;       // [4 ldp][kBwdSepK] rows 4 j + (Re Ex, Im Ex, x Re Ex, x Im Ex)
+    uint16_t* ex_lo;
+    const float2* ey;      // [ny][ldp] e^{2 pi i (a_y y + psi)}
+    const float2* ez;      // [nz][ldp] e^{2 pi i a_z z} (one row of 1 in 2-D)
+    const double* zx;      // x components of the (axis-aligned) wavevector table, [n]
+    double fsx;            // 1 / (2 pi ell_x)
+    int64_t q, qp, ny, nz; // rows ny nz, padded to 32, and their extents
+    int64_t chunks;        // row chunks (partial sums)
+};
+int64_t bwd_sep_chunks(int64_t ldp, int64_t qp);
+
 struct BwdArgs {
     const double* params;  // [ldp] double4 (a_x, a_y, a_z, psi) in revolutions
     int64_t n, ldp;
@@ -306,6 +324,7 @@ struct BwdArgs {
     float* partial;        // workspace [nchunks][5][ldp]
     float* scal_partial;   // workspace [nblocks]
     int64_t nchunks;
+    const BwdSep* sep;     // grid path: separable form (host struct), or nullptr
 };
 int64_t bwd_chunks(int64_t P);
 // floats of scalar-partial workspace: 4 per reduce block plus 1024 dot partials

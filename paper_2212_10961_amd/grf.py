@@ -486,8 +486,9 @@ def field_backward(modes: Modes, xyz: torch.Tensor, grad_y: torch.Tensor, y_save
 
 
 def field_backward_grid(modes: Modes, shape, grad_y: torch.Tensor, origin=None, h=None, y_saved=None,
-                        stream=None):
-    """Gradients for a dense dL/dY over every cell of a structured grid."""
+                        stream=None, method="auto"):
+    """Gradients for a dense dL/dY over every cell of a structured grid.  ``method``: "auto"
+    (the separable form when the x extent is at most 128), "direct_f32" or "sep_bf16_x3"."""
     lib = L.load()
     dev = modes.z.device
     m, g = modes.c(), _grid(shape, origin, h)
@@ -495,9 +496,10 @@ def field_backward_grid(modes: Modes, shape, grad_y: torch.Tensor, origin=None, 
     check(lib.field_backward_grid_ws_size(ctypes.byref(m), ctypes.byref(g), ctypes.byref(need)))
     ws = _workspace(need.value, dev)
     o = _bwd_outputs(modes, dev)
-    check(lib.field_backward_grid(ctypes.byref(m), ctypes.byref(g), _ptr(grad_y), _ptr(y_saved), _ptr(o["dphi"]),
-                                  _ptr(o["dk"]), _ptr(o["dsigma"]), _ptr(o["dell"]),
-                                  ctypes.c_void_p(ws.data_ptr()), ws.numel(), _stream(stream)))
+    check(lib.field_backward_grid_method(ctypes.byref(m), ctypes.byref(g), method_id(method), _ptr(grad_y),
+                                         _ptr(y_saved), _ptr(o["dphi"]), _ptr(o["dk"]), _ptr(o["dsigma"]),
+                                         _ptr(o["dell"]), ctypes.c_void_p(ws.data_ptr()), ws.numel(),
+                                         _stream(stream)))
     return o
 
 

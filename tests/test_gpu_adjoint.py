@@ -24,12 +24,12 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
-def _check(g, ref, tol=1e-4, tol_scalar=1e-4):
+def _check(g, ref, tol=1e-4, tol_scalar=1e-4, tol_sigma=None):
     rel = {"dphi": _rel(to_np(g["dphi"]), ref["dphi"]), "dk": _rel(to_np(g["dk"]), ref["dk"]),
            "dsigma": _rel(to_np(g["dsigma"]), [ref["dsigma"]]), "dell": _rel(to_np(g["dell"]), ref["dell"])}
     print("  rel-L2:", {k: f"{v:.2e}" for k, v in rel.items()}, flush=True)
     assert rel["dphi"] <= tol and rel["dk"] <= tol
-    assert rel["dsigma"] <= tol_scalar and rel["dell"] <= tol_scalar
+    assert rel["dsigma"] <= (tol_scalar if tol_sigma is None else tol_sigma) and rel["dell"] <= tol_scalar
     return rel
 
 
@@ -50,19 +50,73 @@ def test_backward_points(orc, grf, dim, cov, P, n, saved):
     _check(out, ref, tol=2e-5, tol_scalar=2e-4 if saved else 2e-5)
 
 
-def test_backward_grid_dense(orc, grf):
+# gradient bars: FP32 direct sums 2e-5; the separable form's bf16 hi+lo products carry
+# ~2^-17 relative error per term (the lo x lo product is dropped), bar 5e-5.  dL/dsigma is
+# (A / sigma) sum_j C_j, a sum over modes that cancels to a small value: with the separable
+# form's C_j (or a saved FP32 Y) its bar is 2e-4.
+BWD_TOL = {"direct_f32": 2e-5, "sep_bf16_x3": 5e-5}
+SIGMA_TOL = {"direct_f32": 2e-5, "sep_bf16_x3": 2e-4}
+
+
+@pytest.mark.parametrize("meth", ["direct_f32", "sep_bf16_x3"])
+@pytest.mark.parametrize("saved", [False, True])
+def test_backward_grid_dense(orc, grf, meth, saved):
     shape, ell, sigma = (20, 16, 8), (6.0, 6.0, 2.0), 1.0
-    print("case backward grid dense", flush=True)
+    print(f"case backward grid dense {meth} saved={saved}", flush=True)
     (zo, po), m = modes_pair(orc, grf, 3, wl.EXPONENTIAL, 130, 1004, sigma, ell)
     C = int(np.prod(shape))
     g = wl.upstream_grad(C, 1005).astype(np.float32)
-    x = orc.grid_centres(shape, origin=(1.0, 2.0, 3.0), h=(1.0, 0.5, 2.0))
+    geo = dict(origin=(1.0, 2.0, 3.0), h=(1.0, 0.5, 2.0))
+    x = orc.grid_centres(shape, **geo)
     ref = orc.grad_points(zo, po, sigma, ell, x, g.astype(np.float64))
-    out = grf.field_backward_grid(m, shape, torch.from_numpy(g).cuda(), origin=(1.0, 2.0, 3.0), h=(1.0, 0.5, 2.0))
-    _check(out, ref, tol=2e-5, tol_scalar=2e-5)
-    a = grf.field_backward_grid(m, shape, torch.from_numpy(g).cuda(), origin=(1.0, 2.0, 3.0), h=(1.0, 0.5, 2.0))
+    y = grf.field_grid(m, shape, method="direct_f32", **geo)["y"] if saved else None
+    gt = torch.from_numpy(g).cuda()
+    out = grf.field_backward_grid(m, shape, gt, y_saved=y, method=meth, **geo)
+    _check(out, ref, tol=BWD_TOL[meth], tol_scalar=BWD_TOL[meth], tol_sigma=2e-4 if saved else SIGMA_TOL[meth])
+    a = grf.field_backward_grid(m, shape, gt, y_saved=y, method=meth, **geo)
     for k in out:  # deterministic reduction order
         np.testing.assert_array_equal(to_np(out[k]), to_np(a[k]))
+
+
+@pytest.mark.parametrize("shape,ell,n", [((37, 50), (5.0, 7.0), 96), ((128, 33, 5), (9.0, 4.0, 2.0), 200),
+                                         ((1, 40, 3), (3.0, 3.0, 1.0), 64), ((16, 1, 1), (2.0, 2.0, 2.0), 33)])
+def test_backward_grid_separable_shapes(orc, grf, shape, ell, n):
+    """Separable adjoint on 2-D and 3-D grids: x extents 1 .. 128 (padded K), row counts that
+    are not multiples of 32 (padded rows), ny below and above one 32-row tile."""
+    dim = len(shape)
+    sigma = 0.9
+    print(f"case backward separable {shape} n={n}", flush=True)
+    (zo, po), m = modes_pair(orc, grf, dim, wl.GAUSSIAN, n, 1040 + n, sigma, ell)
+    C = int(np.prod(shape))
+    g = wl.upstream_grad(C, 1041).astype(np.float32)
+    geo = dict(origin=(0.5, -3.0, 2.0)[:dim], h=(1.0, 0.7, 1.5)[:dim])
+    x = orc.grid_centres(shape, **geo)
+    ref = orc.grad_points(zo, po, sigma, ell, x, g.astype(np.float64))
+    out = grf.field_backward_grid(m, shape, torch.from_numpy(g).cuda(), method="sep_bf16_x3", **geo)
+    _check(out, ref, tol=BWD_TOL["sep_bf16_x3"], tol_scalar=BWD_TOL["sep_bf16_x3"], tol_sigma=SIGMA_TOL["sep_bf16_x3"])
+
+
+def test_backward_grid_separable_rejects_wide_x(grf):
+    m = grf.modes_from_tables(*grf.make_modes(2, wl.GAUSSIAN, 8, 3), 1.0, (4.0, 4.0))
+    with pytest.raises(RuntimeError, match="x extent"):
+        grf.field_backward_grid(m, (129, 4), torch.zeros(129 * 4, device="cuda"), method="sep_bf16_x3")
+
+
+def test_backward_dense_workload_methods_agree(grf):
+    """The 128^3 dense workload: separable and direct adjoints agree (two different
+    algorithms for the same sums)."""
+    c = wl.WORKLOADS["adjoint_grid3d_128"]
+    print("case backward dense 128^3 sep vs direct", flush=True)
+    z, phi = grf.make_modes(3, c["cov"], c["n_modes"], c["seed"])
+    m = grf.modes_from_tables(z, phi, math.sqrt(c["sigma2"]), c["ell"])
+    C = int(np.prod(c["shape"]))
+    g = torch.from_numpy(wl.upstream_grad(C, 1050).astype(np.float32)).cuda()
+    a = grf.field_backward_grid(m, c["shape"], g, method="direct_f32")
+    b = grf.field_backward_grid(m, c["shape"], g, method="sep_bf16_x3")
+    for k in ("dphi", "dk", "dell", "dsigma"):
+        r = _rel(to_np(b[k]), to_np(a[k]))
+        print(f"  {k}: rel {r:.2e}", flush=True)
+        assert r <= (2e-4 if k == "dsigma" else 1e-4), (k, r)
 
 
 def test_backward_adjoint_workload_obs(orc, grf):
