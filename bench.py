@@ -328,22 +328,36 @@ def adjoint_extra(grf, wl, torch, np, dev):
     b_ms, b_k = _timed(torch, grf, lambda: grf.field_backward(m, xo, gy), 10, 2)
     gd = torch.randn(Cg, device=dev) / Cg
     df_ms, df_k = _timed(torch, grf, lambda: grf.field_grid(m, c["shape"], method="direct_f32"), 3, 1)
-    db_ms, db_k = _timed(torch, grf, lambda: grf.field_backward_grid(m, c["shape"], gd), 3, 1)
-    # the same with the forward's Y handed back (dL/dsigma = sum g Y / sigma, no cosines)
+    # dense adjoint, separable form (the default on this grid) and the direct per-cell form;
+    # the direct form also with the forward's Y handed back (dL/dsigma = sum g Y / sigma)
+    db_ms, db_k = _timed(torch, grf, lambda: grf.field_backward_grid(m, c["shape"], gd, method="sep_bf16_x3"), 10, 2)
+    dd_ms, dd_k = _timed(torch, grf, lambda: grf.field_backward_grid(m, c["shape"], gd, method="direct_f32"), 3, 1)
     yd = grf.field_grid(m, c["shape"], method="direct_f32")["y"]
-    ds_ms, ds_k = _timed(torch, grf, lambda: grf.field_backward_grid(m, c["shape"], gd, y_saved=yd), 3, 1)
+    ds_ms, ds_k = _timed(torch, grf, lambda: grf.field_backward_grid(m, c["shape"], gd, y_saved=yd,
+                                                                    method="direct_f32"), 3, 1)
+    # separable adjoint work: rows ny nz (y padded to 32) x K = 128 (x padded) x 4 ldp
+    # columns, three bf16 passes
+    ldp = (c["n_modes"] + 63) // 64 * 64
+    rows = ((c["shape"][1] + 31) // 32 * 32) * c["shape"][2]
+    sep_flop = 2.0 * rows * 128 * 4 * ldp * 3
     sf_ms, sf_k = _timed(torch, grf, lambda: grf.field_grid(m, c["shape"], method="sep_f16"), 10, 2)
     out["adjoint_grid3d_128"] = {
         "obs": {"fwd_ms": f_ms, "bwd_ms": b_ms, "bwd_over_fwd": b_ms / f_ms,
                 "bwd_mode_points_per_s": c["n_obs"] * c["n_modes"] / (b_k * 1e-3)},
-        "dense": {"fwd_direct_ms": df_ms, "fwd_sep_f16_ms": sf_ms, "bwd_ms": db_ms,
-                  "bwd_over_fwd_direct": db_ms / df_ms,
-                  "bwd_roofline": {"bound": "alu", "achieved": Cg * c["n_modes"] / (db_k * 1e-3), "peak": COS_PEAK,
-                                   "unit": "mode·cell/s", "frac": Cg * c["n_modes"] / (db_k * 1e-3) / COS_PEAK},
-                  "bwd_saved_y_ms": ds_ms,
-                  "bwd_saved_y_roofline": {"bound": "alu", "achieved": Cg * c["n_modes"] / (ds_k * 1e-3),
-                                           "peak": COS_PEAK, "unit": "mode·cell/s",
-                                           "frac": Cg * c["n_modes"] / (ds_k * 1e-3) / COS_PEAK}}}
+        "dense": {"fwd_direct_ms": df_ms, "fwd_sep_f16_ms": sf_ms,
+                  "bwd_sep_bf16_x3_ms": db_ms, "bwd_sep_over_fwd_sep": db_ms / sf_ms,
+                  "bwd_sep_mode_cells_per_s": Cg * c["n_modes"] / (db_k * 1e-3),
+                  "bwd_sep_roofline": {"bound": "mfma", "achieved": sep_flop / (db_k * 1e-3) / 1e12,
+                                       "peak": MFMA_F16_PEAK / 1e12, "unit": "TFLOP/s",
+                                       "frac": sep_flop / (db_k * 1e-3) / MFMA_F16_PEAK},
+                  "bwd_direct_ms": dd_ms, "bwd_direct_over_fwd_direct": dd_ms / df_ms,
+                  "bwd_direct_roofline": {"bound": "alu", "achieved": Cg * c["n_modes"] / (dd_k * 1e-3),
+                                          "peak": COS_PEAK, "unit": "mode·cell/s",
+                                          "frac": Cg * c["n_modes"] / (dd_k * 1e-3) / COS_PEAK},
+                  "bwd_direct_saved_y_ms": ds_ms,
+                  "bwd_direct_saved_y_roofline": {"bound": "alu", "achieved": Cg * c["n_modes"] / (ds_k * 1e-3),
+                                                  "peak": COS_PEAK, "unit": "mode·cell/s",
+                                                  "frac": Cg * c["n_modes"] / (ds_k * 1e-3) / COS_PEAK}}}
     return out
 
 

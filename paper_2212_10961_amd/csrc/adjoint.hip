@@ -289,14 +289,19 @@ __device__ __forceinline__ void split_bf16(float v, uint16_t* hi, uint16_t* lo, 
     lo[e] = __builtin_bit_cast(uint16_t, l);
 }
 
-// dL/dY rows (x fastest) as bf16 hi + lo, x padded to kBwdSepK and rows to qp with zeros.
-__global__ __launch_bounds__(256) void k_bwd_sep_ga(const float* __restrict__ g, int64_t q, int64_t nx, int64_t qp,
-                                                   uint16_t* __restrict__ hi, uint16_t* __restrict__ lo)
+// dL/dY rows as bf16 hi + lo: row r = z nyp + y (y padded to nyp, a multiple of 32, so that a
+// 32-row tile is one z-slice), x padded to kBwdSepK; padding is zero.  Stored fragment-major,
+// [r / 32][x / 16][r % 32][x % 16], so that one k-step of a 32-row tile (the A fragment of
+// every lane of a wave) is one contiguous KiB.
+__global__ __launch_bounds__(256) void k_bwd_sep_ga(const float* __restrict__ g, int64_t nx, int64_t ny, int64_t nyp,
+                                                   int64_t qp, uint16_t* __restrict__ hi, uint16_t* __restrict__ lo)
 {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= qp * kBwdSepK) return;
     const int64_t r = e / kBwdSepK, x = e % kBwdSepK;
-    split_bf16((r < q && x < nx) ? g[r * nx + x] : 0.f, hi, lo, e);
+    const int64_t z = r / nyp, y = r % nyp;
+    const int64_t d = (((r >> 5) * (kBwdSepK / 16) + (x >> 4)) * 32 + (r & 31)) * 16 + (x & 15);
+    split_bf16((y < ny && x < nx) ? g[(z * ny + y) * nx + x] : 0.f, hi, lo, d);
 }
 
 // x operand rows 4 j + (Re Ex, Im Ex, x Re Ex, x Im Ex) at x = ox + (i + 1/2) hx, phase
@@ -343,21 +348,25 @@ struct BwdSepK {
     const uint16_t* ex_lo;
     const float2* ey;
     const float2* ez;
-    int64_t ldp, qp, ny, nz;
+    int64_t ldp, qp, ny, nyp;
     float oy, hy, oz, hz;
 };
 
 // Block: 4 waves, 32 modes (8 per wave: columns 4 j + comp of the wave's 32); grid.y splits
-// the rows q.  Each wave keeps its x-operand fragments (all K) in registers and walks 32-row
-// tiles: 8 k-steps x 3 bf16 MFMAs, then the epilogue.  In the epilogue the lane of column
-// (j, comp) holds 16 rows of that component; it takes the partner component (Re <-> Im) from
-// the neighbouring lane and accumulates: comp 0 -> Re(U W), comp 1 -> Im(U W) with y and z
-// weights, comp 2 -> Im(U^x W).  The two half-waves (rows 4h ..) are added at the end.
+// the rows.  Each wave keeps its x-operand fragments (all K) in registers and walks 32-row
+// tiles (32 consecutive y of one z-slice): 8 k-steps x 3 bf16 MFMAs, then the epilogue.
+// There the lane of column (j, comp) holds 16 rows of that component and takes the partner
+// component (Re <-> Im) from the neighbouring lane; with e = Ey[y][j] it accumulates its
+// component of V = sum_y U e and of sum_y y U e as own e.x + partner (+-e.y) (the sign by
+// comp parity).  At the end of the tile the pair exchanges V once more and applies Ez:
+// comp 0 -> Re(V Ez), comp 1 -> Im(V Ez) (with y and z weights), comp 2 -> Im(V^x Ez).
+// The two half-waves (rows 4h ..) are added at the end.
 __global__ __launch_bounds__(256) void k_bwd_sep(BwdSepK p, float* __restrict__ partial)
 {
     const int t = threadIdx.x, l = t & 63, h = l >> 5;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
     const int col = l & 31, c = col & 3;
+    const float sgn = (c & 1) ? 1.f : -1.f;
     const int64_t jb = static_cast<int64_t>(blockIdx.x) * 32 + w * 8;
     const int64_t j = jb + (col >> 2);
     constexpr int KS = kBwdSepK / 16;
@@ -374,41 +383,50 @@ __global__ __launch_bounds__(256) void k_bwd_sep(BwdSepK p, float* __restrict__ 
     const int64_t t0 = static_cast<int64_t>(blockIdx.y) * per, t1 = min(ntile, t0 + per);
     for (int64_t tile = t0; tile < t1; ++tile) {
         const int64_t q0 = tile * 32;
-        const int64_t arow = (q0 + col) * kBwdSepK + 8 * h;
-        f32x16 acc;
+        const int64_t arow = tile * 32 * kBwdSepK + col * 16 + 8 * h;  // fragment-major rows
+        // three independent accumulator chains (hi hi, hi lo, lo hi) keep the MFMA pipe busy
+        f32x16 a0, a1, a2;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+        for (int e = 0; e < 16; ++e) a0[e] = a1[e] = a2[e] = 0.f;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const uint4 ah = *reinterpret_cast<const uint4*>(p.ga_hi + arow + 16 * ks);
-            const uint4 al = *reinterpret_cast<const uint4*>(p.ga_lo + arow + 16 * ks);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bh[ks]),
-                                                          acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bl[ks]),
-                                                          acc, 0, 0, 0);
-            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al), __builtin_bit_cast(bf16x8, bh[ks]),
-                                                          acc, 0, 0, 0);
+            const uint4 ah = *reinterpret_cast<const uint4*>(p.ga_hi + arow + 512 * ks);
+            const uint4 al = *reinterpret_cast<const uint4*>(p.ga_lo + arow + 512 * ks);
+            a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bh[ks]),
+                                                         a0, 0, 0, 0);
+            a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bl[ks]),
+                                                         a1, 0, 0, 0);
+            a2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al), __builtin_bit_cast(bf16x8, bh[ks]),
+                                                         a2, 0, 0, 0);
         }
-        // lane holds rows 8 (e / 4) + 4 h + e % 4 of the tile, column col
-        const int64_t y0 = q0 % p.ny, z0 = q0 / p.ny;
+        f32x16 acc;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) acc[e] = a0[e] + (a1[e] + a2[e]);
+        // lane holds rows y = y0 + 8 (e / 4) + 4 h + e % 4 of slice zi, column col
+        const int64_t zi = q0 / p.nyp, y0 = q0 - zi * p.nyp + 4 * h;
+        const float yb = p.oy + (static_cast<float>(y0) + 0.5f) * p.hy;
+        const float2* eyr = p.ey + y0 * p.ldp + j;  // the y table has nyp rows (padded rows: U = 0)
+        float vA = 0.f, vY = 0.f;
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-            int64_t yi = y0 + 8 * (e >> 2) + 4 * h + (e & 3), zi = z0;
-            while (yi >= p.ny) {  // at most 32 / ny + 1 steps
-                yi -= p.ny;
-                ++zi;
-            }
-            zi = min(zi, p.nz - 1);  // padded rows (their U is zero)
-            const float2 wy = p.ey[yi * p.ldp + j], wz = p.ez[zi * p.ldp + j];
-            const float wr = wy.x * wz.x - wy.y * wz.y, wi = wy.x * wz.y + wy.y * wz.x;
+            const int r = 8 * (e >> 2) + (e & 3);
+            const float2 ey = eyr[r * p.ldp];
             const float own = acc[e], oth = swap_pair(own);
-            const float re = (c & 1) ? oth : own, im = (c & 1) ? own : oth;
-            const float ix = re * wi + im * wr;
-            sIm += ix;
-            sRe = fmaf(re, wr, fmaf(-im, wi, sRe));
-            sY = fmaf(p.oy + (static_cast<float>(yi) + 0.5f) * p.hy, ix, sY);
-            sZ = fmaf(p.oz + (static_cast<float>(zi) + 0.5f) * p.hz, ix, sZ);
+            const float v = fmaf(own, ey.x, oth * (sgn * ey.y));
+            vA += v;
+            vY = fmaf(fmaf(static_cast<float>(r), p.hy, yb), v, vY);
         }
+        const float2 ez = p.ez[zi * p.ldp + j];
+        const float zc = p.oz + (static_cast<float>(zi) + 0.5f) * p.hz;
+        const float oA = swap_pair(vA), oY = swap_pair(vY);
+        // (re, im) of V and of sum y U e for this lane's pair
+        const float ra = (c & 1) ? oA : vA, ia = (c & 1) ? vA : oA;
+        const float ry = (c & 1) ? oY : vY, iy = (c & 1) ? vY : oY;
+        const float im = fmaf(ra, ez.y, ia * ez.x);
+        sIm += im;
+        sRe += fmaf(ra, ez.x, -ia * ez.y);
+        sY += fmaf(ry, ez.y, iy * ez.x);
+        sZ = fmaf(zc, im, sZ);
     }
     sIm += __shfl_xor(sIm, 32);
     sRe += __shfl_xor(sRe, 32);
@@ -467,15 +485,15 @@ hipError_t launch_backward(const BwdArgs& a, hipStream_t s)
     if (grid && a.sep) {
         const BwdSep& b = *a.sep;
         const int64_t ng = b.qp * kBwdSepK, ne = a.ldp * kBwdSepK;
-        hipLaunchKernelGGL(k_bwd_sep_ga, dim3(static_cast<unsigned>((ng + 255) / 256)), dim3(256), 0, s, a.gy, b.q,
-                           a.gn[0], b.qp, b.ga_hi, b.ga_lo);
+        hipLaunchKernelGGL(k_bwd_sep_ga, dim3(static_cast<unsigned>((ng + 255) / 256)), dim3(256), 0, s, a.gy, a.gn[0],
+                           b.ny, b.nyp, b.qp, b.ga_hi, b.ga_lo);
         hipLaunchKernelGGL(k_bwd_sep_ex, dim3(static_cast<unsigned>((ne + 255) / 256)), dim3(256), 0, s, b.zx, b.fsx,
                            a.go[0], a.gh[0], a.n, a.ldp, a.gn[0], b.ex_hi, b.ex_lo);
     }
     timer_mark(s, true);
     if (grid && a.sep) {
         const BwdSep& b = *a.sep;
-        BwdSepK k{b.ga_hi, b.ga_lo, b.ex_hi, b.ex_lo, b.ey, b.ez, a.ldp, b.qp, b.ny, b.nz,
+        BwdSepK k{b.ga_hi, b.ga_lo, b.ex_hi, b.ex_lo, b.ey, b.ez, a.ldp, b.qp, b.ny, b.nyp,
                   static_cast<float>(geo.oy), static_cast<float>(geo.hy), static_cast<float>(geo.oz),
                   static_cast<float>(geo.hz)};
         if (a.dim != 3) {

@@ -859,20 +859,21 @@ int field_backward_ws_size(const grf_modes* modes, int64_t n_points, size_t* byt
 // The separable dense adjoint applies to grids whose x extent fits one operand (K axis).
 static bool bwd_sep_ok(const grf_grid* g) { return g->n[0] >= 1 && g->n[0] <= kBwdSepK; }
 
-static int64_t bwd_sep_rows(const grf_grid* g) { return g->n[1] * g->n[2]; }
-
 static int64_t round_up32(int64_t v) { return (v + 31) / 32 * 32; }
+
+// Rows of the separable adjoint's operand: y padded to a multiple of 32 per z-slice.
+static int64_t bwd_sep_rows(const grf_grid* g) { return round_up32(g->n[1]) * g->n[2]; }
 
 // Workspace of the separable path: mode parameters, partial sums, scalars, the operands and
 // the y and z tables.
 static size_t bwd_sep_ws(const grf_modes* m, const grf_grid* g)
 {
-    const int64_t ldp = padded_modes(m->n), qp = round_up32(bwd_sep_rows(g));
+    const int64_t ldp = padded_modes(m->n), qp = bwd_sep_rows(g);
     const int64_t nz = m->dim == 3 ? g->n[2] : 1;
     const int64_t nch = bwd_sep_chunks(ldp, qp);
     return rot_ws_bytes(m) + align256(sizeof(double) * 4 * ldp) + align256(sizeof(float) * 5 * ldp * nch) +
            align256(sizeof(float) * bwd_scal_floats(m->n)) + 2 * align256(sizeof(uint16_t) * qp * kBwdSepK) +
-           2 * align256(sizeof(uint16_t) * 4 * ldp * kBwdSepK) + align256(sizeof(float2) * g->n[1] * ldp) +
+           2 * align256(sizeof(uint16_t) * 4 * ldp * kBwdSepK) + align256(sizeof(float2) * round_up32(g->n[1]) * ldp) +
            align256(sizeof(float2) * nz * ldp);
 }
 
@@ -895,7 +896,7 @@ static int backward_common(const char* fn, const grf_modes* modes, const double*
     void* kbuf = c.base;
     c.used += rot_ws_bytes(modes);
     double* params = c.take<double>(4 * ldp);
-    const int64_t qp = grid ? round_up32(bwd_sep_rows(grid)) : 0;
+    const int64_t qp = grid ? bwd_sep_rows(grid) : 0;
     const int64_t nch = sep ? bwd_sep_chunks(ldp, qp) : bwd_chunks(P);
     float* partial = c.take<float>(5 * ldp * nch);
     float* scal = c.take<float>(bwd_scal_floats(modes->n));
@@ -911,7 +912,7 @@ static int backward_common(const char* fn, const grf_modes* modes, const double*
         bs.ga_lo = c.take<uint16_t>(qp * kBwdSepK);
         bs.ex_hi = c.take<uint16_t>(4 * ldp * kBwdSepK);
         bs.ex_lo = c.take<uint16_t>(4 * ldp * kBwdSepK);
-        float2* ey = c.take<float2>(grid->n[1] * ldp);
+        float2* ey = c.take<float2>(round_up32(grid->n[1]) * ldp);
         float2* ez = c.take<float2>(nz * ldp);
         AxisTableArgs d[2];
         for (int k = 0; k < 2; ++k) {
@@ -927,7 +928,7 @@ static int backward_common(const char* fn, const grf_modes* modes, const double*
             t.freq_scale = 1.0 / (6.283185307179586476925286766559 * t.ell);
             t.origin = grid->origin[a];
             t.h = grid->h[a];
-            t.count = a == 1 ? grid->n[1] : nz;
+            t.count = a == 1 ? round_up32(grid->n[1]) : nz;  // y rows up to the padded extent
             t.with_psi = a == 1;
             t.format = TF_CPLX_F32;
             t.out = a == 1 ? static_cast<void*>(ey) : static_cast<void*>(ez);
@@ -937,10 +938,10 @@ static int backward_common(const char* fn, const grf_modes* modes, const double*
         bs.ez = ez;
         bs.zx = am.z;
         bs.fsx = 1.0 / (6.283185307179586476925286766559 * am.ell[0]);
-        bs.q = bwd_sep_rows(grid);
-        bs.qp = qp;
         bs.ny = grid->n[1];
+        bs.nyp = round_up32(grid->n[1]);
         bs.nz = nz;
+        bs.qp = qp;
         bs.chunks = nch;
     } else if (grid) {  // per-axis FP32 revolution tables of the direct method
         tabs = grid_ws(&am, grid, GRF_DIRECT_F32, c.base + c.used);

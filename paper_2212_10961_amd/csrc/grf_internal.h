@@ -284,15 +284,16 @@ hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, i
 // rows q = (y, z), the bracket (and its x-weighted twin) as a bf16 hi+lo matrix product.
 constexpr int kBwdSepK = 128;
 struct BwdSep {
-    uint16_t* ga_hi;       // [qp][kBwdSepK] bf16 hi / lo of dL/dY rows (x padded with zeros)
+    uint16_t* ga_hi;       // qp x kBwdSepK bf16 hi / lo of dL/dY rows z nyp + y (fragment-major)
     uint16_t* ga_lo;
     uint16_t* ex_hi;       // [4 ldp][kBwdSepK] rows 4 j + (Re Ex, Im Ex, x Re Ex, x Im Ex)
     uint16_t* ex_lo;
-    const float2* ey;      // [ny][ldp] e^{2 pi i (a_y y + psi)}
+    const float2* ey;      // [nyp][ldp] e^{2 pi i (a_y y + psi)} (rows past ny: finite, unused)
     const float2* ez;      // [nz][ldp] e^{2 pi i a_z z} (one row of 1 in 2-D)
     const double* zx;      // x components of the (axis-aligned) wavevector table, [n]
     double fsx;            // 1 / (2 pi ell_x)
-    int64_t q, qp, ny, nz; // rows ny nz, padded to 32, and their extents
+    int64_t ny, nyp, nz;   // y extent, padded to a multiple of 32, z extent (1 in 2-D)
+    int64_t qp;            // rows nyp nz
     int64_t chunks;        // row chunks (partial sums)
 };
 int64_t bwd_sep_chunks(int64_t ldp, int64_t qp);
