@@ -384,24 +384,21 @@ __global__ __launch_bounds__(256) void k_bwd_sep(BwdSepK p, float* __restrict__ 
     for (int64_t tile = t0; tile < t1; ++tile) {
         const int64_t q0 = tile * 32;
         const int64_t arow = tile * 32 * kBwdSepK + col * 16 + 8 * h;  // fragment-major rows
-        // three independent accumulator chains (hi hi, hi lo, lo hi) keep the MFMA pipe busy
-        f32x16 a0, a1, a2;
+        // one accumulator: 128 VGPRs, four waves per SIMD to cover the loads and the epilogue
+        f32x16 acc;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) a0[e] = a1[e] = a2[e] = 0.f;
+        for (int e = 0; e < 16; ++e) acc[e] = 0.f;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
             const uint4 ah = *reinterpret_cast<const uint4*>(p.ga_hi + arow + 512 * ks);
             const uint4 al = *reinterpret_cast<const uint4*>(p.ga_lo + arow + 512 * ks);
-            a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bh[ks]),
-                                                         a0, 0, 0, 0);
-            a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bl[ks]),
-                                                         a1, 0, 0, 0);
-            a2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al), __builtin_bit_cast(bf16x8, bh[ks]),
-                                                         a2, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bh[ks]),
+                                                          acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bl[ks]),
+                                                          acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, al), __builtin_bit_cast(bf16x8, bh[ks]),
+                                                          acc, 0, 0, 0);
         }
-        f32x16 acc;
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[e] = a0[e] + (a1[e] + a2[e]);
         // lane holds rows y = y0 + 8 (e / 4) + 4 h + e % 4 of slice zi, column col
         const int64_t zi = q0 / p.nyp, y0 = q0 - zi * p.nyp + 4 * h;
         const float yb = p.oy + (static_cast<float>(y0) + 0.5f) * p.hy;
