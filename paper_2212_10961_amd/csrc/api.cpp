@@ -291,6 +291,31 @@ namespace grf {
 
 // Tables and sum of one grid evaluation with a prepared epilogue; the caller has validated
 // the modes, grid, method (resolved), tile and outputs, and `ws` holds grid_ws(...) bytes.
+// Arguments of the separable kernel for one field whose tables are laid out as `w`.
+static SepArgs sep_args(const grf_modes* modes, const grf_grid* grid, int method, int tile, const Epi& e, float* y,
+                        float* k, uint8_t* ind, const GridWs& w)
+{
+    SepArgs a{};
+    a.method = method;
+    a.n = modes->n;
+    a.ldp = padded_modes(modes->n);
+    a.nx = grid->n[0];
+    a.ny = grid->n[1];
+    a.nz = grid->n[2];
+    a.px = w.t[0];
+    a.px_lo = w.tlo[0];
+    a.qy = w.t[1];
+    a.qy_lo = w.tlo[1];
+    a.ez = modes->dim == 3 ? static_cast<const float2*>(w.t[2]) : nullptr;
+    a.amp = static_cast<float>(modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n)));
+    a.epi = e;
+    a.y = y;
+    a.k = k;
+    a.ind = ind;
+    a.tile = tile;  // -1: size-based default
+    return a;
+}
+
 static int grid_launch(const grf_modes* modes, const grf_grid* grid, int method, int tile, const Epi& e, float* y,
                        float* k, uint8_t* ind, void* ws, hipStream_t s)
 {
@@ -310,25 +335,7 @@ static int grid_launch(const grf_modes* modes, const grf_grid* grid, int method,
                                        static_cast<const double*>(w.t[2]), modes->w, modes->n, ldp, grid->n, amp64, e,
                                        0.0, y, k, ind, nullptr, nullptr, s));
     } else {
-        SepArgs a{};
-        a.method = method;
-        a.n = modes->n;
-        a.ldp = ldp;
-        a.nx = grid->n[0];
-        a.ny = grid->n[1];
-        a.nz = grid->n[2];
-        a.px = w.t[0];
-        a.px_lo = w.tlo[0];
-        a.qy = w.t[1];
-        a.qy_lo = w.tlo[1];
-        a.ez = modes->dim == 3 ? static_cast<const float2*>(w.t[2]) : nullptr;
-        a.amp = amp;
-        a.epi = e;
-        a.y = y;
-        a.k = k;
-        a.ind = ind;
-        a.tile = tile;  // -1: size-based default
-        GRF_HIP(launch_sep(a, s));
+        GRF_HIP(launch_sep(sep_args(modes, grid, method, tile, e, y, k, ind, w), s));
     }
     return GRF_OK;
 }
@@ -415,7 +422,9 @@ static size_t pluri_grid_ws(const grf_modes* m1, const grf_modes* m2, const grf_
                             bool own_y2)
 {
     const int64_t C = g->n[0] * g->n[1] * g->n[2];
-    const size_t t = std::max(grid_ws(m1, g, method, nullptr).bytes, grid_ws(m2, g, method, nullptr).bytes);
+    // separable forms: both fields' tables at once (one table launch, one contraction launch)
+    const size_t b1 = grid_ws(m1, g, method, nullptr).bytes, b2 = grid_ws(m2, g, method, nullptr).bytes;
+    const size_t t = is_sep(method) ? b1 + b2 : std::max(b1, b2);
     const size_t f = align256(sizeof(float) * size_t(C));
     return align256(kRuleBytes) + rot_ws_bytes(m1) + rot_ws_bytes(m2) + (own_y1 ? f : 0) + (own_y2 ? f : 0) + t;
 }
@@ -465,8 +474,21 @@ int eval_pluri_grid(const grf_modes* m1, const grf_modes* m2, const grf_grid* gr
     GRF_HIP(aligned_modes(m1, k1, s, &a1));
     GRF_HIP(aligned_modes(m2, k2, s, &a2));
     GRF_HIP(launch_rule_tables(*rule, rt, s));
-    if ((rc = grid_launch(&a1, grid, method, -1, Epi{}, f1, nullptr, nullptr, tabs, s))) return rc;
-    if ((rc = grid_launch(&a2, grid, method, -1, Epi{}, f2, nullptr, nullptr, tabs, s))) return rc;
+    if (is_sep(method)) {
+        // both fields: one launch of the six (2-D: four) tables, one of the contraction
+        const GridWs w1 = grid_ws(&a1, grid, method, tabs);
+        const GridWs w2 = grid_ws(&a2, grid, method, static_cast<char*>(tabs) + w1.bytes);
+        AxisTableArgs d[6];
+        const int nd1 = grid_table_descs(&a1, grid, method, w1, d);
+        const int nd2 = grid_table_descs(&a2, grid, method, w2, d + nd1);
+        GRF_HIP(launch_axis_tables(d, nd1 + nd2, s));
+        TimedScope timed(s);
+        const SepArgs s2 = sep_args(&a2, grid, method, -1, Epi{}, f2, nullptr, nullptr, w2);
+        GRF_HIP(launch_sep_pair(sep_args(&a1, grid, method, -1, Epi{}, f1, nullptr, nullptr, w1), &s2, s));
+    } else {
+        if ((rc = grid_launch(&a1, grid, method, -1, Epi{}, f1, nullptr, nullptr, tabs, s))) return rc;
+        if ((rc = grid_launch(&a2, grid, method, -1, Epi{}, f2, nullptr, nullptr, tabs, s))) return rc;
+    }
     GRF_HIP(launch_pluri_epilogue(f1, f2, C, make_pluri(rule, rt), facies, value, s));
     return GRF_OK;
 }

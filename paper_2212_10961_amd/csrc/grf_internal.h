@@ -140,7 +140,7 @@ struct AxisTableArgs {
     const double* w;  // per-mode weights folded into complex entries (exp(i 2 pi f) * w_j), or nullptr
 };
 hipError_t launch_axis_table(const AxisTableArgs& a, hipStream_t s);
-hipError_t launch_axis_tables(const AxisTableArgs* d, int nd, hipStream_t s);  // nd <= 3, one launch
+hipError_t launch_axis_tables(const AxisTableArgs* d, int nd, hipStream_t s);  // nd <= 6, one launch
 int64_t axis_table_blocks(const AxisTableArgs& a);  // 256-thread work blocks one table needs
 
 // Table layout of eval_field_grid for a resolved method (base == nullptr: measure only),
@@ -207,6 +207,9 @@ struct SepArgs {
     int tile;              // < 0: size-based default; else tile selector (see sep.hip)
 };
 hipError_t launch_sep(const SepArgs& a, hipStream_t s);
+// Two fields on the same grid (same method, sizes and ldp; the epilogue parameters of `a`
+// apply to both) in one launch; b may be nullptr.
+hipError_t launch_sep_pair(const SepArgs& a, const SepArgs* b, hipStream_t s);
 int sep_tile_count();                // number of tile selectors
 void sep_tile_shape(int tile, int* bm, int* bn);
 int sep_tile_slices(int tile, int method, bool d3);  // z-slices per block

@@ -98,7 +98,8 @@ struct SepShape {
 // WM x WN waves; each wave owns TM x TN MFMA tiles of 32x32 (rows y, cols x).
 // `smem` must hold SepShape<...>::LDS_WORDS words.  Called by whole blocks.
 template <int WM, int WN, int TM, int TN, bool BF, bool X3, bool D3>
-__device__ __forceinline__ void sep_tile_reg(const SepArgs& a, int64_t tx, int64_t ty, int64_t z0, uint4* smem)
+__device__ __forceinline__ void sep_tile_reg(const SepArgs& a, const Epi& epi, int64_t tx, int64_t ty, int64_t z0,
+                                             uint4* smem)
 {
     using S = SepShape<WM, WN, TM, TN, X3>;
     constexpr int NT = S::NT, BM = S::BM, BN = S::BN, NB = S::NB, STAGE_W = S::STAGE_W, NBUF = S::NBUF;
@@ -297,7 +298,7 @@ __device__ __forceinline__ void sep_tile_reg(const SepArgs& a, int64_t tx, int64
                 const int64_t y = y0 + (wm * TM + i) * 32 + 8 * (e >> 2) + 4 * (l >> 5) + (e & 3);
                 if (x < a.nx && y < a.ny) {
                     const int64_t c = plane + y * a.nx + x;
-                    epi_store(c, a.amp * acc[i][j][e], a.epi, a.y, a.k, a.ind);
+                    epi_store(c, a.amp * acc[i][j][e], epi, a.y, a.k, a.ind);
                 }
             }
         }
@@ -351,7 +352,7 @@ constexpr bool use_dl()
 // staging.  `lds0` and `lds1` each hold DlShape<..., D3 ? ZS : 0>::STAGE_B bytes.  Called by
 // whole blocks.
 template <int WM, int WN, int TM, int TN, int ZS, bool BF, bool X3, bool D3>
-__device__ __forceinline__ void sep_tile_dl(const SepArgs& a, int64_t tx, int64_t ty, int64_t zb, uint4* lds0,
+__device__ __forceinline__ void sep_tile_dl(const SepArgs& a, const Epi& epi, int64_t tx, int64_t ty, int64_t zb, uint4* lds0,
                                             uint4* lds1)
 {
     using S = DlShape<WM, WN, TM, TN, X3, D3 ? ZS : 0>;
@@ -605,7 +606,7 @@ __device__ __forceinline__ void sep_tile_dl(const SepArgs& a, int64_t tx, int64_
                     if (x < a.nx && y < a.ny) {
                         const int64_t c = plane + y * a.nx + x;
                         const float yv = a.amp * acc[zs][i][j][e];
-                        epi_store(c, yv, a.epi, a.y, a.k, a.ind);
+                        epi_store(c, yv, epi, a.y, a.k, a.ind);
                     }
                 }
             }
@@ -621,19 +622,37 @@ constexpr int slices_per_block()
 }
 
 template <int WM, int WN, int TM, int TN, int ZS, bool BF, bool X3, bool D3>
-__global__ __launch_bounds__(WM* WN * 64) void k_sep(SepArgs a, int tiles_x, int tiles_y)
+// Blocks [0, per_field) evaluate field `a`, blocks [per_field, 2 per_field) field `b` (two
+// fields on one grid in one launch; `b` is unused when the grid covers one field).
+__global__ __launch_bounds__(WM* WN * 64) void k_sep(SepArgs fa, SepArgs fb, int tiles_x, int tiles_y, int per_field)
 {
-    const int64_t bid = blockIdx.x;
+    // The field's arguments as a local copy with the second field's pointers swapped in
+    // (uniform selects); the shared epilogue parameters are read from `fa` directly, so the
+    // copy is never indexed and stays in scalar registers.
+    const bool second = static_cast<int>(blockIdx.x) >= per_field;
+    SepArgs a = fa;
+    if (second) {
+        a.px = fb.px;
+        a.px_lo = fb.px_lo;
+        a.qy = fb.qy;
+        a.qy_lo = fb.qy_lo;
+        a.ez = fb.ez;
+        a.amp = fb.amp;
+        a.y = fb.y;
+        a.k = fb.k;
+        a.ind = fb.ind;
+    }
+    const int64_t bid = second ? blockIdx.x - per_field : blockIdx.x;
     const int64_t rest = bid / tiles_x;
     if constexpr (use_dl<WM, WN, TM, TN, ZS, BF, X3, D3>()) {
         constexpr int Q = DlShape<WM, WN, TM, TN, X3, D3 ? ZS : 0>::STAGE_B / 16;
         __shared__ uint4 lds0[Q];
         __shared__ uint4 lds1[Q];
         sep_tile_dl<WM, WN, TM, TN, slices_per_block<WM, WN, TM, TN, ZS, BF, X3, D3>(), BF, X3, D3>(
-            a, bid % tiles_x, rest % tiles_y, rest / tiles_y, lds0, lds1);
+            a, fa.epi, bid % tiles_x, rest % tiles_y, rest / tiles_y, lds0, lds1);
     } else {
         __shared__ uint4 smem[SepShape<WM, WN, TM, TN, X3>::LDS_WORDS / 4];
-        sep_tile_reg<WM, WN, TM, TN, BF, X3, D3>(a, bid % tiles_x, rest % tiles_y, rest / tiles_y, smem);
+        sep_tile_reg<WM, WN, TM, TN, BF, X3, D3>(a, fa.epi, bid % tiles_x, rest % tiles_y, rest / tiles_y, smem);
     }
 }
 
@@ -877,16 +896,16 @@ __global__ __launch_bounds__(256) void k_sep_batch(const SepBatchItem* __restric
             else sep_tile_gen<1, 1, BF>(b.a, b.g, local % b.tiles_x, rest, lds0, lds1);
         } else if constexpr (DL) {
             if (b.variant == 0)
-                sep_tile_dl<2, 2, 2, 2, 1, BF, X3, D3>(b.a, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0,
+                sep_tile_dl<2, 2, 2, 2, 1, BF, X3, D3>(b.a, b.a.epi, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0,
                                                        lds1);
             else
-                sep_tile_dl<2, 2, 1, 1, 1, BF, X3, D3>(b.a, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0,
+                sep_tile_dl<2, 2, 1, 1, 1, BF, X3, D3>(b.a, b.a.epi, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0,
                                                        lds1);
         } else {
             if (b.variant == 0)
-                sep_tile_reg<2, 2, 2, 2, BF, X3, D3>(b.a, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0);
+                sep_tile_reg<2, 2, 2, 2, BF, X3, D3>(b.a, b.a.epi, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0);
             else
-                sep_tile_reg<2, 2, 1, 1, BF, X3, D3>(b.a, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0);
+                sep_tile_reg<2, 2, 1, 1, BF, X3, D3>(b.a, b.a.epi, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0);
         }
     }
 }
@@ -921,33 +940,33 @@ constexpr TileCfg kTiles[] = {{256, 256}, {128, 128}, {64, 64},  {128, 256}, {12
                               {128, 128}, {128, 256}, {256, 128}, {256, 128}, {256, 256}};
 
 template <int WM, int WN, int TM, int TN, int ZS, bool BF, bool X3, bool D3>
-hipError_t launch_k(const SepArgs& a, hipStream_t s)
+hipError_t launch_k(const SepArgs& a, const SepArgs* b, hipStream_t s)
 {
     constexpr int BM = WM * TM * 32, BN = WN * TN * 32;
     constexpr int zs = slices_per_block<WM, WN, TM, TN, ZS, BF, X3, D3>();
     const int tiles_x = static_cast<int>((a.nx + BN - 1) / BN);
     const int tiles_y = static_cast<int>((a.ny + BM - 1) / BM);
     const int64_t blocks = static_cast<int64_t>(tiles_x) * tiles_y * ((a.nz + zs - 1) / zs);
-    if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_sep<WM, WN, TM, TN, ZS, BF, X3, D3>), dim3(static_cast<unsigned>(blocks)), dim3(WM * WN * 64),
-                       0, s, a, tiles_x, tiles_y);
+    if (2 * blocks > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_sep<WM, WN, TM, TN, ZS, BF, X3, D3>), dim3(static_cast<unsigned>(b ? 2 * blocks : blocks)),
+                       dim3(WM * WN * 64), 0, s, a, b ? *b : a, tiles_x, tiles_y, static_cast<int>(blocks));
     return hipGetLastError();
 }
 
 template <bool BF, bool X3, bool D3>
-hipError_t launch_t(const SepArgs& a, int tile, hipStream_t s)
+hipError_t launch_t(const SepArgs& a, const SepArgs* b, int tile, hipStream_t s)
 {
     switch (tile) {
-    case 0: return launch_k<2, 4, 4, 2, 1, BF, X3, D3>(a, s);
-    case 1: return launch_k<2, 2, 2, 2, 1, BF, X3, D3>(a, s);
-    case 2: return launch_k<2, 2, 1, 1, 1, BF, X3, D3>(a, s);
-    case 3: return launch_k<2, 4, 2, 2, 1, BF, X3, D3>(a, s);
-    case 4: return D3 ? launch_k<2, 4, 2, 2, 2, BF, X3, D3>(a, s) : launch_k<2, 4, 2, 2, 1, BF, X3, D3>(a, s);
-    case 5: return D3 ? launch_k<2, 2, 2, 2, 2, BF, X3, D3>(a, s) : launch_k<2, 2, 2, 2, 1, BF, X3, D3>(a, s);
-    case 6: return launch_k<1, 8, 4, 1, 2, BF, X3, D3>(a, s);
-    case 7: return launch_k<2, 4, 4, 1, 2, BF, X3, D3>(a, s);
-    case 8: return launch_k<2, 2, 4, 2, 2, BF, X3, D3>(a, s);
-    default: return launch_k<2, 2, 4, 4, 1, BF, X3, D3>(a, s);
+    case 0: return launch_k<2, 4, 4, 2, 1, BF, X3, D3>(a, b, s);
+    case 1: return launch_k<2, 2, 2, 2, 1, BF, X3, D3>(a, b, s);
+    case 2: return launch_k<2, 2, 1, 1, 1, BF, X3, D3>(a, b, s);
+    case 3: return launch_k<2, 4, 2, 2, 1, BF, X3, D3>(a, b, s);
+    case 4: return D3 ? launch_k<2, 4, 2, 2, 2, BF, X3, D3>(a, b, s) : launch_k<2, 4, 2, 2, 1, BF, X3, D3>(a, b, s);
+    case 5: return D3 ? launch_k<2, 2, 2, 2, 2, BF, X3, D3>(a, b, s) : launch_k<2, 2, 2, 2, 1, BF, X3, D3>(a, b, s);
+    case 6: return launch_k<1, 8, 4, 1, 2, BF, X3, D3>(a, b, s);
+    case 7: return launch_k<2, 4, 4, 1, 2, BF, X3, D3>(a, b, s);
+    case 8: return launch_k<2, 2, 4, 2, 2, BF, X3, D3>(a, b, s);
+    default: return launch_k<2, 2, 4, 4, 1, BF, X3, D3>(a, b, s);
     }
 }
 
@@ -966,9 +985,9 @@ int slices_t(int tile)
 }
 
 template <bool BF, bool X3>
-hipError_t launch_d(const SepArgs& a, int tile, hipStream_t s)
+hipError_t launch_d(const SepArgs& a, const SepArgs* b, int tile, hipStream_t s)
 {
-    return a.ez ? launch_t<BF, X3, true>(a, tile, s) : launch_t<BF, X3, false>(a, tile, s);
+    return a.ez ? launch_t<BF, X3, true>(a, b, tile, s) : launch_t<BF, X3, false>(a, b, tile, s);
 }
 
 }  // namespace
@@ -1039,16 +1058,21 @@ int sep_batch_blocks_per_cu(int method, bool d3)
     }
 }
 
-hipError_t launch_sep(const SepArgs& a, hipStream_t s)
+hipError_t launch_sep(const SepArgs& a, hipStream_t s) { return launch_sep_pair(a, nullptr, s); }
+
+hipError_t launch_sep_pair(const SepArgs& a, const SepArgs* b, hipStream_t s)
 {
     int tile = a.tile < 0 ? sep_default_tile(a.method, a.nx, a.ny, a.nz) : a.tile;
     if (tile >= sep_tile_count()) return hipErrorInvalidValue;
     if (a.ldp <= 0 || a.ldp % (2 * kJC) != 0) return hipErrorInvalidValue;  // whole pairs of stages
+    if (b && (b->method != a.method || b->nx != a.nx || b->ny != a.ny || b->nz != a.nz || b->ldp != a.ldp ||
+              (b->ez == nullptr) != (a.ez == nullptr)))
+        return hipErrorInvalidValue;
     switch (a.method) {
-    case GRF_SEP_BF16: return launch_d<true, false>(a, tile, s);
-    case GRF_SEP_F16: return launch_d<false, false>(a, tile, s);
-    case GRF_SEP_BF16_X3: return launch_d<true, true>(a, tile, s);
-    case GRF_SEP_F16_X3: return launch_d<false, true>(a, tile, s);
+    case GRF_SEP_BF16: return launch_d<true, false>(a, b, tile, s);
+    case GRF_SEP_F16: return launch_d<false, false>(a, b, tile, s);
+    case GRF_SEP_BF16_X3: return launch_d<true, true>(a, b, tile, s);
+    case GRF_SEP_F16_X3: return launch_d<false, true>(a, b, tile, s);
     default: return hipErrorInvalidValue;
     }
 }

@@ -138,17 +138,21 @@ __device__ __forceinline__ void axis_table_block(const AxisTableArgs a, int64_t 
     }
 }
 
-// Up to three tables (one grid's axes) in one launch; table t owns work blocks
-// [start[t], start[t + 1]).
+// Up to six tables (the axes of one grid, or of two fields on one grid) in one launch; table
+// t owns work blocks [start[t], start[t + 1]).  Constant indices only: a by-value argument
+// indexed per block would be copied to scratch memory.
 struct TableSet {
-    AxisTableArgs d[3];
-    int64_t start[4];
+    AxisTableArgs d[6];
+    int64_t start[7];
 };
 
 __global__ __launch_bounds__(256) void k_axis_tables3(TableSet ts)
 {
     const int64_t b = blockIdx.x;
-    if (b >= ts.start[2]) axis_table_block(ts.d[2], b - ts.start[2]);
+    if (b >= ts.start[5]) axis_table_block(ts.d[5], b - ts.start[5]);
+    else if (b >= ts.start[4]) axis_table_block(ts.d[4], b - ts.start[4]);
+    else if (b >= ts.start[3]) axis_table_block(ts.d[3], b - ts.start[3]);
+    else if (b >= ts.start[2]) axis_table_block(ts.d[2], b - ts.start[2]);
     else if (b >= ts.start[1]) axis_table_block(ts.d[1], b - ts.start[1]);
     else axis_table_block(ts.d[0], b);
 }
@@ -226,17 +230,17 @@ int64_t axis_table_blocks(const AxisTableArgs& a) { return ((a.count + kTabRows 
 
 hipError_t launch_axis_tables(const AxisTableArgs* d, int nd, hipStream_t s)
 {
-    if (nd < 0 || nd > 3) return hipErrorInvalidValue;
+    if (nd < 0 || nd > 6) return hipErrorInvalidValue;
     TableSet ts{};
     int64_t b = 0;
-    for (int t = 0; t < 3; ++t) {
+    for (int t = 0; t < 6; ++t) {
         ts.start[t] = b;
         if (t < nd) {
             ts.d[t] = d[t];
             b += axis_table_blocks(d[t]);
         }
     }
-    ts.start[3] = b;
+    ts.start[6] = b;
     if (b <= 0) return hipSuccess;
     if (b > 0x7fffffff) return hipErrorInvalidValue;
     hipLaunchKernelGGL(k_axis_tables3, dim3(static_cast<unsigned>(b)), dim3(256), 0, s, ts);
