@@ -727,29 +727,41 @@ __device__ __forceinline__ void sep_tile_gen(const SepArgs& a, const GenArgs& g,
     for (int r = 0; r < RPT; ++r) soff[r] = lbase + (r0 + r) * ROW_B + ((q ^ swz(r0 + r)) << 4);
 
     // per-mode inputs of one stage for this thread's quad, loaded a stage ahead of their use
-    // (padding modes j >= n load mode 0 and are zeroed by selects)
+    // (padding modes j >= n load mode 0 and are zeroed: zero weight and phase)
     struct Params {
         double z[4], p[4];
         float w[4];
     };
     auto load = [&](int64_t j0, Params& pr) {
+        if (j0 + kJC <= a.n) {  // every mode of the stage is a real one (all but the last stage)
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const int64_t j = j0 + 4 * q + m;
-            const int64_t jc = j < a.n ? j : 0;
-            pr.z[m] = za[jc];
-            pr.p[m] = ya ? gphi[jc] : 0.0;
-            pr.w[m] = use_w ? static_cast<float>(gw[jc]) : 1.f;
+            for (int m = 0; m < 4; ++m) {
+                const int64_t j = j0 + 4 * q + m;
+                pr.z[m] = za[j];
+                pr.p[m] = ya ? gphi[j] : 0.0;
+                pr.w[m] = use_w ? static_cast<float>(gw[j]) : 1.f;
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) {
+                const int64_t j = j0 + 4 * q + m;
+                const bool on = j < a.n;
+                const int64_t jc = on ? j : 0;
+                const double zv = za[jc], pv = ya ? gphi[jc] : 0.0;
+                const float wv = use_w ? static_cast<float>(gw[jc]) : 1.f;
+                pr.z[m] = on ? zv : 0.0;  // a padding mode has zero weight (and zero phase)
+                pr.p[m] = on ? pv : 0.0;
+                pr.w[m] = on ? wv : 0.f;
+            }
         }
     };
-    auto gen = [&](int64_t j0, const Params& pr, char* buf) {
+    auto gen = [&](const Params& pr, char* buf) {
         float er[4], ei[4], rr[4], ri[4];
 #pragma unroll
         for (int m = 0; m < 4; ++m) {
-            const bool on = j0 + 4 * q + m < a.n;
-            const double am = pr.z[m] * (on ? fs : 0.0);
-            const double ps = pr.p[m] * (on ? kInvTwoPiD : 0.0);
-            const float wj = on ? pr.w[m] : 0.f;
+            const double am = pr.z[m] * fs;
+            const double ps = pr.p[m] * kInvTwoPiD;
+            const float wj = pr.w[m];
             const double t0 = am * xr0 + ps;
             const double th = am * hh;
             const float f0 = static_cast<float>(t0 - floor(t0));  // exact in FP64
@@ -766,9 +778,13 @@ __device__ __forceinline__ void sep_tile_gen(const SepArgs& a, const GenArgs& g,
             if (r + 1 < RPT) {
 #pragma unroll
                 for (int m = 0; m < 4; ++m) {
-                    const float nr = er[m] * rr[m] - ei[m] * ri[m];
-                    ei[m] = er[m] * ri[m] + ei[m] * rr[m];
+                    float nr = fmaf(er[m], rr[m], -ei[m] * ri[m]);
+                    float ni = fmaf(er[m], ri[m], ei[m] * rr[m]);
+                    // opaque: the next row's pack converts these values (one v_cvt_pk) instead
+                    // of the compiler recomputing the products in mixed precision
+                    asm("" : "+v"(nr), "+v"(ni));
                     er[m] = nr;
+                    ei[m] = ni;
                 }
             }
         }
@@ -817,15 +833,15 @@ __device__ __forceinline__ void sep_tile_gen(const SepArgs& a, const GenArgs& g,
     Params p0, p1;
     load(0, p0);
     load(kJC, p1);
-    gen(0, p0, b0);
+    gen(p0, b0);
     __syncthreads();
     for (int64_t s = 0; s < nstage; s += 2) {
         if (s + 2 < nstage) load((s + 2) * kJC, p0);
-        gen((s + 1) * kJC, p1, b1);
+        gen(p1, b1);
         compute(b0);
         __syncthreads();
         if (s + 3 < nstage) load((s + 3) * kJC, p1);
-        if (s + 2 < nstage) gen((s + 2) * kJC, p0, b0);
+        if (s + 2 < nstage) gen(p0, b0);
         compute(b1);
         __syncthreads();
     }
