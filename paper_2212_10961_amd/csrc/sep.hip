@@ -591,10 +591,44 @@ __device__ __forceinline__ void sep_tile_dl(const SepArgs& a, const Epi& epi, in
     }
 
     // ---- epilogue: D[row][col], lane holds rows 8(e/4) + 4(l/32) + e%4, col l%32
+    // Interior tiles with one FP32 output (Y or K) branch once per tile and address cells by
+    // a uniform 64-bit row base plus a 32-bit lane offset; the rest check every cell.  (Not
+    // for the widest per-wave tiles: their accumulators leave no registers for it.)
+    constexpr bool kFastEpi = TM * TN * ZS <= 8;
+    const bool interior =
+        kFastEpi && x0 + BN <= a.nx && y0 + BM <= a.ny && a.nx < (int64_t(1) << 22);
+    const int only = (a.ind || (a.y && a.k)) ? 0 : (a.k ? 2 : (a.y ? 1 : 0));
 #pragma unroll
     for (int zs = 0; zs < ZS; ++zs) {
         if (z0 + zs >= a.nz) break;
         const int64_t plane = (z0 + zs) * a.ny * a.nx;
+        if (kFastEpi && interior && only != 0) {
+            // byte offsets below 2^32: rows < 256 and nx < 2^22
+            char* const out = reinterpret_cast<char*>((only == 2 ? a.k : a.y) + plane + y0 * a.nx + x0);
+            const uint32_t nxb = static_cast<uint32_t>(a.nx) * 4u;
+            auto cell = [&](int i, int j, int e) {
+                const uint32_t lo = static_cast<uint32_t>((wm * TM + i) * 32 + 4 * h + 8 * (e >> 2) + (e & 3)) * nxb +
+                                    static_cast<uint32_t>(((wn * TN + j) * 32 + (l & 31)) * 4);
+                return reinterpret_cast<float*>(out + lo);
+            };
+            if (only == 2) {
+#pragma clang fp contract(off)  // Y rounded before mu is added, as in the per-cell path
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+#pragma unroll
+                        for (int e = 0; e < 16; ++e) *cell(i, j, e) = expf(epi.mu + a.amp * acc[zs][i][j][e]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int j = 0; j < TN; ++j)
+#pragma unroll
+                        for (int e = 0; e < 16; ++e) *cell(i, j, e) = a.amp * acc[zs][i][j][e];
+            }
+            continue;
+        }
 #pragma unroll
         for (int i = 0; i < TM; ++i)
 #pragma unroll
