@@ -51,6 +51,22 @@ void timer_mark(hipStream_t s, bool begin)
     if (hipEventRecord(t.ev[t.used], s) == hipSuccess) ++t.used;
 }
 
+bool timer_take_pair(hipEvent_t* start, hipEvent_t* stop)
+{
+    KernelTimer& t = ktimer();
+    std::lock_guard<std::mutex> lk(t.mu);
+    if (!t.on || (t.used & 1)) return false;
+    while (t.ev.size() < t.used + 2) {
+        hipEvent_t e;
+        if (hipEventCreate(&e) != hipSuccess) return false;
+        t.ev.push_back(e);
+    }
+    *start = t.ev[t.used];
+    *stop = t.ev[t.used + 1];
+    t.used += 2;
+    return true;
+}
+
 int fail_hip(hipError_t e, const char* what)
 {
     return fail(GRF_EDEVICE, "HIP error in %s: %s", what, hipGetErrorString(e));
@@ -324,6 +340,12 @@ static int grid_launch(const grf_modes* modes, const grf_grid* grid, int method,
     const int64_t ldp = padded_modes(modes->n);
 
     GRF_HIP(build_tables(modes, grid, method, w, s));
+    if (is_sep(method)) {
+        SepArgs a = sep_args(modes, grid, method, tile, e, y, k, ind, w);
+        a.timed = true;
+        GRF_HIP(launch_sep(a, s));
+        return GRF_OK;
+    }
     TimedScope timed(s);
     if (method == GRF_DIRECT_F32) {
         GRF_HIP(launch_direct_grid_f32(static_cast<const float*>(w.t[0]), static_cast<const float*>(w.t[1]),
@@ -334,8 +356,6 @@ static int grid_launch(const grf_modes* modes, const grf_grid* grid, int method,
         GRF_HIP(launch_direct_grid_f64(static_cast<const double*>(w.t[0]), static_cast<const double*>(w.t[1]),
                                        static_cast<const double*>(w.t[2]), modes->w, modes->n, ldp, grid->n, amp64, e,
                                        0.0, y, k, ind, nullptr, nullptr, s));
-    } else {
-        GRF_HIP(launch_sep(sep_args(modes, grid, method, tile, e, y, k, ind, w), s));
     }
     return GRF_OK;
 }
@@ -482,9 +502,10 @@ int eval_pluri_grid(const grf_modes* m1, const grf_modes* m2, const grf_grid* gr
         const int nd1 = grid_table_descs(&a1, grid, method, w1, d);
         const int nd2 = grid_table_descs(&a2, grid, method, w2, d + nd1);
         GRF_HIP(launch_axis_tables(d, nd1 + nd2, s));
-        TimedScope timed(s);
         const SepArgs s2 = sep_args(&a2, grid, method, -1, Epi{}, f2, nullptr, nullptr, w2);
-        GRF_HIP(launch_sep_pair(sep_args(&a1, grid, method, -1, Epi{}, f1, nullptr, nullptr, w1), &s2, s));
+        SepArgs s1 = sep_args(&a1, grid, method, -1, Epi{}, f1, nullptr, nullptr, w1);
+        s1.timed = true;
+        GRF_HIP(launch_sep_pair(s1, &s2, s));
     } else {
         if ((rc = grid_launch(&a1, grid, method, -1, Epi{}, f1, nullptr, nullptr, tabs, s))) return rc;
         if ((rc = grid_launch(&a2, grid, method, -1, Epi{}, f2, nullptr, nullptr, tabs, s))) return rc;

@@ -34,6 +34,9 @@ inline bool is_bf16(int m) { return m == GRF_SEP_BF16 || m == GRF_SEP_BF16_X3; }
 // ---------------------------------------------------------------- kernel timer
 // Records an event pair around the main kernel of a call while the timer is enabled.
 void timer_mark(hipStream_t s, bool begin);
+// While the timer is enabled: the next event pair, for a launch that records its own start
+// and stop on the dispatch (hipExtLaunchKernel), which adds no marker packets to the stream.
+bool timer_take_pair(hipEvent_t* start, hipEvent_t* stop);
 struct TimedScope {
     hipStream_t s;
     explicit TimedScope(hipStream_t st) : s(st) { timer_mark(s, true); }
@@ -205,6 +208,7 @@ struct SepArgs {
     float* k;
     uint8_t* ind;
     int tile;              // < 0: size-based default; else tile selector (see sep.hip)
+    bool timed = false;    // the call's main kernel: timed by the kernel timer when it is on
 };
 hipError_t launch_sep(const SepArgs& a, hipStream_t s);
 // Two fields on the same grid (same method, sizes and ldp; the epilogue parameters of `a`
