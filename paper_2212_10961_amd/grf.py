@@ -13,6 +13,7 @@ or the truncation rule of Sec. 3.1.
 from __future__ import annotations
 
 import ctypes
+import functools
 import math
 from dataclasses import dataclass
 from typing import Optional, Sequence
@@ -90,6 +91,19 @@ class Modes:
         return int(self.z.shape[1])
 
     def c(self) -> L.GrfModes:
+        """C descriptor of the table, rebuilt only when a field it holds changes (tensor
+        contents may change in place: the descriptor holds their addresses)."""
+        key = (self.z.data_ptr(), tuple(self.z.shape), self.phi.data_ptr(),
+               None if self.w is None else self.w.data_ptr(), self.sigma, tuple(self.ell),
+               None if self.rot is None else np.asarray(self.rot, dtype=np.float64).tobytes())
+        d = self.__dict__.get("_cdesc")
+        if d is not None and d[0] == key:
+            return d[1]
+        m = self._c()
+        self.__dict__["_cdesc"] = (key, m)
+        return m
+
+    def _c(self) -> L.GrfModes:
         m = L.GrfModes()
         m.dim = self.dim
         m.n = self.n
@@ -167,6 +181,18 @@ def snap_periodic(z, ell, period, rot=None):
 
 
 def _grid(shape, origin=None, h=None) -> L.GrfGrid:
+    try:
+        return _grid_cached(tuple(shape), None if origin is None else tuple(origin), None if h is None else tuple(h))
+    except TypeError:  # unhashable entries
+        return _grid_build(shape, origin, h)
+
+
+@functools.lru_cache(maxsize=4096)
+def _grid_cached(shape, origin, h) -> L.GrfGrid:
+    return _grid_build(shape, origin, h)
+
+
+def _grid_build(shape, origin=None, h=None) -> L.GrfGrid:
     g = L.GrfGrid()
     n = list(shape) + [1] * (3 - len(shape))
     o = list(origin) if origin is not None else [0.0] * len(shape)
@@ -548,11 +574,19 @@ class Plan:
 
     def run(self, items, stream=None):
         """items: list of (Modes, shape, y tensor) — y flat float32 device tensors."""
-        arr = (L.GrfBatchItem * len(items))()
-        for i, (m, shape, y) in enumerate(items):
-            arr[i].modes = m.c()
-            arr[i].grid = _grid(shape)
-            arr[i].y = y.data_ptr()
+        # descriptors are marshalled once per (table descriptor, shape, output) and reused
+        key = [(m.c(), tuple(shape), y.data_ptr()) for m, shape, y in items]
+        last = getattr(self, "_last", None)
+        if last is not None and len(last[0]) == len(key) and all(
+                a[0] is b[0] and a[1] == b[1] and a[2] == b[2] for a, b in zip(last[0], key)):
+            arr = last[1]
+        else:
+            arr = (L.GrfBatchItem * len(items))()
+            for i, (mc, shape, yp) in enumerate(key):
+                arr[i].modes = mc
+                arr[i].grid = _grid(shape)
+                arr[i].y = yp
+            self._last = (key, arr)
         check(L.load().eval_field_batch(self._h, arr, len(items), _stream(stream)))
 
     def info(self):
