@@ -81,6 +81,59 @@ __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c)
                                                       0);
 }
 
+// Epilogue of one wave for one z-slice: D[row][col] of its TM x TN accumulator tiles, lane
+// holding rows 8(e/4) + 4(l/32) + e%4 and column l%32 of each 32x32 tile; the wave's tiles
+// start at row y0 + r0 and column x0 + c0 of the plane's cells (plane + y nx + x).  A block
+// tile (BM x BN at y0, x0) that lies inside the grid and writes one FP32 output (Y or K)
+// branches once and stores through a uniform row base plus 32-bit lane offsets; otherwise
+// every cell is bounds-checked and goes through epi_store.  FAST = false keeps the per-cell
+// form only (the widest per-wave tiles: their accumulators leave no registers for the other).
+template <int TM, int TN, int BM, int BN, bool FAST>
+__device__ __forceinline__ void store_tiles(const SepArgs& a, const Epi& epi, int64_t plane, int64_t x0, int64_t y0,
+                                            int r0, int c0, int l, const f32x16 (&acc)[TM][TN])
+{
+    const int h = l >> 5;
+    const int only = (a.ind || (a.y && a.k)) ? 0 : (a.k ? 2 : (a.y ? 1 : 0));
+    if (FAST && only != 0 && x0 + BN <= a.nx && y0 + BM <= a.ny && a.nx < (int64_t(1) << 22)) {
+        // byte offsets below 2^32: rows < 256 and nx < 2^22
+        char* const out = reinterpret_cast<char*>((only == 2 ? a.k : a.y) + plane + y0 * a.nx + x0);
+        const uint32_t nxb = static_cast<uint32_t>(a.nx) * 4u;
+        auto cell = [&](int i, int j, int e) {
+            const uint32_t lo = static_cast<uint32_t>(r0 + i * 32 + 4 * h + 8 * (e >> 2) + (e & 3)) * nxb +
+                                static_cast<uint32_t>((c0 + j * 32 + (l & 31)) * 4);
+            return reinterpret_cast<float*>(out + lo);
+        };
+        if (only == 2) {
+#pragma clang fp contract(off)  // Y rounded before mu is added, as in the per-cell path
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) *cell(i, j, e) = expf(epi.mu + a.amp * acc[i][j][e]);
+        } else {
+#pragma unroll
+            for (int i = 0; i < TM; ++i)
+#pragma unroll
+                for (int j = 0; j < TN; ++j)
+#pragma unroll
+                    for (int e = 0; e < 16; ++e) *cell(i, j, e) = a.amp * acc[i][j][e];
+        }
+        return;
+    }
+#pragma unroll
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int j = 0; j < TN; ++j) {
+            const int64_t x = x0 + c0 + j * 32 + (l & 31);
+#pragma unroll
+            for (int e = 0; e < 16; ++e) {
+                const int64_t y = y0 + r0 + i * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
+                if (x < a.nx && y < a.ny) epi_store(plane + y * a.nx + x, a.amp * acc[i][j][e], epi, a.y, a.k, a.ind);
+            }
+        }
+}
+
 // LDS words one tile shape needs (NBUF stages of hi (+ lo) A and B rows).
 template <int WM, int WN, int TM, int TN, bool X3>
 struct SepShape {
@@ -287,22 +340,8 @@ __device__ __forceinline__ void sep_tile_reg(const SepArgs& a, const Epi& epi, i
         __syncthreads();
     }
 
-    // ---- epilogue: D[row][col], lane holds rows 8(e/4) + 4(l/32) + e%4, col l%32
-    const int64_t plane = z0 * a.ny * a.nx;
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            const int64_t x = x0 + (wn * TN + j) * 32 + (l & 31);
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int64_t y = y0 + (wm * TM + i) * 32 + 8 * (e >> 2) + 4 * (l >> 5) + (e & 3);
-                if (x < a.nx && y < a.ny) {
-                    const int64_t c = plane + y * a.nx + x;
-                    epi_store(c, a.amp * acc[i][j][e], epi, a.y, a.k, a.ind);
-                }
-            }
-        }
+    store_tiles<TM, TN, WM * TM * 32, WN * TN * 32, TM * TN <= 8>(a, epi, z0 * a.ny * a.nx, x0, y0, wm * TM * 32,
+                                                                  wn * TN * 32, l, acc);
 }
 
 // ---- direct-to-LDS staging -------------------------------------------------------------
@@ -885,18 +924,7 @@ __device__ __forceinline__ void sep_tile_gen(const SepArgs& a, const GenArgs& g,
         __syncthreads();
     }
 
-    // epilogue: D[row][col], lane holds rows 8(e/4) + 4(l/32) + e%4, col l%32
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int j = 0; j < TN; ++j) {
-            const int64_t x = x0 + (wn * TN + j) * 32 + (l & 31);
-#pragma unroll
-            for (int e = 0; e < 16; ++e) {
-                const int64_t y = y0 + (wm * TM + i) * 32 + 8 * (e >> 2) + 4 * h + (e & 3);
-                if (x < a.nx && y < a.ny) epi_store(y * a.nx + x, a.amp * acc[i][j][e], a.epi, a.y, a.k, a.ind);
-            }
-        }
+    store_tiles<TM, TN, BM, BN, true>(a, a.epi, 0, x0, y0, wm * TM * 32, wn * TN * 32, l, acc);
 }
 
 // Index of the accelerator complex (XCD) this wave runs on (hardware register XCC_ID).
