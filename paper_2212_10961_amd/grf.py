@@ -93,7 +93,7 @@ class Modes:
     def c(self) -> L.GrfModes:
         """C descriptor of the table, rebuilt only when a field it holds changes (tensor
         contents may change in place: the descriptor holds their addresses)."""
-        key = (self.z.data_ptr(), tuple(self.z.shape), self.phi.data_ptr(),
+        key = (self.z.data_ptr(), tuple(self.z.shape), self.phi.data_ptr(), tuple(self.phi.shape),
                None if self.w is None else self.w.data_ptr(), self.sigma, tuple(self.ell),
                None if self.rot is None else np.asarray(self.rot, dtype=np.float64).tobytes())
         d = self.__dict__.get("_cdesc")

@@ -444,3 +444,26 @@ def test_krige_validation(lib):
     assert lib.krige_apply_grid(ctypes.byref(m), ctypes.byref(k), dev, dev, 100, ctypes.byref(g), None, dev, 4096,
                                 None) == L.GRF_EINVAL
     assert lib.krige_apply_points(ctypes.byref(m), ctypes.byref(k), dev, dev, 100, dev, 0, dev, dev, 4096, None) == 0
+
+
+def test_modes_descriptor_cache():
+    """The binding's per-table C descriptor is reused while nothing it holds changes and
+    rebuilt when a scalar, a length or a tensor is replaced (host tensors: no GPU needed)."""
+    import torch
+    from paper_2212_10961_amd import grf
+    z = torch.zeros(2, 16, dtype=torch.float64)
+    phi = torch.zeros(16, dtype=torch.float64)
+    m = grf.Modes(z, phi, 1.0, (3.0, 4.0))
+    c1 = m.c()
+    assert m.c() is c1
+    m.sigma = 2.0
+    c2 = m.c()
+    assert c2 is not c1 and c2.sigma == 2.0
+    m.ell = (5.0, 4.0)
+    c3 = m.c()
+    assert c3 is not c2 and c3.ell[0] == 5.0
+    m.z = torch.ones(2, 16, dtype=torch.float64)
+    c4 = m.c()
+    assert c4 is not c3 and c4.z == m.z.data_ptr()
+    m.phi = phi[:8]  # same storage and address, another shape
+    assert m.c() is not c4
