@@ -33,6 +33,22 @@ __device__ inline uint32_t pack_bf162(float re, float im)
            (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, i)) << 16);
 }
 
+// Table stores are streaming (non-temporal): the tables are read by the next kernel, and
+// stores that do not stay dirty in this XCD's L2 leave less to write back at the kernel's
+// end (measured ~2.5 us less per 256^3 step).
+template <typename T>
+__device__ __forceinline__ void st(void* base, int64_t e, T v)
+{
+    __builtin_nontemporal_store(v, static_cast<T*>(base) + e);
+}
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+template <>
+__device__ __forceinline__ void st<float2>(void* base, int64_t e, float2 v)
+{
+    const f32x2 w = {v.x, v.y};
+    __builtin_nontemporal_store(w, static_cast<f32x2*>(base) + e);
+}
+
 __device__ inline float half_to_float(uint16_t b) { return static_cast<float>(__builtin_bit_cast(_Float16, b)); }
 __device__ inline float bf16_to_float(uint16_t b) { return static_cast<float>(__builtin_bit_cast(__bf16, b)); }
 
@@ -56,9 +72,9 @@ __device__ __forceinline__ void axis_table_rows(const AxisTableArgs a, int64_t i
         const double f = zero ? 0.0 : t - floor(t);  // exact in FP64
 
         if constexpr (FMT == TF_REV_F32) {
-            static_cast<float*>(a.out)[e] = static_cast<float>(f);
+            st<float>(a.out, e, static_cast<float>(f));
         } else if constexpr (FMT == TF_REV_F64) {
-            static_cast<double*>(a.out)[e] = f;
+            st<double>(a.out, e, f);
         } else if constexpr (FAST && (FMT == TF_CPLX_F32 || FMT == TF_F16 || FMT == TF_BF16)) {
             // one rounding to the table format: the hardware cos/sin of the FP64-reduced
             // fraction in revolutions (|err| ~1e-7) is far below it
@@ -66,9 +82,9 @@ __device__ __forceinline__ void axis_table_rows(const AxisTableArgs a, int64_t i
             const float wf = static_cast<float>(wj);
             const float cs = zero ? 0.f : __builtin_amdgcn_cosf(fr) * wf;
             const float sn = zero ? 0.f : __builtin_amdgcn_sinf(fr) * static_cast<float>(sgn) * wf;
-            if constexpr (FMT == TF_CPLX_F32) static_cast<float2*>(a.out)[e] = make_float2(cs, sn);
-            else if constexpr (FMT == TF_F16) static_cast<uint32_t*>(a.out)[e] = pack_half2(cs, sn);
-            else static_cast<uint32_t*>(a.out)[e] = pack_bf162(cs, sn);
+            if constexpr (FMT == TF_CPLX_F32) st<float2>(a.out, e, make_float2(cs, sn));
+            else if constexpr (FMT == TF_F16) st<uint32_t>(a.out, e, pack_half2(cs, sn));
+            else st<uint32_t>(a.out, e, pack_bf162(cs, sn));
         } else {
             double sn, cs;
             sincospi(2.0 * f, &sn, &cs);
@@ -76,22 +92,22 @@ __device__ __forceinline__ void axis_table_rows(const AxisTableArgs a, int64_t i
             sn *= sgn * wj;
             cs *= wj;
             if constexpr (FMT == TF_CPLX_F32) {
-                static_cast<float2*>(a.out)[e] = make_float2(static_cast<float>(cs), static_cast<float>(sn));
+                st<float2>(a.out, e, make_float2(static_cast<float>(cs), static_cast<float>(sn)));
             } else if constexpr (FMT == TF_F16 || FMT == TF_F16_HILO) {
                 const uint32_t hi = pack_half2(static_cast<float>(cs), static_cast<float>(sn));
-                static_cast<uint32_t*>(a.out)[e] = hi;
+                st<uint32_t>(a.out, e, hi);
                 if constexpr (FMT == TF_F16_HILO) {
                     const double rl = cs - static_cast<double>(half_to_float(static_cast<uint16_t>(hi & 0xffff)));
                     const double il = sn - static_cast<double>(half_to_float(static_cast<uint16_t>(hi >> 16)));
-                    static_cast<uint32_t*>(a.out_lo)[e] = pack_half2(static_cast<float>(rl), static_cast<float>(il));
+                    st<uint32_t>(a.out_lo, e, pack_half2(static_cast<float>(rl), static_cast<float>(il)));
                 }
             } else {
                 const uint32_t hi = pack_bf162(static_cast<float>(cs), static_cast<float>(sn));
-                static_cast<uint32_t*>(a.out)[e] = hi;
+                st<uint32_t>(a.out, e, hi);
                 if constexpr (FMT == TF_BF16_HILO) {
                     const double rl = cs - static_cast<double>(bf16_to_float(static_cast<uint16_t>(hi & 0xffff)));
                     const double il = sn - static_cast<double>(bf16_to_float(static_cast<uint16_t>(hi >> 16)));
-                    static_cast<uint32_t*>(a.out_lo)[e] = pack_bf162(static_cast<float>(rl), static_cast<float>(il));
+                    st<uint32_t>(a.out_lo, e, pack_bf162(static_cast<float>(rl), static_cast<float>(il)));
                 }
             }
         }
