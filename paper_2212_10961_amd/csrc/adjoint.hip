@@ -361,8 +361,16 @@ struct BwdSepK {
 // comp parity).  At the end of the tile the pair exchanges V once more and applies Ez:
 // comp 0 -> Re(V Ez), comp 1 -> Im(V Ez) (with y and z weights), comp 2 -> Im(V^x Ez).
 // The two half-waves (rows 4h ..) are added at the end.
+// The dL/dY tiles (hi then lo, 8 KiB each per 32 rows) go through LDS, two buffers, loaded
+// straight from global memory (global_load_lds) one tile ahead: the four waves share each
+// tile instead of each fetching it from L2, and the fetch overlaps the previous tile's work.
+typedef const __attribute__((address_space(1))) void bwd_gbl_void;
+typedef __attribute__((address_space(3))) void bwd_lds_void;
+
 __global__ __launch_bounds__(256) void k_bwd_sep(BwdSepK p, float* __restrict__ partial)
 {
+    constexpr int kTileB = 32 * kBwdSepK * 2;  // bytes of one 32-row bf16 tile
+    __shared__ __attribute__((aligned(16))) char sa[2][2 * kTileB];
     const int t = threadIdx.x, l = t & 63, h = l >> 5;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
     const int col = l & 31, c = col & 3;
@@ -381,17 +389,34 @@ __global__ __launch_bounds__(256) void k_bwd_sep(BwdSepK p, float* __restrict__ 
     const int64_t ntile = p.qp / 32;
     const int64_t per = (ntile + gridDim.y - 1) / gridDim.y;
     const int64_t t0 = static_cast<int64_t>(blockIdx.y) * per, t1 = min(ntile, t0 + per);
+    // 16 chunks of 1 KiB per tile (hi 0..7, lo 8..15), four per wave; lane l moves bytes
+    // 16 l .. 16 l + 15 of its chunk
+    auto issue = [&](int64_t tile, char* buf) {
+        const char* gh = reinterpret_cast<const char*>(p.ga_hi + tile * 32 * kBwdSepK);
+        const char* gl = reinterpret_cast<const char*>(p.ga_lo + tile * 32 * kBwdSepK);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int ch = 4 * w + k;
+            const char* src = (ch < 8 ? gh + ch * 1024 : gl + (ch - 8) * 1024) + 16 * l;
+            __builtin_amdgcn_global_load_lds((bwd_gbl_void*)src, (bwd_lds_void*)(buf + ch * 1024), 16, 0, 0);
+        }
+    };
+    const int fo = (col * 16 + 8 * h) * 2;  // this lane's fragment bytes within a k-step's 1 KiB
+    if (t0 < t1) issue(t0, sa[0]);
     for (int64_t tile = t0; tile < t1; ++tile) {
+        const char* cur = sa[(tile - t0) & 1];
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();  // this tile is in `cur` for every wave; every wave is done with the other buffer
+        if (tile + 1 < t1) issue(tile + 1, sa[(tile + 1 - t0) & 1]);
         const int64_t q0 = tile * 32;
-        const int64_t arow = tile * 32 * kBwdSepK + col * 16 + 8 * h;  // fragment-major rows
         // one accumulator: 128 VGPRs, four waves per SIMD to cover the loads and the epilogue
         f32x16 acc;
 #pragma unroll
         for (int e = 0; e < 16; ++e) acc[e] = 0.f;
 #pragma unroll
         for (int ks = 0; ks < KS; ++ks) {
-            const uint4 ah = *reinterpret_cast<const uint4*>(p.ga_hi + arow + 512 * ks);
-            const uint4 al = *reinterpret_cast<const uint4*>(p.ga_lo + arow + 512 * ks);
+            const uint4 ah = *reinterpret_cast<const uint4*>(cur + ks * 1024 + fo);
+            const uint4 al = *reinterpret_cast<const uint4*>(cur + kTileB + ks * 1024 + fo);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bh[ks]),
                                                           acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, ah), __builtin_bit_cast(bf16x8, bl[ks]),
