@@ -370,7 +370,8 @@ typedef __attribute__((address_space(3))) void bwd_lds_void;
 __global__ __launch_bounds__(256) void k_bwd_sep(BwdSepK p, float* __restrict__ partial)
 {
     constexpr int kTileB = 32 * kBwdSepK * 2;  // bytes of one 32-row bf16 tile
-    __shared__ __attribute__((aligned(16))) char sa[2][2 * kTileB];
+    constexpr int kEyOff = 2 * kTileB, kEzOff = kEyOff + 32 * 32 * 8, kBufB = kEzOff + 32 * 8;
+    __shared__ __attribute__((aligned(16))) char sa[2][kBufB];  // A hi, A lo, Ey rows, Ez row
     const int t = threadIdx.x, l = t & 63, h = l >> 5;
     const int w = __builtin_amdgcn_readfirstlane(t >> 6);
     const int col = l & 31, c = col & 3;
@@ -389,8 +390,10 @@ __global__ __launch_bounds__(256) void k_bwd_sep(BwdSepK p, float* __restrict__ 
     const int64_t ntile = p.qp / 32;
     const int64_t per = (ntile + gridDim.y - 1) / gridDim.y;
     const int64_t t0 = static_cast<int64_t>(blockIdx.y) * per, t1 = min(ntile, t0 + per);
-    // 16 chunks of 1 KiB per tile (hi 0..7, lo 8..15), four per wave; lane l moves bytes
-    // 16 l .. 16 l + 15 of its chunk
+    // Per tile: 16 chunks of 1 KiB of dL/dY (hi 0..7, lo 8..15), four per wave; the tile's 32
+    // Ey rows of the block's 32 modes (256 B each, four rows per chunk), two chunks per wave;
+    // the Ez row of its slice (256 B, 16 lanes of wave 0).  Lane l moves bytes 16 l .. of a chunk.
+    const int64_t jb0 = static_cast<int64_t>(blockIdx.x) * 32;
     auto issue = [&](int64_t tile, char* buf) {
         const char* gh = reinterpret_cast<const char*>(p.ga_hi + tile * 32 * kBwdSepK);
         const char* gl = reinterpret_cast<const char*>(p.ga_lo + tile * 32 * kBwdSepK);
@@ -400,7 +403,19 @@ __global__ __launch_bounds__(256) void k_bwd_sep(BwdSepK p, float* __restrict__ 
             const char* src = (ch < 8 ? gh + ch * 1024 : gl + (ch - 8) * 1024) + 16 * l;
             __builtin_amdgcn_global_load_lds((bwd_gbl_void*)src, (bwd_lds_void*)(buf + ch * 1024), 16, 0, 0);
         }
+        const int64_t zt = tile * 32 / p.nyp, yt = tile * 32 - zt * p.nyp;
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int ch = 2 * w + k;
+            const char* src = reinterpret_cast<const char*>(p.ey + (yt + 4 * ch + (l >> 4)) * p.ldp + jb0) + 16 * (l & 15);
+            __builtin_amdgcn_global_load_lds((bwd_gbl_void*)src, (bwd_lds_void*)(buf + kEyOff + ch * 1024), 16, 0, 0);
+        }
+        if (w == 0 && l < 16) {
+            const char* src = reinterpret_cast<const char*>(p.ez + zt * p.ldp + jb0) + 16 * l;
+            __builtin_amdgcn_global_load_lds((bwd_gbl_void*)src, (bwd_lds_void*)(buf + kEzOff), 16, 0, 0);
+        }
     };
+    const int jl = w * 8 + (col >> 2);  // this lane's mode within the block's 32
     const int fo = (col * 16 + 8 * h) * 2;  // this lane's fragment bytes within a k-step's 1 KiB
     if (t0 < t1) issue(t0, sa[0]);
     for (int64_t tile = t0; tile < t1; ++tile) {
@@ -427,18 +442,19 @@ __global__ __launch_bounds__(256) void k_bwd_sep(BwdSepK p, float* __restrict__ 
         // lane holds rows y = y0 + 8 (e / 4) + 4 h + e % 4 of slice zi, column col
         const int64_t zi = q0 / p.nyp, y0 = q0 - zi * p.nyp + 4 * h;
         const float yb = p.oy + (static_cast<float>(y0) + 0.5f) * p.hy;
-        const float2* eyr = p.ey + y0 * p.ldp + j;  // the y table has nyp rows (padded rows: U = 0)
+        // Ey of rows 4 h + r of the tile (the y table has nyp rows: padded rows have U = 0)
+        const float2* eyr = reinterpret_cast<const float2*>(cur + kEyOff) + 4 * h * 32 + jl;
         float vA = 0.f, vY = 0.f;
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int r = 8 * (e >> 2) + (e & 3);
-            const float2 ey = eyr[r * p.ldp];
+            const float2 ey = eyr[r * 32];
             const float own = acc[e], oth = swap_pair(own);
             const float v = fmaf(own, ey.x, oth * (sgn * ey.y));
             vA += v;
             vY = fmaf(fmaf(static_cast<float>(r), p.hy, yb), v, vY);
         }
-        const float2 ez = p.ez[zi * p.ldp + j];
+        const float2 ez = reinterpret_cast<const float2*>(cur + kEzOff)[jl];
         const float zc = p.oz + (static_cast<float>(zi) + 0.5f) * p.hz;
         const float oA = swap_pair(vA), oY = swap_pair(vY);
         // (re, im) of V and of sum y U e for this lane's pair
