@@ -444,7 +444,8 @@ __global__ __launch_bounds__(256) void k_bwd_sep(BwdSepK p, float* __restrict__ 
         const float yb = p.oy + (static_cast<float>(y0) + 0.5f) * p.hy;
         // Ey of rows 4 h + r of the tile (the y table has nyp rows: padded rows have U = 0)
         const float2* eyr = reinterpret_cast<const float2*>(cur + kEyOff) + 4 * h * 32 + jl;
-        float vA = 0.f, vY = 0.f;
+        // sum_y y U e = yb sum U e + hy sum r U e over the lane's rows r
+        float vA = 0.f, vR = 0.f;
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
             const int r = 8 * (e >> 2) + (e & 3);
@@ -452,8 +453,9 @@ __global__ __launch_bounds__(256) void k_bwd_sep(BwdSepK p, float* __restrict__ 
             const float own = acc[e], oth = swap_pair(own);
             const float v = fmaf(own, ey.x, oth * (sgn * ey.y));
             vA += v;
-            vY = fmaf(fmaf(static_cast<float>(r), p.hy, yb), v, vY);
+            vR = fmaf(static_cast<float>(r), v, vR);
         }
+        const float vY = fmaf(yb, vA, p.hy * vR);
         const float2 ez = reinterpret_cast<const float2*>(cur + kEzOff)[jl];
         const float zc = p.oz + (static_cast<float>(zi) + 0.5f) * p.hz;
         const float oA = swap_pair(vA), oY = swap_pair(vY);
