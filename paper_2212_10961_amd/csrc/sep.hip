@@ -81,12 +81,27 @@ __device__ __forceinline__ f32x16 mfma(uint4 a, uint4 b, f32x16 c)
                                                       0);
 }
 
+// exp(x) for the log-normal stores of interior tiles: 2^t with t = x log2(e) carried as an
+// exact FMA split t_hi + t_lo, the hardware base-2 exponential of t_hi and a first-order
+// correction for t_lo (|t_lo| <= 2^-24 |t|).  Error: that of v_exp_f32 plus ~1 ulp, i.e. a few
+// ulp; inf above ~88.7, 0 far below -87, NaN in, NaN out.
+__device__ __forceinline__ float exp_split(float x)
+{
+    constexpr float kLog2e = 1.44269502162933349609375f;  // log2(e) rounded to FP32
+    constexpr float kLog2eLo = 1.925963033500011e-08f;    // log2(e) - kLog2e
+    constexpr float kLn2 = 0.693147180559945309f;
+    const float th = x * kLog2e;
+    const float tl = fmaf(x, kLog2eLo, fmaf(x, kLog2e, -th));
+    const float e = __builtin_amdgcn_exp2f(th);
+    return fmaf(e, tl * kLn2, e);
+}
+
 // Epilogue of one wave for one z-slice: D[row][col] of its TM x TN accumulator tiles, lane
 // holding rows 8(e/4) + 4(l/32) + e%4 and column l%32 of each 32x32 tile; the wave's tiles
 // start at row y0 + r0 and column x0 + c0 of the plane's cells (plane + y nx + x).  A block
 // tile (BM x BN at y0, x0) that lies inside the grid and writes one FP32 output (Y or K)
-// branches once and stores through a uniform row base plus 32-bit lane offsets; otherwise
-// every cell is bounds-checked and goes through epi_store.  FAST = false keeps the per-cell
+// branches once and stores through a uniform row base plus 32-bit lane offsets (K by
+// exp_split); otherwise every cell is bounds-checked and goes through epi_store.  FAST = false keeps the per-cell
 // form only (the widest per-wave tiles: their accumulators leave no registers for the other).
 template <int TM, int TN, int BM, int BN, bool FAST>
 __device__ __forceinline__ void store_tiles(const SepArgs& a, const Epi& epi, int64_t plane, int64_t x0, int64_t y0,
@@ -110,7 +125,7 @@ __device__ __forceinline__ void store_tiles(const SepArgs& a, const Epi& epi, in
 #pragma unroll
                 for (int j = 0; j < TN; ++j)
 #pragma unroll
-                    for (int e = 0; e < 16; ++e) *cell(i, j, e) = expf(epi.mu + a.amp * acc[i][j][e]);
+                    for (int e = 0; e < 16; ++e) *cell(i, j, e) = exp_split(epi.mu + a.amp * acc[i][j][e]);
         } else {
 #pragma unroll
             for (int i = 0; i < TM; ++i)
@@ -635,9 +650,10 @@ __device__ __forceinline__ void sep_tile_dl(const SepArgs& a, const Epi& epi, in
     }
 
     // ---- epilogue: D[row][col], lane holds rows 8(e/4) + 4(l/32) + e%4, col l%32
-    // Interior tiles with one FP32 output (Y or K) branch once per tile and address cells by
-    // a uniform 64-bit row base plus a 32-bit lane offset; the rest check every cell.  (Not
-    // for the widest per-wave tiles: their accumulators leave no registers for it.)
+    // Interior tiles with one FP32 output (Y or K, the latter by exp_split) branch once per
+    // tile and address cells by a uniform 64-bit row base plus a 32-bit lane offset; the rest
+    // check every cell.  (Not for the widest per-wave tiles: their accumulators leave no
+    // registers for it.)
     constexpr bool kFastEpi = TM * TN * ZS <= 8;
     const bool interior =
         kFastEpi && x0 + BN <= a.nx && y0 + BM <= a.ny && a.nx < (int64_t(1) << 22);
@@ -662,7 +678,7 @@ __device__ __forceinline__ void sep_tile_dl(const SepArgs& a, const Epi& epi, in
 #pragma unroll
                     for (int j = 0; j < TN; ++j)
 #pragma unroll
-                        for (int e = 0; e < 16; ++e) *cell(i, j, e) = expf(epi.mu + a.amp * acc[zs][i][j][e]);
+                        for (int e = 0; e < 16; ++e) *cell(i, j, e) = exp_split(epi.mu + a.amp * acc[zs][i][j][e]);
             } else {
 #pragma unroll
                 for (int i = 0; i < TM; ++i)

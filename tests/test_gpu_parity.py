@@ -274,3 +274,21 @@ def test_grid_call_captured_in_a_graph(orc, grf, meth):
         assert np.max(np.abs(to_np(out["k"]) - kref) / kref) < 1e-5
         grf.field_grid(m, (8, 8, 8), method="direct_f32")  # eager work between replays
         torch.cuda.synchronize()
+
+
+@pytest.mark.parametrize("meth,shape", [("sep_f16", (256, 256, 6)), ("sep_f16", (300, 270, 5)),
+                                        ("sep_bf16_x3", (256, 256, 3)), ("sep_f16", (512, 384))])
+def test_lognormal_store_matches_exp_of_y(grf, meth, shape):
+    """K written alone (interior tiles: exp by the split base-2 form) against exp(mu + Y) in
+    FP64 of the Y the same tiles write alone: within a few FP32 ulp everywhere."""
+    dim = len(shape)
+    _say(f"case lognormal store {meth} {shape}")
+    z, phi = grf.make_modes(dim, wl.EXPONENTIAL, 256, 97)
+    m = grf.modes_from_tables(z, phi, 2.0, (16.0, 16.0, 4.0)[:dim])
+    y = to_np(grf.field_grid(m, shape, method=meth)["y"]).astype(np.float32)
+    for mu in (0.0, -1.5, 3.0):
+        k = to_np(grf.field_grid(m, shape, method=meth, mu=mu, want_y=False, want_k=True)["k"]).astype(np.float64)
+        want = np.exp((np.float32(mu) + y).astype(np.float64))  # the FP32 sum mu + Y, then exp in FP64
+        rel = np.abs(k - want) / want
+        _say(f"  mu={mu}: max rel {rel.max():.2e}")
+        assert rel.max() <= 3e-7
