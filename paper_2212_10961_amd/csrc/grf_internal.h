@@ -54,15 +54,23 @@ struct Epi {
 
 Epi make_epi(const grf_epi* e);
 
+// Output pointers are global memory: as global (not flat) stores they count only against the
+// vector-memory counter, so later LDS waits do not wait for them.
+template <typename T>
+__device__ __forceinline__ __attribute__((address_space(1))) T* global_ptr(T* p)
+{
+    return (__attribute__((address_space(1))) T*)p;
+}
+
 __device__ __forceinline__ void epi_store(int64_t c, float yv, const Epi& e, float* __restrict__ y,
                                           float* __restrict__ k, uint8_t* __restrict__ ind)
 {
-    if (y) y[c] = yv;
-    if (k) k[c] = expf(e.mu + yv);
+    if (y) global_ptr(y)[c] = yv;
+    if (k) global_ptr(k)[c] = expf(e.mu + yv);
     if (ind) {
         int f = 0;
         for (int q = 0; q < e.nthr; ++q) f += (yv > e.thr[q]) ? 1 : 0;
-        ind[c] = static_cast<uint8_t>(f);
+        global_ptr(ind)[c] = static_cast<uint8_t>(f);
     }
 }
 

@@ -111,12 +111,13 @@ __device__ __forceinline__ void store_tiles(const SepArgs& a, const Epi& epi, in
     const int only = (a.ind || (a.y && a.k)) ? 0 : (a.k ? 2 : (a.y ? 1 : 0));
     if (FAST && only != 0 && x0 + BN <= a.nx && y0 + BM <= a.ny && a.nx < (int64_t(1) << 22)) {
         // byte offsets below 2^32: rows < 256 and nx < 2^22
-        char* const out = reinterpret_cast<char*>((only == 2 ? a.k : a.y) + plane + y0 * a.nx + x0);
+        __attribute__((address_space(1))) char* const out =
+            (__attribute__((address_space(1))) char*)((only == 2 ? a.k : a.y) + plane + y0 * a.nx + x0);
         const uint32_t nxb = static_cast<uint32_t>(a.nx) * 4u;
         auto cell = [&](int i, int j, int e) {
             const uint32_t lo = static_cast<uint32_t>(r0 + i * 32 + 4 * h + 8 * (e >> 2) + (e & 3)) * nxb +
                                 static_cast<uint32_t>((c0 + j * 32 + (l & 31)) * 4);
-            return reinterpret_cast<float*>(out + lo);
+            return (__attribute__((address_space(1))) float*)(out + lo);
         };
         if (only == 2) {
 #pragma clang fp contract(off)  // Y rounded before mu is added, as in the per-cell path
