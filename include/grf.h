@@ -412,6 +412,8 @@ int grf_plan_info(const grf_plan* plan, int32_t* tile_m, int32_t* tile_n, int32_
  * pair of HIP events on its stream around its main kernel: the sum kernel of
  * eval_field_grid / eval_field_points, the epilogue kernel of epilogue_apply, the main
  * adjoint kernel of field_backward(_grid) and the persistent kernel of eval_field_batch.
+ * The separable contraction of eval_field_grid (and of eval_pluri_grid) carries the pair on
+ * its own dispatch (hipExtLaunchKernel start/stop events), so it measures that kernel alone.
  *   grf_kernel_timer_enable(1) clears the record and starts recording; (0) stops.
  *   grf_kernel_timer_read waits for the recorded events and returns the summed kernel
  *   time (ms) and the number of timed launches.  Events are created on first use and
