@@ -210,13 +210,22 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(const double* __restrict__ L, 
     }
     __syncthreads();
     if (blockIdx.x == 0 && t < nb) z[k0 + t] = xb[t];
-    const int64_t i = k0 + nb + static_cast<int64_t>(blockIdx.x) * blockDim.x + t;
+    // 32 rows per workgroup, eight lanes per row, four consecutive entries per lane: each row's
+    // block entries are read as one contiguous run; the eight partial dot products are added
+    // by lane exchanges
+    const int64_t i = k0 + nb + static_cast<int64_t>(blockIdx.x) * 32 + (t >> 3);
+    const int q = 4 * (t & 7);
+    double v = 0.0;
     if (i < m) {
         const double* row = L + i * lda + k0;
-        double v = 0.0;
-        for (int l = 0; l < nb; ++l) v += row[l] * xb[l];
-        r[i] -= v;
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (q + u < nb) v += row[q + u] * xb[q + u];
     }
+    v += __shfl_xor(v, 1);
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 4);
+    if (i < m && (t & 7) == 0) r[i] -= v;
 }
 
 // Backward step: x_k = L_kk^-T z_k; z_i -= L_ki^T x_k for rows i < k0.
@@ -362,7 +371,7 @@ hipError_t launch_chol_solve(const double* L, const double* diag, int64_t m, int
     // side z (x, updated in place), solution in b; then b -> x
     for (int64_t k0 = 0; k0 < m; k0 += kNb) {
         const int64_t below = m - k0 - kNb;
-        const unsigned blocks = static_cast<unsigned>(below > 0 ? (below + 255) / 256 : 1);
+        const unsigned blocks = static_cast<unsigned>(below > 0 ? (below + 31) / 32 : 1);
         hipLaunchKernelGGL(k_trsv_fwd, dim3(blocks), dim3(256), 0, s, L, diag, m, lda, k0, b, x);
     }
     for (int64_t k0 = ((m - 1) / kNb) * kNb; k0 >= 0; k0 -= kNb) {
