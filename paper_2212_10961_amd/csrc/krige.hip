@@ -91,6 +91,7 @@ __global__ __launch_bounds__(64) void k_potrf_trsm(double* __restrict__ A, int64
 {
     __shared__ double col[kNb];
     __shared__ double L[kNb][kNb + 1];
+    __shared__ double dinv[kNb];
     const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
     const int r = threadIdx.x;
     double row[kNb];
@@ -125,6 +126,7 @@ __global__ __launch_bounds__(64) void k_potrf_trsm(double* __restrict__ A, int64
             for (int c = 0; c < kNb; ++c) dk[r * kNb + c] = L[r][c];
         }
     }
+    if (r < nb) dinv[r] = 1.0 / L[r][r];  // the substitution below multiplies by reciprocals
     __syncthreads();
     const int64_t i = k0 + nb + static_cast<int64_t>(blockIdx.x) * blockDim.x + r;
     if (i >= m) return;
@@ -135,7 +137,7 @@ __global__ __launch_bounds__(64) void k_potrf_trsm(double* __restrict__ A, int64
         if (j < nb) {
             double v = prow[j];
             for (int l = 0; l < j; ++l) v -= x[l] * L[j][l];
-            x[j] = v / L[j][j];
+            x[j] = v * dinv[j];
         }
     }
 #pragma unroll
@@ -180,12 +182,14 @@ __global__ __launch_bounds__(256) void k_syrk_update(double* __restrict__ A, int
 // (the same small solve, redundantly), then updates its share of the remaining right-hand
 // side; workgroup 0 stores the block's solution.  A step reads only the block's right-hand
 // side and writes only the solution and the rows past the block, so workgroups never race.
-__device__ __forceinline__ void stage_diag(const double* __restrict__ dk, int nb, double (&D)[kNb][kNb + 1])
+__device__ __forceinline__ void stage_diag(const double* __restrict__ dk, int nb, double (&D)[kNb][kNb + 1],
+                                           double (&dinv)[kNb])
 {
     for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
         const int r = e / nb, c = e % nb;
         D[r][c] = c <= r ? dk[r * kNb + c] : 0.0;
     }
+    if (static_cast<int>(threadIdx.x) < nb) dinv[threadIdx.x] = 1.0 / dk[threadIdx.x * (kNb + 1)];
 }
 
 // Forward step: z_k = L_kk^-1 r_k; r_i -= L_ik z_k for rows i >= k0 + nb.
@@ -194,15 +198,16 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(const double* __restrict__ L, 
                                                   double* __restrict__ z)
 {
     __shared__ double D[kNb][kNb + 1];
+    __shared__ double dinv[kNb];
     __shared__ double xb[kNb];
     const int t = threadIdx.x;
     const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
-    stage_diag(diag + (k0 / kNb) * kNb * kNb, nb, D);
+    stage_diag(diag + (k0 / kNb) * kNb * kNb, nb, D, dinv);
     if (t < nb) xb[t] = r[k0 + t];
     __syncthreads();
     if (t < 64) {
         for (int j = 0; j < nb; ++j) {
-            const double xj = xb[j] / D[j][j];
+            const double xj = xb[j] * dinv[j];
             if (t > j && t < nb) xb[t] -= D[t][j] * xj;
             if (t == j) xb[j] = xj;
             __builtin_amdgcn_wave_barrier();
@@ -234,15 +239,16 @@ __global__ __launch_bounds__(256) void k_trsv_bwd(const double* __restrict__ L, 
                                                   double* __restrict__ x)
 {
     __shared__ double D[kNb][kNb + 1];
+    __shared__ double dinv[kNb];
     __shared__ double xb[kNb];
     const int t = threadIdx.x;
     const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
-    stage_diag(diag + (k0 / kNb) * kNb * kNb, nb, D);
+    stage_diag(diag + (k0 / kNb) * kNb * kNb, nb, D, dinv);
     if (t < nb) xb[t] = z[k0 + t];
     __syncthreads();
     if (t < 64) {
         for (int j = nb - 1; j >= 0; --j) {
-            const double xj = xb[j] / D[j][j];
+            const double xj = xb[j] * dinv[j];
             if (t < j) xb[t] -= D[j][t] * xj;
             if (t == j) xb[j] = xj;
             __builtin_amdgcn_wave_barrier();
