@@ -192,6 +192,15 @@ __device__ __forceinline__ void stage_diag(const double* __restrict__ dk, int nb
     if (static_cast<int>(threadIdx.x) < nb) dinv[threadIdx.x] = 1.0 / dk[threadIdx.x * (kNb + 1)];
 }
 
+// Value of lane `src` (wave-uniform) of a double, broadcast through scalar registers.
+__device__ __forceinline__ double lane_bcast(double v, int src)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffu), src));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), src));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 // Forward step: z_k = L_kk^-1 r_k; r_i -= L_ik z_k for rows i >= k0 + nb.
 __global__ __launch_bounds__(256) void k_trsv_fwd(const double* __restrict__ L, const double* __restrict__ diag,
                                                   int64_t m, int64_t lda, int64_t k0, double* __restrict__ r,
@@ -206,12 +215,19 @@ __global__ __launch_bounds__(256) void k_trsv_fwd(const double* __restrict__ L, 
     if (t < nb) xb[t] = r[k0 + t];
     __syncthreads();
     if (t < 64) {
-        for (int j = 0; j < nb; ++j) {
-            const double xj = xb[j] * dinv[j];
-            if (t > j && t < nb) xb[t] -= D[t][j] * xj;
-            if (t == j) xb[j] = xj;
-            __builtin_amdgcn_wave_barrier();
+        // one wave, lane t holding x_t and row t of the block: no LDS round trip per step
+        double xr = t < nb ? xb[t] : 0.0, dr[kNb];
+#pragma unroll
+        for (int c = 0; c < kNb; ++c) dr[c] = t < nb ? D[t][c] : 0.0;
+#pragma unroll
+        for (int j = 0; j < kNb; ++j) {
+            if (j < nb) {
+                const double xj = lane_bcast(xr, j) * dinv[j];
+                if (t > j) xr -= dr[j] * xj;
+                if (t == j) xr = xj;
+            }
         }
+        if (t < nb) xb[t] = xr;
     }
     __syncthreads();
     if (blockIdx.x == 0 && t < nb) z[k0 + t] = xb[t];
@@ -247,12 +263,19 @@ __global__ __launch_bounds__(256) void k_trsv_bwd(const double* __restrict__ L, 
     if (t < nb) xb[t] = z[k0 + t];
     __syncthreads();
     if (t < 64) {
-        for (int j = nb - 1; j >= 0; --j) {
-            const double xj = xb[j] * dinv[j];
-            if (t < j) xb[t] -= D[j][t] * xj;
-            if (t == j) xb[j] = xj;
-            __builtin_amdgcn_wave_barrier();
+        // one wave, lane t holding x_t and column t of the block
+        double xr = t < nb ? xb[t] : 0.0, dc[kNb];
+#pragma unroll
+        for (int c = 0; c < kNb; ++c) dc[c] = t < nb ? D[c][t] : 0.0;
+#pragma unroll
+        for (int j = kNb - 1; j >= 0; --j) {
+            if (j < nb) {
+                const double xj = lane_bcast(xr, j) * dinv[j];
+                if (t < j) xr -= dc[j] * xj;
+                if (t == j) xr = xj;
+            }
         }
+        if (t < nb) xb[t] = xr;
     }
     __syncthreads();
     if (blockIdx.x == 0 && t < nb) x[k0 + t] = xb[t];
