@@ -292,3 +292,7 @@ def test_lognormal_store_matches_exp_of_y(grf, meth, shape):
         rel = np.abs(k - want) / want
         _say(f"  mu={mu}: max rel {rel.max():.2e}")
         assert rel.max() <= 3e-7
+        # Y and K together take the per-cell stores: the same Y bits, K within the same bound
+        both = grf.field_grid(m, shape, method=meth, mu=mu, want_y=True, want_k=True)
+        np.testing.assert_array_equal(to_np(both["y"]), y)
+        assert np.max(np.abs(to_np(both["k"]).astype(np.float64) - want) / want) <= 3e-7
