@@ -101,8 +101,9 @@ __device__ __forceinline__ float exp_split(float x)
 // start at row y0 + r0 and column x0 + c0 of the plane's cells (plane + y nx + x).  A block
 // tile (BM x BN at y0, x0) that lies inside the grid and writes one FP32 output (Y or K)
 // branches once and stores through a uniform row base plus 32-bit lane offsets (K by
-// exp_split); otherwise every cell is bounds-checked and goes through epi_store.  FAST = false keeps the per-cell
-// form only (the widest per-wave tiles: their accumulators leave no registers for the other).
+// exp_split); otherwise every cell is bounds-checked and goes through epi_store.  FAST =
+// false keeps the per-cell form only (the widest per-wave tiles: their accumulators leave no
+// registers for the other).
 template <int TM, int TN, int BM, int BN, bool FAST>
 __device__ __forceinline__ void store_tiles(const SepArgs& a, const Epi& epi, int64_t plane, int64_t x0, int64_t y0,
                                             int r0, int c0, int l, const f32x16 (&acc)[TM][TN])
