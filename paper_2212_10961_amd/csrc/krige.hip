@@ -79,6 +79,15 @@ __global__ __launch_bounds__(256) void k_cov_matrix(const double* __restrict__ x
     C[i * lda + j] = c;
 }
 
+// Value of lane `src` (wave-uniform) of a double, broadcast through scalar registers.
+__device__ __forceinline__ double lane_bcast(double v, int src)
+{
+    const uint64_t b = __builtin_bit_cast(uint64_t, v);
+    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffu), src));
+    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), src));
+    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
+}
+
 // One panel step of the Cholesky factorisation: every workgroup (one wave) factors the
 // diagonal block [k0, k0 + nb) itself, unblocked, from A (lane r keeps row r in registers;
 // column j goes through LDS for the rank-1 update), then solves its panel rows
@@ -102,17 +111,20 @@ __global__ __launch_bounds__(64) void k_potrf_trsm(double* __restrict__ A, int64
     for (int j = 0; j < kNb; ++j) {
         if (j < nb) {
             // pivot of column j, from lane j
-            const double d = __shfl(row[j], j, 64);
+            const double d = lane_bcast(row[j], j);
             const double sd = d > 0.0 ? sqrt(d) : __builtin_nan("");
             if (!(d > 0.0) && bad == 0) bad = static_cast<int>(k0 + j + 1);
             if (r == j) row[j] = sd;
             if (r > j && r < nb) row[j] /= sd;
             if (r < kNb) col[r] = row[j];
-            __syncthreads();
+            // the workgroup is one wave, whose LDS accesses complete in program order: a
+            // compiler barrier orders the column's stores before the reads and the reads before
+            // the next column's stores
+            __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int c = j + 1; c < kNb; ++c)
                 if (c <= r && r < nb) row[c] -= row[j] * col[c];
-            __syncthreads();
+            __builtin_amdgcn_wave_barrier();
         }
     }
     if (r < kNb) {
@@ -190,15 +202,6 @@ __device__ __forceinline__ void stage_diag(const double* __restrict__ dk, int nb
         D[r][c] = c <= r ? dk[r * kNb + c] : 0.0;
     }
     if (static_cast<int>(threadIdx.x) < nb) dinv[threadIdx.x] = 1.0 / dk[threadIdx.x * (kNb + 1)];
-}
-
-// Value of lane `src` (wave-uniform) of a double, broadcast through scalar registers.
-__device__ __forceinline__ double lane_bcast(double v, int src)
-{
-    const uint64_t b = __builtin_bit_cast(uint64_t, v);
-    const uint32_t lo = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(b & 0xffffffffu), src));
-    const uint32_t hi = static_cast<uint32_t>(__builtin_amdgcn_readlane(static_cast<int>(b >> 32), src));
-    return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
 }
 
 // Forward step: z_k = L_kk^-1 r_k; r_i -= L_ik z_k for rows i >= k0 + nb.
