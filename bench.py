@@ -19,6 +19,7 @@ import json
 import math
 import os
 import sys
+import tempfile
 import time
 from pathlib import Path
 
@@ -443,8 +444,9 @@ def batch_extra(grf, wl, torch, np, dev):
                                             for m, shape, y in items], 3, 1)
     res["sep_f16_separate_calls"] = {"ms_per_batch": sep_ms, "mode_cells_per_s": total * 2048 / (sep_ms * 1e-3)}
     for meth in ("sep_f16", "direct_f32"):
+        # tuned tile choices persist in a per-user cache file between runs
         plan = grf.Plan(meth, graph=True, autotune=True,
-                        tune_cache=str(ROOT / "gpurun_out" / "tune_cache.txt") if (ROOT / "gpurun_out").exists() else None)
+                        tune_cache=os.path.join(tempfile.gettempdir(), "grf_tune_cache.txt"))
         steps = 10 if meth.startswith("sep") else 2
         ms, kms = _timed(torch, grf, lambda: plan.run(items), steps, 2)
         res[meth] = {"ms_per_batch": ms, "persistent_kernel_ms": kms, "mode_cells_per_s": total * 2048 / (ms * 1e-3),
