@@ -88,24 +88,13 @@ __device__ __forceinline__ double lane_bcast(double v, int src)
     return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
 }
 
-// One panel step of the Cholesky factorisation: every workgroup (one wave) factors the
-// diagonal block [k0, k0 + nb) itself, unblocked, from A (lane r keeps row r in registers;
-// column j goes through LDS for the rank-1 update), then solves its panel rows
-// i >= k0 + nb: L[i][k0 ..] = A[i][k0 ..] L_kk^-T.  A's diagonal block is only read, so the
-// redundant factorisations never race; workgroup 0 stores the factor in `dk` (32 x 32,
-// row-major) and the first non-positive pivot (1-based) in `info` (the factor then carries
-// NaN).
-__global__ __launch_bounds__(64) void k_potrf_trsm(double* __restrict__ A, int64_t m, int64_t lda, int64_t k0,
-                                                  double* __restrict__ dk, int32_t* __restrict__ info)
+// Unblocked factorisation of an nb x nb diagonal block by one wave: lane r holds row r
+// (entries c <= r) in `row` on entry and the factor's row on exit; column j goes through the
+// LDS scratch `col` for the rank-1 update.  Returns the first non-positive pivot (1-based,
+// counted from the matrix's first row via k0) or 0; the factor then carries NaN.
+__device__ __forceinline__ int factor_block(double (&row)[kNb], int nb, int64_t k0, double* col)
 {
-    __shared__ double col[kNb];
-    __shared__ double L[kNb][kNb + 1];
-    __shared__ double dinv[kNb];
-    const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
     const int r = threadIdx.x;
-    double row[kNb];
-#pragma unroll
-    for (int c = 0; c < kNb; ++c) row[c] = (r < nb && c <= r) ? A[(k0 + r) * lda + k0 + c] : 0.0;
     int bad = 0;
 #pragma unroll
     for (int j = 0; j < kNb; ++j) {
@@ -117,9 +106,9 @@ __global__ __launch_bounds__(64) void k_potrf_trsm(double* __restrict__ A, int64
             if (r == j) row[j] = sd;
             if (r > j && r < nb) row[j] /= sd;
             if (r < kNb) col[r] = row[j];
-            // the workgroup is one wave, whose LDS accesses complete in program order: a
-            // compiler barrier orders the column's stores before the reads and the reads before
-            // the next column's stores
+            // one wave, whose LDS accesses complete in program order: a compiler barrier
+            // orders the column's stores before the reads and the reads before the next
+            // column's stores
             __builtin_amdgcn_wave_barrier();
 #pragma unroll
             for (int c = j + 1; c < kNb; ++c)
@@ -127,17 +116,47 @@ __global__ __launch_bounds__(64) void k_potrf_trsm(double* __restrict__ A, int64
             __builtin_amdgcn_wave_barrier();
         }
     }
-    if (r < kNb) {
-#pragma unroll
-        for (int c = 0; c < kNb; ++c) L[r][c] = c <= r ? row[c] : 0.0;
-    }
-    if (blockIdx.x == 0) {
-        if (r == 0 && bad && info && *info == 0) *info = bad;
+    return bad;
+}
+
+// One panel step of the Cholesky factorisation, one wave per workgroup: the factor L_kk of
+// the diagonal block [k0, k0 + nb) is either made here (first panel: every workgroup factors
+// the block itself, workgroup 0 stores it in `dk` (32 x 32, row-major) and the first
+// non-positive pivot in `info`) or read from `dk`, where the preceding trailing update left
+// it; then each workgroup solves its panel rows i >= k0 + nb: L[i][k0 ..] = A[i][k0 ..]
+// L_kk^-T.  A's diagonal block is only read, so the redundant factorisations never race.
+__global__ __launch_bounds__(64) void k_potrf_trsm(double* __restrict__ A, int64_t m, int64_t lda, int64_t k0,
+                                                  double* __restrict__ dk, int32_t* __restrict__ info,
+                                                  int prefactored)
+{
+    __shared__ double col[kNb];
+    __shared__ double L[kNb][kNb + 1];
+    __shared__ double dinv[kNb];
+    const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
+    const int r = threadIdx.x;
+    if (prefactored) {
         if (r < kNb) {
 #pragma unroll
-            for (int c = 0; c < kNb; ++c) dk[r * kNb + c] = L[r][c];
+            for (int c = 0; c < kNb; ++c) L[r][c] = dk[r * kNb + c];
+        }
+    } else {
+        double row[kNb];
+#pragma unroll
+        for (int c = 0; c < kNb; ++c) row[c] = (r < nb && c <= r) ? A[(k0 + r) * lda + k0 + c] : 0.0;
+        const int bad = factor_block(row, nb, k0, col);
+        if (r < kNb) {
+#pragma unroll
+            for (int c = 0; c < kNb; ++c) L[r][c] = c <= r ? row[c] : 0.0;
+        }
+        if (blockIdx.x == 0) {
+            if (r == 0 && bad && info && *info == 0) *info = bad;
+            if (r < kNb) {
+#pragma unroll
+                for (int c = 0; c < kNb; ++c) dk[r * kNb + c] = L[r][c];
+            }
         }
     }
+    __syncthreads();
     if (r < nb) dinv[r] = 1.0 / L[r][r];  // the substitution below multiplies by reciprocals
     __syncthreads();
     const int64_t i = k0 + nb + static_cast<int64_t>(blockIdx.x) * blockDim.x + r;
@@ -159,10 +178,16 @@ __global__ __launch_bounds__(64) void k_potrf_trsm(double* __restrict__ A, int64
 
 // Trailing update A[i][j] -= sum_l L[i][l] L[j][l] over the panel columns [k0, k0 + nb), for
 // rows and columns past the panel, lower triangle; 32 x 32 output tiles, 4 entries per thread.
-__global__ __launch_bounds__(256) void k_syrk_update(double* __restrict__ A, int64_t m, int64_t lda, int64_t k0)
+// The workgroup of tile (0, 0), which updates the next panel's diagonal block, then factors
+// it (its first wave, from the updated values kept in LDS) into `dk_next` and records a
+// non-positive pivot in `info`: the next panel step reads the factor instead of making it.
+__global__ __launch_bounds__(256) void k_syrk_update(double* __restrict__ A, int64_t m, int64_t lda, int64_t k0,
+                                                     double* __restrict__ dk_next, int32_t* __restrict__ info)
 {
     __shared__ double Li[32][kNb + 1];
     __shared__ double Lj[32][kNb + 1];
+    __shared__ double T[kNb][kNb + 1];
+    __shared__ double colbuf[kNb];
     const int64_t s0 = k0 + kNb;  // first trailing row/column (only called when a full panel precedes it)
     const int64_t ti = blockIdx.y, tj = blockIdx.x;
     if (tj > ti) return;
@@ -182,10 +207,31 @@ __global__ __launch_bounds__(256) void k_syrk_update(double* __restrict__ A, int
         for (int q = 0; q < 4; ++q) acc[q] += Li[r0 + 8 * q][l] * b;
     }
     const int64_t j = j0 + c;
+    const bool diag_tile = ti == 0 && tj == 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const int64_t i = i0 + r0 + 8 * q;
-        if (i < m && j < m && j <= i) A[i * lda + j] -= acc[q];
+        if (i < m && j < m && j <= i) {
+            const double v = A[i * lda + j] - acc[q];
+            A[i * lda + j] = v;
+            if (diag_tile) T[r0 + 8 * q][c] = v;
+        }
+    }
+    if (diag_tile) {
+        __syncthreads();
+        if (threadIdx.x < 64) {
+            const int nbn = static_cast<int>(min<int64_t>(kNb, m - s0));
+            const int r = threadIdx.x;
+            double row[kNb];
+#pragma unroll
+            for (int cc = 0; cc < kNb; ++cc) row[cc] = (r < nbn && cc <= r) ? T[r][cc] : 0.0;
+            const int bad = factor_block(row, nbn, s0, colbuf);
+            if (r == 0 && bad && info && *info == 0) *info = bad;
+            if (r < kNb) {
+#pragma unroll
+                for (int cc = 0; cc < kNb; ++cc) dk_next[r * kNb + cc] = cc <= r ? row[cc] : 0.0;
+            }
+        }
     }
 }
 
@@ -384,12 +430,14 @@ hipError_t launch_cholesky(double* A, int64_t m, int64_t lda, double* diag, int3
     for (int64_t k0 = 0; k0 < m; k0 += kNb) {
         const int64_t rest = m - k0 - kNb;
         const unsigned blocks = static_cast<unsigned>(rest > 0 ? (rest + 63) / 64 : 1);
+        // the first panel factors its diagonal block; later ones take the factor that the
+        // preceding trailing update made
         hipLaunchKernelGGL(k_potrf_trsm, dim3(blocks), dim3(64), 0, s, A, m, lda, k0, diag + (k0 / kNb) * kNb * kNb,
-                           info);
+                           info, k0 > 0 ? 1 : 0);
         if (rest <= 0) break;
         const int64_t tiles = (rest + 31) / 32;
         hipLaunchKernelGGL(k_syrk_update, dim3(static_cast<unsigned>(tiles), static_cast<unsigned>(tiles)), dim3(256),
-                           0, s, A, m, lda, k0);
+                           0, s, A, m, lda, k0, diag + (k0 / kNb + 1) * kNb * kNb, info);
         const hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
