@@ -65,17 +65,21 @@ extern "C" {
 #define GRF_MAX_FACIES 64
 
 /* Generator options (App. B dictionary: correlation, Kmean, Ksigma, Lcorr, nu, nfreq,
- * disableY/disableZ as dim). */
+ * disableY/disableZ as dim).  make_modes reads dim, cov, n_modes, seed and nu (the
+ * standardised table does not depend on the scalars); grf_modes_init reads dim, n_modes,
+ * sigma2, ell and len_convention; mu is the caller's grf_epi.mu. */
 typedef struct grf_spec {
     int32_t dim;            /* 2 or 3 */
     int32_t cov;            /* GRF_COV_* */
-    double sigma2;          /* variance of Y (of ln K), > 0 */
-    double mu;              /* mean of ln K (used by the caller's epilogue) */
+    double sigma2;          /* variance of Y (of ln K), >= 0 */
+    double mu;              /* mean of ln K (copied by the caller into grf_epi.mu) */
     double ell[3];          /* correlation lengths per axis, > 0 (ell[2] ignored for dim 2) */
     int64_t n_modes;        /* N >= 1 */
     uint64_t seed;          /* Philox4x32-10 key */
-    int32_t len_convention; /* 0: ell as above; 1: Gaussian ell given as the paper's lambda,
-                               converted by ell = 2 lambda / sqrt(pi) (eq. gauSpe) */
+    int32_t len_convention; /* 0: ell as above; 1: ell given as the paper's length lambda:
+                               Gaussian ell = 2 lambda / sqrt(pi) (eq. gauSpe writes the
+                               correlation as exp(-(pi/4)(r/lambda)^2)); the exponential and
+                               Matern forms take lambda as ell unchanged */
     double nu;              /* Matern smoothness; 2*nu must be an integer in [1, 64] */
 } grf_spec;
 
@@ -133,6 +137,17 @@ const char* grf_last_error(void);
  * shorter table.  Does not touch the GPU.
  */
 int make_modes(const grf_spec* spec, double* z_out, double* phi_out);
+
+/*
+ * grf_modes_init -- the grf_modes descriptor of a table drawn for `spec`: dim, n = n_modes,
+ * sigma = sqrt(sigma2), ell per axis after the len_convention conversion (ell[a] = 1 for
+ * a >= dim), axis-aligned (rotated = 0, rot = I), no weights (w = NULL).
+ *   spec  host; validated (dim, cov, n_modes >= 1, sigma2 finite and >= 0, ell[a < dim]
+ *         finite and > 0, len_convention 0 or 1).
+ *   z, phi  the table's device arrays ([dim][n_modes], [n_modes]); stored, not read.
+ *   out   host, written only on success.  Pure host code; does not touch the GPU.
+ */
+int grf_modes_init(const grf_spec* spec, const double* z, const double* phi, grf_modes* out);
 
 /*
  * make_modes_lattice -- the fixed-frequency, Gaussian-weight form of Sec. 4.1 eq. DiscreteFT
@@ -372,8 +387,12 @@ int krige_apply_points(const grf_modes* modes, const grf_krige* kp, const double
 typedef struct grf_batch_item {
     grf_modes modes; /* per-instance mode table (device) and scalars */
     grf_grid grid;   /* dim 2 or 3 grid */
-    float* y;        /* device float[cells of this grid] */
-} grf_batch_item;
+    grf_epi epi;     /* per-instance epilogue (Sec. 4.1 scaling, Sec. 3.1 truncation rule):
+                        read for k (mu) and ind (thresholds, at least one when ind != NULL) */
+    float* y;        /* device float[cells of this grid] or NULL */
+    float* k;        /* device float[cells]: K = exp(mu + Y), or NULL */
+    uint8_t* ind;    /* device uint8[cells]: facies index #{i : t_i < Y}, or NULL */
+} grf_batch_item;   /* at least one of y, k, ind per item */
 
 typedef struct grf_plan grf_plan;
 
@@ -394,10 +413,13 @@ int grf_plan_destroy(grf_plan* plan);
 
 /*
  * eval_field_batch -- evaluate n items.  items is a host array; each item's outputs
- * receive exactly what eval_field_grid(method) would write for y.  The first call with a
- * new batch signature (sizes, pointers, method) builds descriptors, tunes if asked and
- * captures the graph; later calls with the same signature replay it.  Calls on one plan
- * must not overlap (they share the plan's device memory).
+ * receive what eval_field_grid(method, &item.epi, y, k, ind) would write (bitwise for the
+ * direct method and the hi+lo forms with the same tile shape; the 2-D one-pass forms
+ * generate their operands on chip and agree within the method's rounding).  The first call
+ * with a new batch signature (sizes, scalars, table, weight and output pointers, epilogue,
+ * method) builds descriptors, tunes if asked and captures the graph; later calls with the
+ * same signature replay it, reading the tables' current contents.  Calls on one plan must
+ * not overlap (they share the plan's device memory).
  */
 int eval_field_batch(grf_plan* plan, const grf_batch_item* items, int32_t n, void* stream);
 

@@ -98,6 +98,8 @@ def _load():
                                           ctypes.c_double, ctypes.c_uint64, d, d, d, d, d]
         lib.orc_lattice_modes.restype = i64
         lib.orc_field_points_w.argtypes = [ctypes.c_int, i64, d, d, d, ctypes.c_double, d, i64, d, d]
+        lib.orc_grad_points_w.argtypes = [ctypes.c_int, i64, d, d, d, ctypes.c_double, d, i64, d, d,
+                                          d, d, d, d]
         _lib = lib
     return _lib
 
@@ -396,6 +398,25 @@ def field_points_w(z, phi, w, sigma, ell, x):
     lib.orc_field_points_w(dim, n, _dp(z), _dp(phi), _dp(w), float(sigma), _dp(_ell(ell, dim)), x.shape[0],
                            _dp(x), _dp(y))
     return y
+
+
+def grad_points_w(z, phi, w, sigma, ell, x, g):
+    """Exact gradients through the weighted sum of field_points_w (weights held fixed), given
+    g = dL/dY at points x.  Returns dict with dphi[n], dk[dim][n], dsigma, dell[dim]."""
+    lib = _load()
+    z = _f64(z)
+    phi = _f64(phi)
+    w = _f64(w)
+    dim, n = z.shape
+    x = _f64(x).reshape(-1, dim)
+    g = _f64(g)
+    dphi = np.empty(n)
+    dk = np.empty((dim, n))
+    dsig = np.empty(1)
+    dell = np.empty(3)
+    lib.orc_grad_points_w(dim, n, _dp(z), _dp(phi), _dp(w), float(sigma), _dp(_ell(ell, dim)), x.shape[0],
+                          _dp(x), _dp(g), _dp(dphi), _dp(dk), _dp(dsig), _dp(dell))
+    return {"dphi": dphi, "dk": dk, "dsigma": float(dsig[0]), "dell": dell[:dim].copy()}
 
 
 def correlation(cov: int, r, nu: float = 0.5):

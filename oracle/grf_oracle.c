@@ -562,3 +562,45 @@ void orc_field_points_w(int dim, int64_t n, const double* z, const double* phi, 
         y[p] = amp * s;
     }
 }
+
+/*
+ * Gradients through the weighted random-phase sum of orc_field_points_w (the fixed-frequency
+ * form of Sec. 4.1 eq. DiscreteFT), given g[p] = dL/dY_p.  With theta_jp = k_j . x_p + phi_j,
+ * k = z / ell and amp = sigma sqrt(2/N), the weights w held fixed:
+ *   dL/dphi_j   = -amp w_j sum_p g_p sin theta_jp
+ *   dL/dk_{a,j} = -amp w_j sum_p g_p x_{p,a} sin theta_jp
+ *   dL/dsigma   = sum_p g_p Y_p / sigma                         (Y of the weighted sum)
+ *   dL/dell_a   = sum_j dL/dk_{a,j} * (-z_{a,j} / ell_a^2)
+ */
+void orc_grad_points_w(int dim, int64_t n, const double* z, const double* phi, const double* w, double sigma,
+                       const double* ell, int64_t P, const double* x, const double* g,
+                       double* dphi, double* dk, double* dsigma, double* dell)
+{
+    double amp = sigma * sqrt(2.0 / (double)n);
+    double* y = (double*)malloc(sizeof(double) * (size_t)(P > 0 ? P : 1));
+    orc_field_points_w(dim, n, z, phi, w, sigma, ell, P, x, y);
+    double ds = 0.0;
+    for (int64_t p = 0; p < P; ++p) ds += g[p] * y[p];
+    *dsigma = ds / sigma;
+    free(y);
+
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < n; ++j) {
+        double s = 0.0, u[3] = {0.0, 0.0, 0.0};
+        for (int64_t p = 0; p < P; ++p) {
+            const double* xp = x + p * dim;
+            double th = phi[j];
+            for (int a = 0; a < dim; ++a) th += z[a * n + j] / ell[a] * xp[a];
+            double sn = sin(th);
+            s += g[p] * sn;
+            for (int a = 0; a < dim; ++a) u[a] += g[p] * xp[a] * sn;
+        }
+        dphi[j] = -amp * w[j] * s;
+        for (int a = 0; a < dim; ++a) dk[a * n + j] = -amp * w[j] * u[a];
+    }
+    for (int a = 0; a < dim; ++a) {
+        double acc = 0.0;
+        for (int64_t j = 0; j < n; ++j) acc += dk[a * n + j] * (-z[a * n + j] / (ell[a] * ell[a]));
+        dell[a] = acc;
+    }
+}

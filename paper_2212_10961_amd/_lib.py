@@ -27,7 +27,7 @@ METHODS = {
 
 # Every symbol include/grf.h declares.
 EXPORTS = [
-    "grf_version", "grf_last_error", "make_modes", "make_modes_lattice", "snap_periodic", "eval_field_grid_ws_size", "eval_field_grid",
+    "grf_version", "grf_last_error", "make_modes", "grf_modes_init", "make_modes_lattice", "snap_periodic", "eval_field_grid_ws_size", "eval_field_grid",
     "eval_field_grid_tile", "grf_sep_tile_count", "grf_sep_tile_shape",
     "eval_pluri_grid_ws_size", "eval_pluri_grid", "eval_pluri_points_ws_size", "eval_pluri_points", "pluri_apply",
     "krige_weights_ws_size", "krige_weights", "krige_apply_ws_size", "krige_apply_grid", "krige_apply_points",
@@ -74,7 +74,8 @@ class GrfKrige(ctypes.Structure):
 
 
 class GrfBatchItem(ctypes.Structure):
-    _fields_ = [("modes", GrfModes), ("grid", GrfGrid), ("y", ctypes.c_void_p)]
+    _fields_ = [("modes", GrfModes), ("grid", GrfGrid), ("epi", GrfEpi), ("y", ctypes.c_void_p),
+                ("k", ctypes.c_void_p), ("ind", ctypes.c_void_p)]
 
 
 _lib = None
@@ -101,6 +102,7 @@ def load():
         "grf_version": ([], ctypes.c_int),
         "grf_last_error": ([], ctypes.c_char_p),
         "make_modes": ([P(GrfSpec), vp, vp], ctypes.c_int),
+        "grf_modes_init": ([P(GrfSpec), vp, vp, P(GrfModes)], ctypes.c_int),
         "snap_periodic": ([ctypes.c_int, i64, vp, vp, vp, vp, vp], ctypes.c_int),
         "make_modes_lattice": ([P(GrfSpec), i32, ctypes.c_double, vp, vp, vp], ctypes.c_int),
         "eval_field_grid_ws_size": ([P(GrfModes), P(GrfGrid), ctypes.c_int, P(sz)], ctypes.c_int),

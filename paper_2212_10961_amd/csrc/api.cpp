@@ -130,7 +130,7 @@ int check_grid(const grf_grid* g, int dim, const char* fn)
     return GRF_OK;
 }
 
-static int check_epi(const grf_epi* e, const float* k, const uint8_t* ind, const char* fn)
+int check_epi(const grf_epi* e, const float* k, const uint8_t* ind, const char* fn)
 {
     if ((k || ind) && !e) return fail(GRF_EINVAL, "%s: epi is NULL but k or ind requested", fn);
     if (e && (e->n_thresholds < 0 || e->n_thresholds > GRF_MAX_THRESHOLDS))
@@ -371,7 +371,7 @@ static int check_grid_method(const char* fn, const grf_grid* grid, int* method, 
     return GRF_OK;
 }
 
-static int grid_eval(const char* fn, const grf_modes* modes, const grf_grid* grid, int method, int tile,
+int grid_eval(const char* fn, const grf_modes* modes, const grf_grid* grid, int method, int tile,
                      const grf_epi* epi, float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes, void* stream)
 {
     int rc;

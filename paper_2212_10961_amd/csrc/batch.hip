@@ -127,7 +127,7 @@ void push_bits(std::vector<uint64_t>& s, double d)
 std::vector<uint64_t> signature(const grf_plan* p, const grf_batch_item* items, int32_t n)
 {
     std::vector<uint64_t> s;
-    s.reserve(static_cast<size_t>(n) * 20 + 2);
+    s.reserve(static_cast<size_t>(n) * 26 + 2);
     s.push_back(static_cast<uint64_t>(p->method));
     s.push_back(static_cast<uint64_t>(n));
     for (int32_t i = 0; i < n; ++i) {
@@ -143,7 +143,20 @@ std::vector<uint64_t> signature(const grf_plan* p, const grf_batch_item* items, 
             push_bits(s, it.grid.origin[a]);
             push_bits(s, it.grid.h[a]);
         }
+        s.push_back(reinterpret_cast<uint64_t>(it.modes.w));
+        s.push_back(static_cast<uint64_t>(it.modes.rotated));
         s.push_back(reinterpret_cast<uint64_t>(it.y));
+        s.push_back(reinterpret_cast<uint64_t>(it.k));
+        s.push_back(reinterpret_cast<uint64_t>(it.ind));
+        // the epilogue is baked into the captured descriptors: every field that enters it
+        uint32_t mu;
+        std::memcpy(&mu, &it.epi.mu, sizeof(mu));
+        s.push_back((static_cast<uint64_t>(static_cast<uint32_t>(it.epi.n_thresholds)) << 32) | mu);
+        for (int q = 0; q < it.epi.n_thresholds && q < GRF_MAX_THRESHOLDS; ++q) {
+            uint32_t t;
+            std::memcpy(&t, &it.epi.thresholds[q], sizeof(t));
+            s.push_back(t);
+        }
     }
     return s;
 }
@@ -273,6 +286,9 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
             d.tz = static_cast<const float*>(ws[i].t[2]);
             d.w = it.modes.w;
             d.y = it.y;
+            d.k = it.k;
+            d.ind = it.ind;
+            d.epi = make_epi(&it.epi);
             d.ldp = padded_modes(it.modes.n);
             d.nq = it.grid.n[1] * it.grid.n[2];
             d.n = static_cast<int32_t>(it.modes.n);
@@ -307,7 +323,10 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
             a.qy_lo = ws[i].tlo[1];
             a.ez = p->d3 ? static_cast<const float2*>(ws[i].t[2]) : nullptr;
             a.amp = static_cast<float>(it.modes.sigma * std::sqrt(2.0 / static_cast<double>(it.modes.n)));
+            a.epi = make_epi(&it.epi);
             a.y = it.y;
+            a.k = it.k;
+            a.ind = it.ind;
             a.tile = -1;
             GenArgs& g = si[i].g;
             g = GenArgs{};
@@ -514,7 +533,8 @@ int eval_field_batch(grf_plan* p, const grf_batch_item* items, int32_t n, void* 
         int rc;
         if ((rc = check_modes(&items[i].modes, fn))) return rc;
         if ((rc = check_grid(&items[i].grid, items[i].modes.dim, fn))) return rc;
-        if (!items[i].y) return fail(GRF_EINVAL, "%s: item %d has no output", fn, i);
+        if (!items[i].y && !items[i].k && !items[i].ind) return fail(GRF_EINVAL, "%s: item %d has no output", fn, i);
+        if ((rc = check_epi(&items[i].epi, items[i].k, items[i].ind, fn))) return rc;
         if (items[i].modes.rotated)
             return fail(GRF_EUNSUPPORTED, "%s: item %d: rotated tables are not batched (pass k = rot diag(1/ell) z "
                         "as an axis-aligned table with ell = 1)", fn, i);

@@ -34,8 +34,6 @@ constexpr int kDgRow = (kDgJ + 4) / 4;  // float4 per padded row
 static_assert(kDgB == kDirectTile, "tile side shared with the batch planner");
 
 // One 64 x 64 (x, (y,z)) tile; `sx`, `sq` are LDS arrays of kDgB * kDgRow float4.  Whole block.
-// Without EPI only Y is stored (batched ensembles).
-template <bool EPI>
 __device__ __forceinline__ void direct_tile(const float* __restrict__ tx, const float* __restrict__ ty,
                                             const float* __restrict__ tz, const double* __restrict__ wt, int n,
                                             int64_t ldp, int nx, int ny, int64_t nq, int x0, int64_t q0, float amp,
@@ -116,8 +114,7 @@ __device__ __forceinline__ void direct_tile(const float* __restrict__ tx, const 
         for (int b = 0; b < 4; ++b) {
             const int64_t q = q0 + lq + 4 * b;
             if (x < nx && q < nq) {
-                if constexpr (EPI) store_out(q * nx + x, amp * acc[a][b], epi, y, k, ind);
-                else y[q * nx + x] = amp * acc[a][b];
+                store_out(q * nx + x, amp * acc[a][b], epi, y, k, ind);
             }
         }
     }
@@ -133,7 +130,7 @@ __global__ __launch_bounds__(256, 2) void k_direct_grid(const float* __restrict_
     __shared__ float4 sq[kDgB * kDgRow];
     __shared__ float4 sw[kDgJ / 4];
     const int64_t bid = blockIdx.x;
-    direct_tile<true>(tx, ty, tz, wt, n, ldp, nx, ny, nq, static_cast<int>(bid % nxt) * kDgB, (bid / nxt) * kDgB, amp,
+    direct_tile(tx, ty, tz, wt, n, ldp, nx, ny, nq, static_cast<int>(bid % nxt) * kDgB, (bid / nxt) * kDgB, amp,
                       epi, y, k, ind, sx, sq, sw);
 }
 
@@ -160,8 +157,8 @@ __global__ __launch_bounds__(256, 2) void k_direct_batch(const DirectBatchItem* 
         }
         const DirectBatchItem& b = items[lo];
         const int64_t local = it - b.item0;
-        direct_tile<false>(b.tx, b.ty, b.tz, b.w, b.n, b.ldp, b.nx, b.ny, b.nq, static_cast<int>(local % b.nxt) * kDgB,
-                           (local / b.nxt) * kDgB, b.amp, Epi{}, b.y, nullptr, nullptr, sx, sq, sw);
+        direct_tile(b.tx, b.ty, b.tz, b.w, b.n, b.ldp, b.nx, b.ny, b.nq, static_cast<int>(local % b.nxt) * kDgB,
+                    (local / b.nxt) * kDgB, b.amp, b.epi, b.y, b.k, b.ind, sx, sq, sw);
     }
 }
 

@@ -25,6 +25,8 @@ int fail_hip(hipError_t e, const char* what);
 // ---------------------------------------------------------------- validation (host)
 int check_modes(const grf_modes* m, const char* fn);
 int check_grid(const grf_grid* g, int dim, const char* fn);
+// Epilogue of a call: required when k or ind is written; ind needs a threshold; ascending.
+int check_epi(const grf_epi* e, const float* k, const uint8_t* ind, const char* fn);
 // Axis-aligned view of a table (a rotated table's k written to kbuf; see grf_modes).
 hipError_t aligned_modes(const grf_modes* m, void* kbuf, hipStream_t s, grf_modes* out);
 inline bool is_sep(int m) { return m >= GRF_SEP_BF16 && m <= GRF_SEP_F16_X3; }
@@ -162,6 +164,9 @@ struct GridWs {
     size_t bytes = 0;
 };
 GridWs grid_ws(const grf_modes* m, const grf_grid* g, int method, void* base);
+// eval_field_grid(_tile) after the entry point's name: validation, then tables and sum in `ws`.
+int grid_eval(const char* fn, const grf_modes* modes, const grf_grid* grid, int method, int tile,
+              const grf_epi* epi, float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes, void* stream);
 int grid_table_descs(const grf_modes* m, const grf_grid* g, int method, const GridWs& w, AxisTableArgs* out);
 
 // Rotated tables: out[a * n + j] = sum_b rot[3a + b] z[b * n + j] / ell[b] (device, FP64).
@@ -272,7 +277,10 @@ struct DirectBatchItem {
     const float* ty;
     const float* tz;
     const double* w;  // per-mode weights or nullptr
-    float* y;
+    float* y;         // outputs of the instance, each may be nullptr
+    float* k;
+    uint8_t* ind;
+    Epi epi;
     int64_t ldp;
     int64_t nq;       // ny * nz
     int64_t item0;

@@ -232,3 +232,38 @@ extern "C" int make_modes_lattice(const grf_spec* spec, int32_t m, double du, do
     }
     return GRF_OK;
 }
+
+extern "C" int grf_modes_init(const grf_spec* spec, const double* z, const double* phi, grf_modes* out)
+{
+    using grf::fail;
+    if (!spec || !out) return fail(GRF_EINVAL, "grf_modes_init: spec or out is NULL");
+    if (spec->dim != 2 && spec->dim != 3)
+        return fail(GRF_EINVAL, "grf_modes_init: dim must be 2 or 3 (got %d)", spec->dim);
+    if (spec->n_modes < 1) return fail(GRF_EINVAL, "grf_modes_init: n_modes must be >= 1");
+    if (spec->cov < GRF_COV_GAUSSIAN || spec->cov > GRF_COV_MATERN)
+        return fail(GRF_EINVAL, "grf_modes_init: unknown covariance %d", spec->cov);
+    if (!(spec->sigma2 >= 0.0) || !std::isfinite(spec->sigma2))
+        return fail(GRF_EINVAL, "grf_modes_init: sigma2 must be finite and >= 0");
+    if (spec->len_convention != 0 && spec->len_convention != 1)
+        return fail(GRF_EINVAL, "grf_modes_init: len_convention must be 0 or 1 (got %d)", spec->len_convention);
+    for (int a = 0; a < spec->dim; ++a)
+        if (!(spec->ell[a] > 0.0) || !std::isfinite(spec->ell[a]))
+            return fail(GRF_EINVAL, "grf_modes_init: ell[%d] must be finite and > 0", a);
+    if (!z || !phi) return fail(GRF_EINVAL, "grf_modes_init: z or phi is NULL");
+    // The Gaussian correlation written with the integral scale lambda, exp(-(pi/4)(r/lambda)^2)
+    // (eq. gauSpe), is exp(-r^2/ell^2) with ell = 2 lambda / sqrt(pi); the exponential and
+    // Matern forms use lambda as the length itself.
+    const double scale = (spec->len_convention == 1 && spec->cov == GRF_COV_GAUSSIAN) ? 2.0 / std::sqrt(M_PI) : 1.0;
+    grf_modes m{};
+    m.dim = spec->dim;
+    m.n = spec->n_modes;
+    m.z = z;
+    m.phi = phi;
+    m.sigma = std::sqrt(spec->sigma2);
+    for (int a = 0; a < 3; ++a) m.ell[a] = a < spec->dim ? scale * spec->ell[a] : 1.0;
+    m.rotated = 0;
+    m.rot[0] = m.rot[4] = m.rot[8] = 1.0;
+    m.w = nullptr;
+    *out = m;
+    return GRF_OK;
+}

@@ -25,7 +25,7 @@ from . import _lib as L
 from ._lib import GrfError, check
 
 __all__ = [
-    "Modes", "make_modes", "modes_from_tables", "field_grid", "field_grid_f64", "field_points",
+    "Modes", "make_modes", "modes_from_spec", "modes_from_tables", "field_grid", "field_grid_f64", "field_points",
     "epilogue", "field_backward", "field_backward_grid", "GRFPoints", "Plan", "method_id", "sep_tiles",
     "trunc2", "pluri_grid", "pluri_points", "pluri_apply", "snap_periodic", "make_modes_lattice",
     "krige_weights", "krige_apply_grid", "krige_apply_points", "condition_grid", "condition_points",
@@ -135,6 +135,28 @@ def make_modes(dim: int, cov: int, n_modes: int, seed: int, nu: float = 0.5):
     phi = np.empty(n_modes, dtype=np.float64)
     check(L.load().make_modes(ctypes.byref(spec), z.ctypes.data, phi.ctypes.data))
     return z, phi
+
+
+def modes_from_spec(dim: int, cov: int, n_modes: int, seed: int, sigma2: float, ell, len_convention: int = 0,
+                    nu: float = 0.5, device="cuda") -> Modes:
+    """Draw a table with the library's sampler and describe it by grf_modes_init: sigma =
+    sqrt(sigma2), and ell converted from the paper's length lambda when len_convention = 1."""
+    spec = L.GrfSpec()
+    spec.dim, spec.cov, spec.n_modes, spec.seed, spec.nu = dim, cov, n_modes, seed, float(nu)
+    spec.sigma2 = float(sigma2)
+    e = [float(v) for v in ell] + [1.0] * (3 - len(ell))
+    spec.ell = (ctypes.c_double * 3)(*e[:3])
+    spec.len_convention = int(len_convention)
+    lib = L.load()
+    z = np.empty((dim, n_modes), dtype=np.float64)
+    phi = np.empty(n_modes, dtype=np.float64)
+    check(lib.make_modes(ctypes.byref(spec), z.ctypes.data, phi.ctypes.data))
+    zt = torch.as_tensor(z).to(device).contiguous()
+    pt = torch.as_tensor(phi).to(device).contiguous()
+    m = L.GrfModes()
+    check(lib.grf_modes_init(ctypes.byref(spec), ctypes.c_void_p(zt.data_ptr()), ctypes.c_void_p(pt.data_ptr()),
+                             ctypes.byref(m)))
+    return Modes(zt, pt, m.sigma, [m.ell[a] for a in range(dim)])
 
 
 def modes_from_tables(z, phi, sigma: float, ell, device="cuda", rot=None, w=None) -> Modes:
@@ -572,20 +594,37 @@ class Plan:
                                   tune_cache.encode() if tune_cache else None))
         self._h = h
 
+    @staticmethod
+    def _item_key(item):
+        """(table descriptor, shape, (y, k, ind) addresses, (mu, thresholds)) of one item:
+        (Modes, shape, y) or (Modes, shape, {'y'/'k'/'ind': tensor}[, mu[, thresholds]])."""
+        m, shape, out = item[0], item[1], item[2]
+        mu = item[3] if len(item) > 3 else None
+        thr = item[4] if len(item) > 4 else None
+        if isinstance(out, torch.Tensor):
+            out = {"y": out}
+        ptrs = tuple(out[k].data_ptr() if out.get(k) is not None else 0 for k in ("y", "k", "ind"))
+        epi = (None if mu is None else float(mu),
+               None if thr is None else tuple(float(t) for t in np.atleast_1d(thr)))
+        return (m.c(), tuple(shape), ptrs, epi)
+
     def run(self, items, stream=None):
-        """items: list of (Modes, shape, y tensor) — y flat float32 device tensors."""
-        # descriptors are marshalled once per (table descriptor, shape, output) and reused
-        key = [(m.c(), tuple(shape), y.data_ptr()) for m, shape, y in items]
+        """items: list of (Modes, shape, y) with y a flat float32 device tensor, or
+        (Modes, shape, out[, mu[, thresholds]]) with out a dict of flat device tensors 'y',
+        'k' (float32, K = exp(mu + Y)) and/or 'ind' (uint8 facies index)."""
+        # descriptors are marshalled once per (table descriptor, shape, outputs, epilogue) and reused
+        key = [self._item_key(it) for it in items]
         last = getattr(self, "_last", None)
         if last is not None and len(last[0]) == len(key) and all(
-                a[0] is b[0] and a[1] == b[1] and a[2] == b[2] for a, b in zip(last[0], key)):
+                a[0] is b[0] and a[1:] == b[1:] for a, b in zip(last[0], key)):
             arr = last[1]
         else:
             arr = (L.GrfBatchItem * len(items))()
-            for i, (mc, shape, yp) in enumerate(key):
+            for i, (mc, shape, ptrs, epi) in enumerate(key):
                 arr[i].modes = mc
                 arr[i].grid = _grid(shape)
-                arr[i].y = yp
+                arr[i].epi = _epi(epi[0], epi[1])
+                arr[i].y, arr[i].k, arr[i].ind = (p or None for p in ptrs)
             self._last = (key, arr)
         check(L.load().eval_field_batch(self._h, arr, len(items), _stream(stream)))
 

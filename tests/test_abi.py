@@ -239,7 +239,15 @@ def test_plan_validation(lib):
     assert lib.eval_field_batch(h, items, 2, None) == L.GRF_EINVAL
     items[1].modes = _modes(dim=2)
     items[1].y = 0
+    assert lib.eval_field_batch(h, items, 2, None) == L.GRF_EINVAL   # no output at all
+    items[1].ind = 16                                                 # facies without a threshold
     assert lib.eval_field_batch(h, items, 2, None) == L.GRF_EINVAL
+    items[1].epi.n_thresholds = 2
+    items[1].epi.thresholds[0], items[1].epi.thresholds[1] = 0.5, 0.25  # not ascending
+    assert lib.eval_field_batch(h, items, 2, None) == L.GRF_EINVAL
+    items[1].epi.n_thresholds = L.GRF_MAX_THRESHOLDS + 1
+    assert lib.eval_field_batch(h, items, 2, None) == L.GRF_EINVAL
+    assert b"threshold" in lib.grf_last_error()
     tm, tn, rep, wi = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
     assert lib.grf_plan_info(h, ctypes.byref(tm), ctypes.byref(tn), ctypes.byref(rep), ctypes.byref(wi)) == 0
     assert wi.value == 0 and rep.value == 0
@@ -467,3 +475,44 @@ def test_modes_descriptor_cache():
     assert c4 is not c3 and c4.z == m.z.data_ptr()
     m.phi = phi[:8]  # same storage and address, another shape
     assert m.c() is not c4
+
+
+@pytest.mark.parametrize("cov,conv,ell,want", [
+    (0, 0, (8.0, 4.0, 2.0), (8.0, 4.0, 2.0)),
+    # the paper's Gaussian exp(-(pi/4)(r/lambda)^2) equals exp(-r^2/ell^2) for ell = 2 lambda / sqrt(pi)
+    (0, 1, (8.0, 4.0, 2.0), tuple(2.0 * v / np.sqrt(np.pi) for v in (8.0, 4.0, 2.0))),
+    (1, 1, (16.0, 16.0, 4.0), (16.0, 16.0, 4.0)),   # exponential: lambda is ell
+    (2, 1, (3.0, 2.0, 1.0), (3.0, 2.0, 1.0)),
+])
+def test_modes_init_fills_descriptor(lib, cov, conv, ell, want):
+    s = _spec(cov=cov, len_convention=conv, sigma2=4.0, n_modes=100, nu=1.0)
+    s.ell = (ctypes.c_double * 3)(*ell)
+    m = L.GrfModes()
+    assert lib.grf_modes_init(ctypes.byref(s), ctypes.c_void_p(64), ctypes.c_void_p(128), ctypes.byref(m)) == 0
+    assert (m.dim, m.n, m.z, m.phi, m.w, m.rotated) == (3, 100, 64, 128, None, 0)
+    assert m.sigma == 2.0
+    np.testing.assert_allclose([m.ell[a] for a in range(3)], want, rtol=1e-15)
+    # paper_lambda_to_ell is the same conversion
+    from paper_2212_10961_amd import grf
+    if cov == 0 and conv == 1:
+        assert abs(grf.paper_lambda_to_ell(ell[0]) - m.ell[0]) <= 1e-15 * m.ell[0]
+    # dim 2: the third length is not used and set to 1
+    s.dim = 2
+    assert lib.grf_modes_init(ctypes.byref(s), ctypes.c_void_p(64), ctypes.c_void_p(128), ctypes.byref(m)) == 0
+    assert m.ell[2] == 1.0
+
+
+@pytest.mark.parametrize("bad", [dict(sigma2=-1.0), dict(sigma2=float("inf")), dict(len_convention=2),
+                                 dict(dim=1), dict(n_modes=0), dict(cov=5)])
+def test_modes_init_rejects(lib, bad):
+    s = _spec(**bad)
+    m = L.GrfModes()
+    m.n = 77
+    assert lib.grf_modes_init(ctypes.byref(s), ctypes.c_void_p(64), ctypes.c_void_p(128), ctypes.byref(m)) == L.GRF_EINVAL
+    assert m.n == 77   # untouched on failure
+    s = _spec()
+    s.ell = (ctypes.c_double * 3)(1.0, 0.0, 1.0)
+    assert lib.grf_modes_init(ctypes.byref(s), ctypes.c_void_p(64), ctypes.c_void_p(128), ctypes.byref(m)) == L.GRF_EINVAL
+    s = _spec()
+    assert lib.grf_modes_init(ctypes.byref(s), None, ctypes.c_void_p(128), ctypes.byref(m)) == L.GRF_EINVAL
+    assert lib.grf_modes_init(ctypes.byref(s), ctypes.c_void_p(64), ctypes.c_void_p(128), None) == L.GRF_EINVAL

@@ -136,23 +136,102 @@ def test_autotune_cache(orc, grf, tmp_path):
         np.testing.assert_array_equal(to_np(d["y"]), y)
 
 
-def test_batch512_full_sampled(orc, grf):
-    """The 512-instance uneven ensemble, sides 64..1024, N=2048, one persistent launch."""
-    print("case batch512 full", flush=True)
+@pytest.mark.parametrize("meth", ["sep_f16", "direct_f32"])
+def test_batch512_full_sampled(orc, grf, meth):
+    """The 512-instance uneven ensemble, sides 64..1024, N=2048, one persistent launch:
+    1024 sampled cells of every instance against the oracle (and four whole instances)."""
+    print(f"case batch512 full {meth}", flush=True)
     inst = wl.batch_instances()
-    items, keep = [], []
-    for i, p in enumerate(inst):
+    items = []
+    for p in inst:
         z, phi = grf.make_modes(2, p["cov"], p["n_modes"], p["seed"])
         m = grf.modes_from_tables(z, phi, math.sqrt(p["sigma2"]), p["ell"])
-        y = torch.empty(p["shape"][0] * p["shape"][1], device="cuda")
-        items.append((m, p["shape"], y))
-        if i % 64 == 0:
-            keep.append((i, p, y))
-    plan = grf.Plan("sep_f16", graph=True, autotune=True)
+        items.append((m, p["shape"], torch.full((p["shape"][0] * p["shape"][1],), float("nan"), device="cuda")))
+    plan = grf.Plan(meth, graph=True, autotune=meth != "direct_f32")
     plan.run(items)
-    for i, p, y in keep:
+    torch.cuda.synchronize()
+    ys, refs = [], []
+    whole = set(int(v) for v in np.argsort([p["shape"][0] * p["shape"][1] for p in inst])[[0, 1, 255, 511]])
+    for i, p in enumerate(inst):
         zo, po = orc.sample_modes(2, p["cov"], p["n_modes"], p["seed"])
-        cells = wl.sample_cells(p["shape"][0] * p["shape"][1], 300, 600 + i)
+        cells = wl.sample_cells(p["shape"][0] * p["shape"][1], 1024, 600 + i)
+        if i in whole and p["shape"][0] * p["shape"][1] <= 300_000:
+            cells = np.arange(p["shape"][0] * p["shape"][1], dtype=np.int64)
+        y = to_np(items[i][2])[cells]
         ref = orc.field_cells(zo, po, math.sqrt(p["sigma2"]), p["ell"], p["shape"], cells)
-        assert_field(to_np(y)[cells], ref, math.sqrt(p["sigma2"]), "sep_f16", f"batch512[{i}] {p['shape']}")
+        assert np.isfinite(y).all(), (i, p["shape"])
+        sg = math.sqrt(p["sigma2"])
+        assert np.max(np.abs(y - ref)) <= TOL[meth]["band"] * sg, (i, p["shape"])
+        ys.append(y)
+        refs.append(ref)
+    assert_field(np.concatenate(ys), np.concatenate(refs), 1.0, meth, f"batch512 all instances")
+    plan.close()
+
+
+@pytest.mark.parametrize("meth", ["direct_f32", "sep_f16", "sep_f16_x3"])
+def test_batch_epilogue(orc, grf, meth):
+    """Per-instance epilogues in the persistent launch: K = exp(mu + Y) and facies indices
+    with each instance's own mu and thresholds, equal to solo calls with the same epilogue
+    (bitwise for the direct form and for hi+lo with the same tile) and to the oracle."""
+    print(f"case batch epilogue {meth}", flush=True)
+    inst = _instances(orc, grf, 12, 260, 160, 36)
+    rng = np.random.default_rng(7)
+    items = []
+    for i, d in enumerate(inst):
+        C = int(np.prod(d["shape"]))
+        mu = float(rng.uniform(-1.0, 1.0))
+        thr = np.sort(rng.normal(0.0, 0.7, size=1 + i % 3)).astype(np.float32)
+        out = {"k": torch.full((C,), float("nan"), device="cuda"),
+               "ind": torch.full((C,), 255, dtype=torch.uint8, device="cuda")}
+        if i % 2 == 0:
+            out["y"] = d["y"]
+        d.update(mu=mu, thr=thr, out=out)
+        items.append((d["m"], d["shape"], out, mu, thr))
+    plan = grf.Plan(meth, graph=True, autotune=False)
+    plan.run(items)
+    for i, d in enumerate(inst):
+        k, ind = to_np(d["out"]["k"]), to_np(d["out"]["ind"])
+        solo = grf.field_grid(d["m"], d["shape"], method=meth, mu=d["mu"], thresholds=d["thr"], want_k=True,
+                              want_ind=True, tile=(None if not meth.endswith("_x3") else
+                                                   (1 if d["shape"][0] >= 192 and d["shape"][1] >= 192 else 2)))
+        if meth != "sep_f16":
+            np.testing.assert_array_equal(k, to_np(solo["k"]), err_msg=f"K batch[{i}]")
+            np.testing.assert_array_equal(ind, to_np(solo["ind"]), err_msg=f"ind batch[{i}]")
+            if "y" in d["out"]:
+                np.testing.assert_array_equal(to_np(d["out"]["y"]), to_np(solo["y"]))
+        ref = orc.field_grid(d["zo"], d["po"], d["sigma"], d["ell"], d["shape"])
+        kref = orc.lognormal(ref, d["mu"])
+        band = TOL[meth]["band"] * d["sigma"]
+        assert np.max(np.abs(k - kref) / kref) <= 1.2 * band + 1e-6, (i, meth)
+        want = (ref[:, None] > d["thr"][None, :].astype(np.float64)).sum(axis=1)
+        near = np.any(np.abs(ref[:, None] - d["thr"][None, :]) <= band, axis=1)
+        assert not np.any((ind != want) & ~near), (i, meth)
+        if "y" in d["out"]:
+            assert_field(to_np(d["out"]["y"]), ref, d["sigma"], meth, f"epi batch[{i}]")
+    plan.close()
+
+
+def test_batch_new_weights_rebuild(orc, grf):
+    """A new per-mode weight tensor (same z, phi) is a new batch signature: the plan rebuilds
+    its descriptors instead of replaying the ones that point at the old weights."""
+    print("case batch new weights", flush=True)
+    inst = _instances(orc, grf, 6, 200, 96, 37)
+    rng = np.random.default_rng(11)
+    for rnd in range(2):
+        for d in inst:
+            d["m"].w = torch.as_tensor(rng.uniform(0.2, 1.8, size=96), dtype=torch.float64, device="cuda")
+        items = [(d["m"], d["shape"], d["y"]) for d in inst]
+        if rnd == 0:
+            plan = grf.Plan("direct_f32", graph=True, autotune=False)
+        plan.run(items)
+        assert plan.info()["replayed"] == 0
+        for i, d in enumerate(inst):
+            np.testing.assert_array_equal(to_np(d["y"]), to_np(grf.field_grid(d["m"], d["shape"])["y"]),
+                                          err_msg=f"round {rnd} batch[{i}]")
+        plan.run(items)   # same weights again: replayed, same values
+        assert plan.info()["replayed"] == 1
+    wo = to_np(inst[0]["m"].w)
+    ref = orc.field_points_w(inst[0]["zo"], inst[0]["po"], wo, inst[0]["sigma"], inst[0]["ell"],
+                             orc.grid_centres(inst[0]["shape"]))
+    assert_field(to_np(inst[0]["y"]), ref, inst[0]["sigma"], "direct_f32", "weighted batch[0]")
     plan.close()

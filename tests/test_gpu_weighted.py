@@ -64,29 +64,47 @@ def test_weighted_points(orc, grf, meth):
     assert_field(y, want, sigma, meth, "weighted points")
 
 
+def _rel(a, b):
+    a, b = np.asarray(a, np.float64).reshape(-1), np.asarray(b, np.float64).reshape(-1)
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
 def test_weighted_backward(orc, grf):
-    """Each mode's terms scale by w_j, so dL/dphi_j and dL/dk_j are w_j times the unweighted
-    oracle gradients (linearity), dL/dsigma = sum g Y_w / sigma and dL/dell follows dL/dk."""
+    """The adjoint of a weighted table against the oracle's weighted gradients."""
     _say("case weighted backward points")
     ell, sigma = np.array([5.0, 3.0, 2.0]), 1.1
     ref, m = _lattice(orc, grf, 3, wl.GAUSSIAN, 6, 0.8, 915, sigma, ell)
     x = wl.points_uniform(800, (30.0, 30.0, 10.0), 916)
     g = wl.upstream_grad(800, 917).astype(np.float32)
-    base = orc.grad_points(ref["z"], ref["phi"], sigma, ell, x, g.astype(np.float64))
-    w = ref["w"]
-    want = {"dphi": base["dphi"] * w, "dk": base["dk"] * w[None, :]}
-    want["dell"] = (want["dk"] * (-ref["z"] / (ell[:, None] ** 2))).sum(axis=1)
-    want["dsigma"] = float(np.dot(g, orc.field_points_w(ref["z"], ref["phi"], w, sigma, ell, x)) / sigma)
-    out = grf.field_backward(m, torch.from_numpy(x).cuda(), torch.from_numpy(g).cuda())
+    want = orc.grad_points_w(ref["z"], ref["phi"], ref["w"], sigma, ell, x, g.astype(np.float64))
+    xt, gt = torch.from_numpy(x).cuda(), torch.from_numpy(g).cuda()
+    for saved in (False, True):
+        y = grf.field_points(m, xt)["y"] if saved else None
+        out = grf.field_backward(m, xt, gt, y_saved=y)
+        r = {k: _rel(to_np(out[k]), want[k]) for k in ("dphi", "dk", "dell")}
+        r["dsigma"] = _rel(to_np(out["dsigma"]), [want["dsigma"]])
+        _say(f"  saved={saved} rel-L2 {r}")
+        assert max(r["dphi"], r["dk"]) <= 2e-5 and r["dell"] <= 2e-5
+        assert r["dsigma"] <= (2e-4 if saved else 2e-5)
 
-    def rel(a, b):
-        a, b = np.asarray(a, np.float64).reshape(-1), np.asarray(b, np.float64).reshape(-1)
-        return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
-    r = {k: rel(to_np(out[k]), want[k]) for k in ("dphi", "dk", "dell")}
-    r["dsigma"] = rel(to_np(out["dsigma"]), [want["dsigma"]])
+@pytest.mark.parametrize("meth", ["direct_f32", "sep_bf16_x3"])
+def test_weighted_backward_grid(orc, grf, meth):
+    """Dense dL/dY over a grid, weighted table, both adjoint forms against the oracle."""
+    shape, ell, sigma = (24, 19, 6), np.array([6.0, 4.0, 2.0]), 1.4
+    _say(f"case weighted backward grid {shape} {meth}")
+    ref, m = _lattice(orc, grf, 3, wl.EXPONENTIAL, 6, 0.9, 918, sigma, ell)
+    geo = dict(origin=(0.5, -1.0, 2.0), h=(1.0, 1.25, 0.5))
+    x = orc.grid_centres(shape, **geo)
+    g = wl.upstream_grad(x.shape[0], 919).astype(np.float32)
+    want = orc.grad_points_w(ref["z"], ref["phi"], ref["w"], sigma, ell, x, g.astype(np.float64))
+    out = grf.field_backward_grid(m, shape, torch.from_numpy(g).cuda(), method=meth, **geo)
+    r = {k: _rel(to_np(out[k]), want[k]) for k in ("dphi", "dk", "dell")}
+    r["dsigma"] = _rel(to_np(out["dsigma"]), [want["dsigma"]])
     _say(f"  rel-L2 {r}")
-    assert max(r.values()) <= 3e-5
+    bar = 2e-5 if meth == "direct_f32" else 5e-5
+    assert max(r["dphi"], r["dk"], r["dell"]) <= bar
+    assert r["dsigma"] <= (2e-5 if meth == "direct_f32" else 2e-4)
 
 
 @pytest.mark.parametrize("meth", ["sep_f16", "direct_f32"])

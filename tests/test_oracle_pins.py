@@ -367,6 +367,48 @@ def test_gradient_fd_error_is_second_order(orc):
     assert 3.0 < errs[0] / errs[1] < 5.0, errs
 
 
+def test_weighted_gradients_match_finite_differences(orc):
+    """Gradients through the weighted (fixed-frequency) sum against central differences of the
+    oracle's own weighted forward map; and with unit weights they equal the unweighted ones."""
+    t = orc.lattice_modes(3, wl.EXPONENTIAL, 4, 0.7, 841)
+    z, phi, w = t["z"], t["phi"], t["w"]
+    n = z.shape[1]
+    ell = np.array([2.5, 1.5, 0.8])
+    sigma = 1.7
+    x = wl.points_uniform(50, (10.0, 8.0, 4.0), 842)
+    g = wl.upstream_grad(50, 843)
+    gr = orc.grad_points_w(z, phi, w, sigma, ell, x, g)
+    h = 1e-6
+
+    def loss(zz=z, pp=phi, sg=sigma, el=ell):
+        return float(np.dot(g, orc.field_points_w(zz, pp, w, sg, el, x)))
+
+    for j in (0, 5, n - 1):
+        d = np.zeros(n)
+        d[j] = h
+        fd = (loss(pp=phi + d) - loss(pp=phi - d)) / (2 * h)
+        assert abs(fd - gr["dphi"][j]) < 1e-7 * (1 + abs(fd)), (j, fd, gr["dphi"][j])
+        for a in range(3):
+            dz = np.zeros_like(z)
+            dz[a, j] = h * ell[a]       # k = z / ell moves by h
+            fd = (loss(zz=z + dz) - loss(zz=z - dz)) / (2 * h)
+            assert abs(fd - gr["dk"][a, j]) < 1e-6 * (1 + abs(fd)), (j, a)
+    fd = (loss(sg=sigma + h) - loss(sg=sigma - h)) / (2 * h)
+    assert abs(fd - gr["dsigma"]) < 1e-7 * (1 + abs(fd))
+    for a in range(3):
+        e = np.zeros(3)
+        e[a] = h
+        fd = (loss(el=ell + e) - loss(el=ell - e)) / (2 * h)
+        assert abs(fd - gr["dell"][a]) < 1e-6 * (1 + abs(fd)), (a, fd, gr["dell"][a])
+    # non-trivial weights matter: a wrong (unweighted) gradient is far off
+    unw = orc.grad_points(z, phi, sigma, ell, x, g)
+    assert np.max(np.abs(unw["dphi"] - gr["dphi"])) > 1e-3 * np.max(np.abs(gr["dphi"]))
+    one = orc.grad_points_w(z, phi, np.ones(n), sigma, ell, x, g)
+    for key in ("dphi", "dk", "dell"):
+        np.testing.assert_allclose(one[key], unw[key], rtol=1e-12, atol=1e-14)
+    assert abs(one["dsigma"] - unw["dsigma"]) <= 1e-12 * (1 + abs(unw["dsigma"]))
+
+
 # ------------------------------------------------------------------ pluri-Gaussian (bitruncated)
 
 def _golden_pluri():
