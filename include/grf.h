@@ -197,6 +197,23 @@ int eval_field_grid(const grf_modes* modes, const grf_grid* grid, int method, co
                     float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes, void* stream);
 
 /*
+ * eval_field_grid_noalloc -- eval_field_grid for callers that cannot allocate device memory
+ * (code under hipGraph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * per-axis tables go to a fixed scratch array of GRF_NOALLOC_SCRATCH_BYTES that the library
+ * holds on each device it runs on until the process ends, instead of a caller workspace.
+ *   Arguments as eval_field_grid without ws / ws_bytes; outputs are still the caller's.
+ *   A problem whose workspace (eval_field_grid_ws_size) exceeds the scratch size is
+ *   GRF_ENOMEM, with nothing enqueued.  Allocates nothing (no hipMalloc, hipFree or
+ *   allocating library call); the first call on a device looks up that device's copy.
+ * Every call on one device shares that device's array: calls that overlap on one GPU (other
+ * streams or threads, before the previous call's kernels have finished) race on it.  Calls
+ * in order on one stream are safe.  The array's contents on entry are never read.
+ */
+#define GRF_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+int eval_field_grid_noalloc(const grf_modes* modes, const grf_grid* grid, int method, const grf_epi* epi,
+                            float* y, float* k, uint8_t* ind, void* stream);
+
+/*
  * eval_field_grid_tile -- eval_field_grid with an explicit tile shape for the separable
  * methods (tuning and tests).  tile = -1 is the size-based default (what eval_field_grid
  * uses); 0 .. grf_sep_tile_count()-1 selects a shape.  Any selector gives the same field up

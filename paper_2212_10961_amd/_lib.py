@@ -18,6 +18,7 @@ GRF_MAX_THRESHOLDS = 15
 GRF_MAX_FACIES = 64
 GRF_PLURI_APPLY_WS_BYTES = 512
 GRF_PLAN_GRAPH, GRF_PLAN_AUTOTUNE = 1, 2
+GRF_NOALLOC_SCRATCH_BYTES = 32 << 20
 
 METHODS = {
     "auto": GRF_AUTO, "direct_f32": GRF_DIRECT_F32, "direct_f64": GRF_DIRECT_F64,
@@ -35,7 +36,7 @@ EXPORTS = [
     "field_backward_ws_size", "field_backward", "field_backward_grid_ws_size", "field_backward_grid",
     "field_backward_grid_method",
     "grf_plan_create", "grf_plan_destroy", "eval_field_batch", "grf_plan_info",
-    "grf_kernel_timer_enable", "grf_kernel_timer_read",
+    "grf_kernel_timer_enable", "grf_kernel_timer_read", "eval_field_grid_noalloc",
 ]
 
 
@@ -139,6 +140,8 @@ def load():
         "grf_plan_destroy": ([vp], ctypes.c_int),
         "eval_field_batch": ([vp, P(GrfBatchItem), i32, vp], ctypes.c_int),
         "grf_plan_info": ([vp, P(i32), P(i32), P(i32), P(i64)], ctypes.c_int),
+        "eval_field_grid_noalloc": ([P(GrfModes), P(GrfGrid), ctypes.c_int, P(GrfEpi), vp, vp, vp, vp],
+                                    ctypes.c_int),
         "grf_kernel_timer_enable": ([ctypes.c_int], ctypes.c_int),
         "grf_kernel_timer_read": ([P(ctypes.c_double), P(i64)], ctypes.c_int),
     }

@@ -12,7 +12,7 @@ ROOT = PKG.parent
 CSRC = PKG / "csrc"
 OBJ = PKG / "_build"
 LIB = PKG / "libgrf.so"
-SOURCES = ["api.cpp", "modes.cpp", "tables.hip", "direct.hip", "sep.hip", "adjoint.hip", "batch.hip", "krige.hip"]
+SOURCES = ["api.cpp", "modes.cpp", "tables.hip", "direct.hip", "sep.hip", "adjoint.hip", "batch.hip", "krige.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

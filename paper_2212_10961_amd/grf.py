@@ -25,7 +25,7 @@ from . import _lib as L
 from ._lib import GrfError, check
 
 __all__ = [
-    "Modes", "make_modes", "modes_from_spec", "modes_from_tables", "field_grid", "field_grid_f64", "field_points",
+    "Modes", "make_modes", "modes_from_spec", "modes_from_tables", "field_grid", "field_grid_noalloc", "field_grid_f64", "field_points",
     "epilogue", "field_backward", "field_backward_grid", "GRFPoints", "Plan", "method_id", "sep_tiles",
     "trunc2", "pluri_grid", "pluri_points", "pluri_apply", "snap_periodic", "make_modes_lattice",
     "krige_weights", "krige_apply_grid", "krige_apply_points", "condition_grid", "condition_points",
@@ -278,6 +278,28 @@ def field_grid(modes: Modes, shape, origin=None, h=None, method="direct_f32", mu
         check(lib.eval_field_grid(ctypes.byref(m), ctypes.byref(g), meth, ctypes.byref(e), *ptrs))
     else:
         check(lib.eval_field_grid_tile(ctypes.byref(m), ctypes.byref(g), meth, int(tile), ctypes.byref(e), *ptrs))
+    return out
+
+
+def field_grid_noalloc(modes: Modes, shape, origin=None, h=None, method="direct_f32", mu=None, thresholds=None,
+                       want_y=True, want_k=False, want_ind=False, out=None, stream=None):
+    """field_grid through eval_field_grid_noalloc: the tables live in the library's fixed
+    per-device scratch array (no workspace; for callers that cannot allocate)."""
+    lib = L.load()
+    dev = modes.z.device
+    m, g = modes.c(), _grid(shape, origin, h)
+    cells = int(np.prod(list(shape)))
+    out = dict(out or {})
+    if want_y and "y" not in out:
+        out["y"] = torch.empty(cells, dtype=torch.float32, device=dev)
+    if want_k and "k" not in out:
+        out["k"] = torch.empty(cells, dtype=torch.float32, device=dev)
+    if want_ind and "ind" not in out:
+        out["ind"] = torch.empty(cells, dtype=torch.uint8, device=dev)
+    e = _epi(mu, thresholds)
+    check(lib.eval_field_grid_noalloc(ctypes.byref(m), ctypes.byref(g), method_id(method), ctypes.byref(e),
+                                      _ptr(out.get("y")), _ptr(out.get("k")), _ptr(out.get("ind")),
+                                      _stream(stream)))
     return out
 
 
