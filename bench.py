@@ -38,6 +38,49 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def cpu_model() -> str:
+    try:
+        for line in Path("/proc/cpuinfo").read_text().splitlines():
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def field_errors(np, y, ref, sigma):
+    """rel-RMS and max |dY| / sigma of a sample against the FP64 oracle."""
+    y = np.asarray(y, dtype=np.float64)
+    ref = np.asarray(ref, dtype=np.float64)
+    return {"rel_rms": float(np.sqrt(np.mean((y - ref) ** 2) / np.mean(ref ** 2))),
+            "max_abs_over_sigma": float(np.max(np.abs(y - ref)) / sigma), "samples": int(y.size)}
+
+
+def indicator_errors(np, ind, ref, thresholds, band, sigma):
+    """Facies indices against the oracle's: mismatches outside the stated error band of the
+    thresholds (must be 0) and the number of samples inside the band (band in units of Y)."""
+    thr = np.atleast_1d(np.asarray(thresholds, dtype=np.float64))
+    want = (ref[:, None] > thr[None, :]).sum(axis=1)
+    near = np.any(np.abs(ref[:, None] - thr[None, :]) <= band, axis=1)
+    return {"mismatch_outside_band": int(np.count_nonzero((np.asarray(ind) != want) & ~near)),
+            "in_band": int(np.count_nonzero(near)), "band_over_sigma": band / sigma, "samples": int(len(ref))}
+
+
+def grad_errors(np, got, ref):
+    """rel-L2 of each gradient block against the oracle's exact gradients."""
+    out = {}
+    for k in ("dphi", "dk", "dsigma", "dell"):
+        a = np.asarray(got[k].detach().cpu().numpy() if hasattr(got[k], "detach") else got[k], np.float64).ravel()
+        b = np.atleast_1d(np.asarray(ref[k], np.float64)).ravel()
+        out[k] = float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    return out
+
+
+# Error bands (x sigma) each path states before any run: the indicator tolerance.
+BAND = {"direct_f32": 1e-4, "direct_f64": 1e-6, "sep_f16": 1e-2, "sep_bf16": 5e-2, "sep_f16_x3": 2e-4,
+        "sep_bf16_x3": 4e-4}
+
+
 def sha(path: Path) -> str:
     return hashlib.sha256(path.read_bytes()).hexdigest()[:16]
 
@@ -52,7 +95,7 @@ def read_traffic(name: str, kernel_src: Path):
         if ":" in line and not line.startswith("#"):
             k, v = line.split(":", 1)
             kv[k.strip()] = v.strip()
-    if kv.get("source_sha") != sha(kernel_src) or kv.get("bench_sha") != sha(Path(__file__)):
+    if kv.get("source_sha") != sha(kernel_src):  # counters taken on another version of the kernel
         return None
     try:
         return float(kv["hbm_bytes_per_launch"])
@@ -68,8 +111,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU-baseline (oracle) leg")
     ap.add_argument("--no-extras", action="store_true", help="only the headline workload")
     ap.add_argument("--only", default=None, help="time a single grid method (profiling runs)")
-    ap.add_argument("--extras", default="points,epilogue,adjoint,pluri,krige,batch",
-                    help="comma-separated extra workloads to time (points, epilogue, adjoint, pluri, krige, batch)")
+    ap.add_argument("--extras", default="grid2d,points,epilogue,adjoint,pluri,krige,batch,probe",
+                    help="comma-separated extra workloads to time (grid2d, points, epilogue, adjoint, pluri, "
+                         "krige, batch, probe)")
     ap.add_argument("--extras-only", action="store_true", help="skip the headline workload (profiling runs)")
     ap.add_argument("--spinup-ms", type=float, default=500.0,
                     help="untimed GPU work before the first timed loop (steady clocks)")
@@ -176,7 +220,16 @@ def main():
         dt = time.perf_counter() - t0
         cpu = {"value": cells.size * N / dt, "unit": "mode·cell/s", "cores": threads, "kind": "oracle",
                "sample": f"{cells.size} seeded random cells of the 256^3 grid x {N} modes (FP64 direct sum), "
-                         f"{dt:.1f} s"}
+                         f"{dt:.1f} s", "cpu_model": cpu_model()}
+        # the same oracle on one thread (a smaller sample of ~3 s)
+        oracle.set_threads(1)
+        one = wl.sample_cells(C, int(min(max(3.0 * rate / threads / N, 256), 200_000)), 4244)
+        t0 = time.perf_counter()
+        oracle.field_cells(z, phi, sigma, cfg["ell"], shape, one)
+        dt1 = time.perf_counter() - t0
+        oracle.set_threads(threads)
+        cpu["one_thread"] = {"value": one.size * N / dt1, "unit": "mode·cell/s",
+                             "sample": f"{one.size} seeded random cells x {N} modes, {dt1:.1f} s"}
         idx = torch.from_numpy(cells).to(dev)
         kref = oracle.lognormal(ref, cfg["mu"])
         for m in methods:
@@ -257,26 +310,82 @@ def _timed(torch, grf, fn, steps, warm):
 
 def extras(args, grf, wl, torch, np, dev):
     sel = set(s.strip() for s in args.extras.split(",") if s.strip())
+    err = not args.no_cpu  # errors against the FP64 oracle (CPU) beside each leg's timing
     out = {}
+    if "grid2d" in sel:
+        out.update(grid2d_extra(grf, wl, torch, np, dev, err))
     if "points" in sel:
-        out.update(points_extra(grf, wl, torch, np, dev))
+        out.update(points_extra(grf, wl, torch, np, dev, err))
     if "epilogue" in sel:
         out.update(epilogue_extra(grf, wl, torch, np, dev))
     if "adjoint" in sel:
-        out.update(adjoint_extra(grf, wl, torch, np, dev))
+        out.update(adjoint_extra(grf, wl, torch, np, dev, err))
     if "pluri" in sel:
         out.update(pluri_extra(grf, wl, torch, np, dev))
     if "krige" in sel:
         out.update(krige_extra(grf, wl, torch, np, dev))
     if "batch" in sel:
         try:
-            out["batch512_2d"] = batch_extra(grf, wl, torch, np, dev)
+            out["batch512_2d"] = batch_extra(grf, wl, torch, np, dev, err)
         except grf.GrfError as e:
             out["batch512_2d"] = {"error": str(e)}
+    if "probe" in sel:
+        out["cos_rate_probe"] = cos_probe(torch, dev)
     return out
 
 
-def points_extra(grf, wl, torch, np, dev):
+def cos_probe(torch, dev):
+    """Measured issue rate of the hardware cosine in a register loop (alone, and in the direct
+    sum's per-term mix), beside the nominal half-rate peak used for the direct-sum rooflines."""
+    import ctypes
+    lib = ctypes.CDLL(str(ROOT / "paper_2212_10961_amd" / "libgrf_probe.so"))
+    lib.grf_probe_cos_rates.argtypes = [ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_int,
+                                        ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    blocks = 256 * 8
+    buf = torch.empty(blocks * 256, dtype=torch.float32, device=dev)
+    a, b = ctypes.c_double(), ctypes.c_double()
+    torch.cuda.synchronize()
+    rc = lib.grf_probe_cos_rates(ctypes.c_void_p(buf.data_ptr()), blocks, 4096, 5, ctypes.byref(a), ctypes.byref(b))
+    if rc != 0:
+        return {"error": rc}
+    return {"cos_per_s": a.value, "cos_mix_terms_per_s": b.value, "nominal_peak": COS_PEAK,
+            "cos_frac_of_nominal": a.value / COS_PEAK, "mix_frac_of_nominal": b.value / COS_PEAK,
+            "probe": f"{blocks} blocks x 256 lanes x 4096 iterations x 8 chains, best of 5",
+            "mix": "acc = fma(w, cos(x + acc q), acc): one cosine, one FMA and one multiply-add per term"}
+
+
+def grid2d_extra(grf, wl, torch, np, dev, err):
+    """The plain FP64 method on the 64x64 Gaussian workload (N = 1000), beside the FP32 direct
+    sum: launch-latency-bound, reported in microseconds with the errors of both."""
+    c = wl.WORKLOADS["grid2d_64_gauss"]
+    log("[bench] extras: grid2d_64_gauss")
+    sg = math.sqrt(c["sigma2"])
+    z, phi = grf.make_modes(2, c["cov"], c["n_modes"], c["seed"])
+    m = grf.modes_from_tables(z, phi, sg, c["ell"], device=dev)
+    shape = c["shape"]
+    C = int(np.prod(shape))
+    f64 = grf.field_grid_f64(m, shape, mu=c["mu"])
+    ms64, k64 = _timed(torch, grf, lambda: grf.field_grid_f64(m, shape, mu=c["mu"]), 50, 5)
+    ws = torch.empty(grf.grid_workspace_bytes(m, shape, "direct_f32"), dtype=torch.uint8, device=dev)
+    o32 = {"y": torch.empty(C, device=dev), "k": torch.empty(C, device=dev)}
+    ms32, k32 = _timed(torch, grf, lambda: grf.field_grid(m, shape, method="direct_f32", mu=c["mu"], want_k=True,
+                                                          out=o32, workspace=ws), 50, 5)
+    res = {"cells": C, "n_modes": c["n_modes"], "mode_cells": C * c["n_modes"],
+           "direct_f64": {"us_per_call": ms64 * 1e3, "kernel_us": k64 * 1e3},
+           "direct_f32": {"us_per_call": ms32 * 1e3, "kernel_us": k32 * 1e3}}
+    if err:
+        import oracle
+        ref = oracle.field_grid(z, phi, sg, c["ell"], shape)
+        kref = oracle.lognormal(ref, c["mu"])
+        y64 = f64["y"].cpu().numpy()
+        res["direct_f64"].update(field_errors(np, y64, ref, sg))
+        res["direct_f64"]["k_max_rel"] = float(np.max(np.abs(f64["k"].cpu().numpy() - kref) / kref))
+        res["direct_f32"].update(field_errors(np, o32["y"].double().cpu().numpy(), ref, sg))
+        res["direct_f32"]["k_max_rel"] = float(np.max(np.abs(o32["k"].double().cpu().numpy() - kref) / kref))
+    return {"grid2d_64_gauss": res}
+
+
+def points_extra(grf, wl, torch, np, dev, err=False):
     out = {}
     # unstructured points, FP64 phase reduction per mode and point, indicator epilogue
     c = wl.WORKLOADS["points_2m_gauss"]
@@ -285,14 +394,36 @@ def points_extra(grf, wl, torch, np, dev):
     m = grf.modes_from_tables(z, phi, math.sqrt(c["sigma2"]), c["ell"], device=dev)
     x = torch.from_numpy(wl.points_uniform(c["n_points"], c["box"], c["point_seed"])).to(dev)
     o = {"y": torch.empty(c["n_points"], device=dev), "ind": torch.empty(c["n_points"], dtype=torch.uint8, device=dev)}
-    ws = torch.empty(1 << 20, dtype=torch.uint8, device=dev)
-    ms, kms = _timed(torch, grf, lambda: grf.field_points(m, x, thresholds=[c["threshold"]], want_ind=True, out=o,
-                                                          workspace=ws), 5, 1)
     work = c["n_points"] * c["n_modes"]
-    out["points_2m_gauss"] = {"ms_per_call": ms, "mode_points_per_s": work / (ms * 1e-3),
-                              "roofline": {"bound": "alu", "achieved": work / (kms * 1e-3), "peak": COS_PEAK,
-                                           "unit": "mode·point/s", "frac": work / (kms * 1e-3) / COS_PEAK},
+    res = {}
+    # the default form for this many points (binned), then the per-point FP64 phase form
+    for form in ("direct_f32_binned", "direct_f32_pointwise"):
+        ws = torch.empty(grf.points_workspace_bytes(m, c["n_points"], form), dtype=torch.uint8, device=dev)
+        ms, kms = _timed(torch, grf, lambda: grf.field_points(m, x, method=form, thresholds=[c["threshold"]],
+                                                              want_ind=True, out=o, workspace=ws), 5, 1)
+        res[form] = {"ms_per_call": ms, "kernel_ms": kms, "mode_points_per_s": work / (ms * 1e-3),
+                     "roofline": {"bound": "alu", "achieved": work / (kms * 1e-3), "peak": COS_PEAK,
+                                  "unit": "mode·point/s", "frac": work / (kms * 1e-3) / COS_PEAK,
+                                  "kernel": "k_points_binned" if form.endswith("binned") else "k_direct_points"}}
+        del ws
+    head = res["direct_f32_binned"]
+    out["points_2m_gauss"] = {"ms_per_call": head["ms_per_call"], "mode_points_per_s": head["mode_points_per_s"],
+                              "roofline": head["roofline"], "forms": res,
                               "indicator_fraction": float(o["ind"].float().mean().item())}
+    if err:
+        import oracle
+        sg = math.sqrt(c["sigma2"])
+        idx = wl.sample_cells(c["n_points"], 32768, 4245)
+        it = torch.from_numpy(idx).to(dev)
+        ref = oracle.field_points(z, phi, sg, c["ell"], x[it].cpu().numpy())
+        r = out["points_2m_gauss"]
+        for form in ("direct_f32_pointwise", "direct_f32_binned"):
+            grf.field_points(m, x, method=form, thresholds=[c["threshold"]], want_ind=True, out=o)
+            e = field_errors(np, o["y"][it].double().cpu().numpy(), ref, sg)
+            e["indicator"] = indicator_errors(np, o["ind"][it].cpu().numpy(), ref, [c["threshold"]],
+                                              BAND["direct_f32"] * sg, sg)
+            res[form]["errors"] = e
+        r["errors"] = res["direct_f32_binned"]["errors"]
     return out
 
 
@@ -312,22 +443,29 @@ def epilogue_extra(grf, wl, torch, np, dev):
     return out
 
 
-def adjoint_extra(grf, wl, torch, np, dev):
+def adjoint_extra(grf, wl, torch, np, dev, err=False):
     out = {}
-    # adjoint workload: forward + backward at 10,000 observation cells, and the dense variant
+    # adjoint workload: loss = mean squared misfit of ln K against a target field (seed 50) at
+    # 10,000 observation cells (forward + backward), and the dense variant over every cell
     c = wl.WORKLOADS["adjoint_grid3d_128"]
     log("[bench] extras: adjoint_grid3d_128")
     sg = math.sqrt(c["sigma2"])
     z, phi = grf.make_modes(3, c["cov"], c["n_modes"], c["seed"])
     m = grf.modes_from_tables(z, phi, sg, c["ell"], device=dev)
+    zt, pt = grf.make_modes(3, c["cov"], c["n_modes"], c["target_seed"])
+    mt = grf.modes_from_tables(zt, pt, sg, c["ell"], device=dev)
     Cg = int(np.prod(c["shape"]))
     cells = wl.distinct_cells(Cg, c["n_obs"], c["obs_seed"])
     ii = np.stack([cells % 128, (cells // 128) % 128, cells // (128 * 128)], axis=1)
-    xo = torch.from_numpy(np.ascontiguousarray(ii + 0.5)).to(dev)
-    gy = torch.randn(c["n_obs"], device=dev) / c["n_obs"]
+    xo_np = np.ascontiguousarray(ii + 0.5)
+    xo = torch.from_numpy(xo_np).to(dev)
+    # dL/dY of L = (1/M) sum (mu + Y - mu - Y_target)^2 at the observations (mu cancels)
+    gy = (2.0 / c["n_obs"]) * (grf.field_points(m, xo)["y"] - grf.field_points(mt, xo)["y"])
     f_ms, f_k = _timed(torch, grf, lambda: grf.field_points(m, xo), 10, 2)
     b_ms, b_k = _timed(torch, grf, lambda: grf.field_backward(m, xo, gy), 10, 2)
-    gd = torch.randn(Cg, device=dev) / Cg
+    yg = grf.field_grid(m, c["shape"], method="direct_f32")["y"]
+    gd = (2.0 / Cg) * (yg - grf.field_grid(mt, c["shape"], method="direct_f32")["y"])
+    del yg
     df_ms, df_k = _timed(torch, grf, lambda: grf.field_grid(m, c["shape"], method="direct_f32"), 3, 1)
     # dense adjoint, separable form (the default on this grid) and the direct per-cell form;
     # the direct form also with the forward's Y handed back (dL/dsigma = sum g Y / sigma)
@@ -359,6 +497,20 @@ def adjoint_extra(grf, wl, torch, np, dev):
                   "bwd_direct_saved_y_roofline": {"bound": "alu", "achieved": Cg * c["n_modes"] / (ds_k * 1e-3),
                                                   "peak": COS_PEAK, "unit": "mode·cell/s",
                                                   "frac": Cg * c["n_modes"] / (ds_k * 1e-3) / COS_PEAK}}}
+    if err:
+        # gradients against the oracle's exact FP64 gradients (same dL/dY values, widened)
+        import oracle
+        r = out["adjoint_grid3d_128"]
+        ref = oracle.grad_points(z, phi, sg, c["ell"], xo_np, gy.double().cpu().numpy())
+        r["obs"]["grad_rel_l2"] = grad_errors(np, grf.field_backward(m, xo, gy), ref)
+        log("[bench] adjoint: oracle dense gradient over 2,097,152 cells")
+        t0 = time.perf_counter()
+        refd = oracle.grad_points(z, phi, sg, c["ell"], oracle.grid_centres(c["shape"]), gd.double().cpu().numpy())
+        r["dense"]["oracle_s"] = time.perf_counter() - t0
+        r["dense"]["grad_rel_l2_sep_bf16_x3"] = grad_errors(
+            np, grf.field_backward_grid(m, c["shape"], gd, method="sep_bf16_x3"), refd)
+        r["dense"]["grad_rel_l2_direct_f32"] = grad_errors(
+            np, grf.field_backward_grid(m, c["shape"], gd, method="direct_f32"), refd)
     return out
 
 
@@ -426,16 +578,41 @@ def krige_extra(grf, wl, torch, np, dev):
                            "unit": "cell·obs pair/s", "frac": pairs / (a_k * 1e-3) / trans_peak}}}
 
 
-def batch_extra(grf, wl, torch, np, dev):
+def batch_extra(grf, wl, torch, np, dev, err=False):
     inst = wl.batch_instances()
     log("[bench] extras: batch512_2d")
-    items, total = [], 0
+    items, total, tables = [], 0, []
     for p in inst:
         z, phi = grf.make_modes(2, p["cov"], p["n_modes"], p["seed"])
+        tables.append((z, phi))
         m = grf.modes_from_tables(z, phi, math.sqrt(p["sigma2"]), p["ell"], device=dev)
         cells = p["shape"][0] * p["shape"][1]
         total += cells
         items.append((m, p["shape"], torch.empty(cells, device=dev)))
+    # error sample: 4096 seeded cells of every instance plus 16 whole instances from the lower
+    # size quartile, against the FP64 oracle (computed once for both methods)
+    sample = None
+    if err:
+        import oracle
+        sizes = np.array([p["shape"][0] * p["shape"][1] for p in inst])
+        whole = set(int(i) for i in np.argsort(sizes)[:128:8])
+        sample = []
+        t0 = time.perf_counter()
+        for i, p in enumerate(inst):
+            C = int(sizes[i])
+            cells = np.arange(C, dtype=np.int64) if i in whole else wl.sample_cells(C, 4096, 7000 + i)
+            ref = oracle.field_cells(tables[i][0], tables[i][1], math.sqrt(p["sigma2"]), p["ell"], p["shape"], cells)
+            sample.append((cells, ref))
+        oracle_s = time.perf_counter() - t0
+
+    def batch_err(meth):
+        ys = np.concatenate([items[i][2][torch.from_numpy(cl).to(dev)].double().cpu().numpy()
+                             for i, (cl, _) in enumerate(sample)])
+        refs = np.concatenate([r for _, r in sample])
+        e = field_errors(np, ys, refs, 1.0)
+        e["whole_instances"] = 16
+        e["oracle_s"] = oracle_s
+        return e
     res = {"instances": len(inst), "cells": total, "mode_cells": total * 2048}
     # the same 512 evaluations as separate eval_field_grid calls (one workspace, sized for the largest)
     wsb = max(grf.grid_workspace_bytes(m, shape, "sep_f16") for m, shape, _ in items)
@@ -451,6 +628,8 @@ def batch_extra(grf, wl, torch, np, dev):
         ms, kms = _timed(torch, grf, lambda: plan.run(items), steps, 2)
         res[meth] = {"ms_per_batch": ms, "persistent_kernel_ms": kms, "mode_cells_per_s": total * 2048 / (ms * 1e-3),
                      "plan": plan.info()}
+        if sample is not None:
+            res[meth]["errors"] = batch_err(meth)
         plan.close()
     return res
 

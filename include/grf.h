@@ -60,6 +60,9 @@ extern "C" {
 #define GRF_SEP_F16 3       /* matrix-core contraction, fp16 tables, one pass */
 #define GRF_SEP_BF16_X3 4   /* bf16 hi+lo split tables, three passes */
 #define GRF_SEP_F16_X3 5    /* fp16 hi+lo split tables, three passes */
+/* point sums only (eval_field_points, eval_pluri_points): the two forms GRF_DIRECT_F32 picks from */
+#define GRF_DIRECT_F32_BINNED 6    /* points binned in cells, FP64 phase per (mode, cell), FP32 offsets */
+#define GRF_DIRECT_F32_POINTWISE 7 /* FP64 phase per (mode, point) */
 
 #define GRF_MAX_THRESHOLDS 15
 #define GRF_MAX_FACIES 64
@@ -242,9 +245,17 @@ int eval_field_points_ws_size(const grf_modes* modes, int64_t n_points, int meth
  * eval_field_points -- the field at P arbitrary points (unstructured cell centres,
  * Sec. 4.1: the direct sum applies to any mesh).
  *   xyz      device double[P][dim] (row-major).
- *   method   GRF_DIRECT_F32 (phase a.x + psi reduced in FP64 per mode and point, cos
- *            and sum in FP32) or GRF_DIRECT_F64; separable methods -> GRF_EUNSUPPORTED.
- *   y, k, ind, epi, ws: as eval_field_grid.  P = 0 is a no-op.
+ *   method   GRF_DIRECT_F32: cos and sum in FP32 with FP64 phase reduction, in one of two forms
+ *              GRF_DIRECT_F32_BINNED (what GRF_DIRECT_F32 uses from 65,536 points): points are
+ *                sorted into cubic cells of their bounding box (about 256 per cell), the phase
+ *                at the cell centre is reduced in FP64 per mode and group of 8 points of a cell
+ *                and each point adds its offset's phase in FP32; modes whose offset phase can
+ *                reach 4 revolutions within a cell take the per-point FP64 reduction instead.
+ *                At most 2^30 points (GRF_EUNSUPPORTED above).  A point's value does not depend
+ *                on the other points (deterministic);
+ *              GRF_DIRECT_F32_POINTWISE: phase a.x + psi reduced in FP64 per mode and point;
+ *            GRF_DIRECT_F64: FP64 throughout.  Separable methods -> GRF_EUNSUPPORTED.
+ *   y, k, ind, epi, ws: as eval_field_grid (outputs in input order).  P = 0 is a no-op.
  */
 int eval_field_points(const grf_modes* modes, const double* xyz, int64_t n_points, int method,
                       const grf_epi* epi, float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes,

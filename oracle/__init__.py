@@ -111,6 +111,11 @@ def threads() -> int:
     return int(lib.orc_threads())
 
 
+def set_threads(n: int) -> None:
+    """Sets the OpenMP threads of the oracle's loops (for timing at a given core count)."""
+    _load().orc_set_threads(int(n))
+
+
 def _dp(a):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
 

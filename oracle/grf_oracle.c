@@ -58,6 +58,16 @@ int orc_threads(void)
 #endif
 }
 
+/* Sets the threads of the OpenMP loops below (timing of the oracle at a given core count). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------ RNG */
 
 static uint32_t orc_mulhi32(uint32_t a, uint32_t b, uint32_t* lo)

@@ -14,6 +14,7 @@ GRF_OK, GRF_EINVAL, GRF_ENOMEM, GRF_EDEVICE, GRF_EUNSUPPORTED = 0, -1, -2, -3, -
 GRF_COV_GAUSSIAN, GRF_COV_EXPONENTIAL, GRF_COV_MATERN = 0, 1, 2
 GRF_AUTO, GRF_DIRECT_F32, GRF_DIRECT_F64 = -1, 0, 1
 GRF_SEP_BF16, GRF_SEP_F16, GRF_SEP_BF16_X3, GRF_SEP_F16_X3 = 2, 3, 4, 5
+GRF_DIRECT_F32_BINNED, GRF_DIRECT_F32_POINTWISE = 6, 7
 GRF_MAX_THRESHOLDS = 15
 GRF_MAX_FACIES = 64
 GRF_PLURI_APPLY_WS_BYTES = 512
@@ -23,7 +24,7 @@ GRF_NOALLOC_SCRATCH_BYTES = 32 << 20
 METHODS = {
     "auto": GRF_AUTO, "direct_f32": GRF_DIRECT_F32, "direct_f64": GRF_DIRECT_F64,
     "sep_bf16": GRF_SEP_BF16, "sep_f16": GRF_SEP_F16, "sep_bf16_x3": GRF_SEP_BF16_X3,
-    "sep_f16_x3": GRF_SEP_F16_X3,
+    "sep_f16_x3": GRF_SEP_F16_X3, "direct_f32_binned": GRF_DIRECT_F32_BINNED, "direct_f32_pointwise": GRF_DIRECT_F32_POINTWISE,
 }
 
 # Every symbol include/grf.h declares.

@@ -144,12 +144,25 @@ int check_epi(const grf_epi* e, const float* k, const uint8_t* ind, const char* 
 }
 
 
-// Workspace of eval_field_points: per-mode parameters, plus the per-slice partial sums when
-// the FP32 path splits the modes across blocks (few points).
+// The point-sum form GRF_DIRECT_F32 resolves to: binned for many points, else per point.
+static int resolve_points_f32(int method, int64_t P)
+{
+    if (method != GRF_DIRECT_F32) return method;
+    return (P >= kBinMinPoints && P <= kBinMaxPoints) ? GRF_DIRECT_F32_BINNED : GRF_DIRECT_F32_POINTWISE;
+}
+
+// Workspace of eval_field_points: per-mode parameters, the binned pass's sort and offsets, plus
+// the per-slice partial sums when an FP32 form splits the modes across blocks.
 static size_t points_ws_bytes(int64_t n, int64_t P, int method)
 {
+    method = resolve_points_f32(method, P);
     size_t b = align256(sizeof(double) * 4 * size_t(padded_modes(n)));
-    const int slices = method == GRF_DIRECT_F32 ? points_mode_slices(P, n) : 1;
+    int slices = 1;
+    if (method == GRF_DIRECT_F32_POINTWISE) slices = points_mode_slices(P, n);
+    if (method == GRF_DIRECT_F32_BINNED) {
+        b += bin_ws_bytes(P, padded_modes(n));
+        slices = bin_mode_slices(P, n);
+    }
     if (slices > 1) b += align256(sizeof(float) * size_t(slices) * size_t(P));
     return b;
 }
@@ -543,23 +556,37 @@ static int points_launch(const grf_modes* modes, const double* xyz, int64_t n_po
                          float* y, float* k, uint8_t* ind, void* ws, hipStream_t s)
 {
     const int64_t ldp = padded_modes(modes->n);
+    method = resolve_points_f32(method, n_points);
     Carve c(ws);
     double* params = c.take<double>(4 * ldp);
-    float* partial = method == GRF_DIRECT_F32 ? c.take<float>(size_t(points_mode_slices(n_points, modes->n)) * n_points)
-                                              : nullptr;
     GRF_HIP(launch_mode_params(modes->z, modes->phi, modes->dim, modes->n, ldp, modes->ell, params, s));
     const float amp = static_cast<float>(modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n)));
+    if (method == GRF_DIRECT_F32_BINNED) {
+        char* bins = c.take<char>(bin_ws_bytes(n_points, ldp));
+        float* partial = c.take<float>(size_t(bin_mode_slices(n_points, modes->n)) * n_points);
+        GRF_HIP(launch_points_binned(params, modes->w, modes->n, ldp, modes->dim, xyz, n_points, amp, e, y, k, ind,
+                                     bins, partial, s));
+        return GRF_OK;
+    }
+    float* partial = method == GRF_DIRECT_F32_POINTWISE
+                         ? c.take<float>(size_t(points_mode_slices(n_points, modes->n)) * n_points)
+                         : nullptr;
     TimedScope timed(s);
     GRF_HIP(launch_direct_points(params, modes->w, modes->n, modes->dim, xyz, n_points, method == GRF_DIRECT_F64, amp,
                                  e, y, k, ind, partial, s));
     return GRF_OK;
 }
 
-static int check_points_method(const char* fn, int* method)
+static int check_points_method(const char* fn, int* method, int64_t n_points)
 {
     if (*method == GRF_AUTO) *method = GRF_DIRECT_F32;
     if (is_sep(*method)) return fail(GRF_EUNSUPPORTED, "%s: separable methods need a structured grid", fn);
-    if (*method != GRF_DIRECT_F32 && *method != GRF_DIRECT_F64) return fail(GRF_EINVAL, "%s: unknown method %d", fn, *method);
+    if (*method != GRF_DIRECT_F32 && *method != GRF_DIRECT_F64 && *method != GRF_DIRECT_F32_BINNED &&
+        *method != GRF_DIRECT_F32_POINTWISE)
+        return fail(GRF_EINVAL, "%s: unknown method %d", fn, *method);
+    if (*method == GRF_DIRECT_F32_BINNED && n_points > kBinMaxPoints)
+        return fail(GRF_EUNSUPPORTED, "%s: the binned form takes at most %lld points", fn,
+                    static_cast<long long>(kBinMaxPoints));
     return GRF_OK;
 }
 
@@ -575,7 +602,7 @@ int eval_pluri_points_ws_size(const grf_modes* m1, const grf_modes* m2, int64_t 
     if ((rc = check_pair(m1, m2, fn))) return rc;
     if (!bytes) return fail(GRF_EINVAL, "%s: bytes is NULL", fn);
     if (n_points < 0) return fail(GRF_EINVAL, "%s: n_points < 0", fn);
-    if ((rc = check_points_method(fn, &method))) return rc;
+    if ((rc = check_points_method(fn, &method, n_points))) return rc;
     *bytes = align256(kRuleBytes) + rot_ws_bytes(m1) + rot_ws_bytes(m2) + 2 * align256(sizeof(float) * size_t(n_points)) +
              std::max(points_ws_bytes(m1->n, n_points, method), points_ws_bytes(m2->n, n_points, method));
     return GRF_OK;
@@ -590,7 +617,7 @@ int eval_pluri_points(const grf_modes* m1, const grf_modes* m2, const double* xy
     if ((rc = check_pair(m1, m2, fn))) return rc;
     if (n_points < 0) return fail(GRF_EINVAL, "%s: n_points < 0", fn);
     if (n_points > (int64_t(1) << 40)) return fail(GRF_EINVAL, "%s: too many points", fn);
-    if ((rc = check_points_method(fn, &method))) return rc;
+    if ((rc = check_points_method(fn, &method, n_points))) return rc;
     if ((rc = check_trunc2(rule, value != nullptr, fn))) return rc;
     if (n_points == 0) return GRF_OK;
     if (!facies && !value) return fail(GRF_EINVAL, "%s: facies or value output required", fn);
@@ -683,10 +710,7 @@ int eval_field_points_ws_size(const grf_modes* modes, int64_t n_points, int meth
     if ((rc = check_modes(modes, "eval_field_points_ws_size"))) return rc;
     if (!bytes) return fail(GRF_EINVAL, "eval_field_points_ws_size: bytes is NULL");
     if (n_points < 0) return fail(GRF_EINVAL, "eval_field_points_ws_size: n_points < 0");
-    if (method == GRF_AUTO) method = GRF_DIRECT_F32;
-    if (is_sep(method)) return fail(GRF_EUNSUPPORTED, "eval_field_points_ws_size: separable methods need a grid");
-    if (method != GRF_DIRECT_F32 && method != GRF_DIRECT_F64)
-        return fail(GRF_EINVAL, "eval_field_points_ws_size: unknown method %d", method);
+    if ((rc = check_points_method("eval_field_points_ws_size", &method, n_points))) return rc;
     *bytes = rot_ws_bytes(modes) + points_ws_bytes(modes->n, n_points, method);
     return GRF_OK;
 }
@@ -700,7 +724,7 @@ int eval_field_points(const grf_modes* modes, const double* xyz, int64_t n_point
     if ((rc = check_modes(modes, fn))) return rc;
     if (n_points < 0) return fail(GRF_EINVAL, "%s: n_points < 0", fn);
     if (n_points > (int64_t(1) << 40)) return fail(GRF_EINVAL, "%s: too many points", fn);
-    if ((rc = check_points_method(fn, &method))) return rc;
+    if ((rc = check_points_method(fn, &method, n_points))) return rc;
     if ((rc = check_epi(epi, k, ind, fn))) return rc;
     if (n_points == 0) return GRF_OK;
     if (!y && !k && !ind) return fail(GRF_EINVAL, "%s: no output requested", fn);

@@ -424,6 +424,25 @@ hipError_t launch_direct_points(const double* params, const double* w, int64_t n
     return hipGetLastError();
 }
 
+hipError_t launch_points_reduce(const float* partial, int slices, int64_t P, float amp, const Epi& epi, float* y,
+                                float* k, uint8_t* ind, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_points_reduce, dim3(static_cast<unsigned>((P + 255) / 256)), dim3(256), 0, s, partial, slices,
+                       P, amp, epi, y, k, ind);
+    return hipGetLastError();
+}
+
+int bin_mode_slices(int64_t P, int64_t n)
+{
+    // about 8192 work-item waves (several per SIMD); each slice keeps >= 64 modes
+    if (P <= 0 || n <= 0) return 1;
+    const int64_t waves = (P + kBinItemSlots - 1) / kBinItemSlots;
+    int64_t s = (8192 + waves - 1) / waves;
+    s = std::min<int64_t>(s, std::max<int64_t>(n / 64, 1));
+    s = std::min<int64_t>(s, 64);
+    return static_cast<int>(std::max<int64_t>(s, 1));
+}
+
 int points_mode_slices(int64_t P, int64_t n)
 {
     // Enough blocks to fill 256 CUs several times over; each slice keeps >= 64 modes.

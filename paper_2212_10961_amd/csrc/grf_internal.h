@@ -201,6 +201,48 @@ constexpr int kPointsPerLane = 8;
 int points_mode_slices(int64_t P, int64_t n);
 hipError_t launch_epilogue(const float* y, int64_t n, const Epi& epi, float* k, uint8_t* ind,
                            hipStream_t s);
+// out[p] = epilogue(amp * sum over slices of partial[slice][p]), slices added in order.
+hipError_t launch_points_reduce(const float* partial, int slices, int64_t P, float amp, const Epi& epi, float* y,
+                                float* k, uint8_t* ind, hipStream_t s);
+
+// ---------------------------------------------------------------- binned point sum (points.hip)
+// Points sorted into cubic cells of their bounding box, each cell's slots padded to whole work
+// items of kBinItemSlots; per (mode, work item) the phase at the cell centre is reduced in FP64
+// and the points' local phases are formed in FP32 by a matrix product on the matrix cores.
+constexpr int kBinItemSlots = 256;     // points per work item (one wave: 16 groups of 16)
+constexpr int kBinTarget = 2048;       // points per cell on average
+constexpr int kBinBboxBlocks = 512;    // blocks of the bounding-box pass
+constexpr int64_t kBinMinPoints = int64_t(1) << 16;  // GRF_DIRECT_F32 bins from this many points
+constexpr int64_t kBinMaxPoints = int64_t(1) << 30;  // (slot indices are 32-bit)
+struct BinGeom {
+    double lo[3];      // bounding-box corner
+    double s, inv_s;   // cell side and its reciprocal
+    int32_t n[3];      // cells per axis (x fastest)
+    int32_t ncell;
+    int64_t nslot;     // sorted slots: every cell padded to whole work items
+    int64_t nitem;     // nslot / kBinItemSlots
+    int32_t n64;       // modes whose local phase is reduced per point in FP64
+    int32_t pad_;
+};
+struct BinCaps {
+    int64_t cells, slots, items;
+};
+inline BinCaps bin_caps(int64_t P)
+{
+    BinCaps c;
+    c.cells = P / (kBinTarget / 2) + 64;
+    c.items = (P + (kBinItemSlots - 1) * c.cells + kBinItemSlots - 1) / kBinItemSlots;
+    c.slots = c.items * kBinItemSlots;
+    return c;
+}
+// Mode slices of the binned sum (partial sums per slice when > 1).
+int bin_mode_slices(int64_t P, int64_t n);
+// Workspace of the binned pass for P points and ldp padded modes (the per-slice partial sums
+// excluded: bin_mode_slices(P, n) * P floats when that is > 1).
+size_t bin_ws_bytes(int64_t P, int64_t ldp);
+hipError_t launch_points_binned(const double* params, const double* w, int64_t n, int64_t ldp, int dim,
+                                const double* xyz, int64_t P, float amp, const Epi& epi, float* y, float* k,
+                                uint8_t* ind, void* ws, float* partial, hipStream_t s);
 
 // ---------------------------------------------------------------- separable (matrix cores)
 // Y[z][y][x] = amp Re sum_j P[x,j] Q[y,j],  P = Ex[x,j] Ez[z,j] (3-D) or Ex (2-D),

@@ -474,6 +474,13 @@ def grid_workspace_bytes(modes: Modes, shape, method) -> int:
     return need.value
 
 
+def points_workspace_bytes(modes: Modes, n_points: int, method="direct_f32") -> int:
+    need = ctypes.c_size_t()
+    check(L.load().eval_field_points_ws_size(ctypes.byref(modes.c()), int(n_points), method_id(method),
+                                             ctypes.byref(need)))
+    return need.value
+
+
 def field_grid_f64(modes: Modes, shape, origin=None, h=None, mu=0.0, want_k=True, stream=None):
     """FP64 Y and K of the plain method on a structured grid."""
     lib = L.load()

@@ -216,6 +216,27 @@ def test_points_validation(lib):
                                  None, ctypes.c_void_p(16), b.value - 1, None) == L.GRF_ENOMEM
 
 
+def test_points_forms_validation_and_workspace(lib):
+    """The two FP32 point-sum forms: GRF_DIRECT_F32 takes the binned one from 65,536 points; the
+    binned form needs room for its sort; neither applies to grids."""
+    m = _modes(n=4096)
+    sz = {}
+    for meth in (L.GRF_DIRECT_F32, L.GRF_DIRECT_F32_BINNED, L.GRF_DIRECT_F32_POINTWISE, L.GRF_DIRECT_F64):
+        for P in (1, 65535, 65536, 2_000_000):
+            b = ctypes.c_size_t()
+            assert lib.eval_field_points_ws_size(ctypes.byref(m), P, meth, ctypes.byref(b)) == 0
+            sz[meth, P] = b.value
+    assert sz[L.GRF_DIRECT_F32, 65535] == sz[L.GRF_DIRECT_F32_POINTWISE, 65535]
+    assert sz[L.GRF_DIRECT_F32, 65536] == sz[L.GRF_DIRECT_F32_BINNED, 65536]
+    assert sz[L.GRF_DIRECT_F32_BINNED, 2_000_000] > 2_000_000 * 32  # one 32-byte record per point at least
+    b = ctypes.c_size_t()
+    assert lib.eval_field_points_ws_size(ctypes.byref(m), (1 << 30) + 1, L.GRF_DIRECT_F32_BINNED,
+                                         ctypes.byref(b)) == L.GRF_EUNSUPPORTED
+    assert lib.eval_field_points_ws_size(ctypes.byref(m), 10, 8, ctypes.byref(b)) == L.GRF_EINVAL
+    for meth in (L.GRF_DIRECT_F32_BINNED, L.GRF_DIRECT_F32_POINTWISE):
+        assert lib.eval_field_grid_ws_size(ctypes.byref(m), ctypes.byref(_grid()), meth, ctypes.byref(b)) == L.GRF_EINVAL
+
+
 def test_plan_validation(lib):
     h = ctypes.c_void_p()
     assert lib.grf_plan_create(ctypes.byref(h), L.GRF_DIRECT_F64, 0, None) == L.GRF_EINVAL
