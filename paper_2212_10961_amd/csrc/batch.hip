@@ -48,6 +48,9 @@ struct grf_plan {
     AxisTableArgs* d_tdesc = nullptr;
     uint64_t* d_tblk = nullptr;  // per work block: (descriptor << 40) | local block
     size_t cap_tdesc = 0;
+    GenModeDesc* d_gmd = nullptr;             // generated forms: per-instance mode-table descriptors
+    size_t cap_gmd = 0;
+    int64_t ldp_max = 0;
     unsigned long long* d_counter = nullptr;  // kMaxQueues counters, kQueueStride apart
     BatchQueue* d_queues = nullptr;           // in the same allocation, after the counters
     int nq = 1;
@@ -179,6 +182,10 @@ hipError_t enqueue(grf_plan* p, hipStream_t s, const void* items, int n_items_de
         e = launch_axis_tables_batched(p->d_tdesc, p->d_tblk, p->table_blocks, s);
         if (e != hipSuccess) return e;
     }
+    if (p->d_gmd && p->ldp_max > 0) {
+        e = launch_gen_modes(p->d_gmd, p->n_inst, p->ldp_max, s);
+        if (e != hipSuccess) return e;
+    }
     if (sep)
         return launch_sep_batch(p->method, p->d3, static_cast<const SepBatchItem*>(items), n_items_desc, p->d_queues,
                                 p->nq, p->d_counter, p->grid, s);
@@ -211,21 +218,82 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
     p->d3 = items[0].modes.dim == 3;
     const bool gen = sep && sep_batch_generates(p->method, p->d3);  // operands made on chip
 
-    // ---- table layout and descriptors (same tables as eval_field_grid would build); none
-    // when the kernel generates its operands
+    // ---- table layout and descriptors (same tables as eval_field_grid would build); for the
+    // generated forms, each instance's local x table and mode table instead
     std::vector<GridWs> ws(n);
     std::vector<size_t> toff(n);
     size_t tbytes = 0;
-    if (!gen) {
-        for (int32_t i = 0; i < n; ++i) {
+    for (int32_t i = 0; i < n; ++i) {
+        const int64_t ldp = padded_modes(items[i].modes.n);
+        toff[i] = tbytes;
+        if (gen) {
+            tbytes += align256(sizeof(uint32_t) * size_t(kGenRows) * size_t(ldp)) + align256(sizeof(GenMode) * size_t(ldp));
+        } else {
             ws[i] = grid_ws(&items[i].modes, &items[i].grid, p->method, nullptr);
-            toff[i] = tbytes;
             tbytes += ws[i].bytes;
         }
-        GRF_HIP(ensure(p->d_tables, p->cap_tables, tbytes));
     }
+    GRF_HIP(ensure(p->d_tables, p->cap_tables, tbytes));
     std::vector<AxisTableArgs> td;
     std::vector<uint64_t> blk;
+    std::vector<GenModeDesc> gmd;
+    std::vector<const uint32_t*> rx_of(n);
+    std::vector<const GenMode*> md_of(n);
+    p->ldp_max = 0;
+    if (gen) {
+        int64_t total = 0;
+        for (int32_t i = 0; i < n; ++i) {
+            const grf_modes& m = items[i].modes;
+            const grf_grid& gr = items[i].grid;
+            const int64_t ldp = padded_modes(m.n);
+            char* base = static_cast<char*>(p->d_tables) + toff[i];
+            AxisTableArgs t{};
+            t.z = m.z;
+            t.phi = m.phi;
+            t.n = m.n;
+            t.ldp = ldp;
+            t.axis = 0;
+            t.ell = m.ell[0];
+            t.freq_scale = 1.0 / (6.283185307179586476925286766559 * m.ell[0]);
+            t.origin = -0.5 * gr.h[0];  // entry r at x = r hx: R_j(r) = e^{2 pi i a_x r hx}
+            t.h = gr.h[0];
+            t.count = kGenRows;
+            t.with_psi = false;
+            t.conj = true;
+            t.fast_trig = true;  // one fp16/bf16 rounding of the operand
+            t.blocked = true;
+            t.format = is_bf16(p->method) ? TF_BF16 : TF_F16;
+            t.out = base;
+            t.out_lo = nullptr;
+            t.w = nullptr;
+            rx_of[i] = static_cast<const uint32_t*>(t.out);
+            td.push_back(t);
+            total += axis_table_blocks(t);
+            GenModeDesc g{};
+            g.z = m.z;
+            g.phi = m.phi;
+            g.w = m.w;
+            g.n = m.n;
+            g.ldp = ldp;
+            g.fsx = t.freq_scale;
+            g.fsy = 1.0 / (6.283185307179586476925286766559 * m.ell[1]);
+            g.ox = gr.origin[0];
+            g.oy = gr.origin[1];
+            g.hx = gr.h[0];
+            g.hy = gr.h[1];
+            g.out = reinterpret_cast<GenMode*>(base + align256(sizeof(uint32_t) * size_t(kGenRows) * size_t(ldp)));
+            md_of[i] = g.out;
+            gmd.push_back(g);
+            p->ldp_max = std::max(p->ldp_max, ldp);
+        }
+        if (total > 0x7fffffff) return fail(GRF_EINVAL, "%s: batch tables too large for one launch", fn);
+        for (size_t di = 0; di < td.size(); ++di) {
+            const int64_t nb = axis_table_blocks(td[di]);
+            for (int64_t w = 0; w < nb; ++w) blk.push_back((static_cast<uint64_t>(di) << 40) | static_cast<uint64_t>(w));
+        }
+        GRF_HIP(ensure(p->d_gmd, p->cap_gmd, gmd.size() * sizeof(GenModeDesc)));
+        GRF_HIP(hipMemcpy(p->d_gmd, gmd.data(), gmd.size() * sizeof(GenModeDesc), hipMemcpyHostToDevice));
+    }
     if (!gen) {
         int64_t total = 0;
         for (int32_t i = 0; i < n; ++i) {
@@ -331,14 +399,8 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
             GenArgs& g = si[i].g;
             g = GenArgs{};
             if (gen) {
-                constexpr double kTwoPi = 6.283185307179586476925286766559;
-                g.z = it.modes.z;
-                g.phi = it.modes.phi;
-                g.w = it.modes.w;
-                g.fsx = 1.0 / (kTwoPi * it.modes.ell[0]);
-                g.fsy = 1.0 / (kTwoPi * it.modes.ell[1]);
-                g.ox = it.grid.origin[0];
-                g.oy = it.grid.origin[1];
+                g.rx = rx_of[i];
+                g.md = md_of[i];
                 g.hx = it.grid.h[0];
                 g.hy = it.grid.h[1];
             }
@@ -363,6 +425,7 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
         if (!pending.empty()) {
             if (p->table_blocks > 0)
                 GRF_HIP(launch_axis_tables_batched(p->d_tdesc, p->d_tblk, p->table_blocks, p->cap));
+            if (gen) GRF_HIP(launch_gen_modes(p->d_gmd, n, p->ldp_max, p->cap));
             hipEvent_t e0, e1;
             GRF_HIP(hipEventCreate(&e0));
             GRF_HIP(hipEventCreate(&e1));
@@ -506,7 +569,7 @@ int grf_plan_create(grf_plan** plan, int method, int flags, const char* tune_cac
 int grf_plan_destroy(grf_plan* p)
 {
     if (!p) return GRF_OK;
-    const bool touched = p->cap || p->d_tables || p->d_items || p->d_tdesc || p->d_counter;
+    const bool touched = p->cap || p->d_tables || p->d_items || p->d_tdesc || p->d_counter || p->d_gmd;
     if (touched) {
         // Launches of this plan may still be queued on the caller's streams.
         if (p->cap) hipStreamSynchronize(p->cap);
@@ -517,6 +580,7 @@ int grf_plan_destroy(grf_plan* p)
     if (p->d_items) hipFree(p->d_items);
     if (p->d_tdesc) hipFree(p->d_tdesc);
     if (p->d_counter) hipFree(p->d_counter);
+    if (p->d_gmd) hipFree(p->d_gmd);
     if (p->cap) hipStreamDestroy(p->cap);
     delete p;
     return GRF_OK;

@@ -275,15 +275,36 @@ int sep_tile_slices(int tile, int method, bool d3);  // z-slices per block
 int sep_default_tile(int method, int64_t nx, int64_t ny, int64_t nz);
 
 // ---------------------------------------------------------------- batched (persistent) launches
-// Per-mode inputs of a 2-D one-pass separable tile whose operands are generated on chip
-// (no per-axis tables in memory): a_{j,x} = z[0][j] fsx, a_{j,y} = z[1][j] fsy revolutions
-// per unit length, psi_j = phi_j / 2 pi and the weight w_j ride on the y operand.
-struct GenArgs {
+// Generated operands of the 2-D one-pass separable batch tiles.  With E_j(x) = e^{2 pi i a_x x}
+// and Q_j(y) = w_j e^{2 pi i (a_y y + psi_j)}, a tile at (x0, y0) of an instance is
+//   Y[y0 + s][x0 + r] = A Re sum_j [Q_j(y0 + s) E_j(x0)] R_j(r),   R_j(r) = e^{2 pi i a_x r hx},
+// so its x-side operand R is the same for every tile of the instance (a local table of
+// kGenRows rows made once per batch call), and only the y side, which carries the tile's
+// x0 phase, is generated on chip per tile.
+constexpr int kGenRows = 128;  // rows of the local x table (the widest tile)
+struct alignas(16) GenMode {
+    double ax, ay;  // revolutions per unit length along x and y
+    double psi;     // phase of cell (0, 0): psi_j + a_y (oy + hy / 2) + a_x (ox + hx / 2)
+    float w;        // weight (0 for padding modes)
+    float rc, rs;   // e^{2 pi i frac(a_y hy)}: the step from one row to the next
+    float pad_[3];
+};
+static_assert(sizeof(GenMode) == 48, "three 16-byte loads per mode");
+struct GenModeDesc {
     const double* z;    // [2][n]
     const double* phi;  // [n]
     const double* w;    // [n] or nullptr
+    int64_t n, ldp;
     double fsx, fsy;    // 1 / (2 pi ell_x), 1 / (2 pi ell_y)
     double ox, oy, hx, hy;
+    GenMode* out;       // [ldp]
+};
+// out[j] of every descriptor (one block row per instance, ldp_max >= every ldp).
+hipError_t launch_gen_modes(const GenModeDesc* d, int n_inst, int64_t ldp_max, hipStream_t s);
+struct GenArgs {
+    const uint32_t* rx;  // local x table: stage-major [ldp / 32][kGenRows][32] (Re, -Im) fp16/bf16 pairs
+    const GenMode* md;   // [ldp]
+    double hx, hy;
 };
 
 // One descriptor per instance; work items [item0, item0 + tiles_x * tiles_y * nz) belong to it.

@@ -763,18 +763,18 @@ using SmallT3 = SepShape<2, 2, 1, 1, true>;
 
 // ---- operands generated on chip (2-D one-pass fp16/bf16, batched ensembles) ------------
 //
-// On a 2-D grid the per-axis tables hold (nx + ny) N complex entries against nx ny cells:
-// for the grids of an ensemble (sides of a few hundred) they are several times larger than
-// the field, and writing them to memory and streaming them back dominates.  Here a block
-// generates each operand stage in LDS itself.  Thread (quad q, segment) owns modes
-// 4q .. 4q + 3 of the stage and RPT consecutive rows of one operand: the first row's phase is
-// formed and reduced in FP64 exactly as the tables are (frac(a x + psi), hardware cos/sin of
-// the fraction in revolutions, times w), and each further row is one FP32 complex product
-// with the step e^{2 pi i frac(a h)} (at most 7 of them: a relative error ~1e-6, far below
-// the fp16/bf16 rounding of the operand).  Stage s + 1 is generated while the MFMAs consume
-// stage s; the LDS layout and the fragment reads are those of the staged tiles.
-constexpr double kInvTwoPiD = 0.15915494309189533576888376337251;
-
+// On a 2-D grid the per-axis tables hold (nx + ny) N complex entries against nx ny cells: for
+// the grids of an ensemble (sides of a few hundred) writing whole tables and streaming them
+// back costs more than the contraction.  Here the x side of a tile is the instance's local
+// table R_j(r) = e^{2 pi i a_x r hx} (r < kGenRows, the same for every tile of the instance:
+// see GenArgs), staged straight into LDS, and the block generates the y side, which carries
+// the tile's x0 phase, in LDS itself: thread (pair p, segment) owns modes 2p, 2p + 1 of the
+// stage and RPT consecutive rows; the first row's phase psi' + a_y (y0 + r0) hy + a_x x0 hx is
+// formed and reduced in FP64 (hardware cos/sin of the fraction in revolutions, times w), and
+// each further row is one FP32 complex product with the step e^{2 pi i frac(a_y hy)} (at most
+// 7 of them: a relative error ~1e-6, far below the fp16/bf16 rounding of the operand).  Stage
+// s + 1 is generated and loaded while the MFMAs consume stage s; the LDS layout and the
+// fragment reads are those of the staged tiles.
 template <bool BF>
 __device__ __forceinline__ uint32_t pack2(float re, float im)
 {
@@ -795,87 +795,74 @@ __device__ __forceinline__ void sep_tile_gen(const SepArgs& a, const GenArgs& g,
     constexpr int WN = 2;
     constexpr int BM = 2 * TM * 32, BN = WN * TN * 32;
     constexpr int ROW_B = kJC * 4;
-    constexpr int RPT = (BM + BN) / 32;  // rows per thread: 256 threads = 8 quads x 32 segments
-    static_assert(BM % RPT == 0 && RPT <= 8, "a segment lies in one operand");
+    constexpr int RPT = BM / 16;        // rows per thread: 16 mode pairs x 16 segments
+    constexpr int KB = BN / 32;         // B load instructions per wave and stage (8 rows each)
+    static_assert(RPT >= 1 && RPT <= 8 && BN <= kGenRows, "tile shape");
     const int t = threadIdx.x;
     const int l = t & 63, h = l >> 5;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int wm = wave / WN, wn = wave % WN;
     const int64_t x0 = tx * BN, y0 = ty * BM;
 
-    // generation role: quad q of every stage, rows r0 .. r0 + RPT - 1 of the y operand (A) or
-    // of the x operand (B, stored conjugated)
-    // (the first two waves make the y operand, the last two the x operand: a wave-uniform role)
-    typedef const double __attribute__((address_space(1)))* gptr;
-    const int q = t & 7, seg = t >> 3;
-    const bool ya = __builtin_amdgcn_readfirstlane(static_cast<int>(seg * RPT < BM)) != 0;
-    const int r0 = ya ? seg * RPT : seg * RPT - BM;
-    const int lbase = ya ? 0 : BM * ROW_B;
-    const double hh = ya ? g.hy : g.hx, fs = ya ? g.fsy : g.fsx;
-    const double xr0 = (ya ? g.oy : g.ox) + (static_cast<double>((ya ? y0 : x0) + r0) + 0.5) * hh;
-    const gptr za = (gptr)(g.z + (ya ? a.n : 0));  // address-space cast: global loads
-    const gptr gphi = (gptr)(g.phi);
-    const gptr gw = (gptr)(g.w);
-    const bool use_w = ya && g.w != nullptr;
-    const float sg = ya ? 1.f : -1.f;
+    // generation role: modes 2p, 2p + 1 of every stage, rows r0 .. r0 + RPT - 1 of the y operand
+    const int p = t & 15, seg = t >> 4;
+    const int r0 = seg * RPT;
+    const double yoff = static_cast<double>(y0 + r0) * g.hy, xoff = static_cast<double>(x0) * g.hx;
     int soff[RPT];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) soff[r] = lbase + (r0 + r) * ROW_B + ((q ^ swz(r0 + r)) << 4);
+    for (int r = 0; r < RPT; ++r) soff[r] = (r0 + r) * ROW_B + (((p >> 1) ^ swz(r0 + r)) << 4) + ((p & 1) << 3);
 
-    // per-mode inputs of one stage for this thread's quad, loaded a stage ahead of their use
-    // (padding modes j >= n load mode 0 and are zeroed: zero weight and phase)
-    struct Params {
-        double z[4], p[4];
-        float w[4];
+    // x-side rows [BM, BM + BN) of a stage: instruction k of this wave fills rows 8 rb .. 8 rb + 7
+    int32_t offb[KB];
+    int ldb[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const int rb = wave * KB + k;
+        const int row = rb * 8 + (l >> 3);
+        offb[k] = row * kJC + 4 * ((l & 7) ^ swz(row));
+        ldb[k] = BM * ROW_B + rb * 8 * ROW_B;
+    }
+    auto issue = [&](int64_t s, char* buf) {
+        const uint32_t* src = g.rx + s * (kGenRows * kJC);
+#pragma unroll
+        for (int k = 0; k < KB; ++k) load_to_lds(src + offb[k], buf + ldb[k]);
     };
-    auto load = [&](int64_t j0, Params& pr) {
-        if (j0 + kJC <= a.n) {  // every mode of the stage is a real one (all but the last stage)
+
+    typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+    typedef const u32x4 __attribute__((address_space(1)))* gq;
+    struct Params {
+        GenMode m[2];
+    };
+    auto load = [&](int64_t s, Params& pr) {
+        // three 16-byte global loads per mode (address-space cast: global, not flat, loads)
+        const gq src = (gq)(g.md + s * kJC + 2 * p);
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int64_t j = j0 + 4 * q + m;
-                pr.z[m] = za[j];
-                pr.p[m] = ya ? gphi[j] : 0.0;
-                pr.w[m] = use_w ? static_cast<float>(gw[j]) : 1.f;
-            }
-        } else {
+        for (int m = 0; m < 2; ++m) {
+            struct Raw {
+                u32x4 q[3];
+            } raw;
 #pragma unroll
-            for (int m = 0; m < 4; ++m) {
-                const int64_t j = j0 + 4 * q + m;
-                const bool on = j < a.n;
-                const int64_t jc = on ? j : 0;
-                const double zv = za[jc], pv = ya ? gphi[jc] : 0.0;
-                const float wv = use_w ? static_cast<float>(gw[jc]) : 1.f;
-                pr.z[m] = on ? zv : 0.0;  // a padding mode has zero weight (and zero phase)
-                pr.p[m] = on ? pv : 0.0;
-                pr.w[m] = on ? wv : 0.f;
-            }
+            for (int c = 0; c < 3; ++c) raw.q[c] = src[3 * m + c];
+            pr.m[m] = __builtin_bit_cast(GenMode, raw);
         }
     };
     auto gen = [&](const Params& pr, char* buf) {
-        float er[4], ei[4], rr[4], ri[4];
+        float er[2], ei[2];
 #pragma unroll
-        for (int m = 0; m < 4; ++m) {
-            const double am = pr.z[m] * fs;
-            const double ps = pr.p[m] * kInvTwoPiD;
-            const float wj = pr.w[m];
-            const double t0 = am * xr0 + ps;
-            const double th = am * hh;
+        for (int m = 0; m < 2; ++m) {
+            const double t0 = fma(pr.m[m].ay, yoff, fma(pr.m[m].ax, xoff, pr.m[m].psi));
             const float f0 = static_cast<float>(t0 - floor(t0));  // exact in FP64
-            const float fh = static_cast<float>(th - floor(th));
-            er[m] = __builtin_amdgcn_cosf(f0) * wj;
-            ei[m] = __builtin_amdgcn_sinf(f0) * sg * wj;
-            rr[m] = __builtin_amdgcn_cosf(fh);
-            ri[m] = __builtin_amdgcn_sinf(fh) * sg;
+            er[m] = __builtin_amdgcn_cosf(f0) * pr.m[m].w;
+            ei[m] = __builtin_amdgcn_sinf(f0) * pr.m[m].w;
         }
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            *reinterpret_cast<uint4*>(buf + soff[r]) = make_uint4(pack2<BF>(er[0], ei[0]), pack2<BF>(er[1], ei[1]),
-                                                                  pack2<BF>(er[2], ei[2]), pack2<BF>(er[3], ei[3]));
+            *reinterpret_cast<uint2*>(buf + soff[r]) = make_uint2(pack2<BF>(er[0], ei[0]), pack2<BF>(er[1], ei[1]));
             if (r + 1 < RPT) {
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    float nr = fmaf(er[m], rr[m], -ei[m] * ri[m]);
-                    float ni = fmaf(er[m], ri[m], ei[m] * rr[m]);
+                for (int m = 0; m < 2; ++m) {
+                    float nr = fmaf(er[m], pr.m[m].rc, -ei[m] * pr.m[m].rs);
+                    float ni = fmaf(er[m], pr.m[m].rs, ei[m] * pr.m[m].rc);
                     // opaque: the next row's pack converts these values (one v_cvt_pk) instead
                     // of the compiler recomputing the products in mixed precision
                     asm("" : "+v"(nr), "+v"(ni));
@@ -921,24 +908,31 @@ __device__ __forceinline__ void sep_tile_gen(const SepArgs& a, const GenArgs& g,
         }
     };
 
-    // two stages per iteration (ldp is a multiple of 64): stage s + 1 is generated into the
-    // other buffer while stage s feeds the MFMAs; the barrier after each half hands it over
+    // two stages per iteration (ldp is a multiple of 64): stage s + 1 is loaded and generated
+    // into the other buffer while stage s feeds the MFMAs; the barrier after each half hands
+    // it over
     char* b0 = reinterpret_cast<char*>(lds0);
     char* b1 = reinterpret_cast<char*>(lds1);
     const int64_t nstage = a.ldp / kJC;
     Params p0, p1;
     load(0, p0);
-    load(kJC, p1);
+    load(1, p1);
+    issue(0, b0);
     gen(p0, b0);
+    wait_loads();
     __syncthreads();
     for (int64_t s = 0; s < nstage; s += 2) {
-        if (s + 2 < nstage) load((s + 2) * kJC, p0);
+        issue(s + 1, b1);
+        if (s + 2 < nstage) load(s + 2, p0);
         gen(p1, b1);
         compute(b0);
+        wait_loads();
         __syncthreads();
-        if (s + 3 < nstage) load((s + 3) * kJC, p1);
+        if (s + 2 < nstage) issue(s + 2, b0);
+        if (s + 3 < nstage) load(s + 3, p1);
         if (s + 2 < nstage) gen(p0, b0);
         compute(b1);
+        wait_loads();
         __syncthreads();
     }
 

@@ -240,6 +240,29 @@ __global__ __launch_bounds__(256) void k_mode_params(const double* z, const doub
     out[j] = p;
 }
 
+// Per-mode inputs of the generated batch tiles, one block row per instance.
+__global__ __launch_bounds__(256) void k_gen_modes(const GenModeDesc* __restrict__ descs)
+{
+    const GenModeDesc d = descs[blockIdx.y];
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    if (j >= d.ldp) return;
+    GenMode m{};
+    m.rc = 1.f;
+    if (j < d.n) {
+        constexpr double kInvTwoPi = 0.15915494309189533576888376337251;
+        const double ax = d.z[j] * d.fsx, ay = d.z[d.n + j] * d.fsy;
+        m.ax = ax;
+        m.ay = ay;
+        m.psi = d.phi[j] * kInvTwoPi + ay * (d.oy + 0.5 * d.hy) + ax * (d.ox + 0.5 * d.hx);
+        m.w = d.w ? static_cast<float>(d.w[j]) : 1.f;
+        const double th = ay * d.hy;
+        const float fh = static_cast<float>(th - floor(th));  // exact in FP64
+        m.rc = __builtin_amdgcn_cosf(fh);
+        m.rs = __builtin_amdgcn_sinf(fh);
+    }
+    d.out[j] = m;
+}
+
 }  // namespace
 
 int64_t axis_table_blocks(const AxisTableArgs& a) { return ((a.count + kTabRows - 1) / kTabRows) * ((a.ldp + 255) / 256); }
@@ -313,6 +336,14 @@ hipError_t launch_mode_params(const double* z, const double* phi, int dim, int64
     const int64_t blocks = (ldp + 255) / 256;
     hipLaunchKernelGGL(k_mode_params, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, z, phi, dim, n, ldp,
                        ell[0], ell[1], dim == 3 ? ell[2] : 1.0, reinterpret_cast<double4*>(out));
+    return hipGetLastError();
+}
+
+hipError_t launch_gen_modes(const GenModeDesc* d, int n_inst, int64_t ldp_max, hipStream_t s)
+{
+    if (n_inst < 1) return hipSuccess;
+    const dim3 grid(static_cast<unsigned>((ldp_max + 255) / 256), static_cast<unsigned>(n_inst));
+    hipLaunchKernelGGL(k_gen_modes, grid, dim3(256), 0, s, d);
     return hipGetLastError();
 }
 
