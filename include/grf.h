@@ -378,8 +378,8 @@ typedef struct grf_krige {
     double nugget;   /* >= 0: nugget * sigma^2 is added to the diagonal of C(X, X) */
 } grf_krige;
 
-/* Workspace of krige_weights: the FP64 M x M matrix, its factored 32 x 32 diagonal blocks, residuals,
- * and the point evaluation of Y. */
+/* Workspace of krige_weights: the FP64 M x M matrix, the inverses of its 64 x 64 diagonal
+ * factors, two FP64 vectors of the substitutions, and the point evaluation of Y. */
 int krige_weights_ws_size(const grf_modes* modes, int64_t n_obs, size_t* bytes);
 
 /*

@@ -553,7 +553,7 @@ namespace grf {
 // Per-mode parameters and the point sum with a prepared epilogue (validated by the caller;
 // `ws` holds points_ws_bytes(...)).
 static int points_launch(const grf_modes* modes, const double* xyz, int64_t n_points, int method, const Epi& e,
-                         float* y, float* k, uint8_t* ind, void* ws, hipStream_t s)
+                         float* y, float* k, uint8_t* ind, void* ws, hipStream_t s, bool timed = true)
 {
     const int64_t ldp = padded_modes(modes->n);
     method = resolve_points_f32(method, n_points);
@@ -571,7 +571,7 @@ static int points_launch(const grf_modes* modes, const double* xyz, int64_t n_po
     float* partial = method == GRF_DIRECT_F32_POINTWISE
                          ? c.take<float>(size_t(points_mode_slices(n_points, modes->n)) * n_points)
                          : nullptr;
-    TimedScope timed(s);
+    TimedScope scope(s, timed);
     GRF_HIP(launch_direct_points(params, modes->w, modes->n, modes->dim, xyz, n_points, method == GRF_DIRECT_F64, amp,
                                  e, y, k, ind, partial, s));
     return GRF_OK;
@@ -775,9 +775,9 @@ static int make_krige_model(const grf_modes* m, const grf_krige* kp, const char*
 
 static size_t krige_ws(const grf_modes* m, int64_t M)
 {
-    const size_t nblk = size_t((M + 31) / 32);
-    return align256(sizeof(double) * size_t(M) * size_t(M)) + align256(sizeof(double) * size_t(M)) +
-           align256(sizeof(float) * size_t(M)) + align256(sizeof(double) * nblk * 32 * 32) + rot_ws_bytes(m) +
+    const size_t nblk = size_t((M + 63) / 64);
+    return align256(sizeof(double) * size_t(M) * size_t(M)) + 2 * align256(sizeof(double) * size_t(M)) +
+           align256(sizeof(float) * size_t(M)) + align256(sizeof(double) * nblk * 64 * 64) + rot_ws_bytes(m) +
            points_ws_bytes(m->n, M, GRF_DIRECT_F32);
 }
 
@@ -814,20 +814,21 @@ int krige_weights(const grf_modes* modes, const grf_krige* kp, const double* xob
     Carve c(ws);
     double* C = c.take<double>(size_t(M) * size_t(M));
     double* resid = c.take<double>(size_t(M));
+    double* zf = c.take<double>(size_t(M));
     float* yu = c.take<float>(size_t(M));
-    double* diag = c.take<double>(size_t((M + 31) / 32) * 32 * 32);
+    double* dinv = c.take<double>(size_t((M + 63) / 64) * 64 * 64);
     void* kbuf = c.base + c.used;
     c.used += rot_ws_bytes(modes);
     void* pws = c.base + c.used;
     if (info) GRF_HIP(launch_fill_i32(info, 0, s));
     grf_modes am;
     GRF_HIP(aligned_modes(modes, kbuf, s, &am));
-    if ((rc = points_launch(&am, xobs, M, GRF_DIRECT_F32, Epi{}, yu, nullptr, nullptr, pws, s))) return rc;
+    if ((rc = points_launch(&am, xobs, M, GRF_DIRECT_F32, Epi{}, yu, nullptr, nullptr, pws, s, false))) return rc;
     GRF_HIP(launch_residual(dobs, yu, M, resid, s));
     GRF_HIP(launch_cov_matrix(xobs, M, modes->dim, km, C, M, s));
     TimedScope timed(s);
-    GRF_HIP(launch_cholesky(C, M, M, diag, info, s));
-    GRF_HIP(launch_chol_solve(C, diag, M, M, resid, alpha, s));
+    GRF_HIP(launch_cholesky(C, M, M, dinv, resid, zf, info, s));
+    GRF_HIP(launch_chol_back(C, M, M, dinv, resid, zf, alpha, s));
     return GRF_OK;
 }
 

@@ -41,8 +41,15 @@ void timer_mark(hipStream_t s, bool begin);
 bool timer_take_pair(hipEvent_t* start, hipEvent_t* stop);
 struct TimedScope {
     hipStream_t s;
-    explicit TimedScope(hipStream_t st) : s(st) { timer_mark(s, true); }
-    ~TimedScope() { timer_mark(s, false); }
+    bool on;
+    explicit TimedScope(hipStream_t st, bool enabled = true) : s(st), on(enabled)
+    {
+        if (on) timer_mark(s, true);
+    }
+    ~TimedScope()
+    {
+        if (on) timer_mark(s, false);
+    }
 };
 
 // ---------------------------------------------------------------- epilogue
@@ -436,12 +443,15 @@ struct KrigeTarget {
 };
 hipError_t launch_cov_matrix(const double* x, int64_t m, int dim, const KrigeModel& km, double* C, int64_t lda,
                              hipStream_t s);
-// Lower Cholesky factor of A in place (below the diagonal blocks); the factored 32 x 32
-// diagonal blocks go to `diag` (ceil(m / 32) blocks of 32 x 32 doubles).
-hipError_t launch_cholesky(double* A, int64_t m, int64_t lda, double* diag, int32_t* info, hipStream_t s);
-// x = (L L^T)^-1 b with the factor of launch_cholesky; b (m doubles) is overwritten.
-hipError_t launch_chol_solve(const double* L, const double* diag, int64_t m, int64_t lda, double* b, double* x,
-                             hipStream_t s);
+// Blocked Cholesky A = L L^T (64-wide blocks; A's lower triangle is consumed) with the forward
+// substitution L z = r: L below the diagonal blocks goes, transposed, to A's upper triangle;
+// the inverses of the diagonal factors to `dinv` (ceil(m / 64) blocks of 64 x 64 doubles); r
+// (m doubles) is updated in place and z (m doubles) receives every block of z but the last.
+hipError_t launch_cholesky(double* A, int64_t m, int64_t lda, double* dinv, double* r, double* z, int32_t* info,
+                           hipStream_t s);
+// Backward substitution L^T x = z with the output of launch_cholesky (z is overwritten).
+hipError_t launch_chol_back(const double* A, int64_t m, int64_t lda, const double* dinv, const double* r, double* z,
+                            double* x, hipStream_t s);
 hipError_t launch_residual(const float* d, const float* y, int64_t m, double* r, hipStream_t s);
 hipError_t launch_krige_stage(const double* x, const double* alpha, int64_t m, int dim, const KrigeModel& km,
                               float4* out, hipStream_t s);

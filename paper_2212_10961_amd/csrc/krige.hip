@@ -4,11 +4,13 @@
 // with the model covariance C(dx) = sigma^2 rho(|M^T dx|), M = R diag(1/ell) (the same
 // anisotropy as the field's wavevectors k = M z; App. A correlations).
 //
-// The M x M system is factorised in FP64 by a blocked right-looking Cholesky (diagonal block
-// factored by every panel workgroup, panel triangular solve, trailing update), solved by
-// blocked substitution (one launch
-// per block and direction, the right-hand side updated by many workgroups), and the
-// correction is summed in FP32 with observation chunks staged in LDS.
+// The M x M system is factorised in FP64 by a right-looking blocked Cholesky with 64-wide
+// panels, one launch per panel: the panel's rows are solved against the stored inverse of its
+// diagonal factor and the trailing matrix updated on the FP64 matrix cores, the forward
+// substitution rides along as an extra row, and the workgroup that updates the next diagonal
+// block factors and inverts it.  The backward substitution takes one launch per block (the
+// block solve is a product with the stored inverse).  The correction is summed in FP32 with
+// observation chunks staged in LDS.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -19,7 +21,8 @@ namespace grf {
 
 namespace {
 
-constexpr int kNb = 32;  // Cholesky block
+constexpr int kB = 64;        // Cholesky block and panel width
+constexpr int kLd = kB + 2;   // LDS row stride in doubles: matrix-core operand reads hit distinct banks
 
 // rho(r^2) of the standardised covariance (App. A): Gaussian exp(-r^2), exponential exp(-r),
 // Matern 3/2 (1 + sqrt3 r) exp(-sqrt3 r), Matern 5/2 (1 + sqrt5 r + 5 r^2/3) exp(-sqrt5 r).
@@ -88,252 +91,511 @@ __device__ __forceinline__ double lane_bcast(double v, int src)
     return __builtin_bit_cast(double, (static_cast<uint64_t>(hi) << 32) | lo);
 }
 
-// Unblocked factorisation of an nb x nb diagonal block by one wave: lane r holds row r
-// (entries c <= r) in `row` on entry and the factor's row on exit; column j goes through the
-// LDS scratch `col` for the rank-1 update.  Returns the first non-positive pivot (1-based,
-// counted from the matrix's first row via k0) or 0; the factor then carries NaN.
-__device__ __forceinline__ int factor_block(double (&row)[kNb], int nb, int64_t k0, double* col)
+typedef double v4d __attribute__((ext_vector_type(4)));
+
+// One FP64 matrix-core step D = A B + C on 16 x 16 x 4: lane l supplies A[l % 16][l / 16] and
+// B[l / 16][l % 16] and holds D[4 e + l / 16][l % 16] in element e (the FP64 form interleaves
+// its output rows across the four lane groups, unlike the 16-bit forms).
+__device__ __forceinline__ v4d mfma64(double a, double b, v4d c)
 {
-    const int r = threadIdx.x;
-    int bad = 0;
-#pragma unroll
-    for (int j = 0; j < kNb; ++j) {
-        if (j < nb) {
-            // pivot of column j, from lane j
-            const double d = lane_bcast(row[j], j);
-            const double sd = d > 0.0 ? sqrt(d) : __builtin_nan("");
-            if (!(d > 0.0) && bad == 0) bad = static_cast<int>(k0 + j + 1);
-            if (r == j) row[j] = sd;
-            if (r > j && r < nb) row[j] /= sd;
-            if (r < kNb) col[r] = row[j];
-            // one wave, whose LDS accesses complete in program order: a compiler barrier
-            // orders the column's stores before the reads and the reads before the next
-            // column's stores
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int c = j + 1; c < kNb; ++c)
-                if (c <= r && r < nb) row[c] -= row[j] * col[c];
-            __builtin_amdgcn_wave_barrier();
-        }
-    }
-    return bad;
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
-// One panel step of the Cholesky factorisation, one wave per workgroup: the factor L_kk of
-// the diagonal block [k0, k0 + nb) is either made here (first panel: every workgroup factors
-// the block itself, workgroup 0 stores it in `dk` (32 x 32, row-major) and the first
-// non-positive pivot in `info`) or read from `dk`, where the preceding trailing update left
-// it; then each workgroup solves its panel rows i >= k0 + nb: L[i][k0 ..] = A[i][k0 ..]
-// L_kk^-T.  A's diagonal block is only read, so the redundant factorisations never race.
-__global__ __launch_bounds__(64) void k_potrf_trsm(double* __restrict__ A, int64_t m, int64_t lda, int64_t k0,
-                                                  double* __restrict__ dk, int32_t* __restrict__ info,
-                                                  int prefactored)
-{
-    __shared__ double col[kNb];
-    __shared__ double L[kNb][kNb + 1];
-    __shared__ double dinv[kNb];
-    const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
-    const int r = threadIdx.x;
-    if (prefactored) {
-        if (r < kNb) {
-#pragma unroll
-            for (int c = 0; c < kNb; ++c) L[r][c] = dk[r * kNb + c];
-        }
-    } else {
-        double row[kNb];
-#pragma unroll
-        for (int c = 0; c < kNb; ++c) row[c] = (r < nb && c <= r) ? A[(k0 + r) * lda + k0 + c] : 0.0;
-        const int bad = factor_block(row, nb, k0, col);
-        if (r < kNb) {
-#pragma unroll
-            for (int c = 0; c < kNb; ++c) L[r][c] = c <= r ? row[c] : 0.0;
-        }
-        if (blockIdx.x == 0) {
-            if (r == 0 && bad && info && *info == 0) *info = bad;
-            if (r < kNb) {
-#pragma unroll
-                for (int c = 0; c < kNb; ++c) dk[r * kNb + c] = L[r][c];
-            }
-        }
-    }
-    __syncthreads();
-    if (r < nb) dinv[r] = 1.0 / L[r][r];  // the substitution below multiplies by reciprocals
-    __syncthreads();
-    const int64_t i = k0 + nb + static_cast<int64_t>(blockIdx.x) * blockDim.x + r;
-    if (i >= m) return;
-    double* prow = A + i * lda + k0;
-    double x[kNb];
-#pragma unroll
-    for (int j = 0; j < kNb; ++j) {
-        if (j < nb) {
-            double v = prow[j];
-            for (int l = 0; l < j; ++l) v -= x[l] * L[j][l];
-            x[j] = v * dinv[j];
-        }
-    }
-#pragma unroll
-    for (int j = 0; j < kNb; ++j)
-        if (j < nb) prow[j] = x[j];
-}
+using Blk = double[kB][kLd];
 
-// Trailing update A[i][j] -= sum_l L[i][l] L[j][l] over the panel columns [k0, k0 + nb), for
-// rows and columns past the panel, lower triangle; 32 x 32 output tiles, 4 entries per thread.
-// The workgroup of tile (0, 0), which updates the next panel's diagonal block, then factors
-// it (its first wave, from the updated values kept in LDS) into `dk_next` and records a
-// non-positive pivot in `info`: the next panel step reads the factor instead of making it.
-__global__ __launch_bounds__(256) void k_syrk_update(double* __restrict__ A, int64_t m, int64_t lda, int64_t k0,
-                                                     double* __restrict__ dk_next, int32_t* __restrict__ info)
+// acc += s X Y^T over the 64 columns of the LDS blocks X and Y (s = -1 when `neg`), for the
+// 32 x 32 quadrant of the 64 x 64 product that wave w owns (rows 32 (w / 2), columns 32 (w % 2)),
+// as 2 x 2 tiles of 16 x 16.
+__device__ __forceinline__ void gemm_nt(const Blk& X, const Blk& Y, v4d (&acc)[2][2], bool neg)
 {
-    __shared__ double Li[32][kNb + 1];
-    __shared__ double Lj[32][kNb + 1];
-    __shared__ double T[kNb][kNb + 1];
-    __shared__ double colbuf[kNb];
-    const int64_t s0 = k0 + kNb;  // first trailing row/column (only called when a full panel precedes it)
-    const int64_t ti = blockIdx.y, tj = blockIdx.x;
-    if (tj > ti) return;
-    const int64_t i0 = s0 + ti * 32, j0 = s0 + tj * 32;
-    for (int e = threadIdx.x; e < 32 * kNb; e += blockDim.x) {
-        const int r = e / kNb, c = e % kNb;
-        Li[r][c] = i0 + r < m ? A[(i0 + r) * lda + k0 + c] : 0.0;
-        Lj[r][c] = j0 + r < m ? A[(j0 + r) * lda + k0 + c] : 0.0;
-    }
-    __syncthreads();
-    const int c = threadIdx.x & 31, r0 = threadIdx.x >> 5;  // rows r0, r0 + 8, r0 + 16, r0 + 24
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll 8
-    for (int l = 0; l < kNb; ++l) {
-        const double b = Lj[c][l];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) acc[q] += Li[r0 + 8 * q][l] * b;
-    }
-    const int64_t j = j0 + c;
-    const bool diag_tile = ti == 0 && tj == 0;
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        const int64_t i = i0 + r0 + 8 * q;
-        if (i < m && j < m && j <= i) {
-            const double v = A[i * lda + j] - acc[q];
-            A[i * lda + j] = v;
-            if (diag_tile) T[r0 + 8 * q][c] = v;
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 15, q = lane >> 4;
+    const int rb = 32 * (w >> 1), cb = 32 * (w & 1);
+#pragma unroll 4
+    for (int k = 0; k < kB; k += 4) {
+        double a0 = X[rb + r][k + q], a1 = X[rb + 16 + r][k + q];
+        const double b0 = Y[cb + r][k + q], b1 = Y[cb + 16 + r][k + q];
+        if (neg) {
+            a0 = -a0;
+            a1 = -a1;
         }
-    }
-    if (diag_tile) {
-        __syncthreads();
-        if (threadIdx.x < 64) {
-            const int nbn = static_cast<int>(min<int64_t>(kNb, m - s0));
-            const int r = threadIdx.x;
-            double row[kNb];
-#pragma unroll
-            for (int cc = 0; cc < kNb; ++cc) row[cc] = (r < nbn && cc <= r) ? T[r][cc] : 0.0;
-            const int bad = factor_block(row, nbn, s0, colbuf);
-            if (r == 0 && bad && info && *info == 0) *info = bad;
-            if (r < kNb) {
-#pragma unroll
-                for (int cc = 0; cc < kNb; ++cc) dk_next[r * kNb + cc] = cc <= r ? row[cc] : 0.0;
-            }
-        }
+        acc[0][0] = mfma64(a0, b0, acc[0][0]);
+        acc[0][1] = mfma64(a0, b1, acc[0][1]);
+        acc[1][0] = mfma64(a1, b0, acc[1][0]);
+        acc[1][1] = mfma64(a1, b1, acc[1][1]);
     }
 }
 
-// x = (L L^T)^-1 b by blocked substitution, one launch per 32-row block and direction.  In
-// every launch each workgroup stages the diagonal block in LDS and solves it with one wave
-// (the same small solve, redundantly), then updates its share of the remaining right-hand
-// side; workgroup 0 stores the block's solution.  A step reads only the block's right-hand
-// side and writes only the solution and the rows past the block, so workgroups never race.
-__device__ __forceinline__ void stage_diag(const double* __restrict__ dk, int nb, double (&D)[kNb][kNb + 1],
-                                           double (&dinv)[kNb])
+// Row and column, within the 64 x 64 block, of element e of accumulator tile (bi, bj).
+__device__ __forceinline__ int acc_row(int bi, int e)
 {
-    for (int e = threadIdx.x; e < nb * nb; e += blockDim.x) {
-        const int r = e / nb, c = e % nb;
-        D[r][c] = c <= r ? dk[r * kNb + c] : 0.0;
-    }
-    if (static_cast<int>(threadIdx.x) < nb) dinv[threadIdx.x] = 1.0 / dk[threadIdx.x * (kNb + 1)];
+    return 32 * (static_cast<int>(threadIdx.x) >> 7) + 16 * bi + 4 * e + ((threadIdx.x & 63) >> 4);
+}
+__device__ __forceinline__ int acc_col(int bj)
+{
+    return 32 * ((threadIdx.x >> 6) & 1) + 16 * bj + (threadIdx.x & 15);
 }
 
-// Forward step: z_k = L_kk^-1 r_k; r_i -= L_ik z_k for rows i >= k0 + nb.
-__global__ __launch_bounds__(256) void k_trsv_fwd(const double* __restrict__ L, const double* __restrict__ diag,
-                                                  int64_t m, int64_t lda, int64_t k0, double* __restrict__ r,
-                                                  double* __restrict__ z)
+__device__ __forceinline__ void acc_zero(v4d (&acc)[2][2])
 {
-    __shared__ double D[kNb][kNb + 1];
-    __shared__ double dinv[kNb];
-    __shared__ double xb[kNb];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
+}
+
+__device__ __forceinline__ void acc_to_lds(const v4d (&acc)[2][2], Blk& S)
+{
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) S[acc_row(bi, e)][acc_col(bj)] = acc[bi][bj][e];
+}
+
+// S[r][c] = A[r0 + r][c0 + c] for rows r0 + r < rows (else 0), all 64 columns (each wave reads
+// whole 512-byte rows).
+__device__ __forceinline__ void load_block(Blk& S, const double* __restrict__ A, int64_t lda, int64_t r0, int64_t c0,
+                                           int64_t rows)
+{
+    const int c = threadIdx.x & 63;
+    for (int r = threadIdx.x >> 6; r < kB; r += 4) S[r][c] = r0 + r < rows ? A[(r0 + r) * lda + c0 + c] : 0.0;
+}
+
+// Dense 64 x 64 row-major block from global memory into LDS.
+__device__ __forceinline__ void load_dense(Blk& S, const double* __restrict__ D)
+{
+    const int c = threadIdx.x & 63;
+    for (int r = threadIdx.x >> 6; r < kB; r += 4) S[r][c] = D[r * kB + c];
+}
+
+// 1 / sqrt(d): the hardware estimate refined by two Newton steps, y += y (1/2 - d y^2 / 2), to about
+// an ulp.  A pivot d <= 0 or NaN gives NaN (the estimate is NaN below zero and infinite at zero,
+// where the first step makes 0 * inf).
+__device__ __forceinline__ double rsqrt_nan(double d)
+{
+    double y = __builtin_amdgcn_rsq(d);
+    const double h = 0.5 * d;
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    return y;
+}
+
+// Columns [j0, j0 + 16) of the diagonal block in S, factored by one wave in registers (lane r
+// holds row r's 16 entries).  Software-pipelined over the columns: column j's pivot reciprocal
+// is made in the previous step; the entries of column j that the next two columns need come by
+// lane broadcasts, the rest through LDS, read one step early and applied in the next step (in
+// the shadow of the next pivot's chain).  Entries above the diagonal (c > r in lane r) take part
+// in the arithmetic and end up holding values that are never read.  Updated entries are pinned:
+// otherwise the compiler defers every update to the entry's first use, lengthening the pivot
+// chain.  The pivot reciprocals go to rdiag[j0 ..].
+__device__ __forceinline__ void factor_subpanel(Blk& S, int j0, double* __restrict__ rdiag, double* colb)
+{
     const int t = threadIdx.x;
-    const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
-    stage_diag(diag + (k0 / kNb) * kNb * kNb, nb, D, dinv);
-    if (t < nb) xb[t] = r[k0 + t];
-    __syncthreads();
-    if (t < 64) {
-        // one wave, lane t holding x_t and row t of the block: no LDS round trip per step
-        double xr = t < nb ? xb[t] : 0.0, dr[kNb];
+    double pv[16], cb[16], isv[16], lprev = 0.0;
+    // a zero the compiler cannot see through, so that the broadcast reads below use one base
+    // register with immediate offsets instead of materialising every address
+    int zero;
+    asm volatile("v_mov_b32 %0, 0" : "=v"(zero));
+    const double* cbase = colb + zero;
 #pragma unroll
-        for (int c = 0; c < kNb; ++c) dr[c] = t < nb ? D[t][c] : 0.0;
+    for (int c = 0; c < 16; ++c) pv[c] = S[t][j0 + c];
+    double is = rsqrt_nan(lane_bcast(pv[0], j0));
 #pragma unroll
-        for (int j = 0; j < kNb; ++j) {
-            if (j < nb) {
-                const double xj = lane_bcast(xr, j) * dinv[j];
-                if (t > j) xr -= dr[j] * xj;
-                if (t == j) xr = xj;
+    for (int j = 0; j < 16; ++j) {
+        const double lj = pv[j] * is;  // the pivot's own lane: d / sqrt(d)
+        pv[j] = lj;
+        isv[j] = is;
+#pragma unroll
+        for (int c = j + 1; c < j + 3 && c < 16; ++c) {
+            pv[c] -= lj * lane_bcast(lj, j0 + c);
+            asm volatile("" : "+v"(pv[c]));
+        }
+        if (j + 1 < 16) is = rsqrt_nan(lane_bcast(pv[j + 1], j0 + j + 1));
+        if (j >= 1 && j <= 13) {
+#pragma unroll
+            for (int c = j + 2; c < 16; ++c) {
+                pv[c] -= lprev * cb[c];
+                asm volatile("" : "+v"(pv[c]));
             }
         }
-        if (t < nb) xb[t] = xr;
+        // the scheduler may overlap what follows with the next column's pivot chain, but moves
+        // nothing of this column's chain below this point
+        __builtin_amdgcn_sched_barrier(0);
+        if (j + 3 < 16) {
+            colb[t] = lj;
+            // one wave, whose LDS accesses complete in program order: compiler barriers order
+            // the store before the reads and the reads before the next column's store
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int c = j + 3; c < 16; ++c) cb[c] = cbase[j0 + c];
+            __builtin_amdgcn_wave_barrier();
+            lprev = lj;
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < 16; ++c) S[t][j0 + c] = pv[c];
+    if (t == 0) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) rdiag[j0 + j] = isv[j];
+    }
+}
+
+// S[r0 ..][c0 ..] (a 16 x 16 tile) -= L[r0 ..][j0 ..] L[c0 ..][j0 ..]^T over the 16 columns of
+// the sub-panel at j0, by one wave on the matrix cores.
+__device__ __forceinline__ void trail_tile(Blk& S, int j0, int r0, int c0)
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    v4d acc;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) acc[e] = S[r0 + 4 * e + q][c0 + r];
+#pragma unroll
+    for (int k = 0; k < 16; k += 4) acc = mfma64(-S[r0 + r][j0 + k + q], S[c0 + r][j0 + k + q], acc);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) S[r0 + 4 * e + q][c0 + r] = acc[e];
+}
+
+// Inverse of the 16 x 16 diagonal factor at o = 16 b (one wave): lane c (of each group of 16;
+// the first group stores) makes column c by forward substitution, row by row.
+__device__ __forceinline__ void leaf_inverse(const Blk& S, Blk& T, const double* __restrict__ rdiag, int o,
+                                             double* __restrict__ dout)
+{
+    const int lane = threadIdx.x & 63, c = lane & 15;
+    double x[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        double a0 = j == c ? 1.0 : 0.0, a1 = 0.0;
+#pragma unroll
+        for (int l = 0; l < j; l += 2) {
+            a0 -= S[o + j][o + l] * x[l];
+            if (l + 1 < j) a1 -= S[o + j][o + l + 1] * x[l + 1];
+        }
+        x[j] = (a0 + a1) * rdiag[o + j];
+        if ((j & 3) == 3) __builtin_amdgcn_sched_barrier(0);
+    }
+    if (lane < 16) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            T[o + j][o + c] = x[j];
+            dout[(o + j) * kB + o + c] = x[j];
+        }
+    }
+}
+
+// Lower-left 16 x 16 block of the inverse of the 32 x 32 half at o (one wave), from the
+// diagonal blocks' inverses A^-1 (at o) and C^-1 (at o + 16) and the factor's block B:
+// -C^-1 (B A^-1), with B A^-1 staged in S's unused upper triangle.  Two accumulators halve the
+// dependent chain of products.
+__device__ __forceinline__ void half_inverse(Blk& S, Blk& T, int o, double* __restrict__ dout)
+{
+    const int lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
+    v4d a0 = {0.0, 0.0, 0.0, 0.0}, a1 = a0;
+    a0 = mfma64(S[o + 16 + r][o + q], T[o + q][o + r], a0);
+    a1 = mfma64(S[o + 16 + r][o + 8 + q], T[o + 8 + q][o + r], a1);
+    a0 = mfma64(S[o + 16 + r][o + 4 + q], T[o + 4 + q][o + r], a0);
+    a1 = mfma64(S[o + 16 + r][o + 12 + q], T[o + 12 + q][o + r], a1);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) S[o + 4 * e + q][o + 16 + r] = a0[e] + a1[e];
+    __builtin_amdgcn_wave_barrier();
+    a0 = v4d{0.0, 0.0, 0.0, 0.0};
+    a1 = a0;
+    a0 = mfma64(T[o + 16 + r][o + 16 + q], S[o + q][o + 16 + r], a0);
+    a1 = mfma64(T[o + 16 + r][o + 24 + q], S[o + 8 + q][o + 16 + r], a1);
+    a0 = mfma64(T[o + 16 + r][o + 20 + q], S[o + 4 + q][o + 16 + r], a0);
+    a1 = mfma64(T[o + 16 + r][o + 28 + q], S[o + 12 + q][o + 16 + r], a1);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const double v = -(a0[e] + a1[e]);
+        T[o + 16 + 4 * e + q][o + r] = v;
+        dout[(o + 16 + 4 * e + q) * kB + o + r] = v;
+    }
+}
+
+// Factor and invert one diagonal block.  On entry S holds the block's lower triangle (rows and
+// columns from nb on padded with the identity); on exit S's lower triangle holds the factor L
+// (its upper triangle holds values that are never read) and `dout` the inverse L^-1 (64 x 64
+// row-major, zeros above the diagonal).  The first non-positive pivot, counted 1-based from the
+// matrix's first row via g0, goes to `info` if none was reported before.  T is LDS scratch.
+//
+// The factorisation runs in four 16-column sub-panels, each factored by wave 0 in registers and
+// then applied to the trailing rows and columns (rank-16 updates) on the matrix cores.  Only the
+// tiles of the next sub-panel's columns are updated before wave 0 moves on; the other waves
+// apply the rest, invert the finished 16 x 16 diagonal factors and form the first-level
+// off-diagonal blocks of the inverse while wave 0 factors the next sub-panel.  The inverse
+// follows from inv([[A, 0], [B, C]]) = [[A^-1, 0], [-C^-1 B A^-1, C^-1]], within each 32 x 32
+// half and then for the whole block.
+__device__ __forceinline__ void factor_invert(Blk& S, Blk& T, int nb, int64_t g0, double* __restrict__ dout,
+                                              int32_t* __restrict__ info)
+{
+    __shared__ double rdiag[kB];
+    __shared__ double colb[kB];
+    const int t = threadIdx.x, lane = t & 63, w = t >> 6, r = lane & 15, q = lane >> 4;
+    // the inverse's zero blocks above its diagonal 16 x 16 blocks
+    for (int e = t; e < kB * kB; e += blockDim.x) {
+        const int rr = e >> 6, cc = e & 63;
+        if ((cc >> 4) > (rr >> 4)) dout[e] = 0.0;
+    }
+    // the upper-right 16 x 16 block of each 32 x 32 half of the inverse, in T
+    if (w == 3) {
+#pragma unroll
+        for (int j = 0; j < 16; j += 4) {
+            T[j + q][16 + r] = 0.0;
+            T[32 + j + q][48 + r] = 0.0;
+        }
+    }
+#pragma unroll
+    for (int sp = 0; sp < 4; ++sp) {
+        const int j0 = 16 * sp;
+        if (w == 0) {
+            factor_subpanel(S, j0, rdiag, colb);
+        } else {
+            // work that the previous sub-panel left, in the shadow of this factorisation
+            if (w == 1 && sp >= 1) leaf_inverse(S, T, rdiag, j0 - 16, dout);
+            if (sp == 1) {
+                // the previous update's tiles right of this sub-panel's columns
+                if (w == 2) {
+                    trail_tile(S, 0, 32, 32);
+                    trail_tile(S, 0, 48, 48);
+                }
+                if (w == 3) trail_tile(S, 0, 48, 32);
+            }
+            if (sp == 2 && w == 2) trail_tile(S, 16, 48, 48);
+            if (sp == 3 && w == 2) half_inverse(S, T, 0, dout);
+        }
+        __syncthreads();
+        // the update of the next sub-panel's columns by this one
+        if (w < 3 - sp) trail_tile(S, j0, j0 + 16 + 16 * w, j0 + 16);
+        if (sp < 3) __syncthreads();
+    }
+    if (w == 0) {
+        // a non-positive pivot leaves NaN on its diagonal and on every later one: the first
+        // row of the block whose diagonal is not positive is the one to report
+        const uint64_t badm = __ballot(t < nb && !(S[t][t] > 0.0));
+        if (t == 0 && badm && info && *info == 0) *info = static_cast<int>(g0 + __builtin_ctzll(badm) + 1);
+    }
+    if (w == 1) {
+        leaf_inverse(S, T, rdiag, 48, dout);
+        __builtin_amdgcn_wave_barrier();
+        half_inverse(S, T, 32, dout);
     }
     __syncthreads();
-    if (blockIdx.x == 0 && t < nb) z[k0 + t] = xb[t];
-    // 32 rows per workgroup, eight lanes per row, four consecutive entries per lane: each row's
-    // block entries are read as one contiguous run; the eight partial dot products are added
-    // by lane exchanges
-    const int64_t i = k0 + nb + static_cast<int64_t>(blockIdx.x) * 32 + (t >> 3);
-    const int q = 4 * (t & 7);
-    double v = 0.0;
-    if (i < m) {
-        const double* row = L + i * lda + k0;
+    // the whole block: W = L21 L11^-1 into T's free upper-right quadrant, then -L22^-1 W, the
+    // lower-left quadrant of the inverse
+    const int wi = 16 * (w >> 1), wj = 16 * (w & 1);
+    v4d a0 = {0.0, 0.0, 0.0, 0.0}, a1 = a0;
 #pragma unroll
-        for (int u = 0; u < 4; ++u)
-            if (q + u < nb) v += row[q + u] * xb[q + u];
+    for (int k = 0; k < 32; k += 8) {
+        a0 = mfma64(S[32 + wi + r][k + q], T[k + q][wj + r], a0);
+        a1 = mfma64(S[32 + wi + r][k + 4 + q], T[k + 4 + q][wj + r], a1);
     }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) T[wi + 4 * e + q][32 + wj + r] = a0[e] + a1[e];
+    __syncthreads();
+    a0 = v4d{0.0, 0.0, 0.0, 0.0};
+    a1 = a0;
+#pragma unroll
+    for (int k = 0; k < 32; k += 8) {
+        a0 = mfma64(T[32 + wi + r][32 + k + q], T[k + q][32 + wj + r], a0);
+        a1 = mfma64(T[32 + wi + r][32 + k + 4 + q], T[k + 4 + q][32 + wj + r], a1);
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) dout[(32 + wi + 4 * e + q) * kB + wj + r] = -(a0[e] + a1[e]);
+}
+
+// Lower triangle of the diagonal block of A at row/column g0 into S, padded with the identity
+// past the matrix's last row.
+__device__ __forceinline__ void stage_diag_block(Blk& S, const double* __restrict__ A, int64_t m, int64_t lda,
+                                                 int64_t g0)
+{
+    const int c = threadIdx.x & 63;
+    for (int r = threadIdx.x >> 6; r < kB; r += 4) {
+        double v = 0.0;
+        if (g0 + r < m) {
+            if (c <= r) v = A[(g0 + r) * lda + g0 + c];
+        } else if (c == r) {
+            v = 1.0;
+        }
+        S[r][c] = v;
+    }
+}
+
+// First diagonal block: factor and invert (one workgroup).
+__global__ __launch_bounds__(256) void k_chol_first(const double* __restrict__ A, int64_t m, int64_t lda,
+                                                   double* __restrict__ dinv, int32_t* __restrict__ info)
+{
+    __shared__ Blk S, T;
+    stage_diag_block(S, A, m, lda, 0);
+    __syncthreads();
+    factor_invert(S, T, static_cast<int>(min<int64_t>(kB, m)), 0, dinv, info);
+}
+
+// One panel step p of the right-looking blocked Cholesky factorisation A = L L^T, with the
+// forward substitution L z = r carried along as an extra row.  Workgroup (a, b), b <= a, owns
+// the trailing tile of row block i = p + 1 + a and column block j = p + 1 + b (workgroup 0 the
+// next diagonal block, so that the step's longest chain starts first).  With the inverse
+// D = L_pp^-1 of the panel's diagonal factor (made by the preceding step):
+//   panel rows:   L_ip = A_ip D^T (and L_jp), on the matrix cores;
+//   update:       A_ij -= L_ip L_jp^T (lower triangle on the diagonal);
+//   column b = 0: stores L_ip transposed in A's unused upper triangle, U[k0 + n][i0 + r] =
+//                 L_ip[r][n], the layout the backward substitution reads;
+//   diagonal:     r_i -= L_ip z_p with z_p = D r_p (workgroup 0 also stores z_p);
+//   workgroup 0:  factors and inverts the updated diagonal block p + 1.
+// Every workgroup reads only panel p and its own tile, and writes its own tile, its own rows of
+// r and of U: no two workgroups touch the same entry.
+__global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ A, int64_t m, int64_t lda, int64_t p,
+                                                  double* __restrict__ dinv, double* __restrict__ r,
+                                                  double* __restrict__ z, int32_t* __restrict__ info)
+{
+    __shared__ Blk X, Y, D;
+    __shared__ double zp[kB];
+    const int t = threadIdx.x;
+    const int64_t k0 = p * kB;
+    const int64_t tid = blockIdx.x;
+    int64_t a = static_cast<int64_t>((sqrt(8.0 * static_cast<double>(tid) + 1.0) - 1.0) * 0.5);
+    while (a * (a + 1) / 2 > tid) --a;
+    while ((a + 1) * (a + 2) / 2 <= tid) ++a;
+    const int64_t b = tid - a * (a + 1) / 2;
+    const int64_t i0 = (p + 1 + a) * kB, j0 = (p + 1 + b) * kB;
+    const bool diag = a == b;
+
+    load_dense(D, dinv + p * kB * kB);
+    load_block(X, A, lda, i0, k0, m);
+    if (!diag) load_block(Y, A, lda, j0, k0, m);
+    v4d c[2][2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t gi = i0 + acc_row(bi, e), gj = j0 + acc_col(bj);
+                c[bi][bj][e] = gi < m && gj <= gi ? A[gi * lda + gj] : 0.0;
+            }
+    __syncthreads();
+    v4d pi[2][2], pj[2][2];
+    acc_zero(pi);
+    gemm_nt(X, D, pi, false);
+    if (!diag) {
+        acc_zero(pj);
+        gemm_nt(Y, D, pj, false);
+    }
+    if (diag && t < kB) {
+        // z_p = D r_p (D lower triangular)
+        double v0 = 0.0, v1 = 0.0;
+        for (int k = 0; k <= t; k += 2) {
+            v0 += D[t][k] * r[k0 + k];
+            if (k + 1 <= t) v1 += D[t][k + 1] * r[k0 + k + 1];
+        }
+        zp[t] = v0 + v1;
+    }
+    __syncthreads();
+    acc_to_lds(pi, X);
+    if (!diag) acc_to_lds(pj, Y);
+    __syncthreads();
+    if (b == 0) {
+        // U rows k0 + n, columns i0 .. i0 + 63: consecutive lanes take consecutive columns
+        const int rr = t & 63;
+        if (i0 + rr < m)
+            for (int n = t >> 6; n < kB; n += 4) A[(k0 + n) * lda + i0 + rr] = X[rr][n];
+    }
+    if (diag && t < kB) {
+        if (i0 + t < m) {
+            double v0 = 0.0, v1 = 0.0;
+#pragma unroll 8
+            for (int n = 0; n < kB; n += 2) {
+                v0 += X[t][n] * zp[n];
+                v1 += X[t][n + 1] * zp[n + 1];
+            }
+            r[i0 + t] -= v0 + v1;
+        }
+        if (a == 0) z[k0 + t] = zp[t];
+    }
+    gemm_nt(X, diag ? X : Y, c, true);
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t gi = i0 + acc_row(bi, e), gj = j0 + acc_col(bj);
+                if (gi < m && gj <= gi) A[gi * lda + gj] = c[bi][bj][e];
+            }
+    if (tid == 0) {
+        // the next diagonal block, from the updated values still in registers
+        const int nbn = static_cast<int>(min<int64_t>(kB, m - i0));
+        __syncthreads();
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const int rr = acc_row(bi, e), cc = acc_col(bj);
+                    double v = 0.0;
+                    if (rr < nbn) {
+                        if (cc <= rr) v = c[bi][bj][e];
+                    } else if (cc == rr) {
+                        v = 1.0;
+                    }
+                    D[rr][cc] = v;
+                }
+        __syncthreads();
+        factor_invert(D, Y, nbn, i0, dinv + (p + 1) * kB * kB, info);
+    }
+}
+
+// One block step of the backward substitution L^T x = z, from the last block to the first:
+// x_b = D_b^T z_b with D_b = L_bb^-1, then z_q -= L_bq^T x_b for the rows above the block, read
+// from U (row q0 + n of U holds column n of L below block q).  For the last block z_b is made
+// here from the forward-updated right-hand side, z_b = D_b r_b.  Every workgroup forms x_b itself
+// (a 64 x 64 matrix-vector product) and updates 32 rows of z; workgroup 0 stores x_b.
+__global__ __launch_bounds__(256) void k_chol_back(const double* __restrict__ A, int64_t m, int64_t lda, int64_t bk,
+                                                  const double* __restrict__ dinv, const double* __restrict__ r,
+                                                  double* __restrict__ z, double* __restrict__ x, int last)
+{
+    __shared__ Blk D;
+    __shared__ double zb[kB], xb[kB];
+    const int t = threadIdx.x;
+    const int64_t b0 = bk * kB;
+    const int nb = static_cast<int>(min<int64_t>(kB, m - b0));
+    load_dense(D, dinv + bk * kB * kB);
+    if (t < kB) zb[t] = t < nb ? (last ? r[b0 + t] : z[b0 + t]) : 0.0;
+    __syncthreads();
+    // four lanes per output entry, each summing every fourth term; the partial sums meet by
+    // lane exchanges within the group of four
+    const int o = t >> 2, g = t & 3;
+    if (last) {
+        double v = 0.0;
+        for (int k = g; k <= o && k < nb; k += 4) v += D[o][k] * zb[k];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        __syncthreads();
+        if (g == 0) zb[o] = o < nb ? v : 0.0;
+        __syncthreads();
+    }
+    {
+        double v = 0.0;
+        for (int k = o + g; k < nb; k += 4) v += D[k][o] * zb[k];
+        v += __shfl_xor(v, 1);
+        v += __shfl_xor(v, 2);
+        if (g == 0) xb[o] = o < nb ? v : 0.0;
+    }
+    __syncthreads();
+    if (blockIdx.x == 0 && t < nb) x[b0 + t] = xb[t];
+    // 32 rows per workgroup, eight lanes per row, eight consecutive entries per lane
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 32 + (t >> 3);
+    if (i >= b0) return;
+    const int q = 8 * (t & 7);
+    const double* row = A + i * lda + b0;
+    double v = 0.0;
+#pragma unroll
+    for (int u = 0; u < 8; ++u)
+        if (q + u < nb) v += row[q + u] * xb[q + u];
     v += __shfl_xor(v, 1);
     v += __shfl_xor(v, 2);
     v += __shfl_xor(v, 4);
-    if (i < m && (t & 7) == 0) r[i] -= v;
-}
-
-// Backward step: x_k = L_kk^-T z_k; z_i -= L_ki^T x_k for rows i < k0.
-__global__ __launch_bounds__(256) void k_trsv_bwd(const double* __restrict__ L, const double* __restrict__ diag,
-                                                  int64_t m, int64_t lda, int64_t k0, double* __restrict__ z,
-                                                  double* __restrict__ x)
-{
-    __shared__ double D[kNb][kNb + 1];
-    __shared__ double dinv[kNb];
-    __shared__ double xb[kNb];
-    const int t = threadIdx.x;
-    const int nb = static_cast<int>(min<int64_t>(kNb, m - k0));
-    stage_diag(diag + (k0 / kNb) * kNb * kNb, nb, D, dinv);
-    if (t < nb) xb[t] = z[k0 + t];
-    __syncthreads();
-    if (t < 64) {
-        // one wave, lane t holding x_t and column t of the block
-        double xr = t < nb ? xb[t] : 0.0, dc[kNb];
-#pragma unroll
-        for (int c = 0; c < kNb; ++c) dc[c] = t < nb ? D[c][t] : 0.0;
-#pragma unroll
-        for (int j = kNb - 1; j >= 0; --j) {
-            if (j < nb) {
-                const double xj = lane_bcast(xr, j) * dinv[j];
-                if (t < j) xr -= dc[j] * xj;
-                if (t == j) xr = xj;
-            }
-        }
-        if (t < nb) xb[t] = xr;
-    }
-    __syncthreads();
-    if (blockIdx.x == 0 && t < nb) x[k0 + t] = xb[t];
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * blockDim.x + t;
-    if (i < k0) {
-        double v = 0.0;
-        for (int l = 0; l < nb; ++l) v += L[(k0 + l) * lda + i] * xb[l];
-        z[i] -= v;
-    }
+    if ((t & 7) == 0) z[i] -= v;
 }
 
 // r = d - y (FP64 residuals).
@@ -425,42 +687,30 @@ hipError_t launch_cov_matrix(const double* x, int64_t m, int dim, const KrigeMod
     return hipGetLastError();
 }
 
-hipError_t launch_cholesky(double* A, int64_t m, int64_t lda, double* diag, int32_t* info, hipStream_t s)
+hipError_t launch_cholesky(double* A, int64_t m, int64_t lda, double* dinv, double* r, double* z, int32_t* info,
+                           hipStream_t s)
 {
-    for (int64_t k0 = 0; k0 < m; k0 += kNb) {
-        const int64_t rest = m - k0 - kNb;
-        const unsigned blocks = static_cast<unsigned>(rest > 0 ? (rest + 63) / 64 : 1);
-        // the first panel factors its diagonal block; later ones take the factor that the
-        // preceding trailing update made
-        hipLaunchKernelGGL(k_potrf_trsm, dim3(blocks), dim3(64), 0, s, A, m, lda, k0, diag + (k0 / kNb) * kNb * kNb,
-                           info, k0 > 0 ? 1 : 0);
-        if (rest <= 0) break;
-        const int64_t tiles = (rest + 31) / 32;
-        hipLaunchKernelGGL(k_syrk_update, dim3(static_cast<unsigned>(tiles), static_cast<unsigned>(tiles)), dim3(256),
-                           0, s, A, m, lda, k0, diag + (k0 / kNb + 1) * kNb * kNb, info);
-        const hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+    const int64_t nblk = (m + kB - 1) / kB;
+    if ((nblk - 1) * nblk / 2 > 0x7fffffff) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_chol_first, dim3(1), dim3(256), 0, s, A, m, lda, dinv, info);
+    for (int64_t p = 0; p + 1 < nblk; ++p) {
+        const int64_t n = nblk - 1 - p;
+        hipLaunchKernelGGL(k_chol_step, dim3(static_cast<unsigned>(n * (n + 1) / 2)), dim3(256), 0, s, A, m, lda, p,
+                           dinv, r, z, info);
     }
     return hipGetLastError();
 }
 
-hipError_t launch_chol_solve(const double* L, const double* diag, int64_t m, int64_t lda, double* b, double* x,
-                             hipStream_t s)
+hipError_t launch_chol_back(const double* A, int64_t m, int64_t lda, const double* dinv, const double* r, double* z,
+                            double* x, hipStream_t s)
 {
-    // forward: right-hand side b (updated in place), solution z in x; backward: right-hand
-    // side z (x, updated in place), solution in b; then b -> x
-    for (int64_t k0 = 0; k0 < m; k0 += kNb) {
-        const int64_t below = m - k0 - kNb;
-        const unsigned blocks = static_cast<unsigned>(below > 0 ? (below + 31) / 32 : 1);
-        hipLaunchKernelGGL(k_trsv_fwd, dim3(blocks), dim3(256), 0, s, L, diag, m, lda, k0, b, x);
+    const int64_t nblk = (m + kB - 1) / kB;
+    for (int64_t bk = nblk - 1; bk >= 0; --bk) {
+        const unsigned blocks = static_cast<unsigned>(bk > 0 ? (bk * kB + 31) / 32 : 1);
+        hipLaunchKernelGGL(k_chol_back, dim3(blocks), dim3(256), 0, s, A, m, lda, bk, dinv, r, z, x,
+                           bk == nblk - 1 ? 1 : 0);
     }
-    for (int64_t k0 = ((m - 1) / kNb) * kNb; k0 >= 0; k0 -= kNb) {
-        const unsigned blocks = static_cast<unsigned>(k0 > 0 ? (k0 + 255) / 256 : 1);
-        hipLaunchKernelGGL(k_trsv_bwd, dim3(blocks), dim3(256), 0, s, L, diag, m, lda, k0, x, b);
-    }
-    hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    return hipMemcpyAsync(x, b, static_cast<size_t>(m) * sizeof(double), hipMemcpyDeviceToDevice, s);
+    return hipGetLastError();
 }
 
 hipError_t launch_residual(const float* d, const float* y, int64_t m, double* r, hipStream_t s)

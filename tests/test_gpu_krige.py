@@ -98,17 +98,17 @@ def test_krige_weights_match_oracle_and_report_singular(orc, grf):
     assert int(to_np(info)[0]) == 2
 
 
-@pytest.mark.parametrize("dup", [(40, 50), (3, 65), (31, 32)])
-def test_krige_singular_pivot_in_later_panels(orc, grf, dup):
-    """Non-positive pivots past the first 32-row panel are reported too (they are found by the
+@pytest.mark.parametrize("M,dup", [(70, (40, 50)), (70, (3, 65)), (70, (31, 32)), (70, (10, 64)), (70, (63, 64)),
+                                   (200, (5, 150)), (200, (100, 191)), (200, (127, 128))])
+def test_krige_singular_pivot_in_later_panels(orc, grf, M, dup):
+    """Non-positive pivots past the first 64-row panel are reported too (they are found by the
     trailing update that factors the next diagonal block).  Observations 1000 correlation
     lengths apart make C(X, X) the identity in FP64 except for one duplicated pair, whose second
     pivot is then exactly 1 - 1 = 0: info is its 1-based index and alpha is NaN throughout."""
     i, j = dup
-    _say(f"case krige singular pivot, x[{j}] = x[{i}]")
+    _say(f"case krige singular pivot, M={M}, x[{j}] = x[{i}]")
     (zo, po), m = modes_pair(orc, grf, 2, wl.EXPONENTIAL, 64, 975, 1.0, (1.0, 1.0))
-    M = 70
-    xs = np.stack([1000.0 * (np.arange(M) % 9), 1000.0 * (np.arange(M) // 9)], axis=1)
+    xs = np.stack([1000.0 * (np.arange(M) % 15), 1000.0 * (np.arange(M) // 15)], axis=1)
     xs[j] = xs[i]
     alpha, info = grf.krige_weights(m, torch.from_numpy(np.ascontiguousarray(xs)).cuda(),
                                     torch.ones(M, device="cuda"), wl.EXPONENTIAL)
@@ -118,7 +118,7 @@ def test_krige_singular_pivot_in_later_panels(orc, grf, dup):
     alpha, info = grf.krige_weights(m, torch.from_numpy(np.ascontiguousarray(xs)).cuda(),
                                     torch.ones(M, device="cuda"), wl.EXPONENTIAL, nugget=0.5)
     assert int(to_np(info)[0]) == 0 and np.isfinite(to_np(alpha)).all()
-    xs[j] = (1000.0 * 20, 1000.0 * 20)
+    xs[j] = (1000.0 * 40, 1000.0 * 40)
     alpha, info = grf.krige_weights(m, torch.from_numpy(np.ascontiguousarray(xs)).cuda(),
                                     torch.ones(M, device="cuda"), wl.EXPONENTIAL)
     assert int(to_np(info)[0]) == 0
@@ -126,9 +126,10 @@ def test_krige_singular_pivot_in_later_panels(orc, grf, dup):
     np.testing.assert_allclose(to_np(alpha), want, rtol=0, atol=2e-5)
 
 
-@pytest.mark.parametrize("M", [1, 31, 32, 33, 97, 1000])
+@pytest.mark.parametrize("M", [1, 2, 31, 63, 64, 65, 127, 128, 129, 191, 1000])
 def test_cholesky_block_edges(orc, grf, M):
-    """Sizes below, at and across the 32-row factorisation blocks."""
+    """Sizes below, at and across the 64-row factorisation blocks (one panel, a ragged last
+    block, several trailing steps)."""
     _say(f"case krige weights M={M}")
     ell, sigma = (6.0, 6.0, 2.0), 1.0
     (zo, po), m = modes_pair(orc, grf, 3, wl.EXPONENTIAL, 64, 971, sigma, ell)
