@@ -154,20 +154,36 @@ __device__ __forceinline__ void acc_to_lds(const v4d (&acc)[2][2], Blk& S)
             for (int e = 0; e < 4; ++e) S[acc_row(bi, e)][acc_col(bj)] = acc[bi][bj][e];
 }
 
-// S[r][c] = A[r0 + r][c0 + c] for rows r0 + r < rows (else 0), all 64 columns (each wave reads
-// whole 512-byte rows).
-__device__ __forceinline__ void load_block(Blk& S, const double* __restrict__ A, int64_t lda, int64_t r0, int64_t c0,
+// A 64 x 64 block moves between global memory and LDS in two halves: every thread first loads
+// its sixteen entries (rows t / 64 + 4 i, column t % 64; each wave reads whole 512-byte rows)
+// into registers, with all loads in flight together, and stores them to LDS afterwards.
+using Rows = double[16];
+
+// v = A[r0 + r][c0 + c] for rows r0 + r < rows (else 0).
+__device__ __forceinline__ void fetch_rows(Rows& v, const double* __restrict__ A, int64_t lda, int64_t r0, int64_t c0,
                                            int64_t rows)
 {
-    const int c = threadIdx.x & 63;
-    for (int r = threadIdx.x >> 6; r < kB; r += 4) S[r][c] = r0 + r < rows ? A[(r0 + r) * lda + c0 + c] : 0.0;
+    const int c = threadIdx.x & 63, rb = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int64_t gr = r0 + rb + 4 * i;
+        v[i] = gr < rows ? A[gr * lda + c0 + c] : 0.0;
+    }
 }
 
-// Dense 64 x 64 row-major block from global memory into LDS.
-__device__ __forceinline__ void load_dense(Blk& S, const double* __restrict__ D)
+// v = D[r][c] of a dense 64 x 64 row-major block.
+__device__ __forceinline__ void fetch_dense(Rows& v, const double* __restrict__ D)
 {
-    const int c = threadIdx.x & 63;
-    for (int r = threadIdx.x >> 6; r < kB; r += 4) S[r][c] = D[r * kB + c];
+    const int c = threadIdx.x & 63, rb = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) v[i] = D[(rb + 4 * i) * kB + c];
+}
+
+__device__ __forceinline__ void store_rows(Blk& S, const Rows& v)
+{
+    const int c = threadIdx.x & 63, rb = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) S[rb + 4 * i][c] = v[i];
 }
 
 // 1 / sqrt(d): the hardware estimate refined by two Newton steps, y += y (1/2 - d y^2 / 2), to about
@@ -184,9 +200,9 @@ __device__ __forceinline__ double rsqrt_nan(double d)
 
 // Columns [j0, j0 + 16) of the diagonal block in S, factored by one wave in registers (lane r
 // holds row r's 16 entries).  Software-pipelined over the columns: column j's pivot reciprocal
-// is made in the previous step; the entries of column j that the next two columns need come by
-// lane broadcasts, the rest through LDS, read one step early and applied in the next step (in
-// the shadow of the next pivot's chain).  Entries above the diagonal (c > r in lane r) take part
+// is made in the previous step, in the pivot's own lane; the entries of column j that the next
+// two columns need come by lane broadcasts, the rest through LDS, read one step early and
+// applied in the next step (in the shadow of the next pivot's chain).  Entries above the diagonal (c > r in lane r) take part
 // in the arithmetic and end up holding values that are never read.  Updated entries are pinned:
 // otherwise the compiler defers every update to the entry's first use, lengthening the pivot
 // chain.  The pivot reciprocals go to rdiag[j0 ..].
@@ -207,12 +223,13 @@ __device__ __forceinline__ void factor_subpanel(Blk& S, int j0, double* __restri
         const double lj = pv[j] * is;  // the pivot's own lane: d / sqrt(d)
         pv[j] = lj;
         isv[j] = is;
+        // the next pivot, made in its own lane: its entry of this column is its own lj
+        if (j + 1 < 16) is = rsqrt_nan(lane_bcast(fma(-lj, lj, pv[j + 1]), j0 + j + 1));
 #pragma unroll
         for (int c = j + 1; c < j + 3 && c < 16; ++c) {
             pv[c] -= lj * lane_bcast(lj, j0 + c);
             asm volatile("" : "+v"(pv[c]));
         }
-        if (j + 1 < 16) is = rsqrt_nan(lane_bcast(pv[j + 1], j0 + j + 1));
         if (j >= 1 && j <= 13) {
 #pragma unroll
             for (int c = j + 2; c < 16; ++c) {
@@ -408,16 +425,14 @@ __device__ __forceinline__ void factor_invert(Blk& S, Blk& T, int nb, int64_t g0
 __device__ __forceinline__ void stage_diag_block(Blk& S, const double* __restrict__ A, int64_t m, int64_t lda,
                                                  int64_t g0)
 {
-    const int c = threadIdx.x & 63;
-    for (int r = threadIdx.x >> 6; r < kB; r += 4) {
-        double v = 0.0;
-        if (g0 + r < m) {
-            if (c <= r) v = A[(g0 + r) * lda + g0 + c];
-        } else if (c == r) {
-            v = 1.0;
-        }
-        S[r][c] = v;
+    const int c = threadIdx.x & 63, rb = threadIdx.x >> 6;
+    Rows v;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int r = rb + 4 * i;
+        v[i] = g0 + r < m ? (c <= r ? A[(g0 + r) * lda + g0 + c] : 0.0) : (c == r ? 1.0 : 0.0);
     }
+    store_rows(S, v);
 }
 
 // First diagonal block: factor and invert (one workgroup).
@@ -448,7 +463,7 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ A, int64
                                                   double* __restrict__ z, int32_t* __restrict__ info)
 {
     __shared__ Blk X, Y, D;
-    __shared__ double zp[kB];
+    __shared__ double zp[kB], rp[kB];
     const int t = threadIdx.x;
     const int64_t k0 = p * kB;
     const int64_t tid = blockIdx.x;
@@ -459,9 +474,11 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ A, int64
     const int64_t i0 = (p + 1 + a) * kB, j0 = (p + 1 + b) * kB;
     const bool diag = a == b;
 
-    load_dense(D, dinv + p * kB * kB);
-    load_block(X, A, lda, i0, k0, m);
-    if (!diag) load_block(Y, A, lda, j0, k0, m);
+    Rows vd, vx, vy;
+    const double rv = diag && t < kB ? r[k0 + t] : 0.0;
+    fetch_dense(vd, dinv + p * kB * kB);
+    fetch_rows(vx, A, lda, i0, k0, m);
+    if (!diag) fetch_rows(vy, A, lda, j0, k0, m);
     v4d c[2][2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
@@ -472,6 +489,10 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ A, int64
                 const int64_t gi = i0 + acc_row(bi, e), gj = j0 + acc_col(bj);
                 c[bi][bj][e] = gi < m && gj <= gi ? A[gi * lda + gj] : 0.0;
             }
+    store_rows(D, vd);
+    store_rows(X, vx);
+    if (!diag) store_rows(Y, vy);
+    if (diag && t < kB) rp[t] = rv;
     __syncthreads();
     v4d pi[2][2], pj[2][2];
     acc_zero(pi);
@@ -481,13 +502,11 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ A, int64
         gemm_nt(Y, D, pj, false);
     }
     if (diag && t < kB) {
-        // z_p = D r_p (D lower triangular)
-        double v0 = 0.0, v1 = 0.0;
-        for (int k = 0; k <= t; k += 2) {
-            v0 += D[t][k] * r[k0 + k];
-            if (k + 1 <= t) v1 += D[t][k + 1] * r[k0 + k + 1];
-        }
-        zp[t] = v0 + v1;
+        // z_p = D r_p (D's zeros above the diagonal make the full-length sum exact)
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int k = 0; k < kB; ++k) v[k & 3] += D[t][k] * rp[k];
+        zp[t] = (v[0] + v[1]) + (v[2] + v[3]);
     }
     __syncthreads();
     acc_to_lds(pi, X);
@@ -501,26 +520,26 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ A, int64
     }
     if (diag && t < kB) {
         if (i0 + t < m) {
-            double v0 = 0.0, v1 = 0.0;
-#pragma unroll 8
-            for (int n = 0; n < kB; n += 2) {
-                v0 += X[t][n] * zp[n];
-                v1 += X[t][n + 1] * zp[n + 1];
-            }
-            r[i0 + t] -= v0 + v1;
+            double v[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int n = 0; n < kB; ++n) v[n & 3] += X[t][n] * zp[n];
+            r[i0 + t] -= (v[0] + v[1]) + (v[2] + v[3]);
         }
         if (a == 0) z[k0 + t] = zp[t];
     }
     gemm_nt(X, diag ? X : Y, c, true);
+    if (tid != 0) {
+        // (the next diagonal block is factored below and never read from A again)
 #pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
+        for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
+            for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
-            for (int e = 0; e < 4; ++e) {
-                const int64_t gi = i0 + acc_row(bi, e), gj = j0 + acc_col(bj);
-                if (gi < m && gj <= gi) A[gi * lda + gj] = c[bi][bj][e];
-            }
+                for (int e = 0; e < 4; ++e) {
+                    const int64_t gi = i0 + acc_row(bi, e), gj = j0 + acc_col(bj);
+                    if (gi < m && gj <= gi) A[gi * lda + gj] = c[bi][bj][e];
+                }
+    }
     if (tid == 0) {
         // the next diagonal block, from the updated values still in registers
         const int nbn = static_cast<int>(min<int64_t>(kB, m - i0));
@@ -545,57 +564,93 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ A, int64
     }
 }
 
-// One block step of the backward substitution L^T x = z, from the last block to the first:
-// x_b = D_b^T z_b with D_b = L_bb^-1, then z_q -= L_bq^T x_b for the rows above the block, read
-// from U (row q0 + n of U holds column n of L below block q).  For the last block z_b is made
-// here from the forward-updated right-hand side, z_b = D_b r_b.  Every workgroup forms x_b itself
-// (a 64 x 64 matrix-vector product) and updates 32 rows of z; workgroup 0 stores x_b.
-__global__ __launch_bounds__(256) void k_chol_back(const double* __restrict__ A, int64_t m, int64_t lda, int64_t bk,
-                                                  const double* __restrict__ dinv, const double* __restrict__ r,
-                                                  double* __restrict__ z, double* __restrict__ x, int last)
+// y_o = sum_k M[k][o] v_k (trans) or sum_k M[o][k] v_k over all 64 k (v is zero where M's block
+// ends), for the 64 x 64 LDS block M: four lanes per output o = t / 4, each summing every fourth
+// term, the partial sums meeting by lane exchanges; outputs from no on are 0.
+__device__ __forceinline__ double matvec64(const Blk& M, const double* v, int no, bool trans)
 {
-    __shared__ Blk D;
-    __shared__ double zb[kB], xb[kB];
+    const int t = threadIdx.x, o = t >> 2, g = t & 3;
+    double a0 = 0.0, a1 = 0.0;
+#pragma unroll
+    for (int k = 0; k < kB; k += 8) {
+        a0 += (trans ? M[k + g][o] : M[o][k + g]) * v[k + g];
+        a1 += (trans ? M[k + 4 + g][o] : M[o][k + 4 + g]) * v[k + 4 + g];
+    }
+    double acc = a0 + a1;
+    acc += __shfl_xor(acc, 1);
+    acc += __shfl_xor(acc, 2);
+    return o < no ? acc : 0.0;
+}
+
+// Backward substitution L^T x = z, two blocks per launch (from the last block to the first): for
+// the upper block h and the lower block l = h - 1,
+//   x_h = D_h^T z_h,   x_l = D_l^T (z_l - L_hl^T x_h),   z_q -= L_lq^T x_l + L_hq^T x_h (q < l),
+// with D_b = L_bb^-1 and L below the diagonal read from U (row q0 + n of U holds column n of L
+// below block q).  With `two` = 0 the launch takes block h alone.  For the last block z_h is
+// made here from the forward-updated right-hand side, z_h = D_h r_h.  Every workgroup forms the
+// blocks' solution itself (three 64 x 64 matrix-vector products) and updates 32 rows of z, whose
+// U entries it loads first; workgroup 0 stores the solution.
+__global__ __launch_bounds__(256) void k_chol_back(const double* __restrict__ A, int64_t m, int64_t lda, int64_t bh,
+                                                  int two, const double* __restrict__ dinv,
+                                                  const double* __restrict__ r, double* __restrict__ z,
+                                                  double* __restrict__ x, int last)
+{
+    __shared__ Blk Dh, Dl, Uhl;
+    __shared__ double zs[kB], xs[2 * kB];
     const int t = threadIdx.x;
-    const int64_t b0 = bk * kB;
-    const int nb = static_cast<int>(min<int64_t>(kB, m - b0));
-    load_dense(D, dinv + bk * kB * kB);
-    if (t < kB) zb[t] = t < nb ? (last ? r[b0 + t] : z[b0 + t]) : 0.0;
+    const int64_t h0 = bh * kB, l0 = two ? h0 - kB : h0;
+    const int nh = static_cast<int>(min<int64_t>(kB, m - h0));
+    // this workgroup's 32 rows of z: eight lanes per row, sixteen consecutive U entries per lane
+    // over the columns of the launch's blocks (issued before anything waits)
+    const int64_t i = static_cast<int64_t>(blockIdx.x) * 32 + (t >> 3);
+    const int q = 16 * (t & 7);
+    const int ncols = two ? kB + nh : nh;
+    double u[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) u[e] = i < l0 && q + e < ncols ? A[i * lda + l0 + q + e] : 0.0;
+    Rows vh, vl, vu;
+    fetch_dense(vh, dinv + bh * kB * kB);
+    if (two) {
+        fetch_dense(vl, dinv + (bh - 1) * kB * kB);
+        // U rows of block l, columns of block h (zero past the matrix's last column)
+        const int c = t & 63, rb = t >> 6;
+#pragma unroll
+        for (int e = 0; e < 16; ++e) vu[e] = c < nh ? A[(l0 + rb + 4 * e) * lda + h0 + c] : 0.0;
+        store_rows(Dl, vl);
+        store_rows(Uhl, vu);
+    }
+    store_rows(Dh, vh);
+    if (t < kB) zs[t] = t < nh ? (last ? r[h0 + t] : z[h0 + t]) : 0.0;
+    if (t < 2 * kB) xs[t] = 0.0;
     __syncthreads();
-    // four lanes per output entry, each summing every fourth term; the partial sums meet by
-    // lane exchanges within the group of four
-    const int o = t >> 2, g = t & 3;
     if (last) {
-        double v = 0.0;
-        for (int k = g; k <= o && k < nb; k += 4) v += D[o][k] * zb[k];
-        v += __shfl_xor(v, 1);
-        v += __shfl_xor(v, 2);
+        const double v = matvec64(Dh, zs, nh, false);
         __syncthreads();
-        if (g == 0) zb[o] = o < nb ? v : 0.0;
+        if ((t & 3) == 0) zs[t >> 2] = v;
         __syncthreads();
     }
     {
-        double v = 0.0;
-        for (int k = o + g; k < nb; k += 4) v += D[k][o] * zb[k];
-        v += __shfl_xor(v, 1);
-        v += __shfl_xor(v, 2);
-        if (g == 0) xb[o] = o < nb ? v : 0.0;
+        const double v = matvec64(Dh, zs, nh, true);
+        if ((t & 3) == 0) xs[(two ? kB : 0) + (t >> 2)] = v;
     }
     __syncthreads();
-    if (blockIdx.x == 0 && t < nb) x[b0 + t] = xb[t];
-    // 32 rows per workgroup, eight lanes per row, eight consecutive entries per lane
-    const int64_t i = static_cast<int64_t>(blockIdx.x) * 32 + (t >> 3);
-    if (i >= b0) return;
-    const int q = 8 * (t & 7);
-    const double* row = A + i * lda + b0;
+    if (two) {
+        // z_l - L_hl^T x_h, then x_l
+        const double v = matvec64(Uhl, xs + kB, kB, false);
+        if ((t & 3) == 0) zs[t >> 2] = z[l0 + (t >> 2)] - v;
+        __syncthreads();
+        const double xl = matvec64(Dl, zs, kB, true);
+        if ((t & 3) == 0) xs[t >> 2] = xl;
+        __syncthreads();
+    }
+    if (blockIdx.x == 0 && t < ncols) x[l0 + t] = xs[t];
     double v = 0.0;
 #pragma unroll
-    for (int u = 0; u < 8; ++u)
-        if (q + u < nb) v += row[q + u] * xb[q + u];
+    for (int e = 0; e < 16; ++e) v += u[e] * xs[(q + e) & (2 * kB - 1)];
     v += __shfl_xor(v, 1);
     v += __shfl_xor(v, 2);
     v += __shfl_xor(v, 4);
-    if ((t & 7) == 0) z[i] -= v;
+    if (i < l0 && (t & 7) == 0) z[i] -= v;
 }
 
 // r = d - y (FP64 residuals).
@@ -705,10 +760,12 @@ hipError_t launch_chol_back(const double* A, int64_t m, int64_t lda, const doubl
                             double* x, hipStream_t s)
 {
     const int64_t nblk = (m + kB - 1) / kB;
-    for (int64_t bk = nblk - 1; bk >= 0; --bk) {
-        const unsigned blocks = static_cast<unsigned>(bk > 0 ? (bk * kB + 31) / 32 : 1);
-        hipLaunchKernelGGL(k_chol_back, dim3(blocks), dim3(256), 0, s, A, m, lda, bk, dinv, r, z, x,
-                           bk == nblk - 1 ? 1 : 0);
+    for (int64_t bh = nblk - 1; bh >= 0; bh -= 2) {
+        const int two = bh >= 1 ? 1 : 0;
+        const int64_t rows = (bh - two) * kB;  // rows above the launch's blocks
+        const unsigned blocks = static_cast<unsigned>(rows > 0 ? (rows + 31) / 32 : 1);
+        hipLaunchKernelGGL(k_chol_back, dim3(blocks), dim3(256), 0, s, A, m, lda, bh, two, dinv, r, z, x,
+                           bh == nblk - 1 ? 1 : 0);
     }
     return hipGetLastError();
 }
