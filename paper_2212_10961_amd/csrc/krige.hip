@@ -126,6 +126,35 @@ __device__ __forceinline__ void gemm_nt(const Blk& X, const Blk& Y, v4d (&acc)[2
     }
 }
 
+// P = X D^T for the LDS block X and the lower-triangular LDS block D (zero above its diagonal):
+// wave w makes the 16-row strip 16 w of P, column tile bj in acc[bj], whose sum over k stops at
+// D's diagonal (k < 16 (bj + 1)), so every wave takes 40 of the 64 products of a full strip.
+__device__ __forceinline__ void gemm_lower(const Blk& X, const Blk& D, v4d (&acc)[4])
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 15, q = lane >> 4, rb = 16 * w;
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj) acc[bj] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int k = 0; k < kB; k += 4) {
+        const double a = X[rb + r][k + q];
+#pragma unroll
+        for (int bj = 0; bj < 4; ++bj)
+            if (k < 16 * (bj + 1)) acc[bj] = mfma64(a, D[16 * bj + r][k + q], acc[bj]);
+    }
+}
+
+// The strip layout of gemm_lower into LDS.
+__device__ __forceinline__ void strip_to_lds(const v4d (&acc)[4], Blk& S)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int r = lane & 15, q = lane >> 4;
+#pragma unroll
+    for (int bj = 0; bj < 4; ++bj)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) S[16 * w + 4 * e + q][16 * bj + r] = acc[bj][e];
+}
+
 // Row and column, within the 64 x 64 block, of element e of accumulator tile (bi, bj).
 __device__ __forceinline__ int acc_row(int bi, int e)
 {
@@ -134,24 +163,6 @@ __device__ __forceinline__ int acc_row(int bi, int e)
 __device__ __forceinline__ int acc_col(int bj)
 {
     return 32 * ((threadIdx.x >> 6) & 1) + 16 * bj + (threadIdx.x & 15);
-}
-
-__device__ __forceinline__ void acc_zero(v4d (&acc)[2][2])
-{
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = v4d{0.0, 0.0, 0.0, 0.0};
-}
-
-__device__ __forceinline__ void acc_to_lds(const v4d (&acc)[2][2], Blk& S)
-{
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj)
-#pragma unroll
-            for (int e = 0; e < 4; ++e) S[acc_row(bi, e)][acc_col(bj)] = acc[bi][bj][e];
 }
 
 // A 64 x 64 block moves between global memory and LDS in two halves: every thread first loads
@@ -378,7 +389,24 @@ __device__ __forceinline__ void factor_invert(Blk& S, Blk& T, int nb, int64_t g0
                 if (w == 3) trail_tile(S, 0, 48, 32);
             }
             if (sp == 2 && w == 2) trail_tile(S, 16, 48, 48);
-            if (sp == 3 && w == 2) half_inverse(S, T, 0, dout);
+            if (sp == 3 && w == 2) {
+                half_inverse(S, T, 0, dout);
+                __builtin_amdgcn_wave_barrier();
+                // W = L21 L11^-1 (the first product of the whole block's off-diagonal block)
+                // into T's free upper-right quadrant; L11^-1 is now complete
+#pragma unroll
+                for (int tile = 0; tile < 4; ++tile) {
+                    const int wi = 16 * (tile >> 1), wj = 16 * (tile & 1);
+                    v4d a0 = {0.0, 0.0, 0.0, 0.0}, a1 = a0;
+#pragma unroll
+                    for (int k = 0; k < 32; k += 8) {
+                        a0 = mfma64(S[32 + wi + r][k + q], T[k + q][wj + r], a0);
+                        a1 = mfma64(S[32 + wi + r][k + 4 + q], T[k + 4 + q][wj + r], a1);
+                    }
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) T[wi + 4 * e + q][32 + wj + r] = a0[e] + a1[e];
+                }
+            }
         }
         __syncthreads();
         // the update of the next sub-panel's columns by this one
@@ -397,20 +425,9 @@ __device__ __forceinline__ void factor_invert(Blk& S, Blk& T, int nb, int64_t g0
         half_inverse(S, T, 32, dout);
     }
     __syncthreads();
-    // the whole block: W = L21 L11^-1 into T's free upper-right quadrant, then -L22^-1 W, the
-    // lower-left quadrant of the inverse
+    // the whole block's lower-left quadrant of the inverse, -L22^-1 W (W made above)
     const int wi = 16 * (w >> 1), wj = 16 * (w & 1);
     v4d a0 = {0.0, 0.0, 0.0, 0.0}, a1 = a0;
-#pragma unroll
-    for (int k = 0; k < 32; k += 8) {
-        a0 = mfma64(S[32 + wi + r][k + q], T[k + q][wj + r], a0);
-        a1 = mfma64(S[32 + wi + r][k + 4 + q], T[k + 4 + q][wj + r], a1);
-    }
-#pragma unroll
-    for (int e = 0; e < 4; ++e) T[wi + 4 * e + q][32 + wj + r] = a0[e] + a1[e];
-    __syncthreads();
-    a0 = v4d{0.0, 0.0, 0.0, 0.0};
-    a1 = a0;
 #pragma unroll
     for (int k = 0; k < 32; k += 8) {
         a0 = mfma64(T[32 + wi + r][32 + k + q], T[k + q][32 + wj + r], a0);
@@ -494,13 +511,9 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ A, int64
     if (!diag) store_rows(Y, vy);
     if (diag && t < kB) rp[t] = rv;
     __syncthreads();
-    v4d pi[2][2], pj[2][2];
-    acc_zero(pi);
-    gemm_nt(X, D, pi, false);
-    if (!diag) {
-        acc_zero(pj);
-        gemm_nt(Y, D, pj, false);
-    }
+    v4d pi[4], pj[4];
+    gemm_lower(X, D, pi);
+    if (!diag) gemm_lower(Y, D, pj);
     if (diag && t < kB) {
         // z_p = D r_p (D's zeros above the diagonal make the full-length sum exact)
         double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -509,8 +522,8 @@ __global__ __launch_bounds__(256) void k_chol_step(double* __restrict__ A, int64
         zp[t] = (v[0] + v[1]) + (v[2] + v[3]);
     }
     __syncthreads();
-    acc_to_lds(pi, X);
-    if (!diag) acc_to_lds(pj, Y);
+    strip_to_lds(pi, X);
+    if (!diag) strip_to_lds(pj, Y);
     __syncthreads();
     if (b == 0) {
         // U rows k0 + n, columns i0 .. i0 + 63: consecutive lanes take consecutive columns
