@@ -383,6 +383,12 @@ __device__ __forceinline__ void load_to_lds(const uint32_t* g, char* s)
     __builtin_amdgcn_global_load_lds((gbl_void*)g, (lds_void*)s, 16, 0, 0);
 }
 
+// The same from a uniform base plus an unsigned 32-bit byte offset.
+__device__ __forceinline__ void load_to_lds_b(const char* base, uint32_t off, char* s)
+{
+    __builtin_amdgcn_global_load_lds((gbl_void*)(base + off), (lds_void*)s, 16, 0, 0);
+}
+
 __device__ __forceinline__ void wait_loads() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
 // LDS stage: A rows (hi, lo), B rows (hi, lo), then EZR rows of Ez (one per z-slice, 3-D).
@@ -433,20 +439,22 @@ __device__ __forceinline__ void sep_tile_dl(const SepArgs& a, const Epi& epi, in
     // operand.  Tiles start at rotated row blocks so that concurrent requests of different
     // CUs (every z-slice reads the same Q and Ex rows) spread over cache lines and channels.
     const int rot = static_cast<int>((zb * 37 + tx * 11 + ty * 5) & 31);
-    int32_t offa[KA], offb[KB];
+    // byte offsets from the stage's uniform table base (32-bit and unsigned, so the loads take
+    // the scalar-base address form: one register per load and no 64-bit address arithmetic)
+    uint32_t offa[KA], offb[KB];
     int lda[KA], ldb[KB];
 #pragma unroll
     for (int k = 0; k < KA; ++k) {
         const int rb = (wave * KA + k + rot) & (BM / 8 - 1);
         const int row = rb * 8 + (l >> 3);
-        offa[k] = static_cast<int32_t>(min(y0 + row, a.ny - 1) * kJC + 4 * ((l & 7) ^ swz(row)));
+        offa[k] = static_cast<uint32_t>(min(y0 + row, a.ny - 1) * kJC + 4 * ((l & 7) ^ swz(row))) * 4u;
         lda[k] = rb * 8 * ROW_B;
     }
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
         const int rb = (wave * KB + k + rot) & (BN / 8 - 1);
         const int row = rb * 8 + (l >> 3);
-        offb[k] = static_cast<int32_t>(min(x0 + row, a.nx - 1) * kJC + 4 * ((l & 7) ^ swz(row)));
+        offb[k] = static_cast<uint32_t>(min(x0 + row, a.nx - 1) * kJC + 4 * ((l & 7) ^ swz(row))) * 4u;
         ldb[k] = rb * 8 * ROW_B;
     }
 
@@ -458,21 +466,21 @@ __device__ __forceinline__ void sep_tile_dl(const SepArgs& a, const Epi& epi, in
         if constexpr (D3) {
             if (wave == 0 && l < 8 * ZS) load_to_lds(ezl + j0, buf + EZ_OFF);
         }
-        const uint32_t* sa = qy + j0 * a.ny;
+        const char* sa = reinterpret_cast<const char*>(qy + j0 * a.ny);
 #pragma unroll
-        for (int k = 0; k < KA; ++k) load_to_lds(sa + offa[k], buf + lda[k]);
+        for (int k = 0; k < KA; ++k) load_to_lds_b(sa, offa[k], buf + lda[k]);
         if constexpr (X3) {
-            const uint32_t* sl = qy_lo + j0 * a.ny;
+            const char* sl = reinterpret_cast<const char*>(qy_lo + j0 * a.ny);
 #pragma unroll
-            for (int k = 0; k < KA; ++k) load_to_lds(sl + offa[k], buf + BM * ROW_B + lda[k]);
+            for (int k = 0; k < KA; ++k) load_to_lds_b(sl, offa[k], buf + BM * ROW_B + lda[k]);
         }
-        const uint32_t* sb = px + j0 * a.nx;
+        const char* sb = reinterpret_cast<const char*>(px + j0 * a.nx);
 #pragma unroll
-        for (int k = 0; k < KB; ++k) load_to_lds(sb + offb[k], buf + NB * BM * ROW_B + ldb[k]);
+        for (int k = 0; k < KB; ++k) load_to_lds_b(sb, offb[k], buf + NB * BM * ROW_B + ldb[k]);
         if constexpr (X3) {
-            const uint32_t* sl = px_lo + j0 * a.nx;
+            const char* sl = reinterpret_cast<const char*>(px_lo + j0 * a.nx);
 #pragma unroll
-            for (int k = 0; k < KB; ++k) load_to_lds(sl + offb[k], buf + (NB * BM + BN) * ROW_B + ldb[k]);
+            for (int k = 0; k < KB; ++k) load_to_lds_b(sl, offb[k], buf + (NB * BM + BN) * ROW_B + ldb[k]);
         }
     };
 
