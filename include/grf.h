@@ -247,10 +247,11 @@ int eval_field_points_ws_size(const grf_modes* modes, int64_t n_points, int meth
  *   xyz      device double[P][dim] (row-major).
  *   method   GRF_DIRECT_F32: cos and sum in FP32 with FP64 phase reduction, in one of two forms
  *              GRF_DIRECT_F32_BINNED (what GRF_DIRECT_F32 uses from 65,536 points): points are
- *                sorted into cubic cells of their bounding box (about 256 per cell), the phase
- *                at the cell centre is reduced in FP64 per mode and group of 8 points of a cell
- *                and each point adds its offset's phase in FP32; modes whose offset phase can
- *                reach 4 revolutions within a cell take the per-point FP64 reduction instead.
+ *                sorted into cubic cells of their bounding box (about 2,048 per cell, slots
+ *                padded to work items of 256), the phase at the cell centre is reduced in FP64
+ *                per mode and work item and each point adds its offset's phase, formed on the
+ *                matrix cores with FP32 accuracy; modes whose offset phase can reach 4
+ *                revolutions within a cell take the per-point FP64 reduction instead.
  *                At most 2^30 points (GRF_EUNSUPPORTED above).  A point's value does not depend
  *                on the other points (deterministic);
  *              GRF_DIRECT_F32_POINTWISE: phase a.x + psi reduced in FP64 per mode and point;

@@ -7,9 +7,10 @@
 // mode j at point p of a cell with centre c is
 //   r_jp = frac(a_j . c + psi_j) + a_j . (x_p - c),
 // the first part reduced in FP64 once per (mode, work item), the second small (cells are
-// small).  For 16 modes and 16 points both parts together are one FP32 matrix product on the
-// matrix cores, [a_x a_y a_z frac(a.c + psi)] (16 x 4) times [dx dy dz 1]^T (4 x 16), so the
-// vector units spend one hardware cosine (argument in revolutions) and one FMA per term.
+// small).  For 16 modes and 16 points both parts together are one matrix product on the
+// matrix cores, [a_x a_y a_z frac(a.c + psi)] (16 x 4) times [dx dy dz 1]^T (4 x 16), taken in
+// fp16 with FP32 accumulation and every factor split hi + lo (FP32-accurate), so the vector
+// units spend one hardware cosine (argument in revolutions) and one FMA per term.
 // Modes whose local part can reach kLocalRev revolutions in a cell (heavy spectral tails) take
 // weight 0 in that pass and are added in a second pass that reduces a_j . x_p + psi_j per
 // point in FP64 from the FP64 offsets (a branch uniform over the wave).  A point's value
