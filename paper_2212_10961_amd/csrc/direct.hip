@@ -199,8 +199,18 @@ __global__ __launch_bounds__(256) void k_points_reduce(const float* __restrict__
 {
     const int64_t p = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (p >= P) return;
+    // Sixteen slice loads are in flight at a time; the adds keep slice order.
+    constexpr int kGroup = 16;
     float s = 0.f;
-    for (int q = 0; q < slices; ++q) s += partial[static_cast<int64_t>(q) * P + p];
+    int q = 0;
+    for (; q + kGroup <= slices; q += kGroup) {
+        float v[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) v[u] = partial[static_cast<int64_t>(q + u) * P + p];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) s += v[u];
+    }
+    for (; q < slices; ++q) s += partial[static_cast<int64_t>(q) * P + p];
     store_out(p, amp * s, epi, y, k, ind);
 }
 
