@@ -40,21 +40,31 @@ __device__ __forceinline__ T corr_r2(int kind, T r2)
     return (T(1) + a + a * a * T(1.0 / 3.0)) * exp(-a);
 }
 
-// FP32 correlation for the correction sum, on the hardware square root and base-2 exponential
-// (about 1 ulp each; the sum is FP32 anyway).
-template <int KIND>
-__device__ __forceinline__ float corr_r2f(float r2)
+// The correction sum works on lags scaled by kappa, chosen so that the base-2 exponential takes
+// the scaled distance as it is: Gaussian exp(-r^2) = 2^-(kappa r)^2 with kappa^2 = log2(e);
+// exponential exp(-r) = 2^-(kappa r) with kappa = log2(e); Matern nu = 3/2, 5/2:
+// exp(-c r) = 2^-(kappa r) with kappa = c log2(e), c = sqrt3, sqrt5, and c r = (kappa r) ln 2.
+__device__ __forceinline__ double lag_scale(int kind)
 {
-    constexpr float kLog2e = 1.4426950408889634f;
-    if constexpr (KIND == KR_GAUSS) return __builtin_amdgcn_exp2f(-r2 * kLog2e);
-    const float r = __builtin_amdgcn_sqrtf(r2);
-    if constexpr (KIND == KR_EXP) return __builtin_amdgcn_exp2f(-r * kLog2e);
-    if constexpr (KIND == KR_M32) {
-        const float a = 1.7320508f * r;
-        return (1.f + a) * __builtin_amdgcn_exp2f(-a * kLog2e);
-    }
-    const float a = 2.2360680f * r;
-    return (1.f + a + a * a * (1.f / 3.f)) * __builtin_amdgcn_exp2f(-a * kLog2e);
+    constexpr double kLog2e = 1.4426950408889634074;
+    if (kind == KR_GAUSS) return 1.2011224087864498;  // sqrt(log2(e))
+    if (kind == KR_EXP) return kLog2e;
+    if (kind == KR_M32) return 1.7320508075688772935 * kLog2e;
+    return 2.2360679774997896964 * kLog2e;
+}
+
+// FP32 correlation of the scaled squared lag q = (kappa r)^2, on the hardware square root and
+// base-2 exponential (about 1 ulp each; the sum is FP32 anyway).
+template <int KIND>
+__device__ __forceinline__ float corr_scaled(float q)
+{
+    if constexpr (KIND == KR_GAUSS) return __builtin_amdgcn_exp2f(-q);
+    const float s = __builtin_amdgcn_sqrtf(q);
+    const float e = __builtin_amdgcn_exp2f(-s);
+    if constexpr (KIND == KR_EXP) return e;
+    const float a = s * 0.69314718f;  // c r
+    if constexpr (KIND == KR_M32) return fmaf(a, e, e);
+    return fmaf(fmaf(a, 1.f / 3.f, 1.f), a, 1.f) * e;
 }
 
 // Standardised lag u = M^T dx (M^T given row-major 3 x 3 in `mt`).
@@ -674,8 +684,8 @@ __global__ __launch_bounds__(256) void k_residual(const float* __restrict__ d, c
     if (i < m) r[i] = static_cast<double>(d[i]) - static_cast<double>(y[i]);
 }
 
-// Observation staging for the correction: (u = M^T (x_i - x_0) as FP32, w_i = sigma^2 alpha_i);
-// lags are taken from the first observation so that the FP32 differences stay small.
+// Observation staging for the correction: (u = kappa M^T (x_i - x_0) as FP32, w_i = sigma^2
+// alpha_i); lags are taken from the first observation so that the FP32 differences stay small.
 __global__ __launch_bounds__(256) void k_krige_stage(const double* __restrict__ x, const double* __restrict__ alpha,
                                                     int64_t m, int dim, KrigeModel km, float4* __restrict__ out)
 {
@@ -683,15 +693,17 @@ __global__ __launch_bounds__(256) void k_krige_stage(const double* __restrict__ 
     if (i >= m) return;
     const double* xi = x + i * dim;
     const double d0 = xi[0] - x[0], d1 = xi[1] - x[1], d2 = dim == 3 ? xi[2] - x[2] : 0.0;
-    const double u0 = km.mt[0] * d0 + km.mt[1] * d1 + km.mt[2] * d2;
-    const double u1 = km.mt[3] * d0 + km.mt[4] * d1 + km.mt[5] * d2;
-    const double u2 = km.mt[6] * d0 + km.mt[7] * d1 + km.mt[8] * d2;
+    const double ks = lag_scale(km.kind);
+    const double u0 = ks * (km.mt[0] * d0 + km.mt[1] * d1 + km.mt[2] * d2);
+    const double u1 = ks * (km.mt[3] * d0 + km.mt[4] * d1 + km.mt[5] * d2);
+    const double u2 = ks * (km.mt[6] * d0 + km.mt[7] * d1 + km.mt[8] * d2);
     out[i] = make_float4(static_cast<float>(u0), static_cast<float>(u1), static_cast<float>(u2),
                          static_cast<float>(km.s2 * alpha[i]));
 }
 
 constexpr int kKc = 256;  // observations per LDS chunk
-constexpr int kKr = 4;    // cells per lane
+constexpr int kKr = 4;    // cells per lane (general form)
+constexpr int kKx = 8;    // cells per lane along a grid row (row form)
 
 // y[c] += sum_i w_i rho(|u(c) - u_i|) for cells of a grid (grid != nullptr) or points.
 template <bool GRID, int KIND>
@@ -700,6 +712,7 @@ __global__ __launch_bounds__(256) void k_krige_apply(const float4* __restrict__ 
 {
     __shared__ float4 so[kKc];
     const int64_t base = static_cast<int64_t>(blockIdx.x) * (256 * kKr) + threadIdx.x;
+    const double ks = lag_scale(KIND);
     float v0[kKr], v1[kKr], v2[kKr], acc[kKr];
 #pragma unroll
     for (int r = 0; r < kKr; ++r) {
@@ -717,9 +730,9 @@ __global__ __launch_bounds__(256) void k_krige_apply(const float4* __restrict__ 
             if (tg.dim == 3) x2 = tg.xyz[c * tg.dim + 2];
         }
         const double d0 = x0 - ref[0], d1 = x1 - ref[1], d2 = tg.dim == 3 ? x2 - ref[2] : 0.0;
-        v0[r] = static_cast<float>(km.mt[0] * d0 + km.mt[1] * d1 + km.mt[2] * d2);
-        v1[r] = static_cast<float>(km.mt[3] * d0 + km.mt[4] * d1 + km.mt[5] * d2);
-        v2[r] = static_cast<float>(km.mt[6] * d0 + km.mt[7] * d1 + km.mt[8] * d2);
+        v0[r] = static_cast<float>(ks * (km.mt[0] * d0 + km.mt[1] * d1 + km.mt[2] * d2));
+        v1[r] = static_cast<float>(ks * (km.mt[3] * d0 + km.mt[4] * d1 + km.mt[5] * d2));
+        v2[r] = static_cast<float>(ks * (km.mt[6] * d0 + km.mt[7] * d1 + km.mt[8] * d2));
         acc[r] = 0.f;
     }
     for (int64_t i0 = 0; i0 < m; i0 += kKc) {
@@ -732,7 +745,7 @@ __global__ __launch_bounds__(256) void k_krige_apply(const float4* __restrict__ 
 #pragma unroll
             for (int r = 0; r < kKr; ++r) {
                 const float a = v0[r] - o.x, b = v1[r] - o.y, e = v2[r] - o.z;
-                acc[r] = fmaf(o.w, corr_r2f<KIND>(a * a + b * b + e * e), acc[r]);
+                acc[r] = fmaf(o.w, corr_scaled<KIND>(a * a + b * b + e * e), acc[r]);
             }
         }
     }
@@ -741,6 +754,58 @@ __global__ __launch_bounds__(256) void k_krige_apply(const float4* __restrict__ 
         const int64_t c = base + 256 * r;
         if (c < tg.count) y[c] += acc[r];
     }
+}
+
+// Row form of the grid correction, for maps whose second and third lag components do not
+// depend on the x index (M^T entries (1, 0) and (2, 0) zero: no rotation that mixes x into
+// them).  Each lane takes kKx consecutive cells of one grid row; they share u1 and u2, so the
+// part (u1 - u_i1)^2 + (u2 - u_i2)^2 of the squared lag is formed once per observation and row.
+template <int KIND>
+__global__ __launch_bounds__(256) void k_krige_apply_rows(const float4* __restrict__ obs,
+                                                         const double* __restrict__ ref, int64_t m, KrigeModel km,
+                                                         KrigeTarget tg, float* __restrict__ y)
+{
+    __shared__ float4 so[kKc];
+    const int64_t n0 = tg.n[0];
+    const int64_t nq = (n0 + kKx - 1) / kKx;  // lanes per row
+    const int64_t units = tg.count / n0 * nq;
+    const int64_t u = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
+    const int64_t uc = min(u, units - 1);
+    const int64_t row = uc / nq, xs = (uc % nq) * kKx;
+    const int64_t j = row % tg.n[1], k = row / tg.n[1];
+    const double ks = lag_scale(KIND);
+    const double d1 = tg.o[1] + (static_cast<double>(j) + 0.5) * tg.h[1] - ref[1];
+    const double d2 = tg.dim == 3 ? tg.o[2] + (static_cast<double>(k) + 0.5) * tg.h[2] - ref[2] : 0.0;
+    const float w1 = static_cast<float>(ks * (km.mt[4] * d1 + km.mt[5] * d2));
+    const float w2 = static_cast<float>(ks * (km.mt[7] * d1 + km.mt[8] * d2));
+    float v0[kKx], acc[kKx];
+#pragma unroll
+    for (int r = 0; r < kKx; ++r) {
+        const double d0 = tg.o[0] + (static_cast<double>(min(xs + r, n0 - 1)) + 0.5) * tg.h[0] - ref[0];
+        v0[r] = static_cast<float>(ks * (km.mt[0] * d0 + km.mt[1] * d1 + km.mt[2] * d2));
+        acc[r] = 0.f;
+    }
+    for (int64_t i0 = 0; i0 < m; i0 += kKc) {
+        const int nc = static_cast<int>(min<int64_t>(kKc, m - i0));
+        __syncthreads();
+        if (threadIdx.x < nc) so[threadIdx.x] = obs[i0 + threadIdx.x];
+        __syncthreads();
+        for (int q = 0; q < nc; ++q) {
+            const float4 o = so[q];
+            const float b = w1 - o.y, e = w2 - o.z;
+            const float be = fmaf(b, b, e * e);
+#pragma unroll
+            for (int r = 0; r < kKx; ++r) {
+                const float a = v0[r] - o.x;
+                acc[r] = fmaf(o.w, corr_scaled<KIND>(fmaf(a, a, be)), acc[r]);
+            }
+        }
+    }
+    if (u >= units) return;
+    float* yr = y + row * n0;
+#pragma unroll
+    for (int r = 0; r < kKx; ++r)
+        if (xs + r < n0) yr[xs + r] += acc[r];
 }
 
 }  // namespace
@@ -800,8 +865,22 @@ hipError_t launch_krige_stage(const double* x, const double* alpha, int64_t m, i
 hipError_t launch_krige_apply(const float4* obs, const double* xobs, int64_t m, const KrigeModel& km,
                               const KrigeTarget& tg, float* y, hipStream_t s)
 {
+    if (tg.count <= 0) return hipSuccess;
+    if (tg.grid && km.mt[3] == 0.0 && km.mt[6] == 0.0) {
+        const int64_t n0 = tg.n[0];
+        const int64_t units = tg.count / n0 * ((n0 + kKx - 1) / kKx);
+        const int64_t rb = (units + 255) / 256;
+        if (rb > 0x7fffffff) return hipErrorInvalidValue;
+        const dim3 gr(static_cast<unsigned>(rb));
+        switch (km.kind) {
+        case KR_GAUSS: hipLaunchKernelGGL((k_krige_apply_rows<KR_GAUSS>), gr, dim3(256), 0, s, obs, xobs, m, km, tg, y); break;
+        case KR_EXP: hipLaunchKernelGGL((k_krige_apply_rows<KR_EXP>), gr, dim3(256), 0, s, obs, xobs, m, km, tg, y); break;
+        case KR_M32: hipLaunchKernelGGL((k_krige_apply_rows<KR_M32>), gr, dim3(256), 0, s, obs, xobs, m, km, tg, y); break;
+        default: hipLaunchKernelGGL((k_krige_apply_rows<KR_M52>), gr, dim3(256), 0, s, obs, xobs, m, km, tg, y); break;
+        }
+        return hipGetLastError();
+    }
     const int64_t blocks = (tg.count + 256 * kKr - 1) / (256 * kKr);
-    if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 g(static_cast<unsigned>(blocks));
     switch (km.kind * 2 + (tg.grid ? 1 : 0)) {
