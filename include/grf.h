@@ -192,7 +192,9 @@ int eval_field_grid_ws_size(const grf_modes* modes, const grf_grid* grid, int me
  *                     At least one output must be non-NULL.  epi may be NULL when
  *                     k and ind are NULL.
  *   ws, ws_bytes      device workspace of at least eval_field_grid_ws_size bytes
- *                     (GRF_ENOMEM otherwise); contents on entry are ignored.
+ *                     (GRF_ENOMEM otherwise): the per-axis tables and, for DIRECT_F64 on
+ *                     grids too small to fill the device (under 131,072 cells), the FP64
+ *                     partial sums of its mode slices; contents on entry are ignored.
  * Separable methods require dim 3 grids with nx, ny >= 1 (any size; ragged tiles
  * are masked) or dim 2 grids.  Phases are range-reduced per axis in FP64.
  */
@@ -202,8 +204,9 @@ int eval_field_grid(const grf_modes* modes, const grf_grid* grid, int method, co
 /*
  * eval_field_grid_noalloc -- eval_field_grid for callers that cannot allocate device memory
  * (code under hipGraph capture, tight serving loops, harnesses that forbid hipMalloc): the
- * per-axis tables go to a fixed scratch array of GRF_NOALLOC_SCRATCH_BYTES that the library
- * holds on each device it runs on until the process ends, instead of a caller workspace.
+ * workspace (per-axis tables, partial sums) goes to a fixed scratch array of
+ * GRF_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on until the
+ * process ends, instead of a caller workspace.
  *   Arguments as eval_field_grid without ws / ws_bytes; outputs are still the caller's.
  *   A problem whose workspace (eval_field_grid_ws_size) exceeds the scratch size is
  *   GRF_ENOMEM, with nothing enqueued.  Allocates nothing (no hipMalloc, hipFree or

@@ -186,6 +186,8 @@ GridWs grid_ws(const grf_modes* m, const grf_grid* g, int method, void* base)
         for (int a = 0; a < 3; ++a) w.t[a] = c.take<float>(size_t(g->n[a]) * ldp);
     } else if (method == GRF_DIRECT_F64) {
         for (int a = 0; a < 3; ++a) w.t[a] = c.take<double>(size_t(g->n[a]) * ldp);
+        const ModeSlices ms = direct_grid_f64_slices(g->n, m->n);
+        if (ms.slices > 1) w.partial = c.take<double>(size_t(ms.slices) * size_t(g->n[0] * g->n[1] * g->n[2]));
     } else if (is_sep(method)) {
         const bool hilo = is_hilo(method);
         if (dim == 2) {
@@ -368,7 +370,7 @@ static int grid_launch(const grf_modes* modes, const grf_grid* grid, int method,
         const double amp64 = modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n));
         GRF_HIP(launch_direct_grid_f64(static_cast<const double*>(w.t[0]), static_cast<const double*>(w.t[1]),
                                        static_cast<const double*>(w.t[2]), modes->w, modes->n, ldp, grid->n, amp64, e,
-                                       0.0, y, k, ind, nullptr, nullptr, s));
+                                       0.0, y, k, ind, nullptr, nullptr, static_cast<double*>(w.partial), s));
     }
     return GRF_OK;
 }
@@ -700,7 +702,8 @@ int eval_field_grid_f64(const grf_modes* modes, const grf_grid* grid, double mu,
     const double amp64 = modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n));
     GRF_HIP(launch_direct_grid_f64(static_cast<const double*>(w.t[0]), static_cast<const double*>(w.t[1]),
                                    static_cast<const double*>(w.t[2]), modes->w, modes->n, padded_modes(modes->n),
-                                   grid->n, amp64, Epi{}, mu, nullptr, nullptr, nullptr, y64, k64, s));
+                                   grid->n, amp64, Epi{}, mu, nullptr, nullptr, nullptr, y64, k64,
+                                   static_cast<double*>(w.partial), s));
     return GRF_OK;
 }
 

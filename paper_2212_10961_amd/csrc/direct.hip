@@ -8,6 +8,8 @@
 // to it without a further reduction.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "grf_internal.h"
 
 namespace grf {
@@ -23,17 +25,21 @@ __device__ __forceinline__ void store_out(int64_t c, float yv, const Epi& e, flo
 }
 
 // ---------------------------------------------------------------------------- grid, FP32
-// Block tile: 64 x-cells by 64 (y,z) pairs; 256 threads; each lane owns 4 x 4 cells
-// (x = x0 + lx + 16 rx, q = q0 + 16 w + ly + 4 rq).  Mode chunks of 64 are staged in
+// Block tile: 16 RA x-cells by 16 RB (y,z) pairs; 256 threads; each lane owns RA x RB cells
+// (x = x0 + lx + 16 a, q = q0 + 4 RB w + (l / 16) + 4 b).  Mode chunks of 64 are staged in
 // LDS: sx[x][j] = Tx, sq[q][j] = Ty + Tz (psi folded in Ty), sw[j] = per-mode weight (1
-// without weights).  Rows are padded to 68 floats so the 16 distinct x rows of a wave's
-// 128-bit reads hit distinct banks.
+// without weights).  Rows of J modes are padded by 4 floats so the 16 distinct x rows of a
+// wave's 128-bit reads hit distinct banks.  Every cell is summed by one lane over the modes
+// in order, whatever the tile and chunk: neither changes a result bit.  Large grids take
+// 4 x 4 cells per lane (64 x 64 tiles, the batch's tile, chunks of 64 modes); small ones
+// 2 x 2 or 1 x 1 cells for more blocks, with chunks of 128 or 256 modes so that the fewer
+// terms per lane still cover each chunk's loads.
 constexpr int kDgB = 64;
-constexpr int kDgJ = 64;
-constexpr int kDgRow = (kDgJ + 4) / 4;  // float4 per padded row
 static_assert(kDgB == kDirectTile, "tile side shared with the batch planner");
 
-// One 64 x 64 (x, (y,z)) tile; `sx`, `sq` are LDS arrays of kDgB * kDgRow float4.  Whole block.
+// One (16 RA) x (16 RB) (x, (y,z)) tile, mode chunks of J; `sx`, `sq` are LDS arrays of
+// 16 RA (16 RB) * (J + 4) / 4 float4, `sw` of J / 4.  Whole block.
+template <int RA, int RB, int J>
 __device__ __forceinline__ void direct_tile(const float* __restrict__ tx, const float* __restrict__ ty,
                                             const float* __restrict__ tz, const double* __restrict__ wt, int n,
                                             int64_t ldp, int nx, int ny, int64_t nq, int x0, int64_t q0, float amp,
@@ -42,28 +48,43 @@ __device__ __forceinline__ void direct_tile(const float* __restrict__ tx, const 
 {
     const int t = threadIdx.x;
     const int w = t >> 6, l = t & 63;
-    const int lx = l & 15, lq = w * 16 + (l >> 4);
+    const int lx = l & 15, lq = w * 4 * RB + (l >> 4);
+    constexpr int kRow = (J + 4) / 4;  // float4 per padded row
+    constexpr int kC4 = J / 4;         // float4 per chunk of one row
 
-    float acc[4][4];
+    float acc[RA][RB];
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < RA; ++a)
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.f;
+        for (int b = 0; b < RB; ++b) acc[a][b] = 0.f;
 
-    for (int j0 = 0; j0 < n; j0 += kDgJ) {
+    for (int j0 = 0; j0 < n; j0 += J) {
+        // (rows are ldp long, a multiple of 64: a chunk past it stages zeros it never sums)
 #pragma unroll
-        for (int it = 0; it < 4; ++it) {
+        for (int it = 0; it < RA * J / 64; ++it) {
             const int e = it * 256 + t;
-            const int row = e >> 4, c4 = e & 15;
+            const int row = e / kC4, c4 = e % kC4;
             const int xg = min(x0 + row, nx - 1);
-            sx[row * kDgRow + c4] = *reinterpret_cast<const float4*>(tx + static_cast<int64_t>(xg) * ldp + j0 + 4 * c4);
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (J == 64 || j0 + 4 * c4 < ldp)
+                v = *reinterpret_cast<const float4*>(tx + static_cast<int64_t>(xg) * ldp + j0 + 4 * c4);
+            sx[row * kRow + c4] = v;
+        }
+#pragma unroll
+        for (int it = 0; it < RB * J / 64; ++it) {
+            const int e = it * 256 + t;
+            const int row = e / kC4, c4 = e % kC4;
             const int64_t q = min(q0 + row, nq - 1);
             const int64_t yy = q % ny, zz = q / ny;
-            const float4 a = *reinterpret_cast<const float4*>(ty + yy * ldp + j0 + 4 * c4);
-            const float4 b = *reinterpret_cast<const float4*>(tz + zz * ldp + j0 + 4 * c4);
-            sq[row * kDgRow + c4] = make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (J == 64 || j0 + 4 * c4 < ldp) {
+                const float4 a = *reinterpret_cast<const float4*>(ty + yy * ldp + j0 + 4 * c4);
+                const float4 b = *reinterpret_cast<const float4*>(tz + zz * ldp + j0 + 4 * c4);
+                v = make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+            }
+            sq[row * kRow + c4] = v;
         }
-        if (t < kDgJ / 4) {
+        if (t < J / 4) {
             float4 wv = make_float4(1.f, 1.f, 1.f, 1.f);
             if (wt) {
                 const int j = j0 + 4 * t;  // modes past n carry no weight (their terms are not summed)
@@ -74,19 +95,19 @@ __device__ __forceinline__ void direct_tile(const float* __restrict__ tx, const 
             sw[t] = wv;
         }
         __syncthreads();
-        const int jn = min(kDgJ, n - j0);
+        const int jn = min(J, n - j0);
         const int j4 = jn >> 2;
         for (int m = 0; m < j4; ++m) {
-            float4 vx[4], vq[4];
+            float4 vx[RA], vq[RB];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) vx[r] = sx[(lx + 16 * r) * kDgRow + m];
+            for (int r = 0; r < RA; ++r) vx[r] = sx[(lx + 16 * r) * kRow + m];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) vq[r] = sq[(lq + 4 * r) * kDgRow + m];
+            for (int r = 0; r < RB; ++r) vq[r] = sq[(lq + 4 * r) * kRow + m];
             const float4 wv = sw[m];
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < RA; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b) {
+                for (int b = 0; b < RB; ++b) {
                     acc[a][b] = fmaf(wv.x, cos_rev(vx[a].x + vq[b].x), acc[a][b]);
                     acc[a][b] = fmaf(wv.y, cos_rev(vx[a].y + vq[b].y), acc[a][b]);
                     acc[a][b] = fmaf(wv.z, cos_rev(vx[a].z + vq[b].z), acc[a][b]);
@@ -98,20 +119,20 @@ __device__ __forceinline__ void direct_tile(const float* __restrict__ tx, const 
         const float* swf = reinterpret_cast<const float*>(sw);
         for (int m = j4 * 4; m < jn; ++m) {
 #pragma unroll
-            for (int a = 0; a < 4; ++a)
+            for (int a = 0; a < RA; ++a)
 #pragma unroll
-                for (int b = 0; b < 4; ++b)
-                    acc[a][b] = fmaf(swf[m], cos_rev(sxf[(lx + 16 * a) * kDgRow * 4 + m] + sqf[(lq + 4 * b) * kDgRow * 4 + m]),
+                for (int b = 0; b < RB; ++b)
+                    acc[a][b] = fmaf(swf[m], cos_rev(sxf[(lx + 16 * a) * kRow * 4 + m] + sqf[(lq + 4 * b) * kRow * 4 + m]),
                                      acc[a][b]);
         }
         __syncthreads();
     }
 
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
+    for (int a = 0; a < RA; ++a) {
         const int x = x0 + lx + 16 * a;
 #pragma unroll
-        for (int b = 0; b < 4; ++b) {
+        for (int b = 0; b < RB; ++b) {
             const int64_t q = q0 + lq + 4 * b;
             if (x < nx && q < nq) {
                 store_out(q * nx + x, amp * acc[a][b], epi, y, k, ind);
@@ -120,18 +141,19 @@ __device__ __forceinline__ void direct_tile(const float* __restrict__ tx, const 
     }
 }
 
+template <int R, int J>
 __global__ __launch_bounds__(256, 2) void k_direct_grid(const float* __restrict__ tx, const float* __restrict__ ty,
                                                        const float* __restrict__ tz, const double* __restrict__ wt,
                                                        int n, int64_t ldp, int nx, int ny, int64_t nq, int nxt,
                                                        float amp, Epi epi, float* __restrict__ y,
                                                        float* __restrict__ k, uint8_t* __restrict__ ind)
 {
-    __shared__ float4 sx[kDgB * kDgRow];
-    __shared__ float4 sq[kDgB * kDgRow];
-    __shared__ float4 sw[kDgJ / 4];
+    __shared__ float4 sx[16 * R * ((J + 4) / 4)];
+    __shared__ float4 sq[16 * R * ((J + 4) / 4)];
+    __shared__ float4 sw[J / 4];
     const int64_t bid = blockIdx.x;
-    direct_tile(tx, ty, tz, wt, n, ldp, nx, ny, nq, static_cast<int>(bid % nxt) * kDgB, (bid / nxt) * kDgB, amp,
-                      epi, y, k, ind, sx, sq, sw);
+    direct_tile<R, R, J>(tx, ty, tz, wt, n, ldp, nx, ny, nq, static_cast<int>(bid % nxt) * 16 * R, (bid / nxt) * 16 * R,
+                      amp, epi, y, k, ind, sx, sq, sw);
 }
 
 // Persistent batched form: blocks pull (instance, tile) work items from one atomic counter
@@ -139,9 +161,9 @@ __global__ __launch_bounds__(256, 2) void k_direct_grid(const float* __restrict_
 __global__ __launch_bounds__(256, 2) void k_direct_batch(const DirectBatchItem* __restrict__ items, int n_inst,
                                                         int64_t total, unsigned long long* counter)
 {
-    __shared__ float4 sx[kDgB * kDgRow];
-    __shared__ float4 sq[kDgB * kDgRow];
-    __shared__ float4 sw[kDgJ / 4];
+    __shared__ float4 sx[kDgB * 17];
+    __shared__ float4 sq[kDgB * 17];
+    __shared__ float4 sw[16];
     __shared__ unsigned long long s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1ull);
@@ -157,21 +179,35 @@ __global__ __launch_bounds__(256, 2) void k_direct_batch(const DirectBatchItem* 
         }
         const DirectBatchItem& b = items[lo];
         const int64_t local = it - b.item0;
-        direct_tile(b.tx, b.ty, b.tz, b.w, b.n, b.ldp, b.nx, b.ny, b.nq, static_cast<int>(local % b.nxt) * kDgB,
-                    (local / b.nxt) * kDgB, b.amp, b.epi, b.y, b.k, b.ind, sx, sq, sw);
+        direct_tile<4, 4, 64>(b.tx, b.ty, b.tz, b.w, b.n, b.ldp, b.nx, b.ny, b.nq, static_cast<int>(local % b.nxt) * kDgB,
+                          (local / b.nxt) * kDgB, b.amp, b.epi, b.y, b.k, b.ind, sx, sq, sw);
     }
 }
 
 // ---------------------------------------------------------------------------- grid, FP64
 // One thread per cell, FP64 per-axis fractions summed and reduced in FP64, cos by
-// the device library's cospi.  For small problems and as a reference-grade path.
+// the device library's cospi.  For small problems and as a reference-grade path.  Grids
+// too small to fill the device split the modes over blockIdx.y slices of `mslice` modes:
+// each slice writes its raw FP64 sums to partial[slice][C] and k_grid_reduce_f64 adds them
+// in slice order.
+__device__ __forceinline__ void grid_out_f64(int64_t c, double yv, const Epi& epi, double mu64,
+                                             float* __restrict__ y, float* __restrict__ k,
+                                             uint8_t* __restrict__ ind, double* __restrict__ y64,
+                                             double* __restrict__ k64)
+{
+    if (y64) y64[c] = yv;
+    if (k64) k64[c] = exp(mu64 + yv);
+    if (y || k || ind) store_out(c, static_cast<float>(yv), epi, y, k, ind);
+}
+
 __global__ __launch_bounds__(256) void k_direct_grid_f64(const double* __restrict__ tx, const double* __restrict__ ty,
                                                         const double* __restrict__ tz, const double* __restrict__ wt,
                                                         int n, int64_t ldp, int nx,
                                                         int ny, int64_t C, double amp, Epi epi, double mu64,
                                                         float* __restrict__ y, float* __restrict__ k,
                                                         uint8_t* __restrict__ ind, double* __restrict__ y64,
-                                                        double* __restrict__ k64)
+                                                        double* __restrict__ k64, int mslice,
+                                                        double* __restrict__ partial)
 {
     const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (c >= C) return;
@@ -180,16 +216,41 @@ __global__ __launch_bounds__(256) void k_direct_grid_f64(const double* __restric
     const double* rx = tx + i * ldp;
     const double* ry = ty + jy * ldp;
     const double* rz = tz + kz * ldp;
+    const int j0 = static_cast<int>(blockIdx.y) * mslice;
+    const int j1 = min(n, j0 + mslice);
     double s = 0.0;
-    for (int j = 0; j < n; ++j) {
+    for (int j = j0; j < j1; ++j) {
         double f = rx[j] + ry[j] + rz[j];
         f = __builtin_amdgcn_fract(f);  // x - floor(x) in one FP64 instruction
         s += (wt ? wt[j] : 1.0) * cospi(2.0 * f);
     }
-    const double yv = amp * s;
-    if (y64) y64[c] = yv;
-    if (k64) k64[c] = exp(mu64 + yv);
-    if (y || k || ind) store_out(c, static_cast<float>(yv), epi, y, k, ind);
+    if (partial) {
+        partial[static_cast<int64_t>(blockIdx.y) * C + c] = s;
+        return;
+    }
+    grid_out_f64(c, amp * s, epi, mu64, y, k, ind, y64, k64);
+}
+
+__global__ __launch_bounds__(256) void k_grid_reduce_f64(const double* __restrict__ partial, int slices, int64_t C,
+                                                        double amp, Epi epi, double mu64, float* __restrict__ y,
+                                                        float* __restrict__ k, uint8_t* __restrict__ ind,
+                                                        double* __restrict__ y64, double* __restrict__ k64)
+{
+    const int64_t c = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= C) return;
+    // Sixteen slice loads are in flight at a time; the adds keep slice order.
+    constexpr int kGroup = 16;
+    double s = 0.0;
+    int q = 0;
+    for (; q + kGroup <= slices; q += kGroup) {
+        double v[kGroup];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) v[u] = partial[static_cast<int64_t>(q + u) * C + c];
+#pragma unroll
+        for (int u = 0; u < kGroup; ++u) s += v[u];
+    }
+    for (; q < slices; ++q) s += partial[static_cast<int64_t>(q) * C + c];
+    grid_out_f64(c, amp * s, epi, mu64, y, k, ind, y64, k64);
 }
 
 // ---------------------------------------------------------------------------- points
@@ -377,24 +438,55 @@ hipError_t launch_direct_grid_f32(const float* tx, const float* ty, const float*
 {
     const int nx = static_cast<int>(gn[0]), ny = static_cast<int>(gn[1]);
     const int64_t nq = gn[1] * gn[2];
-    const int nxt = (nx + kDgB - 1) / kDgB;
-    const int64_t blocks = static_cast<int64_t>(nxt) * ((nq + kDgB - 1) / kDgB);
+    // the widest tile that still gives two blocks per CU (512), else 1 x 1 cells per lane
+    auto blocks_of = [&](int side) { return ((nx + side - 1) / side) * ((nq + side - 1) / side); };
+    const int side = blocks_of(64) >= 512 ? 64 : blocks_of(32) >= 512 ? 32 : 16;
+    const int nxt = (nx + side - 1) / side;
+    const int64_t blocks = blocks_of(side);
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_direct_grid, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, tx, ty, tz, w,
-                       static_cast<int>(n), ldp, nx, ny, nq, nxt, amp, epi, y, k, ind);
+    const dim3 g(static_cast<unsigned>(blocks));
+    if (side == 64)
+        hipLaunchKernelGGL((k_direct_grid<4, 64>), g, dim3(256), 0, s, tx, ty, tz, w, static_cast<int>(n), ldp, nx, ny, nq,
+                           nxt, amp, epi, y, k, ind);
+    else if (side == 32)
+        hipLaunchKernelGGL((k_direct_grid<2, 128>), g, dim3(256), 0, s, tx, ty, tz, w, static_cast<int>(n), ldp, nx, ny, nq,
+                           nxt, amp, epi, y, k, ind);
+    else
+        hipLaunchKernelGGL((k_direct_grid<1, 256>), g, dim3(256), 0, s, tx, ty, tz, w, static_cast<int>(n), ldp, nx, ny, nq,
+                           nxt, amp, epi, y, k, ind);
     return hipGetLastError();
+}
+
+ModeSlices direct_grid_f64_slices(const int64_t* gn, int64_t n)
+{
+    // about 1024 blocks in all, at least 32 modes per slice, at most 64 slices
+    const int64_t blocks = (gn[0] * gn[1] * gn[2] + 255) / 256;
+    ModeSlices r{1, n};
+    if (blocks <= 0 || n <= 0 || blocks >= 512) return r;
+    int64_t sl = std::min<int64_t>(std::min<int64_t>((1024 + blocks - 1) / blocks, n / 32), 64);
+    if (sl <= 1) return r;
+    r.mslice = (n + sl - 1) / sl;
+    r.slices = static_cast<int>((n + r.mslice - 1) / r.mslice);
+    return r;
 }
 
 hipError_t launch_direct_grid_f64(const double* tx, const double* ty, const double* tz, const double* w, int64_t n,
                                   int64_t ldp, const int64_t* gn, double amp, const Epi& epi, double mu64, float* y,
-                                  float* k, uint8_t* ind, double* y64, double* k64, hipStream_t s)
+                                  float* k, uint8_t* ind, double* y64, double* k64, double* partial, hipStream_t s)
 {
     const int64_t C = gn[0] * gn[1] * gn[2];
     const int64_t blocks = (C + 255) / 256;
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_direct_grid_f64, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, tx, ty, tz, w,
-                       static_cast<int>(n), ldp, static_cast<int>(gn[0]), static_cast<int>(gn[1]), C, amp, epi, mu64,
-                       y, k, ind, y64, k64);
+    const ModeSlices ms = direct_grid_f64_slices(gn, n);
+    if (ms.slices > 1 && !partial) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_direct_grid_f64, dim3(static_cast<unsigned>(blocks), static_cast<unsigned>(ms.slices)),
+                       dim3(256), 0, s, tx, ty, tz, w, static_cast<int>(n), ldp, static_cast<int>(gn[0]),
+                       static_cast<int>(gn[1]), C, amp, epi, mu64, y, k, ind, y64, k64, static_cast<int>(ms.mslice),
+                       ms.slices > 1 ? partial : nullptr);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess || ms.slices == 1) return e;
+    hipLaunchKernelGGL(k_grid_reduce_f64, dim3(static_cast<unsigned>(blocks)), dim3(256), 0, s, partial, ms.slices, C,
+                       amp, epi, mu64, y, k, ind, y64, k64);
     return hipGetLastError();
 }
 

@@ -168,6 +168,7 @@ int64_t axis_table_blocks(const AxisTableArgs& a);  // 256-thread work blocks on
 struct GridWs {
     void* t[3] = {nullptr, nullptr, nullptr};
     void* tlo[3] = {nullptr, nullptr, nullptr};
+    void* partial = nullptr;  // DIRECT_F64 on small grids: per-slice sums
     size_t bytes = 0;
 };
 GridWs grid_ws(const grf_modes* m, const grf_grid* g, int method, void* base);
@@ -195,10 +196,19 @@ hipError_t launch_mode_params(const double* z, const double* phi, int dim, int64
 hipError_t launch_direct_grid_f32(const float* tx, const float* ty, const float* tz, const double* w, int64_t n,
                                   int64_t ldp, const int64_t* gn, float amp, const Epi& epi,
                                   float* y, float* k, uint8_t* ind, hipStream_t s);
+// Mode slices of the FP64 grid sum: grids too small to fill the device split the modes
+// into `slices` runs of `mslice` (slices = 1: no split).
+struct ModeSlices {
+    int slices;
+    int64_t mslice;
+};
+ModeSlices direct_grid_f64_slices(const int64_t* gn, int64_t n);
+// `partial` (workspace of direct_grid_f64_slices(gn, n).slices * cells doubles when that is
+// > 1, else unused) receives the slices' raw sums before they are added in slice order.
 hipError_t launch_direct_grid_f64(const double* tx, const double* ty, const double* tz, const double* w, int64_t n,
                                   int64_t ldp, const int64_t* gn, double amp, const Epi& epi,
                                   double mu64, float* y, float* k, uint8_t* ind, double* y64,
-                                  double* k64, hipStream_t s);
+                                  double* k64, double* partial, hipStream_t s);
 // `partial` (workspace, points_mode_slices(P, n) * P floats when that is > 1) receives the
 // per-slice sums when the modes are split across blocks.
 hipError_t launch_direct_points(const double* params, const double* w, int64_t n, int dim, const double* xyz,

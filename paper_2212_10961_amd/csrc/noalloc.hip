@@ -1,6 +1,6 @@
 // eval_field_grid for callers that cannot allocate device memory (code under graph capture,
-// tight serving loops): the per-axis tables live in a fixed array of the library's own
-// device memory instead of a caller workspace.
+// tight serving loops): the workspace (per-axis tables, partial sums) lives in a fixed array
+// of the library's own device memory instead of a caller's.
 #include <hip/hip_runtime.h>
 
 #include <mutex>
@@ -9,7 +9,7 @@
 
 namespace {
 
-// The tables of one grid evaluation.  Each device the library runs on holds its own copy
+// The workspace of one grid evaluation.  Each device the library runs on holds its own copy
 // until the process ends; every call on a device uses that copy.
 static __device__ __align__(256) unsigned char scratch[GRF_NOALLOC_SCRATCH_BYTES];
 

@@ -55,6 +55,26 @@ def test_grid2d_64_gauss_plain(orc, grf):
 
 # ------------------------------------------------------------------ ragged multi-tile grids
 
+def test_direct_f32_tile_shapes_match_batch(orc, grf):
+    """DIRECT_F32 takes 64-, 32- or 16-cell tiles by grid size (4 x 4, 2 x 2 or 1 x 1 cells per
+    lane; mode chunks of 64, 128 or 256); each cell is summed by one lane over the modes in
+    order, so every shape equals the batch's 64x64-tile result bit for bit, and the oracle on
+    sampled cells.  300 modes (rows padded to 320) leave the wider chunks a partial last one."""
+    sigma, ell = 1.1, (7.0, 5.0, 2.0)
+    (zo, po), m = modes_pair(orc, grf, 3, wl.GAUSSIAN, 300, 1401, sigma, ell)
+    shapes = [(256, 256, 32), (512, 512, 4), (70, 45, 9)]  # 64-, 32- and 16-cell tiles
+    items = [(m, s, torch.empty(int(np.prod(s)), device="cuda")) for s in shapes]
+    plan = grf.Plan("direct_f32", graph=False, autotune=False)
+    plan.run(items)
+    for (_, shape, yb), seed in zip(items, (1402, 1403, 1404)):
+        _say(f"case direct_f32 tile shape {shape}")
+        y = to_np(grf.field_grid(m, shape, method="direct_f32")["y"])
+        np.testing.assert_array_equal(y, to_np(yb), err_msg=f"{shape}")
+        cells = wl.sample_cells(int(np.prod(shape)), 3000, seed)
+        assert_field(y[cells], orc.field_cells(zo, po, sigma, ell, shape, cells), sigma, "direct_f32", f"{shape}")
+    plan.close()
+
+
 @pytest.mark.parametrize("meth", METHODS)
 def test_grid3d_ragged_all_methods(orc, grf, meth):
     shape, o, h, ell = (70, 45, 9), (0.5, -3.0, 2.0), (1.0, 1.5, 0.75), (6.0, 5.0, 2.0)
