@@ -1,11 +1,13 @@
 // Direct spectral sums (Sec. 4.1 eq. DiscreteFT, random-phase reading):
 //   Y_c = A sum_j cos(2 pi r_jc),   r_jc = frac-reduced phase in revolutions,
-// one hardware cosine per mode and cell, plus the fused epilogue
-// (K = exp(mu + Y), facies index = #{thresholds below Y}; Secs. 4.1 and 3.1).
+// plus the fused epilogue (K = exp(mu + Y), facies index = #{thresholds below Y}; Secs. 4.1
+// and 3.1).  At points: one hardware cosine per mode and point.  On grids the phase splits
+// into an x part and a (y,z) part, and each term is their angle sum, two FMAs on cosines
+// and sines formed once per grid row and mode.
 //
-// v_cos_f32 takes its argument in revolutions and reduces it exactly, so the
-// per-axis FP64-reduced fractions are summed in FP32 (values in [0, 3)) and fed
-// to it without a further reduction.
+// v_cos_f32 / v_sin_f32 take their argument in revolutions and reduce it exactly, so the
+// per-axis FP64-reduced fractions are summed in FP32 (values in [0, 3)) and fed to them
+// without a further reduction.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -26,31 +28,44 @@ __device__ __forceinline__ void store_out(int64_t c, float yv, const Epi& e, flo
 
 // ---------------------------------------------------------------------------- grid, FP32
 // Block tile: 16 RA x-cells by 16 RB (y,z) pairs; 256 threads; each lane owns RA x RB cells
-// (x = x0 + lx + 16 a, q = q0 + 4 RB w + (l / 16) + 4 b).  Mode chunks of 64 are staged in
-// LDS: sx[x][j] = Tx, sq[q][j] = Ty + Tz (psi folded in Ty), sw[j] = per-mode weight (1
-// without weights).  Rows of J modes are padded by 4 floats so the 16 distinct x rows of a
-// wave's 128-bit reads hit distinct banks.  Every cell is summed by one lane over the modes
-// in order, whatever the tile and chunk: neither changes a result bit.  Large grids take
-// 4 x 4 cells per lane (64 x 64 tiles, the batch's tile, chunks of 64 modes); small ones
-// 2 x 2 or 1 x 1 cells for more blocks, with chunks of 128 or 256 modes so that the fewer
-// terms per lane still cover each chunk's loads.
+// (x = x0 + lx + 16 a, q = q0 + 4 RB w + (l / 16) + 4 b).  With the x phase A = 2 pi Tx and
+// the (y,z) phase B = 2 pi (Ty + Tz) (psi folded in Ty), each term is the angle sum
+// cos(A + B) = cos A cos B - sin A sin B: two FMAs.  Per chunk of J modes the block stages in
+// LDS, for each of its x rows, cos A and sin A (hardware cosine and sine of the FP64-reduced
+// fraction), and for each (y,z) row w cos B and w sin B (B from the FP32 sum of the two
+// fractions, w the mode weight, 1 without weights): rows [J cosines | J sines | 4 floats of
+// pad], so the 16 distinct x rows of a wave's 128-bit reads hit distinct banks.  Every cell
+// is summed by one lane over the modes in order, whatever the tile and chunk: neither changes
+// a result bit.  Large grids take 4 x 8 cells per lane (64 x 128 tiles, 32-mode chunks); the
+// batch and mid-size grids 4 x 4 (64 x 64); small grids 2 x 2 or 1 x 1 cells for more blocks,
+// with chunks of 64 or 256 modes so that the fewer terms per lane still cover each chunk's loads.
 constexpr int kDgB = 64;
 static_assert(kDgB == kDirectTile, "tile side shared with the batch planner");
 
+__device__ __forceinline__ float sin_rev(float r) { return __builtin_amdgcn_sinf(r); }
+
+// LDS float4 of one tile: 16 (RA + RB) rows of (2 J + 4) floats.
+template <int RA, int RB, int J>
+struct DirectShape {
+    static constexpr int ROW = (2 * J + 4) / 4;  // float4 per padded row
+    static constexpr int X4 = 16 * RA * ROW, Q4 = 16 * RB * ROW;
+};
+
 // One (16 RA) x (16 RB) (x, (y,z)) tile, mode chunks of J; `sx`, `sq` are LDS arrays of
-// 16 RA (16 RB) * (J + 4) / 4 float4, `sw` of J / 4.  Whole block.
+// DirectShape<RA, RB, J>::X4 and ::Q4 float4.  Whole block.
 template <int RA, int RB, int J>
 __device__ __forceinline__ void direct_tile(const float* __restrict__ tx, const float* __restrict__ ty,
                                             const float* __restrict__ tz, const double* __restrict__ wt, int n,
                                             int64_t ldp, int nx, int ny, int64_t nq, int x0, int64_t q0, float amp,
                                             const Epi& epi, float* __restrict__ y, float* __restrict__ k,
-                                            uint8_t* __restrict__ ind, float4* sx, float4* sq, float4* sw)
+                                            uint8_t* __restrict__ ind, float4* sx, float4* sq)
 {
+    static_assert(J % 32 == 0, "row stride 2 J + 4 must be 4 (mod 64) floats");
     const int t = threadIdx.x;
     const int w = t >> 6, l = t & 63;
     const int lx = l & 15, lq = w * 4 * RB + (l >> 4);
-    constexpr int kRow = (J + 4) / 4;  // float4 per padded row
-    constexpr int kC4 = J / 4;         // float4 per chunk of one row
+    constexpr int kRow = DirectShape<RA, RB, J>::ROW;
+    constexpr int kG = J / 4;  // groups of 4 modes per chunk
 
     float acc[RA][RB];
 #pragma unroll
@@ -59,71 +74,91 @@ __device__ __forceinline__ void direct_tile(const float* __restrict__ tx, const 
         for (int b = 0; b < RB; ++b) acc[a][b] = 0.f;
 
     for (int j0 = 0; j0 < n; j0 += J) {
-        // (rows are ldp long, a multiple of 64: a chunk past it stages zeros it never sums)
+        // (rows are ldp long, a multiple of 64: a chunk of 128 past it stages zeros it never sums)
 #pragma unroll
         for (int it = 0; it < RA * J / 64; ++it) {
             const int e = it * 256 + t;
-            const int row = e / kC4, c4 = e % kC4;
+            const int row = e / kG, g = e % kG;
             const int xg = min(x0 + row, nx - 1);
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (J == 64 || j0 + 4 * c4 < ldp)
-                v = *reinterpret_cast<const float4*>(tx + static_cast<int64_t>(xg) * ldp + j0 + 4 * c4);
-            sx[row * kRow + c4] = v;
+            float4 c = make_float4(0.f, 0.f, 0.f, 0.f), sn = c;
+            if (J <= 64 || j0 + 4 * g < ldp) {
+                const float4 f = *reinterpret_cast<const float4*>(tx + static_cast<int64_t>(xg) * ldp + j0 + 4 * g);
+                c = make_float4(cos_rev(f.x), cos_rev(f.y), cos_rev(f.z), cos_rev(f.w));
+                sn = make_float4(sin_rev(f.x), sin_rev(f.y), sin_rev(f.z), sin_rev(f.w));
+            }
+            sx[row * kRow + g] = c;
+            sx[row * kRow + kG + g] = sn;
         }
 #pragma unroll
         for (int it = 0; it < RB * J / 64; ++it) {
             const int e = it * 256 + t;
-            const int row = e / kC4, c4 = e % kC4;
+            const int row = e / kG, g = e % kG;
             const int64_t q = min(q0 + row, nq - 1);
             const int64_t yy = q % ny, zz = q / ny;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (J == 64 || j0 + 4 * c4 < ldp) {
-                const float4 a = *reinterpret_cast<const float4*>(ty + yy * ldp + j0 + 4 * c4);
-                const float4 b = *reinterpret_cast<const float4*>(tz + zz * ldp + j0 + 4 * c4);
-                v = make_float4(a.x + b.x, a.y + b.y, a.z + b.z, a.w + b.w);
+            float4 c = make_float4(0.f, 0.f, 0.f, 0.f), sn = c;
+            if (J <= 64 || j0 + 4 * g < ldp) {
+                const float4 fa = *reinterpret_cast<const float4*>(ty + yy * ldp + j0 + 4 * g);
+                const float4 fb = *reinterpret_cast<const float4*>(tz + zz * ldp + j0 + 4 * g);
+                const float4 f = make_float4(fa.x + fb.x, fa.y + fb.y, fa.z + fb.z, fa.w + fb.w);
+                c = make_float4(cos_rev(f.x), cos_rev(f.y), cos_rev(f.z), cos_rev(f.w));
+                sn = make_float4(sin_rev(f.x), sin_rev(f.y), sin_rev(f.z), sin_rev(f.w));
+                if (wt) {
+                    // modes past n carry no weight (their terms are not summed)
+                    const int j = j0 + 4 * g;
+                    const float4 wv = make_float4(j < n ? static_cast<float>(wt[j]) : 0.f,
+                                                  j + 1 < n ? static_cast<float>(wt[j + 1]) : 0.f,
+                                                  j + 2 < n ? static_cast<float>(wt[j + 2]) : 0.f,
+                                                  j + 3 < n ? static_cast<float>(wt[j + 3]) : 0.f);
+                    c = make_float4(wv.x * c.x, wv.y * c.y, wv.z * c.z, wv.w * c.w);
+                    sn = make_float4(wv.x * sn.x, wv.y * sn.y, wv.z * sn.z, wv.w * sn.w);
+                }
             }
-            sq[row * kRow + c4] = v;
-        }
-        if (t < J / 4) {
-            float4 wv = make_float4(1.f, 1.f, 1.f, 1.f);
-            if (wt) {
-                const int j = j0 + 4 * t;  // modes past n carry no weight (their terms are not summed)
-                wv = make_float4(j < n ? static_cast<float>(wt[j]) : 0.f, j + 1 < n ? static_cast<float>(wt[j + 1]) : 0.f,
-                                 j + 2 < n ? static_cast<float>(wt[j + 2]) : 0.f,
-                                 j + 3 < n ? static_cast<float>(wt[j + 3]) : 0.f);
-            }
-            sw[t] = wv;
+            sq[row * kRow + g] = c;
+            sq[row * kRow + kG + g] = sn;
         }
         __syncthreads();
         const int jn = min(J, n - j0);
         const int j4 = jn >> 2;
         for (int m = 0; m < j4; ++m) {
-            float4 vx[RA], vq[RB];
+            float4 xc[RA], xs[RA], qc[RB], qs[RB];
 #pragma unroll
-            for (int r = 0; r < RA; ++r) vx[r] = sx[(lx + 16 * r) * kRow + m];
+            for (int r = 0; r < RA; ++r) {
+                xc[r] = sx[(lx + 16 * r) * kRow + m];
+                xs[r] = sx[(lx + 16 * r) * kRow + kG + m];
+            }
 #pragma unroll
-            for (int r = 0; r < RB; ++r) vq[r] = sq[(lq + 4 * r) * kRow + m];
-            const float4 wv = sw[m];
+            for (int r = 0; r < RB; ++r) {
+                qc[r] = sq[(lq + 4 * r) * kRow + m];
+                qs[r] = sq[(lq + 4 * r) * kRow + kG + m];
+            }
 #pragma unroll
             for (int a = 0; a < RA; ++a)
 #pragma unroll
                 for (int b = 0; b < RB; ++b) {
-                    acc[a][b] = fmaf(wv.x, cos_rev(vx[a].x + vq[b].x), acc[a][b]);
-                    acc[a][b] = fmaf(wv.y, cos_rev(vx[a].y + vq[b].y), acc[a][b]);
-                    acc[a][b] = fmaf(wv.z, cos_rev(vx[a].z + vq[b].z), acc[a][b]);
-                    acc[a][b] = fmaf(wv.w, cos_rev(vx[a].w + vq[b].w), acc[a][b]);
+                    float v = acc[a][b];
+                    v = fmaf(xc[a].x, qc[b].x, v);
+                    v = fmaf(-xs[a].x, qs[b].x, v);
+                    v = fmaf(xc[a].y, qc[b].y, v);
+                    v = fmaf(-xs[a].y, qs[b].y, v);
+                    v = fmaf(xc[a].z, qc[b].z, v);
+                    v = fmaf(-xs[a].z, qs[b].z, v);
+                    v = fmaf(xc[a].w, qc[b].w, v);
+                    v = fmaf(-xs[a].w, qs[b].w, v);
+                    acc[a][b] = v;
                 }
         }
         const float* sxf = reinterpret_cast<const float*>(sx);
         const float* sqf = reinterpret_cast<const float*>(sq);
-        const float* swf = reinterpret_cast<const float*>(sw);
         for (int m = j4 * 4; m < jn; ++m) {
 #pragma unroll
             for (int a = 0; a < RA; ++a)
 #pragma unroll
-                for (int b = 0; b < RB; ++b)
-                    acc[a][b] = fmaf(swf[m], cos_rev(sxf[(lx + 16 * a) * kRow * 4 + m] + sqf[(lq + 4 * b) * kRow * 4 + m]),
-                                     acc[a][b]);
+                for (int b = 0; b < RB; ++b) {
+                    const float* rx = sxf + (lx + 16 * a) * kRow * 4;
+                    const float* rq = sqf + (lq + 4 * b) * kRow * 4;
+                    acc[a][b] = fmaf(rx[m], rq[m], acc[a][b]);
+                    acc[a][b] = fmaf(-rx[J + m], rq[J + m], acc[a][b]);
+                }
         }
         __syncthreads();
     }
@@ -141,19 +176,19 @@ __device__ __forceinline__ void direct_tile(const float* __restrict__ tx, const 
     }
 }
 
-template <int R, int J>
+template <int RA, int RB, int J>
 __global__ __launch_bounds__(256, 2) void k_direct_grid(const float* __restrict__ tx, const float* __restrict__ ty,
                                                        const float* __restrict__ tz, const double* __restrict__ wt,
                                                        int n, int64_t ldp, int nx, int ny, int64_t nq, int nxt,
                                                        float amp, Epi epi, float* __restrict__ y,
                                                        float* __restrict__ k, uint8_t* __restrict__ ind)
 {
-    __shared__ float4 sx[16 * R * ((J + 4) / 4)];
-    __shared__ float4 sq[16 * R * ((J + 4) / 4)];
-    __shared__ float4 sw[J / 4];
+    using S = DirectShape<RA, RB, J>;
+    __shared__ float4 sx[S::X4];
+    __shared__ float4 sq[S::Q4];
     const int64_t bid = blockIdx.x;
-    direct_tile<R, R, J>(tx, ty, tz, wt, n, ldp, nx, ny, nq, static_cast<int>(bid % nxt) * 16 * R, (bid / nxt) * 16 * R,
-                      amp, epi, y, k, ind, sx, sq, sw);
+    direct_tile<RA, RB, J>(tx, ty, tz, wt, n, ldp, nx, ny, nq, static_cast<int>(bid % nxt) * 16 * RA,
+                           (bid / nxt) * 16 * RB, amp, epi, y, k, ind, sx, sq);
 }
 
 // Persistent batched form: blocks pull (instance, tile) work items from one atomic counter
@@ -161,9 +196,9 @@ __global__ __launch_bounds__(256, 2) void k_direct_grid(const float* __restrict_
 __global__ __launch_bounds__(256, 2) void k_direct_batch(const DirectBatchItem* __restrict__ items, int n_inst,
                                                         int64_t total, unsigned long long* counter)
 {
-    __shared__ float4 sx[kDgB * 17];
-    __shared__ float4 sq[kDgB * 17];
-    __shared__ float4 sw[16];
+    using S = DirectShape<4, 4, 32>;
+    __shared__ float4 sx[S::X4];
+    __shared__ float4 sq[S::Q4];
     __shared__ unsigned long long s_item;
     for (;;) {
         if (threadIdx.x == 0) s_item = atomicAdd(counter, 1ull);
@@ -179,8 +214,8 @@ __global__ __launch_bounds__(256, 2) void k_direct_batch(const DirectBatchItem* 
         }
         const DirectBatchItem& b = items[lo];
         const int64_t local = it - b.item0;
-        direct_tile<4, 4, 64>(b.tx, b.ty, b.tz, b.w, b.n, b.ldp, b.nx, b.ny, b.nq, static_cast<int>(local % b.nxt) * kDgB,
-                          (local / b.nxt) * kDgB, b.amp, b.epi, b.y, b.k, b.ind, sx, sq, sw);
+        direct_tile<4, 4, 32>(b.tx, b.ty, b.tz, b.w, b.n, b.ldp, b.nx, b.ny, b.nq, static_cast<int>(local % b.nxt) * kDgB,
+                              (local / b.nxt) * kDgB, b.amp, b.epi, b.y, b.k, b.ind, sx, sq);
     }
 }
 
@@ -439,21 +474,25 @@ hipError_t launch_direct_grid_f32(const float* tx, const float* ty, const float*
     const int nx = static_cast<int>(gn[0]), ny = static_cast<int>(gn[1]);
     const int64_t nq = gn[1] * gn[2];
     // the widest tile that still gives two blocks per CU (512), else 1 x 1 cells per lane
-    auto blocks_of = [&](int side) { return ((nx + side - 1) / side) * ((nq + side - 1) / side); };
-    const int side = blocks_of(64) >= 512 ? 64 : blocks_of(32) >= 512 ? 32 : 16;
-    const int nxt = (nx + side - 1) / side;
-    const int64_t blocks = blocks_of(side);
+    auto blocks_of = [&](int sx_, int sq_) -> int64_t {
+        return static_cast<int64_t>((nx + sx_ - 1) / sx_) * ((nq + sq_ - 1) / sq_);
+    };
+    int v = 3;
+    if (blocks_of(64, 128) >= 512) v = 0;
+    else if (blocks_of(64, 64) >= 512) v = 1;
+    else if (blocks_of(32, 32) >= 512) v = 2;
+    static constexpr int kSx[4] = {64, 64, 32, 16}, kSq[4] = {128, 64, 32, 16};
+    const int nxt = (nx + kSx[v] - 1) / kSx[v];
+    const int64_t blocks = blocks_of(kSx[v], kSq[v]);
     if (blocks > 0x7fffffff) return hipErrorInvalidValue;
     const dim3 g(static_cast<unsigned>(blocks));
-    if (side == 64)
-        hipLaunchKernelGGL((k_direct_grid<4, 64>), g, dim3(256), 0, s, tx, ty, tz, w, static_cast<int>(n), ldp, nx, ny, nq,
-                           nxt, amp, epi, y, k, ind);
-    else if (side == 32)
-        hipLaunchKernelGGL((k_direct_grid<2, 128>), g, dim3(256), 0, s, tx, ty, tz, w, static_cast<int>(n), ldp, nx, ny, nq,
-                           nxt, amp, epi, y, k, ind);
-    else
-        hipLaunchKernelGGL((k_direct_grid<1, 256>), g, dim3(256), 0, s, tx, ty, tz, w, static_cast<int>(n), ldp, nx, ny, nq,
-                           nxt, amp, epi, y, k, ind);
+    const int nn = static_cast<int>(n);
+    switch (v) {
+    case 0: hipLaunchKernelGGL((k_direct_grid<4, 8, 32>), g, dim3(256), 0, s, tx, ty, tz, w, nn, ldp, nx, ny, nq, nxt, amp, epi, y, k, ind); break;
+    case 1: hipLaunchKernelGGL((k_direct_grid<4, 4, 32>), g, dim3(256), 0, s, tx, ty, tz, w, nn, ldp, nx, ny, nq, nxt, amp, epi, y, k, ind); break;
+    case 2: hipLaunchKernelGGL((k_direct_grid<2, 2, 64>), g, dim3(256), 0, s, tx, ty, tz, w, nn, ldp, nx, ny, nq, nxt, amp, epi, y, k, ind); break;
+    default: hipLaunchKernelGGL((k_direct_grid<1, 1, 256>), g, dim3(256), 0, s, tx, ty, tz, w, nn, ldp, nx, ny, nq, nxt, amp, epi, y, k, ind); break;
+    }
     return hipGetLastError();
 }
 

@@ -3,8 +3,10 @@
 Tolerances are fixed before any run, from the arithmetic of each path:
 
 - DIRECT_F32: per-axis fractions rounded to FP32 (<= 2^-25 rev each), their FP32 sum
-  (< 3 rev, <= 2^-23 rev), v_cos_f32 (measured max |err| 1.24e-7) and FP32 accumulation
-  of N unit terms.  Expected rel-RMS ~1e-6, max |dY| a few 1e-6 sigma.
+  (< 3 rev, <= 2^-23 rev), v_cos_f32 / v_sin_f32 (measured max |err| 1.24e-7) and FP32
+  accumulation of N unit terms (on grids each term is cos A cos B - sin A sin B of the x and
+  (y,z) parts of the phase: one more rounding per product).  Expected rel-RMS ~1e-6, max
+  |dY| a few 1e-6 sigma.
   Bar: rel-RMS <= 2e-5, max |dY| <= 1e-4 sigma (also the indicator band).
 - DIRECT_F64: FP64 throughout; through the FP32 outputs only the final rounding
   remains (|Y| <~ 6 sigma -> <= 4e-7 sigma).  Bar: rel-RMS <= 2e-7, max |dY| <= 1e-6 sigma
