@@ -30,7 +30,8 @@ METRIC = "mode·cell evals/s: FP32 direct sum vs MFMA separable at rel-RMS≤1e-
 HBM_PEAK = 8.0e12            # B/s
 MFMA_F16_PEAK = 2.5e15       # dense fp16/bf16 flop/s
 # ALU roofline of the direct sums: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 lane-ops/s;
-# v_cos_f32 issues at half rate on gfx950, and every mode-cell needs one cosine.
+# v_cos_f32 issues at half rate on gfx950 and every mode-point needs one cosine; on grids every
+# mode-cell is two full-rate FMAs (the angle sum of the x and (y,z) phases): the same peak.
 COS_PEAK = 256 * 4 * 16 * 2.4e9 / 2.0
 
 
@@ -335,7 +336,7 @@ def extras(args, grf, wl, torch, np, dev):
 
 
 def cos_probe(torch, dev):
-    """Measured issue rate of the hardware cosine in a register loop (alone, and in the direct
+    """Measured issue rate of the hardware cosine in a register loop (alone, and in the point
     sum's per-term mix), beside the nominal half-rate peak used for the direct-sum rooflines."""
     import ctypes
     lib = ctypes.CDLL(str(ROOT / "paper_2212_10961_amd" / "libgrf_probe.so"))
