@@ -36,6 +36,20 @@ def _check(grf, m, x, ref, sigma, form, label, thresholds=None):
 
 
 @pytest.mark.parametrize("form", FORMS)
+@pytest.mark.parametrize("P", [5, 300])
+def test_points_many_mode_slices(orc, grf, form, P):
+    # Few points and 1,500 modes: the modes split into 23 slices of 64 whose partial sums are
+    # added in slice order, one group of 16 loads in flight and then the remaining 7.
+    c = wl.WORKLOADS["points_2m_gauss"]
+    sigma = math.sqrt(c["sigma2"])
+    print(f"case points {form} P={P} N=1500", flush=True)
+    (zo, po), m = modes_pair(orc, grf, 3, c["cov"], 1500, 1421, sigma, c["ell"])
+    x = wl.points_uniform(P, c["box"], 1422 + P)
+    ref = orc.field_points(zo, po, sigma, c["ell"], x)
+    _check(grf, m, x, ref, sigma, form, f"P={P} N=1500", thresholds=[-0.4, c["threshold"]])
+
+
+@pytest.mark.parametrize("form", FORMS)
 @pytest.mark.parametrize("P", [1, 7, 1025, 3001, 70001])
 def test_points_forms_ragged(orc, grf, form, P):
     c = wl.WORKLOADS["points_2m_gauss"]
