@@ -82,29 +82,33 @@ def test_conditioned_points_interpolate_rotated(orc, grf):
 # The grid correction has a row form (maps that leave the second and third lag components free
 # of x: unrotated, or rotated about x alone; each lane takes 8 cells of a row) and a general form
 # (rotations that mix x into them).  Rows of 13 and 5 cells leave lanes with fewer than 8 cells.
-@pytest.mark.parametrize("dim,shape,angles,cov,nu,nugget", [
-    (3, (37, 21, 5), (0.4, -0.3, 0.5), wl.EXPONENTIAL, 0.5, 0.0),  # general form
-    (3, (37, 21, 5), (0.0, 0.0, 0.6), wl.MATERN, 1.5, 0.0),        # row form, u1 and u2 mix y and z
-    (2, (13, 40), (0.0,), wl.GAUSSIAN, 0.5, 1e-5),                 # row form, ragged rows
-    (2, (5, 60), (0.7,), wl.MATERN, 2.5, 0.0),                     # general form, 5-cell rows
-    (2, (5, 60), (0.0,), wl.EXPONENTIAL, 0.5, 0.0),                # row form, 5-cell rows
+@pytest.mark.parametrize("dim,shape,angles,cov,nu,nugget,geo", [
+    (3, (37, 21, 5), (0.4, -0.3, 0.5), wl.EXPONENTIAL, 0.5, 0.0, None),  # general form
+    (3, (37, 21, 5), (0.0, 0.0, 0.6), wl.MATERN, 1.5, 0.0, None),        # row form, u1 and u2 mix y and z
+    (2, (13, 40), (0.0,), wl.GAUSSIAN, 0.5, 1e-5, None),                 # row form, ragged rows
+    (2, (5, 60), (0.7,), wl.MATERN, 2.5, 0.0, None),                     # general form, 5-cell rows
+    (2, (5, 60), (0.0,), wl.EXPONENTIAL, 0.5, 0.0, None),                # row form, 5-cell rows
+    # row form on a grid with an offset origin and uneven spacing
+    (3, (29, 17, 6), (0.0, 0.0, 0.3), wl.GAUSSIAN, 0.5, 1e-5, ((-3.0, 2.0, 0.5), (0.7, 1.3, 0.5))),
 ])
-def test_conditioned_grid_forms(orc, grf, dim, shape, angles, cov, nu, nugget):
+def test_conditioned_grid_forms(orc, grf, dim, shape, angles, cov, nu, nugget, geo):
     ell, sigma = np.array((9.0, 5.0, 2.0)[:dim]), 1.1
-    _say(f"case krige grid form dim={dim} shape={shape} angles={angles} cov={cov} nu={nu}")
+    origin, h = geo if geo else (None, None)
+    _say(f"case krige grid form dim={dim} shape={shape} angles={angles} cov={cov} nu={nu} geo={geo}")
     (zo, po), m = modes_pair(orc, grf, dim, wl.EXPONENTIAL, 200, 971, sigma, ell)
     R = orc.rotation_matrix(dim, angles)
     m.rot = R
-    xo = _separated(30, tuple(float(n) for n in shape), 4.0, 972)
+    x = orc.grid_centres(shape, origin, h)
+    lo, hi = x.min(axis=0), x.max(axis=0)
+    xo = lo + _separated(30, tuple(float(v) for v in hi - lo), 4.0, 972)
     d = np.random.default_rng(973).normal(size=xo.shape[0]) * sigma
-    x = orc.grid_centres(shape)
     M = R @ np.diag(1.0 / ell)
     yu = orc.field_points_mat(zo, po, sigma, M, x)
     yuo = orc.field_points_mat(zo, po, sigma, M, xo)
     a = orc.krige_weights(cov, sigma, ell, xo, d - yuo, nugget=nugget, nu=nu, rot=R)
     want = yu + orc.krige_correction(cov, sigma, ell, xo, a, x, nu=nu, rot=R)
     y, _, info = grf.condition_grid(m, shape, torch.from_numpy(xo).cuda(), torch.from_numpy(d).float().cuda(), cov,
-                                    nu=nu, nugget=nugget)
+                                    nu=nu, nugget=nugget, origin=origin, h=h)
     assert int(to_np(info)[0]) == 0
     err = np.max(np.abs(to_np(y).ravel() - want))
     _say(f"  {xo.shape[0]} observations, max |Y_c - ref| / sigma = {err / sigma:.3e}")
