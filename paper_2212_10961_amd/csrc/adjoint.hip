@@ -176,13 +176,19 @@ __global__ __launch_bounds__(256) void k_bwd_final(const float* __restrict__ sca
 }
 
 // Dense adjoint on a structured grid from the per-axis revolution tables (FP64-reduced,
-// psi folded into the y table): theta_jc / 2 pi = Tx[i][j] + Ty[y][j] + Tz[z][j].
-// One lane per mode; the block walks a chunk of 16 x 16 (x, (y,z)) cell tiles.  Each lane
-// keeps its mode's 16 + 16 table entries of the tile in registers, and the per-cell weights
-// (g, g x) are shared through LDS (broadcast reads).  Along one tile row y and z are fixed,
-// so the row sums r = sum_x g sin and r_x = sum_x g x sin give s += r, u_x += r_x,
-// u_y += y r, u_z += z r: one sine and two FMAs per cell.  Cells outside the grid get g = 0.
-constexpr int kBT = 16;
+// psi folded into the y table): theta_jc = A_jx + B_jq with A = 2 pi Tx[x][j] and
+// B = 2 pi (Ty[y][j] + Tz[z][j]).  One lane per mode; the block walks a chunk of 32 x 32
+// (x, (y,z)) cell tiles.  Per tile each lane forms the cosines and sines of its mode's 32 x
+// and 32 (y,z) phases; the per-cell weights g (0 outside the grid) and the tile's coordinates
+// are shared through LDS (broadcast reads).  Along tile row q the angle sum gives
+//   sum_x g sin(A + B) = cos B S1 + sin B S2,   sum_x g x sin(A + B) = cos B S3 + sin B S4,
+//   sum_x g cos(A + B) = cos B S2 - sin B S1,
+// with S1 = sum_x g sin A, S2 = sum_x g cos A and S3, S4 their x-weighted twins: four FMAs
+// per cell, then s += r, u_x += r_x, u_y += y r, u_z += z r per row.
+constexpr int kBT = 32;
+
+__device__ __forceinline__ float cos_rev_b(float r) { return __builtin_amdgcn_cosf(r); }
+__device__ __forceinline__ float sin_rev_b(float r) { return __builtin_amdgcn_sinf(r); }
 
 template <bool WANT_C>
 __global__ __launch_bounds__(256) void k_bwd_grid_tab(const float* __restrict__ tx, const float* __restrict__ ty,
@@ -190,8 +196,10 @@ __global__ __launch_bounds__(256) void k_bwd_grid_tab(const float* __restrict__ 
                                                      int nxt, int64_t ntiles, int64_t tiles_per_chunk,
                                                      const float* __restrict__ gy, float* __restrict__ partial)
 {
-    __shared__ float2 sw[kBT * kBT];
-    __shared__ float2 syz[kBT];
+    constexpr int kA4 = kBT / 4;            // float4 of g per tile row
+    __shared__ float4 sg[kBT * kA4];        // g of cell (row b, column a) at [kA4 b + a / 4].(a % 4)
+    __shared__ float sxc[kBT];              // x of the tile's columns
+    __shared__ float2 syz[kBT];             // (y, z) of the tile's rows
     const int t = threadIdx.x;
     const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + t;
     const int64_t jc = min(j, ldp - 1);
@@ -201,47 +209,61 @@ __global__ __launch_bounds__(256) void k_bwd_grid_tab(const float* __restrict__ 
     for (int64_t tile = t0; tile < t1; ++tile) {
         const int64_t x0 = (tile % nxt) * kBT;
         const int64_t q0 = (tile / nxt) * kBT;
-        float vx[kBT], vq[kBT];
+        float cA[kBT], sA[kBT], cB[kBT], sB[kBT];
 #pragma unroll
         for (int r = 0; r < kBT; ++r) {
-            vx[r] = tx[min(x0 + r, geo.nx - 1) * ldp + jc];
+            const float fx = tx[min(x0 + r, geo.nx - 1) * ldp + jc];
             const int64_t q = min(q0 + r, nq - 1);
-            vq[r] = ty[(q % geo.ny) * ldp + jc] + tz[(q / geo.ny) * ldp + jc];
+            const float fq = ty[(q % geo.ny) * ldp + jc] + tz[(q / geo.ny) * ldp + jc];
+            cA[r] = cos_rev_b(fx);
+            sA[r] = sin_rev_b(fx);
+            cB[r] = cos_rev_b(fq);
+            sB[r] = sin_rev_b(fq);
         }
         __syncthreads();  // previous tile's weights are no longer read
-        {
-            const int64_t xi = x0 + (t % kBT), q = q0 + (t / kBT);
-            float2 w = make_float2(0.f, 0.f);
-            if (xi < geo.nx && q < nq) {
-                const float g = gy[q * geo.nx + xi];
-                const float x = static_cast<float>(geo.ox + (static_cast<double>(xi) + 0.5) * geo.hx);
-                w = make_float2(g, g * x);
-            }
-            sw[t] = w;
-            if (t < kBT) {
-                const int64_t qr = min(q0 + t, nq - 1);
-                syz[t] = make_float2(static_cast<float>(geo.oy + (static_cast<double>(qr % geo.ny) + 0.5) * geo.hy),
-                                     static_cast<float>(geo.oz + (static_cast<double>(qr / geo.ny) + 0.5) * geo.hz));
-            }
+#pragma unroll
+        for (int e = t; e < kBT * kBT; e += 256) {
+            const int64_t xi = x0 + (e % kBT), q = q0 + (e / kBT);
+            reinterpret_cast<float*>(sg)[e] = (xi < geo.nx && q < nq) ? gy[q * geo.nx + xi] : 0.f;
+        }
+        if (t < kBT) {
+            sxc[t] = static_cast<float>(geo.ox + (static_cast<double>(x0 + t) + 0.5) * geo.hx);
+            const int64_t qr = min(q0 + t, nq - 1);
+            syz[t] = make_float2(static_cast<float>(geo.oy + (static_cast<double>(qr % geo.ny) + 0.5) * geo.hy),
+                                 static_cast<float>(geo.oz + (static_cast<double>(qr / geo.ny) + 0.5) * geo.hz));
         }
         __syncthreads();
-#pragma unroll 4
-        for (int b = 0; b < kBT; ++b) {
-            float rs = 0.f, rx = 0.f;
+        float xs[kBT], xc[kBT];
 #pragma unroll
-            for (int a = 0; a < kBT; ++a) {
-                const float2 w = sw[b * kBT + a];
-                const float p = vx[a] + vq[b];
-                const float sn = __builtin_amdgcn_sinf(p);
-                rs = fmaf(w.x, sn, rs);
-                rx = fmaf(w.y, sn, rx);
-                if (WANT_C) cc = fmaf(w.x, __builtin_amdgcn_cosf(p), cc);
+        for (int a = 0; a < kBT; ++a) {
+            const float x = sxc[a];
+            xs[a] = x * sA[a];
+            xc[a] = x * cA[a];
+        }
+#pragma unroll 2
+        for (int b = 0; b < kBT; ++b) {
+            float s1 = 0.f, s2 = 0.f, s3 = 0.f, s4 = 0.f;
+#pragma unroll
+            for (int a4 = 0; a4 < kA4; ++a4) {
+                const float4 g = sg[b * kA4 + a4];
+                const float gv[4] = {g.x, g.y, g.z, g.w};
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int a = 4 * a4 + u;
+                    s1 = fmaf(gv[u], sA[a], s1);
+                    s2 = fmaf(gv[u], cA[a], s2);
+                    s3 = fmaf(gv[u], xs[a], s3);
+                    s4 = fmaf(gv[u], xc[a], s4);
+                }
             }
+            const float rs = fmaf(cB[b], s1, sB[b] * s2);
+            const float rx = fmaf(cB[b], s3, sB[b] * s4);
             const float2 yz = syz[b];
             s += rs;
             ux += rx;
             uy = fmaf(yz.x, rs, uy);
             uz = fmaf(yz.y, rs, uz);
+            if (WANT_C) cc += fmaf(cB[b], s2, -(sB[b] * s1));
         }
     }
     if (j < ldp) {
