@@ -47,16 +47,15 @@ __device__ __forceinline__ uint32_t ez_prod(uint32_t ew, uint32_t zw)
 constexpr int kJC = 32;         // modes per LDS stage (64 reals of K)
 constexpr int kRowW = kJC + 4;  // padded LDS row, in 32-bit words
 
+// (re, im) rounded to nearest-even fp16 / bf16 and packed (re low): one v_cvt_pk_f16_f32 /
+// v_cvt_pk_bf16_f32 on gfx950.
 __device__ __forceinline__ uint32_t pack_pair(float re, float im, bool bf)
 {
-    if (bf) {
-        const __bf16 r = static_cast<__bf16>(re), i = static_cast<__bf16>(im);
-        return static_cast<uint32_t>(__builtin_bit_cast(uint16_t, r)) |
-               (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, i)) << 16);
-    }
-    const _Float16 r = static_cast<_Float16>(re), i = static_cast<_Float16>(im);
-    return static_cast<uint32_t>(__builtin_bit_cast(uint16_t, r)) |
-           (static_cast<uint32_t>(__builtin_bit_cast(uint16_t, i)) << 16);
+    typedef float f2 __attribute__((ext_vector_type(2)));
+    typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+    const f2 v = {re, im};
+    if (bf) return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, b2));
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(v, h2));
 }
 
 __device__ __forceinline__ float lo16f(uint32_t v, bool bf)
