@@ -357,9 +357,9 @@ int field_backward_grid(const grf_modes* modes, const grf_grid* grid, const floa
  *   GRF_SEP_BF16_X3  separable form: the per-mode sums factor over the axes like the forward
  *                    sum (eq. DiscreteFT with k.x split per axis), S_j = sum_{y,z}
  *                    [sum_x g Ex] Ey Ez, the bracket a bf16 hi+lo matrix product (relative
- *                    error ~2^-16) reduced with Ey Ez in FP32; needs n[0] <= 128
- *                    (GRF_EUNSUPPORTED otherwise);
- *   GRF_AUTO         the separable form when it applies (what field_backward_grid does).
+ *                    error ~2^-16) reduced with Ey Ez in FP32; x runs in chunks of 128
+ *                    cells, one after another;
+ *   GRF_AUTO         the separable form (what field_backward_grid does).
  * The workspace of field_backward_grid_ws_size fits every method.
  */
 int field_backward_grid_method(const grf_modes* modes, const grf_grid* grid, int method, const float* grad_y,

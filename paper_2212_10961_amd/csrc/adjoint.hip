@@ -290,7 +290,7 @@ void launch_bwd_main(const BwdArgs& a, int64_t chunk, const Geo& geo, bool want_
 }
 
 
-// ---- separable dense adjoint (grid path, x extent <= kBwdSepK) ---------------------------
+// ---- separable dense adjoint (grid path; x in chunks of kBwdSepK cells) -----------------
 //
 // On a structured grid the per-mode sums factor like the forward sum: with rows q = (y, z)
 // and U_j[q] = sum_x g[q][x] Ex[x][j] (and its x-weighted twin U^x),
@@ -311,34 +311,35 @@ __device__ __forceinline__ void split_bf16(float v, uint16_t* hi, uint16_t* lo, 
     lo[e] = __builtin_bit_cast(uint16_t, l);
 }
 
-// dL/dY rows as bf16 hi + lo: row r = z nyp + y (y padded to nyp, a multiple of 32, so that a
-// 32-row tile is one z-slice), x padded to kBwdSepK; padding is zero.  Stored fragment-major,
-// [r / 32][x / 16][r % 32][x % 16], so that one k-step of a 32-row tile (the A fragment of
-// every lane of a wave) is one contiguous KiB.
-__global__ __launch_bounds__(256) void k_bwd_sep_ga(const float* __restrict__ g, int64_t nx, int64_t ny, int64_t nyp,
-                                                   int64_t qp, uint16_t* __restrict__ hi, uint16_t* __restrict__ lo)
+// dL/dY rows as bf16 hi + lo for the x chunk [x0, x0 + kBwdSepK): row r = z nyp + y (y
+// padded to nyp, a multiple of 32, so that a 32-row tile is one z-slice), cells past nx and
+// padded rows zero.  Stored fragment-major, [r / 32][x / 16][r % 32][x % 16], so that one
+// k-step of a 32-row tile (the A fragment of every lane of a wave) is one contiguous KiB.
+__global__ __launch_bounds__(256) void k_bwd_sep_ga(const float* __restrict__ g, int64_t nx, int64_t x0, int64_t ny,
+                                                   int64_t nyp, int64_t qp, uint16_t* __restrict__ hi,
+                                                   uint16_t* __restrict__ lo)
 {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= qp * kBwdSepK) return;
     const int64_t r = e / kBwdSepK, x = e % kBwdSepK;
     const int64_t z = r / nyp, y = r % nyp;
     const int64_t d = (((r >> 5) * (kBwdSepK / 16) + (x >> 4)) * 32 + (r & 31)) * 16 + (x & 15);
-    split_bf16((y < ny && x < nx) ? g[(z * ny + y) * nx + x] : 0.f, hi, lo, d);
+    split_bf16((y < ny && x0 + x < nx) ? g[(z * ny + y) * nx + x0 + x] : 0.f, hi, lo, d);
 }
 
-// x operand rows 4 j + (Re Ex, Im Ex, x Re Ex, x Im Ex) at x = ox + (i + 1/2) hx, phase
-// frac(a_j x) formed and reduced in FP64, then split into bf16 hi + lo; zero for j >= n and
-// i >= nx.
+// x operand rows 4 j + (Re Ex, Im Ex, x Re Ex, x Im Ex) of the x chunk at x0, at x = ox +
+// (x0 + i + 1/2) hx, phase frac(a_j x) formed and reduced in FP64, then split into bf16 hi +
+// lo; zero for j >= n and x0 + i >= nx.
 __global__ __launch_bounds__(256) void k_bwd_sep_ex(const double* __restrict__ zx, double fs, double ox, double hx,
-                                                   int64_t n, int64_t ldp, int64_t nx, uint16_t* __restrict__ hi,
-                                                   uint16_t* __restrict__ lo)
+                                                   int64_t n, int64_t ldp, int64_t nx, int64_t x0,
+                                                   uint16_t* __restrict__ hi, uint16_t* __restrict__ lo)
 {
     const int64_t e = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     if (e >= ldp * kBwdSepK) return;
     const int64_t j = e / kBwdSepK, i = e % kBwdSepK;
     double v[4] = {0.0, 0.0, 0.0, 0.0};
-    if (j < n && i < nx) {
-        const double x = ox + (static_cast<double>(i) + 0.5) * hx;
+    if (j < n && x0 + i < nx) {
+        const double x = ox + (static_cast<double>(x0 + i) + 0.5) * hx;
         const double t = zx[j] * fs * x;
         double sn, cs;
         sincospi(2.0 * (t - floor(t)), &sn, &cs);
@@ -545,16 +546,12 @@ hipError_t launch_backward(const BwdArgs& a, hipStream_t s)
     }
     const bool want_c = a.gsigma != nullptr && a.ysaved == nullptr;
     if (grid && a.sep) {
+        // x in chunks of kBwdSepK cells, one after another on the stream (the operand buffers
+        // hold one chunk); chunk xc writes its row-chunk sums to partial slots
+        // [xc chunks, (xc + 1) chunks), and the reduction adds every slot
         const BwdSep& b = *a.sep;
         const int64_t ng = b.qp * kBwdSepK, ne = a.ldp * kBwdSepK;
-        hipLaunchKernelGGL(k_bwd_sep_ga, dim3(static_cast<unsigned>((ng + 255) / 256)), dim3(256), 0, s, a.gy, a.gn[0],
-                           b.ny, b.nyp, b.qp, b.ga_hi, b.ga_lo);
-        hipLaunchKernelGGL(k_bwd_sep_ex, dim3(static_cast<unsigned>((ne + 255) / 256)), dim3(256), 0, s, b.zx, b.fsx,
-                           a.go[0], a.gh[0], a.n, a.ldp, a.gn[0], b.ex_hi, b.ex_lo);
-    }
-    timer_mark(s, true);
-    if (grid && a.sep) {
-        const BwdSep& b = *a.sep;
+        const int64_t nxc = (a.gn[0] + kBwdSepK - 1) / kBwdSepK;
         BwdSepK k{b.ga_hi, b.ga_lo, b.ex_hi, b.ex_lo, b.ey, b.ez, a.ldp, b.qp, b.ny, b.nyp,
                   static_cast<float>(geo.oy), static_cast<float>(geo.hy), static_cast<float>(geo.oz),
                   static_cast<float>(geo.hz)};
@@ -562,9 +559,18 @@ hipError_t launch_backward(const BwdArgs& a, hipStream_t s)
             k.oz = 0.f;
             k.hz = 0.f;
         }
-        hipLaunchKernelGGL(k_bwd_sep, dim3(static_cast<unsigned>(a.ldp / 32), static_cast<unsigned>(b.chunks)),
-                           dim3(256), 0, s, k, a.partial);
+        for (int64_t xc = 0; xc < nxc; ++xc) {
+            const int64_t x0 = xc * kBwdSepK;
+            hipLaunchKernelGGL(k_bwd_sep_ga, dim3(static_cast<unsigned>((ng + 255) / 256)), dim3(256), 0, s, a.gy,
+                               a.gn[0], x0, b.ny, b.nyp, b.qp, b.ga_hi, b.ga_lo);
+            hipLaunchKernelGGL(k_bwd_sep_ex, dim3(static_cast<unsigned>((ne + 255) / 256)), dim3(256), 0, s, b.zx,
+                               b.fsx, a.go[0], a.gh[0], a.n, a.ldp, a.gn[0], x0, b.ex_hi, b.ex_lo);
+            if (xc == 0) timer_mark(s, true);
+            hipLaunchKernelGGL(k_bwd_sep, dim3(static_cast<unsigned>(a.ldp / 32), static_cast<unsigned>(b.chunks)),
+                               dim3(256), 0, s, k, a.partial + xc * b.chunks * 5 * a.ldp);
+        }
     } else if (grid && a.tx) {
+        timer_mark(s, true);
         const int64_t nq = a.gn[1] * a.gn[2];
         const int nxt = static_cast<int>((a.gn[0] + kBT - 1) / kBT);
         const int64_t ntiles = static_cast<int64_t>(nxt) * ((nq + kBT - 1) / kBT);
@@ -576,12 +582,15 @@ hipError_t launch_backward(const BwdArgs& a, hipStream_t s)
         else
             hipLaunchKernelGGL(k_bwd_grid_tab<false>, g, dim3(256), 0, s, a.tx, a.ty, a.tz, a.ldp, geo, nq, nxt,
                                ntiles, per, a.gy, a.partial);
-    } else if (a.dim == 3) {
-        if (grid) launch_bwd_main<3, true>(a, chunk, geo, want_c, s);
-        else launch_bwd_main<3, false>(a, chunk, geo, want_c, s);
     } else {
-        if (grid) launch_bwd_main<2, true>(a, chunk, geo, want_c, s);
-        else launch_bwd_main<2, false>(a, chunk, geo, want_c, s);
+        timer_mark(s, true);
+        if (a.dim == 3) {
+            if (grid) launch_bwd_main<3, true>(a, chunk, geo, want_c, s);
+            else launch_bwd_main<3, false>(a, chunk, geo, want_c, s);
+        } else {
+            if (grid) launch_bwd_main<2, true>(a, chunk, geo, want_c, s);
+            else launch_bwd_main<2, false>(a, chunk, geo, want_c, s);
+        }
     }
     timer_mark(s, false);
     hipError_t e = hipGetLastError();

@@ -927,8 +927,10 @@ int field_backward_ws_size(const grf_modes* modes, int64_t n_points, size_t* byt
     return GRF_OK;
 }
 
-// The separable dense adjoint applies to grids whose x extent fits one operand (K axis).
-static bool bwd_sep_ok(const grf_grid* g) { return g->n[0] >= 1 && g->n[0] <= kBwdSepK; }
+// The separable dense adjoint takes x in chunks of kBwdSepK cells (the K axis of one
+// operand); each chunk's row-chunk sums get their own partial slots.
+static bool bwd_sep_ok(const grf_grid* g) { return g->n[0] >= 1; }
+static int64_t bwd_sep_xchunks(const grf_grid* g) { return (g->n[0] + kBwdSepK - 1) / kBwdSepK; }
 
 static int64_t round_up32(int64_t v) { return (v + 31) / 32 * 32; }
 
@@ -941,7 +943,7 @@ static size_t bwd_sep_ws(const grf_modes* m, const grf_grid* g)
 {
     const int64_t ldp = padded_modes(m->n), qp = bwd_sep_rows(g);
     const int64_t nz = m->dim == 3 ? g->n[2] : 1;
-    const int64_t nch = bwd_sep_chunks(ldp, qp);
+    const int64_t nch = bwd_sep_chunks(ldp, qp) * bwd_sep_xchunks(g);
     return rot_ws_bytes(m) + align256(sizeof(double) * 4 * ldp) + align256(sizeof(float) * 5 * ldp * nch) +
            align256(sizeof(float) * bwd_scal_floats(m->n)) + 2 * align256(sizeof(uint16_t) * qp * kBwdSepK) +
            2 * align256(sizeof(uint16_t) * 4 * ldp * kBwdSepK) + align256(sizeof(float2) * round_up32(g->n[1]) * ldp) +
@@ -968,7 +970,7 @@ static int backward_common(const char* fn, const grf_modes* modes, const double*
     c.used += rot_ws_bytes(modes);
     double* params = c.take<double>(4 * ldp);
     const int64_t qp = grid ? bwd_sep_rows(grid) : 0;
-    const int64_t nch = sep ? bwd_sep_chunks(ldp, qp) : bwd_chunks(P);
+    const int64_t nch = sep ? bwd_sep_chunks(ldp, qp) * bwd_sep_xchunks(grid) : bwd_chunks(P);
     float* partial = c.take<float>(5 * ldp * nch);
     float* scal = c.take<float>(bwd_scal_floats(modes->n));
     grf_modes am;  // sums run on k itself; grad_ell maps back through the original table
@@ -1013,7 +1015,7 @@ static int backward_common(const char* fn, const grf_modes* modes, const double*
         bs.nyp = round_up32(grid->n[1]);
         bs.nz = nz;
         bs.qp = qp;
-        bs.chunks = nch;
+        bs.chunks = bwd_sep_chunks(ldp, qp);  // per x chunk
     } else if (grid) {  // per-axis FP32 revolution tables of the direct method
         tabs = grid_ws(&am, grid, GRF_DIRECT_F32, c.base + c.used);
         GRF_HIP(build_tables(&am, grid, GRF_DIRECT_F32, tabs, s));
@@ -1096,8 +1098,6 @@ int field_backward_grid_method(const grf_modes* modes, const grf_grid* grid, int
     if ((rc = check_grid(grid, modes->dim, fn))) return rc;
     if (method != GRF_AUTO && method != GRF_DIRECT_F32 && method != GRF_SEP_BF16_X3)
         return fail(GRF_EINVAL, "%s: method must be GRF_AUTO, GRF_DIRECT_F32 or GRF_SEP_BF16_X3", fn);
-    if (method == GRF_SEP_BF16_X3 && !bwd_sep_ok(grid))
-        return fail(GRF_EUNSUPPORTED, "%s: the separable adjoint needs an x extent of at most %d cells", fn, kBwdSepK);
     if (modes->sigma <= 0.0 && grad_sigma) return fail(GRF_EINVAL, "%s: sigma must be > 0 for grad_sigma", fn);
     return backward_common(fn, modes, nullptr, grid, grid->n[0] * grid->n[1] * grid->n[2], grad_y, y_saved, grad_phi,
                            grad_k, grad_sigma, grad_ell, ws, ws_bytes, stream, method);

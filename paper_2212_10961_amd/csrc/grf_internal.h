@@ -382,7 +382,7 @@ hipError_t launch_axis_tables_batched(const AxisTableArgs* descs, const uint64_t
 hipError_t launch_fill_u64(unsigned long long* p, unsigned long long v, int n, int stride, hipStream_t s);
 
 // ---------------------------------------------------------------- adjoint
-// Separable dense adjoint on a grid whose x extent is at most kBwdSepK: per mode j,
+// Separable dense adjoint on a grid, x in chunks of kBwdSepK cells: per mode j,
 // S_j = sum_c g_c e^{i theta_jc} = sum_q [sum_x g[q][x] Ex[x][j]] Ey[y_q][j] Ez[z_q][j] over the
 // rows q = (y, z), the bracket (and its x-weighted twin) as a bf16 hi+lo matrix product.
 constexpr int kBwdSepK = 128;

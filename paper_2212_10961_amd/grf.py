@@ -565,7 +565,7 @@ def field_backward(modes: Modes, xyz: torch.Tensor, grad_y: torch.Tensor, y_save
 def field_backward_grid(modes: Modes, shape, grad_y: torch.Tensor, origin=None, h=None, y_saved=None,
                         stream=None, method="auto"):
     """Gradients for a dense dL/dY over every cell of a structured grid.  ``method``: "auto"
-    (the separable form when the x extent is at most 128), "direct_f32" or "sep_bf16_x3"."""
+    (the separable form, x in chunks of 128 cells), "direct_f32" or "sep_bf16_x3"."""
     lib = L.load()
     dev = modes.z.device
     m, g = modes.c(), _grid(shape, origin, h)

@@ -79,10 +79,12 @@ def test_backward_grid_dense(orc, grf, meth, saved):
 
 
 @pytest.mark.parametrize("shape,ell,n", [((37, 50), (5.0, 7.0), 96), ((128, 33, 5), (9.0, 4.0, 2.0), 200),
-                                         ((1, 40, 3), (3.0, 3.0, 1.0), 64), ((16, 1, 1), (2.0, 2.0, 2.0), 33)])
+                                         ((1, 40, 3), (3.0, 3.0, 1.0), 64), ((16, 1, 1), (2.0, 2.0, 2.0), 33),
+                                         ((129, 20), (5.0, 7.0), 96), ((300, 9, 3), (9.0, 4.0, 2.0), 150)])
 def test_backward_grid_separable_shapes(orc, grf, shape, ell, n):
-    """Separable adjoint on 2-D and 3-D grids: x extents 1 .. 128 (padded K), row counts that
-    are not multiples of 32 (padded rows), ny below and above one 32-row tile."""
+    """Separable adjoint on 2-D and 3-D grids: x extents 1 .. 128 (padded K) and wider ones in
+    chunks of 128 (129: a second chunk of one cell; 300: three chunks, the last of 44), row
+    counts that are not multiples of 32 (padded rows), ny below and above one 32-row tile."""
     dim = len(shape)
     sigma = 0.9
     print(f"case backward separable {shape} n={n}", flush=True)
@@ -94,12 +96,6 @@ def test_backward_grid_separable_shapes(orc, grf, shape, ell, n):
     ref = orc.grad_points(zo, po, sigma, ell, x, g.astype(np.float64))
     out = grf.field_backward_grid(m, shape, torch.from_numpy(g).cuda(), method="sep_bf16_x3", **geo)
     _check(out, ref, tol=BWD_TOL["sep_bf16_x3"], tol_scalar=BWD_TOL["sep_bf16_x3"], tol_sigma=SIGMA_TOL["sep_bf16_x3"])
-
-
-def test_backward_grid_separable_rejects_wide_x(grf):
-    m = grf.modes_from_tables(*grf.make_modes(2, wl.GAUSSIAN, 8, 3), 1.0, (4.0, 4.0))
-    with pytest.raises(RuntimeError, match="x extent"):
-        grf.field_backward_grid(m, (129, 4), torch.zeros(129 * 4, device="cuda"), method="sep_bf16_x3")
 
 
 def test_backward_dense_workload_methods_agree(grf):
