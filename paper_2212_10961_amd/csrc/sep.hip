@@ -775,11 +775,12 @@ using SmallT3 = SepShape<2, 2, 1, 1, true>;
 // back costs more than the contraction.  Here the x side of a tile is the instance's local
 // table R_j(r) = e^{2 pi i a_x r hx} (r < kGenRows, the same for every tile of the instance:
 // see GenArgs), staged straight into LDS, and the block generates the y side, which carries
-// the tile's x0 phase, in LDS itself: thread (pair p, segment) owns modes 2p, 2p + 1 of the
-// stage and RPT consecutive rows; the first row's phase psi' + a_y (y0 + r0) hy + a_x x0 hx is
-// formed and reduced in FP64 (hardware cos/sin of the fraction in revolutions, times w), and
-// each further row is one FP32 complex product with the step e^{2 pi i frac(a_y hy)} (at most
-// 7 of them: a relative error ~1e-6, far below the fp16/bf16 rounding of the operand).  Stage
+// the tile's x0 phase, in LDS itself: thread (p, segment) owns mode p of the stage and RPT
+// consecutive rows (16 of the 128-row tile); the first row's phase psi' + a_y (y0 + r0) hy +
+// a_x x0 hx is formed and reduced in FP64 (hardware cos/sin of the fraction in revolutions,
+// times w), and each further row is one FP32 complex product with the step
+// e^{2 pi i frac(a_y hy)} (at most 15 of them: a relative error ~2e-6, far below the
+// fp16/bf16 rounding of the operand).  Stage
 // s + 1 is generated and loaded while the MFMAs consume stage s; the LDS layout and the
 // fragment reads are those of the staged tiles.
 template <bool BF>
@@ -802,22 +803,23 @@ __device__ __forceinline__ void sep_tile_gen(const SepArgs& a, const GenArgs& g,
     constexpr int WN = 2;
     constexpr int BM = 2 * TM * 32, BN = WN * TN * 32;
     constexpr int ROW_B = kJC * 4;
-    constexpr int RPT = BM / 16;        // rows per thread: 16 mode pairs x 16 segments
+    constexpr int RPT = BM / 8;         // rows per thread: 32 modes x 8 segments
     constexpr int KB = BN / 32;         // B load instructions per wave and stage (8 rows each)
-    static_assert(RPT >= 1 && RPT <= 8 && BN <= kGenRows, "tile shape");
+    static_assert(RPT >= 1 && RPT <= 16 && BN <= kGenRows, "tile shape");
     const int t = threadIdx.x;
     const int l = t & 63, h = l >> 5;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int wm = wave / WN, wn = wave % WN;
     const int64_t x0 = tx * BN, y0 = ty * BM;
 
-    // generation role: modes 2p, 2p + 1 of every stage, rows r0 .. r0 + RPT - 1 of the y operand
-    const int p = t & 15, seg = t >> 4;
+    // generation role: mode p of every stage, rows r0 .. r0 + RPT - 1 of the y operand (each
+    // mode's FP64 phase, cosine and sine are formed by 8 threads, its record loaded 8 times)
+    const int p = t & 31, seg = t >> 5;
     const int r0 = seg * RPT;
     const double yoff = static_cast<double>(y0 + r0) * g.hy, xoff = static_cast<double>(x0) * g.hx;
     int soff[RPT];
 #pragma unroll
-    for (int r = 0; r < RPT; ++r) soff[r] = (r0 + r) * ROW_B + (((p >> 1) ^ swz(r0 + r)) << 4) + ((p & 1) << 3);
+    for (int r = 0; r < RPT; ++r) soff[r] = (r0 + r) * ROW_B + (((p >> 2) ^ swz(r0 + r)) << 4) + ((p & 3) << 2);
 
     // x-side rows [BM, BM + BN) of a stage: instruction k of this wave fills rows 8 rb .. 8 rb + 7
     int32_t offb[KB];
@@ -838,44 +840,34 @@ __device__ __forceinline__ void sep_tile_gen(const SepArgs& a, const GenArgs& g,
     typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
     typedef const u32x4 __attribute__((address_space(1)))* gq;
     struct Params {
-        GenMode m[2];
+        GenMode m;
     };
     auto load = [&](int64_t s, Params& pr) {
-        // three 16-byte global loads per mode (address-space cast: global, not flat, loads)
-        const gq src = (gq)(g.md + s * kJC + 2 * p);
+        // three 16-byte global loads (address-space cast: global, not flat, loads)
+        const gq src = (gq)(g.md + s * kJC + p);
+        struct Raw {
+            u32x4 q[3];
+        } raw;
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            struct Raw {
-                u32x4 q[3];
-            } raw;
-#pragma unroll
-            for (int c = 0; c < 3; ++c) raw.q[c] = src[3 * m + c];
-            pr.m[m] = __builtin_bit_cast(GenMode, raw);
-        }
+        for (int c = 0; c < 3; ++c) raw.q[c] = src[c];
+        pr.m = __builtin_bit_cast(GenMode, raw);
     };
     auto gen = [&](const Params& pr, char* buf) {
-        float er[2], ei[2];
-#pragma unroll
-        for (int m = 0; m < 2; ++m) {
-            const double t0 = fma(pr.m[m].ay, yoff, fma(pr.m[m].ax, xoff, pr.m[m].psi));
-            const float f0 = static_cast<float>(t0 - floor(t0));  // exact in FP64
-            er[m] = __builtin_amdgcn_cosf(f0) * pr.m[m].w;
-            ei[m] = __builtin_amdgcn_sinf(f0) * pr.m[m].w;
-        }
+        const double t0 = fma(pr.m.ay, yoff, fma(pr.m.ax, xoff, pr.m.psi));
+        const float f0 = static_cast<float>(t0 - floor(t0));  // exact in FP64
+        float er = __builtin_amdgcn_cosf(f0) * pr.m.w;
+        float ei = __builtin_amdgcn_sinf(f0) * pr.m.w;
 #pragma unroll
         for (int r = 0; r < RPT; ++r) {
-            *reinterpret_cast<uint2*>(buf + soff[r]) = make_uint2(pack2<BF>(er[0], ei[0]), pack2<BF>(er[1], ei[1]));
+            *reinterpret_cast<uint32_t*>(buf + soff[r]) = pack2<BF>(er, ei);
             if (r + 1 < RPT) {
-#pragma unroll
-                for (int m = 0; m < 2; ++m) {
-                    float nr = fmaf(er[m], pr.m[m].rc, -ei[m] * pr.m[m].rs);
-                    float ni = fmaf(er[m], pr.m[m].rs, ei[m] * pr.m[m].rc);
-                    // opaque: the next row's pack converts these values (one v_cvt_pk) instead
-                    // of the compiler recomputing the products in mixed precision
-                    asm("" : "+v"(nr), "+v"(ni));
-                    er[m] = nr;
-                    ei[m] = ni;
-                }
+                float nr = fmaf(er, pr.m.rc, -ei * pr.m.rs);
+                float ni = fmaf(er, pr.m.rs, ei * pr.m.rc);
+                // opaque: the next row's pack converts these values (one v_cvt_pk) instead
+                // of the compiler recomputing the products in mixed precision
+                asm("" : "+v"(nr), "+v"(ni));
+                er = nr;
+                ei = ni;
             }
         }
     };
@@ -955,7 +947,7 @@ __device__ __forceinline__ unsigned xcc_id()
 }
 
 template <bool BF, bool X3, bool D3, bool GEN>
-__global__ __launch_bounds__(256) void k_sep_batch(const SepBatchItem* __restrict__ items, int n_inst,
+__global__ __launch_bounds__(256, GEN ? 2 : 1) void k_sep_batch(const SepBatchItem* __restrict__ items, int n_inst,
                                                    const BatchQueue* __restrict__ queues, int nq,
                                                    unsigned long long* counters)
 {
