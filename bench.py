@@ -401,7 +401,7 @@ def points_extra(grf, wl, torch, np, dev, err=False):
     for form in ("direct_f32_binned", "direct_f32_pointwise"):
         ws = torch.empty(grf.points_workspace_bytes(m, c["n_points"], form), dtype=torch.uint8, device=dev)
         ms, kms = _timed(torch, grf, lambda: grf.field_points(m, x, method=form, thresholds=[c["threshold"]],
-                                                              want_ind=True, out=o, workspace=ws), 5, 1)
+                                                              want_ind=True, out=o, workspace=ws), 20, 3)
         res[form] = {"ms_per_call": ms, "kernel_ms": kms, "mode_points_per_s": work / (ms * 1e-3),
                      "roofline": {"bound": "alu", "achieved": work / (kms * 1e-3), "peak": COS_PEAK,
                                   "unit": "mode·point/s", "frac": work / (kms * 1e-3) / COS_PEAK,

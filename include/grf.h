@@ -250,13 +250,15 @@ int eval_field_points_ws_size(const grf_modes* modes, int64_t n_points, int meth
  *   xyz      device double[P][dim] (row-major).
  *   method   GRF_DIRECT_F32: cos and sum in FP32 with FP64 phase reduction, in one of two forms
  *              GRF_DIRECT_F32_BINNED (what GRF_DIRECT_F32 uses from 65,536 points): points are
- *                sorted into cubic cells of their bounding box (about 2,048 per cell, slots
- *                padded to work items of 256), the phase at the cell centre is reduced in FP64
- *                per mode and work item and each point adds its offset's phase, formed on the
- *                matrix cores with FP32 accuracy; modes whose offset phase can reach 4
+ *                sorted into cells of the bounding box of their finite coordinates (sides
+ *                about equal, a whole number of cells per axis, about 2,048 points per cell,
+ *                slots padded to work items of 256), the phase at the cell centre is reduced in
+ *                FP64 per mode and work item and each point adds its offset's phase, formed on
+ *                the matrix cores with FP32 accuracy; modes whose offset phase can reach 4
  *                revolutions within a cell take the per-point FP64 reduction instead.
- *                At most 2^30 points (GRF_EUNSUPPORTED above).  A point's value does not depend
- *                on the other points (deterministic);
+ *                At most 2^30 points (GRF_EUNSUPPORTED above).  A point's value depends on the
+ *                other points only through the cell geometry, not on their order
+ *                (deterministic); a point with a non-finite coordinate gets NaN;
  *              GRF_DIRECT_F32_POINTWISE: phase a.x + psi reduced in FP64 per mode and point;
  *            GRF_DIRECT_F64: FP64 throughout.  Separable methods -> GRF_EUNSUPPORTED.
  *   y, k, ind, epi, ws: as eval_field_grid (outputs in input order).  P = 0 is a no-op.

@@ -223,9 +223,10 @@ hipError_t launch_points_reduce(const float* partial, int slices, int64_t P, flo
                                 float* k, uint8_t* ind, hipStream_t s);
 
 // ---------------------------------------------------------------- binned point sum (points.hip)
-// Points sorted into cubic cells of their bounding box, each cell's slots padded to whole work
-// items of kBinItemSlots; per (mode, work item) the phase at the cell centre is reduced in FP64
-// and the points' local phases are formed in FP32 by a matrix product on the matrix cores.
+// Points sorted into cells of their bounding box (sides about equal, each axis cut into a whole
+// number of them), each cell's slots padded to whole work items of kBinItemSlots; per (mode,
+// work item) the phase at the cell centre is reduced in FP64 and the points' local phases are
+// formed in FP32 by a matrix product on the matrix cores.
 constexpr int kBinItemSlots = 256;     // points per work item (one wave: 16 groups of 16)
 constexpr int kBinTarget = 2048;       // points per cell on average
 constexpr int kBinBboxBlocks = 512;    // blocks of the bounding-box pass
@@ -233,7 +234,8 @@ constexpr int64_t kBinMinPoints = int64_t(1) << 16;  // GRF_DIRECT_F32 bins from
 constexpr int64_t kBinMaxPoints = int64_t(1) << 30;  // (slot indices are 32-bit)
 struct BinGeom {
     double lo[3];      // bounding-box corner
-    double s, inv_s;   // cell side and its reciprocal
+    double s[3];       // cell side per axis (each axis of the box holds a whole number of cells)
+    double inv_s[3];   // and its reciprocal
     int32_t n[3];      // cells per axis (x fastest)
     int32_t ncell;
     int64_t nslot;     // sorted slots: every cell padded to whole work items

@@ -2,8 +2,8 @@
 // evaluated at every cell centre).
 //
 // The per-point form reduces every phase a_j . x_p + psi_j in FP64 (three FP64 FMAs, a fract
-// and a conversion per mode and point).  Here the points are first sorted into cubic cells of
-// their bounding box (each cell's slots padded to whole work items of 256), and the phase of
+// and a conversion per mode and point).  Here the points are first sorted into cells of their
+// bounding box (each cell's slots padded to whole work items of 256), and the phase of
 // mode j at point p of a cell with centre c is
 //   r_jp = frac(a_j . c + psi_j) + a_j . (x_p - c),
 // the first part reduced in FP64 once per (mode, work item), the second small (cells are
@@ -47,8 +47,10 @@ __global__ __launch_bounds__(256) void k_bin_bbox(const double* __restrict__ xyz
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
             const double v = xyz[p * DIM + a];
-            lo[a] = fmin(lo[a], v);
-            hi[a] = fmax(hi[a], v);
+            if (isfinite(v)) {  // a non-finite coordinate spoils only its own point's value
+                lo[a] = fmin(lo[a], v);
+                hi[a] = fmax(hi[a], v);
+            }
         }
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
@@ -68,8 +70,11 @@ __global__ __launch_bounds__(256) void k_bin_bbox(const double* __restrict__ xyz
     if (threadIdx.x < 6) part[blockIdx.x * 6 + threadIdx.x] = s[threadIdx.x][0];
 }
 
-// Cell geometry from the bounding box (one block): cubic cells of side s holding about
-// `target` points on average, at most `cap` cells; clears the cell counters.
+// Cell geometry from the bounding box (one block): cells of side about s holding about
+// `target` points on average, at most `cap` cells; each axis of extent e > 0 is cut into
+// n = round(e / s) >= 1 cells of side e / n, so that no row of cells sticks out of the box (a
+// partly filled last row pads its cells to whole work items for few points).  Clears the
+// cell counters.
 __global__ __launch_bounds__(256) void k_bin_geom(const double* __restrict__ part, int nb, int dim, int64_t P,
                                                   double target, int64_t cap, BinGeom* __restrict__ geom,
                                                   int32_t* __restrict__ count)
@@ -120,7 +125,7 @@ __global__ __launch_bounds__(256) void k_bin_geom(const double* __restrict__ par
         for (int it = 0;; ++it) {
             int64_t tot = 1;
             for (int a = 0; a < 3; ++a) {
-                const double q = (a < dim && ext[a] > 0.0) ? ceil(ext[a] / s) : 1.0;
+                const double q = (a < dim && ext[a] > 0.0) ? floor(ext[a] / s + 0.5) : 1.0;
                 n[a] = !(q >= 1.0) ? 1 : (q >= double(1 << 20) ? int64_t(1) << 20 : static_cast<int64_t>(q));
                 tot *= n[a];
             }
@@ -129,11 +134,15 @@ __global__ __launch_bounds__(256) void k_bin_geom(const double* __restrict__ par
         }
         if (n[0] * n[1] * n[2] > cap) n[0] = n[1] = n[2] = 1;
         for (int a = 0; a < 3; ++a) {
-            g.lo[a] = a < dim ? lo[a] : 0.0;
+            g.lo[a] = a < dim && isfinite(lo[a]) ? lo[a] : 0.0;  // (no finite coordinate: any)
             g.n[a] = static_cast<int32_t>(n[a]);
+            // the side that tiles the extent; s on flat axes (and for extents so small that the
+            // reciprocal would overflow)
+            double sa = (a < dim && ext[a] > 0.0) ? ext[a] / static_cast<double>(n[a]) : s;
+            if (!(sa > 0.0) || !isfinite(sa) || !isfinite(1.0 / sa)) sa = s;
+            g.s[a] = sa;
+            g.inv_s[a] = 1.0 / sa;
         }
-        g.s = s;
-        g.inv_s = 1.0 / s;
         g.ncell = static_cast<int32_t>(n[0] * n[1] * n[2]);
         *geom = g;
         ncell_s = g.ncell;
@@ -148,7 +157,7 @@ __device__ __forceinline__ int32_t cell_of(const BinGeom& g, const double* x)
     int32_t c = 0, stride = 1;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
-        double f = floor((x[a] - g.lo[a]) * g.inv_s);
+        double f = floor((x[a] - g.lo[a]) * g.inv_s[a]);
         if (!(f >= 0.0)) f = 0.0;  // also NaN
         if (f > static_cast<double>(g.n[a] - 1)) f = static_cast<double>(g.n[a] - 1);
         c += static_cast<int32_t>(f) * stride;
@@ -277,7 +286,7 @@ __global__ __launch_bounds__(256) void k_bin_scatter(const double* __restrict__ 
     for (int a = 0; a < DIM; ++a) {
         const int32_t i = rest % g.n[a];
         rest /= g.n[a];
-        d[a] = xyz[p * DIM + a] - (g.lo[a] + (static_cast<double>(i) + 0.5) * g.s);
+        d[a] = xyz[p * DIM + a] - (g.lo[a] + (static_cast<double>(i) + 0.5) * g.s[a]);
     }
     rec[slot] = make_double4(d[0], d[1], d[2], static_cast<double>(p));
 }
@@ -336,13 +345,14 @@ __global__ __launch_bounds__(256) void k_bin_modes(const double4* __restrict__ p
     const int64_t j = static_cast<int64_t>(blockIdx.x) * 256 + threadIdx.x;
     if (j >= ldp) return;
     const double4 m = prm[j];
-    const double half = 0.5 * geom->s;  // offsets from the centre are at most half a side per axis
-    const double reach = half * (fabs(m.x) + fabs(m.y) + (dim == 3 ? fabs(m.z) : 0.0));
+    const BinGeom& g = *geom;
+    // offsets from the centre are at most half a side per axis
+    const double reach = 0.5 * (fabs(m.x) * g.s[0] + fabs(m.y) * g.s[1] + (dim == 3 ? fabs(m.z) * g.s[2] : 0.0));
     ModeF f;
     // revolutions per cell side: the matrix pass multiplies them by offsets in cell sides
-    f.ax = static_cast<float>(m.x * geom->s);
-    f.ay = static_cast<float>(m.y * geom->s);
-    f.az = static_cast<float>(dim == 3 ? m.z * geom->s : 0.0);
+    f.ax = static_cast<float>(m.x * g.s[0]);
+    f.ay = static_cast<float>(m.y * g.s[1]);
+    f.az = static_cast<float>(dim == 3 ? m.z * g.s[2] : 0.0);
     const float wj = j < n ? (wt ? static_cast<float>(wt[j]) : 1.f) : 0.f;
     f.fp64 = reach > kLocalRev ? 1 : 0;
     if (f.fp64) f.ax = f.ay = f.az = 0.f;  // finite fp16 operands (weight 0 in the matrix pass)
@@ -366,7 +376,7 @@ __global__ __launch_bounds__(256) void k_bin_modes(const double4* __restrict__ p
 
 
 // The sum: wave w of the launch takes work item w (kItem slots of one cell).  With offsets
-// u = (x - c) / s in cell sides and b = a s in revolutions per side, the phase of mode j at
+// u = (x - c) / s per axis in cell sides and b = a s in revolutions per side, the phase of mode j at
 // point p is t_j + b_j . u_p with t_j = frac(a_j . c + psi_j) reduced in FP64.  For a tile of 16
 // modes and a group of 16 points that is one fp16 matrix product with FP32 accumulation,
 // [16 x 16] x [16 x 16], whose K entries carry each factor split as hi + lo (fp16 each):
@@ -408,7 +418,7 @@ __global__ __launch_bounds__(256, 5) void k_points_binned(const double4* __restr
     for (int a = 0; a < DIM; ++a) {
         const int32_t i = rest % gm.n[a];
         rest /= gm.n[a];
-        cen[a] = gm.lo[a] + (static_cast<double>(i) + 0.5) * gm.s;
+        cen[a] = gm.lo[a] + (static_cast<double>(i) + 0.5) * gm.s[a];
     }
     // point operand of each 16-point group: this lane's four K entries of point 16 g + jl
     const _Float16 one = static_cast<_Float16>(1.f), zero = static_cast<_Float16>(0.f);
@@ -416,8 +426,8 @@ __global__ __launch_bounds__(256, 5) void k_points_binned(const double4* __restr
 #pragma unroll
     for (int g = 0; g < kGroups; ++g) {
         const double4 r = rec[slot0 + 16 * g + jl];
-        float u[3] = {static_cast<float>(r.x * gm.inv_s), static_cast<float>(r.y * gm.inv_s),
-                      DIM == 3 ? static_cast<float>(r.z * gm.inv_s) : 0.f};
+        float u[3] = {static_cast<float>(r.x * gm.inv_s[0]), static_cast<float>(r.y * gm.inv_s[1]),
+                      DIM == 3 ? static_cast<float>(r.z * gm.inv_s[2]) : 0.f};
         _Float16 h[3], lo[3];
 #pragma unroll
         for (int a = 0; a < 3; ++a) {

@@ -101,6 +101,28 @@ def test_points_binned_degenerate_boxes(orc, grf, layout):
         assert np.all(y == y[0])
 
 
+@pytest.mark.parametrize("form", FORMS)
+def test_points_non_finite_coordinates(orc, grf, form):
+    """A point with an infinite or NaN coordinate has a NaN value; every other point keeps its
+    value (the binned form takes its cells from the finite coordinates only)."""
+    print(f"case points non-finite {form}", flush=True)
+    P = 70000
+    x = wl.points_uniform(P, (500.0, 400.0, 60.0), 1413)
+    bad = np.array([3, 4100, 4101, 40000, P - 1])
+    x[bad[0], 0] = np.inf
+    x[bad[1], 1] = -np.inf
+    x[bad[2], 2] = np.nan
+    x[bad[3]] = np.nan
+    x[bad[4], 0] = -np.inf
+    (zo, po), m = modes_pair(orc, grf, 3, wl.GAUSSIAN, 400, 1414, 1.0, (30.0, 30.0, 6.0))
+    ok = np.ones(P, dtype=bool)
+    ok[bad] = False
+    ref = orc.field_points(zo, po, 1.0, (30.0, 30.0, 6.0), x[ok])
+    y = to_np(grf.field_points(m, torch.from_numpy(x).cuda(), method=form)["y"])
+    assert np.all(np.isnan(y[bad]))
+    assert_field(y[ok], ref, 1.0, "direct_f32", f"non-finite {form}")
+
+
 def test_points_binned_weighted_and_rotated(orc, grf):
     print("case points binned weighted + rotated", flush=True)
     ref_t = orc.lattice_modes(3, wl.EXPONENTIAL, 12, 0.7, 1409)
