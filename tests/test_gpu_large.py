@@ -60,3 +60,33 @@ def test_grid_beyond_2_31_cells(grf, case, method):
         del eo
     del out
     torch.cuda.empty_cache()
+
+
+def test_points_at_the_binned_limit(orc, grf):
+    """2^30 points, the most the binned form takes: both forms against the oracle on sampled
+    points (first, last, random) and against each other everywhere."""
+    P = 2 ** 30
+    print(f"case points P={P}", flush=True)
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(1503)
+    x = torch.rand(P, 3, dtype=torch.float64, device="cuda", generator=gen)
+    x *= torch.tensor([4000.0, 4000.0, 400.0], dtype=torch.float64, device="cuda")
+    ell = (50.0, 50.0, 10.0)
+    (zo, po), m = modes_pair(orc, grf, 3, wl.GAUSSIAN, 16, 1504, 1.0, ell)
+    rng = np.random.default_rng(1505)
+    idx = np.unique(np.concatenate([np.arange(256), np.arange(P - 256, P), rng.integers(0, P, size=4096)]))
+    it = torch.from_numpy(idx).cuda()
+    ref = orc.field_points(zo, po, 1.0, ell, x[it].cpu().numpy())
+    thr = [0.4]
+    ys = {}
+    for form in ("direct_f32_binned", "direct_f32_pointwise"):
+        out = grf.field_points(m, x, method=form, thresholds=thr, want_ind=True)
+        assert_field(to_np(out["y"][it]), ref, 1.0, "direct_f32", f"P=2^30 {form}")
+        assert_indicator(to_np(out["ind"][it]), ref, thr, 1.0, "direct_f32")
+        ys[form] = out["y"]
+        del out
+        torch.cuda.empty_cache()
+    d = float((ys["direct_f32_binned"] - ys["direct_f32_pointwise"]).abs().max().item())
+    assert d <= 2 * TOL["direct_f32"]["band"], d
+    del ys, x
+    torch.cuda.empty_cache()
