@@ -36,8 +36,8 @@ __global__ __launch_bounds__(256) void k_bwd(const double4* __restrict__ prm, in
     const int64_t p1 = min(P, p0 + chunk);
     const double4 m = prm[min(j, ldp - 1)];
     float s = 0.f, ux = 0.f, uy = 0.f, uz = 0.f, cc = 0.f;
-    for (int64_t p = p0; p < p1; ++p) {
-        double x, y, z = 0.0;
+    auto point = [&](int64_t p, double& x, double& y, double& z, float& g) {
+        z = 0.0;
         if (GRID) {
             const int64_t i = p % geo.nx, q = p / geo.nx;
             x = geo.ox + (static_cast<double>(i) + 0.5) * geo.hx;
@@ -48,7 +48,9 @@ __global__ __launch_bounds__(256) void k_bwd(const double4* __restrict__ prm, in
             y = xyz[p * DIM + 1];
             if (DIM == 3) z = xyz[p * DIM + 2];
         }
-        const float g = gy[p];
+        g = gy[p];
+    };
+    auto term = [&](double x, double y, double z, float g) {
         double ph = DIM == 3 ? fma(m.z, z, m.w) : m.w;
         ph = fma(m.y, y, ph);
         ph = fma(m.x, x, ph);
@@ -60,6 +62,24 @@ __global__ __launch_bounds__(256) void k_bwd(const double4* __restrict__ prm, in
         uy = fmaf(g * static_cast<float>(y), sn, uy);
         if (DIM == 3) uz = fmaf(g * static_cast<float>(z), sn, uz);
         if (WANT_C) cc = fmaf(g, __builtin_amdgcn_cosf(f), cc);
+    };
+    // The points' (uniform) loads go out eight at a time, ahead of their terms; the sums keep
+    // point order.
+    constexpr int kU = 8;
+    int64_t p = p0;
+    for (; p + kU <= p1; p += kU) {
+        double x[kU], y[kU], z[kU];
+        float g[kU];
+#pragma unroll
+        for (int u = 0; u < kU; ++u) point(p + u, x[u], y[u], z[u], g[u]);
+#pragma unroll
+        for (int u = 0; u < kU; ++u) term(x[u], y[u], z[u], g[u]);
+    }
+    for (; p < p1; ++p) {
+        double x, y, z;
+        float g;
+        point(p, x, y, z, g);
+        term(x, y, z, g);
     }
     if (j < ldp) {
         float* out = partial + ch * 5 * ldp;
@@ -101,8 +121,28 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(const float* __restrict__ pa
     const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
     float tl[3] = {0.f, 0.f, 0.f}, tc = 0.f;
     if (j < n) {
+        // Sixteen chunks' loads are in flight at a time; the adds keep chunk order.
+        constexpr int kGroup = 16;
         float S = 0.f, U[3] = {0.f, 0.f, 0.f}, C = 0.f;
-        for (int64_t c = 0; c < nch; ++c) {
+        int64_t c = 0;
+        for (; c + kGroup <= nch; c += kGroup) {
+            float v[kGroup][5];
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+                const float* pc = partial + (c + u) * 5 * ldp + j;
+#pragma unroll
+                for (int q = 0; q < 5; ++q) v[u][q] = pc[q * ldp];
+            }
+#pragma unroll
+            for (int u = 0; u < kGroup; ++u) {
+                S += v[u][0];
+                U[0] += v[u][1];
+                U[1] += v[u][2];
+                U[2] += v[u][3];
+                C += v[u][4];
+            }
+        }
+        for (; c < nch; ++c) {
             const float* pc = partial + c * 5 * ldp;
             S += pc[j];
             U[0] += pc[ldp + j];
@@ -154,23 +194,42 @@ __global__ __launch_bounds__(256) void k_dot_partial(const float* __restrict__ a
     if (threadIdx.x == 0) out[blockIdx.x] = r;
 }
 
+// The block partials are summed in block order (one thread per sum); they are first loaded
+// by the whole block into LDS, 1024 values at a time, so that the loads are in flight together
+// instead of one after another.
 __global__ __launch_bounds__(256) void k_bwd_final(const float* __restrict__ scal, int nblk, int dim,
                                                   const float* __restrict__ dotp, int ndot, float amp, float sigma,
                                                   float* __restrict__ gsigma, float* __restrict__ gell)
 {
-    if (threadIdx.x != 0) return;
-    float acc[4] = {0.f, 0.f, 0.f, 0.f};
-    for (int b = 0; b < nblk; ++b)
-        for (int q = 0; q < 4; ++q) acc[q] += scal[b * 4 + q];
-    if (gell)
-        for (int a = 0; a < dim; ++a) gell[a] = acc[a];
+    constexpr int kStage = 1024;
+    __shared__ float st[kStage];
+    const int t = threadIdx.x;
+    float acc = 0.f, d = 0.f;  // thread q < 4: scalar sum q; thread 4: the dot product
+    const int64_t ns = static_cast<int64_t>(nblk) * 4;
+    for (int64_t b0 = 0; b0 < ns; b0 += kStage) {
+        const int m = static_cast<int>(ns - b0 < kStage ? ns - b0 : kStage);
+        __syncthreads();
+        for (int e = t; e < m; e += 256) st[e] = scal[b0 + e];
+        __syncthreads();
+        if (t < 4)
+            for (int e = t; e < m; e += 4) acc += st[e];
+    }
+    if (dotp) {
+        for (int64_t b0 = 0; b0 < ndot; b0 += kStage) {
+            const int m = static_cast<int>(ndot - b0 < kStage ? ndot - b0 : kStage);
+            __syncthreads();
+            for (int e = t; e < m; e += 256) st[e] = dotp[b0 + e];
+            __syncthreads();
+            if (t == 4)
+                for (int e = 0; e < m; ++e) d += st[e];
+        }
+    }
+    if (gell && t < dim) gell[t] = acc;
     if (gsigma) {
         if (dotp) {
-            float d = 0.f;
-            for (int b = 0; b < ndot; ++b) d += dotp[b];
-            gsigma[0] = d / sigma;
-        } else {
-            gsigma[0] = amp / sigma * acc[3];
+            if (t == 4) gsigma[0] = d / sigma;
+        } else if (t == 3) {
+            gsigma[0] = amp / sigma * acc;
         }
     }
 }
@@ -614,7 +673,7 @@ hipError_t launch_backward(const BwdArgs& a, hipStream_t s)
         if (e != hipSuccess) return e;
         dotp = dp;
     }
-    hipLaunchKernelGGL(k_bwd_final, dim3(1), dim3(64), 0, s, a.scal_partial, nblk, a.dim, dotp, ndot, a.amp, a.sigma,
+    hipLaunchKernelGGL(k_bwd_final, dim3(1), dim3(256), 0, s, a.scal_partial, nblk, a.dim, dotp, ndot, a.amp, a.sigma,
                        a.gsigma, a.gell);
     return hipGetLastError();
 }
