@@ -336,9 +336,7 @@ __global__ __launch_bounds__(256) void k_direct_points(const double4* __restrict
         pz[r] = DIM == 3 ? xyz[p * DIM + 2] : 0.0;
         acc[r] = 0.f;
     }
-    for (int j = j0; j < j1; ++j) {
-        const double4 m = prm[j];
-        const float wj = wt ? static_cast<float>(wt[j]) : 1.f;
+    auto mode = [&](const double4& m, float wj) {
 #pragma unroll
         for (int r = 0; r < R; ++r) {
             double ph = DIM == 3 ? fma(m.z, pz[r], m.w) : m.w;
@@ -347,7 +345,27 @@ __global__ __launch_bounds__(256) void k_direct_points(const double4* __restrict
             ph = __builtin_amdgcn_fract(ph);  // x - floor(x) in one FP64 instruction
             acc[r] = fmaf(wj, cos_rev(static_cast<float>(ph)), acc[r]);
         }
+    };
+    // The (uniform) mode records are loaded four at a time, ahead of their terms; each point
+    // still sums the modes in order.
+    constexpr int kMG = 4;
+    int j = j0;
+    for (; j + kMG <= j1; j += kMG) {
+        double4 mm[kMG];
+        float ww[kMG];
+#pragma unroll
+        for (int u = 0; u < kMG; ++u) mm[u] = prm[j + u];
+        if (wt) {
+#pragma unroll
+            for (int u = 0; u < kMG; ++u) ww[u] = static_cast<float>(wt[j + u]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < kMG; ++u) ww[u] = 1.f;
+        }
+#pragma unroll
+        for (int u = 0; u < kMG; ++u) mode(mm[u], ww[u]);
     }
+    for (; j < j1; ++j) mode(prm[j], wt ? static_cast<float>(wt[j]) : 1.f);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const int64_t p = base + 256 * r;
