@@ -201,9 +201,31 @@ GridWs grid_ws(const grf_modes* m, const grf_grid* g, int method, void* base)
         }
         w.t[1] = c.take<uint32_t>(size_t(g->n[1]) * ldp);
         if (hilo) w.tlo[1] = c.take<uint32_t>(size_t(g->n[1]) * ldp);
+        // grids of few tiles: the modes split over slices whose sums are added afterwards
+        w.slices = sep_mode_slices(method, dim, g->n[0], g->n[1], g->n[2], ldp, &w.pairs);
+        if (w.slices > 1) {
+            const size_t before = c.used;
+            w.partial = c.take<float>(size_t(w.slices) * size_t(g->n[0] * g->n[1] * g->n[2]));
+            w.split_bytes = c.used - before;
+        }
     }
     w.bytes = c.used;
     return w;
+}
+
+int grid_ws_bytes(const char* fn, const grf_modes* modes, const grf_grid* grid, int method, size_t* bytes,
+                  size_t* least)
+{
+    int rc;
+    if ((rc = check_modes(modes, fn))) return rc;
+    if ((rc = check_grid(grid, modes->dim, fn))) return rc;
+    if (!bytes || !least) return fail(GRF_EINVAL, "%s: bytes is NULL", fn);
+    method = resolve_grid_method(method, grid);
+    if (method < GRF_DIRECT_F32 || method > GRF_SEP_F16_X3) return fail(GRF_EINVAL, "%s: unknown method %d", fn, method);
+    const GridWs w = grid_ws(modes, grid, method, nullptr);
+    *bytes = rot_ws_bytes(modes) + w.bytes;
+    *least = *bytes - w.split_bytes;
+    return GRF_OK;
 }
 
 int grid_table_descs(const grf_modes* m, const grf_grid* g, int method, const GridWs& w, AxisTableArgs* out)
@@ -305,15 +327,8 @@ const char* grf_last_error(void) { return g_err; }
 
 int eval_field_grid_ws_size(const grf_modes* modes, const grf_grid* grid, int method, size_t* bytes)
 {
-    int rc;
-    if ((rc = check_modes(modes, "eval_field_grid_ws_size"))) return rc;
-    if ((rc = check_grid(grid, modes->dim, "eval_field_grid_ws_size"))) return rc;
-    if (!bytes) return fail(GRF_EINVAL, "eval_field_grid_ws_size: bytes is NULL");
-    method = resolve_grid_method(method, grid);
-    if (method < GRF_DIRECT_F32 || method > GRF_SEP_F16_X3)
-        return fail(GRF_EINVAL, "eval_field_grid_ws_size: unknown method %d", method);
-    *bytes = rot_ws_bytes(modes) + grid_ws(modes, grid, method, nullptr).bytes;
-    return GRF_OK;
+    size_t least = 0;
+    return grf::grid_ws_bytes("eval_field_grid_ws_size", modes, grid, method, bytes, &least);
 }
 
 }  // extern "C"
@@ -344,13 +359,19 @@ static SepArgs sep_args(const grf_modes* modes, const grf_grid* grid, int method
     a.k = k;
     a.ind = ind;
     a.tile = tile;  // -1: size-based default
+    if (tile < 0 && w.partial) {  // the mode split of the default tile (grid_ws decides)
+        a.partial = static_cast<float*>(w.partial);
+        a.slices = w.slices;
+        a.pairs = w.pairs;
+    }
     return a;
 }
 
 static int grid_launch(const grf_modes* modes, const grf_grid* grid, int method, int tile, const Epi& e, float* y,
-                       float* k, uint8_t* ind, void* ws, hipStream_t s)
+                       float* k, uint8_t* ind, void* ws, hipStream_t s, bool allow_split = true)
 {
-    const GridWs w = grid_ws(modes, grid, method, ws);
+    GridWs w = grid_ws(modes, grid, method, ws);
+    if (!allow_split && w.split_bytes) w.partial = nullptr;  // the workspace holds the tables only
     const float amp = static_cast<float>(modes->sigma * std::sqrt(2.0 / static_cast<double>(modes->n)));
     const int64_t ldp = padded_modes(modes->n);
 
@@ -396,13 +417,17 @@ int grid_eval(const char* fn, const grf_modes* modes, const grf_grid* grid, int 
     if ((rc = check_epi(epi, k, ind, fn))) return rc;
     if ((rc = check_grid_method(fn, grid, &method, tile))) return rc;
     const size_t rb = rot_ws_bytes(modes);
-    const size_t need = rb + grid_ws(modes, grid, method, nullptr).bytes;
+    const GridWs gw = grid_ws(modes, grid, method, nullptr);
+    // A workspace without room for the mode split's sums (eval_field_grid_ws_size counts them)
+    // runs the unsplit contraction.
+    const size_t need = rb + gw.bytes - gw.split_bytes;
     if (ws_bytes < need || (!ws && need))
         return fail(GRF_ENOMEM, "%s: workspace of %zu bytes needed, %zu given", fn, need, ws_bytes);
     hipStream_t s = static_cast<hipStream_t>(stream);
     grf_modes am;
     GRF_HIP(aligned_modes(modes, ws, s, &am));
-    return grid_launch(&am, grid, method, tile, make_epi(epi), y, k, ind, static_cast<char*>(ws) + rb, s);
+    return grid_launch(&am, grid, method, tile, make_epi(epi), y, k, ind, static_cast<char*>(ws) + rb, s,
+                       ws_bytes >= rb + gw.bytes);
 }
 
 // ---------------------------------------------------------------- bitruncated (pluri-Gaussian) rule

@@ -230,7 +230,7 @@ static int build_plan(grf_plan* p, const grf_batch_item* items, int32_t n, hipSt
             tbytes += align256(sizeof(uint32_t) * size_t(kGenRows) * size_t(ldp)) + align256(sizeof(GenMode) * size_t(ldp));
         } else {
             ws[i] = grid_ws(&items[i].modes, &items[i].grid, p->method, nullptr);
-            tbytes += ws[i].bytes;
+            tbytes += ws[i].bytes - ws[i].split_bytes;  // tables only: batch tiles do not split the modes
         }
     }
     GRF_HIP(ensure(p->d_tables, p->cap_tables, tbytes));

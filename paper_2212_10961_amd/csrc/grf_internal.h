@@ -168,10 +168,18 @@ int64_t axis_table_blocks(const AxisTableArgs& a);  // 256-thread work blocks on
 struct GridWs {
     void* t[3] = {nullptr, nullptr, nullptr};
     void* tlo[3] = {nullptr, nullptr, nullptr};
-    void* partial = nullptr;  // DIRECT_F64 on small grids: per-slice sums
+    void* partial = nullptr;  // DIRECT_F64 on small grids, FP64; separable mode split, FP32:
+                              // per-slice sums
+    int slices = 1;           // separable mode split: slices of `pairs` stage pairs each
+    int64_t pairs = 0;
+    size_t split_bytes = 0;   // bytes of the separable split's sums (the last part of `bytes`)
     size_t bytes = 0;
 };
 GridWs grid_ws(const grf_modes* m, const grf_grid* g, int method, void* base);
+// Validated workspace bytes of a grid evaluation: all of it, and the least that it runs in (the
+// tables without the mode split's sums; the split is then not taken).
+int grid_ws_bytes(const char* fn, const grf_modes* modes, const grf_grid* grid, int method, size_t* bytes,
+                  size_t* least);
 // eval_field_grid(_tile) after the entry point's name: validation, then tables and sum in `ws`.
 int grid_eval(const char* fn, const grf_modes* modes, const grf_grid* grid, int method, int tile,
               const grf_epi* epi, float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes, void* stream);
@@ -283,6 +291,12 @@ struct SepArgs {
     uint8_t* ind;
     int tile;              // < 0: size-based default; else tile selector (see sep.hip)
     bool timed = false;    // the call's main kernel: timed by the kernel timer when it is on
+    // Mode split (default tile, one-pass forms, grids of few blocks): blockIdx.y = slice sums
+    // stage pairs [slice pairs, (slice + 1) pairs) into partial[slice][nx ny nz]; a second
+    // pass adds the slices in order and applies amp and the epilogue.  nullptr: no split.
+    float* partial = nullptr;
+    int slices = 1;
+    int64_t pairs = 0;
 };
 hipError_t launch_sep(const SepArgs& a, hipStream_t s);
 // Two fields on the same grid (same method, sizes and ldp; the epilogue parameters of `a`
@@ -292,6 +306,8 @@ int sep_tile_count();                // number of tile selectors
 void sep_tile_shape(int tile, int* bm, int* bn);
 int sep_tile_slices(int tile, int method, bool d3);  // z-slices per block
 int sep_default_tile(int method, int64_t nx, int64_t ny, int64_t nz);
+// Mode slices of the default tile for one field (1: no split); *pairs = stage pairs per slice.
+int sep_mode_slices(int method, int dim, int64_t nx, int64_t ny, int64_t nz, int64_t ldp, int64_t* pairs);
 
 // ---------------------------------------------------------------- batched (persistent) launches
 // Generated operands of the 2-D one-pass separable batch tiles.  With E_j(x) = e^{2 pi i a_x x}

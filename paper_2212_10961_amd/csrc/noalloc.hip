@@ -42,8 +42,8 @@ extern "C" int eval_field_grid_noalloc(const grf_modes* modes, const grf_grid* g
                                        float* y, float* k, uint8_t* ind, void* stream)
 {
     const char* fn = "eval_field_grid_noalloc";
-    size_t need = 0;
-    int rc = eval_field_grid_ws_size(modes, grid, method, &need);
+    size_t full = 0, need = 0;  // with the scratch below `full` the mode split is not taken
+    int rc = grf::grid_ws_bytes(fn, modes, grid, method, &full, &need);
     if (rc) return rc;
     if (need > GRF_NOALLOC_SCRATCH_BYTES)
         return grf::fail(GRF_ENOMEM, "%s: this grid and method need %zu bytes of tables, above the fixed %zu-byte "

@@ -411,11 +411,11 @@ constexpr bool use_dl()
 }
 
 // One output tile (rows y0.., cols x0.., slices zb*ZS .. zb*ZS+ZS-1) with direct-to-LDS
-// staging.  `lds0` and `lds1` each hold DlShape<..., D3 ? ZS : 0>::STAGE_B bytes.  Called by
-// whole blocks.
+// staging, summed over the mode stages [s0, s1) (s0 and s1 even).  `lds0` and `lds1` each hold
+// DlShape<..., D3 ? ZS : 0>::STAGE_B bytes.  Called by whole blocks.
 template <int WM, int WN, int TM, int TN, int ZS, bool BF, bool X3, bool D3>
 __device__ __forceinline__ void sep_tile_dl(const SepArgs& a, const Epi& epi, int64_t tx, int64_t ty, int64_t zb, uint4* lds0,
-                                            uint4* lds1)
+                                            uint4* lds1, int64_t s0, int64_t s1)
 {
     using S = DlShape<WM, WN, TM, TN, X3, D3 ? ZS : 0>;
     constexpr int BM = S::BM, BN = S::BN, NB = S::NB, ROW_B = S::ROW_B, NW = S::NW, EZ_OFF = S::EZ_OFF;
@@ -643,9 +643,8 @@ __device__ __forceinline__ void sep_tile_dl(const SepArgs& a, const Epi& epi, in
     // loads of the next stage are in flight while the current buffer feeds the MFMAs.
     char* b0 = reinterpret_cast<char*>(lds0);
     char* b1 = reinterpret_cast<char*>(lds1);
-    const int64_t nstage = ldp / kJC;
-    issue(0, b0);
-    for (int64_t s = 0; s < nstage; s += 2) {
+    issue(s0 * kJC, b0);
+    for (int64_t s = s0; s < s1; s += 2) {
         wait_loads();
         __syncthreads();  // stage s is in b0 for every wave; every wave is done with b1
         issue((s + 1) * kJC, b1);
@@ -653,7 +652,7 @@ __device__ __forceinline__ void sep_tile_dl(const SepArgs& a, const Epi& epi, in
         compute(b0);
         wait_loads();
         __syncthreads();  // stage s + 1 is in b1; every wave is done with b0
-        if (s + 2 < nstage) issue((s + 2) * kJC, b0);
+        if (s + 2 < s1) issue((s + 2) * kJC, b0);
         __builtin_amdgcn_sched_barrier(0);
         compute(b1);
     }
@@ -744,6 +743,7 @@ __global__ __launch_bounds__(WM* WN * 64) void k_sep(SepArgs fa, SepArgs fb, int
         a.y = fb.y;
         a.k = fb.k;
         a.ind = fb.ind;
+        a.partial = fb.partial;
     }
     const int64_t bid = second ? blockIdx.x - per_field : blockIdx.x;
     const int64_t rest = bid / tiles_x;
@@ -751,8 +751,18 @@ __global__ __launch_bounds__(WM* WN * 64) void k_sep(SepArgs fa, SepArgs fb, int
         constexpr int Q = DlShape<WM, WN, TM, TN, X3, D3 ? ZS : 0>::STAGE_B / 16;
         __shared__ uint4 lds0[Q];
         __shared__ uint4 lds1[Q];
+        int64_t s0 = 0, s1 = fa.ldp / kJC;
+        if (a.partial) {
+            // mode split: this slice's stage pairs, raw sums into the slice's plane of partial
+            s0 = static_cast<int64_t>(blockIdx.y) * 2 * fa.pairs;
+            s1 = min(s1, s0 + 2 * fa.pairs);
+            a.y = a.partial + static_cast<int64_t>(blockIdx.y) * (fa.nx * fa.ny * fa.nz);
+            a.k = nullptr;
+            a.ind = nullptr;
+            a.amp = 1.f;
+        }
         sep_tile_dl<WM, WN, TM, TN, slices_per_block<WM, WN, TM, TN, ZS, BF, X3, D3>(), BF, X3, D3>(
-            a, fa.epi, bid % tiles_x, rest % tiles_y, rest / tiles_y, lds0, lds1);
+            a, fa.epi, bid % tiles_x, rest % tiles_y, rest / tiles_y, lds0, lds1, s0, s1);
     } else {
         __shared__ uint4 smem[SepShape<WM, WN, TM, TN, X3>::LDS_WORDS / 4];
         sep_tile_reg<WM, WN, TM, TN, BF, X3, D3>(a, fa.epi, bid % tiles_x, rest % tiles_y, rest / tiles_y, smem);
@@ -989,12 +999,13 @@ __global__ __launch_bounds__(256, GEN ? 2 : 1) void k_sep_batch(const SepBatchIt
             if (b.variant == 0) sep_tile_gen<2, 2, BF>(b.a, b.g, local % b.tiles_x, rest, lds0, lds1);
             else sep_tile_gen<1, 1, BF>(b.a, b.g, local % b.tiles_x, rest, lds0, lds1);
         } else if constexpr (DL) {
+            const int64_t ns = b.a.ldp / kJC;
             if (b.variant == 0)
                 sep_tile_dl<2, 2, 2, 2, 1, BF, X3, D3>(b.a, b.a.epi, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0,
-                                                       lds1);
+                                                       lds1, 0, ns);
             else
                 sep_tile_dl<2, 2, 1, 1, 1, BF, X3, D3>(b.a, b.a.epi, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0,
-                                                       lds1);
+                                                       lds1, 0, ns);
         } else {
             if (b.variant == 0)
                 sep_tile_reg<2, 2, 2, 2, BF, X3, D3>(b.a, b.a.epi, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0);
@@ -1042,9 +1053,12 @@ hipError_t launch_k(const SepArgs& a, const SepArgs* b, hipStream_t s)
     const int tiles_y = static_cast<int>((a.ny + BM - 1) / BM);
     const int64_t blocks = static_cast<int64_t>(tiles_x) * tiles_y * ((a.nz + zs - 1) / zs);
     if (2 * blocks > 0x7fffffff) return hipErrorInvalidValue;
-    const dim3 grid(static_cast<unsigned>(b ? 2 * blocks : blocks)), block(WM * WN * 64);
+    const bool split = a.partial != nullptr;
+    if (split && !use_dl<WM, WN, TM, TN, ZS, BF, X3, D3>()) return hipErrorInvalidValue;  // direct-to-LDS forms only
+    const dim3 grid(static_cast<unsigned>(b ? 2 * blocks : blocks), static_cast<unsigned>(split ? a.slices : 1)),
+        block(WM * WN * 64);
     hipEvent_t t0 = nullptr, t1 = nullptr;
-    if (a.timed && timer_take_pair(&t0, &t1))  // start/stop stamped on the dispatch itself
+    if (a.timed && !split && timer_take_pair(&t0, &t1))  // start/stop stamped on the dispatch itself
         hipExtLaunchKernelGGL((k_sep<WM, WN, TM, TN, ZS, BF, X3, D3>), grid, block, 0, s, t0, t1, 0u, a, b ? *b : a,
                               tiles_x, tiles_y, static_cast<int>(blocks));
     else
@@ -1127,6 +1141,29 @@ int sep_default_tile(int method, int64_t nx, int64_t ny, int64_t nz)
     return 2;
 }
 
+int sep_mode_slices(int method, int dim, int64_t nx, int64_t ny, int64_t nz, int64_t ldp, int64_t* pairs)
+{
+    // Direct-to-LDS one-pass forms whose default tiling gives fewer blocks than CUs: the modes
+    // split into slices of at least two stage pairs (128 modes) so that the launch has about two
+    // blocks per CU; the slices' sums (at most 32 MiB) are added by a second pass.
+    constexpr int64_t kCUs = 256, kMaxBytes = int64_t(32) << 20;
+    const int64_t np = ldp / (2 * kJC);
+    *pairs = np;
+    if (method != GRF_SEP_F16 && !(method == GRF_SEP_BF16 && dim == 2)) return 1;
+    const int tile = sep_default_tile(method, nx, ny, nz);
+    const int zs = dim == 3 ? sep_tile_slices(tile, method, true) : 1;
+    const int64_t blocks = ((nx + kTiles[tile].bn - 1) / kTiles[tile].bn) * ((ny + kTiles[tile].bm - 1) / kTiles[tile].bm) *
+                           ((nz + zs - 1) / zs);
+    const int64_t cells = nx * ny * nz;
+    if (blocks >= kCUs || np < 4) return 1;
+    int64_t sl = std::min<int64_t>((2 * kCUs + blocks - 1) / blocks, np / 2);
+    sl = std::min<int64_t>(sl, kMaxBytes / (4 * cells));
+    if (sl < 2) return 1;
+    const int64_t per = (np + sl - 1) / sl;
+    *pairs = per;
+    return static_cast<int>((np + per - 1) / per);
+}
+
 hipError_t launch_sep_batch(int method, bool d3, const SepBatchItem* items, int n_inst, const BatchQueue* queues,
                             int nq, unsigned long long* counters, int grid, hipStream_t s)
 {
@@ -1168,13 +1205,24 @@ hipError_t launch_sep_pair(const SepArgs& a, const SepArgs* b, hipStream_t s)
     if (b && (b->method != a.method || b->nx != a.nx || b->ny != a.ny || b->nz != a.nz || b->ldp != a.ldp ||
               (b->ez == nullptr) != (a.ez == nullptr)))
         return hipErrorInvalidValue;
+    const bool split = a.partial != nullptr;
+    if (split && (a.tile >= 0 || a.slices < 1 || a.pairs < 1 || (b && b->partial == nullptr) ||
+                  static_cast<int64_t>(a.slices) * a.pairs * 2 * kJC < a.ldp))
+        return hipErrorInvalidValue;
+    TimedScope timed(s, split && a.timed);  // the contraction and the slice sums
+    hipError_t e;
     switch (a.method) {
-    case GRF_SEP_BF16: return launch_d<true, false>(a, b, tile, s);
-    case GRF_SEP_F16: return launch_d<false, false>(a, b, tile, s);
-    case GRF_SEP_BF16_X3: return launch_d<true, true>(a, b, tile, s);
-    case GRF_SEP_F16_X3: return launch_d<false, true>(a, b, tile, s);
+    case GRF_SEP_BF16: e = launch_d<true, false>(a, b, tile, s); break;
+    case GRF_SEP_F16: e = launch_d<false, false>(a, b, tile, s); break;
+    case GRF_SEP_BF16_X3: e = launch_d<true, true>(a, b, tile, s); break;
+    case GRF_SEP_F16_X3: e = launch_d<false, true>(a, b, tile, s); break;
     default: return hipErrorInvalidValue;
     }
+    if (e != hipSuccess || !split) return e;
+    const int64_t C = a.nx * a.ny * a.nz;
+    e = launch_points_reduce(a.partial, a.slices, C, a.amp, a.epi, a.y, a.k, a.ind, s);
+    if (e == hipSuccess && b) e = launch_points_reduce(b->partial, a.slices, C, b->amp, a.epi, b->y, b->k, b->ind, s);
+    return e;
 }
 
 }  // namespace grf
