@@ -181,7 +181,8 @@ int make_modes_lattice(const grf_spec* spec, int32_t m, double du, double* z_out
 int snap_periodic(int dim, int64_t n, const double* z, const double* ell, const double* rot, const double* period,
                   double* z_out);
 
-/* Device workspace (bytes) that eval_field_grid needs for this problem and method. */
+/* Device workspace (bytes) that eval_field_grid takes for this problem and method, including
+ * the sums of the separable mode split where it applies (see eval_field_grid). */
 int eval_field_grid_ws_size(const grf_modes* modes, const grf_grid* grid, int method, size_t* bytes);
 
 /*
@@ -191,10 +192,16 @@ int eval_field_grid_ws_size(const grf_modes* modes, const grf_grid* grid, int me
  *   y, k              device float[C] or NULL; ind device uint8[C] or NULL (C = cells).
  *                     At least one output must be non-NULL.  epi may be NULL when
  *                     k and ind are NULL.
- *   ws, ws_bytes      device workspace of at least eval_field_grid_ws_size bytes
- *                     (GRF_ENOMEM otherwise): the per-axis tables and, for DIRECT_F64 on
- *                     grids too small to fill the device (under 131,072 cells), the FP64
- *                     partial sums of its mode slices; contents on entry are ignored.
+ *   ws, ws_bytes      device workspace of eval_field_grid_ws_size bytes: the per-axis
+ *                     tables; for DIRECT_F64 on grids too small to fill the device (under
+ *                     131,072 cells) the FP64 partial sums of its mode slices; for GRF_SEP_F16
+ *                     (and 2-D GRF_SEP_BF16) on grids of fewer default tiles than the device
+ *                     has CUs, the FP32 sums of the mode slices that the contraction is split
+ *                     into (at most 32 MiB; the slices are added in order by a second pass
+ *                     that applies the epilogue).  A workspace smaller than that but large
+ *                     enough for the tables runs the contraction unsplit (the same field up
+ *                     to FP32 summation order); below that GRF_ENOMEM.  Contents on entry
+ *                     are ignored.
  * Separable methods require dim 3 grids with nx, ny >= 1 (any size; ragged tiles
  * are masked) or dim 2 grids.  Phases are range-reduced per axis in FP64.
  */
@@ -208,8 +215,8 @@ int eval_field_grid(const grf_modes* modes, const grf_grid* grid, int method, co
  * GRF_NOALLOC_SCRATCH_BYTES that the library holds on each device it runs on until the
  * process ends, instead of a caller workspace.
  *   Arguments as eval_field_grid without ws / ws_bytes; outputs are still the caller's.
- *   A problem whose workspace (eval_field_grid_ws_size) exceeds the scratch size is
- *   GRF_ENOMEM, with nothing enqueued.  Allocates nothing (no hipMalloc, hipFree or
+ *   A problem whose tables exceed the scratch size is GRF_ENOMEM, with nothing enqueued;
+ *   the separable mode split is taken when its sums fit as well.  Allocates nothing (no hipMalloc, hipFree or
  *   allocating library call); the first call on a device looks up that device's copy.
  * Every call on one device shares that device's array: calls that overlap on one GPU (other
  * streams or threads, before the previous call's kernels have finished) race on it.  Calls
@@ -223,8 +230,9 @@ int eval_field_grid_noalloc(const grf_modes* modes, const grf_grid* grid, int me
  * eval_field_grid_tile -- eval_field_grid with an explicit tile shape for the separable
  * methods (tuning and tests).  tile = -1 is the size-based default (what eval_field_grid
  * uses); 0 .. grf_sep_tile_count()-1 selects a shape.  Any selector gives the same field up
- * to the rounding of the fp16/bf16 operands' FP32 accumulation order.  A selector >= 0 with
- * a direct method, or one out of range, is GRF_EINVAL.  Other arguments as eval_field_grid.
+ * to the rounding of the fp16/bf16 operands' FP32 accumulation order.  A selector >= 0 runs
+ * unsplit (no mode split).  A selector >= 0 with a direct method, or one out of range, is
+ * GRF_EINVAL.  Other arguments as eval_field_grid.
  */
 int eval_field_grid_tile(const grf_modes* modes, const grf_grid* grid, int method, int tile, const grf_epi* epi,
                          float* y, float* k, uint8_t* ind, void* ws, size_t ws_bytes, void* stream);

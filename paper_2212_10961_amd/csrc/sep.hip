@@ -1098,6 +1098,34 @@ int slices_t(int tile)
     }
 }
 
+// Whether tile selector `tile` stages directly into LDS (mirrors launch_t).
+template <bool BF, bool X3, bool D3>
+bool dl_t(int tile)
+{
+    switch (tile) {
+    case 0: return use_dl<2, 4, 4, 2, 1, BF, X3, D3>();
+    case 1: return use_dl<2, 2, 2, 2, 1, BF, X3, D3>();
+    case 2: return use_dl<2, 2, 1, 1, 1, BF, X3, D3>();
+    case 3: return use_dl<2, 4, 2, 2, 1, BF, X3, D3>();
+    case 4: return D3 ? use_dl<2, 4, 2, 2, 2, BF, X3, D3>() : use_dl<2, 4, 2, 2, 1, BF, X3, D3>();
+    case 5: return D3 ? use_dl<2, 2, 2, 2, 2, BF, X3, D3>() : use_dl<2, 2, 2, 2, 1, BF, X3, D3>();
+    case 6: return use_dl<1, 8, 4, 1, 2, BF, X3, D3>();
+    case 7: return use_dl<2, 4, 4, 1, 2, BF, X3, D3>();
+    case 8: return use_dl<2, 2, 4, 2, 2, BF, X3, D3>();
+    default: return use_dl<2, 2, 4, 4, 1, BF, X3, D3>();
+    }
+}
+
+bool sep_tile_direct(int tile, int method, bool d3)
+{
+    switch (method) {
+    case GRF_SEP_BF16: return d3 ? dl_t<true, false, true>(tile) : dl_t<true, false, false>(tile);
+    case GRF_SEP_F16: return d3 ? dl_t<false, false, true>(tile) : dl_t<false, false, false>(tile);
+    case GRF_SEP_BF16_X3: return d3 ? dl_t<true, true, true>(tile) : dl_t<true, true, false>(tile);
+    default: return d3 ? dl_t<false, true, true>(tile) : dl_t<false, true, false>(tile);
+    }
+}
+
 template <bool BF, bool X3>
 hipError_t launch_d(const SepArgs& a, const SepArgs* b, int tile, hipStream_t s)
 {
@@ -1143,14 +1171,15 @@ int sep_default_tile(int method, int64_t nx, int64_t ny, int64_t nz)
 
 int sep_mode_slices(int method, int dim, int64_t nx, int64_t ny, int64_t nz, int64_t ldp, int64_t* pairs)
 {
-    // Direct-to-LDS one-pass forms whose default tiling gives fewer blocks than CUs: the modes
-    // split into slices of at least two stage pairs (128 modes) so that the launch has about two
+    // Default tiles that stage directly into LDS and give fewer blocks than CUs: the modes split
+    // into slices of at least two stage pairs (128 modes) so that the launch has about two
     // blocks per CU; the slices' sums (at most 32 MiB) are added by a second pass.
     constexpr int64_t kCUs = 256, kMaxBytes = int64_t(32) << 20;
     const int64_t np = ldp / (2 * kJC);
     *pairs = np;
-    if (method != GRF_SEP_F16 && !(method == GRF_SEP_BF16 && dim == 2)) return 1;
+    if (method < GRF_SEP_BF16 || method > GRF_SEP_F16_X3) return 1;
     const int tile = sep_default_tile(method, nx, ny, nz);
+    if (!sep_tile_direct(tile, method, dim == 3)) return 1;
     const int zs = dim == 3 ? sep_tile_slices(tile, method, true) : 1;
     const int64_t blocks = ((nx + kTiles[tile].bn - 1) / kTiles[tile].bn) * ((ny + kTiles[tile].bm - 1) / kTiles[tile].bm) *
                            ((nz + zs - 1) / zs);

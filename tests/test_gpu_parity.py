@@ -4,6 +4,7 @@ Each side draws its own mode table from the same seed (library sampler vs oracle
 sampler); all other inputs come from paper_2212_10961_amd.workloads.  Tolerances are
 stated in tests/gpu_common.py.
 """
+import ctypes
 import math
 
 import numpy as np
@@ -316,3 +317,57 @@ def test_lognormal_store_matches_exp_of_y(grf, meth, shape):
         both = grf.field_grid(m, shape, method=meth, mu=mu, want_y=True, want_k=True)
         np.testing.assert_array_equal(to_np(both["y"]), y)
         assert np.max(np.abs(to_np(both["k"]).astype(np.float64) - want) / want) <= 3e-7
+
+
+@pytest.mark.parametrize("meth,shape,n", [("sep_f16", (96, 80, 7), 1000), ("sep_f16", (300, 200), 2048),
+                                          ("sep_bf16", (512, 384), 256), ("sep_f16", (33, 20, 3), 300),
+                                          ("sep_f16_x3", (300, 200), 2048), ("sep_bf16_x3", (100, 70), 700)])
+def test_mode_split_matches_unsplit(orc, grf, meth, shape, n):
+    """Grids of fewer tiles than CUs split the modes over slices (default tile, forms that stage
+    straight into LDS: every 2-D form, the one-pass fp16 3-D form); the same tile chosen
+    explicitly runs unsplit.  Both against the oracle, with K and facies, and within the
+    method's rounding of each other."""
+    _say(f"case mode split {meth} {shape} N={n}")
+    dim = len(shape)
+    ell = (9.0, 7.0, 3.0)[:dim]
+    (zo, po), m = modes_pair(orc, grf, dim, wl.EXPONENTIAL, n, 1510 + n, 1.2, ell)
+    ref = orc.field_grid(zo, po, 1.2, ell, shape)
+    kw = dict(method=meth, mu=0.3, thresholds=[-0.5, 0.4], want_k=True, want_ind=True)
+    split = grf.field_grid(m, shape, **kw)
+    unsplit = grf.field_grid(m, shape, tile=2, **kw)  # the default tile of these grids, selected
+    for o, label in ((split, "split"), (unsplit, "unsplit")):
+        y = to_np(o["y"])
+        assert_field(y, ref, 1.2, meth, f"{label} {shape}")
+        assert_indicator(to_np(o["ind"]), ref, [-0.5, 0.4], 1.2, meth)
+        kref = orc.lognormal(ref, 0.3)
+        assert np.max(np.abs(to_np(o["k"]) - kref) / kref) <= 1.2 * TOL[meth]["band"] * 1.2 + 1e-6
+    rel, _ = errors(to_np(split["y"]), to_np(unsplit["y"]))
+    assert rel <= 1e-5, rel  # FP32 accumulation order only
+
+
+def test_mode_split_needs_its_workspace(orc, grf):
+    """A workspace with room for the tables only runs the unsplit contraction (same values as the
+    explicit tile); the full workspace takes the split."""
+    shape, n = (150, 97, 21), 700
+    _say(f"case mode split workspace {shape}")
+    (zo, po), m = modes_pair(orc, grf, 3, wl.EXPONENTIAL, n, 1520, 1.0, (9.0, 7.0, 3.0))
+    full = grf.grid_workspace_bytes(m, shape, "sep_f16")
+    C = int(np.prod(shape))
+    slices_bytes = 4 * C * 2  # at least two slices of sums when split
+    small = torch.empty(full - slices_bytes, dtype=torch.uint8, device="cuda")
+    ya = torch.empty(C, device="cuda")
+    from paper_2212_10961_amd import _lib as L
+    lib = L.load()
+    mc, gc, ec = m.c(), grf._grid(shape), grf._epi(None, None)
+    assert lib.eval_field_grid(ctypes.byref(mc), ctypes.byref(gc), L.GRF_SEP_F16, ctypes.byref(ec),
+                               ctypes.c_void_p(ya.data_ptr()), None, None, ctypes.c_void_p(small.data_ptr()),
+                               small.numel(), None) == 0
+    torch.cuda.synchronize()
+    a = to_np(ya)
+    b = to_np(grf.field_grid(m, shape, method="sep_f16", tile=2)["y"])
+    np.testing.assert_array_equal(a, b)
+    c = to_np(grf.field_grid(m, shape, method="sep_f16")["y"])
+    cells = wl.sample_cells(C, 2000, 1521)
+    ref = orc.field_cells(zo, po, 1.0, (9.0, 7.0, 3.0), shape, cells)
+    assert_field(c[cells], ref, 1.0, "sep_f16", "split")
+    assert_field(a[cells], ref, 1.0, "sep_f16", "unsplit")
