@@ -194,8 +194,8 @@ int eval_field_grid_ws_size(const grf_modes* modes, const grf_grid* grid, int me
  *                     k and ind are NULL.
  *   ws, ws_bytes      device workspace of eval_field_grid_ws_size bytes: the per-axis
  *                     tables; for DIRECT_F64 on grids too small to fill the device (under
- *                     131,072 cells) the FP64 partial sums of its mode slices; for GRF_SEP_F16
- *                     (and 2-D GRF_SEP_BF16) on grids of fewer default tiles than the device
+ *                     131,072 cells) the FP64 partial sums of its mode slices; for the
+ *                     separable methods on grids of fewer default tiles than the device
  *                     has CUs, the FP32 sums of the mode slices that the contraction is split
  *                     into (at most 32 MiB; the slices are added in order by a second pass
  *                     that applies the epilogue).  A workspace smaller than that but large

@@ -291,7 +291,7 @@ struct SepArgs {
     uint8_t* ind;
     int tile;              // < 0: size-based default; else tile selector (see sep.hip)
     bool timed = false;    // the call's main kernel: timed by the kernel timer when it is on
-    // Mode split (default tile, one-pass forms, grids of few blocks): blockIdx.y = slice sums
+    // Mode split (default tile, grids of fewer blocks than CUs): blockIdx.y = slice sums
     // stage pairs [slice pairs, (slice + 1) pairs) into partial[slice][nx ny nz]; a second
     // pass adds the slices in order and applies amp and the epilogue.  nullptr: no split.
     float* partial = nullptr;

@@ -169,7 +169,7 @@ struct SepShape {
 // `smem` must hold SepShape<...>::LDS_WORDS words.  Called by whole blocks.
 template <int WM, int WN, int TM, int TN, bool BF, bool X3, bool D3>
 __device__ __forceinline__ void sep_tile_reg(const SepArgs& a, const Epi& epi, int64_t tx, int64_t ty, int64_t z0,
-                                             uint4* smem)
+                                             uint4* smem, int64_t s0, int64_t s1)
 {
     using S = SepShape<WM, WN, TM, TN, X3>;
     constexpr int NT = S::NT, BM = S::BM, BN = S::BN, NB = S::NB, STAGE_W = S::STAGE_W, NBUF = S::NBUF;
@@ -341,15 +341,15 @@ __device__ __forceinline__ void sep_tile_reg(const SepArgs& a, const Epi& epi, i
     };
 
     uint32_t* sbase = reinterpret_cast<uint32_t*>(smem);
-    load(0);
+    load(s0 * kJC);
     store(sbase);
     __syncthreads();
-    const int64_t nstage = ldp / kJC;
-    // Loads and stores are unconditional (the last iteration re-stages the last stage into
-    // the idle buffer) so that the prefetch registers stay in registers.
-    for (int64_t s = 0; s < nstage; ++s) {
+    // Stages [s0, s1), s0 even.  Loads and stores are unconditional (the last iteration
+    // re-stages the last stage into the idle buffer) so that the prefetch registers stay in
+    // registers.
+    for (int64_t s = s0; s < s1; ++s) {
         uint32_t* cur = sbase + (NBUF == 2 ? (s & 1) * STAGE_W : 0);
-        load(min(s + 1, nstage - 1) * kJC);
+        load(min(s + 1, s1 - 1) * kJC);
         compute(cur);
         if constexpr (NBUF == 1) __syncthreads();
         store(sbase + (NBUF == 2 ? ((s + 1) & 1) * STAGE_W : 0));
@@ -747,25 +747,26 @@ __global__ __launch_bounds__(WM* WN * 64) void k_sep(SepArgs fa, SepArgs fb, int
     }
     const int64_t bid = second ? blockIdx.x - per_field : blockIdx.x;
     const int64_t rest = bid / tiles_x;
+    int64_t s0 = 0, s1 = fa.ldp / kJC;
+    if (a.partial) {
+        // mode split: this slice's stage pairs, raw sums into the slice's plane of partial
+        s0 = static_cast<int64_t>(blockIdx.y) * 2 * fa.pairs;
+        s1 = min(s1, s0 + 2 * fa.pairs);
+        a.y = a.partial + static_cast<int64_t>(blockIdx.y) * (fa.nx * fa.ny * fa.nz);
+        a.k = nullptr;
+        a.ind = nullptr;
+        a.amp = 1.f;
+    }
     if constexpr (use_dl<WM, WN, TM, TN, ZS, BF, X3, D3>()) {
         constexpr int Q = DlShape<WM, WN, TM, TN, X3, D3 ? ZS : 0>::STAGE_B / 16;
         __shared__ uint4 lds0[Q];
         __shared__ uint4 lds1[Q];
-        int64_t s0 = 0, s1 = fa.ldp / kJC;
-        if (a.partial) {
-            // mode split: this slice's stage pairs, raw sums into the slice's plane of partial
-            s0 = static_cast<int64_t>(blockIdx.y) * 2 * fa.pairs;
-            s1 = min(s1, s0 + 2 * fa.pairs);
-            a.y = a.partial + static_cast<int64_t>(blockIdx.y) * (fa.nx * fa.ny * fa.nz);
-            a.k = nullptr;
-            a.ind = nullptr;
-            a.amp = 1.f;
-        }
         sep_tile_dl<WM, WN, TM, TN, slices_per_block<WM, WN, TM, TN, ZS, BF, X3, D3>(), BF, X3, D3>(
             a, fa.epi, bid % tiles_x, rest % tiles_y, rest / tiles_y, lds0, lds1, s0, s1);
     } else {
         __shared__ uint4 smem[SepShape<WM, WN, TM, TN, X3>::LDS_WORDS / 4];
-        sep_tile_reg<WM, WN, TM, TN, BF, X3, D3>(a, fa.epi, bid % tiles_x, rest % tiles_y, rest / tiles_y, smem);
+        sep_tile_reg<WM, WN, TM, TN, BF, X3, D3>(a, fa.epi, bid % tiles_x, rest % tiles_y, rest / tiles_y, smem, s0,
+                                                 s1);
     }
 }
 
@@ -1008,9 +1009,11 @@ __global__ __launch_bounds__(256, GEN ? 2 : 1) void k_sep_batch(const SepBatchIt
                                                        lds1, 0, ns);
         } else {
             if (b.variant == 0)
-                sep_tile_reg<2, 2, 2, 2, BF, X3, D3>(b.a, b.a.epi, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0);
+                sep_tile_reg<2, 2, 2, 2, BF, X3, D3>(b.a, b.a.epi, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0,
+                                                     0, b.a.ldp / kJC);
             else
-                sep_tile_reg<2, 2, 1, 1, BF, X3, D3>(b.a, b.a.epi, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0);
+                sep_tile_reg<2, 2, 1, 1, BF, X3, D3>(b.a, b.a.epi, local % b.tiles_x, rest % b.tiles_y, rest / b.tiles_y, lds0,
+                                                     0, b.a.ldp / kJC);
         }
     }
 }
@@ -1054,7 +1057,6 @@ hipError_t launch_k(const SepArgs& a, const SepArgs* b, hipStream_t s)
     const int64_t blocks = static_cast<int64_t>(tiles_x) * tiles_y * ((a.nz + zs - 1) / zs);
     if (2 * blocks > 0x7fffffff) return hipErrorInvalidValue;
     const bool split = a.partial != nullptr;
-    if (split && !use_dl<WM, WN, TM, TN, ZS, BF, X3, D3>()) return hipErrorInvalidValue;  // direct-to-LDS forms only
     const dim3 grid(static_cast<unsigned>(b ? 2 * blocks : blocks), static_cast<unsigned>(split ? a.slices : 1)),
         block(WM * WN * 64);
     hipEvent_t t0 = nullptr, t1 = nullptr;
@@ -1095,34 +1097,6 @@ int slices_t(int tile)
     case 7: return slices_per_block<2, 4, 4, 1, 2, BF, X3, D3>();
     case 8: return slices_per_block<2, 2, 4, 2, 2, BF, X3, D3>();
     default: return 1;
-    }
-}
-
-// Whether tile selector `tile` stages directly into LDS (mirrors launch_t).
-template <bool BF, bool X3, bool D3>
-bool dl_t(int tile)
-{
-    switch (tile) {
-    case 0: return use_dl<2, 4, 4, 2, 1, BF, X3, D3>();
-    case 1: return use_dl<2, 2, 2, 2, 1, BF, X3, D3>();
-    case 2: return use_dl<2, 2, 1, 1, 1, BF, X3, D3>();
-    case 3: return use_dl<2, 4, 2, 2, 1, BF, X3, D3>();
-    case 4: return D3 ? use_dl<2, 4, 2, 2, 2, BF, X3, D3>() : use_dl<2, 4, 2, 2, 1, BF, X3, D3>();
-    case 5: return D3 ? use_dl<2, 2, 2, 2, 2, BF, X3, D3>() : use_dl<2, 2, 2, 2, 1, BF, X3, D3>();
-    case 6: return use_dl<1, 8, 4, 1, 2, BF, X3, D3>();
-    case 7: return use_dl<2, 4, 4, 1, 2, BF, X3, D3>();
-    case 8: return use_dl<2, 2, 4, 2, 2, BF, X3, D3>();
-    default: return use_dl<2, 2, 4, 4, 1, BF, X3, D3>();
-    }
-}
-
-bool sep_tile_direct(int tile, int method, bool d3)
-{
-    switch (method) {
-    case GRF_SEP_BF16: return d3 ? dl_t<true, false, true>(tile) : dl_t<true, false, false>(tile);
-    case GRF_SEP_F16: return d3 ? dl_t<false, false, true>(tile) : dl_t<false, false, false>(tile);
-    case GRF_SEP_BF16_X3: return d3 ? dl_t<true, true, true>(tile) : dl_t<true, true, false>(tile);
-    default: return d3 ? dl_t<false, true, true>(tile) : dl_t<false, true, false>(tile);
     }
 }
 
@@ -1171,15 +1145,14 @@ int sep_default_tile(int method, int64_t nx, int64_t ny, int64_t nz)
 
 int sep_mode_slices(int method, int dim, int64_t nx, int64_t ny, int64_t nz, int64_t ldp, int64_t* pairs)
 {
-    // Default tiles that stage directly into LDS and give fewer blocks than CUs: the modes split
-    // into slices of at least two stage pairs (128 modes) so that the launch has about two
-    // blocks per CU; the slices' sums (at most 32 MiB) are added by a second pass.
+    // Default tiles that give fewer blocks than CUs: the modes split into slices of at least two
+    // stage pairs (128 modes) so that the launch has about two blocks per CU; the slices' sums
+    // (at most 32 MiB) are added by a second pass.
     constexpr int64_t kCUs = 256, kMaxBytes = int64_t(32) << 20;
     const int64_t np = ldp / (2 * kJC);
     *pairs = np;
     if (method < GRF_SEP_BF16 || method > GRF_SEP_F16_X3) return 1;
     const int tile = sep_default_tile(method, nx, ny, nz);
-    if (!sep_tile_direct(tile, method, dim == 3)) return 1;
     const int zs = dim == 3 ? sep_tile_slices(tile, method, true) : 1;
     const int64_t blocks = ((nx + kTiles[tile].bn - 1) / kTiles[tile].bn) * ((ny + kTiles[tile].bm - 1) / kTiles[tile].bm) *
                            ((nz + zs - 1) / zs);

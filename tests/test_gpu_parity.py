@@ -321,11 +321,12 @@ def test_lognormal_store_matches_exp_of_y(grf, meth, shape):
 
 @pytest.mark.parametrize("meth,shape,n", [("sep_f16", (96, 80, 7), 1000), ("sep_f16", (300, 200), 2048),
                                           ("sep_bf16", (512, 384), 256), ("sep_f16", (33, 20, 3), 300),
-                                          ("sep_f16_x3", (300, 200), 2048), ("sep_bf16_x3", (100, 70), 700)])
+                                          ("sep_f16_x3", (300, 200), 2048), ("sep_bf16_x3", (100, 70), 700),
+                                          ("sep_f16_x3", (96, 80, 7), 1000), ("sep_bf16", (96, 80, 7), 1000)])
 def test_mode_split_matches_unsplit(orc, grf, meth, shape, n):
-    """Grids of fewer tiles than CUs split the modes over slices (default tile, forms that stage
-    straight into LDS: every 2-D form, the one-pass fp16 3-D form); the same tile chosen
-    explicitly runs unsplit.  Both against the oracle, with K and facies, and within the
+    """Grids of fewer tiles than CUs split the modes over slices (default tile; both the forms
+    that stage straight into LDS and the 3-D forms that stage through registers); the same tile
+    chosen explicitly runs unsplit.  Both against the oracle, with K and facies, and within the
     method's rounding of each other."""
     _say(f"case mode split {meth} {shape} N={n}")
     dim = len(shape)
