@@ -254,11 +254,33 @@ __global__ __launch_bounds__(256) void k_direct_grid_f64(const double* __restric
     const int j0 = static_cast<int>(blockIdx.y) * mslice;
     const int j1 = min(n, j0 + mslice);
     double s = 0.0;
-    for (int j = j0; j < j1; ++j) {
-        double f = rx[j] + ry[j] + rz[j];
+    auto term = [&](double fx, double fy, double fz, double wj) {
+        double f = fx + fy + fz;
         f = __builtin_amdgcn_fract(f);  // x - floor(x) in one FP64 instruction
-        s += (wt ? wt[j] : 1.0) * cospi(2.0 * f);
+        s += wj * cospi(2.0 * f);
+    };
+    // Eight modes' table entries are loaded ahead of their terms; the sum keeps mode order.
+    constexpr int kMG = 8;
+    int j = j0;
+    for (; j + kMG <= j1; j += kMG) {
+        double fx[kMG], fy[kMG], fz[kMG], ww[kMG];
+#pragma unroll
+        for (int u = 0; u < kMG; ++u) {
+            fx[u] = rx[j + u];
+            fy[u] = ry[j + u];
+            fz[u] = rz[j + u];
+        }
+        if (wt) {
+#pragma unroll
+            for (int u = 0; u < kMG; ++u) ww[u] = wt[j + u];
+        } else {
+#pragma unroll
+            for (int u = 0; u < kMG; ++u) ww[u] = 1.0;
+        }
+#pragma unroll
+        for (int u = 0; u < kMG; ++u) term(fx[u], fy[u], fz[u], ww[u]);
     }
+    for (; j < j1; ++j) term(rx[j], ry[j], rz[j], wt ? wt[j] : 1.0);
     if (partial) {
         partial[static_cast<int64_t>(blockIdx.y) * C + c] = s;
         return;
