@@ -354,6 +354,16 @@ int field_backward(const grf_modes* modes, const double* xyz, int64_t n_points, 
                    const float* y_saved, float* grad_phi, float* grad_k, float* grad_sigma,
                    float* grad_ell, void* ws, size_t ws_bytes, void* stream);
 
+/*
+ * grad_z_from_k -- the chain rule from the wavevector gradient to the standard draws z of the
+ * table, k_j = rot diag(1/ell) z_j (Sec. 4.1; rot = identity for axis-aligned tables):
+ *   grad_z[b*n + j] = (1/ell_b) sum_a rot[a][b] grad_k[a*n + j]   (FP64 sum, FP32 result).
+ *   modes    as for field_backward (dim, n, ell, rot / rotated are read).
+ *   grad_k   device float[dim][n] (field_backward's grad_k); grad_z device float[dim][n],
+ *            overwritten, not aliasing grad_k (GRF_EINVAL).  n = 0: nothing is enqueued.
+ */
+int grad_z_from_k(const grf_modes* modes, const float* grad_k, float* grad_z, void* stream);
+
 /* The same gradients for a dense dL/dY over every cell of a structured grid.
  * grad_y device float[C] (x fastest). */
 int field_backward_grid_ws_size(const grf_modes* modes, const grf_grid* grid, size_t* bytes);

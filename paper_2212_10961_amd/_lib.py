@@ -35,7 +35,7 @@ EXPORTS = [
     "krige_weights_ws_size", "krige_weights", "krige_apply_ws_size", "krige_apply_grid", "krige_apply_points",
     "eval_field_grid_f64", "eval_field_points_ws_size", "eval_field_points", "epilogue_apply",
     "field_backward_ws_size", "field_backward", "field_backward_grid_ws_size", "field_backward_grid",
-    "field_backward_grid_method",
+    "field_backward_grid_method", "grad_z_from_k",
     "grf_plan_create", "grf_plan_destroy", "eval_field_batch", "grf_plan_info",
     "grf_kernel_timer_enable", "grf_kernel_timer_read", "eval_field_grid_noalloc",
 ]
@@ -137,6 +137,7 @@ def load():
         "field_backward_grid": ([P(GrfModes), P(GrfGrid), vp, vp, vp, vp, vp, vp, vp, sz, vp], ctypes.c_int),
         "field_backward_grid_method": ([P(GrfModes), P(GrfGrid), ctypes.c_int, vp, vp, vp, vp, vp, vp, vp, sz, vp],
                                        ctypes.c_int),
+        "grad_z_from_k": ([P(GrfModes), vp, vp, vp], ctypes.c_int),
         "grf_plan_create": ([P(vp), ctypes.c_int, ctypes.c_int, ctypes.c_char_p], ctypes.c_int),
         "grf_plan_destroy": ([vp], ctypes.c_int),
         "eval_field_batch": ([vp, P(GrfBatchItem), i32, vp], ctypes.c_int),

@@ -182,6 +182,20 @@ __global__ __launch_bounds__(256) void k_bwd_reduce(const float* __restrict__ pa
     }
 }
 
+// dL/dz of a table whose wavevectors are k_j = rot diag(1/ell) z_j, from dL/dk:
+// grad_z[b n + j] = (1/ell_b) sum_a rot_ab grad_k[a n + j] (FP64 sum of the FP32 inputs).
+__global__ __launch_bounds__(256) void k_grad_z(const float* __restrict__ gk, int dim, int64_t n, EllMap em,
+                                               float* __restrict__ gz)
+{
+    const int64_t j = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    for (int b = 0; b < dim; ++b) {
+        double w = 0.0;
+        for (int a = 0; a < dim; ++a) w += static_cast<double>(gk[a * n + j]) * em.r[3 * a + b];
+        gz[b * n + j] = static_cast<float>(w / em.ell[b]);
+    }
+}
+
 // sum_p g_p y_p over chunks of the points (when Y was saved by the forward pass).
 __global__ __launch_bounds__(256) void k_dot_partial(const float* __restrict__ a, const float* __restrict__ b,
                                                     int64_t P, float* __restrict__ out)
@@ -675,6 +689,17 @@ hipError_t launch_backward(const BwdArgs& a, hipStream_t s)
     }
     hipLaunchKernelGGL(k_bwd_final, dim3(1), dim3(256), 0, s, a.scal_partial, nblk, a.dim, dotp, ndot, a.amp, a.sigma,
                        a.gsigma, a.gell);
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_z(const float* gk, int dim, int64_t n, const double* rot, const double* ell, float* gz,
+                         hipStream_t s)
+{
+    if (n <= 0) return hipSuccess;
+    EllMap em{};
+    for (int i = 0; i < 9; ++i) em.r[i] = rot ? rot[i] : (i % 4 == 0 ? 1.0 : 0.0);
+    for (int b = 0; b < 3; ++b) em.ell[b] = b < dim ? ell[b] : 1.0;
+    hipLaunchKernelGGL(k_grad_z, dim3(static_cast<unsigned>((n + 255) / 256)), dim3(256), 0, s, gk, dim, n, em, gz);
     return hipGetLastError();
 }
 

@@ -1090,6 +1090,17 @@ int field_backward(const grf_modes* modes, const double* xyz, int64_t n_points, 
                            grad_sigma, grad_ell, ws, ws_bytes, stream);
 }
 
+int grad_z_from_k(const grf_modes* modes, const float* grad_k, float* grad_z, void* stream)
+{
+    int rc = check_modes(modes, "grad_z_from_k");
+    if (rc) return rc;
+    if (modes->n > 0 && (!grad_k || !grad_z)) return fail(GRF_EINVAL, "grad_z_from_k: grad_k and grad_z are required");
+    if (modes->n > 0 && grad_k == grad_z) return fail(GRF_EINVAL, "grad_z_from_k: grad_z must not alias grad_k");
+    GRF_HIP(launch_grad_z(grad_k, modes->dim, modes->n, modes->rotated ? modes->rot : nullptr, modes->ell, grad_z,
+                          static_cast<hipStream_t>(stream)));
+    return GRF_OK;
+}
+
 int field_backward_grid_ws_size(const grf_modes* modes, const grf_grid* grid, size_t* bytes)
 {
     int rc;

@@ -176,6 +176,9 @@ struct GridWs {
     size_t bytes = 0;
 };
 GridWs grid_ws(const grf_modes* m, const grf_grid* g, int method, void* base);
+// grad_z[b n + j] = (1/ell_b) sum_a rot_ab grad_k[a n + j] (rot host row-major or nullptr = I).
+hipError_t launch_grad_z(const float* gk, int dim, int64_t n, const double* rot, const double* ell, float* gz,
+                         hipStream_t s);
 // Validated workspace bytes of a grid evaluation: all of it, and the least that it runs in (the
 // tables without the mode split's sums; the split is then not taken).
 int grid_ws_bytes(const char* fn, const grf_modes* modes, const grf_grid* grid, int method, size_t* bytes,

@@ -580,6 +580,16 @@ def field_backward_grid(modes: Modes, shape, grad_y: torch.Tensor, origin=None, 
     return o
 
 
+def grad_z_from_k(modes: Modes, grad_k: torch.Tensor, out: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+    """dL/dz of the table's standard draws from dL/dk (k = rot diag(1/ell) z), float32 [dim][n]."""
+    lib = L.load()
+    gk = grad_k.to(torch.float32).contiguous()
+    gz = out if out is not None else torch.empty_like(gk)
+    check(lib.grad_z_from_k(ctypes.byref(modes.c()), _ptr(gk), _ptr(gz), _stream(stream)))
+    return gz
+
+
 class GRFPoints(torch.autograd.Function):
     """Y at fixed points as a differentiable function of (phi, z, sigma, ell).
 
@@ -603,11 +613,7 @@ class GRFPoints(torch.autograd.Function):
         modes = Modes(z.detach().contiguous(), phi.detach().contiguous(), float(sigma),
                       [float(v) for v in ell.detach().cpu()], ctx.rot)
         g = field_backward(modes, xyz, gy.detach().to(torch.float32).contiguous(), y_saved=y)
-        ellv = ell.detach().to(torch.float64).reshape(-1, 1)
-        dk = g["dk"].to(torch.float64)
-        if ctx.rot is not None:  # k = rot diag(1/ell) z: dL/dz = diag(1/ell) rot^T dL/dk
-            dk = torch.as_tensor(ctx.rot, dtype=torch.float64, device=dk.device).T @ dk
-        dz = dk / ellv
+        dz = grad_z_from_k(modes, g["dk"])  # k = rot diag(1/ell) z: dL/dz = diag(1/ell) rot^T dL/dk
         return (g["dphi"].to(phi.dtype), dz.to(z.dtype), g["dsigma"].reshape(()).to(sigma.dtype),
                 g["dell"].to(ell.dtype), None, None)
 

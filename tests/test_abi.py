@@ -303,6 +303,11 @@ def test_epilogue_and_backward_validation(lib):
     assert lib.field_backward(ctypes.byref(m), ctypes.c_void_p(16), 1000, ctypes.c_void_p(16), None,
                               ctypes.c_void_p(16), None, None, None, ctypes.c_void_p(16), b.value - 1,
                               None) == L.GRF_ENOMEM
+    # chain rule dk -> dz: both arrays required, no aliasing (checked before any launch)
+    assert lib.grad_z_from_k(ctypes.byref(m), None, ctypes.c_void_p(16), None) == L.GRF_EINVAL
+    assert lib.grad_z_from_k(ctypes.byref(m), ctypes.c_void_p(16), None, None) == L.GRF_EINVAL
+    assert lib.grad_z_from_k(ctypes.byref(m), ctypes.c_void_p(16), ctypes.c_void_p(16), None) == L.GRF_EINVAL
+    assert lib.grad_z_from_k(None, ctypes.c_void_p(16), ctypes.c_void_p(32), None) == L.GRF_EINVAL
 
 
 def _trunc(nt=1, ns=1, rule=None, nv=0, **kw):
