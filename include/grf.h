@@ -302,8 +302,10 @@ typedef struct grf_trunc2 {
     float values[GRF_MAX_FACIES];
 } grf_trunc2;
 
-/* Workspace of eval_pluri_grid when the caller keeps neither field (y1 == y2 == NULL); each
- * field buffer the caller passes makes the need C * 4 bytes (rounded up to 256) smaller. */
+/* Workspace of eval_pluri_grid when the caller keeps neither field (y1 == y2 == NULL): both
+ * fields' tables (and, where eval_field_grid would split the modes, both fields' slice sums),
+ * the rule tables and the fields.  Each field buffer the caller passes makes the need C * 4
+ * bytes (rounded up to 256) smaller. */
 int eval_pluri_grid_ws_size(const grf_modes* m1, const grf_modes* m2, const grf_grid* grid, int method,
                             size_t* bytes);
 
